@@ -1,0 +1,43 @@
+/*
+ * FP64 CPU oracle for the hybrid-dimensional VAG scheme — TEST INFRASTRUCTURE.
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg use
+ * it.  It shares no code with the GPU library.
+ */
+#ifndef VAG_ORACLE_H
+#define VAG_ORACLE_H
+#include <stdint.h>
+
+typedef struct {
+    int64_t n_nodes, n_cells, n_frac;
+    const double *xyz;          /* [n_nodes][3] */
+    const int32_t *hex8;        /* [n_cells][8] VTK order */
+    const int32_t *frac_nodes;  /* [n_frac][4] cyclic */
+    const double *frac_width;   /* [n_frac] d_f */
+    const double *frac_perm;    /* [n_frac] Lambda_f */
+    const double *frac_poro;    /* [n_frac] phi_f */
+    const double *perm;         /* [n_cells][6] xx yy zz xy xz yz */
+    const double *poro;         /* [n_cells] phi_m */
+    double mu;
+    const uint8_t *dirichlet;   /* [n_nodes] */
+    const double *p_bar;        /* [n_nodes] */
+    const double *c_bar;        /* [n_nodes] */
+} orc_problem;
+
+int orc_topology(const orc_problem *P, int32_t *cell_frac, int32_t *frac_cell, int32_t *frac_lface);
+double orc_cell_matrix(const orc_problem *P, int64_t K, const int32_t *cell_frac6, double *a,
+                       int *m_out, double *full15);
+double orc_frac_matrix(const orc_problem *P, int64_t f, double *A5);
+int64_t orc_system_size(const orc_problem *P, int64_t *n_out, int64_t *nnz_out);
+int orc_system_csr(const orc_problem *P, int64_t *row_ptr, int64_t *col, double *val, double *b);
+int orc_solve_darcy(const orc_problem *P, double rtol, int max_iter, double *u_node, double *u_cell,
+                    double *u_frac, double *F_cell, double *F_cell_frac, double *F_frac,
+                    int *iters, double *relres);
+int orc_porous_volumes(const orc_problem *P, double *phi_cell, double *phi_frac, double *phi_node);
+int orc_cfl(const orc_problem *P, const double *F_cell, const double *F_cell_frac,
+            const double *F_frac, const double *phi_cell, const double *phi_frac,
+            const double *phi_node, double *dt3);
+int orc_transport(const orc_problem *P, const double *F_cell, const double *F_cell_frac,
+                  const double *F_frac, const double *phi_cell, const double *phi_frac,
+                  const double *phi_node, double dt, int64_t n_steps, double last_dt,
+                  double *c_cell, double *c_frac, double *c_node);
+#endif

@@ -1,0 +1,408 @@
+"""Seeded generators for hexahedral meshes with fracture faces.
+
+Conventions shared by every consumer (they describe the *input format*, not
+any computation of the scheme):
+
+* Logical grid of ``nx * ny * nz`` hexahedra.  Node ``(i, j, k)`` has index
+  ``i + (nx+1) * (j + (ny+1) * k)``; cell ``(i, j, k)`` has index
+  ``i + nx * (j + ny * k)``.
+* ``hex8[c]`` lists the cell's 8 nodes in VTK order: the bottom quad
+  ``(i,j,k) (i+1,j,k) (i+1,j+1,k) (i,j+1,k)`` then the same four at ``k+1``.
+* A fracture is a set of mesh faces (the paper's conforming assumption, §3.1);
+  each fracture face is given by its 4 node indices in cyclic order.
+* Permeability tensors are packed ``[xx, yy, zz, xy, xz, yz]``.
+* Dirichlet nodes carry ``p_bar`` (pressure) and ``c_bar`` (injected
+  concentration); every other node gets a conservation equation.
+
+Random draws use ``numpy.random.default_rng(seed)`` in a fixed, documented order
+so the same problem is rebuilt bit for bit on every machine.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Problem:
+    name: str
+    dims: tuple
+    xyz: np.ndarray          # [n_nodes, 3] float64
+    hex8: np.ndarray         # [n_cells, 8] int32
+    frac_nodes: np.ndarray   # [n_frac, 4] int32
+    frac_width: np.ndarray   # [n_frac] float64   d_f
+    frac_perm: np.ndarray    # [n_frac] float64   Lambda_f (isotropic in plane)
+    frac_poro: np.ndarray    # [n_frac] float64   phi_f
+    perm: np.ndarray         # [n_cells, 6] float64
+    poro: np.ndarray         # [n_cells] float64  phi_m
+    mu: float
+    dirichlet: np.ndarray    # [n_nodes] uint8
+    p_bar: np.ndarray        # [n_nodes] float64
+    c_bar: np.ndarray        # [n_nodes] float64
+    rtol: float = 1e-10
+    cfl: float = 0.9
+    n_steps: int = 50
+    t_final: float = 0.0     # > 0: integrate to this time, last step shortened
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.hex8.shape[0])
+
+    @property
+    def n_frac(self) -> int:
+        return int(self.frac_nodes.shape[0])
+
+
+# ----------------------------------------------------------------------------
+# grid topology
+# ----------------------------------------------------------------------------
+
+def node_index(dims, i, j, k):
+    nx, ny, _ = dims
+    return i + (nx + 1) * (j + (ny + 1) * k)
+
+
+def structured_hex(nx: int, ny: int, nz: int):
+    """Unit-box coordinates and VTK-ordered connectivity of a logical grid."""
+    i = np.arange(nx + 1, dtype=np.float64) / nx
+    j = np.arange(ny + 1, dtype=np.float64) / ny
+    k = np.arange(nz + 1, dtype=np.float64) / nz
+    zz, yy, xx = np.meshgrid(k, j, i, indexing="ij")
+    xyz = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+
+    ci, cj, ck = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    ci = ci.transpose(2, 1, 0).ravel()
+    cj = cj.transpose(2, 1, 0).ravel()
+    ck = ck.transpose(2, 1, 0).ravel()
+    dims = (nx, ny, nz)
+    n = lambda a, b, c: node_index(dims, a, b, c)  # noqa: E731
+    hex8 = np.stack([
+        n(ci, cj, ck), n(ci + 1, cj, ck), n(ci + 1, cj + 1, ck), n(ci, cj + 1, ck),
+        n(ci, cj, ck + 1), n(ci + 1, cj, ck + 1), n(ci + 1, cj + 1, ck + 1), n(ci, cj + 1, ck + 1),
+    ], axis=1).astype(np.int32)
+    return xyz, hex8
+
+
+def plane_faces(dims, axis: int, plane: int, a_lo: int, a_hi: int, b_lo: int, b_hi: int):
+    """Grid faces on node plane ``plane`` normal to ``axis``.
+
+    The two in-plane axes ``a < b`` are the remaining ones in increasing order;
+    face indices run over ``[a_lo, a_hi) x [b_lo, b_hi)``.  Returns ``[m, 4]``
+    node indices in cyclic order.
+    """
+    a_ax, b_ax = [d for d in range(3) if d != axis]
+    A, B = np.meshgrid(np.arange(a_lo, a_hi), np.arange(b_lo, b_hi), indexing="ij")
+    A = A.ravel()
+    B = B.ravel()
+
+    def idx(da, db):
+        c = [None, None, None]
+        c[axis] = np.full_like(A, plane)
+        c[a_ax] = A + da
+        c[b_ax] = B + db
+        return node_index(dims, c[0], c[1], c[2])
+
+    f = np.stack([idx(0, 0), idx(1, 0), idx(1, 1), idx(0, 1)], axis=1)
+    return f.astype(np.int32)
+
+
+def merge_patches(patches):
+    """Union of (faces, value) patches; a face listed twice keeps the max value."""
+    if not patches:
+        return np.zeros((0, 4), np.int32), np.zeros(0)
+    faces = np.concatenate([p[0] for p in patches])
+    vals = np.concatenate([np.full(len(p[0]), float(p[1])) for p in patches])
+    key = np.sort(faces, axis=1)
+    order = np.lexsort((-vals, key[:, 3], key[:, 2], key[:, 1], key[:, 0]))
+    key = key[order]
+    keep = np.ones(len(order), bool)
+    keep[1:] = np.any(key[1:] != key[:-1], axis=1)
+    sel = np.sort(order[keep])
+    return faces[sel].astype(np.int32), vals[sel]
+
+
+def interior_mask(dims):
+    nx, ny, nz = dims
+    zz, yy, xx = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    return ((xx > 0) & (xx < nx) & (yy > 0) & (yy < ny) & (zz > 0) & (zz < nz)).ravel()
+
+
+def grid_i(dims):
+    nx, ny, nz = dims
+    return np.tile(np.arange(nx + 1), (ny + 1) * (nz + 1))
+
+
+def jitter_nodes(xyz, dims, amp, rng):
+    """Move every node off the domain boundary by U[-amp*h, amp*h] per axis."""
+    m = interior_mask(dims)
+    h = np.array([1.0 / dims[0], 1.0 / dims[1], 1.0 / dims[2]])
+    d = rng.uniform(-1.0, 1.0, size=(int(m.sum()), 3)) * (amp * h)
+    out = xyz.copy()
+    out[m] += d
+    return out
+
+
+def lognormal_tensors(n_cells, sigma, rng):
+    """Lambda = R diag(exp(z)) R^T with z ~ N(0, sigma^2), R Haar-distributed."""
+    z = rng.standard_normal((n_cells, 3)) * sigma
+    g = rng.standard_normal((n_cells, 3, 3))
+    q, r = np.linalg.qr(g)
+    s = np.sign(np.diagonal(r, axis1=1, axis2=2))
+    s[s == 0] = 1.0
+    q = q * s[:, None, :]
+    lam = np.einsum("nij,nj,nkj->nik", q, np.exp(z), q)
+    return np.stack([lam[:, 0, 0], lam[:, 1, 1], lam[:, 2, 2],
+                     lam[:, 0, 1], lam[:, 0, 2], lam[:, 1, 2]], axis=1)
+
+
+def isotropic(n_cells, value=1.0):
+    p = np.zeros((n_cells, 6))
+    p[:, :3] = value
+    return p
+
+
+def random_patches(dims, n_patches, rng, ratios=(1e2, 1e4, 1e6), fixed_ratio=None):
+    """Axis-aligned rectangular patches of grid faces.
+
+    Per patch, in this draw order: axis ~ U{0,1,2}; plane ~ U{1..n-1};
+    side lengths ~ U{ceil(n/16)..ceil(n/4)} per in-plane axis; corner ~ U over
+    valid positions; ratio ~ U(ratios) unless ``fixed_ratio`` is given.
+    """
+    patches = []
+    for _ in range(n_patches):
+        axis = int(rng.integers(0, 3))
+        n_ax = dims[axis]
+        plane = int(rng.integers(1, n_ax))
+        a_ax, b_ax = [d for d in range(3) if d != axis]
+        lens = []
+        for ax in (a_ax, b_ax):
+            n = dims[ax]
+            lo, hi = math.ceil(n / 16), math.ceil(n / 4)
+            lens.append(int(rng.integers(lo, hi + 1)))
+        corner = [int(rng.integers(0, dims[ax] - L + 1)) for ax, L in zip((a_ax, b_ax), lens)]
+        ratio = fixed_ratio if fixed_ratio is not None else float(ratios[int(rng.integers(0, len(ratios)))])
+        f = plane_faces(dims, axis, plane, corner[0], corner[0] + lens[0], corner[1], corner[1] + lens[1])
+        patches.append((f, ratio))
+    return patches
+
+
+def x_dirichlet(dims, n_nodes, xyz):
+    """Dirichlet pressure 1 / concentration 1 at x=0, pressure 0 / concentration 0 at x=1."""
+    gi = grid_i(dims)
+    dirichlet = ((gi == 0) | (gi == dims[0])).astype(np.uint8)
+    p_bar = np.where(gi == 0, 1.0, 0.0)
+    c_bar = np.where(gi == 0, 1.0, 0.0)
+    return dirichlet, p_bar, c_bar
+
+
+def _assemble(name, dims, xyz, hex8, faces, ratios, perm, df=0.01, lam_m=1.0, **kw):
+    nf = len(faces)
+    return Problem(
+        name=name, dims=dims, xyz=np.ascontiguousarray(xyz, np.float64),
+        hex8=np.ascontiguousarray(hex8, np.int32),
+        frac_nodes=np.ascontiguousarray(faces, np.int32).reshape(nf, 4),
+        frac_width=np.full(nf, df), frac_perm=np.asarray(ratios, np.float64) * lam_m,
+        frac_poro=np.ones(nf), perm=np.ascontiguousarray(perm, np.float64),
+        poro=np.ones(len(hex8)), mu=1.0, **kw)
+
+
+def cartesian_problem(n, planes=(), ratio=1e4, df=0.01, jitter=0.0, aniso_sigma=None,
+                      seed=0, name=None, **kw):
+    """Cube of n^3 cells; ``planes`` = [(axis, plane, a_lo, a_hi, b_lo, b_hi), ...]."""
+    dims = (n, n, n)
+    xyz, hex8 = structured_hex(*dims)
+    rng = np.random.default_rng(seed)
+    if jitter > 0:
+        xyz = jitter_nodes(xyz, dims, jitter, rng)
+    perm = lognormal_tensors(n ** 3, aniso_sigma, rng) if aniso_sigma else isotropic(n ** 3)
+    patches = [(plane_faces(dims, *p), ratio) for p in planes]
+    faces, ratios = merge_patches(patches)
+    d, pb, cb = x_dirichlet(dims, len(xyz), xyz)
+    return _assemble(name or f"cart{n}", dims, xyz, hex8, faces, ratios, perm, df=df,
+                     dirichlet=d, p_bar=pb, c_bar=cb, **kw)
+
+
+def random_problem(dims, seed, jitter=0.2, aniso_sigma=1.0, n_patches=3,
+                   ratios=(1e2, 1e4, 1e6), name=None, **kw):
+    """Small random instance: jitter, lognormal tensors, random face patches."""
+    xyz, hex8 = structured_hex(*dims)
+    rng = np.random.default_rng(seed)
+    if jitter > 0:
+        xyz = jitter_nodes(xyz, dims, jitter, rng)
+    nc = len(hex8)
+    perm = lognormal_tensors(nc, aniso_sigma, rng) if aniso_sigma else isotropic(nc)
+    faces, r = merge_patches(random_patches(dims, n_patches, rng, ratios))
+    d, pb, cb = x_dirichlet(dims, len(xyz), xyz)
+    return _assemble(name or f"rand{dims}-{seed}", dims, xyz, hex8, faces, r, perm,
+                     dirichlet=d, p_bar=pb, c_bar=cb, **kw)
+
+
+# ----------------------------------------------------------------------------
+# The five benchmark workloads
+# ----------------------------------------------------------------------------
+
+def config1():
+    """10^3 unit cube, one fracture = all faces of plane x=0.5, d_f*Lambda_f = 100."""
+    n = 10
+    return cartesian_problem(n, planes=[(0, 5, 0, n, 0, n)], ratio=1e4, name="config1",
+                             rtol=1e-10, cfl=0.9, n_steps=50)
+
+
+def config2(n=64, seed=2):
+    """n^3 cube, four clipped fractures on planes x=n/2, y=n/2, z=n/4, z=3n/4."""
+    rng = np.random.default_rng(seed)
+    planes = []
+    lo_hi = lambda: (int(rng.integers(0, n * 12 // 64 + 1)), int(rng.integers(n * 52 // 64, n + 1)))  # noqa: E731
+    for axis, plane in ((0, n // 2), (1, n // 2), (2, n // 4), (2, 3 * n // 4)):
+        a_lo, a_hi = lo_hi()
+        b_lo, b_hi = lo_hi()
+        planes.append((axis, plane, a_lo, a_hi, b_lo, b_hi))
+    return cartesian_problem(n, planes=planes, ratio=1e4, name=f"config2-n{n}",
+                             rtol=1e-8, cfl=0.9, n_steps=200)
+
+
+def config3(n=128, seed=3, n_patches=40):
+    """Jittered n^3 mesh, lognormal anisotropic tensors, random face patches."""
+    dims = (n, n, n)
+    xyz, hex8 = structured_hex(*dims)
+    rng = np.random.default_rng(seed)
+    xyz = jitter_nodes(xyz, dims, 0.2, rng)
+    perm = lognormal_tensors(n ** 3, 1.0, rng)
+    faces, r = merge_patches(random_patches(dims, n_patches, rng))
+    d, pb, cb = x_dirichlet(dims, len(xyz), xyz)
+    return _assemble(f"config3-n{n}", dims, xyz, hex8, faces, r, perm,
+                     dirichlet=d, p_bar=pb, c_bar=cb, rtol=1e-8, cfl=0.9, n_steps=200)
+
+
+def config4_job(j, n_range=(16, 96)):
+    """Serving job j: jittered n^3, isotropic matrix, 1-20 patches, one ratio per job."""
+    rng = np.random.default_rng([4, j])
+    n = int(rng.integers(n_range[0], n_range[1] + 1))
+    dims = (n, n, n)
+    xyz, hex8 = structured_hex(*dims)
+    xyz = jitter_nodes(xyz, dims, 0.2, rng)
+    n_p = int(rng.integers(1, 21))
+    ratio = float((1e2, 1e4, 1e6)[int(rng.integers(0, 3))])
+    faces, r = merge_patches(random_patches(dims, n_p, rng, fixed_ratio=ratio))
+    d, pb, cb = x_dirichlet(dims, len(xyz), xyz)
+    return _assemble(f"config4-job{j}-n{n}", dims, xyz, hex8, faces, r, isotropic(n ** 3),
+                     dirichlet=d, p_bar=pb, c_bar=cb, rtol=1e-8, cfl=0.9, n_steps=100)
+
+
+def config5(n=192, seed=5, n_patches=200):
+    """Largest instance: jittered n^3, lognormal tensors, patches at ratio 1e6."""
+    dims = (n, n, n)
+    xyz, hex8 = structured_hex(*dims)
+    rng = np.random.default_rng(seed)
+    xyz = jitter_nodes(xyz, dims, 0.2, rng)
+    perm = lognormal_tensors(n ** 3, 1.0, rng)
+    faces, r = merge_patches(random_patches(dims, n_patches, rng, fixed_ratio=1e6))
+    d, pb, cb = x_dirichlet(dims, len(xyz), xyz)
+    return _assemble(f"config5-n{n}", dims, xyz, hex8, faces, r, perm,
+                     dirichlet=d, p_bar=pb, c_bar=cb, rtol=1e-8, cfl=0.9, n_steps=1000)
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3, 5: config5}
+
+
+# ----------------------------------------------------------------------------
+# The paper's two analytical test cases (§5.1, §5.2), extruded to one layer
+# ----------------------------------------------------------------------------
+
+def _extruded(n, xy):
+    """n x n x 1 grid whose (i, j) node sits at xy[j, i]; layer thickness 1/n."""
+    dims = (n, n, 1)
+    xyz, hex8 = structured_hex(*dims)
+    for k in range(2):
+        sl = slice(k * (n + 1) ** 2, (k + 1) * (n + 1) ** 2)
+        xyz[sl, 0] = xy[..., 0].ravel()
+        xyz[sl, 1] = xy[..., 1].ravel()
+        xyz[sl, 2] = k / n
+    return dims, xyz, hex8
+
+
+def e1_problem(n, tan_theta=0.5, lam_f=20.0, df=0.01, t_final=0.5):
+    """§5.1: one fracture from (0,1/4) to (1,1/4+tan(theta)); u = 1 - x."""
+    assert n % 2 == 0
+    h = n // 2
+    x = np.arange(n + 1) / n
+    yf = 0.25 + x * tan_theta
+    xy = np.zeros((n + 1, n + 1, 2))
+    for j in range(n + 1):
+        xy[j, :, 0] = x
+        if j <= h:
+            xy[j, :, 1] = (j / h) * yf
+        else:
+            xy[j, :, 1] = yf + ((j - h) / h) * (1.0 - yf)
+    dims, xyz, hex8 = _extruded(n, xy)
+    faces = plane_faces(dims, 1, h, 0, n, 0, 1)
+    gi = grid_i(dims)
+    dirichlet = ((gi == 0) | (gi == n)).astype(np.uint8)
+    p_bar = 1.0 - xyz[:, 0]
+    c_bar = np.where(gi == 0, 1.0, 0.0)
+    nf = len(faces)
+    return Problem(name=f"e1-n{n}", dims=dims, xyz=xyz, hex8=hex8, frac_nodes=faces,
+                   frac_width=np.full(nf, df), frac_perm=np.full(nf, lam_f), frac_poro=np.ones(nf),
+                   perm=isotropic(len(hex8)), poro=np.ones(len(hex8)), mu=1.0,
+                   dirichlet=dirichlet, p_bar=p_bar, c_bar=c_bar, rtol=1e-13, cfl=1.0,
+                   n_steps=0, t_final=t_final,
+                   meta=dict(tan_theta=tan_theta, lam_f=lam_f, df=df, row=h))
+
+
+def e2_problem(n, tan1=5 / 8, tan2=1 / 4, lam_f1=200.0, lam_f3=400.0, df=0.01, t_final=3.0):
+    """§5.2: four fractures meeting at x0; mesh = 4 bilinear blocks conforming to both lines."""
+    assert n % 2 == 0
+    h = n // 2
+    x0 = (3 - tan2) / (4 * (1 + tan1 * tan2))
+    y0 = (1 + 3 * tan1) / (4 * (1 + tan1 * tan2))
+    P = {
+        "A": (0.0, 0.0), "B": (1.0, 0.0), "C": (1.0, 1.0), "D": (0.0, 1.0),
+        "x1": (0.0, 0.25), "x2": (1.0, 0.25 + tan1), "x3": (0.75, 0.0), "x4": (0.75 - tan2, 1.0),
+        "x0": (x0, y0),
+    }
+    P = {k: np.array(v) for k, v in P.items()}
+    xy = np.zeros((n + 1, n + 1, 2))
+    blocks = [  # (i range, j range, corners p00 p10 p11 p01)
+        ((0, h), (0, h), ("A", "x3", "x0", "x1")),
+        ((h, n), (0, h), ("x3", "B", "x2", "x0")),
+        ((0, h), (h, n), ("x1", "x0", "x4", "D")),
+        ((h, n), (h, n), ("x0", "x2", "C", "x4")),
+    ]
+    for (i0, i1), (j0, j1), (c00, c10, c11, c01) in blocks:
+        for j in range(j0, j1 + 1):
+            v = (j - j0) / (j1 - j0)
+            for i in range(i0, i1 + 1):
+                u = (i - i0) / (i1 - i0)
+                xy[j, i] = ((1 - u) * (1 - v) * P[c00] + u * (1 - v) * P[c10]
+                            + u * v * P[c11] + (1 - u) * v * P[c01])
+    dims, xyz, hex8 = _extruded(n, xy)
+    f1 = plane_faces(dims, 1, h, 0, h, 0, 1)      # Gamma_1: x1 -> x0
+    f2 = plane_faces(dims, 1, h, h, n, 0, 1)      # Gamma_2: x0 -> x2
+    f3 = plane_faces(dims, 0, h, 0, h, 0, 1)      # Gamma_3: x3 -> x0
+    f4 = plane_faces(dims, 0, h, h, n, 0, 1)      # Gamma_4: x0 -> x4
+    faces = np.concatenate([f1, f2, f3, f4])
+    perm_f = np.concatenate([np.full(len(f1) + len(f2), lam_f1), np.full(len(f3) + len(f4), lam_f3)])
+    branch = np.concatenate([np.full(len(f), b) for b, f in enumerate((f1, f2, f3, f4), start=1)])
+    gi = grid_i(dims)
+    gj = np.tile(np.repeat(np.arange(n + 1), n + 1), 2)
+    tip3 = (gi == h) & (gj == 0)
+    tip4 = (gi == h) & (gj == n)
+    dirichlet = ((gi == 0) | (gi == n) | tip3 | tip4).astype(np.uint8)
+    p_bar = 1.0 - xyz[:, 0]
+    tip1 = (gi == 0) & (gj == h)
+    c_bar = np.where(tip1 | tip4, 1.0, 0.0)
+    nf = len(faces)
+    return Problem(name=f"e2-n{n}", dims=dims, xyz=xyz, hex8=hex8, frac_nodes=faces,
+                   frac_width=np.full(nf, df), frac_perm=perm_f, frac_poro=np.ones(nf),
+                   perm=isotropic(len(hex8)), poro=np.ones(len(hex8)), mu=1.0,
+                   dirichlet=dirichlet, p_bar=p_bar, c_bar=c_bar, rtol=1e-13, cfl=1.0,
+                   n_steps=0, t_final=t_final,
+                   meta=dict(tan1=tan1, tan2=tan2, lam_f1=lam_f1, lam_f3=lam_f3, df=df,
+                             x0=x0, y0=y0, branch=branch))
