@@ -1,0 +1,128 @@
+#!/usr/bin/env python3
+"""Benchmark: Darcy + transport solves per second on one MI355X.
+
+One step = one full pass of the hot path over the resident 64^3 workload
+(four clipped fractures, contrast 1e4): per-cell VAG matrices, cell
+elimination and assembly, preconditioned CG to rtol 1e-8, cell recovery and
+fluxes, porous volumes, CFL step and 200 explicit upwind steps.  The mesh's
+symbolic phase (topology only) is done once before timing and reported apart.
+
+Prints one JSON line (see the field list at the end of main()).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(h, sinfo, tinfo):
+    n, nnz = sinfo["n_unknowns"], sinfo["nnz"]
+    spmv = 12 * nnz + 4 * (n + 1) + 16 * n                       # CSR FP64: val+col, row_ptr, x, y
+    step = 12 * tinfo["t_nnz"] + 24 * tinfo["n_rows"]            # upwind sweep: entries, diag, c in/out
+    return dict(spmv=spmv, transport_step=step)
+
+
+def cpu_baseline(prob, budget_s=30.0):
+    """The oracle, as it stands, on one full solve of the same workload."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    oracle.run(prob, rtol=prob.rtol)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"one full solve of {prob.name} (Jacobi-PCG to rtol {prob.rtol:g} + {prob.n_steps} steps), "
+                      f"{dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precond", choices=["jacobi", "amg"], default=os.environ.get("VAG_BENCH_PRECOND", "amg"))
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is a design note, "
+              "not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1602_03641_amd import vag
+
+    prob = synth.config2(n=args.n)
+    opts = dict(rtol=prob.rtol, cfl=prob.cfl, max_iter=50000,
+                precond=vag.VAG_PC_AMG if args.precond == "amg" else vag.VAG_PC_JACOBI,
+                precision=vag.VAG_MIXED if args.precision == "mixed" else vag.VAG_FP64)
+    t0 = time.perf_counter()
+    h = vag.Handle(prob, **opts)
+    torch.cuda.synchronize()
+    symbolic_s = time.perf_counter() - t0
+
+    def step():
+        s = h.solve_pressure()
+        t = h.transport(n_steps=prob.n_steps)
+        return s, t
+
+    for _ in range(args.warmup):
+        sinfo, tinfo = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sinfo, tinfo = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    # roofline of the dominant kernel: per-launch time from HIP events on the handle's stream
+    ab = algorithmic_bytes(h, sinfo, tinfo)
+    ms_spmv = h.benchmark_kernel(vag.VAG_KERNEL_SPMV, 100)
+    ms_step = h.benchmark_kernel(vag.VAG_KERNEL_TRANSPORT_STEP, 100)
+    n_spmv = sinfo["iterations"] + 1
+    share = {"spmv": ms_spmv * n_spmv, "transport_step": ms_step * tinfo["n_steps"]}
+    dom = max(share, key=share.get)
+    ms_dom = ms_spmv if dom == "spmv" else ms_step
+    achieved = ab[dom] / (ms_dom * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "pcg_spmv_kernel" if dom == "spmv" else "transport_step_kernel",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": ab[dom], "ms_per_launch": ms_dom,
+                "other": {"spmv_GBs": round(ab["spmv"] / (ms_spmv * 1e-3) / 1e9, 1),
+                          "transport_step_GBs": round(ab["transport_step"] / (ms_step * 1e-3) / 1e9, 1)}}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(prob)
+
+    out = {
+        "metric": "Darcy+transport solves/sec", "value": round(args.steps / elapsed, 4), "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"config2: cartesian {args.n}^3 hexahedra, 4 clipped face fractures, "
+                               f"contrast 1e4, CG rtol {prob.rtol:g}, {prob.n_steps} upwind steps",
+                   "precond": args.precond, "precision": args.precision,
+                   "n_unknowns": sinfo["n_unknowns"], "nnz": sinfo["nnz"], "n_frac": prob.n_frac},
+        "iterations": sinfo["iterations"], "rel_residual": sinfo["rel_residual"],
+        "phase_ms": {k: round(sinfo[k], 3) for k in ("ms_assembly", "ms_setup", "ms_solve", "ms_fluxes")}
+        | {"transport_setup": round(tinfo["ms_setup"], 3), "transport_steps": round(tinfo["ms_steps"], 3)},
+        "symbolic_s": round(symbolic_s, 3),
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,262 @@
+/*
+ * libvag — hybrid-dimensional Vertex Approximate Gradient (VAG) Darcy flow and
+ * explicit upwind transport in fractured porous media, on one AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The problem statement follows Xing, Masson, Lopez, "Parallel Vertex
+ * Approximate Gradient discretization of hybrid dimensional Darcy flow and
+ * transport in discrete fracture networks" (arXiv:1602.03641):
+ *   - mesh D and conforming fracture faces F_Gamma ........ §3.1
+ *   - Darcy unknowns u_K, u_s, u_sigma and the VAG fluxes .. §3.1, eqs VAGFluxMatrix,
+ *                                                          VAGFluxFracture
+ *   - cell elimination (Schur complement) .................. §4.2, eqs sysowndarcy,
+ *                                                          eqschur, eqschurcell
+ *   - control volumes and porous volumes ................... §3.2.1
+ *   - explicit upwind steps and the CFL bound .............. §3.2.2, eqs darcyfluxH,
+ *                                                          eq_CFL; §4.3
+ *
+ * Conventions
+ *   - All entry points are extern "C", take plain pointers and sizes, and never
+ *     throw or abort: they return a vag_status (negative = error,
+ *     VAG_WARN_NOT_CONVERGED = best iterate returned).  vag_last_error() gives
+ *     the text of the last error of a handle (with the offending index where
+ *     one exists).
+ *   - Array arguments are caller-owned.  Input arrays are read during the call
+ *     only (the library copies what it keeps).  Output arrays are written by the
+ *     call.  A vag_mem argument says whether the pointers are host or device
+ *     (HIP) memory; the same space applies to every array of the call.
+ *   - A handle binds one HIP stream (the one given at creation, or the null
+ *     stream).  All device work of the handle is queued on it.  Calls that
+ *     return host data synchronise that stream.  A handle is not thread-safe;
+ *     distinct handles are independent.
+ *   - Index types are int32 (cells, nodes, fracture faces < 2^31); the
+ *     assembled nodal system must have fewer than 2^31 nonzeros.
+ */
+#ifndef VAG_H
+#define VAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VAG_OK = 0,
+    VAG_WARN_NOT_CONVERGED = 1,
+    VAG_ERR_ARG = -1,          /* invalid argument or inconsistent input */
+    VAG_ERR_MESH = -2,         /* invalid mesh: non-positive sub-tetrahedron, unknown fracture face */
+    VAG_ERR_UNSUPPORTED = -3,  /* valid request this build does not implement */
+    VAG_ERR_OOM = -4,          /* device allocation failed */
+    VAG_ERR_HIP = -5,          /* HIP runtime error */
+    VAG_ERR_STATE = -6         /* call out of order (e.g. transport before a pressure solve) */
+} vag_status;
+
+typedef enum { VAG_MEM_HOST = 0, VAG_MEM_DEVICE = 1 } vag_mem;
+
+typedef enum { VAG_FP64 = 0, VAG_MIXED = 1 } vag_precision;
+typedef enum { VAG_CG = 0, VAG_GMRES = 1 } vag_krylov;
+typedef enum { VAG_PC_JACOBI = 0, VAG_PC_AMG = 1 } vag_precond;
+
+/*
+ * Generalised polyhedral mesh restricted to hexahedra (§3.1).  Each cell lists
+ * its 8 nodes in VTK order (bottom quad counter-clockwise seen from above, then
+ * the top quad); faces may be non-planar.  The cell centre is the mean of its
+ * nodes and a face centre the mean of its 4 nodes (beta = 1/4).  Every one of
+ * the 24 sub-tetrahedra (x_K, x_sigma, edge) must have positive volume.
+ */
+typedef struct {
+    int64_t n_nodes;
+    int64_t n_cells;
+    const double *node_xyz;  /* [n_nodes][3] */
+    const int32_t *hex8;     /* [n_cells][8] */
+} vag_mesh;
+
+/*
+ * Fracture faces F_Gamma (§3.1: the fracture network is a union of mesh faces).
+ * Each is given by its 4 nodes in cyclic order; it must be a face of one or two
+ * cells and listed once.  width = d_f, perm = Lambda_f (isotropic in the
+ * plane), porosity = phi_f, each per fracture face.
+ */
+typedef struct {
+    int64_t n_frac;
+    const int32_t *face_nodes;  /* [n_frac][4] */
+    const double *width;        /* [n_frac] */
+    const double *perm;         /* [n_frac] */
+    const double *porosity;     /* [n_frac] */
+} vag_fractures;
+
+/* Matrix rock: symmetric positive definite Lambda_m per cell packed
+ * [xx, yy, zz, xy, xz, yz], porosity phi_m per cell, constant viscosity mu. */
+typedef struct {
+    const double *perm;      /* [n_cells][6] */
+    const double *porosity;  /* [n_cells] */
+    double mu;
+} vag_rock;
+
+/*
+ * Boundary data.  A node with node_dirichlet = 1 has pressure p_bar and, in the
+ * transport, the fixed concentration c_bar (§3.1 last equation, §3.2.2).
+ * Every other node carries the conservation equation of an interior node
+ * (homogeneous Neumann where it lies on the boundary).  At least one node must
+ * be Dirichlet.
+ */
+typedef struct {
+    const uint8_t *node_dirichlet;  /* [n_nodes] 0/1 */
+    const double *p_bar;            /* [n_nodes], read where flagged */
+    const double *c_bar;            /* [n_nodes], read where flagged */
+} vag_bc;
+
+typedef struct {
+    int precision;          /* vag_precision */
+    int krylov;             /* vag_krylov */
+    int precond;            /* vag_precond */
+    double rtol;            /* stop when ||b - A x||_2 <= rtol ||b||_2, x0 = 0 */
+    double inner_rtol;      /* VAG_MIXED: relative tolerance of each FP32 inner solve */
+    int max_iter;           /* Krylov iterations (VAG_MIXED: inner iterations in total) */
+    int gmres_restart;      /* GMRES basis size */
+    int check_every;        /* iterations queued between host convergence checks */
+    double cfl;             /* transport step = cfl * CFL bound (eq_CFL) */
+    int amg_coarse_size;    /* stop coarsening below this many unknowns */
+    int amg_max_levels;
+    double amg_theta;       /* strength threshold |a_ij| >= theta sqrt(a_ii a_jj) */
+    int amg_sweeps;         /* pre- and post-smoothing Jacobi sweeps */
+    int reserved[8];
+} vag_options;
+
+typedef struct {
+    int iterations;         /* Krylov iterations (total inner iterations in VAG_MIXED) */
+    int outer_iterations;   /* refinement steps (VAG_MIXED), else 1 */
+    double rel_residual;    /* final ||b - A x|| / ||b||, computed in FP64 */
+    int64_t n_unknowns;     /* size of the nodal (+ fracture-face) system */
+    int64_t nnz;
+    int amg_levels;
+    double amg_operator_complexity;
+    double ms_assembly, ms_setup, ms_solve, ms_fluxes;  /* HIP-event times */
+} vag_solve_info;
+
+typedef struct {
+    int64_t n_steps;        /* steps taken */
+    double dt;              /* time step of the first n_steps-1 steps */
+    double last_dt;         /* time step of the last step */
+    double dt_bounds[3];    /* CFL minima over cells, fracture faces, nodes */
+    double ms_setup, ms_steps;
+    int64_t n_rows;         /* control volumes: cells + fracture faces + nodes */
+    int64_t t_nnz;          /* off-diagonal entries of the upwind operator */
+    int64_t t_stored;       /* stored entries including slice padding */
+} vag_transport_info;
+
+/* Kernels that vag_benchmark_kernel can time. */
+typedef enum {
+    VAG_KERNEL_SPMV = 0,            /* y = A x with the assembled system (Krylov operator) */
+    VAG_KERNEL_TRANSPORT_STEP = 1,  /* one explicit upwind step */
+    VAG_KERNEL_LOCAL = 2,           /* per-cell local VAG matrices */
+    VAG_KERNEL_PRECOND = 3          /* one application of the preconditioner */
+} vag_kernel;
+
+typedef struct vag_handle vag_handle;
+
+/* Library version string. */
+const char *vag_version(void);
+
+/* Fills *opt with defaults: FP64, CG, AMG, rtol 1e-8, cfl 0.9. */
+vag_status vag_default_options(vag_options *opt);
+
+/*
+ * Creates a handle: validates the mesh, matches fracture faces to cell faces,
+ * numbers the unknowns (free nodes, then fracture faces), builds the sparsity
+ * pattern of the cell-eliminated system (eq eqschur), the cell colouring used
+ * for conflict-free assembly and the node adjacency used by transport, and
+ * copies all data to the device.  hip_stream may be NULL (null stream).
+ * Errors: VAG_ERR_ARG (null/size problems, fracture face listed twice, no
+ * Dirichlet node), VAG_ERR_MESH (fracture face that is not a mesh face, face
+ * with more than two cells, cell with a non-positive sub-tetrahedron —
+ * detected at the first solve), VAG_ERR_OOM, VAG_ERR_HIP.
+ */
+vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag_rock *rock,
+                      const vag_bc *bc, const vag_options *opt, vag_mem inputs_mem,
+                      void *hip_stream, vag_handle **out);
+
+/*
+ * Replaces the numeric data (permeabilities, porosities, fracture widths,
+ * boundary values) of a handle without touching its topology; NULL pointers
+ * keep the current values.  Takes effect at the next vag_solve_pressure.
+ */
+vag_status vag_update(vag_handle *h, const vag_rock *rock, const vag_fractures *frac_props,
+                      const double *p_bar, const double *c_bar, vag_mem mem);
+
+/* Replaces the solver options of a handle (takes effect at the next solve). */
+vag_status vag_set_options(vag_handle *h, const vag_options *opt);
+
+/*
+ * Darcy solve, Algorithm paraimpdarcy on one device: per-cell VAG matrices
+ * (eq VAGFluxMatrix) and fracture matrices (eq VAGFluxFracture), elimination of
+ * the cell unknowns (eq eqschur), Dirichlet columns to the right-hand side,
+ * preconditioned Krylov solve, cell recovery (eq eqschurcell), then the fluxes
+ * F_{K,nu} and F_{sigma,s} kept on the device for transport.
+ * Returns VAG_WARN_NOT_CONVERGED with the last iterate if rtol is not reached.
+ */
+vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info);
+
+/*
+ * Explicit upwind transport (§3.2.2, eq darcyfluxH; §4.3): porous volumes of
+ * the control volumes, time step dt = cfl * CFL bound (eq eq_CFL), then steps.
+ * With t_final > 0: N = ceil(t_final/dt) steps, the last one t_final-(N-1) dt;
+ * otherwise n_steps steps of dt.  The initial state is c0 (cell, fracture-face,
+ * node arrays; NULL = continue from the current state, which is 0 after a
+ * solve); Dirichlet nodes are held at c_bar.
+ */
+vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const double *c0_cell,
+                         const double *c0_frac, const double *c0_node, vag_mem mem,
+                         vag_transport_info *info);
+
+/* Pressures: u_node[n_nodes] (Dirichlet nodes carry p_bar), u_cell[n_cells],
+ * u_frac[n_frac].  Any pointer may be NULL. */
+vag_status vag_get_pressure(vag_handle *h, double *u_node, double *u_cell, double *u_frac,
+                            vag_mem mem);
+
+/* Fluxes: F_cell[n_cells][8] = F_{K,s} in VTK node order; F_cell_frac[n_frac][2]
+ * = F_{K,sigma} for the cells of sigma by ascending cell index (0 for a missing
+ * second cell); F_frac[n_frac][4] = F_{sigma,s} in the face's input node order. */
+vag_status vag_get_fluxes(vag_handle *h, double *F_cell, double *F_cell_frac, double *F_frac,
+                          vag_mem mem);
+
+/* Porous volumes phi_K, phi_sigma, phi_s (0 at Dirichlet nodes). */
+vag_status vag_get_porous_volumes(vag_handle *h, double *phi_cell, double *phi_frac,
+                                  double *phi_node, vag_mem mem);
+
+/* Concentrations after the last transport call. */
+vag_status vag_get_concentration(vag_handle *h, double *c_cell, double *c_frac, double *c_node,
+                                 vag_mem mem);
+
+/* Size of the assembled system of eq eqschur (after the first solve). */
+vag_status vag_system_size(vag_handle *h, int64_t *n, int64_t *nnz);
+
+/* Copies the assembled system: CSR row_ptr[n+1], col[nnz] (int64), val[nnz], b[n].
+ * Unknown order: free nodes by node index, then fracture faces. */
+vag_status vag_get_system(vag_handle *h, int64_t *row_ptr, int64_t *col, double *val, double *b,
+                          vag_mem mem);
+
+/*
+ * Measurement helper: launches `kernel` `reps` times back to back on the
+ * handle's stream with the handle's current data (after a solve; the transport
+ * step also needs a transport call) and returns the mean duration of one
+ * launch from HIP events.  Scratch vectors only are written.
+ */
+vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms_per_launch);
+
+/* Device bytes held by the handle. */
+size_t vag_footprint_bytes(const vag_handle *h);
+
+/* Text of the handle's last error ("" if none); for a NULL handle, of the last
+ * failed vag_create in this thread. */
+const char *vag_last_error(const vag_handle *h);
+
+/* Releases all device and host memory of the handle. */
+void vag_destroy(vag_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VAG_H */

@@ -1,0 +1,281 @@
+// Symbolic phase: everything that depends only on the mesh topology, the
+// fracture face list and the Dirichlet flags.  Runs once per mesh on the host.
+//
+//  - match fracture faces to cell faces (the conforming assumption of §3.1),
+//  - number the unknowns of the cell-eliminated system (eq eqschur): free
+//    nodes by node index, then fracture faces,
+//  - sparsity pattern: the unknowns of a cell (its free nodes and fracture
+//    faces) are pairwise coupled after eliminating u_K, so the pattern is the
+//    union over cells of these cliques,
+//  - greedy cell colouring such that cells of one colour share no node: the
+//    assembly scatters one colour at a time without atomics (deterministic),
+//  - per-cell slot maps: position in the CSR values of each local pair,
+//  - node -> (cell, slot) and node -> (fracture, vertex) adjacency.
+#include <algorithm>
+#include <array>
+#include <unordered_map>
+
+#include "vag_internal.h"
+
+namespace vag {
+
+namespace {
+
+struct Key4 {
+    std::array<int32_t, 4> v;
+    bool operator==(const Key4 &o) const { return v == o.v; }
+};
+struct Key4Hash {
+    size_t operator()(const Key4 &k) const {
+        uint64_t h = 1469598103934665603ull;
+        for (int32_t x : k.v) {
+            h ^= static_cast<uint32_t>(x);
+            h *= 1099511628211ull;
+        }
+        return static_cast<size_t>(h);
+    }
+};
+
+Key4 sorted_key(const int32_t *n) {
+    Key4 k{{n[0], n[1], n[2], n[3]}};
+    std::sort(k.v.begin(), k.v.end());
+    return k;
+}
+
+// true if b lists the same 4-cycle as a (any rotation, either direction)
+bool same_cycle(const int32_t *a, const int32_t *b) {
+    int p = -1;
+    for (int i = 0; i < 4; ++i)
+        if (a[i] == b[0]) p = i;
+    if (p < 0) return false;
+    bool fwd = true, bwd = true;
+    for (int i = 0; i < 4; ++i) {
+        fwd &= (a[(p + i) & 3] == b[i]);
+        bwd &= (a[(p - i + 4) & 3] == b[i]);
+    }
+    return fwd || bwd;
+}
+
+}  // namespace
+
+void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex8,
+                    const int32_t *frac_nodes, const uint8_t *dirichlet, Symbolic &S) {
+    if (nn64 <= 0 || nc64 <= 0 || nf64 < 0 || nn64 >= INT32_MAX || nc64 >= INT32_MAX / 8 ||
+        nf64 >= INT32_MAX / 4)
+        throw Error(VAG_ERR_ARG, "mesh sizes out of range");
+    const int32_t nn = (int32_t)nn64, nc = (int32_t)nc64, nf = (int32_t)nf64;
+    S.nn = nn;
+    S.nc = nc;
+    S.nf = nf;
+
+    for (int64_t i = 0; i < 8 * (int64_t)nc; ++i)
+        if (hex8[i] < 0 || hex8[i] >= nn)
+            throw Error(VAG_ERR_ARG, "hex8 node index out of range at cell " + std::to_string(i / 8));
+    for (int64_t i = 0; i < 4 * (int64_t)nf; ++i)
+        if (frac_nodes[i] < 0 || frac_nodes[i] >= nn)
+            throw Error(VAG_ERR_ARG, "fracture face node index out of range at face " + std::to_string(i / 4));
+
+    // node -> (cell, slot)
+    S.node_cell_ptr.assign(nn + 1, 0);
+    for (int64_t i = 0; i < 8 * (int64_t)nc; ++i) S.node_cell_ptr[hex8[i] + 1]++;
+    for (int32_t s = 0; s < nn; ++s) S.node_cell_ptr[s + 1] += S.node_cell_ptr[s];
+    S.node_cell.resize(S.node_cell_ptr[nn]);
+    {
+        std::vector<int32_t> fill(S.node_cell_ptr.begin(), S.node_cell_ptr.end() - 1);
+        for (int32_t K = 0; K < nc; ++K)
+            for (int a = 0; a < 8; ++a) S.node_cell[fill[hex8[8 * (int64_t)K + a]]++] = K * 8 + a;
+    }
+
+    // fracture faces: match against cell faces
+    S.frac_node.assign(nn, 0);
+    for (int64_t i = 0; i < 4 * (int64_t)nf; ++i) S.frac_node[frac_nodes[i]] = 1;
+    std::unordered_map<Key4, int32_t, Key4Hash> fmap;
+    fmap.reserve((size_t)nf * 2 + 1);
+    for (int32_t f = 0; f < nf; ++f) {
+        const int32_t *fn = frac_nodes + 4 * (int64_t)f;
+        Key4 k = sorted_key(fn);
+        if (k.v[0] == k.v[1] || k.v[1] == k.v[2] || k.v[2] == k.v[3])
+            throw Error(VAG_ERR_ARG, "fracture face " + std::to_string(f) + " repeats a node");
+        if (!fmap.emplace(k, f).second)
+            throw Error(VAG_ERR_ARG, "fracture face " + std::to_string(f) + " is listed twice");
+    }
+    S.fmask.assign(nc, 0);
+    S.cell_frac.assign(6 * (size_t)nc, -1);
+    S.frac_cell.assign(2 * (size_t)nf, -1);
+    if (nf > 0) {
+        for (int32_t K = 0; K < nc; ++K) {
+            const int32_t *cn = hex8 + 8 * (int64_t)K;
+            for (int lf = 0; lf < 6; ++lf) {
+                int32_t q[4];
+                bool all = true;
+                for (int i = 0; i < 4; ++i) {
+                    q[i] = cn[hexf(lf, i)];
+                    all &= S.frac_node[q[i]] != 0;
+                }
+                if (!all) continue;
+                auto it = fmap.find(sorted_key(q));
+                if (it == fmap.end()) continue;
+                int32_t f = it->second;
+                if (!same_cycle(q, frac_nodes + 4 * (int64_t)f))
+                    throw Error(VAG_ERR_MESH, "fracture face " + std::to_string(f) +
+                                                  " nodes are not in cyclic order");
+                int side = S.frac_cell[2 * (size_t)f] < 0 ? 0 : (S.frac_cell[2 * (size_t)f + 1] < 0 ? 1 : 2);
+                if (side == 2)
+                    throw Error(VAG_ERR_MESH, "fracture face " + std::to_string(f) + " has more than two cells");
+                S.frac_cell[2 * (size_t)f + side] = K;  // cells visited in ascending order
+                S.cell_frac[6 * (size_t)K + lf] = f;
+                S.fmask[K] |= (uint8_t)(1u << lf);
+            }
+        }
+    }
+    S.frac_slot.assign(4 * (size_t)nf, -1);
+    for (int32_t f = 0; f < nf; ++f) {
+        int32_t K = S.frac_cell[2 * (size_t)f];
+        if (K < 0) throw Error(VAG_ERR_MESH, "fracture face " + std::to_string(f) + " is not a face of the mesh");
+        for (int i = 0; i < 4; ++i)
+            for (int a = 0; a < 8; ++a)
+                if (hex8[8 * (int64_t)K + a] == frac_nodes[4 * (int64_t)f + i]) S.frac_slot[4 * (size_t)f + i] = a;
+    }
+
+    // node -> (fracture, vertex)
+    S.node_frac_ptr.assign(nn + 1, 0);
+    for (int64_t i = 0; i < 4 * (int64_t)nf; ++i) S.node_frac_ptr[frac_nodes[i] + 1]++;
+    for (int32_t s = 0; s < nn; ++s) S.node_frac_ptr[s + 1] += S.node_frac_ptr[s];
+    S.node_frac.resize(S.node_frac_ptr[nn]);
+    {
+        std::vector<int32_t> fill(S.node_frac_ptr.begin(), S.node_frac_ptr.end() - 1);
+        for (int32_t f = 0; f < nf; ++f)
+            for (int i = 0; i < 4; ++i) S.node_frac[fill[frac_nodes[4 * (int64_t)f + i]]++] = f * 4 + i;
+    }
+
+    // unknowns
+    S.node_unk.assign(nn, -1);
+    int32_t nfree = 0;
+    for (int32_t s = 0; s < nn; ++s)
+        if (!dirichlet[s]) S.node_unk[s] = nfree++;
+    if (nfree == nn) throw Error(VAG_ERR_ARG, "no Dirichlet node: the Darcy problem is singular");
+    S.nfree = nfree;
+    S.nunk = nfree + nf;
+
+    auto cell_unknowns = [&](int32_t K, int32_t *u) {
+        int m = 0;
+        for (int a = 0; a < 8; ++a) u[m++] = S.node_unk[hex8[8 * (int64_t)K + a]];
+        for (int lf = 0; lf < 6; ++lf)
+            if (S.fmask[K] >> lf & 1) u[m++] = nfree + S.cell_frac[6 * (size_t)K + lf];
+        return m;
+    };
+
+    // CSR pattern: row = free node or fracture face
+    S.row_ptr.assign((size_t)S.nunk + 1, 0);
+    std::vector<int32_t> marker((size_t)S.nunk, -1);
+    std::vector<int32_t> cols;
+    cols.reserve(64);
+    // two passes: count then fill
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+            for (int32_t r = 0; r < S.nunk; ++r) S.row_ptr[r + 1] += S.row_ptr[r];
+            if (S.row_ptr[S.nunk] < 0 || (int64_t)S.row_ptr[S.nunk] >= INT32_MAX)
+                throw Error(VAG_ERR_UNSUPPORTED, "system has more than 2^31 nonzeros");
+            S.col.resize(S.row_ptr[S.nunk]);
+            std::fill(marker.begin(), marker.end(), -1);
+        }
+        auto emit_row = [&](int32_t row, const int32_t *cells, int ncells) {
+            cols.clear();
+            for (int c = 0; c < ncells; ++c) {
+                int32_t u[14];
+                int m = cell_unknowns(cells[c], u);
+                for (int i = 0; i < m; ++i)
+                    if (u[i] >= 0 && marker[u[i]] != row) {
+                        marker[u[i]] = row;
+                        cols.push_back(u[i]);
+                    }
+            }
+            if (pass == 0) {
+                S.row_ptr[row + 1] = (int32_t)cols.size();
+            } else {
+                std::sort(cols.begin(), cols.end());
+                std::copy(cols.begin(), cols.end(), S.col.begin() + S.row_ptr[row]);
+            }
+        };
+        std::vector<int32_t> cl;
+        for (int32_t s = 0; s < nn; ++s) {
+            int32_t row = S.node_unk[s];
+            if (row < 0) continue;
+            cl.clear();
+            for (int32_t q = S.node_cell_ptr[s]; q < S.node_cell_ptr[s + 1]; ++q) cl.push_back(S.node_cell[q] >> 3);
+            emit_row(row, cl.data(), (int)cl.size());
+        }
+        for (int32_t f = 0; f < nf; ++f) {
+            int32_t cl2[2];
+            int n2 = 0;
+            for (int side = 0; side < 2; ++side)
+                if (S.frac_cell[2 * (size_t)f + side] >= 0) cl2[n2++] = S.frac_cell[2 * (size_t)f + side];
+            emit_row(nfree + f, cl2, n2);
+        }
+    }
+    S.nnz = S.row_ptr[S.nunk];
+    S.diag_pos.assign(S.nunk, -1);
+    for (int32_t r = 0; r < S.nunk; ++r)
+        for (int32_t q = S.row_ptr[r]; q < S.row_ptr[r + 1]; ++q)
+            if (S.col[q] == r) S.diag_pos[r] = q;
+
+    // slot maps
+    S.slot_ptr.assign((size_t)nc + 1, 0);
+    for (int32_t K = 0; K < nc; ++K) {
+        int m = 8 + __builtin_popcount(S.fmask[K]);
+        S.slot_ptr[K + 1] = S.slot_ptr[K] + m * m;
+    }
+    S.slots.resize(S.slot_ptr[nc]);
+    for (int32_t K = 0; K < nc; ++K) {
+        int32_t u[14];
+        int m = cell_unknowns(K, u);
+        int32_t *out = S.slots.data() + S.slot_ptr[K];
+        for (int a = 0; a < m; ++a)
+            for (int b = 0; b < m; ++b) {
+                int32_t v;
+                if (u[a] < 0) {
+                    v = -1;
+                } else if (u[b] < 0) {
+                    v = -2;
+                } else {
+                    const int32_t *c0 = S.col.data() + S.row_ptr[u[a]];
+                    const int32_t *c1 = S.col.data() + S.row_ptr[u[a] + 1];
+                    v = (int32_t)(std::lower_bound(c0, c1, u[b]) - S.col.data());
+                }
+                out[a * m + b] = v;
+            }
+    }
+
+    // greedy colouring: cells sharing a node get different colours
+    std::vector<int32_t> color(nc, -1);
+    std::vector<int32_t> seen(64, -1);
+    int ncolor = 0;
+    for (int32_t K = 0; K < nc; ++K) {
+        for (int a = 0; a < 8; ++a) {
+            int32_t s = hex8[8 * (int64_t)K + a];
+            for (int32_t q = S.node_cell_ptr[s]; q < S.node_cell_ptr[s + 1]; ++q) {
+                int32_t L = S.node_cell[q] >> 3;
+                if (color[L] >= 0) {
+                    if (color[L] >= (int)seen.size()) seen.resize(color[L] + 1, -1);
+                    seen[color[L]] = K;
+                }
+            }
+        }
+        int c = 0;
+        while (c < (int)seen.size() && seen[c] == K) ++c;
+        color[K] = c;
+        ncolor = std::max(ncolor, c + 1);
+        if (c >= (int)seen.size()) seen.resize(c + 1, -1);
+    }
+    S.ncolor = ncolor;
+    S.color_ptr.assign(ncolor + 1, 0);
+    for (int32_t K = 0; K < nc; ++K) S.color_ptr[color[K] + 1]++;
+    for (int c = 0; c < ncolor; ++c) S.color_ptr[c + 1] += S.color_ptr[c];
+    S.color_cells.resize(nc);
+    {
+        std::vector<int32_t> fill(S.color_ptr.begin(), S.color_ptr.end() - 1);
+        for (int32_t K = 0; K < nc; ++K) S.color_cells[fill[color[K]]++] = K;
+    }
+}
+
+}  // namespace vag

@@ -1,0 +1,519 @@
+// After the Darcy solve: cell recovery (eq eqschurcell), VAG fluxes
+// (eqs VAGFluxMatrix, VAGFluxFracture), porous volumes (§3.2.1), CFL time step
+// (eq eq_CFL) and the explicit upwind steps (eq darcyfluxH, §3.2.2).
+//
+// Control-volume vector layout: [cells | fracture faces | nodes].
+//
+// The fluxes are fixed during transport, so the explicit step is linear:
+// c^{n+1} = T c^n with, per control volume i and dt/phi_i = w_i,
+//   T_ii = 1 - w_i * (sum of outgoing fluxes), T_ij = w_i * (incoming flux from j).
+// Each pair (K,nu) contributes one off-diagonal, in the row of the downstream
+// control volume.  T is built once per transport call, stored in sliced ELL
+// (slices of 64 rows = one wavefront, column-major inside a slice), and every
+// step is one coalesced sweep over it.  Dirichlet nodes keep T_ii = 1, no
+// off-diagonal, so they stay at c_bar.
+#include "reduce.h"
+
+namespace vag {
+
+constexpr int kT = 256;
+static inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+__global__ __launch_bounds__(kT) void node_pressure_kernel(int32_t nn, const int32_t *__restrict__ node_unk,
+                                                           const double *__restrict__ x,
+                                                           const double *__restrict__ p_bar,
+                                                           double *__restrict__ u_node) {
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nn) return;
+    const int32_t k = node_unk[s];
+    u_node[s] = k >= 0 ? x[k] : p_bar[s];
+}
+
+__global__ __launch_bounds__(128) void cell_flux_kernel(
+    int32_t nc, const int32_t *__restrict__ hex8, const uint8_t *__restrict__ fmask,
+    const int32_t *__restrict__ cell_frac, const int32_t *__restrict__ frac_cell, const double *__restrict__ aK,
+    const double *__restrict__ rK, const double *__restrict__ AKK, const double *__restrict__ fside,
+    const double *__restrict__ u_node, const double *__restrict__ u_frac, double *__restrict__ u_cell,
+    double *__restrict__ F_cell, double *__restrict__ F_cell_frac) {
+    const int32_t K = blockIdx.x * blockDim.x + threadIdx.x;
+    if (K >= nc) return;
+    const unsigned mask = fmask[K];
+    double u[8], r[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        u[a] = u_node[hex8[8 * (int64_t)K + a]];
+        r[a] = rK[(int64_t)a * nc + K];
+    }
+    double t = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) t += r[a] * u[a];
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+        if ((mask >> f) & 1u) {
+            const int32_t sg = cell_frac[6 * (int64_t)K + f];
+            const int side = frac_cell[2 * (int64_t)sg] == K ? 0 : 1;
+            t += fside[(2 * (int64_t)sg + side) * 6 + 5] * u_frac[sg];
+        }
+    const double uK = t / AKK[K];  // eq eqschurcell with zero cell right-hand side
+    u_cell[K] = uK;
+    double F[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s += aK[(int64_t)sym8(a, c) * nc + K] * (uK - u[c]);
+        F[a] = s;
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+        if ((mask >> f) & 1u) {
+            const int32_t sg = cell_frac[6 * (int64_t)K + f];
+            const int side = frac_cell[2 * (int64_t)sg] == K ? 0 : 1;
+            const double *o = fside + (2 * (int64_t)sg + side) * 6;
+            const double us = u_frac[sg];
+            double Fs = o[0] * (uK - us);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                Fs += o[1 + i] * (uK - u[hexf(f, i)]);
+                F[hexf(f, i)] += o[1 + i] * (uK - us);
+            }
+            F_cell_frac[2 * (int64_t)sg + side] = Fs;
+        }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) F_cell[8 * (int64_t)K + a] = F[a];
+}
+
+__global__ __launch_bounds__(kT) void frac_flux_kernel(int32_t nf, const int32_t *__restrict__ frac_nodes,
+                                                       const double *__restrict__ A5,
+                                                       const double *__restrict__ u_node,
+                                                       const double *__restrict__ u_frac,
+                                                       double *__restrict__ F_frac) {
+    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    double u[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) u[i] = u_node[frac_nodes[4 * (int64_t)f + i]];
+    const double us = u_frac[f];
+    const double *M = A5 + 25 * (int64_t)f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s += M[5 * (1 + i) + 1 + j] * (us - u[j]);
+        F_frac[4 * (int64_t)f + i] = s;
+    }
+}
+
+// Porous volumes with alpha_{K,s} = 1/16 and alpha_{sigma,s} = 1/8: matrix
+// nodes take 1/16 of each adjacent cell, fracture nodes 1/8 of each adjacent
+// fracture face, Dirichlet nodes nothing.
+__global__ __launch_bounds__(kT) void porous_kernel(
+    int32_t nc, int32_t nf, int32_t nn, const int32_t *__restrict__ hex8, const int32_t *__restrict__ frac_nodes,
+    const uint8_t *__restrict__ dirichlet, const uint8_t *__restrict__ frac_node,
+    const int32_t *__restrict__ ncp, const int32_t *__restrict__ ncl, const int32_t *__restrict__ nfp,
+    const int32_t *__restrict__ nfl, const double *__restrict__ vol, const double *__restrict__ poro,
+    const double *__restrict__ area, const double *__restrict__ fwidth, const double *__restrict__ fporo,
+    double *__restrict__ phi_cell, double *__restrict__ phi_frac, double *__restrict__ phi_node) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nc) {
+        const int32_t K = (int32_t)i;
+        double sa = 0.0;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int32_t s = hex8[8 * (int64_t)K + a];
+            if (!dirichlet[s] && !frac_node[s]) sa += 1.0 / 16.0;
+        }
+        phi_cell[K] = (1.0 - sa) * (vol[K] * poro[K]);
+    } else if (i < (int64_t)nc + nf) {
+        const int32_t f = (int32_t)(i - nc);
+        double sa = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (!dirichlet[frac_nodes[4 * (int64_t)f + k]]) sa += 1.0 / 8.0;
+        phi_frac[f] = (1.0 - sa) * (fwidth[f] * area[f] * fporo[f]);
+    } else if (i < (int64_t)nc + nf + nn) {
+        const int32_t s = (int32_t)(i - nc - nf);
+        double p = 0.0;
+        if (!dirichlet[s]) {
+            if (frac_node[s]) {
+                for (int32_t q = nfp[s]; q < nfp[s + 1]; ++q) {
+                    const int32_t f = nfl[q] >> 2;
+                    p += (1.0 / 8.0) * (fwidth[f] * area[f] * fporo[f]);
+                }
+            } else {
+                for (int32_t q = ncp[s]; q < ncp[s + 1]; ++q) {
+                    const int32_t K = ncl[q] >> 3;
+                    p += (1.0 / 16.0) * (vol[K] * poro[K]);
+                }
+            }
+        }
+        phi_node[s] = p;
+    }
+}
+
+// Sum of outgoing fluxes of a control volume (denominators of eq eq_CFL).
+__device__ inline double cell_out(int32_t K, unsigned mask, const int32_t *cell_frac, const int32_t *frac_cell,
+                                  const double *F_cell, const double *F_cell_frac) {
+    double o = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) o += fmax(F_cell[8 * (int64_t)K + a], 0.0);
+    if (mask) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f)
+            if ((mask >> f) & 1u) {
+                const int32_t sg = cell_frac[6 * (int64_t)K + f];
+                const int side = frac_cell[2 * (int64_t)sg] == K ? 0 : 1;
+                o += fmax(F_cell_frac[2 * (int64_t)sg + side], 0.0);
+            }
+    }
+    return o;
+}
+__device__ inline double frac_out(int32_t f, const int32_t *frac_cell, const double *F_frac,
+                                  const double *F_cell_frac) {
+    double o = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o += fmax(F_frac[4 * (int64_t)f + i], 0.0);
+    for (int side = 0; side < 2; ++side)
+        if (frac_cell[2 * (int64_t)f + side] >= 0) o += fmax(-F_cell_frac[2 * (int64_t)f + side], 0.0);
+    return o;
+}
+__device__ inline double node_out(int32_t s, const int32_t *ncp, const int32_t *ncl, const int32_t *nfp,
+                                  const int32_t *nfl, const double *F_cell, const double *F_frac) {
+    double o = 0.0;
+    for (int32_t q = ncp[s]; q < ncp[s + 1]; ++q) o += fmax(-F_cell[ncl[q]], 0.0);
+    for (int32_t q = nfp[s]; q < nfp[s + 1]; ++q) o += fmax(-F_frac[nfl[q]], 0.0);
+    return o;
+}
+
+__global__ __launch_bounds__(kT) void cfl_kernel(
+    int32_t nc, int32_t nf, int32_t nn, const int32_t *__restrict__ hex8, const uint8_t *__restrict__ fmask,
+    const int32_t *__restrict__ cell_frac, const int32_t *__restrict__ frac_cell,
+    const uint8_t *__restrict__ dirichlet, const int32_t *__restrict__ ncp, const int32_t *__restrict__ ncl,
+    const int32_t *__restrict__ nfp, const int32_t *__restrict__ nfl, const double *__restrict__ F_cell,
+    const double *__restrict__ F_cell_frac, const double *__restrict__ F_frac, const double *__restrict__ phi_cell,
+    const double *__restrict__ phi_frac, const double *__restrict__ phi_node, double cfl, ReduceScratch rs,
+    double *__restrict__ dt_out) {
+    const double inf = __builtin_inf();
+    double v[3] = {inf, inf, inf};
+    const int64_t total = (int64_t)nc + nf + nn;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < nc) {
+            const int32_t K = (int32_t)i;
+            const double o = cell_out(K, fmask[K], cell_frac, frac_cell, F_cell, F_cell_frac);
+            if (o > 0.0) v[0] = fmin(v[0], phi_cell[K] / o);
+        } else if (i < (int64_t)nc + nf) {
+            const int32_t f = (int32_t)(i - nc);
+            const double o = frac_out(f, frac_cell, F_frac, F_cell_frac);
+            if (o > 0.0) v[1] = fmin(v[1], phi_frac[f] / o);
+        } else {
+            const int32_t s = (int32_t)(i - nc - nf);
+            if (!dirichlet[s]) {
+                const double o = node_out(s, ncp, ncl, nfp, nfl, F_cell, F_frac);
+                if (o > 0.0) v[2] = fmin(v[2], phi_node[s] / o);
+            }
+        }
+    }
+    if (grid_reduce<OpMin, 3, kT>(v, rs, 3) && threadIdx.x == 0) {
+        dt_out[0] = v[0];
+        dt_out[1] = v[1];
+        dt_out[2] = v[2];
+        dt_out[3] = cfl * fmin(v[0], fmin(v[1], v[2]));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// upwind operator T in sliced ELL
+// ---------------------------------------------------------------------------
+__device__ inline int upwind_row_count(int64_t i, int32_t nc, int32_t nf, const uint8_t *fmask,
+                                       const int32_t *cell_frac, const int32_t *frac_cell, const uint8_t *dirichlet,
+                                       const int32_t *ncp, const int32_t *ncl, const int32_t *nfp,
+                                       const int32_t *nfl, const double *F_cell, const double *F_cell_frac,
+                                       const double *F_frac) {
+    int c = 0;
+    if (i < nc) {
+        const int32_t K = (int32_t)i;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) c += F_cell[8 * (int64_t)K + a] < 0.0;
+        const unsigned mask = fmask[K];
+        if (mask)
+            for (int f = 0; f < 6; ++f)
+                if ((mask >> f) & 1u) {
+                    const int32_t sg = cell_frac[6 * (int64_t)K + f];
+                    const int side = frac_cell[2 * (int64_t)sg] == K ? 0 : 1;
+                    c += F_cell_frac[2 * (int64_t)sg + side] < 0.0;
+                }
+    } else if (i < (int64_t)nc + nf) {
+        const int32_t f = (int32_t)(i - nc);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c += F_frac[4 * (int64_t)f + k] < 0.0;
+        for (int side = 0; side < 2; ++side)
+            if (frac_cell[2 * (int64_t)f + side] >= 0) c += F_cell_frac[2 * (int64_t)f + side] > 0.0;
+    } else {
+        const int32_t s = (int32_t)(i - nc - nf);
+        if (!dirichlet[s]) {
+            for (int32_t q = ncp[s]; q < ncp[s + 1]; ++q) c += F_cell[ncl[q]] > 0.0;
+            for (int32_t q = nfp[s]; q < nfp[s + 1]; ++q) c += F_frac[nfl[q]] > 0.0;
+        }
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(kSliceRows) void upwind_count_kernel(
+    int32_t nc, int32_t nf, int32_t nn, const uint8_t *__restrict__ fmask, const int32_t *__restrict__ cell_frac,
+    const int32_t *__restrict__ frac_cell, const uint8_t *__restrict__ dirichlet, const int32_t *__restrict__ ncp,
+    const int32_t *__restrict__ ncl, const int32_t *__restrict__ nfp, const int32_t *__restrict__ nfl,
+    const double *__restrict__ F_cell, const double *__restrict__ F_cell_frac, const double *__restrict__ F_frac,
+    int32_t *__restrict__ slice_width, unsigned long long *__restrict__ nnz_total) {
+    // one block = one wavefront = one slice
+    const int64_t i = (int64_t)blockIdx.x * kSliceRows + threadIdx.x;
+    const int64_t total = (int64_t)nc + nf + nn;
+    int c = 0;
+    if (i < total)
+        c = upwind_row_count(i, nc, nf, fmask, cell_frac, frac_cell, dirichlet, ncp, ncl, nfp, nfl, F_cell,
+                             F_cell_frac, F_frac);
+    int sum = c;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        c = max(c, __shfl_down(c, o, 64));
+        sum += __shfl_down(sum, o, 64);
+    }
+    if (threadIdx.x == 0) {
+        slice_width[blockIdx.x] = c;
+        atomicAdd(nnz_total, (unsigned long long)sum);  // integer sum: order-independent
+    }
+}
+
+// exclusive scan of 64 * width over the slices, one block
+__global__ __launch_bounds__(1024) void slice_scan_kernel(int32_t nslice, const int32_t *__restrict__ w,
+                                                          int64_t *__restrict__ ptr) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int32_t chunk = (nslice + 1023) / 1024;
+    const int32_t lo = min(nslice, t * chunk), hi = min(nslice, lo + chunk);
+    int64_t s = 0;
+    for (int32_t k = lo; k < hi; ++k) s += (int64_t)w[k] * kSliceRows;
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t run = 0;
+        for (int k = 0; k < 1024; ++k) {
+            const int64_t v = part[k];
+            part[k] = run;
+            run += v;
+        }
+        ptr[nslice] = run;
+    }
+    __syncthreads();
+    int64_t run = part[t];
+    for (int32_t k = lo; k < hi; ++k) {
+        ptr[k] = run;
+        run += (int64_t)w[k] * kSliceRows;
+    }
+}
+
+__global__ __launch_bounds__(kSliceRows) void upwind_fill_kernel(
+    int32_t nc, int32_t nf, int32_t nn, const int32_t *__restrict__ hex8, const uint8_t *__restrict__ fmask,
+    const int32_t *__restrict__ cell_frac, const int32_t *__restrict__ frac_cell,
+    const int32_t *__restrict__ frac_nodes, const uint8_t *__restrict__ dirichlet, const int32_t *__restrict__ ncp,
+    const int32_t *__restrict__ ncl, const int32_t *__restrict__ nfp, const int32_t *__restrict__ nfl,
+    const double *__restrict__ F_cell, const double *__restrict__ F_cell_frac, const double *__restrict__ F_frac,
+    const double *__restrict__ phi_cell, const double *__restrict__ phi_frac, const double *__restrict__ phi_node,
+    const double *__restrict__ dtp, const int64_t *__restrict__ slice_ptr, int32_t *__restrict__ tcol,
+    double *__restrict__ tval, double *__restrict__ tdiag) {
+    const int64_t i = (int64_t)blockIdx.x * kSliceRows + threadIdx.x;
+    const int64_t total = (int64_t)nc + nf + nn;
+    const int64_t base = slice_ptr[blockIdx.x] + threadIdx.x;
+    const int width = (int)((slice_ptr[blockIdx.x + 1] - slice_ptr[blockIdx.x]) / kSliceRows);
+    if (i >= total) {
+        for (int k = 0; k < width; ++k) {
+            tcol[base + (int64_t)k * kSliceRows] = 0;
+            tval[base + (int64_t)k * kSliceRows] = 0.0;
+        }
+        return;
+    }
+    const double dt = dtp[3];
+    int k = 0;
+    double d = 1.0;
+    auto emit = [&](int64_t c, double v) {
+        tcol[base + (int64_t)k * kSliceRows] = (int32_t)c;
+        tval[base + (int64_t)k * kSliceRows] = v;
+        ++k;
+    };
+    const int32_t off_f = nc, off_n = nc + nf;
+    if (i < nc) {
+        const int32_t K = (int32_t)i;
+        const double w = dt / phi_cell[K];
+        double out = 0.0;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const double F = F_cell[8 * (int64_t)K + a];
+            if (F > 0.0) out += F;
+            else if (F < 0.0) emit(off_n + hex8[8 * (int64_t)K + a], -w * F);
+        }
+        const unsigned mask = fmask[K];
+        if (mask)
+            for (int f = 0; f < 6; ++f)
+                if ((mask >> f) & 1u) {
+                    const int32_t sg = cell_frac[6 * (int64_t)K + f];
+                    const int side = frac_cell[2 * (int64_t)sg] == K ? 0 : 1;
+                    const double F = F_cell_frac[2 * (int64_t)sg + side];
+                    if (F > 0.0) out += F;
+                    else if (F < 0.0) emit(off_f + sg, -w * F);
+                }
+        d = 1.0 - w * out;
+    } else if (i < (int64_t)nc + nf) {
+        const int32_t f = (int32_t)(i - nc);
+        const double w = dt / phi_frac[f];
+        double out = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double F = F_frac[4 * (int64_t)f + q];
+            if (F > 0.0) out += F;
+            else if (F < 0.0) emit(off_n + frac_nodes[4 * (int64_t)f + q], -w * F);
+        }
+        for (int side = 0; side < 2; ++side) {
+            const int32_t K = frac_cell[2 * (int64_t)f + side];
+            if (K < 0) continue;
+            const double F = F_cell_frac[2 * (int64_t)f + side];
+            if (F < 0.0) out -= F;
+            else if (F > 0.0) emit(K, w * F);
+        }
+        d = 1.0 - w * out;
+    } else {
+        const int32_t s = (int32_t)(i - nc - nf);
+        if (!dirichlet[s]) {
+            const double w = dt / phi_node[s];
+            double in_neg = 0.0;
+            for (int32_t q = ncp[s]; q < ncp[s + 1]; ++q) {
+                const double F = F_cell[ncl[q]];
+                if (F < 0.0) in_neg += F;
+                else if (F > 0.0) emit(ncl[q] >> 3, w * F);
+            }
+            for (int32_t q = nfp[s]; q < nfp[s + 1]; ++q) {
+                const double F = F_frac[nfl[q]];
+                if (F < 0.0) in_neg += F;
+                else if (F > 0.0) emit(off_f + (nfl[q] >> 2), w * F);
+            }
+            d = 1.0 + w * in_neg;
+        }
+    }
+    for (; k < width; ++k) {
+        tcol[base + (int64_t)k * kSliceRows] = (int32_t)i;
+        tval[base + (int64_t)k * kSliceRows] = 0.0;
+    }
+    tdiag[i] = d;
+}
+
+// c_out = c + theta (T c - c); theta = 1 is the plain step
+__global__ __launch_bounds__(256) void transport_step_kernel(int32_t nrow, const int64_t *__restrict__ slice_ptr,
+                                                             const int32_t *__restrict__ tcol,
+                                                             const double *__restrict__ tval,
+                                                             const double *__restrict__ tdiag,
+                                                             const double *__restrict__ c_in,
+                                                             double *__restrict__ c_out, double theta) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrow) return;
+    const int32_t sl = i / kSliceRows, lane = i % kSliceRows;
+    const int64_t b0 = slice_ptr[sl], b1 = slice_ptr[sl + 1];
+    const double ci = c_in[i];
+    double acc = tdiag[i] * ci;
+    for (int64_t q = b0 + lane; q < b1; q += kSliceRows) acc += tval[q] * c_in[tcol[q]];
+    c_out[i] = (theta == 1.0) ? acc : ci + theta * (acc - ci);
+}
+
+__global__ void set_dirichlet_kernel(int32_t nn, int32_t offset, const uint8_t *__restrict__ dirichlet,
+                                     const double *__restrict__ c_bar, double *__restrict__ c) {
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nn && dirichlet[s]) c[offset + s] = c_bar[s];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void launch_node_pressure(hipStream_t s, int32_t nn, const int32_t *node_unk, const double *x, const double *p_bar,
+                          double *u_node) {
+    hipLaunchKernelGGL(node_pressure_kernel, dim3(nb(nn, kT)), dim3(kT), 0, s, nn, node_unk, x, p_bar, u_node);
+    VAG_HIP(hipGetLastError());
+}
+void launch_cell_flux(hipStream_t s, int32_t nc, const int32_t *hex8, const uint8_t *fmask,
+                      const int32_t *cell_frac, const int32_t *frac_cell, const double *aK, const double *rK,
+                      const double *AKK, const double *fside, const double *u_node, const double *u_frac,
+                      double *u_cell, double *F_cell, double *F_cell_frac) {
+    hipLaunchKernelGGL(cell_flux_kernel, dim3(nb(nc, 128)), dim3(128), 0, s, nc, hex8, fmask, cell_frac, frac_cell,
+                       aK, rK, AKK, fside, u_node, u_frac, u_cell, F_cell, F_cell_frac);
+    VAG_HIP(hipGetLastError());
+}
+void launch_frac_flux(hipStream_t s, int32_t nf, const int32_t *frac_nodes, const double *A5, const double *u_node,
+                      const double *u_frac, double *F_frac) {
+    if (nf <= 0) return;
+    hipLaunchKernelGGL(frac_flux_kernel, dim3(nb(nf, kT)), dim3(kT), 0, s, nf, frac_nodes, A5, u_node, u_frac,
+                       F_frac);
+    VAG_HIP(hipGetLastError());
+}
+void launch_porous(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,
+                   const int32_t *frac_nodes, const uint8_t *dirichlet, const uint8_t *frac_node,
+                   const int32_t *node_cell_ptr, const int32_t *node_cell, const int32_t *node_frac_ptr,
+                   const int32_t *node_frac, const double *vol, const double *poro, const double *area,
+                   const double *fwidth, const double *fporo, double *phi_cell, double *phi_frac,
+                   double *phi_node) {
+    const int64_t total = (int64_t)nc + nf + nn;
+    hipLaunchKernelGGL(porous_kernel, dim3(nb(total, kT)), dim3(kT), 0, s, nc, nf, nn, hex8, frac_nodes, dirichlet,
+                       frac_node, node_cell_ptr, node_cell, node_frac_ptr, node_frac, vol, poro, area, fwidth,
+                       fporo, phi_cell, phi_frac, phi_node);
+    VAG_HIP(hipGetLastError());
+}
+void launch_cfl(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8, const uint8_t *fmask,
+                const int32_t *cell_frac, const int32_t *frac_cell, const uint8_t *dirichlet,
+                const int32_t *node_cell_ptr, const int32_t *node_cell, const int32_t *node_frac_ptr,
+                const int32_t *node_frac, const double *F_cell, const double *F_cell_frac, const double *F_frac,
+                const double *phi_cell, const double *phi_frac, const double *phi_node, double cfl,
+                ReduceScratch rs, double *dt_out) {
+    const int64_t total = (int64_t)nc + nf + nn;
+    hipLaunchKernelGGL(cfl_kernel, dim3(reduce_grid(total, kT)), dim3(kT), 0, s, nc, nf, nn, hex8, fmask, cell_frac,
+                       frac_cell, dirichlet, node_cell_ptr, node_cell, node_frac_ptr, node_frac, F_cell,
+                       F_cell_frac, F_frac, phi_cell, phi_frac, phi_node, cfl, rs, dt_out);
+    VAG_HIP(hipGetLastError());
+}
+void launch_upwind_count(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const uint8_t *fmask,
+                         const int32_t *cell_frac, const int32_t *frac_cell, const uint8_t *dirichlet,
+                         const int32_t *node_cell_ptr, const int32_t *node_cell, const int32_t *node_frac_ptr,
+                         const int32_t *node_frac, const double *F_cell, const double *F_cell_frac,
+                         const double *F_frac, int32_t *slice_width, unsigned long long *nnz_total) {
+    const int64_t total = (int64_t)nc + nf + nn;
+    hipLaunchKernelGGL(upwind_count_kernel, dim3(nb(total, kSliceRows)), dim3(kSliceRows), 0, s, nc, nf, nn, fmask,
+                       cell_frac, frac_cell, dirichlet, node_cell_ptr, node_cell, node_frac_ptr, node_frac, F_cell,
+                       F_cell_frac, F_frac, slice_width, nnz_total);
+    VAG_HIP(hipGetLastError());
+}
+void launch_slice_scan(hipStream_t s, int32_t nslice, const int32_t *slice_width, int64_t *slice_ptr) {
+    hipLaunchKernelGGL(slice_scan_kernel, dim3(1), dim3(1024), 0, s, nslice, slice_width, slice_ptr);
+    VAG_HIP(hipGetLastError());
+}
+void launch_upwind_fill(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,
+                        const uint8_t *fmask, const int32_t *cell_frac, const int32_t *frac_cell,
+                        const int32_t *frac_nodes, const uint8_t *dirichlet, const int32_t *node_cell_ptr,
+                        const int32_t *node_cell, const int32_t *node_frac_ptr, const int32_t *node_frac,
+                        const double *F_cell, const double *F_cell_frac, const double *F_frac,
+                        const double *phi_cell, const double *phi_frac, const double *phi_node, const double *dt,
+                        const int64_t *slice_ptr, int32_t *tcol, double *tval, double *tdiag) {
+    const int64_t total = (int64_t)nc + nf + nn;
+    hipLaunchKernelGGL(upwind_fill_kernel, dim3(nb(total, kSliceRows)), dim3(kSliceRows), 0, s, nc, nf, nn, hex8,
+                       fmask, cell_frac, frac_cell, frac_nodes, dirichlet, node_cell_ptr, node_cell, node_frac_ptr,
+                       node_frac, F_cell, F_cell_frac, F_frac, phi_cell, phi_frac, phi_node, dt, slice_ptr, tcol,
+                       tval, tdiag);
+    VAG_HIP(hipGetLastError());
+}
+void launch_transport_step(hipStream_t s, int32_t nrow, const int64_t *slice_ptr, const int32_t *tcol,
+                           const double *tval, const double *tdiag, const double *c_in, double *c_out,
+                           double theta) {
+    hipLaunchKernelGGL(transport_step_kernel, dim3(nb(nrow, 256)), dim3(256), 0, s, nrow, slice_ptr, tcol, tval,
+                       tdiag, c_in, c_out, theta);
+    VAG_HIP(hipGetLastError());
+}
+void launch_set_dirichlet(hipStream_t s, int32_t nn, int32_t offset, const uint8_t *dirichlet, const double *c_bar,
+                          double *c) {
+    hipLaunchKernelGGL(set_dirichlet_kernel, dim3(nb(nn, 256)), dim3(256), 0, s, nn, offset, dirichlet, c_bar, c);
+    VAG_HIP(hipGetLastError());
+}
+
+}  // namespace vag

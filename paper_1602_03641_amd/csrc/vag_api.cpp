@@ -1,0 +1,599 @@
+// C-ABI of libvag: handle lifecycle and orchestration of the device phases.
+// Every entry point catches internal errors and returns a vag_status.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "vag_internal.h"
+
+using namespace vag;
+
+struct vag_handle {
+    hipStream_t stream = nullptr;
+    vag_options opt{};
+    std::string err;
+    Tracker tr;
+    Symbolic S;
+    double mu = 1.0;
+
+    // topology
+    DBuf<double> xyz;
+    DBuf<int32_t> hex8, cell_frac, frac_cell, frac_slot, frac_nodes, node_unk, node_cell_ptr, node_cell,
+        node_frac_ptr, node_frac, color_cells, row_ptr, col, diag_pos, slots;
+    DBuf<uint8_t> fmask, dirichlet, frac_node;
+    DBuf<int64_t> slot_ptr;
+    // numeric inputs
+    DBuf<double> perm, poro, fwidth, fperm, fporo, p_bar, c_bar;
+    // assembly
+    DBuf<double> aK, rK, AKK, vol, fside, A5, area, A, b, dinv;
+    DBuf<int> bad;
+    // Krylov
+    DBuf<double> x, r, z, p, q, parts, scal;
+    DBuf<unsigned> ticket;
+    DBuf<PcgState> pcg;
+    // results
+    DBuf<double> u_node, u_cell, u_frac, F_cell, F_cell_frac, F_frac, phi_cell, phi_frac, phi_node;
+    // transport
+    DBuf<int32_t> slice_width, tcol;
+    DBuf<int64_t> slice_ptr;
+    DBuf<double> tval, tdiag, cbuf0, cbuf1, dt4;
+    DBuf<unsigned long long> cnt;
+    unsigned long long *h_cnt = nullptr;
+    int cur = 0;
+    bool solved = false, have_c = false;
+
+    PcgState *h_pcg = nullptr;
+    double *h_scal = nullptr;
+    hipEvent_t ev[8] = {};
+
+    ReduceScratch rs() { return ReduceScratch{parts.p, ticket.p}; }
+    double *c_cur() { return cur ? cbuf1.p : cbuf0.p; }
+    double *c_next() { return cur ? cbuf0.p : cbuf1.p; }
+
+    ~vag_handle() {
+        if (h_pcg) (void)hipHostFree(h_pcg);
+        if (h_scal) (void)hipHostFree(h_scal);
+        if (h_cnt) (void)hipHostFree(h_cnt);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+template <class F>
+vag_status guard(vag_handle *h, F &&fn) {
+    try {
+        fn();
+        if (h) h->err.clear();
+        return VAG_OK;
+    } catch (const Error &e) {
+        if (h) h->err = e.what();
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        if (h) h->err = "host allocation failed";
+        return VAG_ERR_OOM;
+    } catch (const std::exception &e) {
+        if (h) h->err = e.what();
+        return VAG_ERR_ARG;
+    }
+}
+
+hipMemcpyKind kind_in(vag_mem m) { return m == VAG_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
+hipMemcpyKind kind_out(vag_mem m) { return m == VAG_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
+
+template <class T>
+void upload(vag_handle *h, DBuf<T> &d, const T *src, size_t n, vag_mem mem) {
+    if (!n) return;
+    if (!src) throw Error(VAG_ERR_ARG, "null input array");
+    if (d.n < n) d.alloc(n, h->tr);
+    VAG_HIP(hipMemcpyAsync(d.p, src, n * sizeof(T), kind_in(mem), h->stream));
+    if (mem == VAG_MEM_HOST) VAG_HIP(hipStreamSynchronize(h->stream));
+}
+
+template <class T>
+void upload_vec(vag_handle *h, DBuf<T> &d, const std::vector<T> &v) {
+    d.alloc(v.size(), h->tr);
+    if (!v.empty()) VAG_HIP(hipMemcpy(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+template <class T>
+void download(vag_handle *h, T *dst, const DBuf<T> &d, size_t n, vag_mem mem) {
+    if (!dst || !n) return;
+    VAG_HIP(hipMemcpyAsync(dst, d.p, n * sizeof(T), kind_out(mem), h->stream));
+}
+
+// host copy of an input that may live in device memory
+template <class T>
+std::vector<T> host_copy(const T *src, size_t n, vag_mem mem) {
+    std::vector<T> v(n);
+    if (n) {
+        if (!src) throw Error(VAG_ERR_ARG, "null input array");
+        if (mem == VAG_MEM_DEVICE)
+            VAG_HIP(hipMemcpy(v.data(), src, n * sizeof(T), hipMemcpyDeviceToHost));
+        else
+            std::memcpy(v.data(), src, n * sizeof(T));
+    }
+    return v;
+}
+
+void check_options(const vag_options &o) {
+    if (!(o.rtol > 0) || o.max_iter < 0 || !(o.cfl > 0) || o.check_every <= 0)
+        throw Error(VAG_ERR_ARG, "invalid options (rtol, max_iter, cfl or check_every)");
+    if (o.precision != VAG_FP64)
+        throw Error(VAG_ERR_UNSUPPORTED, "only VAG_FP64 is implemented in this build");
+    if (o.krylov != VAG_CG) throw Error(VAG_ERR_UNSUPPORTED, "only VAG_CG is implemented in this build");
+    if (o.precond != VAG_PC_JACOBI && o.precond != VAG_PC_AMG)
+        throw Error(VAG_ERR_ARG, "unknown preconditioner");
+}
+
+// z = M^{-1} r for the handle's preconditioner
+void precond_apply(vag_handle *h, const double *r, double *z);
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) ms = 0.f;
+    return ms;
+}
+
+}  // namespace
+
+namespace {
+void precond_apply(vag_handle *h, const double *r, double *z) {
+    launch_jacobi(h->stream, h->S.nunk, h->dinv.p, r, z);
+}
+}  // namespace
+
+extern "C" {
+
+const char *vag_version(void) { return "libvag 0.1 (gfx950)"; }
+
+vag_status vag_default_options(vag_options *o) {
+    if (!o) return VAG_ERR_ARG;
+    std::memset(o, 0, sizeof *o);
+    o->precision = VAG_FP64;
+    o->krylov = VAG_CG;
+    o->precond = VAG_PC_JACOBI;
+    o->rtol = 1e-8;
+    o->inner_rtol = 1e-4;
+    o->max_iter = 20000;
+    o->gmres_restart = 100;
+    o->check_every = 16;
+    o->cfl = 0.9;
+    o->amg_coarse_size = 500;
+    o->amg_max_levels = 12;
+    o->amg_theta = 0.08;
+    o->amg_sweeps = 1;
+    return VAG_OK;
+}
+
+vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag_rock *rock, const vag_bc *bc,
+                      const vag_options *opt, vag_mem mem, void *hip_stream, vag_handle **out) {
+    if (!out) return VAG_ERR_ARG;
+    *out = nullptr;
+    vag_handle *h = nullptr;
+    try {
+        h = new vag_handle();
+    } catch (...) {
+        g_create_error = "host allocation failed";
+        return VAG_ERR_OOM;
+    }
+    vag_status st = guard(h, [&] {
+        if (!mesh || !rock || !bc) throw Error(VAG_ERR_ARG, "mesh, rock and bc are required");
+        if (!(rock->mu > 0)) throw Error(VAG_ERR_ARG, "viscosity must be positive");
+        h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+        if (opt) h->opt = *opt; else vag_default_options(&h->opt);
+        check_options(h->opt);
+        const int64_t nn = mesh->n_nodes, nc = mesh->n_cells, nf = frac ? frac->n_frac : 0;
+        if (nn <= 0 || nc <= 0 || nf < 0) throw Error(VAG_ERR_ARG, "empty mesh");
+        auto hex8 = host_copy(mesh->hex8, 8 * (size_t)nc, mem);
+        std::vector<int32_t> fnodes = nf ? host_copy(frac->face_nodes, 4 * (size_t)nf, mem) : std::vector<int32_t>();
+        auto dir = host_copy(bc->node_dirichlet, (size_t)nn, mem);
+        build_symbolic(nn, nc, nf, hex8.data(), fnodes.data(), dir.data(), h->S);
+        const Symbolic &S = h->S;
+        h->mu = rock->mu;
+
+        upload(h, h->xyz, mesh->node_xyz, 3 * (size_t)nn, mem);
+        upload_vec(h, h->hex8, hex8);
+        upload_vec(h, h->frac_nodes, fnodes);
+        upload_vec(h, h->dirichlet, dir);
+        upload_vec(h, h->fmask, S.fmask);
+        upload_vec(h, h->cell_frac, S.cell_frac);
+        upload_vec(h, h->frac_cell, S.frac_cell);
+        upload_vec(h, h->frac_slot, S.frac_slot);
+        upload_vec(h, h->node_unk, S.node_unk);
+        upload_vec(h, h->frac_node, S.frac_node);
+        upload_vec(h, h->node_cell_ptr, S.node_cell_ptr);
+        upload_vec(h, h->node_cell, S.node_cell);
+        upload_vec(h, h->node_frac_ptr, S.node_frac_ptr);
+        upload_vec(h, h->node_frac, S.node_frac);
+        upload_vec(h, h->color_cells, S.color_cells);
+        upload_vec(h, h->row_ptr, S.row_ptr);
+        upload_vec(h, h->col, S.col);
+        upload_vec(h, h->diag_pos, S.diag_pos);
+        upload_vec(h, h->slot_ptr, S.slot_ptr);
+        upload_vec(h, h->slots, S.slots);
+
+        upload(h, h->perm, rock->perm, 6 * (size_t)nc, mem);
+        upload(h, h->poro, rock->porosity, (size_t)nc, mem);
+        if (nf) {
+            upload(h, h->fwidth, frac->width, (size_t)nf, mem);
+            upload(h, h->fperm, frac->perm, (size_t)nf, mem);
+            upload(h, h->fporo, frac->porosity, (size_t)nf, mem);
+        }
+        upload(h, h->p_bar, bc->p_bar, (size_t)nn, mem);
+        if (bc->c_bar) upload(h, h->c_bar, bc->c_bar, (size_t)nn, mem);
+        else {
+            h->c_bar.alloc(nn, h->tr);
+            launch_fill(h->stream, nn, 0.0, h->c_bar.p);
+        }
+
+        const size_t n = S.nunk;
+        h->aK.alloc(36 * (size_t)nc, h->tr);
+        h->rK.alloc(8 * (size_t)nc, h->tr);
+        h->AKK.alloc(nc, h->tr);
+        h->vol.alloc(nc, h->tr);
+        h->fside.alloc(12 * (size_t)std::max<int64_t>(nf, 1), h->tr);
+        h->A5.alloc(25 * (size_t)std::max<int64_t>(nf, 1), h->tr);
+        h->area.alloc(std::max<int64_t>(nf, 1), h->tr);
+        h->A.alloc(S.nnz, h->tr);
+        h->b.alloc(n, h->tr);
+        h->dinv.alloc(n, h->tr);
+        h->bad.alloc(1, h->tr);
+        for (auto *v : {&h->x, &h->r, &h->z, &h->p, &h->q}) v->alloc(n, h->tr);
+        h->parts.alloc(4 * (size_t)kReduceBlocks, h->tr);
+        h->ticket.alloc(8, h->tr);
+        VAG_HIP(hipMemset(h->ticket.p, 0, 8 * sizeof(unsigned)));
+        h->scal.alloc(8, h->tr);
+        h->pcg.alloc(1, h->tr);
+        h->u_node.alloc(nn, h->tr);
+        h->u_cell.alloc(nc, h->tr);
+        h->u_frac.alloc(std::max<int64_t>(nf, 1), h->tr);
+        h->F_cell.alloc(8 * (size_t)nc, h->tr);
+        h->F_cell_frac.alloc(2 * (size_t)std::max<int64_t>(nf, 1), h->tr);
+        h->F_frac.alloc(4 * (size_t)std::max<int64_t>(nf, 1), h->tr);
+        h->phi_cell.alloc(nc, h->tr);
+        h->phi_frac.alloc(std::max<int64_t>(nf, 1), h->tr);
+        h->phi_node.alloc(nn, h->tr);
+        const int64_t nrow = nc + nf + nn;
+        const int64_t nslice = (nrow + kSliceRows - 1) / kSliceRows;
+        h->slice_width.alloc(nslice, h->tr);
+        h->slice_ptr.alloc(nslice + 1, h->tr);
+        h->tdiag.alloc(nrow, h->tr);
+        h->cbuf0.alloc(nrow, h->tr);
+        h->cbuf1.alloc(nrow, h->tr);
+        h->dt4.alloc(4, h->tr);
+        h->cnt.alloc(1, h->tr);
+        VAG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_cnt), sizeof(unsigned long long)));
+        VAG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_pcg), sizeof(PcgState)));
+        VAG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_scal), 16 * sizeof(double)));
+        for (auto &e : h->ev) VAG_HIP(hipEventCreate(&e));
+        VAG_HIP(hipStreamSynchronize(h->stream));
+    });
+    if (st != VAG_OK) {
+        g_create_error = h->err;
+        delete h;
+        return st;
+    }
+    *out = h;
+    return VAG_OK;
+}
+
+vag_status vag_update(vag_handle *h, const vag_rock *rock, const vag_fractures *fr, const double *p_bar,
+                      const double *c_bar, vag_mem mem) {
+    if (!h) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        const size_t nn = h->S.nn, nc = h->S.nc, nf = h->S.nf;
+        if (rock) {
+            if (rock->perm) upload(h, h->perm, rock->perm, 6 * nc, mem);
+            if (rock->porosity) upload(h, h->poro, rock->porosity, nc, mem);
+            if (rock->mu > 0) h->mu = rock->mu;
+        }
+        if (fr && nf) {
+            if (fr->width) upload(h, h->fwidth, fr->width, nf, mem);
+            if (fr->perm) upload(h, h->fperm, fr->perm, nf, mem);
+            if (fr->porosity) upload(h, h->fporo, fr->porosity, nf, mem);
+        }
+        if (p_bar) upload(h, h->p_bar, p_bar, nn, mem);
+        if (c_bar) upload(h, h->c_bar, c_bar, nn, mem);
+        h->solved = false;
+    });
+}
+
+vag_status vag_set_options(vag_handle *h, const vag_options *opt) {
+    if (!h || !opt) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        check_options(*opt);
+        h->opt = *opt;
+    });
+}
+
+vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
+    if (!h) return VAG_ERR_ARG;
+    bool converged = true;
+    vag_status st = guard(h, [&] {
+        const Symbolic &S = h->S;
+        hipStream_t s = h->stream;
+        const int32_t n = S.nunk;
+        VAG_HIP(hipEventRecord(h->ev[0], s));
+        // 1. local matrices and fracture matrices
+        VAG_HIP(hipMemsetAsync(h->bad.p, 0x7f, sizeof(int), s));
+        launch_local(s, S.nc, h->xyz.p, h->hex8.p, h->perm.p, h->mu, h->fmask.p, h->cell_frac.p, h->frac_cell.p,
+                     h->aK.p, h->rK.p, h->AKK.p, h->vol.p, h->fside.p, h->bad.p);
+        launch_frac_local(s, S.nf, h->xyz.p, h->frac_nodes.p, h->fwidth.p, h->fperm.p, h->mu, h->A5.p, h->area.p);
+        // 2. cell elimination, colour by colour
+        launch_fill(s, S.nnz, 0.0, h->A.p);
+        launch_fill(s, n, 0.0, h->b.p);
+        for (int c = 0; c < S.ncolor; ++c)
+            launch_scatter(s, S.color_ptr[c + 1] - S.color_ptr[c], h->color_cells.p + S.color_ptr[c], S.nc, S.nfree,
+                           h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->frac_slot.p, h->frac_nodes.p,
+                           h->node_unk.p, h->p_bar.p, h->aK.p, h->rK.p, h->AKK.p, h->fside.p, h->A5.p,
+                           h->slot_ptr.p, h->slots.p, h->A.p, h->b.p);
+        launch_diag_inv(s, n, h->diag_pos.p, h->A.p, h->dinv.p);
+        VAG_HIP(hipEventRecord(h->ev[1], s));
+        VAG_HIP(hipEventRecord(h->ev[2], s));
+        // 3. Krylov
+        if (h->opt.precond == VAG_PC_AMG) {
+            // the AMG hierarchy is not part of this build yet: Jacobi
+        }
+        launch_pcg_init(s, n, h->b.p, h->dinv.p, h->x.p, h->r.p, h->z.p, h->p.p, h->rs(), h->pcg.p, h->opt.rtol,
+                        h->opt.max_iter);
+        for (;;) {
+            for (int k = 0; k < h->opt.check_every; ++k)
+                launch_pcg_iter(s, n, h->row_ptr.p, h->col.p, h->A.p, h->dinv.p, h->x.p, h->r.p, h->z.p, h->p.p,
+                                h->q.p, h->rs(), h->pcg.p);
+            VAG_HIP(hipMemcpyAsync(h->h_pcg, h->pcg.p, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+            VAG_HIP(hipStreamSynchronize(s));
+            if (h->h_pcg->done) break;
+        }
+        VAG_HIP(hipEventRecord(h->ev[3], s));
+        const PcgState pst = *h->h_pcg;
+        converged = pst.converged != 0;
+        // 4. recovery and fluxes
+        launch_node_pressure(s, S.nn, h->node_unk.p, h->x.p, h->p_bar.p, h->u_node.p);
+        if (S.nf) launch_copy(s, S.nf, h->x.p + S.nfree, h->u_frac.p);
+        launch_fill(s, 2 * (int64_t)std::max(S.nf, 1), 0.0, h->F_cell_frac.p);
+        launch_cell_flux(s, S.nc, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->aK.p, h->rK.p, h->AKK.p,
+                         h->fside.p, h->u_node.p, h->u_frac.p, h->u_cell.p, h->F_cell.p, h->F_cell_frac.p);
+        launch_frac_flux(s, S.nf, h->frac_nodes.p, h->A5.p, h->u_node.p, h->u_frac.p, h->F_frac.p);
+        launch_porous(s, S.nc, S.nf, S.nn, h->hex8.p, h->frac_nodes.p, h->dirichlet.p, h->frac_node.p,
+                      h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->vol.p, h->poro.p,
+                      h->area.p, h->fwidth.p, h->fporo.p, h->phi_cell.p, h->phi_frac.p, h->phi_node.p);
+        VAG_HIP(hipEventRecord(h->ev[4], s));
+        // true residual ||b - A x|| / ||b||
+        launch_residual_norm(s, n, h->row_ptr.p, h->col.p, h->A.p, h->x.p, h->b.p, h->r.p, h->rs(), h->scal.p);
+        VAG_HIP(hipMemcpyAsync(h->h_scal, h->scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        int bad = 0;
+        VAG_HIP(hipMemcpyAsync(&bad, h->bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipStreamSynchronize(s));
+        if (bad != 0x7f7f7f7f)
+            throw Error(VAG_ERR_MESH, "cell " + std::to_string(bad) + " has a non-positive sub-tetrahedron");
+        if (info) {
+            std::memset(info, 0, sizeof *info);
+            info->iterations = pst.iter;
+            info->outer_iterations = 1;
+            info->rel_residual = h->h_scal[1] > 0 ? std::sqrt(h->h_scal[0] / h->h_scal[1]) : 0.0;
+            info->n_unknowns = n;
+            info->nnz = S.nnz;
+            info->amg_levels = 0;
+            info->amg_operator_complexity = 1.0;
+            info->ms_assembly = elapsed(h->ev[0], h->ev[1]);
+            info->ms_setup = elapsed(h->ev[1], h->ev[2]);
+            info->ms_solve = elapsed(h->ev[2], h->ev[3]);
+            info->ms_fluxes = elapsed(h->ev[3], h->ev[4]);
+        }
+        h->solved = true;
+        h->have_c = false;
+    });
+    if (st == VAG_OK && !converged) {
+        h->err = "Krylov solve stopped at max_iter before reaching rtol";
+        return VAG_WARN_NOT_CONVERGED;
+    }
+    return st;
+}
+
+vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const double *c0_cell,
+                         const double *c0_frac, const double *c0_node, vag_mem mem, vag_transport_info *info) {
+    if (!h) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        if (!h->solved) throw Error(VAG_ERR_STATE, "vag_transport needs a pressure solve first");
+        if (n_steps < 0 || t_final < 0) throw Error(VAG_ERR_ARG, "negative step count or final time");
+        const Symbolic &S = h->S;
+        hipStream_t s = h->stream;
+        const int64_t nrow = (int64_t)S.nc + S.nf + S.nn;
+        const int32_t nslice = (int32_t)((nrow + kSliceRows - 1) / kSliceRows);
+        VAG_HIP(hipEventRecord(h->ev[5], s));
+        launch_cfl(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
+                   h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
+                   h->F_cell_frac.p, h->F_frac.p, h->phi_cell.p, h->phi_frac.p, h->phi_node.p, h->opt.cfl, h->rs(),
+                   h->dt4.p);
+        VAG_HIP(hipMemsetAsync(h->cnt.p, 0, sizeof(unsigned long long), s));
+        launch_upwind_count(s, S.nc, S.nf, S.nn, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
+                            h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
+                            h->F_cell_frac.p, h->F_frac.p, h->slice_width.p, h->cnt.p);
+        launch_slice_scan(s, nslice, h->slice_width.p, h->slice_ptr.p);
+        int64_t total = 0;
+        VAG_HIP(hipMemcpyAsync(&total, h->slice_ptr.p + nslice, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipMemcpyAsync(h->h_cnt, h->cnt.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipMemcpyAsync(h->h_scal, h->dt4.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipStreamSynchronize(s));
+        const double dt = h->h_scal[3];
+        double dtb[3] = {h->h_scal[0], h->h_scal[1], h->h_scal[2]};
+        if (!(dt < INFINITY)) throw Error(VAG_ERR_ARG, "no control volume has an outflow: CFL bound is infinite");
+        if ((size_t)total > h->tcol.n) {
+            h->tcol.alloc((size_t)total + (size_t)total / 8, h->tr);
+            h->tval.alloc((size_t)total + (size_t)total / 8, h->tr);
+        }
+        launch_upwind_fill(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p,
+                           h->frac_nodes.p, h->dirichlet.p, h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p,
+                           h->node_frac.p, h->F_cell.p, h->F_cell_frac.p, h->F_frac.p, h->phi_cell.p, h->phi_frac.p,
+                           h->phi_node.p, h->dt4.p, h->slice_ptr.p, h->tcol.p, h->tval.p, h->tdiag.p);
+        // initial state
+        if (c0_cell || c0_frac || c0_node) {
+            if (!c0_cell || !c0_node || (S.nf && !c0_frac))
+                throw Error(VAG_ERR_ARG, "give all of c0_cell, c0_frac, c0_node or none");
+            h->cur = 0;
+            VAG_HIP(hipMemcpyAsync(h->cbuf0.p, c0_cell, S.nc * sizeof(double), kind_in(mem), s));
+            if (S.nf)
+                VAG_HIP(hipMemcpyAsync(h->cbuf0.p + S.nc, c0_frac, S.nf * sizeof(double), kind_in(mem), s));
+            VAG_HIP(hipMemcpyAsync(h->cbuf0.p + S.nc + S.nf, c0_node, S.nn * sizeof(double), kind_in(mem), s));
+            if (mem == VAG_MEM_HOST) VAG_HIP(hipStreamSynchronize(s));
+        } else if (!h->have_c) {
+            h->cur = 0;
+            launch_fill(s, nrow, 0.0, h->cbuf0.p);
+        }
+        launch_set_dirichlet(s, S.nn, S.nc + S.nf, h->dirichlet.p, h->c_bar.p, h->c_cur());
+        h->have_c = true;
+        int64_t N = n_steps;
+        double theta_last = 1.0, last_dt = dt;
+        if (t_final > 0) {
+            N = (int64_t)std::ceil(t_final / dt);
+            if (N < 1) N = 1;
+            last_dt = t_final - (double)(N - 1) * dt;
+            theta_last = last_dt / dt;
+        }
+        VAG_HIP(hipEventRecord(h->ev[6], s));
+        for (int64_t k = 0; k < N; ++k) {
+            const double th = (k == N - 1) ? theta_last : 1.0;
+            launch_transport_step(s, (int32_t)nrow, h->slice_ptr.p, h->tcol.p, h->tval.p, h->tdiag.p, h->c_cur(),
+                                  h->c_next(), th);
+            h->cur ^= 1;
+        }
+        VAG_HIP(hipEventRecord(h->ev[7], s));
+        VAG_HIP(hipEventSynchronize(h->ev[7]));
+        if (info) {
+            std::memset(info, 0, sizeof *info);
+            info->n_steps = N;
+            info->dt = dt;
+            info->last_dt = last_dt;
+            for (int i = 0; i < 3; ++i) info->dt_bounds[i] = dtb[i];
+            info->ms_setup = elapsed(h->ev[5], h->ev[6]);
+            info->ms_steps = elapsed(h->ev[6], h->ev[7]);
+            info->n_rows = nrow;
+            info->t_nnz = h->h_cnt[0];
+            info->t_stored = total;
+        }
+    });
+}
+
+vag_status vag_get_pressure(vag_handle *h, double *u_node, double *u_cell, double *u_frac, vag_mem mem) {
+    if (!h) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        if (!h->solved) throw Error(VAG_ERR_STATE, "no pressure solve yet");
+        download(h, u_node, h->u_node, h->S.nn, mem);
+        download(h, u_cell, h->u_cell, h->S.nc, mem);
+        download(h, u_frac, h->u_frac, h->S.nf, mem);
+        VAG_HIP(hipStreamSynchronize(h->stream));
+    });
+}
+
+vag_status vag_get_fluxes(vag_handle *h, double *F_cell, double *F_cell_frac, double *F_frac, vag_mem mem) {
+    if (!h) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        if (!h->solved) throw Error(VAG_ERR_STATE, "no pressure solve yet");
+        download(h, F_cell, h->F_cell, 8 * (size_t)h->S.nc, mem);
+        download(h, F_cell_frac, h->F_cell_frac, 2 * (size_t)h->S.nf, mem);
+        download(h, F_frac, h->F_frac, 4 * (size_t)h->S.nf, mem);
+        VAG_HIP(hipStreamSynchronize(h->stream));
+    });
+}
+
+vag_status vag_get_porous_volumes(vag_handle *h, double *phi_cell, double *phi_frac, double *phi_node,
+                                  vag_mem mem) {
+    if (!h) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        if (!h->solved) throw Error(VAG_ERR_STATE, "no pressure solve yet");
+        download(h, phi_cell, h->phi_cell, h->S.nc, mem);
+        download(h, phi_frac, h->phi_frac, h->S.nf, mem);
+        download(h, phi_node, h->phi_node, h->S.nn, mem);
+        VAG_HIP(hipStreamSynchronize(h->stream));
+    });
+}
+
+vag_status vag_get_concentration(vag_handle *h, double *c_cell, double *c_frac, double *c_node, vag_mem mem) {
+    if (!h) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        if (!h->have_c) throw Error(VAG_ERR_STATE, "no transport yet");
+        const Symbolic &S = h->S;
+        hipMemcpyKind k = kind_out(mem);
+        if (c_cell) VAG_HIP(hipMemcpyAsync(c_cell, h->c_cur(), S.nc * sizeof(double), k, h->stream));
+        if (c_frac && S.nf) VAG_HIP(hipMemcpyAsync(c_frac, h->c_cur() + S.nc, S.nf * sizeof(double), k, h->stream));
+        if (c_node) VAG_HIP(hipMemcpyAsync(c_node, h->c_cur() + S.nc + S.nf, S.nn * sizeof(double), k, h->stream));
+        VAG_HIP(hipStreamSynchronize(h->stream));
+    });
+}
+
+vag_status vag_system_size(vag_handle *h, int64_t *n, int64_t *nnz) {
+    if (!h || !n || !nnz) return VAG_ERR_ARG;
+    *n = h->S.nunk;
+    *nnz = h->S.nnz;
+    return VAG_OK;
+}
+
+vag_status vag_get_system(vag_handle *h, int64_t *row_ptr, int64_t *col, double *val, double *b, vag_mem mem) {
+    if (!h) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        if (!h->solved) throw Error(VAG_ERR_STATE, "no pressure solve yet");
+        const Symbolic &S = h->S;
+        std::vector<int64_t> rp(S.row_ptr.begin(), S.row_ptr.end()), cl(S.col.begin(), S.col.end());
+        hipMemcpyKind k = mem == VAG_MEM_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
+        if (row_ptr) VAG_HIP(hipMemcpy(row_ptr, rp.data(), rp.size() * sizeof(int64_t), k));
+        if (col) VAG_HIP(hipMemcpy(col, cl.data(), cl.size() * sizeof(int64_t), k));
+        download(h, val, h->A, S.nnz, mem);
+        download(h, b, h->b, S.nunk, mem);
+        VAG_HIP(hipStreamSynchronize(h->stream));
+    });
+}
+
+vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms) {
+    if (!h || !ms || reps <= 0) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        if (!h->solved) throw Error(VAG_ERR_STATE, "no pressure solve yet");
+        const Symbolic &S = h->S;
+        hipStream_t s = h->stream;
+        const int64_t nrow = (int64_t)S.nc + S.nf + S.nn;
+        if (kernel == VAG_KERNEL_TRANSPORT_STEP && !h->have_c)
+            throw Error(VAG_ERR_STATE, "the transport step needs a transport call first");
+        auto once = [&] {
+            switch (kernel) {
+                case VAG_KERNEL_SPMV:
+                    launch_spmv(s, S.nunk, h->row_ptr.p, h->col.p, h->A.p, h->x.p, h->q.p);
+                    break;
+                case VAG_KERNEL_TRANSPORT_STEP:  // reads the current state, writes the spare buffer
+                    launch_transport_step(s, (int32_t)nrow, h->slice_ptr.p, h->tcol.p, h->tval.p, h->tdiag.p,
+                                          h->c_cur(), h->c_next(), 1.0);
+                    break;
+                case VAG_KERNEL_LOCAL:
+                    launch_local(s, S.nc, h->xyz.p, h->hex8.p, h->perm.p, h->mu, h->fmask.p, h->cell_frac.p,
+                                 h->frac_cell.p, h->aK.p, h->rK.p, h->AKK.p, h->vol.p, h->fside.p, h->bad.p);
+                    break;
+                case VAG_KERNEL_PRECOND:
+                    precond_apply(h, h->r.p, h->z.p);
+                    break;
+                default:
+                    throw Error(VAG_ERR_ARG, "unknown kernel id");
+            }
+        };
+        once();  // warm
+        VAG_HIP(hipEventRecord(h->ev[5], s));
+        for (int k = 0; k < reps; ++k) once();
+        VAG_HIP(hipEventRecord(h->ev[6], s));
+        VAG_HIP(hipEventSynchronize(h->ev[6]));
+        *ms = elapsed(h->ev[5], h->ev[6]) / reps;
+    });
+}
+
+size_t vag_footprint_bytes(const vag_handle *h) { return h ? h->tr.bytes : 0; }
+
+const char *vag_last_error(const vag_handle *h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+void vag_destroy(vag_handle *h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    delete h;
+}
+
+}  // extern "C"

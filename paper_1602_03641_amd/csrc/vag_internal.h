@@ -1,0 +1,198 @@
+// Internal declarations of libvag: device buffers, the handle, the symbolic
+// phase and the kernel launchers.  Nothing here crosses the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "vag.h"
+
+namespace vag {
+
+// ---------------------------------------------------------------------------
+// errors: thrown inside the library, turned into a vag_status at the ABI
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+    vag_status status;
+    Error(vag_status s, const std::string &m) : std::runtime_error(m), status(s) {}
+};
+
+#define VAG_HIP(call)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            throw ::vag::Error(e_ == hipErrorOutOfMemory ? VAG_ERR_OOM : VAG_ERR_HIP,  \
+                               std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+// Faces of a VTK hexahedron, cyclic and outward oriented (right-hand rule), so
+// that every sub-tetrahedron (x_K, x_sigma, s_e, s_e+1) of a valid cell has a
+// positive signed volume.
+__host__ __device__ constexpr int hexf(int f, int i) {
+    constexpr int t[24] = {0, 4, 7, 3, 1, 2, 6, 5, 0, 1, 5, 4, 3, 7, 6, 2, 0, 3, 2, 1, 4, 5, 6, 7};
+    return t[f * 4 + i];
+}
+// packed upper triangle of a symmetric 8x8 block
+__host__ __device__ constexpr int sym8(int i, int j) {
+    return i <= j ? i * 8 - i * (i - 1) / 2 + (j - i) : j * 8 - j * (j - 1) / 2 + (i - j);
+}
+// packed upper triangle of a symmetric 5x5 block
+__host__ __device__ constexpr int sym5(int i, int j) {
+    return i <= j ? i * 5 - i * (i - 1) / 2 + (j - i) : j * 5 - j * (j - 1) / 2 + (i - j);
+}
+
+constexpr int kSliceRows = 64;      // SELL slice height = one wavefront
+constexpr int kReduceBlocks = 1024; // fixed grid of the deterministic reductions
+constexpr int kReduceThreads = 256;
+
+// ---------------------------------------------------------------------------
+// device buffer
+// ---------------------------------------------------------------------------
+struct Tracker {
+    size_t bytes = 0;
+};
+
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    Tracker *tr = nullptr;
+    void alloc(size_t count, Tracker &t) {
+        release();
+        tr = &t;
+        n = count;
+        if (count) {
+            VAG_HIP(hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T)));
+            t.bytes += count * sizeof(T);
+        }
+    }
+    void release() {
+        if (p) {
+            (void)hipFree(p);
+            if (tr) tr->bytes -= n * sizeof(T);
+        }
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+    ~DBuf() { release(); }
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+};
+
+// ---------------------------------------------------------------------------
+// symbolic phase (host): topology-only data structures
+// ---------------------------------------------------------------------------
+struct Symbolic {
+    int32_t nn = 0, nc = 0, nf = 0, nfree = 0, nunk = 0;
+    int64_t nnz = 0;
+    std::vector<uint8_t> fmask;        // [nc] bit f = local face f is a fracture face
+    std::vector<int32_t> cell_frac;    // [nc*6] fracture index of local face, -1
+    std::vector<int32_t> frac_cell;    // [nf*2] cells of sigma, ascending, -1 if absent
+    std::vector<int32_t> frac_slot;    // [nf*4] slot (0..7) in frac_cell[.,0] of input node i
+    std::vector<int32_t> node_unk;     // [nn] unknown index, -1 for Dirichlet nodes
+    std::vector<uint8_t> frac_node;    // [nn] node of some fracture face
+    std::vector<int32_t> node_cell_ptr, node_cell;  // node -> cell*8+slot, ascending
+    std::vector<int32_t> node_frac_ptr, node_frac;  // node -> frac*4+i, ascending
+    int ncolor = 0;
+    std::vector<int32_t> color_ptr, color_cells;     // cells grouped by colour
+    std::vector<int32_t> row_ptr, col, diag_pos;     // CSR pattern of the eliminated system
+    std::vector<int64_t> slot_ptr;                   // [nc+1]
+    std::vector<int32_t> slots;                      // per cell m*m positions (-1 Dirichlet row, -2 Dirichlet col)
+};
+
+// Builds the symbolic data; throws vag::Error on invalid input.
+void build_symbolic(int64_t nn, int64_t nc, int64_t nf, const int32_t *hex8,
+                    const int32_t *frac_nodes, const uint8_t *dirichlet, Symbolic &S);
+
+// ---------------------------------------------------------------------------
+// kernel launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+struct ReduceScratch {  // deterministic grid reductions: block partials + ticket
+    double *parts;      // [kReduceBlocks * 4]
+    unsigned *ticket;   // [4]
+};
+
+struct PcgState {       // device-resident scalars of a Krylov solve
+    double rz, pq, alpha, beta, rr, bnorm2, tol2, pad;
+    int iter, done, max_iter, converged;
+};
+
+// assembly
+void launch_local(hipStream_t s, int32_t nc, const double *xyz, const int32_t *hex8, const double *perm,
+                  double mu, const uint8_t *fmask, const int32_t *cell_frac, const int32_t *frac_cell,
+                  double *aK, double *rK, double *AKK, double *vol, double *fside, int *bad_cell);
+void launch_frac_local(hipStream_t s, int32_t nf, const double *xyz, const int32_t *frac_nodes,
+                       const double *width, const double *perm, double mu, double *A5, double *area);
+void launch_scatter(hipStream_t s, int32_t ncell_color, const int32_t *cells, int32_t nc, int32_t nfree,
+                    const int32_t *hex8, const uint8_t *fmask, const int32_t *cell_frac,
+                    const int32_t *frac_cell, const int32_t *frac_slot, const int32_t *frac_nodes,
+                    const int32_t *node_unk, const double *p_bar, const double *aK, const double *rK,
+                    const double *AKK, const double *fside, const double *A5, const int64_t *slot_ptr,
+                    const int32_t *slots, double *A, double *b);
+void launch_diag_inv(hipStream_t s, int32_t n, const int32_t *diag_pos, const double *A, double *dinv);
+
+// Krylov
+void launch_fill(hipStream_t s, int64_t n, double v, double *x);
+void launch_copy(hipStream_t s, int64_t n, const double *src, double *dst);
+void launch_jacobi(hipStream_t s, int64_t n, const double *dinv, const double *r, double *z);
+void launch_spmv(hipStream_t s, int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                 const double *x, double *y);
+void launch_residual_norm(hipStream_t s, int32_t n, const int32_t *rp, const int32_t *col,
+                          const double *val, const double *x, const double *b, double *r,
+                          ReduceScratch rs, double *out2 /* [2]: ||b-Ax||^2, ||b||^2 */);
+void launch_pcg_init(hipStream_t s, int32_t n, const double *b, const double *dinv, double *x, double *r,
+                     double *z, double *p, ReduceScratch rs, PcgState *st, double rtol, int max_iter);
+void launch_pcg_iter(hipStream_t s, int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                     const double *dinv, double *x, double *r, double *z, double *p, double *q,
+                     ReduceScratch rs, PcgState *st);
+
+// recovery, fluxes, transport
+void launch_node_pressure(hipStream_t s, int32_t nn, const int32_t *node_unk, const double *x,
+                          const double *p_bar, double *u_node);
+void launch_cell_flux(hipStream_t s, int32_t nc, const int32_t *hex8, const uint8_t *fmask,
+                      const int32_t *cell_frac, const int32_t *frac_cell, const double *aK,
+                      const double *rK, const double *AKK, const double *fside, const double *u_node,
+                      const double *u_frac, double *u_cell, double *F_cell, double *F_cell_frac);
+void launch_frac_flux(hipStream_t s, int32_t nf, const int32_t *frac_nodes, const double *A5,
+                      const double *u_node, const double *u_frac, double *F_frac);
+void launch_porous(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,
+                   const int32_t *frac_nodes, const uint8_t *dirichlet, const uint8_t *frac_node,
+                   const int32_t *node_cell_ptr, const int32_t *node_cell, const int32_t *node_frac_ptr,
+                   const int32_t *node_frac, const double *vol, const double *poro, const double *area,
+                   const double *fwidth, const double *fporo, double *phi_cell, double *phi_frac,
+                   double *phi_node);
+void launch_cfl(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,
+                const uint8_t *fmask, const int32_t *cell_frac, const int32_t *frac_cell,
+                const uint8_t *dirichlet, const int32_t *node_cell_ptr, const int32_t *node_cell,
+                const int32_t *node_frac_ptr, const int32_t *node_frac, const double *F_cell,
+                const double *F_cell_frac, const double *F_frac, const double *phi_cell,
+                const double *phi_frac, const double *phi_node, double cfl, ReduceScratch rs,
+                double *dt_out /* [4]: dtM, dtF, dtV, dt */);
+void launch_upwind_count(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const uint8_t *fmask,
+                         const int32_t *cell_frac, const int32_t *frac_cell, const uint8_t *dirichlet,
+                         const int32_t *node_cell_ptr, const int32_t *node_cell,
+                         const int32_t *node_frac_ptr, const int32_t *node_frac, const double *F_cell,
+                         const double *F_cell_frac, const double *F_frac, int32_t *slice_width,
+                         unsigned long long *nnz_total);
+void launch_slice_scan(hipStream_t s, int32_t nslice, const int32_t *slice_width, int64_t *slice_ptr);
+void launch_upwind_fill(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,
+                        const uint8_t *fmask, const int32_t *cell_frac, const int32_t *frac_cell,
+                        const int32_t *frac_nodes, const uint8_t *dirichlet, const int32_t *node_cell_ptr,
+                        const int32_t *node_cell, const int32_t *node_frac_ptr, const int32_t *node_frac,
+                        const double *F_cell, const double *F_cell_frac, const double *F_frac,
+                        const double *phi_cell, const double *phi_frac, const double *phi_node,
+                        const double *dt, const int64_t *slice_ptr, int32_t *tcol, double *tval,
+                        double *tdiag);
+void launch_transport_step(hipStream_t s, int32_t nrow, const int64_t *slice_ptr, const int32_t *tcol,
+                           const double *tval, const double *tdiag, const double *c_in, double *c_out,
+                           double theta);
+void launch_set_dirichlet(hipStream_t s, int32_t nn, int32_t offset, const uint8_t *dirichlet,
+                          const double *c_bar, double *c);
+
+}  // namespace vag

@@ -1,0 +1,269 @@
+"""Python binding of libvag (argument marshalling only).
+
+The functions ``vag_*`` mirror the C-ABI of ``include/vag.h`` one to one.
+``Handle`` is a convenience owner of a ``vag_handle*`` that keeps inputs and
+outputs in torch tensors on the GPU (torch provides device memory and the
+stream; every step of the computation runs in the library's HIP kernels).
+
+The library must be built (``paper_1602_03641_amd.build.build()``); loading
+fails loudly otherwise — there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvag.so")
+
+VAG_OK, VAG_WARN_NOT_CONVERGED = 0, 1
+VAG_ERR_ARG, VAG_ERR_MESH, VAG_ERR_UNSUPPORTED, VAG_ERR_OOM, VAG_ERR_HIP, VAG_ERR_STATE = -1, -2, -3, -4, -5, -6
+VAG_MEM_HOST, VAG_MEM_DEVICE = 0, 1
+VAG_FP64, VAG_MIXED = 0, 1
+VAG_CG, VAG_GMRES = 0, 1
+VAG_PC_JACOBI, VAG_PC_AMG = 0, 1
+VAG_KERNEL_SPMV, VAG_KERNEL_TRANSPORT_STEP, VAG_KERNEL_LOCAL, VAG_KERNEL_PRECOND = 0, 1, 2, 3
+
+STATUS_NAMES = {0: "VAG_OK", 1: "VAG_WARN_NOT_CONVERGED", -1: "VAG_ERR_ARG", -2: "VAG_ERR_MESH",
+                -3: "VAG_ERR_UNSUPPORTED", -4: "VAG_ERR_OOM", -5: "VAG_ERR_HIP", -6: "VAG_ERR_STATE"}
+
+vp = C.c_void_p
+
+
+class vag_mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_cells", C.c_int64), ("node_xyz", vp), ("hex8", vp)]
+
+
+class vag_fractures(C.Structure):
+    _fields_ = [("n_frac", C.c_int64), ("face_nodes", vp), ("width", vp), ("perm", vp), ("porosity", vp)]
+
+
+class vag_rock(C.Structure):
+    _fields_ = [("perm", vp), ("porosity", vp), ("mu", C.c_double)]
+
+
+class vag_bc(C.Structure):
+    _fields_ = [("node_dirichlet", vp), ("p_bar", vp), ("c_bar", vp)]
+
+
+class vag_options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("krylov", C.c_int), ("precond", C.c_int), ("rtol", C.c_double),
+                ("inner_rtol", C.c_double), ("max_iter", C.c_int), ("gmres_restart", C.c_int),
+                ("check_every", C.c_int), ("cfl", C.c_double), ("amg_coarse_size", C.c_int),
+                ("amg_max_levels", C.c_int), ("amg_theta", C.c_double), ("amg_sweeps", C.c_int),
+                ("reserved", C.c_int * 8)]
+
+
+class vag_solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("outer_iterations", C.c_int), ("rel_residual", C.c_double),
+                ("n_unknowns", C.c_int64), ("nnz", C.c_int64), ("amg_levels", C.c_int),
+                ("amg_operator_complexity", C.c_double), ("ms_assembly", C.c_double),
+                ("ms_setup", C.c_double), ("ms_solve", C.c_double), ("ms_fluxes", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class vag_transport_info(C.Structure):
+    _fields_ = [("n_steps", C.c_int64), ("dt", C.c_double), ("last_dt", C.c_double),
+                ("dt_bounds", C.c_double * 3), ("ms_setup", C.c_double), ("ms_steps", C.c_double),
+                ("n_rows", C.c_int64), ("t_nnz", C.c_int64), ("t_stored", C.c_int64)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["dt_bounds"] = list(self.dt_bounds)
+        return d
+
+
+# name -> (argtypes, restype)
+_SIGS = {
+    "vag_version": ([], C.c_char_p),
+    "vag_default_options": ([C.POINTER(vag_options)], C.c_int),
+    "vag_create": ([C.POINTER(vag_mesh), C.POINTER(vag_fractures), C.POINTER(vag_rock), C.POINTER(vag_bc),
+                    C.POINTER(vag_options), C.c_int, vp, C.POINTER(vp)], C.c_int),
+    "vag_update": ([vp, C.POINTER(vag_rock), C.POINTER(vag_fractures), vp, vp, C.c_int], C.c_int),
+    "vag_set_options": ([vp, C.POINTER(vag_options)], C.c_int),
+    "vag_solve_pressure": ([vp, C.POINTER(vag_solve_info)], C.c_int),
+    "vag_transport": ([vp, C.c_int64, C.c_double, vp, vp, vp, C.c_int, C.POINTER(vag_transport_info)], C.c_int),
+    "vag_get_pressure": ([vp, vp, vp, vp, C.c_int], C.c_int),
+    "vag_get_fluxes": ([vp, vp, vp, vp, C.c_int], C.c_int),
+    "vag_get_porous_volumes": ([vp, vp, vp, vp, C.c_int], C.c_int),
+    "vag_get_concentration": ([vp, vp, vp, vp, C.c_int], C.c_int),
+    "vag_system_size": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
+    "vag_get_system": ([vp, vp, vp, vp, vp, C.c_int], C.c_int),
+    "vag_benchmark_kernel": ([vp, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
+    "vag_footprint_bytes": ([vp], C.c_size_t),
+    "vag_last_error": ([vp], C.c_char_p),
+    "vag_destroy": ([vp], None),
+}
+
+_lib = None
+
+
+def load():
+    """Loads libvag.so; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1602_03641_amd.build.build()")
+        lib = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def __getattr__(name):  # vag_* functions resolve to the C symbols
+    if name.startswith("vag_") and name in _SIGS:
+        return getattr(load(), name)
+    raise AttributeError(name)
+
+
+class VagError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def default_options(**kw) -> vag_options:
+    o = vag_options()
+    load().vag_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
+
+
+class Handle:
+    """Owns a vag_handle built from a problem description (numpy arrays).
+
+    Inputs are moved to the GPU as torch tensors and passed as device memory;
+    the handle is bound to torch's current HIP stream.
+    """
+
+    def __init__(self, prob, options=None, device="cuda", **opt_kw):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        lib = load()
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=self.device)  # noqa: E731
+        self.nn, self.nc, self.nf = int(prob.xyz.shape[0]), int(prob.hex8.shape[0]), int(prob.frac_nodes.shape[0])
+        self._in = dict(
+            xyz=t(prob.xyz, torch.float64), hex8=t(prob.hex8, torch.int32),
+            frac_nodes=t(np.asarray(prob.frac_nodes).reshape(-1, 4), torch.int32),
+            frac_width=t(prob.frac_width, torch.float64), frac_perm=t(prob.frac_perm, torch.float64),
+            frac_poro=t(prob.frac_poro, torch.float64), perm=t(prob.perm, torch.float64),
+            poro=t(prob.poro, torch.float64), dirichlet=t(prob.dirichlet, torch.uint8),
+            p_bar=t(prob.p_bar, torch.float64), c_bar=t(prob.c_bar, torch.float64))
+        i = self._in
+        self.mesh = vag_mesh(self.nn, self.nc, _dptr(i["xyz"]), _dptr(i["hex8"]))
+        self.frac = vag_fractures(self.nf, _dptr(i["frac_nodes"]), _dptr(i["frac_width"]),
+                                  _dptr(i["frac_perm"]), _dptr(i["frac_poro"]))
+        self.rock = vag_rock(_dptr(i["perm"]), _dptr(i["poro"]), float(prob.mu))
+        self.bc = vag_bc(_dptr(i["dirichlet"]), _dptr(i["p_bar"]), _dptr(i["c_bar"]))
+        self.options = options if options is not None else default_options(**opt_kw)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        h = C.c_void_p()
+        st = lib.vag_create(C.byref(self.mesh), C.byref(self.frac), C.byref(self.rock), C.byref(self.bc),
+                            C.byref(self.options), VAG_MEM_DEVICE, C.c_void_p(stream), C.byref(h))
+        if st != VAG_OK:
+            raise VagError(st, lib.vag_last_error(None).decode())
+        self.h = h
+
+    def _check(self, st):
+        if st < 0:
+            raise VagError(st, load().vag_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().vag_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_options(self, **kw):
+        for k, v in kw.items():
+            setattr(self.options, k, v)
+        self._check(load().vag_set_options(self.h, C.byref(self.options)))
+
+    def solve_pressure(self):
+        info = vag_solve_info()
+        st = self._check(load().vag_solve_pressure(self.h, C.byref(info)))
+        d = info.as_dict()
+        d["status"] = st
+        return d
+
+    def transport(self, n_steps=0, t_final=0.0, c0=None):
+        info = vag_transport_info()
+        args = (None, None, None)
+        if c0 is not None:
+            tt = [self.torch.as_tensor(np.ascontiguousarray(c0[k]), dtype=self.torch.float64, device=self.device)
+                  for k in ("c_cell", "c_frac", "c_node")]
+            self._c0 = tt
+            args = tuple(_dptr(x) for x in tt)
+        self._check(load().vag_transport(self.h, int(n_steps), float(t_final), *args, VAG_MEM_DEVICE,
+                                         C.byref(info)))
+        return info.as_dict()
+
+    def _get3(self, fn, shapes):
+        outs = [self.torch.empty(s, dtype=self.torch.float64, device=self.device) for s in shapes]
+        self._check(fn(self.h, *[_dptr(o) for o in outs], VAG_MEM_DEVICE))
+        return outs
+
+    def pressure(self):
+        u_node, u_cell, u_frac = self._get3(load().vag_get_pressure, [(self.nn,), (self.nc,), (self.nf,)])
+        return dict(u_node=u_node, u_cell=u_cell, u_frac=u_frac)
+
+    def fluxes(self):
+        a, b, c = self._get3(load().vag_get_fluxes, [(self.nc, 8), (self.nf, 2), (self.nf, 4)])
+        return dict(F_cell=a, F_cell_frac=b, F_frac=c)
+
+    def porous_volumes(self):
+        a, b, c = self._get3(load().vag_get_porous_volumes, [(self.nc,), (self.nf,), (self.nn,)])
+        return dict(phi_cell=a, phi_frac=b, phi_node=c)
+
+    def concentration(self):
+        a, b, c = self._get3(load().vag_get_concentration, [(self.nc,), (self.nf,), (self.nn,)])
+        return dict(c_cell=a, c_frac=b, c_node=c)
+
+    def system(self):
+        n = C.c_int64()
+        nnz = C.c_int64()
+        self._check(load().vag_system_size(self.h, C.byref(n), C.byref(nnz)))
+        rp = np.zeros(n.value + 1, np.int64)
+        col = np.zeros(nnz.value, np.int64)
+        val = np.zeros(nnz.value)
+        b = np.zeros(n.value)
+        p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+        self._check(load().vag_get_system(self.h, p(rp), p(col), p(val), p(b), VAG_MEM_HOST))
+        return rp, col, val, b
+
+    def benchmark_kernel(self, kernel, reps=50):
+        ms = C.c_double()
+        self._check(load().vag_benchmark_kernel(self.h, int(kernel), int(reps), C.byref(ms)))
+        return ms.value
+
+    def footprint_bytes(self):
+        return int(load().vag_footprint_bytes(self.h))
+
+
+def to_numpy(d):
+    return {k: v.detach().cpu().numpy() if hasattr(v, "detach") else v for k, v in d.items()}

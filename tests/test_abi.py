@@ -1,0 +1,102 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+- the shared library loads and exports every entry point declared in
+  include/vag.h;
+- input validation done on the host (before any device work) returns the
+  documented status codes.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from paper_1602_03641_amd import vag
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "vag.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vag_[a-z_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    lib = vag.load()
+    names = declared_functions()
+    assert len(names) >= 16
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in vag.h but not exported"
+    assert set(names) == set(vag.exported_symbols())
+
+
+def test_version_and_defaults():
+    assert vag.load().vag_version().startswith(b"libvag")
+    o = vag.default_options()
+    assert o.precision == vag.VAG_FP64 and o.rtol == 1e-8 and o.cfl == 0.9
+
+
+def _host_create(p, **opt):
+    """vag_create with host arrays; returns (status, error text)."""
+    lib = vag.load()
+    keep = []
+
+    def ptr(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data_as(C.c_void_p) if a.size else None
+
+    mesh = vag.vag_mesh(p.n_nodes, p.n_cells, ptr(p.xyz, np.float64), ptr(p.hex8, np.int32))
+    fr = vag.vag_fractures(len(p.frac_nodes), ptr(np.asarray(p.frac_nodes).reshape(-1, 4), np.int32),
+                           ptr(p.frac_width, np.float64), ptr(p.frac_perm, np.float64), ptr(p.frac_poro, np.float64))
+    rock = vag.vag_rock(ptr(p.perm, np.float64), ptr(p.poro, np.float64), p.mu)
+    bc = vag.vag_bc(ptr(p.dirichlet, np.uint8), ptr(p.p_bar, np.float64), ptr(p.c_bar, np.float64))
+    o = vag.default_options(**opt)
+    h = C.c_void_p()
+    st = lib.vag_create(C.byref(mesh), C.byref(fr), C.byref(rock), C.byref(bc), C.byref(o), vag.VAG_MEM_HOST,
+                        None, C.byref(h))
+    assert not h.value
+    return st, lib.vag_last_error(None).decode()
+
+
+def test_duplicate_fracture_face_rejected():
+    p = synth.cartesian_problem(3, planes=[(0, 1, 0, 3, 0, 3)])
+    p.frac_nodes = np.concatenate([p.frac_nodes, p.frac_nodes[:1, ::-1]])
+    p.frac_width, p.frac_perm, p.frac_poro = [np.append(a, a[0]) for a in (p.frac_width, p.frac_perm, p.frac_poro)]
+    st, msg = _host_create(p)
+    assert st == vag.VAG_ERR_ARG and "listed twice" in msg
+
+
+def test_no_dirichlet_rejected():
+    p = synth.cartesian_problem(2)
+    p.dirichlet[:] = 0
+    st, msg = _host_create(p)
+    assert st == vag.VAG_ERR_ARG and "Dirichlet" in msg
+
+
+def test_fracture_face_not_in_mesh():
+    p = synth.cartesian_problem(3, planes=[(0, 1, 0, 3, 0, 3)])
+    p.frac_nodes[0] = [0, 1, 2, 3]   # not the node set of any cell face
+    st, msg = _host_create(p)
+    assert st == vag.VAG_ERR_MESH and "not a face" in msg
+
+
+def test_fracture_face_not_cyclic():
+    p = synth.cartesian_problem(3, planes=[(0, 1, 0, 3, 0, 3)])
+    p.frac_nodes[1] = p.frac_nodes[1][[0, 2, 1, 3]]
+    st, msg = _host_create(p)
+    assert st == vag.VAG_ERR_MESH and "cyclic" in msg
+
+
+def test_bad_indices_and_options():
+    p = synth.cartesian_problem(2)
+    p.hex8 = p.hex8.copy()
+    p.hex8[1, 3] = 10 ** 6
+    st, msg = _host_create(p)
+    assert st == vag.VAG_ERR_ARG and "out of range" in msg
+    p = synth.cartesian_problem(2)
+    assert _host_create(p, rtol=-1.0)[0] == vag.VAG_ERR_ARG
+    assert _host_create(p, cfl=0.0)[0] == vag.VAG_ERR_ARG

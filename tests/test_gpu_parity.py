@@ -1,0 +1,201 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 CPU oracle.
+
+Tolerances (FP64 path): pressures and fluxes relative L2 <= 1e-8 with both
+sides solved to a relative residual of 1e-13 (conditioning leaves the forward
+error well below that), concentrations <= 1e-10 max-abs.  The assembled
+system itself is compared entry by entry (same unknown order on both sides):
+only the summation order differs, so 1e-12 relative suffices.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, float).ravel()
+    b = np.asarray(b, float).ravel()
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def gpu_run(p, n_steps=None, t_final=None, **opt):
+    _torch()
+    from paper_1602_03641_amd import vag
+    opt.setdefault("cfl", p.cfl)
+    h = vag.Handle(p, **opt)
+    info = h.solve_pressure()
+    out = dict(info=info, **vag.to_numpy(h.pressure()), **vag.to_numpy(h.fluxes()),
+               **vag.to_numpy(h.porous_volumes()))
+    n_steps = p.n_steps if n_steps is None else n_steps
+    t_final = p.t_final if t_final is None else t_final
+    if n_steps or t_final:
+        out["tinfo"] = h.transport(n_steps=n_steps, t_final=t_final)
+        out.update(vag.to_numpy(h.concentration()))
+    out["handle"] = h
+    return out
+
+
+def flux_err(a, b, scale):
+    """max |a - b| relative to the global flux scale (fluxes may vanish exactly)."""
+    a = np.asarray(a, float)
+    return float(np.abs(a - b).max() / scale) if a.size else 0.0
+
+
+def compare(p, g, o, c_tol=1e-10, p_tol=1e-8):
+    d = o["darcy"]
+    assert rel_l2(g["u_node"], d["u_node"]) <= p_tol
+    assert rel_l2(g["u_cell"], d["u_cell"]) <= p_tol
+    scale = max(np.abs(d["F_cell"]).max(), np.abs(d["F_frac"]).max() if p.n_frac else 0.0)
+    assert flux_err(g["F_cell"], d["F_cell"], scale) <= 1e2 * p_tol
+    if p.n_frac:
+        assert rel_l2(g["u_frac"], d["u_frac"]) <= p_tol
+        assert flux_err(g["F_frac"], d["F_frac"], scale) <= 1e2 * p_tol
+        assert flux_err(g["F_cell_frac"], d["F_cell_frac"], scale) <= 1e2 * p_tol
+    for k in ("phi_cell", "phi_frac", "phi_node"):
+        assert rel_l2(g[k], o["phi"][k]) <= 1e-13
+    if "c_cell" in g:
+        assert g["tinfo"]["n_steps"] == o["n_steps"]
+        assert g["tinfo"]["dt"] == pytest.approx(o["dt"], rel=1e-9)
+        for k in ("c_cell", "c_frac", "c_node"):
+            if g[k].size:
+                assert np.abs(g[k] - o[k]).max() <= c_tol, k
+
+
+def test_config1_parity():
+    p = synth.config1()
+    g = gpu_run(p, rtol=1e-13, max_iter=5000)
+    o = oracle.run(p, rtol=1e-13)
+    assert g["info"]["status"] == 0
+    assert g["info"]["rel_residual"] < 1e-12
+    compare(p, g, o)
+    # exact linear solution of config 1
+    np.testing.assert_allclose(g["u_node"], 1 - p.xyz[:, 0], atol=1e-11)
+    np.testing.assert_allclose(g["u_frac"], 0.5, atol=1e-11)
+
+
+def test_config1_system_entries():
+    """The assembled eliminated system equals the oracle's entry by entry."""
+    p = synth.config1()
+    g = gpu_run(p, n_steps=0)
+    rp, col, val, b = g["handle"].system()
+    A, bo = oracle.system(p)
+    np.testing.assert_array_equal(rp, A.indptr)
+    np.testing.assert_array_equal(col, A.indices)
+    scale = np.abs(A.data).max()
+    assert np.abs(val - A.data).max() <= 1e-13 * scale
+    assert np.abs(b - bo).max() <= 1e-13 * max(np.abs(bo).max(), 1e-300)
+
+
+@pytest.mark.parametrize("dims,seed,patches", [((9, 7, 5), 1, 4), ((6, 11, 4), 2, 6), ((13, 5, 6), 3, 8),
+                                               ((5, 5, 5), 4, 12)])
+def test_random_parity(dims, seed, patches):
+    """Jittered cells, full anisotropic tensors, random fracture patches with
+    contrasts 1e2..1e6 (intersections, boundary fractures); several blocks of
+    each kernel plus a ragged tail."""
+    p = synth.random_problem(dims, seed, n_patches=patches, n_steps=30)
+    g = gpu_run(p, rtol=1e-13, max_iter=20000)
+    o = oracle.run(p, rtol=1e-13)
+    # system entries
+    rp, col, val, b = g["handle"].system()
+    A, bo = oracle.system(p)
+    np.testing.assert_array_equal(col, A.indices)
+    assert np.abs(val - A.data).max() <= 1e-12 * np.abs(A.data).max()
+    compare(p, g, o)
+
+
+def test_e1_time_grid_parity():
+    """§5.1 case: final time reached with a shortened last step."""
+    p = synth.e1_problem(32)
+    g = gpu_run(p, rtol=1e-13, max_iter=20000)
+    o = oracle.run(p, rtol=1e-13)
+    assert g["tinfo"]["last_dt"] == pytest.approx(o["last_dt"], rel=1e-8)
+    compare(p, g, o)
+
+
+def test_config2_full_size():
+    """The benchmark workload (64^3, four clipped fractures, contrast 1e4)."""
+    p = synth.config2()
+    g = gpu_run(p, rtol=1e-12, max_iter=20000)
+    o = oracle.run(p, rtol=1e-12)
+    assert g["info"]["status"] == 0
+    compare(p, g, o, p_tol=1e-8, c_tol=1e-10)
+
+
+def test_determinism_bitwise():
+    """Colour-ordered assembly and fixed-shape reductions: two runs agree bit for bit."""
+    p = synth.random_problem((8, 6, 7), 9, n_patches=5, n_steps=20)
+    a = gpu_run(p, rtol=1e-12)
+    b = gpu_run(p, rtol=1e-12)
+    for k in ("u_node", "u_cell", "u_frac", "F_cell", "F_frac", "c_cell", "c_node", "c_frac"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_not_converged_warning():
+    from paper_1602_03641_amd import vag
+    _torch()
+    h = vag.Handle(synth.config1(), rtol=1e-14, max_iter=2, check_every=1)
+    info = h.solve_pressure()
+    assert info["status"] == vag.VAG_WARN_NOT_CONVERGED
+    assert info["iterations"] == 2
+
+
+def test_inverted_cell_reported():
+    from paper_1602_03641_amd import vag
+    _torch()
+    p = synth.cartesian_problem(3)
+    p.hex8 = p.hex8[:, [4, 5, 6, 7, 0, 1, 2, 3]].copy()  # cell 0..: top and bottom swapped
+    p.hex8[1:] = synth.cartesian_problem(3).hex8[1:]
+    h = vag.Handle(p)
+    with pytest.raises(vag.VagError) as e:
+        h.solve_pressure()
+    assert e.value.status == vag.VAG_ERR_MESH and "cell 0" in str(e.value)
+
+
+def test_transport_before_solve():
+    from paper_1602_03641_amd import vag
+    _torch()
+    h = vag.Handle(synth.config1())
+    with pytest.raises(vag.VagError) as e:
+        h.transport(n_steps=1)
+    assert e.value.status == vag.VAG_ERR_STATE
+
+
+def test_tiny_meshes():
+    """Degenerate sizes: one cell (every node Dirichlet), and two cells split
+    by one fracture face whose nodes are all free except the x-walls."""
+    p = synth.cartesian_problem(1, n_steps=3)
+    g = gpu_run(p)
+    o = oracle.run(p)
+    compare(p, g, o)
+    p = synth.cartesian_problem(2, planes=[(0, 1, 0, 2, 0, 2)], ratio=1e6, n_steps=5)
+    g = gpu_run(p, rtol=1e-13)
+    o = oracle.run(p, rtol=1e-13)
+    compare(p, g, o)
+
+
+def test_continue_and_restart_transport():
+    """Transport in two calls equals one call; passing c0 restarts from it."""
+    from paper_1602_03641_amd import vag
+    _torch()
+    p = synth.random_problem((6, 5, 4), 5, n_patches=3)
+    h = vag.Handle(p, rtol=1e-12)
+    h.solve_pressure()
+    h.transport(n_steps=10)
+    mid = vag.to_numpy(h.concentration())
+    h.transport(n_steps=15)
+    a = vag.to_numpy(h.concentration())
+    h.transport(n_steps=15, c0=mid)
+    b = vag.to_numpy(h.concentration())
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
