@@ -119,6 +119,8 @@ def main():
         "phase_ms": {k: round(sinfo[k], 3) for k in ("ms_assembly", "ms_setup", "ms_solve", "ms_fluxes")}
         | {"transport_setup": round(tinfo["ms_setup"], 3), "transport_steps": round(tinfo["ms_steps"], 3)},
         "symbolic_s": round(symbolic_s, 3),
+        "amg_levels": h.amg_levels() if args.precond == "amg" else None,
+        "outer_iterations": sinfo["outer_iterations"],
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -211,6 +211,15 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
                          const double *c0_frac, const double *c0_node, vag_mem mem,
                          vag_transport_info *info);
 
+/*
+ * Transport on given Darcy fluxes (layout of vag_get_fluxes) instead of those
+ * of a pressure solve: the fluxes replace the handle's, porous volumes are
+ * computed from its geometry and porosities, and vag_transport may follow.
+ * Pressures stay unavailable until the next vag_solve_pressure.
+ */
+vag_status vag_set_fluxes(vag_handle *h, const double *F_cell, const double *F_cell_frac, const double *F_frac,
+                          vag_mem mem);
+
 /* Pressures: u_node[n_nodes] (Dirichlet nodes carry p_bar), u_cell[n_cells],
  * u_frac[n_frac].  Any pointer may be NULL. */
 vag_status vag_get_pressure(vag_handle *h, double *u_node, double *u_cell, double *u_frac,
@@ -245,6 +254,10 @@ vag_status vag_get_system(vag_handle *h, int64_t *row_ptr, int64_t *col, double 
  * launch from HIP events.  Scratch vectors only are written.
  */
 vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms_per_launch);
+
+/* AMG hierarchy of the last solve: number of levels, rows and stored entries
+ * (sliced ELL incl. padding) per level, for up to max_levels levels. */
+vag_status vag_amg_levels(vag_handle *h, int *nlev, int64_t *rows, int64_t *stored, int max_levels);
 
 /* Device bytes held by the handle. */
 size_t vag_footprint_bytes(const vag_handle *h);

@@ -1,0 +1,103 @@
+// Host orchestration of the aggregation AMG hierarchy (kernels in amg.hip).
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "vag_internal.h"
+
+namespace vag {
+
+// kernel launchers (amg.hip)
+void amg_launch_diag(hipStream_t s, Sell<double> A, double *diag, double *dinv);
+void amg_launch_mis(hipStream_t s, Sell<double> A, const double *diag, double theta, int rounds, uint64_t *T,
+                    uint64_t *T1, int *undecided, int32_t *flag);
+void amg_launch_scan(hipStream_t s, int32_t n, const int32_t *in, int32_t *out);
+void amg_launch_aggregate(hipStream_t s, Sell<double> A, const double *diag, double theta, const int32_t *root,
+                          const int32_t *rid, int32_t *agg1, int32_t *agg, int32_t *lonely);
+void amg_launch_lonely(hipStream_t s, int32_t n, const int32_t *lonely, const int32_t *lid, const int32_t *nroot,
+                       int32_t *agg);
+void amg_launch_members(hipStream_t s, int32_t n, int32_t nc, const int32_t *agg, int32_t *cnt, int32_t *ptr,
+                        int32_t *cursor, int32_t *rows);
+void amg_launch_galerkin(hipStream_t s, Sell<double> A, const int32_t *agg, const int32_t *mptr,
+                         const int32_t *mrows, int32_t nc, int mode, int32_t *rowlen, const int64_t *cptr,
+                         int32_t *ccol, double *cval, int *overflow);
+void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t *width, int64_t *ptr);
+void amg_launch_slice_tail(hipStream_t s, int32_t n, const int64_t *ptr, int32_t *col, double *val);
+void amg_launch_dense_inverse(hipStream_t s, Sell<double> A, double *D);
+template <class V, class X>
+void amg_launch_pre(hipStream_t s, Sell<V> A, const X *dinv, const X *b, X *x, X *r, const PcgState *st);
+template <class X>
+void amg_launch_restrict(hipStream_t s, int32_t nc, const int32_t *mptr, const int32_t *mrows, const X *r, X *bc,
+                         const PcgState *st);
+template <class V, class X>
+void amg_launch_post(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, const int32_t *agg,
+                     const X *e, X *out, const PcgState *st);
+template <class X>
+void amg_launch_dense(hipStream_t s, int32_t n, const X *Ainv, const X *b, X *x, const PcgState *st);
+template <class V, class X>
+void amg_launch_sweep(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, X *out, const PcgState *st);
+void launch_to_float(hipStream_t s, int64_t n, const double *a, float *b);
+void launch_to_double(hipStream_t s, int64_t n, const float *a, double *b);
+
+// grow-only device buffer (keeps its allocation across solves)
+template <class T>
+void ensure(DBuf<T> &b, size_t n, Tracker &t) {
+    if (b.n < n) b.alloc(n + n / 8 + 64, t);
+}
+
+struct AmgLevel {
+    int32_t n = 0;
+    int64_t stored = 0;             // SELL entries incl. padding
+    DBuf<int64_t> ptr;              // owned storage (coarse levels)
+    DBuf<int32_t> col;
+    DBuf<double> val;
+    Sell<double> A;                 // view (level 0: the handle's matrix)
+    DBuf<double> diag, dinv;
+    DBuf<int32_t> agg, mptr, mrows; // aggregation to the next level
+    DBuf<double> b, xa, xb, r;      // cycle vectors
+    DBuf<float> val32, dinv32, b32, xa32, xb32, r32;
+    Sell<float> A32;
+};
+
+struct AmgOptions {
+    double theta = 0.02;
+    int coarse_size = 256;
+    int max_levels = 12;
+    int mis_rounds = 32;
+    int dense_max = 1024;
+    int coarse_sweeps = 4;
+};
+
+class Amg {
+  public:
+    std::vector<std::unique_ptr<AmgLevel>> L;
+    int nlev = 0;
+    bool dense = false;
+    bool have32 = false;
+    double op_complexity = 1.0;
+    DBuf<double> Ainv;
+    DBuf<float> Ainv32;
+
+    // Builds the hierarchy for A0 (n0 rows); host-synchronises a few times per level.
+    void setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, const AmgOptions &o);
+    // Single-precision copy of every level (values, smoother, coarse inverse).
+    void make_fp32(hipStream_t s, Tracker &tr, const int32_t *A0col);
+    // z = M^-1 r, one V-cycle (FP64 or FP32); st may be null
+    void apply(hipStream_t s, const double *r, double *z, const PcgState *st);
+    void apply32(hipStream_t s, const float *r, float *z, const PcgState *st);
+
+  private:
+    DBuf<uint64_t> T_, T1_;
+    DBuf<int32_t> flag_, rid_, agg1_, lonely_, lid_, cnt_, cursor_, rowlen_, width_;
+    DBuf<int> counters_;
+    int32_t *h_ = nullptr;  // pinned host scratch
+    AmgOptions o_;
+    template <class V, class X>
+    void cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bool fp32);
+
+  public:
+    ~Amg();
+};
+
+}  // namespace vag

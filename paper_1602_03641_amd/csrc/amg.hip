@@ -1,0 +1,599 @@
+// Aggregation AMG for the SPD system of eq eqschur, set up on the device at
+// every solve (the matrix values change with the permeabilities).
+//
+// Coarsening (one level):
+//   strength   j is a strong neighbour of i if |a_ij| >= theta sqrt(|a_ii a_jj|)
+//   roots      a distance-2 maximal independent set of the strength graph,
+//              found by rounds of 2-hop max propagation of (state, hash, index)
+//              keys; a fixed number of rounds, later rounds exit at once when
+//              nothing is left undecided (no host synchronisation)
+//   aggregates each root starts one; other nodes join their strongest root
+//              neighbour, then the strongest already-aggregated neighbour
+//   P          piecewise-constant interpolation (one 1 per row)
+//   A_c        = P^T A P, one wavefront per coarse row: the (coarse column,
+//              fine position) keys of the aggregate's rows are bitonic-sorted
+//              in LDS and each coarse entry sums its fine entries in position
+//              order, so the coarse matrix is bitwise reproducible
+// Smoother: l1-Jacobi, M = diag(sum_j |a_ij|), convergent for any SPD matrix.
+// Cycle: symmetric V-cycle (one pre- and one post-sweep), the coarsest level
+// solved by a dense inverse formed on the device by Gauss-Jordan elimination.
+#include "reduce.h"
+
+namespace vag {
+
+constexpr int kAT = 256;
+constexpr int kCap = 8192;  // candidate entries per coarse row held in LDS
+
+#define GS(i, n) \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+static inline unsigned gridv(int64_t n) { return reduce_grid(n, kAT); }
+
+__device__ inline uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+__device__ inline int rank_of(uint64_t t) { return (int)(t >> 62); }
+
+template <class V>
+__device__ inline bool strong(const V *val, const int32_t *col, int64_t q, int32_t i, double di,
+                              const double *diag, double theta, int32_t &j, double &s) {
+    j = col[q];
+    const double a = fabs((double)val[q]);
+    if (j == i || a == 0.0) return false;
+    const double dd = sqrt(fabs(di * diag[j]));
+    s = a / dd;
+    return a >= theta * dd;
+}
+
+// diag and l1-Jacobi inverse
+__global__ __launch_bounds__(kAT) void amg_diag_kernel(Sell<double> A, double *__restrict__ diag,
+                                                       double *__restrict__ dinv) {
+    GS(i, A.n) {
+        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
+        double d = 0.0, l1 = 0.0;
+        for (int64_t q = b0 + (i & 63); q < b1; q += 64) {
+            const double v = A.val[q];
+            if (A.col[q] == i) d += v;
+            l1 += fabs(v);
+        }
+        diag[i] = d;
+        dinv[i] = 1.0 / l1;
+    }
+}
+
+__global__ __launch_bounds__(kAT) void mis_init_kernel(int32_t n, uint64_t *__restrict__ T) {
+    GS(i, n) T[i] = (1ull << 62) | ((uint64_t)(mix32((uint32_t)i) & 0x3fffffffu) << 32) | (uint64_t)(uint32_t)i;
+}
+
+// Tout[i] = max of T over {i} and its strong neighbours
+__global__ __launch_bounds__(kAT) void mis_max_kernel(Sell<double> A, const double *__restrict__ diag,
+                                                      double theta, const uint64_t *__restrict__ Tin,
+                                                      uint64_t *__restrict__ Tout, const int *__restrict__ active) {
+    if (active && *active == 0) return;
+    GS(i, A.n) {
+        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
+        const double di = diag[i];
+        uint64_t m = Tin[i];
+        for (int64_t q = b0 + (i & 63); q < b1; q += 64) {
+            int32_t j;
+            double s;
+            if (strong(A.val, A.col, q, (int32_t)i, di, diag, theta, j, s)) m = max(m, Tin[j]);
+        }
+        Tout[i] = m;
+    }
+}
+
+// second hop, then the decision of undecided nodes
+__global__ __launch_bounds__(kAT) void mis_select_kernel(Sell<double> A, const double *__restrict__ diag,
+                                                         double theta, const uint64_t *__restrict__ T1,
+                                                         uint64_t *__restrict__ T, int *__restrict__ undecided,
+                                                         const int *__restrict__ active) {
+    if (active && *active == 0) return;
+    int cnt = 0;
+    GS(i, A.n) {
+        const uint64_t own = T[i];
+        if (rank_of(own) != 1) continue;
+        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
+        const double di = diag[i];
+        uint64_t m = T1[i];
+        for (int64_t q = b0 + (i & 63); q < b1; q += 64) {
+            int32_t j;
+            double s;
+            if (strong(A.val, A.col, q, (int32_t)i, di, diag, theta, j, s)) m = max(m, T1[j]);
+        }
+        if (m == own)
+            T[i] = (own & ~(3ull << 62)) | (2ull << 62);  // root
+        else if (rank_of(m) == 2)
+            T[i] = own & ~(3ull << 62);  // a root lies within distance 2
+        else
+            ++cnt;
+    }
+    if (cnt) atomicAdd(undecided, cnt);  // integer count, order-independent
+}
+
+// roots (and nodes left undecided) flagged 1
+__global__ __launch_bounds__(kAT) void mis_flag_kernel(int32_t n, const uint64_t *__restrict__ T,
+                                                       int32_t *__restrict__ flag) {
+    GS(i, n) flag[i] = rank_of(T[i]) >= 1 ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kAT) void agg_pass1_kernel(Sell<double> A, const double *__restrict__ diag, double theta,
+                                                        const int32_t *__restrict__ root, const int32_t *__restrict__ rid,
+                                                        int32_t *__restrict__ agg1) {
+    GS(i, A.n) {
+        if (root[i]) {
+            agg1[i] = rid[i];
+            continue;
+        }
+        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
+        const double di = diag[i];
+        double best = -1.0;
+        int32_t bj = -1;
+        for (int64_t q = b0 + (i & 63); q < b1; q += 64) {
+            int32_t j;
+            double s;
+            if (strong(A.val, A.col, q, (int32_t)i, di, diag, theta, j, s) && root[j] &&
+                (s > best || (s == best && j < bj))) {
+                best = s;
+                bj = j;
+            }
+        }
+        agg1[i] = bj >= 0 ? rid[bj] : -1;
+    }
+}
+
+__global__ __launch_bounds__(kAT) void agg_pass2_kernel(Sell<double> A, const double *__restrict__ diag, double theta,
+                                                        const int32_t *__restrict__ agg1, int32_t *__restrict__ agg,
+                                                        int32_t *__restrict__ lonely) {
+    GS(i, A.n) {
+        int32_t a = agg1[i];
+        if (a < 0) {
+            const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
+            const double di = diag[i];
+            double best = -1.0;
+            int32_t bj = -1;
+            for (int64_t q = b0 + (i & 63); q < b1; q += 64) {
+                int32_t j;
+                double s;
+                if (strong(A.val, A.col, q, (int32_t)i, di, diag, theta, j, s) && agg1[j] >= 0 &&
+                    (s > best || (s == best && j < bj))) {
+                    best = s;
+                    bj = j;
+                }
+            }
+            if (bj >= 0) a = agg1[bj];
+        }
+        agg[i] = a;
+        lonely[i] = a < 0 ? 1 : 0;
+    }
+}
+
+// nodes reached by neither pass become singleton aggregates after the roots
+__global__ __launch_bounds__(kAT) void agg_lonely_kernel(int32_t n, const int32_t *__restrict__ lonely,
+                                                         const int32_t *__restrict__ lid, const int32_t *__restrict__ nroot,
+                                                         int32_t *__restrict__ agg) {
+    GS(i, n) if (lonely[i]) agg[i] = *nroot + lid[i];
+}
+
+__global__ __launch_bounds__(kAT) void count_kernel(int32_t n, const int32_t *__restrict__ agg,
+                                                    int32_t *__restrict__ cnt) {
+    GS(i, n) atomicAdd(&cnt[agg[i]], 1);
+}
+__global__ __launch_bounds__(kAT) void members_fill_kernel(int32_t n, const int32_t *__restrict__ agg,
+                                                           const int32_t *__restrict__ ptr, int32_t *__restrict__ cursor,
+                                                           int32_t *__restrict__ rows) {
+    GS(i, n) {
+        const int32_t a = agg[i];
+        rows[ptr[a] + atomicAdd(&cursor[a], 1)] = (int32_t)i;
+    }
+}
+// insertion sort of each aggregate's rows (atomic fill order is arbitrary)
+__global__ __launch_bounds__(kAT) void members_sort_kernel(int32_t nc, const int32_t *__restrict__ ptr,
+                                                           int32_t *__restrict__ rows) {
+    GS(I, nc) {
+        const int32_t b = ptr[I], e = ptr[I + 1];
+        for (int32_t k = b + 1; k < e; ++k) {
+            const int32_t v = rows[k];
+            int32_t m = k - 1;
+            while (m >= b && rows[m] > v) {
+                rows[m + 1] = rows[m];
+                --m;
+            }
+            rows[m + 1] = v;
+        }
+    }
+}
+
+// exclusive scan of n ints in one block; out[n] = total
+__global__ __launch_bounds__(1024) void scan_int_kernel(int32_t n, const int32_t *__restrict__ in,
+                                                        int32_t *__restrict__ out) {
+    __shared__ int32_t part[1024];
+    const int t = threadIdx.x;
+    const int32_t chunk = (n + 1023) / 1024;
+    const int32_t lo = min(n, t * chunk), hi = min(n, lo + chunk);
+    int32_t s = 0;
+    for (int32_t k = lo; k < hi; ++k) s += in[k];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int32_t run = 0;
+        for (int k = 0; k < 1024; ++k) {
+            const int32_t v = part[k];
+            part[k] = run;
+            run += v;
+        }
+        out[n] = run;
+    }
+    __syncthreads();
+    int32_t run = part[t];
+    for (int32_t k = lo; k < hi; ++k) {
+        const int32_t v = in[k];
+        out[k] = run;
+        run += v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin coarse operator, one wavefront per coarse row
+// ---------------------------------------------------------------------------
+// mode 0: rowlen[I] = number of coarse columns; mode 1: write them (SELL)
+__global__ __launch_bounds__(64) void galerkin_kernel(Sell<double> A, const int32_t *__restrict__ agg,
+                                                      const int32_t *__restrict__ mptr, const int32_t *__restrict__ mrows,
+                                                      int32_t nc, int mode, int32_t *__restrict__ rowlen,
+                                                      const int64_t *__restrict__ cptr, int32_t *__restrict__ ccol,
+                                                      double *__restrict__ cval, int *__restrict__ overflow) {
+    __shared__ uint64_t key[kCap];
+    const int32_t I = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (I >= nc) return;
+    // gather (coarse column, fine position) candidates of the aggregate's rows;
+    // slice padding (value exactly 0) is skipped, lanes compacted by ballot
+    int m = 0;
+    bool over = false;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int32_t t = mptr[I]; t < mptr[I + 1] && !over; ++t) {
+        const int32_t r = mrows[t];
+        const int64_t b0 = A.ptr[r >> 6], b1 = A.ptr[(r >> 6) + 1];
+        const int w = (int)((b1 - b0) >> 6);
+        for (int k0 = 0; k0 < w; k0 += 64) {
+            const int k = k0 + lane;
+            bool keep = false;
+            uint64_t kv = 0;
+            if (k < w) {
+                const int64_t q = b0 + (int64_t)k * 64 + (r & 63);
+                if (A.val[q] != 0.0) {
+                    keep = true;
+                    kv = ((uint64_t)(uint32_t)agg[A.col[q]] << 32) | (uint64_t)(uint32_t)q;
+                }
+            }
+            const uint64_t mask = __ballot(keep);
+            const int off = __popcll(mask & below);
+            const int cnt = __popcll(mask);
+            if (m + cnt > kCap) {
+                over = true;
+                break;
+            }
+            if (keep) key[m + off] = kv;
+            m += cnt;
+        }
+    }
+    if (over) {
+        if (lane == 0) {
+            atomicOr(overflow, 1);
+            if (mode == 0) rowlen[I] = 1;
+        }
+        return;
+    }
+    int mp = 1;
+    while (mp < m) mp <<= 1;
+    for (int k = m + lane; k < mp; k += 64) key[k] = ~0ull;
+    __syncthreads();
+    // bitonic sort of key[0, mp)
+    for (int k = 2; k <= mp; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = lane; i < mp; i += 64) {
+                const int p = i ^ j;
+                if (p > i) {
+                    const uint64_t a = key[i], b = key[p];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) {
+                        key[i] = b;
+                        key[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    // segment heads: first key of each coarse column
+    const int C = mp / 64 > 0 ? mp / 64 : 1;
+    const int lo = min(m, lane * C), hi = min(m, lo + C);
+    int nh = 0;
+    for (int t = lo; t < hi; ++t) nh += (t == 0 || (key[t] >> 32) != (key[t - 1] >> 32));
+    // exclusive wave scan of head counts
+    int incl = nh;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    const int total = __shfl(incl, 63, 64);
+    if (mode == 0) {
+        if (lane == 0) rowlen[I] = total;
+        return;
+    }
+    int rank = incl - nh;
+    const int64_t base = cptr[I >> 6] + (I & 63);
+    for (int t = lo; t < hi; ++t) {
+        if (!(t == 0 || (key[t] >> 32) != (key[t - 1] >> 32))) continue;
+        const uint32_t J = (uint32_t)(key[t] >> 32);
+        double s = 0.0;
+        for (int u = t; u < m && (uint32_t)(key[u] >> 32) == J; ++u) s += A.val[(uint32_t)key[u]];
+        ccol[base + (int64_t)rank * 64] = (int32_t)J;
+        cval[base + (int64_t)rank * 64] = s;
+        ++rank;
+    }
+    // padding of this row up to the slice width
+    const int w = (int)((cptr[(I >> 6) + 1] - cptr[I >> 6]) >> 6);
+    for (int k = total + lane; k < w; k += 64) {
+        ccol[base + (int64_t)k * 64] = I;
+        cval[base + (int64_t)k * 64] = 0.0;
+    }
+}
+
+// slice widths (max row length of each 64-row slice)
+__global__ __launch_bounds__(64) void slice_width_kernel(int32_t n, const int32_t *__restrict__ rowlen,
+                                                         int32_t *__restrict__ width) {
+    const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    int c = i < n ? rowlen[i] : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c = max(c, __shfl_down(c, o, 64));
+    if (threadIdx.x == 0) width[blockIdx.x] = c;
+}
+// rows beyond n in the last slice: padding pointing at row 0
+__global__ __launch_bounds__(64) void slice_tail_kernel(int32_t n, const int64_t *__restrict__ ptr,
+                                                        int32_t *__restrict__ col, double *__restrict__ val) {
+    const int32_t sl = n >> 6;
+    const int lane = threadIdx.x;
+    if ((n & 63) == 0 || lane < (n & 63)) return;
+    for (int64_t q = ptr[sl] + lane; q < ptr[sl + 1]; q += 64) {
+        col[q] = 0;
+        val[q] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// coarsest level: dense inverse
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kAT) void dense_from_sell_kernel(Sell<double> A, double *__restrict__ D) {
+    const int32_t n = A.n;
+    GS(t, (int64_t)n * n) D[t] = 0.0;
+}
+__global__ __launch_bounds__(kAT) void dense_scatter_kernel(Sell<double> A, double *__restrict__ D) {
+    GS(i, A.n) {
+        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
+        for (int64_t q = b0 + (i & 63); q < b1; q += 64) D[i * A.n + A.col[q]] += A.val[q];
+    }
+}
+// In-place Gauss-Jordan inversion of an SPD matrix (no pivoting needed), one block.
+__global__ __launch_bounds__(1024) void gauss_jordan_kernel(int32_t n, double *__restrict__ M) {
+    __shared__ double pivrow_inv;
+    for (int32_t p = 0; p < n; ++p) {
+        if (threadIdx.x == 0) pivrow_inv = 1.0 / M[(int64_t)p * n + p];
+        __syncthreads();
+        const double pinv = pivrow_inv;
+        // scale pivot row
+        for (int32_t j = threadIdx.x; j < n; j += blockDim.x)
+            if (j != p) M[(int64_t)p * n + j] *= pinv;
+        __syncthreads();
+        // eliminate column p from the other rows: a wavefront per row, lanes along the row
+        for (int32_t i = threadIdx.x >> 6; i < n; i += blockDim.x >> 6) {
+            if (i == p) continue;
+            const double mip = M[(int64_t)i * n + p];
+            for (int32_t j = threadIdx.x & 63; j < n; j += 64)
+                if (j != p) M[(int64_t)i * n + j] -= mip * M[(int64_t)p * n + j];
+        }
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < n; i += blockDim.x)
+            if (i != p) M[(int64_t)i * n + p] *= -pinv;
+        __syncthreads();
+        if (threadIdx.x == 0) M[(int64_t)p * n + p] = pinv;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle kernels
+// ---------------------------------------------------------------------------
+// x = M^-1 b (first sweep from zero) and r = b - A x, with x_j formed on the fly
+template <class V, class X>
+__global__ __launch_bounds__(kAT) void vc_pre_kernel(Sell<V> A, const X *__restrict__ dinv, const X *__restrict__ b,
+                                                     X *__restrict__ x, X *__restrict__ r, const PcgState *st) {
+    if (st && st->done) return;
+    GS(i, A.n) {
+        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
+        X s = 0;
+        for (int64_t q = b0 + (i & 63); q < b1; q += 64) {
+            const int32_t j = A.col[q];
+            s += (X)A.val[q] * (dinv[j] * b[j]);
+        }
+        x[i] = dinv[i] * b[i];
+        r[i] = b[i] - s;
+    }
+}
+// b_c[I] = sum of r over aggregate I (rows ascending)
+template <class X>
+__global__ __launch_bounds__(kAT) void vc_restrict_kernel(int32_t nc, const int32_t *__restrict__ mptr,
+                                                          const int32_t *__restrict__ mrows, const X *__restrict__ r,
+                                                          X *__restrict__ bc, const PcgState *st) {
+    if (st && st->done) return;
+    GS(I, nc) {
+        X s = 0;
+        for (int32_t t = mptr[I]; t < mptr[I + 1]; ++t) s += r[mrows[t]];
+        bc[I] = s;
+    }
+}
+// y = x + P e (on the fly), out = y + M^-1 (b - A y)
+template <class V, class X>
+__global__ __launch_bounds__(kAT) void vc_post_kernel(Sell<V> A, const X *__restrict__ dinv, const X *__restrict__ b,
+                                                      const X *__restrict__ x, const int32_t *__restrict__ agg,
+                                                      const X *__restrict__ e, X *__restrict__ out, const PcgState *st) {
+    if (st && st->done) return;
+    GS(i, A.n) {
+        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
+        X s = 0;
+        for (int64_t q = b0 + (i & 63); q < b1; q += 64) {
+            const int32_t j = A.col[q];
+            s += (X)A.val[q] * (x[j] + e[agg[j]]);
+        }
+        const X yi = x[i] + e[agg[i]];
+        out[i] = yi + dinv[i] * (b[i] - s);
+    }
+}
+// dense coarse solve x = Ainv b
+template <class X>
+__global__ __launch_bounds__(kAT) void vc_dense_kernel(int32_t n, const X *__restrict__ Ainv, const X *__restrict__ b,
+                                                       X *__restrict__ x, const PcgState *st) {
+    if (st && st->done) return;
+    GS(i, n) {
+        X s = 0;
+        for (int32_t j = 0; j < n; ++j) s += Ainv[i * n + j] * b[j];
+        x[i] = s;
+    }
+}
+// plain l1-Jacobi sweep out = x + M^-1 (b - A x) (coarsest level when too big for the dense inverse)
+template <class V, class X>
+__global__ __launch_bounds__(kAT) void vc_sweep_kernel(Sell<V> A, const X *__restrict__ dinv, const X *__restrict__ b,
+                                                       const X *__restrict__ x, X *__restrict__ out, const PcgState *st) {
+    if (st && st->done) return;
+    GS(i, A.n) {
+        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
+        X s = 0;
+        for (int64_t q = b0 + (i & 63); q < b1; q += 64) s += (X)A.val[q] * x[A.col[q]];
+        out[i] = x[i] + dinv[i] * (b[i] - s);
+    }
+}
+
+// conversions for the single-precision hierarchy
+__global__ __launch_bounds__(kAT) void to_float_kernel(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
+    GS(i, n) b[i] = (float)a[i];
+}
+__global__ __launch_bounds__(kAT) void to_double_kernel(int64_t n, const float *__restrict__ a, double *__restrict__ b) {
+    GS(i, n) b[i] = (double)a[i];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+#define ALAUNCH(kern, grid, block, ...)                                              \
+    do {                                                                             \
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, __VA_ARGS__);        \
+        VAG_HIP(hipGetLastError());                                                  \
+    } while (0)
+
+void amg_launch_diag(hipStream_t s, Sell<double> A, double *diag, double *dinv) {
+    if (A.n > 0) ALAUNCH(amg_diag_kernel, gridv(A.n), kAT, A, diag, dinv);
+}
+void amg_launch_mis(hipStream_t s, Sell<double> A, const double *diag, double theta, int rounds, uint64_t *T,
+                    uint64_t *T1, int *undecided /* [rounds] zeroed */, int32_t *flag) {
+    ALAUNCH(mis_init_kernel, gridv(A.n), kAT, A.n, T);
+    for (int r = 0; r < rounds; ++r) {
+        const int *active = r ? undecided + r - 1 : nullptr;
+        ALAUNCH(mis_max_kernel, gridv(A.n), kAT, A, diag, theta, T, T1, active);
+        ALAUNCH(mis_select_kernel, gridv(A.n), kAT, A, diag, theta, T1, T, undecided + r, active);
+    }
+    ALAUNCH(mis_flag_kernel, gridv(A.n), kAT, A.n, T, flag);
+}
+void amg_launch_scan(hipStream_t s, int32_t n, const int32_t *in, int32_t *out) {
+    ALAUNCH(scan_int_kernel, 1, 1024, n, in, out);
+}
+void amg_launch_aggregate(hipStream_t s, Sell<double> A, const double *diag, double theta, const int32_t *root,
+                          const int32_t *rid, int32_t *agg1, int32_t *agg, int32_t *lonely) {
+    ALAUNCH(agg_pass1_kernel, gridv(A.n), kAT, A, diag, theta, root, rid, agg1);
+    ALAUNCH(agg_pass2_kernel, gridv(A.n), kAT, A, diag, theta, agg1, agg, lonely);
+}
+void amg_launch_lonely(hipStream_t s, int32_t n, const int32_t *lonely, const int32_t *lid, const int32_t *nroot,
+                       int32_t *agg) {
+    ALAUNCH(agg_lonely_kernel, gridv(n), kAT, n, lonely, lid, nroot, agg);
+}
+void amg_launch_members(hipStream_t s, int32_t n, int32_t nc, const int32_t *agg, int32_t *cnt, int32_t *ptr,
+                        int32_t *cursor, int32_t *rows) {
+    // cnt and cursor zeroed by the caller
+    ALAUNCH(count_kernel, gridv(n), kAT, n, agg, cnt);
+    ALAUNCH(scan_int_kernel, 1, 1024, nc, cnt, ptr);
+    ALAUNCH(members_fill_kernel, gridv(n), kAT, n, agg, ptr, cursor, rows);
+    ALAUNCH(members_sort_kernel, gridv(nc), kAT, nc, ptr, rows);
+}
+void amg_launch_galerkin(hipStream_t s, Sell<double> A, const int32_t *agg, const int32_t *mptr,
+                         const int32_t *mrows, int32_t nc, int mode, int32_t *rowlen, const int64_t *cptr,
+                         int32_t *ccol, double *cval, int *overflow) {
+    if (nc > 0) ALAUNCH(galerkin_kernel, nc, 64, A, agg, mptr, mrows, nc, mode, rowlen, cptr, ccol, cval, overflow);
+}
+void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t *width, int64_t *ptr) {
+    const int32_t ns = (n + 63) / 64;
+    if (ns > 0) ALAUNCH(slice_width_kernel, ns, 64, n, rowlen, width);
+    launch_slice_scan(s, ns, width, ptr);
+}
+void amg_launch_slice_tail(hipStream_t s, int32_t n, const int64_t *ptr, int32_t *col, double *val) {
+    if (n & 63) ALAUNCH(slice_tail_kernel, 1, 64, n, ptr, col, val);
+}
+void amg_launch_dense_inverse(hipStream_t s, Sell<double> A, double *D) {
+    ALAUNCH(dense_from_sell_kernel, gridv((int64_t)A.n * A.n), kAT, A, D);
+    ALAUNCH(dense_scatter_kernel, gridv(A.n), kAT, A, D);
+    ALAUNCH(gauss_jordan_kernel, 1, 1024, A.n, D);
+}
+template <class V, class X>
+void amg_launch_pre(hipStream_t s, Sell<V> A, const X *dinv, const X *b, X *x, X *r, const PcgState *st) {
+    ALAUNCH((vc_pre_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, x, r, st);
+}
+template <class X>
+void amg_launch_restrict(hipStream_t s, int32_t nc, const int32_t *mptr, const int32_t *mrows, const X *r, X *bc,
+                         const PcgState *st) {
+    ALAUNCH(vc_restrict_kernel<X>, gridv(nc), kAT, nc, mptr, mrows, r, bc, st);
+}
+template <class V, class X>
+void amg_launch_post(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, const int32_t *agg, const X *e,
+                     X *out, const PcgState *st) {
+    ALAUNCH((vc_post_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, x, agg, e, out, st);
+}
+template <class X>
+void amg_launch_dense(hipStream_t s, int32_t n, const X *Ainv, const X *b, X *x, const PcgState *st) {
+    ALAUNCH(vc_dense_kernel<X>, gridv(n), kAT, n, Ainv, b, x, st);
+}
+template <class V, class X>
+void amg_launch_sweep(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, X *out, const PcgState *st) {
+    ALAUNCH((vc_sweep_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, x, out, st);
+}
+void launch_to_float(hipStream_t s, int64_t n, const double *a, float *b) {
+    if (n > 0) ALAUNCH(to_float_kernel, gridv(n), kAT, n, a, b);
+}
+void launch_to_double(hipStream_t s, int64_t n, const float *a, double *b) {
+    if (n > 0) ALAUNCH(to_double_kernel, gridv(n), kAT, n, a, b);
+}
+
+template void amg_launch_pre<double, double>(hipStream_t, Sell<double>, const double *, const double *, double *,
+                                             double *, const PcgState *);
+template void amg_launch_pre<float, float>(hipStream_t, Sell<float>, const float *, const float *, float *, float *,
+                                           const PcgState *);
+template void amg_launch_restrict<double>(hipStream_t, int32_t, const int32_t *, const int32_t *, const double *,
+                                          double *, const PcgState *);
+template void amg_launch_restrict<float>(hipStream_t, int32_t, const int32_t *, const int32_t *, const float *,
+                                         float *, const PcgState *);
+template void amg_launch_post<double, double>(hipStream_t, Sell<double>, const double *, const double *,
+                                              const double *, const int32_t *, const double *, double *,
+                                              const PcgState *);
+template void amg_launch_post<float, float>(hipStream_t, Sell<float>, const float *, const float *, const float *,
+                                            const int32_t *, const float *, float *, const PcgState *);
+template void amg_launch_dense<double>(hipStream_t, int32_t, const double *, const double *, double *,
+                                       const PcgState *);
+template void amg_launch_dense<float>(hipStream_t, int32_t, const float *, const float *, float *, const PcgState *);
+template void amg_launch_sweep<double, double>(hipStream_t, Sell<double>, const double *, const double *,
+                                               const double *, double *, const PcgState *);
+template void amg_launch_sweep<float, float>(hipStream_t, Sell<float>, const float *, const float *, const float *,
+                                             float *, const PcgState *);
+
+}  // namespace vag

@@ -1,0 +1,171 @@
+// Setup and application of the aggregation AMG hierarchy (see amg.hip).
+#include "amg.h"
+
+#include <algorithm>
+
+namespace vag {
+
+Amg::~Amg() {
+    if (h_) (void)hipHostFree(h_);
+}
+
+void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, const AmgOptions &o) {
+    o_ = o;
+    if (!h_) VAG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_), 16 * sizeof(int64_t)));
+    const int32_t n0 = A0.n;
+    ensure(T_, n0, tr);
+    ensure(T1_, n0, tr);
+    for (auto *b : {&flag_, &rid_, &agg1_, &lonely_, &lid_, &cnt_, &cursor_, &rowlen_}) ensure(*b, (size_t)n0 + 1, tr);
+    ensure(width_, (size_t)n0 / 64 + 2, tr);
+    ensure(counters_, 64, tr);
+    if (L.empty()) L.emplace_back(new AmgLevel());
+    L[0]->n = n0;
+    L[0]->A = A0;
+    L[0]->stored = stored0;
+    have32 = false;
+    dense = false;
+    int64_t stored_total = stored0;
+    int l = 0;
+    for (;; ++l) {
+        AmgLevel &lv = *L[l];
+        const int32_t n = lv.n;
+        ensure(lv.diag, n, tr);
+        ensure(lv.dinv, n, tr);
+        amg_launch_diag(s, lv.A, lv.diag.p, lv.dinv.p);
+        if (n <= o.coarse_size || l + 1 >= o.max_levels) break;
+        // aggregation
+        VAG_HIP(hipMemsetAsync(counters_.p, 0, 64 * sizeof(int), s));
+        amg_launch_mis(s, lv.A, lv.diag.p, o.theta, std::min(o.mis_rounds, 48), T_.p, T1_.p, counters_.p, flag_.p);
+        amg_launch_scan(s, n, flag_.p, rid_.p);
+        ensure(lv.agg, n, tr);
+        amg_launch_aggregate(s, lv.A, lv.diag.p, o.theta, flag_.p, rid_.p, agg1_.p, lv.agg.p, lonely_.p);
+        amg_launch_scan(s, n, lonely_.p, lid_.p);
+        amg_launch_lonely(s, n, lonely_.p, lid_.p, rid_.p + n, lv.agg.p);
+        VAG_HIP(hipMemcpyAsync(h_, rid_.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipMemcpyAsync(h_ + 1, lid_.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipStreamSynchronize(s));
+        const int32_t nc = h_[0] + h_[1];
+        if (nc <= 0 || nc > (int64_t)n * 9 / 10) break;  // coarsening stalled: this level is the coarsest
+        // aggregate members and the Galerkin product
+        ensure(lv.mptr, (size_t)nc + 1, tr);
+        ensure(lv.mrows, n, tr);
+        VAG_HIP(hipMemsetAsync(cnt_.p, 0, ((size_t)nc + 1) * sizeof(int32_t), s));
+        VAG_HIP(hipMemsetAsync(cursor_.p, 0, ((size_t)nc + 1) * sizeof(int32_t), s));
+        amg_launch_members(s, n, nc, lv.agg.p, cnt_.p, lv.mptr.p, cursor_.p, lv.mrows.p);
+        if ((int)L.size() <= l + 1) L.emplace_back(new AmgLevel());
+        AmgLevel &cv = *L[l + 1];
+        const int32_t ns = (nc + 63) / 64;
+        ensure(cv.ptr, (size_t)ns + 1, tr);
+        amg_launch_galerkin(s, lv.A, lv.agg.p, lv.mptr.p, lv.mrows.p, nc, 0, rowlen_.p, nullptr, nullptr, nullptr,
+                            counters_.p + 63);
+        amg_launch_slices(s, nc, rowlen_.p, width_.p, cv.ptr.p);
+        int64_t hv[2];
+        VAG_HIP(hipMemcpyAsync(&hv[0], cv.ptr.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipMemcpyAsync(h_ + 2, counters_.p + 63, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipStreamSynchronize(s));
+        if (h_[2] != 0) break;  // a coarse row has too many candidates: stop coarsening here
+        const int64_t stored = hv[0];
+        ensure(cv.col, (size_t)stored, tr);
+        ensure(cv.val, (size_t)stored, tr);
+        amg_launch_galerkin(s, lv.A, lv.agg.p, lv.mptr.p, lv.mrows.p, nc, 1, rowlen_.p, cv.ptr.p, cv.col.p, cv.val.p,
+                            counters_.p + 63);
+        amg_launch_slice_tail(s, nc, cv.ptr.p, cv.col.p, cv.val.p);
+        cv.n = nc;
+        cv.stored = stored;
+        cv.A = Sell<double>{nc, cv.ptr.p, cv.col.p, cv.val.p};
+        stored_total += stored;
+        // vectors of the coarse level
+        for (auto *v : {&cv.b, &cv.xa, &cv.xb, &cv.r}) ensure(*v, nc, tr);
+    }
+    nlev = l + 1;
+    op_complexity = (double)stored_total / (double)std::max<int64_t>(stored0, 1);
+    AmgLevel &cl = *L[l];
+    if (l == 0) {
+        for (auto *v : {&cl.xa, &cl.r}) ensure(*v, cl.n, tr);
+    } else {
+        for (auto *v : {&L[0]->xa, &L[0]->r}) ensure(*v, n0, tr);
+    }
+    if (cl.n <= o.dense_max && cl.n > 0) {
+        ensure(Ainv, (size_t)cl.n * cl.n, tr);
+        amg_launch_dense_inverse(s, cl.A, Ainv.p);
+        dense = true;
+    }
+}
+
+void Amg::make_fp32(hipStream_t s, Tracker &tr, const int32_t *) {
+    for (int l = 0; l < nlev; ++l) {
+        AmgLevel &lv = *L[l];
+        ensure(lv.val32, (size_t)lv.stored, tr);
+        launch_to_float(s, lv.stored, lv.A.val, lv.val32.p);
+        ensure(lv.dinv32, lv.n, tr);
+        launch_to_float(s, lv.n, lv.dinv.p, lv.dinv32.p);
+        for (auto *v : {&lv.b32, &lv.xa32, &lv.xb32, &lv.r32}) ensure(*v, lv.n, tr);
+        lv.A32 = Sell<float>{lv.n, lv.A.ptr, lv.A.col, lv.val32.p};
+    }
+    if (dense) {
+        const int32_t nc = L[nlev - 1]->n;
+        ensure(Ainv32, (size_t)nc * nc, tr);
+        launch_to_float(s, (int64_t)nc * nc, Ainv.p, Ainv32.p);
+    }
+    have32 = true;
+}
+
+// V-cycle on level l: out = M_l^-1 b
+template <class V, class X>
+void Amg::cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bool fp32) {
+    AmgLevel &lv = *L[l];
+    Sell<V> A;
+    const X *dinv;
+    X *xa, *r;
+    if constexpr (sizeof(X) == 4) {
+        A = lv.A32;
+        dinv = lv.dinv32.p;
+        xa = lv.xa32.p;
+        r = lv.r32.p;
+    } else {
+        A = lv.A;
+        dinv = lv.dinv.p;
+        xa = lv.xa.p;
+        r = lv.r.p;
+    }
+    if (l == nlev - 1) {
+        if (dense) {
+            const X *Ai;
+            if constexpr (sizeof(X) == 4) Ai = Ainv32.p; else Ai = Ainv.p;
+            amg_launch_dense<X>(s, lv.n, Ai, b, out, st);
+        } else {
+            // a few l1-Jacobi sweeps from zero, ping-ponging between xa and out
+            amg_launch_pre<V, X>(s, A, dinv, b, xa, r, st);
+            X *src = xa, *dst = out;
+            for (int k = 1; k < o_.coarse_sweeps; ++k) {
+                amg_launch_sweep<V, X>(s, A, dinv, b, src, dst, st);
+                std::swap(src, dst);
+            }
+            if (src != out) amg_launch_sweep<V, X>(s, A, dinv, b, src, out, st);
+        }
+        return;
+    }
+    AmgLevel &cv = *L[l + 1];
+    X *bc, *ec;
+    if constexpr (sizeof(X) == 4) {
+        bc = cv.b32.p;
+        ec = cv.xb32.p;
+    } else {
+        bc = cv.b.p;
+        ec = cv.xb.p;
+    }
+    amg_launch_pre<V, X>(s, A, dinv, b, xa, r, st);
+    amg_launch_restrict<X>(s, cv.n, lv.mptr.p, lv.mrows.p, r, bc, st);
+    cycle<V, X>(s, l + 1, bc, ec, st, fp32);
+    amg_launch_post<V, X>(s, A, dinv, b, xa, lv.agg.p, ec, out, st);
+}
+
+void Amg::apply(hipStream_t s, const double *r, double *z, const PcgState *st) {
+    cycle<double, double>(s, 0, r, z, st, false);
+}
+
+void Amg::apply32(hipStream_t s, const float *r, float *z, const PcgState *st) {
+    cycle<float, float>(s, 0, r, z, st, true);
+}
+
+}  // namespace vag

@@ -1,151 +1,174 @@
-// Krylov kernels for the SPD system of eq eqschur: CSR SpMV (a group of LPR
-// lanes per row, row entries read contiguously), and preconditioned CG whose
-// scalars stay on the device.  Every kernel of an iteration first reads the
-// `done` flag and returns at once when the solve has converged, so the host
-// can queue many iterations and check convergence only now and then.
+// Krylov kernels for the SPD system of eq eqschur.
+//
+// SpMV on sliced ELL: one row per lane, a wavefront = one 64-row slice, so
+// every value/column load of a wave is one contiguous 512/256-byte segment.
+//
+// Preconditioned CG keeps its scalars on the device.  An iteration k is
+//   direction(k): convergence test on ||r_k||^2, p = z + beta p
+//   spmv:         q = A p, partials of p.q
+//   update(k):    alpha = (r.z)/(p.q), x += alpha p, r -= alpha q,
+//                 z = M^-1 r, partials of r.z and r.r
+// Each kernel forms the totals it needs from the previous kernels' block
+// partials (redundantly in every block, in a fixed order), so no grid-wide
+// fence or atomic is needed and the arithmetic is reproducible bit for bit.
+// Partials are double-buffered by iteration parity.  Once the test succeeds the
+// `done` flag makes every later kernel return at once: the host queues many
+// iterations and reads the flag only now and then.
 #include "reduce.h"
 
 namespace vag {
 
-constexpr int kLPR = 8;       // lanes per CSR row (rows have ~27 entries)
 constexpr int kThreads = 256;
 
-template <int LPR>
-__device__ inline double row_dot(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                 const double *__restrict__ val, const double *__restrict__ x, int32_t row,
-                                 int lane) {
-    double s = 0.0;
-    const int32_t e = rp[row + 1];
-    for (int32_t k = rp[row] + lane; k < e; k += LPR) s += val[k] * x[col[k]];
-#pragma unroll
-    for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
-    return s;
-}
+int pcg_grid(int64_t n) { return (int)reduce_grid(n, kThreads); }
 
-__global__ __launch_bounds__(kThreads) void spmv_kernel(int32_t n, const int32_t *__restrict__ rp,
-                                                        const int32_t *__restrict__ col,
-                                                        const double *__restrict__ val,
-                                                        const double *__restrict__ x, double *__restrict__ y) {
-    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLPR;
-    const int lane = threadIdx.x % kLPR;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x / kLPR;
-    for (int64_t row = g; row < n; row += stride) {
-        const double s = row_dot<kLPR>(rp, col, val, x, (int32_t)row, lane);
-        if (lane == 0) y[row] = s;
+template <class V, class X>
+__device__ inline double sell_row(const Sell<V> &A, const X *__restrict__ x, int32_t row) {
+    const int64_t b1 = A.ptr[(row >> 6) + 1];
+    int64_t q = A.ptr[row >> 6] + (row & 63);
+    // four independent chains keep several gathers in flight
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (; q + 192 < b1; q += 256) {
+        s0 += (double)A.val[q] * (double)x[A.col[q]];
+        s1 += (double)A.val[q + 64] * (double)x[A.col[q + 64]];
+        s2 += (double)A.val[q + 128] * (double)x[A.col[q + 128]];
+        s3 += (double)A.val[q + 192] * (double)x[A.col[q + 192]];
     }
+    for (; q < b1; q += 64) s0 += (double)A.val[q] * (double)x[A.col[q]];
+    return (s0 + s1) + (s2 + s3);
 }
 
-// r = b - A x; parts: ||r||^2, ||b||^2
-__global__ __launch_bounds__(kThreads) void residual_kernel(int32_t n, const int32_t *__restrict__ rp,
-                                                            const int32_t *__restrict__ col,
-                                                            const double *__restrict__ val,
-                                                            const double *__restrict__ x,
+#define GRID_STRIDE(i, n) \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+__global__ __launch_bounds__(kThreads) void spmv_kernel(Sell<double> A, const double *__restrict__ x,
+                                                        double *__restrict__ y) {
+    GRID_STRIDE(i, A.n) y[i] = sell_row(A, x, (int32_t)i);
+}
+
+__global__ __launch_bounds__(kThreads) void residual_kernel(Sell<double> A, const double *__restrict__ x,
                                                             const double *__restrict__ b, double *__restrict__ r,
-                                                            ReduceScratch rs, double *__restrict__ out) {
-    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLPR;
-    const int lane = threadIdx.x % kLPR;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x / kLPR;
+                                                            double *__restrict__ parts) {
     double v[2] = {0.0, 0.0};
-    for (int64_t row = g; row < n; row += stride) {
-        const double s = row_dot<kLPR>(rp, col, val, x, (int32_t)row, lane);
-        if (lane == 0) {
-            const double t = b[row] - s;
-            r[row] = t;
-            v[0] += t * t;
-            v[1] += b[row] * b[row];
-        }
+    GRID_STRIDE(i, A.n) {
+        const double t = b[i] - sell_row(A, x, (int32_t)i);
+        r[i] = t;
+        v[0] += t * t;
+        v[1] += b[i] * b[i];
     }
-    if (grid_reduce<OpSum, 2, kThreads>(v, rs, 0) && threadIdx.x == 0) {
-        out[0] = v[0];
-        out[1] = v[1];
+    block_partials<OpSum, 2, kThreads>(v, parts, gridDim.x);
+}
+
+template <class Op>
+__global__ __launch_bounds__(kThreads) void finalize_kernel(const double *__restrict__ parts, int stride, int nparts,
+                                                            int nv, double *__restrict__ out) {
+    for (int k = 0; k < nv; ++k) {
+        const double t = sum_parts<Op, kThreads>(parts + (size_t)k * stride, nparts);
+        if (threadIdx.x == 0) out[k] = t;
     }
 }
 
 __global__ __launch_bounds__(kThreads) void fill_kernel(int64_t n, double v, double *__restrict__ x) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        x[i] = v;
+    GRID_STRIDE(i, n) x[i] = v;
 }
 __global__ __launch_bounds__(kThreads) void copy_kernel(int64_t n, const double *__restrict__ s,
                                                         double *__restrict__ d) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        d[i] = s[i];
+    GRID_STRIDE(i, n) d[i] = s[i];
 }
-
 __global__ __launch_bounds__(kThreads) void jacobi_kernel(int64_t n, const double *__restrict__ dinv,
                                                           const double *__restrict__ r, double *__restrict__ z) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        z[i] = dinv[i] * r[i];
+    GRID_STRIDE(i, n) z[i] = dinv[i] * r[i];
 }
 
 // ---------------------------------------------------------------------------
-// Jacobi-preconditioned CG, x0 = 0
+// preconditioned CG, x0 = 0
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void pcg_init_kernel(int32_t n, const double *__restrict__ b,
                                                             const double *__restrict__ dinv,
                                                             double *__restrict__ x, double *__restrict__ r,
-                                                            double *__restrict__ z, double *__restrict__ p,
-                                                            ReduceScratch rs, PcgState *st, double rtol,
-                                                            int max_iter) {
+                                                            double *__restrict__ z, PcgParts P) {
     double v[2] = {0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    GRID_STRIDE(i, n) {
         const double bi = b[i];
-        const double zi = dinv[i] * bi;
         x[i] = 0.0;
         r[i] = bi;
-        z[i] = zi;
-        p[i] = zi;
-        v[0] += bi * zi;
+        if (dinv) {
+            const double zi = dinv[i] * bi;
+            z[i] = zi;
+            v[0] += bi * zi;
+        }
         v[1] += bi * bi;
     }
-    if (grid_reduce<OpSum, 2, kThreads>(v, rs, 0) && threadIdx.x == 0) {
-        st->rz = v[0];
-        st->rr = v[1];
-        st->bnorm2 = v[1];
-        st->tol2 = rtol * rtol * v[1];
+    block_reduce<OpSum, 2, kThreads>(v);
+    if (threadIdx.x == 0) {
+        if (dinv) P.rz(-1)[blockIdx.x] = v[0];
+        P.rr(-1)[blockIdx.x] = v[1];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void pcg_start_kernel(PcgParts P, PcgState *st, double rtol) {
+    const double bb = sum_parts<OpSum, kThreads>(P.rr(-1), P.G);
+    if (threadIdx.x == 0) {
+        st->bnorm2 = bb;
+        st->tol2 = rtol * rtol * bb;
+        st->rr = bb;
         st->iter = 0;
-        st->max_iter = max_iter;
-        const bool conv = (v[1] == 0.0);
-        st->done = conv || max_iter <= 0;
-        st->converged = conv;
-        st->alpha = st->beta = st->pq = 0.0;
+        st->done = (bb == 0.0);
+        st->converged = (bb == 0.0);
     }
 }
 
-// q = A p, alpha = rz / (p . q)
-__global__ __launch_bounds__(kThreads) void pcg_spmv_kernel(int32_t n, const int32_t *__restrict__ rp,
-                                                            const int32_t *__restrict__ col,
-                                                            const double *__restrict__ val,
-                                                            const double *__restrict__ p, double *__restrict__ q,
-                                                            ReduceScratch rs, PcgState *st) {
+template <class T>
+__global__ __launch_bounds__(kThreads) void pcg_direction_kernel(int32_t n, int k, const T *__restrict__ z,
+                                                                 T *__restrict__ p, PcgParts P, PcgState *st,
+                                                                 int update) {
     if (st->done) return;
-    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLPR;
-    const int lane = threadIdx.x % kLPR;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x / kLPR;
-    double v[1] = {0.0};
-    for (int64_t row = g; row < n; row += stride) {
-        const double s = row_dot<kLPR>(rp, col, val, p, (int32_t)row, lane);
-        if (lane == 0) {
-            q[row] = s;
-            v[0] += p[row] * s;
+    const double rr = sum_parts<OpSum, kThreads>(P.rr(k - 1), P.G);
+    if (rr <= st->tol2) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->done = 1;
+            st->converged = 1;
+            st->rr = rr;
         }
+        return;
     }
-    if (grid_reduce<OpSum, 1, kThreads>(v, rs, 1) && threadIdx.x == 0) {
-        st->pq = v[0];
-        st->alpha = st->rz / v[0];
+    if (!update) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->rr = rr;
+        return;
+    }
+    double beta = 0.0;
+    if (k > 0) beta = sum_parts<OpSum, kThreads>(P.rz(k - 1), P.G) / sum_parts<OpSum, kThreads>(P.rz(k), P.G);
+    if (k == 0) {
+        GRID_STRIDE(i, n) p[i] = z[i];
+    } else {
+        const T b = (T)beta;
+        GRID_STRIDE(i, n) p[i] = z[i] + b * p[i];
     }
 }
 
-// x += alpha p, r -= alpha q, z = D^-1 r, beta = (r.z)_new / (r.z)_old
-__global__ __launch_bounds__(kThreads) void pcg_update_kernel(int32_t n, double *__restrict__ x,
+template <class V, class T>
+__global__ __launch_bounds__(kThreads) void pcg_spmv_kernel(Sell<V> A, const T *__restrict__ p, T *__restrict__ q,
+                                                            PcgParts P, const PcgState *st) {
+    if (st->done) return;
+    double v[1] = {0.0};
+    GRID_STRIDE(i, A.n) {
+        const double s = sell_row(A, p, (int32_t)i);
+        q[i] = (T)s;
+        v[0] += (double)p[i] * s;
+    }
+    block_partials<OpSum, 1, kThreads>(v, P.pq(), P.G);
+}
+
+__global__ __launch_bounds__(kThreads) void pcg_update_kernel(int32_t n, int k, double *__restrict__ x,
                                                               double *__restrict__ r, double *__restrict__ z,
                                                               const double *__restrict__ p,
                                                               const double *__restrict__ q,
-                                                              const double *__restrict__ dinv,
-                                                              ReduceScratch rs, PcgState *st) {
+                                                              const double *__restrict__ dinv, PcgParts P,
+                                                              PcgState *st) {
     if (st->done) return;
-    const double alpha = st->alpha;
+    const double alpha = sum_parts<OpSum, kThreads>(P.rz(k - 1), P.G) / sum_parts<OpSum, kThreads>(P.pq(), P.G);
     double v[2] = {0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    GRID_STRIDE(i, n) {
         x[i] += alpha * p[i];
         const double ri = r[i] - alpha * q[i];
         const double zi = dinv[i] * ri;
@@ -154,75 +177,193 @@ __global__ __launch_bounds__(kThreads) void pcg_update_kernel(int32_t n, double 
         v[0] += ri * zi;
         v[1] += ri * ri;
     }
-    if (grid_reduce<OpSum, 2, kThreads>(v, rs, 2) && threadIdx.x == 0) {
-        st->beta = v[0] / st->rz;
-        st->rz = v[0];
-        st->rr = v[1];
-        st->iter += 1;
-        if (v[1] <= st->tol2) {
-            st->done = 1;
-            st->converged = 1;
-        } else if (st->iter >= st->max_iter) {
-            st->done = 1;
-        }
+    block_reduce<OpSum, 2, kThreads>(v);
+    if (threadIdx.x == 0) {
+        P.rz(k)[blockIdx.x] = v[0];
+        P.rr(k)[blockIdx.x] = v[1];
+        if (blockIdx.x == 0) st->iter = k + 1;
     }
 }
 
-__global__ __launch_bounds__(kThreads) void pcg_direction_kernel(int32_t n, const double *__restrict__ z,
-                                                                 double *__restrict__ p, const PcgState *st) {
+template <class T>
+__global__ __launch_bounds__(kThreads) void pcg_update_xr_kernel(int32_t n, int k, T *__restrict__ x,
+                                                                 T *__restrict__ r, const T *__restrict__ p,
+                                                                 const T *__restrict__ q, PcgParts P, PcgState *st) {
     if (st->done) return;
-    const double beta = st->beta;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = z[i] + beta * p[i];
+    const double alpha = sum_parts<OpSum, kThreads>(P.rz(k - 1), P.G) / sum_parts<OpSum, kThreads>(P.pq(), P.G);
+    const T a = (T)alpha;
+    double v[1] = {0.0};
+    GRID_STRIDE(i, n) {
+        x[i] += a * p[i];
+        const T ri = r[i] - a * q[i];
+        r[i] = ri;
+        v[0] += (double)ri * (double)ri;
+    }
+    block_reduce<OpSum, 1, kThreads>(v);
+    if (threadIdx.x == 0) {
+        P.rr(k)[blockIdx.x] = v[0];
+        if (blockIdx.x == 0) st->iter = k + 1;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void pcg_dot_rz_kernel(int32_t n, int k, const T *__restrict__ r,
+                                                              const T *__restrict__ z, PcgParts P,
+                                                              const PcgState *st) {
+    if (st && st->done) return;
+    double v[1] = {0.0};
+    GRID_STRIDE(i, n) v[0] += (double)r[i] * (double)z[i];
+    block_reduce<OpSum, 1, kThreads>(v);
+    if (threadIdx.x == 0) P.rz(k)[blockIdx.x] = v[0];
+}
+
+// x = 0, r = b (no preconditioner applied), partials of b.b
+template <class T>
+__global__ __launch_bounds__(kThreads) void pcg_init_plain_kernel(int32_t n, const T *__restrict__ b,
+                                                                  T *__restrict__ x, T *__restrict__ r, PcgParts P) {
+    double v[1] = {0.0};
+    GRID_STRIDE(i, n) {
+        x[i] = (T)0;
+        r[i] = b[i];
+        v[0] += (double)b[i] * (double)b[i];
+    }
+    block_reduce<OpSum, 1, kThreads>(v);
+    if (threadIdx.x == 0) P.rr(-1)[blockIdx.x] = v[0];
+}
+
+// mixed precision with the symmetric diagonal scaling S = D^-1/2:
+//   partials of ||S r||^2; r32 = S r / ||S r||; x += ||S r|| S d32
+__global__ __launch_bounds__(kThreads) void scaled_norm_kernel(int32_t n, const double *__restrict__ sc,
+                                                               const double *__restrict__ r,
+                                                               double *__restrict__ parts) {
+    double v[1] = {0.0};
+    GRID_STRIDE(i, n) {
+        const double t = sc[i] * r[i];
+        v[0] += t * t;
+    }
+    block_partials<OpSum, 1, kThreads>(v, parts, gridDim.x);
+}
+__global__ __launch_bounds__(kThreads) void scale_to_float_kernel(int32_t n, const double *__restrict__ sc,
+                                                                  const double *__restrict__ r,
+                                                                  const double *__restrict__ nrm2,
+                                                                  float *__restrict__ r32) {
+    const double s = nrm2[0] > 0.0 ? 1.0 / sqrt(nrm2[0]) : 0.0;
+    GRID_STRIDE(i, n) r32[i] = (float)(sc[i] * r[i] * s);
+}
+__global__ __launch_bounds__(kThreads) void correct_kernel(int32_t n, double *__restrict__ x,
+                                                           const double *__restrict__ sc,
+                                                           const float *__restrict__ d32,
+                                                           const double *__restrict__ nrm2) {
+    const double s = sqrt(nrm2[0]);
+    GRID_STRIDE(i, n) x[i] += s * sc[i] * (double)d32[i];
+}
+// sc_i = 1/sqrt(a_ii); As = S A S (same sliced-ELL pattern)
+__global__ __launch_bounds__(kThreads) void diag_scale_kernel(int32_t n, const int32_t *__restrict__ diag_pos,
+                                                              const double *__restrict__ A, double *__restrict__ sc) {
+    GRID_STRIDE(i, n) sc[i] = 1.0 / sqrt(A[diag_pos[i]]);
+}
+__global__ __launch_bounds__(kThreads) void scale_matrix_kernel(Sell<double> A, const double *__restrict__ sc,
+                                                                double *__restrict__ As) {
+    GRID_STRIDE(i, A.n) {
+        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
+        const double si = sc[i];
+        for (int64_t q = b0 + (i & 63); q < b1; q += 64) As[q] = si * A.val[q] * sc[A.col[q]];
+    }
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static inline unsigned rows_grid(int64_t n) { return reduce_grid(n * kLPR, kThreads); }
 static inline unsigned vec_grid(int64_t n) { return reduce_grid(n, kThreads); }
+#define LAUNCH(kern, grid, ...)                                                          \
+    do {                                                                                 \
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, s, __VA_ARGS__);         \
+        VAG_HIP(hipGetLastError());                                                      \
+    } while (0)
 
 void launch_fill(hipStream_t s, int64_t n, double v, double *x) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(fill_kernel, dim3(vec_grid(n)), dim3(kThreads), 0, s, n, v, x);
-    VAG_HIP(hipGetLastError());
+    if (n > 0) LAUNCH(fill_kernel, vec_grid(n), n, v, x);
 }
 void launch_copy(hipStream_t s, int64_t n, const double *src, double *dst) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(copy_kernel, dim3(vec_grid(n)), dim3(kThreads), 0, s, n, src, dst);
-    VAG_HIP(hipGetLastError());
+    if (n > 0) LAUNCH(copy_kernel, vec_grid(n), n, src, dst);
 }
 void launch_jacobi(hipStream_t s, int64_t n, const double *dinv, const double *r, double *z) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(jacobi_kernel, dim3(vec_grid(n)), dim3(kThreads), 0, s, n, dinv, r, z);
-    VAG_HIP(hipGetLastError());
+    if (n > 0) LAUNCH(jacobi_kernel, vec_grid(n), n, dinv, r, z);
 }
-void launch_spmv(hipStream_t s, int32_t n, const int32_t *rp, const int32_t *col, const double *val,
-                 const double *x, double *y) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(spmv_kernel, dim3(rows_grid(n)), dim3(kThreads), 0, s, n, rp, col, val, x, y);
-    VAG_HIP(hipGetLastError());
+void launch_spmv(hipStream_t s, Sell<double> A, const double *x, double *y) {
+    if (A.n > 0) LAUNCH(spmv_kernel, vec_grid(A.n), A, x, y);
 }
-void launch_residual_norm(hipStream_t s, int32_t n, const int32_t *rp, const int32_t *col, const double *val,
-                          const double *x, const double *b, double *r, ReduceScratch rs, double *out2) {
-    hipLaunchKernelGGL(residual_kernel, dim3(rows_grid(n)), dim3(kThreads), 0, s, n, rp, col, val, x, b, r, rs,
-                       out2);
-    VAG_HIP(hipGetLastError());
+void launch_finalize_sum(hipStream_t s, const double *parts, int stride, int nparts, int nv, double *out) {
+    LAUNCH(finalize_kernel<OpSum>, 1, parts, stride, nparts, nv, out);
+}
+void launch_finalize_min(hipStream_t s, const double *parts, int stride, int nparts, int nv, double *out) {
+    LAUNCH(finalize_kernel<OpMin>, 1, parts, stride, nparts, nv, out);
+}
+void launch_residual_norm(hipStream_t s, Sell<double> A, const double *x, const double *b, double *r,
+                          double *parts, double *out2) {
+    const unsigned g = vec_grid(A.n);
+    LAUNCH(residual_kernel, g, A, x, b, r, parts);
+    launch_finalize_sum(s, parts, (int)g, (int)g, 2, out2);
 }
 void launch_pcg_init(hipStream_t s, int32_t n, const double *b, const double *dinv, double *x, double *r,
-                     double *z, double *p, ReduceScratch rs, PcgState *st, double rtol, int max_iter) {
-    hipLaunchKernelGGL(pcg_init_kernel, dim3(vec_grid(n)), dim3(kThreads), 0, s, n, b, dinv, x, r, z, p, rs, st,
-                       rtol, max_iter);
-    VAG_HIP(hipGetLastError());
+                     double *z, PcgParts P) {
+    LAUNCH(pcg_init_kernel, P.G, n, b, dinv, x, r, z, P);
 }
-void launch_pcg_iter(hipStream_t s, int32_t n, const int32_t *rp, const int32_t *col, const double *val,
-                     const double *dinv, double *x, double *r, double *z, double *p, double *q,
-                     ReduceScratch rs, PcgState *st) {
-    hipLaunchKernelGGL(pcg_spmv_kernel, dim3(rows_grid(n)), dim3(kThreads), 0, s, n, rp, col, val, p, q, rs, st);
-    hipLaunchKernelGGL(pcg_update_kernel, dim3(vec_grid(n)), dim3(kThreads), 0, s, n, x, r, z, p, q, dinv, rs,
-                       st);
-    hipLaunchKernelGGL(pcg_direction_kernel, dim3(vec_grid(n)), dim3(kThreads), 0, s, n, z, p, st);
-    VAG_HIP(hipGetLastError());
+void launch_pcg_start(hipStream_t s, PcgParts P, PcgState *st, double rtol) {
+    LAUNCH(pcg_start_kernel, 1, P, st, rtol);
 }
+template <class T>
+void launch_pcg_direction(hipStream_t s, int32_t n, int k, const T *z, T *p, PcgParts P, PcgState *st, bool update) {
+    LAUNCH(pcg_direction_kernel<T>, P.G, n, k, z, p, P, st, update ? 1 : 0);
+}
+template <class V, class T>
+void launch_pcg_spmv(hipStream_t s, Sell<V> A, const T *p, T *q, PcgParts P, const PcgState *st) {
+    LAUNCH((pcg_spmv_kernel<V, T>), P.G, A, p, q, P, st);
+}
+void launch_pcg_update(hipStream_t s, int32_t n, int k, double *x, double *r, double *z, const double *p,
+                       const double *q, const double *dinv, PcgParts P, PcgState *st) {
+    LAUNCH(pcg_update_kernel, P.G, n, k, x, r, z, p, q, dinv, P, st);
+}
+template <class T>
+void launch_pcg_update_xr(hipStream_t s, int32_t n, int k, T *x, T *r, const T *p, const T *q, PcgParts P,
+                          PcgState *st) {
+    LAUNCH(pcg_update_xr_kernel<T>, P.G, n, k, x, r, p, q, P, st);
+}
+template <class T>
+void launch_pcg_dot_rz(hipStream_t s, int32_t n, int k, const T *r, const T *z, PcgParts P, const PcgState *st) {
+    LAUNCH(pcg_dot_rz_kernel<T>, P.G, n, k, r, z, P, st);
+}
+template <class T>
+void launch_pcg_init_plain(hipStream_t s, int32_t n, const T *b, T *x, T *r, PcgParts P) {
+    LAUNCH(pcg_init_plain_kernel<T>, P.G, n, b, x, r, P);
+}
+void launch_scaled_norm(hipStream_t s, int32_t n, const double *sc, const double *r, double *parts, double *out) {
+    const unsigned g = vec_grid(n);
+    LAUNCH(scaled_norm_kernel, g, n, sc, r, parts);
+    launch_finalize_sum(s, parts, (int)g, (int)g, 1, out);
+}
+void launch_scale_to_float(hipStream_t s, int32_t n, const double *sc, const double *r, const double *nrm2,
+                           float *r32) {
+    if (n > 0) LAUNCH(scale_to_float_kernel, vec_grid(n), n, sc, r, nrm2, r32);
+}
+void launch_correct(hipStream_t s, int32_t n, double *x, const double *sc, const float *d32, const double *nrm2) {
+    if (n > 0) LAUNCH(correct_kernel, vec_grid(n), n, x, sc, d32, nrm2);
+}
+void launch_diag_scaling(hipStream_t s, Sell<double> A, const int32_t *diag_pos, double *sc, double *As) {
+    if (A.n <= 0) return;
+    LAUNCH(diag_scale_kernel, vec_grid(A.n), A.n, diag_pos, A.val, sc);
+    LAUNCH(scale_matrix_kernel, vec_grid(A.n), A, sc, As);
+}
+
+#define INST(T)                                                                                                   \
+    template void launch_pcg_direction<T>(hipStream_t, int32_t, int, const T *, T *, PcgParts, PcgState *, bool); \
+    template void launch_pcg_spmv<T, T>(hipStream_t, Sell<T>, const T *, T *, PcgParts, const PcgState *);        \
+    template void launch_pcg_update_xr<T>(hipStream_t, int32_t, int, T *, T *, const T *, const T *, PcgParts,   \
+                                          PcgState *);                                                            \
+    template void launch_pcg_dot_rz<T>(hipStream_t, int32_t, int, const T *, const T *, PcgParts,                 \
+                                       const PcgState *);                                                         \
+    template void launch_pcg_init_plain<T>(hipStream_t, int32_t, const T *, T *, T *, PcgParts);
+INST(double)
+INST(float)
 
 }  // namespace vag

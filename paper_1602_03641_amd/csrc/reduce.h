@@ -1,10 +1,11 @@
-// Deterministic grid-wide reductions for wave64 devices.
+// Deterministic reductions for wave64 devices without grid-wide fences.
 //
-// Each block reduces its threads' values (wave shuffles, then LDS across the
-// block's waves), writes one partial per block, and the last block to finish
-// (ticket counter) sums the partials in block order.  The summation order
-// depends only on the launch shape, never on timing, so results are bitwise
-// reproducible run to run.
+// A reducing kernel writes one partial per block (block_partials).  The total
+// is formed later, after a kernel boundary has made the partials visible: either
+// redundantly by every block of the consuming kernel (sum_parts, all blocks
+// read the same partials in the same order and get the same bits), or by a
+// one-block finishing kernel.  The summation order depends only on the launch
+// shape, never on timing, so results are bitwise reproducible.
 #pragma once
 
 #include "vag_internal.h"
@@ -27,10 +28,11 @@ __device__ inline double wave_reduce(double v) {
     return v;  // valid in lane 0
 }
 
-// Reduces NV values per thread over the block; results valid in thread 0.
+// Reduces NV values per thread over the block; results valid in every thread.
 template <class Op, int NV, int NT>
 __device__ inline void block_reduce(double (&v)[NV]) {
     __shared__ double lds[NV][NT / 64];
+    __shared__ double res[NV];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -38,50 +40,34 @@ __device__ inline void block_reduce(double (&v)[NV]) {
         if (lane == 0) lds[k][w] = t;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double t = lds[k][0];
-            for (int i = 1; i < NT / 64; ++i) t = Op::op(t, lds[k][i]);
-            v[k] = t;
-        }
+    if (threadIdx.x < NV) {
+        double t = lds[threadIdx.x][0];
+        for (int i = 1; i < NT / 64; ++i) t = Op::op(t, lds[threadIdx.x][i]);
+        res[threadIdx.x] = t;
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = res[k];
     __syncthreads();
 }
 
-// Grid reduction; returns true in the block that holds the final values
-// (valid in its thread 0).  Uses ticket slot `slot`; resets it for reuse.
+// Writes the block's reduction of NV values to parts[k * stride + blockIdx.x].
 template <class Op, int NV, int NT>
-__device__ inline bool grid_reduce(double (&v)[NV], ReduceScratch rs, int slot) {
-    __shared__ bool is_last;
+__device__ inline void block_partials(double (&v)[NV], double *parts, int stride) {
     block_reduce<Op, NV, NT>(v);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k)
-            __hip_atomic_store(&rs.parts[(size_t)blockIdx.x * NV + k], v[k], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const unsigned t = atomicAdd(&rs.ticket[slot], 1u);
-        is_last = (t == gridDim.x - 1);
+        for (int k = 0; k < NV; ++k) parts[(size_t)k * stride + blockIdx.x] = v[k];
     }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double acc[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = Op::id();
-    for (unsigned i = threadIdx.x; i < gridDim.x; i += NT)
-#pragma unroll
-        for (int k = 0; k < NV; ++k)
-            acc[k] = Op::op(acc[k], __hip_atomic_load(&rs.parts[(size_t)i * NV + k], __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT));
-    block_reduce<Op, NV, NT>(acc);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] = acc[k];
-        rs.ticket[slot] = 0u;
-    }
-    return true;
+}
+
+// Total of nparts partials, identical in every thread of every block.
+template <class Op, int NT>
+__device__ inline double sum_parts(const double *parts, int nparts) {
+    double v[1] = {Op::id()};
+    for (int i = threadIdx.x; i < nparts; i += NT) v[0] = Op::op(v[0], parts[i]);
+    block_reduce<Op, 1, NT>(v);
+    return v[0];
 }
 
 inline unsigned reduce_grid(int64_t n_items, int threads) {
@@ -90,5 +76,9 @@ inline unsigned reduce_grid(int64_t n_items, int threads) {
     if (b < 1) b = 1;
     return (unsigned)b;
 }
+
+// one-block kernel: out[k] = Op-total of parts[k*stride .. k*stride+nparts)
+void launch_finalize_sum(hipStream_t s, const double *parts, int stride, int nparts, int nv, double *out);
+void launch_finalize_min(hipStream_t s, const double *parts, int stride, int nparts, int nv, double *out);
 
 }  // namespace vag

@@ -214,10 +214,42 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
         }
     }
     S.nnz = S.row_ptr[S.nunk];
+
+    // sliced ELL copy of the pattern (64-row slices, column-major in a slice)
+    {
+        const int32_t n = S.nunk;
+        const int64_t nslice = (n + kSliceRows - 1) / kSliceRows;
+        S.sell_ptr.assign(nslice + 1, 0);
+        for (int64_t sl = 0; sl < nslice; ++sl) {
+            int32_t w = 0;
+            for (int32_t r = (int32_t)(sl * kSliceRows); r < std::min<int64_t>(n, (sl + 1) * kSliceRows); ++r)
+                w = std::max(w, S.row_ptr[r + 1] - S.row_ptr[r]);
+            S.sell_ptr[sl + 1] = S.sell_ptr[sl] + (int64_t)w * kSliceRows;
+        }
+        if (S.sell_ptr[nslice] >= INT32_MAX)
+            throw Error(VAG_ERR_UNSUPPORTED, "padded system has more than 2^31 entries");
+        S.sell_col.assign(S.sell_ptr[nslice], 0);
+        S.csr2sell.assign(S.nnz, -1);
+        for (int64_t sl = 0; sl < nslice; ++sl) {
+            const int32_t w = (int32_t)((S.sell_ptr[sl + 1] - S.sell_ptr[sl]) / kSliceRows);
+            for (int lane = 0; lane < kSliceRows; ++lane) {
+                const int64_t r = sl * kSliceRows + lane;
+                for (int32_t k = 0; k < w; ++k) {
+                    const int64_t pos = S.sell_ptr[sl] + (int64_t)k * kSliceRows + lane;
+                    if (r < n && k < S.row_ptr[r + 1] - S.row_ptr[r]) {
+                        S.sell_col[pos] = S.col[S.row_ptr[r] + k];
+                        S.csr2sell[S.row_ptr[r] + k] = (int32_t)pos;
+                    } else {
+                        S.sell_col[pos] = r < n ? (int32_t)r : 0;  // padding: own row, value 0
+                    }
+                }
+            }
+        }
+    }
     S.diag_pos.assign(S.nunk, -1);
     for (int32_t r = 0; r < S.nunk; ++r)
         for (int32_t q = S.row_ptr[r]; q < S.row_ptr[r + 1]; ++q)
-            if (S.col[q] == r) S.diag_pos[r] = q;
+            if (S.col[q] == r) S.diag_pos[r] = S.csr2sell[q];
 
     // slot maps
     S.slot_ptr.assign((size_t)nc + 1, 0);
@@ -240,7 +272,7 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
                 } else {
                     const int32_t *c0 = S.col.data() + S.row_ptr[u[a]];
                     const int32_t *c1 = S.col.data() + S.row_ptr[u[a] + 1];
-                    v = (int32_t)(std::lower_bound(c0, c1, u[b]) - S.col.data());
+                    v = S.csr2sell[std::lower_bound(c0, c1, u[b]) - S.col.data()];
                 }
                 out[a * m + b] = v;
             }

@@ -191,8 +191,7 @@ __global__ __launch_bounds__(kT) void cfl_kernel(
     const uint8_t *__restrict__ dirichlet, const int32_t *__restrict__ ncp, const int32_t *__restrict__ ncl,
     const int32_t *__restrict__ nfp, const int32_t *__restrict__ nfl, const double *__restrict__ F_cell,
     const double *__restrict__ F_cell_frac, const double *__restrict__ F_frac, const double *__restrict__ phi_cell,
-    const double *__restrict__ phi_frac, const double *__restrict__ phi_node, double cfl, ReduceScratch rs,
-    double *__restrict__ dt_out) {
+    const double *__restrict__ phi_frac, const double *__restrict__ phi_node, double *__restrict__ parts) {
     const double inf = __builtin_inf();
     double v[3] = {inf, inf, inf};
     const int64_t total = (int64_t)nc + nf + nn;
@@ -213,11 +212,19 @@ __global__ __launch_bounds__(kT) void cfl_kernel(
             }
         }
     }
-    if (grid_reduce<OpMin, 3, kT>(v, rs, 3) && threadIdx.x == 0) {
-        dt_out[0] = v[0];
-        dt_out[1] = v[1];
-        dt_out[2] = v[2];
-        dt_out[3] = cfl * fmin(v[0], fmin(v[1], v[2]));
+    block_partials<OpMin, 3, kT>(v, parts, gridDim.x);
+}
+
+__global__ __launch_bounds__(kT) void cfl_finish_kernel(const double *__restrict__ parts, int G, double cfl,
+                                                        double *__restrict__ dt_out) {
+    const double a = sum_parts<OpMin, kT>(parts, G);
+    const double b = sum_parts<OpMin, kT>(parts + G, G);
+    const double c = sum_parts<OpMin, kT>(parts + 2 * (size_t)G, G);
+    if (threadIdx.x == 0) {
+        dt_out[0] = a;
+        dt_out[1] = b;
+        dt_out[2] = c;
+        dt_out[3] = cfl * fmin(a, fmin(b, c));
     }
 }
 
@@ -467,11 +474,13 @@ void launch_cfl(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t
                 const int32_t *node_cell_ptr, const int32_t *node_cell, const int32_t *node_frac_ptr,
                 const int32_t *node_frac, const double *F_cell, const double *F_cell_frac, const double *F_frac,
                 const double *phi_cell, const double *phi_frac, const double *phi_node, double cfl,
-                ReduceScratch rs, double *dt_out) {
+                double *parts, double *dt_out) {
     const int64_t total = (int64_t)nc + nf + nn;
-    hipLaunchKernelGGL(cfl_kernel, dim3(reduce_grid(total, kT)), dim3(kT), 0, s, nc, nf, nn, hex8, fmask, cell_frac,
-                       frac_cell, dirichlet, node_cell_ptr, node_cell, node_frac_ptr, node_frac, F_cell,
-                       F_cell_frac, F_frac, phi_cell, phi_frac, phi_node, cfl, rs, dt_out);
+    const unsigned G = reduce_grid(total, kT);
+    hipLaunchKernelGGL(cfl_kernel, dim3(G), dim3(kT), 0, s, nc, nf, nn, hex8, fmask, cell_frac, frac_cell,
+                       dirichlet, node_cell_ptr, node_cell, node_frac_ptr, node_frac, F_cell, F_cell_frac, F_frac,
+                       phi_cell, phi_frac, phi_node, parts);
+    hipLaunchKernelGGL(cfl_finish_kernel, dim3(1), dim3(kT), 0, s, parts, (int)G, cfl, dt_out);
     VAG_HIP(hipGetLastError());
 }
 void launch_upwind_count(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const uint8_t *fmask,

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "amg.h"
 #include "vag_internal.h"
 
 using namespace vag;
@@ -19,7 +20,8 @@ struct vag_handle {
     // topology
     DBuf<double> xyz;
     DBuf<int32_t> hex8, cell_frac, frac_cell, frac_slot, frac_nodes, node_unk, node_cell_ptr, node_cell,
-        node_frac_ptr, node_frac, color_cells, row_ptr, col, diag_pos, slots;
+        node_frac_ptr, node_frac, color_cells, sell_col, diag_pos, slots;
+    DBuf<int64_t> sell_ptr;
     DBuf<uint8_t> fmask, dirichlet, frac_node;
     DBuf<int64_t> slot_ptr;
     // numeric inputs
@@ -28,9 +30,8 @@ struct vag_handle {
     DBuf<double> aK, rK, AKK, vol, fside, A5, area, A, b, dinv;
     DBuf<int> bad;
     // Krylov
-    DBuf<double> x, r, z, p, q, parts, scal;
-    DBuf<unsigned> ticket;
-    DBuf<PcgState> pcg;
+    DBuf<double> x, r, z, p, q, parts, rparts, scal;
+    DBuf<PcgState> pcg;  // [0] the solve, [1] kernel timing (never done)
     // results
     DBuf<double> u_node, u_cell, u_frac, F_cell, F_cell_frac, F_frac, phi_cell, phi_frac, phi_node;
     // transport
@@ -40,13 +41,17 @@ struct vag_handle {
     DBuf<unsigned long long> cnt;
     unsigned long long *h_cnt = nullptr;
     int cur = 0;
-    bool solved = false, have_c = false;
+    bool solved = false, have_flux = false, have_c = false;
 
+    Amg amg;
+    DBuf<float> b32, x32, r32, z32, p32, q32;  // inner single-precision solve (VAG_MIXED)
+    DBuf<double> dsc, As;                      // D^-1/2 and the scaled matrix D^-1/2 A D^-1/2
+    int last_outer = 1, last_inner = 0;
     PcgState *h_pcg = nullptr;
     double *h_scal = nullptr;
     hipEvent_t ev[8] = {};
 
-    ReduceScratch rs() { return ReduceScratch{parts.p, ticket.p}; }
+    Sell<double> Asell() const { return Sell<double>{S.nunk, sell_ptr.p, sell_col.p, A.p}; }
     double *c_cur() { return cur ? cbuf1.p : cbuf0.p; }
     double *c_next() { return cur ? cbuf0.p : cbuf1.p; }
 
@@ -122,15 +127,18 @@ std::vector<T> host_copy(const T *src, size_t n, vag_mem mem) {
 void check_options(const vag_options &o) {
     if (!(o.rtol > 0) || o.max_iter < 0 || !(o.cfl > 0) || o.check_every <= 0)
         throw Error(VAG_ERR_ARG, "invalid options (rtol, max_iter, cfl or check_every)");
-    if (o.precision != VAG_FP64)
-        throw Error(VAG_ERR_UNSUPPORTED, "only VAG_FP64 is implemented in this build");
+    if (o.precision != VAG_FP64 && o.precision != VAG_MIXED) throw Error(VAG_ERR_ARG, "unknown precision");
+    if (o.precision == VAG_MIXED && o.precond != VAG_PC_AMG)
+        throw Error(VAG_ERR_UNSUPPORTED, "VAG_MIXED needs the AMG preconditioner");
+    if (o.precision == VAG_MIXED && !(o.inner_rtol > 0 && o.inner_rtol < 1))
+        throw Error(VAG_ERR_ARG, "inner_rtol must lie in (0, 1)");
     if (o.krylov != VAG_CG) throw Error(VAG_ERR_UNSUPPORTED, "only VAG_CG is implemented in this build");
     if (o.precond != VAG_PC_JACOBI && o.precond != VAG_PC_AMG)
         throw Error(VAG_ERR_ARG, "unknown preconditioner");
 }
 
 // z = M^{-1} r for the handle's preconditioner
-void precond_apply(vag_handle *h, const double *r, double *z);
+void precond_apply(vag_handle *h, const double *r, double *z, const PcgState *st);
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
     float ms = 0.f;
@@ -141,8 +149,122 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 }  // namespace
 
 namespace {
-void precond_apply(vag_handle *h, const double *r, double *z) {
-    launch_jacobi(h->stream, h->S.nunk, h->dinv.p, r, z);
+void precond_apply(vag_handle *h, const double *r, double *z, const PcgState *st) {
+    if (h->opt.precond == VAG_PC_AMG)
+        h->amg.apply(h->stream, r, z, st);
+    else
+        launch_jacobi(h->stream, h->S.nunk, h->dinv.p, r, z);
+}
+
+AmgOptions amg_options(const vag_options &o) {
+    AmgOptions a;
+    if (o.amg_theta > 0) a.theta = o.amg_theta;
+    if (o.amg_coarse_size > 0) a.coarse_size = o.amg_coarse_size;
+    if (o.amg_max_levels > 0) a.max_levels = o.amg_max_levels;
+    return a;
+}
+
+// Preconditioned CG from x = 0 on the device; the host only queues iterations
+// and reads the state every check_every iterations.
+void run_pcg(vag_handle *h) {
+    hipStream_t s = h->stream;
+    const int32_t n = h->S.nunk;
+    const PcgParts P{h->parts.p, pcg_grid(n)};
+    PcgState *st = h->pcg.p;
+    const bool jacobi = h->opt.precond == VAG_PC_JACOBI;
+    if (jacobi) {
+        launch_pcg_init(s, n, h->b.p, h->dinv.p, h->x.p, h->r.p, h->z.p, P);
+    } else {
+        launch_pcg_init(s, n, h->b.p, nullptr, h->x.p, h->r.p, h->z.p, P);
+        precond_apply(h, h->r.p, h->z.p, nullptr);
+        launch_pcg_dot_rz<double>(s, n, -1, h->r.p, h->z.p, P, nullptr);
+    }
+    launch_pcg_start(s, P, st, h->opt.rtol);
+    const Sell<double> A = h->Asell();
+    int k = 0;
+    const int max_iter = h->opt.max_iter;
+    for (;;) {
+        const int kend = std::min(k + h->opt.check_every, max_iter);
+        for (; k < kend; ++k) {
+            launch_pcg_direction<double>(s, n, k, h->z.p, h->p.p, P, st, true);
+            launch_pcg_spmv<double, double>(s, A, h->p.p, h->q.p, P, st);
+            if (jacobi) {
+                launch_pcg_update(s, n, k, h->x.p, h->r.p, h->z.p, h->p.p, h->q.p, h->dinv.p, P, st);
+            } else {
+                launch_pcg_update_xr<double>(s, n, k, h->x.p, h->r.p, h->p.p, h->q.p, P, st);
+                precond_apply(h, h->r.p, h->z.p, st);
+                launch_pcg_dot_rz<double>(s, n, k, h->r.p, h->z.p, P, st);
+            }
+        }
+        if (k >= max_iter) launch_pcg_direction<double>(s, n, k, h->z.p, h->p.p, P, st, false);  // final test only
+        VAG_HIP(hipMemcpyAsync(h->h_pcg, st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipStreamSynchronize(s));
+        if (h->h_pcg->done || k >= max_iter) break;
+    }
+    h->last_inner = h->h_pcg->iter;
+    h->last_outer = 1;
+}
+
+// FP64 iterative refinement: r = b - A x in FP64.  With S = D^-1/2 the
+// correction solves (S A S) d = S r / ||S r|| by CG in FP32 with the FP32
+// hierarchy of S A S to inner_rtol, then x += ||S r|| S d in FP64.  The scaling
+// makes every FP32 matrix entry O(1) whatever the permeability contrast.
+// Stops when ||r|| <= rtol ||b||.
+void run_mixed(vag_handle *h) {
+    hipStream_t s = h->stream;
+    const int32_t n = h->S.nunk;
+    const PcgParts P{h->parts.p, pcg_grid(n)};
+    PcgState *st = h->pcg.p;
+    Tracker &tr = h->tr;
+    for (auto *v : {&h->b32, &h->x32, &h->r32, &h->z32, &h->p32, &h->q32}) ensure(*v, (size_t)std::max(n, 1), tr);
+    h->amg.make_fp32(s, tr, nullptr);
+    const Sell<float> A32 = h->amg.L[0]->A32;
+    launch_fill(s, n, 0.0, h->x.p);
+    launch_residual_norm(s, h->Asell(), h->x.p, h->b.p, h->r.p, h->rparts.p, h->scal.p);
+    VAG_HIP(hipMemcpyAsync(h->h_scal, h->scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    VAG_HIP(hipStreamSynchronize(s));
+    const double bb = h->h_scal[1];
+    double rr = h->h_scal[0];
+    const double tol2 = h->opt.rtol * h->opt.rtol * bb;
+    int inner_total = 0, outer = 0;
+    bool converged = (rr <= tol2);
+    while (!converged && inner_total < h->opt.max_iter) {
+        ++outer;
+        launch_scaled_norm(s, n, h->dsc.p, h->r.p, h->rparts.p, h->scal.p + 2);
+        launch_scale_to_float(s, n, h->dsc.p, h->r.p, h->scal.p + 2, h->b32.p);
+        launch_pcg_init_plain<float>(s, n, h->b32.p, h->x32.p, h->r32.p, P);
+        h->amg.apply32(s, h->r32.p, h->z32.p, nullptr);
+        launch_pcg_dot_rz<float>(s, n, -1, h->r32.p, h->z32.p, P, nullptr);
+        launch_pcg_start(s, P, st, h->opt.inner_rtol);
+        const int budget = h->opt.max_iter - inner_total;
+        int k = 0;
+        for (;;) {
+            const int kend = std::min(k + h->opt.check_every, budget);
+            for (; k < kend; ++k) {
+                launch_pcg_direction<float>(s, n, k, h->z32.p, h->p32.p, P, st, true);
+                launch_pcg_spmv<float, float>(s, A32, h->p32.p, h->q32.p, P, st);
+                launch_pcg_update_xr<float>(s, n, k, h->x32.p, h->r32.p, h->p32.p, h->q32.p, P, st);
+                h->amg.apply32(s, h->r32.p, h->z32.p, st);
+                launch_pcg_dot_rz<float>(s, n, k, h->r32.p, h->z32.p, P, st);
+            }
+            if (k >= budget) launch_pcg_direction<float>(s, n, k, h->z32.p, h->p32.p, P, st, false);
+            VAG_HIP(hipMemcpyAsync(h->h_pcg, st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+            VAG_HIP(hipStreamSynchronize(s));
+            if (h->h_pcg->done || k >= budget) break;
+        }
+        inner_total += std::max(h->h_pcg->iter, 1);
+        launch_correct(s, n, h->x.p, h->dsc.p, h->x32.p, h->scal.p + 2);
+        launch_residual_norm(s, h->Asell(), h->x.p, h->b.p, h->r.p, h->rparts.p, h->scal.p);
+        VAG_HIP(hipMemcpyAsync(h->h_scal, h->scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipStreamSynchronize(s));
+        rr = h->h_scal[0];
+        converged = (rr <= tol2);
+    }
+    h->h_pcg->iter = inner_total;
+    h->h_pcg->converged = converged;
+    h->h_pcg->done = 1;
+    h->last_inner = inner_total;
+    h->last_outer = outer;
 }
 }  // namespace
 
@@ -164,7 +286,7 @@ vag_status vag_default_options(vag_options *o) {
     o->cfl = 0.9;
     o->amg_coarse_size = 500;
     o->amg_max_levels = 12;
-    o->amg_theta = 0.08;
+    o->amg_theta = 0.02;
     o->amg_sweeps = 1;
     return VAG_OK;
 }
@@ -210,8 +332,8 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         upload_vec(h, h->node_frac_ptr, S.node_frac_ptr);
         upload_vec(h, h->node_frac, S.node_frac);
         upload_vec(h, h->color_cells, S.color_cells);
-        upload_vec(h, h->row_ptr, S.row_ptr);
-        upload_vec(h, h->col, S.col);
+        upload_vec(h, h->sell_ptr, S.sell_ptr);
+        upload_vec(h, h->sell_col, S.sell_col);
         upload_vec(h, h->diag_pos, S.diag_pos);
         upload_vec(h, h->slot_ptr, S.slot_ptr);
         upload_vec(h, h->slots, S.slots);
@@ -238,16 +360,16 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         h->fside.alloc(12 * (size_t)std::max<int64_t>(nf, 1), h->tr);
         h->A5.alloc(25 * (size_t)std::max<int64_t>(nf, 1), h->tr);
         h->area.alloc(std::max<int64_t>(nf, 1), h->tr);
-        h->A.alloc(S.nnz, h->tr);
+        h->A.alloc(S.sell_col.size(), h->tr);
         h->b.alloc(n, h->tr);
         h->dinv.alloc(n, h->tr);
         h->bad.alloc(1, h->tr);
         for (auto *v : {&h->x, &h->r, &h->z, &h->p, &h->q}) v->alloc(n, h->tr);
-        h->parts.alloc(4 * (size_t)kReduceBlocks, h->tr);
-        h->ticket.alloc(8, h->tr);
-        VAG_HIP(hipMemset(h->ticket.p, 0, 8 * sizeof(unsigned)));
+        h->parts.alloc(5 * (size_t)kReduceBlocks, h->tr);
+        h->rparts.alloc(4 * (size_t)kReduceBlocks, h->tr);
         h->scal.alloc(8, h->tr);
-        h->pcg.alloc(1, h->tr);
+        h->pcg.alloc(2, h->tr);
+        VAG_HIP(hipMemset(h->pcg.p, 0, 2 * sizeof(PcgState)));
         h->u_node.alloc(nn, h->tr);
         h->u_cell.alloc(nc, h->tr);
         h->u_frac.alloc(std::max<int64_t>(nf, 1), h->tr);
@@ -299,6 +421,34 @@ vag_status vag_update(vag_handle *h, const vag_rock *rock, const vag_fractures *
         if (p_bar) upload(h, h->p_bar, p_bar, nn, mem);
         if (c_bar) upload(h, h->c_bar, c_bar, nn, mem);
         h->solved = false;
+        h->have_flux = false;
+    });
+}
+
+vag_status vag_set_fluxes(vag_handle *h, const double *F_cell, const double *F_cell_frac, const double *F_frac,
+                          vag_mem mem) {
+    if (!h) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        const Symbolic &S = h->S;
+        hipStream_t s = h->stream;
+        if (!F_cell || (S.nf && (!F_cell_frac || !F_frac))) throw Error(VAG_ERR_ARG, "null flux array");
+        VAG_HIP(hipMemcpyAsync(h->F_cell.p, F_cell, 8 * (size_t)S.nc * sizeof(double), kind_in(mem), s));
+        if (S.nf) {
+            VAG_HIP(hipMemcpyAsync(h->F_cell_frac.p, F_cell_frac, 2 * (size_t)S.nf * sizeof(double), kind_in(mem), s));
+            VAG_HIP(hipMemcpyAsync(h->F_frac.p, F_frac, 4 * (size_t)S.nf * sizeof(double), kind_in(mem), s));
+        }
+        // cell volumes and face areas come with the local matrices
+        VAG_HIP(hipMemsetAsync(h->bad.p, 0x7f, sizeof(int), s));
+        launch_local(s, S.nc, h->xyz.p, h->hex8.p, h->perm.p, h->mu, h->fmask.p, h->cell_frac.p, h->frac_cell.p,
+                     h->aK.p, h->rK.p, h->AKK.p, h->vol.p, h->fside.p, h->bad.p);
+        launch_frac_local(s, S.nf, h->xyz.p, h->frac_nodes.p, h->fwidth.p, h->fperm.p, h->mu, h->A5.p, h->area.p);
+        launch_porous(s, S.nc, S.nf, S.nn, h->hex8.p, h->frac_nodes.p, h->dirichlet.p, h->frac_node.p,
+                      h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->vol.p, h->poro.p,
+                      h->area.p, h->fwidth.p, h->fporo.p, h->phi_cell.p, h->phi_frac.p, h->phi_node.p);
+        VAG_HIP(hipStreamSynchronize(s));
+        h->solved = false;
+        h->have_flux = true;
+        h->have_c = false;
     });
 }
 
@@ -324,7 +474,7 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
                      h->aK.p, h->rK.p, h->AKK.p, h->vol.p, h->fside.p, h->bad.p);
         launch_frac_local(s, S.nf, h->xyz.p, h->frac_nodes.p, h->fwidth.p, h->fperm.p, h->mu, h->A5.p, h->area.p);
         // 2. cell elimination, colour by colour
-        launch_fill(s, S.nnz, 0.0, h->A.p);
+        launch_fill(s, (int64_t)h->A.n, 0.0, h->A.p);  // padding stays 0
         launch_fill(s, n, 0.0, h->b.p);
         for (int c = 0; c < S.ncolor; ++c)
             launch_scatter(s, S.color_ptr[c + 1] - S.color_ptr[c], h->color_cells.p + S.color_ptr[c], S.nc, S.nfree,
@@ -333,21 +483,23 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
                            h->slot_ptr.p, h->slots.p, h->A.p, h->b.p);
         launch_diag_inv(s, n, h->diag_pos.p, h->A.p, h->dinv.p);
         VAG_HIP(hipEventRecord(h->ev[1], s));
+        if (h->opt.precision == VAG_MIXED) {
+            // the single-precision hierarchy is built on the symmetrically scaled matrix
+            ensure(h->dsc, (size_t)std::max(n, 1), h->tr);
+            ensure(h->As, h->A.n, h->tr);
+            launch_fill(s, (int64_t)h->A.n, 0.0, h->As.p);
+            launch_diag_scaling(s, h->Asell(), h->diag_pos.p, h->dsc.p, h->As.p);
+            h->amg.setup(s, h->tr, Sell<double>{n, h->sell_ptr.p, h->sell_col.p, h->As.p}, (int64_t)h->A.n,
+                         amg_options(h->opt));
+        } else if (h->opt.precond == VAG_PC_AMG) {
+            h->amg.setup(s, h->tr, h->Asell(), (int64_t)h->A.n, amg_options(h->opt));
+        }
         VAG_HIP(hipEventRecord(h->ev[2], s));
         // 3. Krylov
-        if (h->opt.precond == VAG_PC_AMG) {
-            // the AMG hierarchy is not part of this build yet: Jacobi
-        }
-        launch_pcg_init(s, n, h->b.p, h->dinv.p, h->x.p, h->r.p, h->z.p, h->p.p, h->rs(), h->pcg.p, h->opt.rtol,
-                        h->opt.max_iter);
-        for (;;) {
-            for (int k = 0; k < h->opt.check_every; ++k)
-                launch_pcg_iter(s, n, h->row_ptr.p, h->col.p, h->A.p, h->dinv.p, h->x.p, h->r.p, h->z.p, h->p.p,
-                                h->q.p, h->rs(), h->pcg.p);
-            VAG_HIP(hipMemcpyAsync(h->h_pcg, h->pcg.p, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-            VAG_HIP(hipStreamSynchronize(s));
-            if (h->h_pcg->done) break;
-        }
+        if (h->opt.precision == VAG_MIXED)
+            run_mixed(h);
+        else
+            run_pcg(h);
         VAG_HIP(hipEventRecord(h->ev[3], s));
         const PcgState pst = *h->h_pcg;
         converged = pst.converged != 0;
@@ -363,7 +515,7 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
                       h->area.p, h->fwidth.p, h->fporo.p, h->phi_cell.p, h->phi_frac.p, h->phi_node.p);
         VAG_HIP(hipEventRecord(h->ev[4], s));
         // true residual ||b - A x|| / ||b||
-        launch_residual_norm(s, n, h->row_ptr.p, h->col.p, h->A.p, h->x.p, h->b.p, h->r.p, h->rs(), h->scal.p);
+        launch_residual_norm(s, h->Asell(), h->x.p, h->b.p, h->r.p, h->rparts.p, h->scal.p);
         VAG_HIP(hipMemcpyAsync(h->h_scal, h->scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         int bad = 0;
         VAG_HIP(hipMemcpyAsync(&bad, h->bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -373,18 +525,19 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
         if (info) {
             std::memset(info, 0, sizeof *info);
             info->iterations = pst.iter;
-            info->outer_iterations = 1;
+            info->outer_iterations = h->last_outer;
             info->rel_residual = h->h_scal[1] > 0 ? std::sqrt(h->h_scal[0] / h->h_scal[1]) : 0.0;
             info->n_unknowns = n;
             info->nnz = S.nnz;
-            info->amg_levels = 0;
-            info->amg_operator_complexity = 1.0;
+            info->amg_levels = h->opt.precond == VAG_PC_AMG ? h->amg.nlev : 0;
+            info->amg_operator_complexity = h->opt.precond == VAG_PC_AMG ? h->amg.op_complexity : 1.0;
             info->ms_assembly = elapsed(h->ev[0], h->ev[1]);
             info->ms_setup = elapsed(h->ev[1], h->ev[2]);
             info->ms_solve = elapsed(h->ev[2], h->ev[3]);
             info->ms_fluxes = elapsed(h->ev[3], h->ev[4]);
         }
         h->solved = true;
+        h->have_flux = true;
         h->have_c = false;
     });
     if (st == VAG_OK && !converged) {
@@ -398,7 +551,7 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
                          const double *c0_frac, const double *c0_node, vag_mem mem, vag_transport_info *info) {
     if (!h) return VAG_ERR_ARG;
     return guard(h, [&] {
-        if (!h->solved) throw Error(VAG_ERR_STATE, "vag_transport needs a pressure solve first");
+        if (!h->have_flux) throw Error(VAG_ERR_STATE, "vag_transport needs a pressure solve (or vag_set_fluxes) first");
         if (n_steps < 0 || t_final < 0) throw Error(VAG_ERR_ARG, "negative step count or final time");
         const Symbolic &S = h->S;
         hipStream_t s = h->stream;
@@ -407,8 +560,8 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
         VAG_HIP(hipEventRecord(h->ev[5], s));
         launch_cfl(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
                    h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
-                   h->F_cell_frac.p, h->F_frac.p, h->phi_cell.p, h->phi_frac.p, h->phi_node.p, h->opt.cfl, h->rs(),
-                   h->dt4.p);
+                   h->F_cell_frac.p, h->F_frac.p, h->phi_cell.p, h->phi_frac.p, h->phi_node.p, h->opt.cfl,
+                   h->rparts.p, h->dt4.p);
         VAG_HIP(hipMemsetAsync(h->cnt.p, 0, sizeof(unsigned long long), s));
         launch_upwind_count(s, S.nc, S.nf, S.nn, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
                             h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
@@ -492,7 +645,7 @@ vag_status vag_get_pressure(vag_handle *h, double *u_node, double *u_cell, doubl
 vag_status vag_get_fluxes(vag_handle *h, double *F_cell, double *F_cell_frac, double *F_frac, vag_mem mem) {
     if (!h) return VAG_ERR_ARG;
     return guard(h, [&] {
-        if (!h->solved) throw Error(VAG_ERR_STATE, "no pressure solve yet");
+        if (!h->have_flux) throw Error(VAG_ERR_STATE, "no pressure solve yet");
         download(h, F_cell, h->F_cell, 8 * (size_t)h->S.nc, mem);
         download(h, F_cell_frac, h->F_cell_frac, 2 * (size_t)h->S.nf, mem);
         download(h, F_frac, h->F_frac, 4 * (size_t)h->S.nf, mem);
@@ -504,7 +657,7 @@ vag_status vag_get_porous_volumes(vag_handle *h, double *phi_cell, double *phi_f
                                   vag_mem mem) {
     if (!h) return VAG_ERR_ARG;
     return guard(h, [&] {
-        if (!h->solved) throw Error(VAG_ERR_STATE, "no pressure solve yet");
+        if (!h->have_flux) throw Error(VAG_ERR_STATE, "no pressure solve yet");
         download(h, phi_cell, h->phi_cell, h->S.nc, mem);
         download(h, phi_frac, h->phi_frac, h->S.nf, mem);
         download(h, phi_node, h->phi_node, h->S.nn, mem);
@@ -538,10 +691,14 @@ vag_status vag_get_system(vag_handle *h, int64_t *row_ptr, int64_t *col, double 
         if (!h->solved) throw Error(VAG_ERR_STATE, "no pressure solve yet");
         const Symbolic &S = h->S;
         std::vector<int64_t> rp(S.row_ptr.begin(), S.row_ptr.end()), cl(S.col.begin(), S.col.end());
+        std::vector<double> sv(h->A.n), cv(S.nnz);
+        VAG_HIP(hipMemcpyAsync(sv.data(), h->A.p, sv.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        VAG_HIP(hipStreamSynchronize(h->stream));
+        for (int64_t q = 0; q < S.nnz; ++q) cv[q] = sv[S.csr2sell[q]];
         hipMemcpyKind k = mem == VAG_MEM_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
         if (row_ptr) VAG_HIP(hipMemcpy(row_ptr, rp.data(), rp.size() * sizeof(int64_t), k));
         if (col) VAG_HIP(hipMemcpy(col, cl.data(), cl.size() * sizeof(int64_t), k));
-        download(h, val, h->A, S.nnz, mem);
+        if (val) VAG_HIP(hipMemcpy(val, cv.data(), cv.size() * sizeof(double), k));
         download(h, b, h->b, S.nunk, mem);
         VAG_HIP(hipStreamSynchronize(h->stream));
     });
@@ -558,8 +715,13 @@ vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms)
             throw Error(VAG_ERR_STATE, "the transport step needs a transport call first");
         auto once = [&] {
             switch (kernel) {
-                case VAG_KERNEL_SPMV:
-                    launch_spmv(s, S.nunk, h->row_ptr.p, h->col.p, h->A.p, h->x.p, h->q.p);
+                case VAG_KERNEL_SPMV:  // the Krylov loop's SpMV (with its dot-product partials)
+                    if (h->opt.precision == VAG_MIXED && h->amg.have32)
+                        launch_pcg_spmv<float, float>(s, h->amg.L[0]->A32, h->x32.p, h->q32.p,
+                                                      PcgParts{h->parts.p, pcg_grid(S.nunk)}, h->pcg.p + 1);
+                    else
+                        launch_pcg_spmv<double, double>(s, h->Asell(), h->x.p, h->q.p,
+                                                        PcgParts{h->parts.p, pcg_grid(S.nunk)}, h->pcg.p + 1);
                     break;
                 case VAG_KERNEL_TRANSPORT_STEP:  // reads the current state, writes the spare buffer
                     launch_transport_step(s, (int32_t)nrow, h->slice_ptr.p, h->tcol.p, h->tval.p, h->tdiag.p,
@@ -570,7 +732,10 @@ vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms)
                                  h->frac_cell.p, h->aK.p, h->rK.p, h->AKK.p, h->vol.p, h->fside.p, h->bad.p);
                     break;
                 case VAG_KERNEL_PRECOND:
-                    precond_apply(h, h->r.p, h->z.p);
+                    if (h->opt.precision == VAG_MIXED && h->amg.have32)
+                        h->amg.apply32(s, h->r32.p, h->z32.p, nullptr);
+                    else
+                        precond_apply(h, h->r.p, h->z.p, nullptr);
                     break;
                 default:
                     throw Error(VAG_ERR_ARG, "unknown kernel id");
@@ -583,6 +748,16 @@ vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms)
         VAG_HIP(hipEventSynchronize(h->ev[6]));
         *ms = elapsed(h->ev[5], h->ev[6]) / reps;
     });
+}
+
+vag_status vag_amg_levels(vag_handle *h, int *nlev, int64_t *rows, int64_t *stored, int max_levels) {
+    if (!h || !nlev) return VAG_ERR_ARG;
+    *nlev = h->opt.precond == VAG_PC_AMG ? h->amg.nlev : 0;
+    for (int l = 0; l < *nlev && l < max_levels; ++l) {
+        if (rows) rows[l] = h->amg.L[l]->n;
+        if (stored) stored[l] = h->amg.L[l]->stored;
+    }
+    return VAG_OK;
 }
 
 size_t vag_footprint_bytes(const vag_handle *h) { return h ? h->tr.bytes : 0; }

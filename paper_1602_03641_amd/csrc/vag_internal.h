@@ -101,9 +101,11 @@ struct Symbolic {
     std::vector<int32_t> node_frac_ptr, node_frac;  // node -> frac*4+i, ascending
     int ncolor = 0;
     std::vector<int32_t> color_ptr, color_cells;     // cells grouped by colour
-    std::vector<int32_t> row_ptr, col, diag_pos;     // CSR pattern of the eliminated system
+    std::vector<int32_t> row_ptr, col;               // CSR pattern of the eliminated system
+    std::vector<int64_t> sell_ptr;                   // same pattern in sliced ELL
+    std::vector<int32_t> sell_col, csr2sell, diag_pos;  // diag_pos: SELL position of a_ii
     std::vector<int64_t> slot_ptr;                   // [nc+1]
-    std::vector<int32_t> slots;                      // per cell m*m positions (-1 Dirichlet row, -2 Dirichlet col)
+    std::vector<int32_t> slots;                      // per cell m*m SELL positions (-1 Dirichlet row, -2 Dirichlet col)
 };
 
 // Builds the symbolic data; throws vag::Error on invalid input.
@@ -113,14 +115,30 @@ void build_symbolic(int64_t nn, int64_t nc, int64_t nf, const int32_t *hex8,
 // ---------------------------------------------------------------------------
 // kernel launchers (defined in the .hip files)
 // ---------------------------------------------------------------------------
-struct ReduceScratch {  // deterministic grid reductions: block partials + ticket
-    double *parts;      // [kReduceBlocks * 4]
-    unsigned *ticket;   // [4]
+// Sliced ELL: slices of 64 rows (one wavefront), entries of a slice stored
+// column-major (entry k of row r at ptr[r/64] + 64 k + r%64), slice width = its
+// longest row; padding entries point at their own row with value 0.
+template <class V>
+struct Sell {
+    int32_t n = 0;
+    const int64_t *ptr = nullptr;
+    const int32_t *col = nullptr;
+    const V *val = nullptr;
 };
 
 struct PcgState {       // device-resident scalars of a Krylov solve
-    double rz, pq, alpha, beta, rr, bnorm2, tol2, pad;
-    int iter, done, max_iter, converged;
+    double tol2, bnorm2, rr, pad;
+    int iter, done, converged, pad2;
+};
+
+// Partials of the CG scalars, double-buffered by iteration parity:
+// pq at [0, G), rz[p] at [(1+p) G, (2+p) G), rr[p] at [(3+p) G, (4+p) G).
+struct PcgParts {
+    double *base;
+    int G;
+    __host__ __device__ double *pq() const { return base; }
+    __host__ __device__ double *rz(int k) const { return base + (size_t)(1 + (k & 1)) * G; }
+    __host__ __device__ double *rr(int k) const { return base + (size_t)(3 + (k & 1)) * G; }
 };
 
 // assembly
@@ -138,19 +156,44 @@ void launch_scatter(hipStream_t s, int32_t ncell_color, const int32_t *cells, in
 void launch_diag_inv(hipStream_t s, int32_t n, const int32_t *diag_pos, const double *A, double *dinv);
 
 // Krylov
+int pcg_grid(int64_t n);
 void launch_fill(hipStream_t s, int64_t n, double v, double *x);
 void launch_copy(hipStream_t s, int64_t n, const double *src, double *dst);
 void launch_jacobi(hipStream_t s, int64_t n, const double *dinv, const double *r, double *z);
-void launch_spmv(hipStream_t s, int32_t n, const int32_t *rp, const int32_t *col, const double *val,
-                 const double *x, double *y);
-void launch_residual_norm(hipStream_t s, int32_t n, const int32_t *rp, const int32_t *col,
-                          const double *val, const double *x, const double *b, double *r,
-                          ReduceScratch rs, double *out2 /* [2]: ||b-Ax||^2, ||b||^2 */);
+void launch_spmv(hipStream_t s, Sell<double> A, const double *x, double *y);
+void launch_residual_norm(hipStream_t s, Sell<double> A, const double *x, const double *b, double *r,
+                          double *parts, double *out2 /* [2]: ||b-Ax||^2, ||b||^2 */);
+// x = 0, r = b, parts rr(-1) = b.b; with dinv also z = D^-1 b, p = z and parts rz(-1)
 void launch_pcg_init(hipStream_t s, int32_t n, const double *b, const double *dinv, double *x, double *r,
-                     double *z, double *p, ReduceScratch rs, PcgState *st, double rtol, int max_iter);
-void launch_pcg_iter(hipStream_t s, int32_t n, const int32_t *rp, const int32_t *col, const double *val,
-                     const double *dinv, double *x, double *r, double *z, double *p, double *q,
-                     ReduceScratch rs, PcgState *st);
+                     double *z, PcgParts P);
+// one block: tolerance from rr(-1), state reset
+void launch_pcg_start(hipStream_t s, PcgParts P, PcgState *st, double rtol);
+// convergence test on rr(k-1); then p = z + beta p (beta = rz(k-1)/rz(k-2), 0 at k = 0)
+template <class T>
+void launch_pcg_direction(hipStream_t s, int32_t n, int k, const T *z, T *p, PcgParts P, PcgState *st, bool update);
+// q = A p, partials of p.q
+template <class V, class T>
+void launch_pcg_spmv(hipStream_t s, Sell<V> A, const T *p, T *q, PcgParts P, const PcgState *st);
+// alpha = rz(k-1) / p.q; x += alpha p; r -= alpha q; Jacobi: z = D^-1 r and partials rz(k), rr(k)
+void launch_pcg_update(hipStream_t s, int32_t n, int k, double *x, double *r, double *z, const double *p,
+                       const double *q, const double *dinv, PcgParts P, PcgState *st);
+// same without the preconditioner: partials rr(k) only
+template <class T>
+void launch_pcg_update_xr(hipStream_t s, int32_t n, int k, T *x, T *r, const T *p, const T *q, PcgParts P,
+                          PcgState *st);
+// partials rz(k) = r.z
+template <class T>
+void launch_pcg_dot_rz(hipStream_t s, int32_t n, int k, const T *r, const T *z, PcgParts P, const PcgState *st);
+// x = 0, r = b, partials rr(-1) = b.b
+template <class T>
+void launch_pcg_init_plain(hipStream_t s, int32_t n, const T *b, T *x, T *r, PcgParts P);
+// mixed precision helpers with S = diag(sc) = D^-1/2:  out[0] = ||S r||^2;
+// r32 = S r / ||S r||; x += ||S r|| S d32; As = S A S
+void launch_scaled_norm(hipStream_t s, int32_t n, const double *sc, const double *r, double *parts, double *out);
+void launch_scale_to_float(hipStream_t s, int32_t n, const double *sc, const double *r, const double *nrm2,
+                           float *r32);
+void launch_correct(hipStream_t s, int32_t n, double *x, const double *sc, const float *d32, const double *nrm2);
+void launch_diag_scaling(hipStream_t s, Sell<double> A, const int32_t *diag_pos, double *sc, double *As);
 
 // recovery, fluxes, transport
 void launch_node_pressure(hipStream_t s, int32_t nn, const int32_t *node_unk, const double *x,
@@ -172,7 +215,7 @@ void launch_cfl(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t
                 const uint8_t *dirichlet, const int32_t *node_cell_ptr, const int32_t *node_cell,
                 const int32_t *node_frac_ptr, const int32_t *node_frac, const double *F_cell,
                 const double *F_cell_frac, const double *F_frac, const double *phi_cell,
-                const double *phi_frac, const double *phi_node, double cfl, ReduceScratch rs,
+                const double *phi_frac, const double *phi_node, double cfl, double *parts,
                 double *dt_out /* [4]: dtM, dtF, dtV, dt */);
 void launch_upwind_count(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const uint8_t *fmask,
                          const int32_t *cell_frac, const int32_t *frac_cell, const uint8_t *dirichlet,

@@ -87,6 +87,7 @@ _SIGS = {
     "vag_set_options": ([vp, C.POINTER(vag_options)], C.c_int),
     "vag_solve_pressure": ([vp, C.POINTER(vag_solve_info)], C.c_int),
     "vag_transport": ([vp, C.c_int64, C.c_double, vp, vp, vp, C.c_int, C.POINTER(vag_transport_info)], C.c_int),
+    "vag_set_fluxes": ([vp, vp, vp, vp, C.c_int], C.c_int),
     "vag_get_pressure": ([vp, vp, vp, vp, C.c_int], C.c_int),
     "vag_get_fluxes": ([vp, vp, vp, vp, C.c_int], C.c_int),
     "vag_get_porous_volumes": ([vp, vp, vp, vp, C.c_int], C.c_int),
@@ -94,6 +95,7 @@ _SIGS = {
     "vag_system_size": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "vag_get_system": ([vp, vp, vp, vp, vp, C.c_int], C.c_int),
     "vag_benchmark_kernel": ([vp, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
+    "vag_amg_levels": ([vp, C.POINTER(C.c_int), vp, vp, C.c_int], C.c_int),
     "vag_footprint_bytes": ([vp], C.c_size_t),
     "vag_last_error": ([vp], C.c_char_p),
     "vag_destroy": ([vp], None),
@@ -223,6 +225,11 @@ class Handle:
                                          C.byref(info)))
         return info.as_dict()
 
+    def set_fluxes(self, flux):
+        tt = [self.torch.as_tensor(np.ascontiguousarray(flux[k]), dtype=self.torch.float64, device=self.device)
+              for k in ("F_cell", "F_cell_frac", "F_frac")]
+        self._check(load().vag_set_fluxes(self.h, *[_dptr(x) for x in tt], VAG_MEM_DEVICE))
+
     def _get3(self, fn, shapes):
         outs = [self.torch.empty(s, dtype=self.torch.float64, device=self.device) for s in shapes]
         self._check(fn(self.h, *[_dptr(o) for o in outs], VAG_MEM_DEVICE))
@@ -260,6 +267,14 @@ class Handle:
         ms = C.c_double()
         self._check(load().vag_benchmark_kernel(self.h, int(kernel), int(reps), C.byref(ms)))
         return ms.value
+
+    def amg_levels(self):
+        nl = C.c_int()
+        rows = np.zeros(32, np.int64)
+        stored = np.zeros(32, np.int64)
+        self._check(load().vag_amg_levels(self.h, C.byref(nl), rows.ctypes.data_as(C.c_void_p),
+                                          stored.ctypes.data_as(C.c_void_p), 32))
+        return [(int(rows[i]), int(stored[i])) for i in range(nl.value)]
 
     def footprint_bytes(self):
         return int(load().vag_footprint_bytes(self.h))
