@@ -50,7 +50,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precond", choices=["jacobi", "amg"], default=os.environ.get("VAG_BENCH_PRECOND", "amg"))
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "mixed_ir"], default="fp64")
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -66,7 +66,7 @@ def main():
     prob = synth.config2(n=args.n)
     opts = dict(rtol=prob.rtol, cfl=prob.cfl, max_iter=50000,
                 precond=vag.VAG_PC_AMG if args.precond == "amg" else vag.VAG_PC_JACOBI,
-                precision=vag.VAG_MIXED if args.precision == "mixed" else vag.VAG_FP64)
+                precision={"fp64": vag.VAG_FP64, "mixed": vag.VAG_MIXED, "mixed_ir": vag.VAG_MIXED_IR}[args.precision])
     t0 = time.perf_counter()
     h = vag.Handle(prob, **opts)
     torch.cuda.synchronize()

@@ -55,7 +55,12 @@ typedef enum {
 
 typedef enum { VAG_MEM_HOST = 0, VAG_MEM_DEVICE = 1 } vag_mem;
 
-typedef enum { VAG_FP64 = 0, VAG_MIXED = 1 } vag_precision;
+/* VAG_MIXED: the AMG hierarchy (every level's matrix) is stored and applied in
+ * FP32 while the Krylov vectors, the system matrix products and residuals stay
+ * FP64.  VAG_MIXED_IR: FP64 iterative refinement around an FP32 CG with the
+ * FP32 hierarchy of the diagonally scaled matrix.  Assembly, elimination,
+ * fluxes and transport are FP64 in every mode. */
+typedef enum { VAG_FP64 = 0, VAG_MIXED = 1, VAG_MIXED_IR = 2 } vag_precision;
 typedef enum { VAG_CG = 0, VAG_GMRES = 1 } vag_krylov;
 typedef enum { VAG_PC_JACOBI = 0, VAG_PC_AMG = 1 } vag_precond;
 
@@ -122,7 +127,9 @@ typedef struct {
     int amg_max_levels;
     double amg_theta;       /* strength threshold |a_ij| >= theta sqrt(a_ii a_jj) */
     int amg_sweeps;         /* pre- and post-smoothing Jacobi sweeps */
-    int reserved[8];
+    int eliminate_frac_faces;  /* 1: eliminate fracture-face groups onto the nodes
+                                  (fixed at vag_create); 0: faces stay unknowns */
+    int reserved[7];
 } vag_options;
 
 typedef struct {
@@ -160,7 +167,8 @@ typedef struct vag_handle vag_handle;
 /* Library version string. */
 const char *vag_version(void);
 
-/* Fills *opt with defaults: FP64, CG, AMG, rtol 1e-8, cfl 0.9. */
+/* Fills *opt with defaults: FP64, CG, Jacobi, rtol 1e-8, cfl 0.9, fracture-face
+ * groups eliminated. */
 vag_status vag_default_options(vag_options *opt);
 
 /*
@@ -169,6 +177,13 @@ vag_status vag_default_options(vag_options *opt);
  * pattern of the cell-eliminated system (eq eqschur), the cell colouring used
  * for conflict-free assembly and the node adjacency used by transport, and
  * copies all data to the device.  hip_stream may be NULL (null stream).
+ * With opt->eliminate_frac_faces, the fracture faces are grouped by shared
+ * cells (after the cell elimination the face-face block is block diagonal
+ * over these groups) and every group of at most 32 faces whose cells have at
+ * most 64 free nodes is eliminated exactly onto those nodes: the system then
+ * holds the free nodes and the remaining faces only, with the extra node-node
+ * couplings this creates; the eliminated face pressures are recovered after
+ * the solve.  The solution is the same as with the faces kept.
  * Errors: VAG_ERR_ARG (null/size problems, fracture face listed twice, no
  * Dirichlet node), VAG_ERR_MESH (fracture face that is not a mesh face, face
  * with more than two cells, cell with a non-positive sub-tetrahedron —
@@ -239,11 +254,13 @@ vag_status vag_get_porous_volumes(vag_handle *h, double *phi_cell, double *phi_f
 vag_status vag_get_concentration(vag_handle *h, double *c_cell, double *c_frac, double *c_node,
                                  vag_mem mem);
 
-/* Size of the assembled system of eq eqschur (after the first solve). */
+/* Size of the assembled system of eq eqschur, after the elimination of the
+ * fracture-face groups when enabled. */
 vag_status vag_system_size(vag_handle *h, int64_t *n, int64_t *nnz);
 
-/* Copies the assembled system: CSR row_ptr[n+1], col[nnz] (int64), val[nnz], b[n].
- * Unknown order: free nodes by node index, then fracture faces. */
+/* Copies the assembled system (after a solve): CSR row_ptr[n+1], col[nnz]
+ * (int64), val[nnz], b[n].  Unknown order: free nodes by node index, then the
+ * fracture faces that are not eliminated, by face index. */
 vag_status vag_get_system(vag_handle *h, int64_t *row_ptr, int64_t *col, double *val, double *b,
                           vag_mem mem);
 

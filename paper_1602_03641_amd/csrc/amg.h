@@ -11,17 +11,19 @@ namespace vag {
 // kernel launchers (amg.hip)
 void amg_launch_diag(hipStream_t s, Sell<double> A, double *diag, double *dinv);
 void amg_launch_mis(hipStream_t s, Sell<double> A, const double *diag, double theta, int rounds, uint64_t *T,
-                    uint64_t *T1, int *undecided, int32_t *flag);
-void amg_launch_scan(hipStream_t s, int32_t n, const int32_t *in, int32_t *out);
+                    uint64_t *T1, int *undecided, int32_t *flag, int32_t *hpin, uint8_t *strongq);
+void amg_launch_scan(hipStream_t s, int32_t n, const int32_t *in, int32_t *out, int32_t *tmp);
 void amg_launch_aggregate(hipStream_t s, Sell<double> A, const double *diag, double theta, const int32_t *root,
                           const int32_t *rid, int32_t *agg1, int32_t *agg, int32_t *lonely);
 void amg_launch_lonely(hipStream_t s, int32_t n, const int32_t *lonely, const int32_t *lid, const int32_t *nroot,
                        int32_t *agg);
 void amg_launch_members(hipStream_t s, int32_t n, int32_t nc, const int32_t *agg, int32_t *cnt, int32_t *ptr,
-                        int32_t *cursor, int32_t *rows);
-void amg_launch_galerkin(hipStream_t s, Sell<double> A, const int32_t *agg, const int32_t *mptr,
-                         const int32_t *mrows, int32_t nc, int mode, int32_t *rowlen, const int64_t *cptr,
-                         int32_t *ccol, double *cval, int *overflow);
+                        int32_t *cursor, int32_t *tmp, int32_t *rows, int32_t *scan_tmp);
+void amg_launch_collapse(hipStream_t s, Sell<double> A, const int32_t *agg, int32_t *Jcol, int32_t *apJ,
+                         double *apv);
+void amg_launch_galerkin(hipStream_t s, Sell<double> A, const int32_t *Jcol, const double *apv, const int32_t *mptr,
+                         const int32_t *mrows, int32_t nc, int mode, int32_t *big, int32_t *rowlen,
+                         const int64_t *cptr, int32_t *ccol, double *cval, int *overflow);
 void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t *width, int64_t *ptr);
 void amg_launch_slice_tail(hipStream_t s, int32_t n, const int64_t *ptr, int32_t *col, double *val);
 void amg_launch_dense_inverse(hipStream_t s, Sell<double> A, double *D);
@@ -30,9 +32,10 @@ void amg_launch_pre(hipStream_t s, Sell<V> A, const X *dinv, const X *b, X *x, X
 template <class X>
 void amg_launch_restrict(hipStream_t s, int32_t nc, const int32_t *mptr, const int32_t *mrows, const X *r, X *bc,
                          const PcgState *st);
+// y = x + P e, then out = y + M^-1 (b - A y)
 template <class V, class X>
 void amg_launch_post(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, const int32_t *agg,
-                     const X *e, X *out, const PcgState *st);
+                     const X *e, X *y, X *out, const PcgState *st);
 template <class X>
 void amg_launch_dense(hipStream_t s, int32_t n, const X *Ainv, const X *b, X *x, const PcgState *st);
 template <class V, class X>
@@ -86,10 +89,15 @@ class Amg {
     // z = M^-1 r, one V-cycle (FP64 or FP32); st may be null
     void apply(hipStream_t s, const double *r, double *z, const PcgState *st);
     void apply32(hipStream_t s, const float *r, float *z, const PcgState *st);
+    // FP32 matrices, FP64 vectors
+    void apply_mixed(hipStream_t s, const double *r, double *z, const PcgState *st);
 
   private:
     DBuf<uint64_t> T_, T1_;
-    DBuf<int32_t> flag_, rid_, agg1_, lonely_, lid_, cnt_, cursor_, rowlen_, width_;
+    DBuf<int32_t> flag_, rid_, agg1_, lonely_, lid_, cnt_, cursor_, rowlen_, width_, big_, mtmp_, stmp_, jcol_;
+    DBuf<double> apv_;
+    DBuf<int32_t> apj_;
+    DBuf<uint8_t> strong_;
     DBuf<int> counters_;
     int32_t *h_ = nullptr;  // pinned host scratch
     AmgOptions o_;

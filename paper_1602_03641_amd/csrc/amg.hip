@@ -18,6 +18,7 @@
 // Cycle: symmetric V-cycle (one pre- and one post-sweep), the coarsest level
 // solved by a dense inverse formed on the device by Gauss-Jordan elimination.
 #include "reduce.h"
+#include "sell.h"
 
 namespace vag {
 
@@ -66,46 +67,51 @@ __global__ __launch_bounds__(kAT) void amg_diag_kernel(Sell<double> A, double *_
     }
 }
 
+// strong[q] = 1 if entry q is a strong off-diagonal coupling
+__global__ __launch_bounds__(kAT) void strength_kernel(Sell<double> A, const double *__restrict__ diag, double theta,
+                                                       uint8_t *__restrict__ strongq) {
+    GS(i, A.n) {
+        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
+        const double di = diag[i];
+        for (int64_t q = b0 + (i & 63); q < b1; q += 64) {
+            int32_t j;
+            double s;
+            strongq[q] = strong(A.val, A.col, q, (int32_t)i, di, diag, theta, j, s) ? 1 : 0;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kAT) void mis_init_kernel(int32_t n, uint64_t *__restrict__ T) {
     GS(i, n) T[i] = (1ull << 62) | ((uint64_t)(mix32((uint32_t)i) & 0x3fffffffu) << 32) | (uint64_t)(uint32_t)i;
 }
 
 // Tout[i] = max of T over {i} and its strong neighbours
-__global__ __launch_bounds__(kAT) void mis_max_kernel(Sell<double> A, const double *__restrict__ diag,
-                                                      double theta, const uint64_t *__restrict__ Tin,
-                                                      uint64_t *__restrict__ Tout, const int *__restrict__ active) {
+__global__ __launch_bounds__(kAT) void mis_max_kernel(Sell<double> A, const uint8_t *__restrict__ strongq,
+                                                      const uint64_t *__restrict__ Tin, uint64_t *__restrict__ Tout,
+                                                      const int *__restrict__ active) {
     if (active && *active == 0) return;
     GS(i, A.n) {
         const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
-        const double di = diag[i];
         uint64_t m = Tin[i];
-        for (int64_t q = b0 + (i & 63); q < b1; q += 64) {
-            int32_t j;
-            double s;
-            if (strong(A.val, A.col, q, (int32_t)i, di, diag, theta, j, s)) m = max(m, Tin[j]);
-        }
+        for (int64_t q = b0 + (i & 63); q < b1; q += 64)
+            if (strongq[q]) m = max(m, Tin[A.col[q]]);
         Tout[i] = m;
     }
 }
 
 // second hop, then the decision of undecided nodes
-__global__ __launch_bounds__(kAT) void mis_select_kernel(Sell<double> A, const double *__restrict__ diag,
-                                                         double theta, const uint64_t *__restrict__ T1,
-                                                         uint64_t *__restrict__ T, int *__restrict__ undecided,
-                                                         const int *__restrict__ active) {
+__global__ __launch_bounds__(kAT) void mis_select_kernel(Sell<double> A, const uint8_t *__restrict__ strongq,
+                                                         const uint64_t *__restrict__ T1, uint64_t *__restrict__ T,
+                                                         int *__restrict__ undecided, const int *__restrict__ active) {
     if (active && *active == 0) return;
     int cnt = 0;
     GS(i, A.n) {
         const uint64_t own = T[i];
         if (rank_of(own) != 1) continue;
         const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
-        const double di = diag[i];
         uint64_t m = T1[i];
-        for (int64_t q = b0 + (i & 63); q < b1; q += 64) {
-            int32_t j;
-            double s;
-            if (strong(A.val, A.col, q, (int32_t)i, di, diag, theta, j, s)) m = max(m, T1[j]);
-        }
+        for (int64_t q = b0 + (i & 63); q < b1; q += 64)
+            if (strongq[q]) m = max(m, T1[A.col[q]]);
         if (m == own)
             T[i] = (own & ~(3ull << 62)) | (2ull << 62);  // root
         else if (rank_of(m) == 2)
@@ -192,19 +198,20 @@ __global__ __launch_bounds__(kAT) void members_fill_kernel(int32_t n, const int3
         rows[ptr[a] + atomicAdd(&cursor[a], 1)] = (int32_t)i;
     }
 }
-// insertion sort of each aggregate's rows (atomic fill order is arbitrary)
-__global__ __launch_bounds__(kAT) void members_sort_kernel(int32_t nc, const int32_t *__restrict__ ptr,
-                                                           int32_t *__restrict__ rows) {
-    GS(I, nc) {
+// members in ascending row order: the rank of each member is the number of
+// smaller members (one wavefront per aggregate; atomic fill order is arbitrary)
+__global__ __launch_bounds__(kAT) void members_rank_kernel(int32_t nc, const int32_t *__restrict__ ptr,
+                                                           const int32_t *__restrict__ tmp, int32_t *__restrict__ rows) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t I = w0; I < nc; I += nw) {
         const int32_t b = ptr[I], e = ptr[I + 1];
-        for (int32_t k = b + 1; k < e; ++k) {
-            const int32_t v = rows[k];
-            int32_t m = k - 1;
-            while (m >= b && rows[m] > v) {
-                rows[m + 1] = rows[m];
-                --m;
-            }
-            rows[m + 1] = v;
+        for (int32_t t = b + lane; t < e; t += 64) {
+            const int32_t v = tmp[t];
+            int32_t rank = 0;
+            for (int32_t u = b; u < e; ++u) rank += tmp[u] < v;
+            rows[b + rank] = v;
         }
     }
 }
@@ -238,21 +245,118 @@ __global__ __launch_bounds__(1024) void scan_int_kernel(int32_t n, const int32_t
     }
 }
 
+
+// multi-block exclusive scan of n ints (out[n] = total): block sums, one-block
+// scan of the block sums, then per-block scan with offsets
+constexpr int kScanItems = 4;
+__global__ __launch_bounds__(256) void scan_sums_kernel(int32_t n, const int32_t *__restrict__ in,
+                                                        int32_t *__restrict__ sums) {
+    __shared__ int32_t w[4];
+    const int64_t base = (int64_t)blockIdx.x * 256 * kScanItems;
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + (int64_t)k * 256 + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) sums[blockIdx.x] = w[0] + w[1] + w[2] + w[3];
+}
+__global__ __launch_bounds__(256) void scan_apply_kernel(int32_t n, const int32_t *__restrict__ in,
+                                                         const int32_t *__restrict__ offs, int32_t *__restrict__ out) {
+    __shared__ int32_t wsum[4];
+    const int64_t base = (int64_t)blockIdx.x * 256 * kScanItems + (int64_t)threadIdx.x * kScanItems;
+    int32_t v[kScanItems];
+    int32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        t += v[k];
+    }
+    // inclusive scan of t over the block
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t incl = t;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int32_t off = offs[blockIdx.x];
+    for (int k = 0; k < wv; ++k) off += wsum[k];
+    int32_t run = off + incl - t;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (base + kScanItems >= n && base < n) out[n] = run;  // the thread holding the last element
+}
+
 // ---------------------------------------------------------------------------
 // Galerkin coarse operator, one wavefront per coarse row
 // ---------------------------------------------------------------------------
-// mode 0: rowlen[I] = number of coarse columns; mode 1: write them (SELL)
-__global__ __launch_bounds__(64) void galerkin_kernel(Sell<double> A, const int32_t *__restrict__ agg,
+// Jcol[q] = aggregate of the column of entry q (same sliced-ELL layout as A)
+__global__ __launch_bounds__(kAT) void agg_col_kernel(Sell<double> A, const int32_t *__restrict__ agg,
+                                                      int32_t *__restrict__ Jcol) {
+    GS(i, A.n) {
+        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
+        for (int64_t q = b0 + (i & 63); q < b1; q += 64) Jcol[q] = agg[A.col[q]];
+    }
+}
+// Row i of A P (P = aggregate indicator): the distinct aggregates of the row's
+// columns, in increasing order, each with the sum of its entries (in column
+// order), written to the row's first slots of (apJ, apv); the remaining slots
+// get value 0, which later passes skip like padding.  The lanes of a wave scan
+// slot k together, so the passes are coalesced.
+__global__ __launch_bounds__(kAT) void ap_collapse_kernel(Sell<double> A, const int32_t *__restrict__ Jcol,
+                                                          int32_t *__restrict__ apJ, double *__restrict__ apv) {
+    GS(i, A.n) {
+        const int64_t b0 = A.ptr[i >> 6] + (i & 63), b1 = A.ptr[(i >> 6) + 1];
+        int64_t out = b0;
+        int32_t last = -1;
+        for (;;) {
+            int32_t jm = INT32_MAX;
+            for (int64_t q = b0; q < b1; q += 64) {
+                const int32_t J = Jcol[q];
+                if (J > last && J < jm && A.val[q] != 0.0) jm = J;
+            }
+            if (jm == INT32_MAX) break;
+            double sum = 0.0;
+            for (int64_t q = b0; q < b1; q += 64)
+                if (Jcol[q] == jm) sum += A.val[q];
+            apJ[out] = jm;
+            apv[out] = sum;
+            out += 64;
+            last = jm;
+        }
+        for (; out < b1; out += 64) {
+            apJ[out] = (int32_t)i;
+            apv[out] = 0.0;
+        }
+    }
+}
+
+// mode 0: rowlen[I] = number of coarse columns; mode 1: write them (SELL).
+// Candidates are the nonzero collapsed entries of the aggregate's rows.
+// Rows with more than CAP candidates set big[I] and are redone with the larger CAP.
+template <int CAP>
+__global__ __launch_bounds__(64) void galerkin_kernel(Sell<double> A, const int32_t *__restrict__ Jcol,
+                                                      const double *__restrict__ apv,
                                                       const int32_t *__restrict__ mptr, const int32_t *__restrict__ mrows,
-                                                      int32_t nc, int mode, int32_t *__restrict__ rowlen,
-                                                      const int64_t *__restrict__ cptr, int32_t *__restrict__ ccol,
-                                                      double *__restrict__ cval, int *__restrict__ overflow) {
-    __shared__ uint64_t key[kCap];
+                                                      int32_t nc, int mode, int32_t *__restrict__ big,
+                                                      int32_t *__restrict__ rowlen, const int64_t *__restrict__ cptr,
+                                                      int32_t *__restrict__ ccol, double *__restrict__ cval,
+                                                      int *__restrict__ overflow) {
+    __shared__ uint64_t key[CAP];
     const int32_t I = blockIdx.x;
     const int lane = threadIdx.x;
     if (I >= nc) return;
-    // gather (coarse column, fine position) candidates of the aggregate's rows;
-    // slice padding (value exactly 0) is skipped, lanes compacted by ballot
+    if (CAP > 2048 && !big[I]) return;
     int m = 0;
     bool over = false;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -266,15 +370,15 @@ __global__ __launch_bounds__(64) void galerkin_kernel(Sell<double> A, const int3
             uint64_t kv = 0;
             if (k < w) {
                 const int64_t q = b0 + (int64_t)k * 64 + (r & 63);
-                if (A.val[q] != 0.0) {
+                if (apv[q] != 0.0) {
                     keep = true;
-                    kv = ((uint64_t)(uint32_t)agg[A.col[q]] << 32) | (uint64_t)(uint32_t)q;
+                    kv = ((uint64_t)(uint32_t)Jcol[q] << 32) | (uint64_t)(uint32_t)q;
                 }
             }
             const uint64_t mask = __ballot(keep);
             const int off = __popcll(mask & below);
             const int cnt = __popcll(mask);
-            if (m + cnt > kCap) {
+            if (m + cnt > CAP) {
                 over = true;
                 break;
             }
@@ -284,16 +388,17 @@ __global__ __launch_bounds__(64) void galerkin_kernel(Sell<double> A, const int3
     }
     if (over) {
         if (lane == 0) {
-            atomicOr(overflow, 1);
-            if (mode == 0) rowlen[I] = 1;
+            if (CAP <= 2048) big[I] = 1;
+            else atomicOr(overflow, 1);
+            if (mode == 0 && CAP > 2048) rowlen[I] = 1;
         }
         return;
     }
+    if (CAP <= 2048 && mode == 0 && lane == 0) big[I] = 0;
     int mp = 1;
     while (mp < m) mp <<= 1;
     for (int k = m + lane; k < mp; k += 64) key[k] = ~0ull;
     __syncthreads();
-    // bitonic sort of key[0, mp)
     for (int k = 2; k <= mp; k <<= 1)
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int i = lane; i < mp; i += 64) {
@@ -309,12 +414,10 @@ __global__ __launch_bounds__(64) void galerkin_kernel(Sell<double> A, const int3
             }
             __syncthreads();
         }
-    // segment heads: first key of each coarse column
     const int C = mp / 64 > 0 ? mp / 64 : 1;
     const int lo = min(m, lane * C), hi = min(m, lo + C);
     int nh = 0;
     for (int t = lo; t < hi; ++t) nh += (t == 0 || (key[t] >> 32) != (key[t - 1] >> 32));
-    // exclusive wave scan of head counts
     int incl = nh;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -332,12 +435,11 @@ __global__ __launch_bounds__(64) void galerkin_kernel(Sell<double> A, const int3
         if (!(t == 0 || (key[t] >> 32) != (key[t - 1] >> 32))) continue;
         const uint32_t J = (uint32_t)(key[t] >> 32);
         double s = 0.0;
-        for (int u = t; u < m && (uint32_t)(key[u] >> 32) == J; ++u) s += A.val[(uint32_t)key[u]];
+        for (int u = t; u < m && (uint32_t)(key[u] >> 32) == J; ++u) s += apv[(uint32_t)key[u]];
         ccol[base + (int64_t)rank * 64] = (int32_t)J;
         cval[base + (int64_t)rank * 64] = s;
         ++rank;
     }
-    // padding of this row up to the slice width
     const int w = (int)((cptr[(I >> 6) + 1] - cptr[I >> 6]) >> 6);
     for (int k = total + lane; k < w; k += 64) {
         ccol[base + (int64_t)k * 64] = I;
@@ -409,49 +511,54 @@ __global__ __launch_bounds__(1024) void gauss_jordan_kernel(int32_t n, double *_
 // ---------------------------------------------------------------------------
 // V-cycle kernels
 // ---------------------------------------------------------------------------
-// x = M^-1 b (first sweep from zero) and r = b - A x, with x_j formed on the fly
-template <class V, class X>
-__global__ __launch_bounds__(kAT) void vc_pre_kernel(Sell<V> A, const X *__restrict__ dinv, const X *__restrict__ b,
-                                                     X *__restrict__ x, X *__restrict__ r, const PcgState *st) {
+// x = M^-1 b (first sweep from zero)
+template <class X>
+__global__ __launch_bounds__(kAT) void vc_scale_kernel(int32_t n, const X *__restrict__ dinv, const X *__restrict__ b,
+                                                       X *__restrict__ x, const PcgState *st) {
     if (st && st->done) return;
-    GS(i, A.n) {
-        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
-        X s = 0;
-        for (int64_t q = b0 + (i & 63); q < b1; q += 64) {
-            const int32_t j = A.col[q];
-            s += (X)A.val[q] * (dinv[j] * b[j]);
-        }
-        x[i] = dinv[i] * b[i];
-        r[i] = b[i] - s;
-    }
+    GS(i, n) x[i] = dinv[i] * b[i];
 }
-// b_c[I] = sum of r over aggregate I (rows ascending)
+// r = b - A x
+template <class V, class X>
+__global__ __launch_bounds__(kAT) void vc_resid_kernel(Sell<V> A, const X *__restrict__ b, const X *__restrict__ x,
+                                                       X *__restrict__ r, const PcgState *st) {
+    if (st && st->done) return;
+    GS(i, A.n) r[i] = b[i] - sell_row_apply<V, X>(A, (int32_t)i, [&](int32_t j) { return x[j]; });
+}
+// b_c[I] = sum of r over aggregate I: one wavefront per coarse row, members
+// strided over the lanes and combined by a fixed shuffle tree
 template <class X>
 __global__ __launch_bounds__(kAT) void vc_restrict_kernel(int32_t nc, const int32_t *__restrict__ mptr,
                                                           const int32_t *__restrict__ mrows, const X *__restrict__ r,
                                                           X *__restrict__ bc, const PcgState *st) {
     if (st && st->done) return;
-    GS(I, nc) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t I = w0; I < nc; I += nw) {
         X s = 0;
-        for (int32_t t = mptr[I]; t < mptr[I + 1]; ++t) s += r[mrows[t]];
-        bc[I] = s;
+        for (int32_t t = mptr[I] + lane; t < mptr[I + 1]; t += 64) s += r[mrows[t]];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (lane == 0) bc[I] = s;
     }
 }
-// y = x + P e (on the fly), out = y + M^-1 (b - A y)
+// y = x + P e (injection from the aggregate)
+template <class X>
+__global__ __launch_bounds__(kAT) void vc_prolong_kernel(int32_t n, const X *__restrict__ x,
+                                                         const int32_t *__restrict__ agg, const X *__restrict__ e,
+                                                         X *__restrict__ y, const PcgState *st) {
+    if (st && st->done) return;
+    GS(i, n) y[i] = x[i] + e[agg[i]];
+}
+// out = y + M^-1 (b - A y)
 template <class V, class X>
-__global__ __launch_bounds__(kAT) void vc_post_kernel(Sell<V> A, const X *__restrict__ dinv, const X *__restrict__ b,
-                                                      const X *__restrict__ x, const int32_t *__restrict__ agg,
-                                                      const X *__restrict__ e, X *__restrict__ out, const PcgState *st) {
+__global__ __launch_bounds__(kAT) void vc_sweep_kernel(Sell<V> A, const X *__restrict__ dinv, const X *__restrict__ b,
+                                                       const X *__restrict__ y, X *__restrict__ out, const PcgState *st) {
     if (st && st->done) return;
     GS(i, A.n) {
-        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
-        X s = 0;
-        for (int64_t q = b0 + (i & 63); q < b1; q += 64) {
-            const int32_t j = A.col[q];
-            s += (X)A.val[q] * (x[j] + e[agg[j]]);
-        }
-        const X yi = x[i] + e[agg[i]];
-        out[i] = yi + dinv[i] * (b[i] - s);
+        const X s = sell_row_apply<V, X>(A, (int32_t)i, [&](int32_t j) { return y[j]; });
+        out[i] = y[i] + dinv[i] * (b[i] - s);
     }
 }
 // dense coarse solve x = Ainv b
@@ -465,19 +572,6 @@ __global__ __launch_bounds__(kAT) void vc_dense_kernel(int32_t n, const X *__res
         x[i] = s;
     }
 }
-// plain l1-Jacobi sweep out = x + M^-1 (b - A x) (coarsest level when too big for the dense inverse)
-template <class V, class X>
-__global__ __launch_bounds__(kAT) void vc_sweep_kernel(Sell<V> A, const X *__restrict__ dinv, const X *__restrict__ b,
-                                                       const X *__restrict__ x, X *__restrict__ out, const PcgState *st) {
-    if (st && st->done) return;
-    GS(i, A.n) {
-        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
-        X s = 0;
-        for (int64_t q = b0 + (i & 63); q < b1; q += 64) s += (X)A.val[q] * x[A.col[q]];
-        out[i] = x[i] + dinv[i] * (b[i] - s);
-    }
-}
-
 // conversions for the single-precision hierarchy
 __global__ __launch_bounds__(kAT) void to_float_kernel(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
     GS(i, n) b[i] = (float)a[i];
@@ -499,17 +593,32 @@ void amg_launch_diag(hipStream_t s, Sell<double> A, double *diag, double *dinv) 
     if (A.n > 0) ALAUNCH(amg_diag_kernel, gridv(A.n), kAT, A, diag, dinv);
 }
 void amg_launch_mis(hipStream_t s, Sell<double> A, const double *diag, double theta, int rounds, uint64_t *T,
-                    uint64_t *T1, int *undecided /* [rounds] zeroed */, int32_t *flag) {
+                    uint64_t *T1, int *undecided /* [rounds] zeroed */, int32_t *flag, int32_t *hpin,
+                    uint8_t *strongq) {
+    ALAUNCH(strength_kernel, gridv(A.n), kAT, A, diag, theta, strongq);
     ALAUNCH(mis_init_kernel, gridv(A.n), kAT, A.n, T);
     for (int r = 0; r < rounds; ++r) {
         const int *active = r ? undecided + r - 1 : nullptr;
-        ALAUNCH(mis_max_kernel, gridv(A.n), kAT, A, diag, theta, T, T1, active);
-        ALAUNCH(mis_select_kernel, gridv(A.n), kAT, A, diag, theta, T1, T, undecided + r, active);
+        ALAUNCH(mis_max_kernel, gridv(A.n), kAT, A, strongq, T, T1, active);
+        ALAUNCH(mis_select_kernel, gridv(A.n), kAT, A, strongq, T1, T, undecided + r, active);
+        if ((r & 3) == 3 && r + 1 < rounds) {  // stop queueing rounds once nothing is undecided
+            VAG_HIP(hipMemcpyAsync(hpin, undecided + r, sizeof(int), hipMemcpyDeviceToHost, s));
+            VAG_HIP(hipStreamSynchronize(s));
+            if (*hpin == 0) break;
+        }
     }
     ALAUNCH(mis_flag_kernel, gridv(A.n), kAT, A.n, T, flag);
 }
-void amg_launch_scan(hipStream_t s, int32_t n, const int32_t *in, int32_t *out) {
-    ALAUNCH(scan_int_kernel, 1, 1024, n, in, out);
+void amg_launch_scan(hipStream_t s, int32_t n, const int32_t *in, int32_t *out, int32_t *tmp) {
+    // tmp: at least 2 * (n / 1024 + 2) ints
+    const int32_t nb = (n + 256 * kScanItems - 1) / (256 * kScanItems);
+    if (nb <= 1) {
+        ALAUNCH(scan_int_kernel, 1, 1024, n, in, out);
+        return;
+    }
+    ALAUNCH(scan_sums_kernel, nb, 256, n, in, tmp);
+    ALAUNCH(scan_int_kernel, 1, 1024, nb, tmp, tmp + nb + 1);
+    ALAUNCH(scan_apply_kernel, nb, 256, n, in, tmp + nb + 1, out);
 }
 void amg_launch_aggregate(hipStream_t s, Sell<double> A, const double *diag, double theta, const int32_t *root,
                           const int32_t *rid, int32_t *agg1, int32_t *agg, int32_t *lonely) {
@@ -521,17 +630,26 @@ void amg_launch_lonely(hipStream_t s, int32_t n, const int32_t *lonely, const in
     ALAUNCH(agg_lonely_kernel, gridv(n), kAT, n, lonely, lid, nroot, agg);
 }
 void amg_launch_members(hipStream_t s, int32_t n, int32_t nc, const int32_t *agg, int32_t *cnt, int32_t *ptr,
-                        int32_t *cursor, int32_t *rows) {
+                        int32_t *cursor, int32_t *tmp, int32_t *rows, int32_t *scan_tmp) {
     // cnt and cursor zeroed by the caller
     ALAUNCH(count_kernel, gridv(n), kAT, n, agg, cnt);
-    ALAUNCH(scan_int_kernel, 1, 1024, nc, cnt, ptr);
-    ALAUNCH(members_fill_kernel, gridv(n), kAT, n, agg, ptr, cursor, rows);
-    ALAUNCH(members_sort_kernel, gridv(nc), kAT, nc, ptr, rows);
+    amg_launch_scan(s, nc, cnt, ptr, scan_tmp);
+    ALAUNCH(members_fill_kernel, gridv(n), kAT, n, agg, ptr, cursor, tmp);
+    ALAUNCH(members_rank_kernel, reduce_grid((int64_t)nc * 64, kAT), kAT, nc, ptr, tmp, rows);
 }
-void amg_launch_galerkin(hipStream_t s, Sell<double> A, const int32_t *agg, const int32_t *mptr,
-                         const int32_t *mrows, int32_t nc, int mode, int32_t *rowlen, const int64_t *cptr,
-                         int32_t *ccol, double *cval, int *overflow) {
-    if (nc > 0) ALAUNCH(galerkin_kernel, nc, 64, A, agg, mptr, mrows, nc, mode, rowlen, cptr, ccol, cval, overflow);
+void amg_launch_collapse(hipStream_t s, Sell<double> A, const int32_t *agg, int32_t *Jcol, int32_t *apJ,
+                         double *apv) {
+    ALAUNCH(agg_col_kernel, gridv(A.n), kAT, A, agg, Jcol);
+    ALAUNCH(ap_collapse_kernel, gridv(A.n), kAT, A, Jcol, apJ, apv);
+}
+void amg_launch_galerkin(hipStream_t s, Sell<double> A, const int32_t *Jcol, const double *apv, const int32_t *mptr,
+                         const int32_t *mrows, int32_t nc, int mode, int32_t *big, int32_t *rowlen,
+                         const int64_t *cptr, int32_t *ccol, double *cval, int *overflow) {
+    if (nc <= 0) return;
+    ALAUNCH(galerkin_kernel<2048>, nc, 64, A, Jcol, apv, mptr, mrows, nc, mode, big, rowlen, cptr, ccol, cval,
+            overflow);
+    ALAUNCH(galerkin_kernel<8192>, nc, 64, A, Jcol, apv, mptr, mrows, nc, mode, big, rowlen, cptr, ccol, cval,
+            overflow);
 }
 void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t *width, int64_t *ptr) {
     const int32_t ns = (n + 63) / 64;
@@ -548,17 +666,19 @@ void amg_launch_dense_inverse(hipStream_t s, Sell<double> A, double *D) {
 }
 template <class V, class X>
 void amg_launch_pre(hipStream_t s, Sell<V> A, const X *dinv, const X *b, X *x, X *r, const PcgState *st) {
-    ALAUNCH((vc_pre_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, x, r, st);
+    ALAUNCH(vc_scale_kernel<X>, gridv(A.n), kAT, A.n, dinv, b, x, st);
+    ALAUNCH((vc_resid_kernel<V, X>), gridv(A.n), kAT, A, b, x, r, st);
 }
 template <class X>
 void amg_launch_restrict(hipStream_t s, int32_t nc, const int32_t *mptr, const int32_t *mrows, const X *r, X *bc,
                          const PcgState *st) {
-    ALAUNCH(vc_restrict_kernel<X>, gridv(nc), kAT, nc, mptr, mrows, r, bc, st);
+    ALAUNCH(vc_restrict_kernel<X>, reduce_grid((int64_t)nc * 64, kAT), kAT, nc, mptr, mrows, r, bc, st);
 }
 template <class V, class X>
 void amg_launch_post(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, const int32_t *agg, const X *e,
-                     X *out, const PcgState *st) {
-    ALAUNCH((vc_post_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, x, agg, e, out, st);
+                     X *y, X *out, const PcgState *st) {
+    ALAUNCH(vc_prolong_kernel<X>, gridv(A.n), kAT, A.n, x, agg, e, y, st);
+    ALAUNCH((vc_sweep_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, y, out, st);
 }
 template <class X>
 void amg_launch_dense(hipStream_t s, int32_t n, const X *Ainv, const X *b, X *x, const PcgState *st) {
@@ -577,6 +697,13 @@ void launch_to_double(hipStream_t s, int64_t n, const float *a, double *b) {
 
 template void amg_launch_pre<double, double>(hipStream_t, Sell<double>, const double *, const double *, double *,
                                              double *, const PcgState *);
+template void amg_launch_pre<float, double>(hipStream_t, Sell<float>, const double *, const double *, double *,
+                                            double *, const PcgState *);
+template void amg_launch_post<float, double>(hipStream_t, Sell<float>, const double *, const double *,
+                                             const double *, const int32_t *, const double *, double *, double *,
+                                             const PcgState *);
+template void amg_launch_sweep<float, double>(hipStream_t, Sell<float>, const double *, const double *,
+                                              const double *, double *, const PcgState *);
 template void amg_launch_pre<float, float>(hipStream_t, Sell<float>, const float *, const float *, float *, float *,
                                            const PcgState *);
 template void amg_launch_restrict<double>(hipStream_t, int32_t, const int32_t *, const int32_t *, const double *,
@@ -584,10 +711,10 @@ template void amg_launch_restrict<double>(hipStream_t, int32_t, const int32_t *,
 template void amg_launch_restrict<float>(hipStream_t, int32_t, const int32_t *, const int32_t *, const float *,
                                          float *, const PcgState *);
 template void amg_launch_post<double, double>(hipStream_t, Sell<double>, const double *, const double *,
-                                              const double *, const int32_t *, const double *, double *,
+                                              const double *, const int32_t *, const double *, double *, double *,
                                               const PcgState *);
 template void amg_launch_post<float, float>(hipStream_t, Sell<float>, const float *, const float *, const float *,
-                                            const int32_t *, const float *, float *, const PcgState *);
+                                            const int32_t *, const float *, float *, float *, const PcgState *);
 template void amg_launch_dense<double>(hipStream_t, int32_t, const double *, const double *, double *,
                                        const PcgState *);
 template void amg_launch_dense<float>(hipStream_t, int32_t, const float *, const float *, float *, const PcgState *);

@@ -17,6 +17,11 @@ void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, co
     ensure(T1_, n0, tr);
     for (auto *b : {&flag_, &rid_, &agg1_, &lonely_, &lid_, &cnt_, &cursor_, &rowlen_}) ensure(*b, (size_t)n0 + 1, tr);
     ensure(width_, (size_t)n0 / 64 + 2, tr);
+    ensure(big_, (size_t)n0 + 1, tr);
+    ensure(mtmp_, (size_t)n0 + 1, tr);
+    ensure(stmp_, 2 * ((size_t)n0 / 1024 + 4), tr);
+    ensure(jcol_, (size_t)stored0, tr);
+    ensure(apv_, (size_t)stored0, tr);
     ensure(counters_, 64, tr);
     if (L.empty()) L.emplace_back(new AmgLevel());
     L[0]->n = n0;
@@ -35,11 +40,13 @@ void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, co
         if (n <= o.coarse_size || l + 1 >= o.max_levels) break;
         // aggregation
         VAG_HIP(hipMemsetAsync(counters_.p, 0, 64 * sizeof(int), s));
-        amg_launch_mis(s, lv.A, lv.diag.p, o.theta, std::min(o.mis_rounds, 48), T_.p, T1_.p, counters_.p, flag_.p);
-        amg_launch_scan(s, n, flag_.p, rid_.p);
+        ensure(strong_, (size_t)lv.stored, tr);
+        amg_launch_mis(s, lv.A, lv.diag.p, o.theta, std::min(o.mis_rounds, 48), T_.p, T1_.p, counters_.p, flag_.p,
+                       h_ + 8, strong_.p);
+        amg_launch_scan(s, n, flag_.p, rid_.p, stmp_.p);
         ensure(lv.agg, n, tr);
         amg_launch_aggregate(s, lv.A, lv.diag.p, o.theta, flag_.p, rid_.p, agg1_.p, lv.agg.p, lonely_.p);
-        amg_launch_scan(s, n, lonely_.p, lid_.p);
+        amg_launch_scan(s, n, lonely_.p, lid_.p, stmp_.p);
         amg_launch_lonely(s, n, lonely_.p, lid_.p, rid_.p + n, lv.agg.p);
         VAG_HIP(hipMemcpyAsync(h_, rid_.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipMemcpyAsync(h_ + 1, lid_.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -51,13 +58,17 @@ void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, co
         ensure(lv.mrows, n, tr);
         VAG_HIP(hipMemsetAsync(cnt_.p, 0, ((size_t)nc + 1) * sizeof(int32_t), s));
         VAG_HIP(hipMemsetAsync(cursor_.p, 0, ((size_t)nc + 1) * sizeof(int32_t), s));
-        amg_launch_members(s, n, nc, lv.agg.p, cnt_.p, lv.mptr.p, cursor_.p, lv.mrows.p);
+        amg_launch_members(s, n, nc, lv.agg.p, cnt_.p, lv.mptr.p, cursor_.p, mtmp_.p, lv.mrows.p, stmp_.p);
+        ensure(jcol_, (size_t)lv.stored, tr);
+        ensure(apv_, (size_t)lv.stored, tr);
+        ensure(apj_, (size_t)lv.stored, tr);
+        amg_launch_collapse(s, lv.A, lv.agg.p, jcol_.p, apj_.p, apv_.p);
         if ((int)L.size() <= l + 1) L.emplace_back(new AmgLevel());
         AmgLevel &cv = *L[l + 1];
         const int32_t ns = (nc + 63) / 64;
         ensure(cv.ptr, (size_t)ns + 1, tr);
-        amg_launch_galerkin(s, lv.A, lv.agg.p, lv.mptr.p, lv.mrows.p, nc, 0, rowlen_.p, nullptr, nullptr, nullptr,
-                            counters_.p + 63);
+        amg_launch_galerkin(s, lv.A, apj_.p, apv_.p, lv.mptr.p, lv.mrows.p, nc, 0, big_.p, rowlen_.p, nullptr,
+                            nullptr, nullptr, counters_.p + 63);
         amg_launch_slices(s, nc, rowlen_.p, width_.p, cv.ptr.p);
         int64_t hv[2];
         VAG_HIP(hipMemcpyAsync(&hv[0], cv.ptr.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -67,8 +78,8 @@ void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, co
         const int64_t stored = hv[0];
         ensure(cv.col, (size_t)stored, tr);
         ensure(cv.val, (size_t)stored, tr);
-        amg_launch_galerkin(s, lv.A, lv.agg.p, lv.mptr.p, lv.mrows.p, nc, 1, rowlen_.p, cv.ptr.p, cv.col.p, cv.val.p,
-                            counters_.p + 63);
+        amg_launch_galerkin(s, lv.A, apj_.p, apv_.p, lv.mptr.p, lv.mrows.p, nc, 1, big_.p, rowlen_.p, cv.ptr.p,
+                            cv.col.p, cv.val.p, counters_.p + 63);
         amg_launch_slice_tail(s, nc, cv.ptr.p, cv.col.p, cv.val.p);
         cv.n = nc;
         cv.stored = stored;
@@ -117,13 +128,12 @@ void Amg::cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bo
     Sell<V> A;
     const X *dinv;
     X *xa, *r;
+    if constexpr (sizeof(V) == 4) A = lv.A32; else A = lv.A;
     if constexpr (sizeof(X) == 4) {
-        A = lv.A32;
         dinv = lv.dinv32.p;
         xa = lv.xa32.p;
         r = lv.r32.p;
     } else {
-        A = lv.A;
         dinv = lv.dinv.p;
         xa = lv.xa.p;
         r = lv.r.p;
@@ -157,7 +167,7 @@ void Amg::cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bo
     amg_launch_pre<V, X>(s, A, dinv, b, xa, r, st);
     amg_launch_restrict<X>(s, cv.n, lv.mptr.p, lv.mrows.p, r, bc, st);
     cycle<V, X>(s, l + 1, bc, ec, st, fp32);
-    amg_launch_post<V, X>(s, A, dinv, b, xa, lv.agg.p, ec, out, st);
+    amg_launch_post<V, X>(s, A, dinv, b, xa, lv.agg.p, ec, r, out, st);  // r reused for y
 }
 
 void Amg::apply(hipStream_t s, const double *r, double *z, const PcgState *st) {
@@ -166,6 +176,10 @@ void Amg::apply(hipStream_t s, const double *r, double *z, const PcgState *st) {
 
 void Amg::apply32(hipStream_t s, const float *r, float *z, const PcgState *st) {
     cycle<float, float>(s, 0, r, z, st, true);
+}
+
+void Amg::apply_mixed(hipStream_t s, const double *r, double *z, const PcgState *st) {
+    cycle<float, double>(s, 0, r, z, st, true);
 }
 
 }  // namespace vag

@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void vag_frac_kernel(int32_t nf, const double 
     area[f] = A;
 }
 
-// Adds v at CSR position given by a slot code; a Dirichlet column goes to b.
+// Adds v at the position given by a slot code; a Dirichlet column goes to b.
 __device__ inline void put(int32_t slot, double v, int32_t row, double pb, double *__restrict__ A,
                            double *__restrict__ b) {
     if (slot >= 0)
@@ -207,15 +207,17 @@ __device__ inline void put(int32_t slot, double v, int32_t row, double pb, doubl
         b[row] -= v * pb;
 }
 
+// Scatters M_K = a - r r^T / A_KK of the cells of one colour.  Rows of an
+// eliminated fracture face go to the dense group blocks Gb instead of A.
 __global__ __launch_bounds__(128) void vag_scatter_kernel(
-    int32_t ncell, const int32_t *__restrict__ cells, int32_t nc, int32_t nfree,
+    int32_t ncell, const int32_t *__restrict__ cells, int32_t nc, int32_t nsys,
     const int32_t *__restrict__ hex8, const uint8_t *__restrict__ fmask,
     const int32_t *__restrict__ cell_frac, const int32_t *__restrict__ frac_cell,
     const int32_t *__restrict__ frac_slot, const int32_t *__restrict__ frac_nodes,
-    const int32_t *__restrict__ node_unk, const double *__restrict__ p_bar, const double *__restrict__ aK,
-    const double *__restrict__ rK, const double *__restrict__ AKK, const double *__restrict__ fside,
-    const double *__restrict__ A5, const int64_t *__restrict__ slot_ptr, const int32_t *__restrict__ slots,
-    double *__restrict__ A, double *__restrict__ b) {
+    const int32_t *__restrict__ node_unk, const int32_t *__restrict__ frac_unk, const double *__restrict__ p_bar,
+    const double *__restrict__ aK, const double *__restrict__ rK, const double *__restrict__ AKK,
+    const double *__restrict__ fside, const double *__restrict__ A5, const int64_t *__restrict__ slot_ptr,
+    const int32_t *__restrict__ slots, double *__restrict__ A, double *__restrict__ Gb, double *__restrict__ b) {
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ncell) return;
     const int32_t K = cells[t];
@@ -262,7 +264,8 @@ __global__ __launch_bounds__(128) void vag_scatter_kernel(
     for (int f = 0; f < 6; ++f) {
         if (!((mask >> f) & 1u)) continue;
         const int j = 8 + __popc(mask & ((1u << f) - 1u));
-        const int32_t frow = nfree + sig[f];
+        const int32_t frow = frac_unk[sig[f]];
+        double *Af = frow >= nsys ? Gb : A;  // row of sigma
         const double *o = fside + (2 * (int64_t)sig[f] + sd[f]) * 6;
         double af[8];
 #pragma unroll
@@ -272,15 +275,15 @@ __global__ __launch_bounds__(128) void vag_scatter_kernel(
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const double v = af[c] - rs[f] * r[c] * inv;
-            put(sl[j * m + c], v, frow, pb[c], A, b);  // row sigma, column node c
-            if (row[c] >= 0) A[sl[c * m + j]] += v;     // row node c, column sigma
+            put(sl[j * m + c], v, frow, pb[c], Af, b);   // row sigma, column node c
+            put(sl[c * m + j], v, row[c], 0.0, A, b);    // row node c, column sigma (-1: not stored)
         }
 #pragma unroll
         for (int f2 = 0; f2 < 6; ++f2) {
             if (!((mask >> f2) & 1u)) continue;
             const int j2 = 8 + __popc(mask & ((1u << f2) - 1u));
             const double v = (f2 == f ? o[0] : 0.0) - rs[f] * rs[f2] * inv;
-            A[sl[j * m + j2]] += v;
+            put(sl[j * m + j2], v, frow, 0.0, Af, b);
         }
         // fracture block of sigma, added by its lower-index cell:
         // (sigma,sigma) += R, (sigma,s) = (s,sigma) += -rho_s, (s,s') += a_sigma
@@ -297,17 +300,124 @@ __global__ __launch_bounds__(128) void vag_scatter_kernel(
                 frw[i] = node_unk[fn[i]];
                 fpb[i] = frw[i] < 0 ? p_bar[fn[i]] : 0.0;
             }
-            A[sl[j * m + j]] += M[0];
+            put(sl[j * m + j], M[0], frow, 0.0, Af, b);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                put(sl[j * m + q[i]], M[1 + i], frow, fpb[i], A, b);
+                put(sl[j * m + q[i]], M[1 + i], frow, fpb[i], Af, b);
                 if (frw[i] < 0) continue;
-                A[sl[q[i] * m + j]] += M[5 * (1 + i)];
+                put(sl[q[i] * m + j], M[5 * (1 + i)], frw[i], 0.0, A, b);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) put(sl[q[i] * m + q[k]], M[5 * (1 + i) + 1 + k], frw[i], fpb[k], A, b);
             }
         }
     }
+}
+
+// Exact elimination of fracture-face groups of one colour, one wavefront per
+// group.  The group block [A_GG | A_GB] (g x (g+m), row-major) and its
+// right-hand side b_G are factored in LDS: A_GG = L L^T, Y = L^-1 A_GB,
+// y = L^-1 b_G; then A_BB -= Y^T Y and b_B -= Y^T y are subtracted from the
+// node rows.  L, Y and y are written back for the recovery of u_G.
+// Groups of one colour share no free node, so the updates do not collide;
+// every sum runs in a fixed order (deterministic).
+__global__ __launch_bounds__(64) void vag_group_elim_kernel(
+    int32_t first, int32_t ngroup, const int32_t *__restrict__ grp_ptr, const int32_t *__restrict__ grp_face,
+    const int32_t *__restrict__ grp_nptr, const int32_t *__restrict__ grp_node, const int64_t *__restrict__ grp_off,
+    const int64_t *__restrict__ grp_poff, const int32_t *__restrict__ grp_pos, const int32_t *__restrict__ frac_unk,
+    double *__restrict__ Gb, double *__restrict__ A, double *__restrict__ b, int *__restrict__ bad) {
+    extern __shared__ double lds[];
+    const int32_t G = first + blockIdx.x;
+    if (blockIdx.x >= ngroup) return;
+    const int tid = threadIdx.x;
+    const int g = grp_ptr[G + 1] - grp_ptr[G];
+    const int m = grp_nptr[G + 1] - grp_nptr[G];
+    const int W = g + m + 1;                       // LDS row: [A_GG | A_GB | b_G]
+    double *blk = Gb + grp_off[G];
+    const int32_t *faces = grp_face + grp_ptr[G];
+    const int32_t *B = grp_node + grp_nptr[G];
+    for (int e = tid; e < g * W; e += 64) {
+        const int i = e / W, c = e - i * W;
+        lds[e] = c < g + m ? blk[(int64_t)i * (g + m) + c] : b[frac_unk[faces[i]]];
+    }
+    __syncthreads();
+    // right-looking Cholesky of A_GG
+    for (int k = 0; k < g; ++k) {
+        const double piv = lds[k * W + k];
+        if (!(piv > 0.0)) {
+            if (tid == 0) atomicMin(bad, -1 - G);
+            return;  // uniform across the block: piv is read from LDS by every lane
+        }
+        const double d = sqrt(piv);
+        __syncthreads();
+        if (tid == 0) lds[k * W + k] = d;
+        for (int i = k + 1 + tid; i < g; i += 64) lds[i * W + k] /= d;
+        __syncthreads();
+        const int rem = g - k - 1;
+        for (int e = tid; e < rem * rem; e += 64) {
+            const int i = k + 1 + e / rem, j = k + 1 + e % rem;
+            if (j <= i) lds[i * W + j] -= lds[i * W + k] * lds[j * W + k];
+        }
+        __syncthreads();
+    }
+    // forward substitution, one column of [A_GB | b_G] per lane
+    for (int c = g + tid; c < W; c += 64) {
+        for (int i = 0; i < g; ++i) {
+            double v = lds[i * W + c];
+            for (int k = 0; k < i; ++k) v -= lds[i * W + k] * lds[k * W + c];
+            lds[i * W + c] = v / lds[i * W + i];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < g * W; e += 64) {
+        const int i = e / W, c = e - i * W;
+        if (c < g + m) blk[(int64_t)i * (g + m) + c] = lds[e];
+        else b[frac_unk[faces[i]]] = lds[e];
+    }
+    // Schur complement on the node rows
+    const int32_t *pos = grp_pos + grp_poff[G];
+    for (int e = tid; e < m * m; e += 64) {
+        const int p = e / m, q = e - p * m;
+        double sum = 0.0;
+        for (int k = 0; k < g; ++k) sum += lds[k * W + g + p] * lds[k * W + g + q];
+        A[pos[e]] -= sum;
+    }
+    for (int p = tid; p < m; p += 64) {
+        double sum = 0.0;
+        for (int k = 0; k < g; ++k) sum += lds[k * W + g + p] * lds[k * W + g + m];
+        b[B[p]] -= sum;
+    }
+}
+
+// Recovery of the eliminated faces: u_G = L^-T (y - Y u_B), one wavefront per group.
+__global__ __launch_bounds__(64) void vag_group_back_kernel(
+    int32_t ngroup, const int32_t *__restrict__ grp_ptr, const int32_t *__restrict__ grp_face,
+    const int32_t *__restrict__ grp_nptr, const int32_t *__restrict__ grp_node, const int64_t *__restrict__ grp_off,
+    const int32_t *__restrict__ frac_unk, const double *__restrict__ Gb, const double *__restrict__ b,
+    double *__restrict__ x) {
+    __shared__ double z[kGroupMaxFaces];
+    const int32_t G = blockIdx.x;
+    if (G >= ngroup) return;
+    const int tid = threadIdx.x;
+    const int g = grp_ptr[G + 1] - grp_ptr[G];
+    const int m = grp_nptr[G + 1] - grp_nptr[G];
+    const double *blk = Gb + grp_off[G];
+    const int32_t *faces = grp_face + grp_ptr[G];
+    const int32_t *B = grp_node + grp_nptr[G];
+    if (tid < g) {
+        double v = b[frac_unk[faces[tid]]];
+        for (int p = 0; p < m; ++p) v -= blk[(int64_t)tid * (g + m) + g + p] * x[B[p]];
+        z[tid] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int i = g - 1; i >= 0; --i) {
+            double v = z[i];
+            for (int k = i + 1; k < g; ++k) v -= blk[(int64_t)k * (g + m) + i] * z[k];
+            z[i] = v / blk[(int64_t)i * (g + m) + i];
+        }
+    }
+    __syncthreads();
+    if (tid < g) x[frac_unk[faces[tid]]] = z[tid];
 }
 
 __global__ void vag_diag_inv_kernel(int32_t n, const int32_t *__restrict__ diag_pos,
@@ -335,16 +445,37 @@ void launch_frac_local(hipStream_t s, int32_t nf, const double *xyz, const int32
     VAG_HIP(hipGetLastError());
 }
 
-void launch_scatter(hipStream_t s, int32_t ncell_color, const int32_t *cells, int32_t nc, int32_t nfree,
+void launch_scatter(hipStream_t s, int32_t ncell_color, const int32_t *cells, int32_t nc, int32_t nsys,
                     const int32_t *hex8, const uint8_t *fmask, const int32_t *cell_frac,
                     const int32_t *frac_cell, const int32_t *frac_slot, const int32_t *frac_nodes,
-                    const int32_t *node_unk, const double *p_bar, const double *aK, const double *rK,
-                    const double *AKK, const double *fside, const double *A5, const int64_t *slot_ptr,
-                    const int32_t *slots, double *A, double *b) {
+                    const int32_t *node_unk, const int32_t *frac_unk, const double *p_bar, const double *aK,
+                    const double *rK, const double *AKK, const double *fside, const double *A5,
+                    const int64_t *slot_ptr, const int32_t *slots, double *A, double *Gb, double *b) {
     if (ncell_color <= 0) return;
     hipLaunchKernelGGL(vag_scatter_kernel, dim3(nblk(ncell_color, 128)), dim3(128), 0, s, ncell_color,
-                       cells, nc, nfree, hex8, fmask, cell_frac, frac_cell, frac_slot, frac_nodes, node_unk,
-                       p_bar, aK, rK, AKK, fside, A5, slot_ptr, slots, A, b);
+                       cells, nc, nsys, hex8, fmask, cell_frac, frac_cell, frac_slot, frac_nodes, node_unk,
+                       frac_unk, p_bar, aK, rK, AKK, fside, A5, slot_ptr, slots, A, Gb, b);
+    VAG_HIP(hipGetLastError());
+}
+
+void launch_group_elim(hipStream_t s, int32_t first, int32_t ngroup, int max_g, int max_m, const int32_t *grp_ptr,
+                       const int32_t *grp_face, const int32_t *grp_nptr, const int32_t *grp_node,
+                       const int64_t *grp_off, const int64_t *grp_poff, const int32_t *grp_pos,
+                       const int32_t *frac_unk, double *Gb, double *A, double *b, int *bad) {
+    if (ngroup <= 0) return;
+    if (max_g > kGroupMaxFaces || max_m > kGroupMaxNodes) throw Error(VAG_ERR_ARG, "internal: group too large");
+    const size_t lds = (size_t)max_g * (max_g + max_m + 1) * sizeof(double);
+    hipLaunchKernelGGL(vag_group_elim_kernel, dim3(ngroup), dim3(64), lds, s, first, ngroup, grp_ptr, grp_face,
+                       grp_nptr, grp_node, grp_off, grp_poff, grp_pos, frac_unk, Gb, A, b, bad);
+    VAG_HIP(hipGetLastError());
+}
+
+void launch_group_back(hipStream_t s, int32_t ngroup, const int32_t *grp_ptr, const int32_t *grp_face,
+                       const int32_t *grp_nptr, const int32_t *grp_node, const int64_t *grp_off,
+                       const int32_t *frac_unk, const double *Gb, const double *b, double *x) {
+    if (ngroup <= 0) return;
+    hipLaunchKernelGGL(vag_group_back_kernel, dim3(ngroup), dim3(64), 0, s, ngroup, grp_ptr, grp_face, grp_nptr,
+                       grp_node, grp_off, frac_unk, Gb, b, x);
     VAG_HIP(hipGetLastError());
 }
 

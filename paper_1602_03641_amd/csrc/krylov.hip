@@ -106,20 +106,20 @@ __global__ __launch_bounds__(kThreads) void pcg_init_kernel(int32_t n, const dou
     }
 }
 
-__global__ __launch_bounds__(kThreads) void pcg_start_kernel(PcgParts P, PcgState *st, double rtol) {
-    const double bb = sum_parts<OpSum, kThreads>(P.rr(-1), P.G);
+__global__ __launch_bounds__(kThreads) void pcg_start_kernel(PcgParts P, PcgState *st, double rtol, int k0) {
+    const double bb = sum_parts<OpSum, kThreads>(P.rr(k0 - 1), P.G);
     if (threadIdx.x == 0) {
         st->bnorm2 = bb;
         st->tol2 = rtol * rtol * bb;
         st->rr = bb;
-        st->iter = 0;
+        st->iter = k0;
         st->done = (bb == 0.0);
         st->converged = (bb == 0.0);
     }
 }
 
 template <class T>
-__global__ __launch_bounds__(kThreads) void pcg_direction_kernel(int32_t n, int k, const T *__restrict__ z,
+__global__ __launch_bounds__(kThreads) void pcg_direction_kernel(int32_t n, int k, int k0, const T *__restrict__ z,
                                                                  T *__restrict__ p, PcgParts P, PcgState *st,
                                                                  int update) {
     if (st->done) return;
@@ -137,8 +137,8 @@ __global__ __launch_bounds__(kThreads) void pcg_direction_kernel(int32_t n, int 
         return;
     }
     double beta = 0.0;
-    if (k > 0) beta = sum_parts<OpSum, kThreads>(P.rz(k - 1), P.G) / sum_parts<OpSum, kThreads>(P.rz(k), P.G);
-    if (k == 0) {
+    if (k > k0) beta = sum_parts<OpSum, kThreads>(P.rz(k - 1), P.G) / sum_parts<OpSum, kThreads>(P.rz(k), P.G);
+    if (k == k0) {
         GRID_STRIDE(i, n) p[i] = z[i];
     } else {
         const T b = (T)beta;
@@ -215,6 +215,30 @@ __global__ __launch_bounds__(kThreads) void pcg_dot_rz_kernel(int32_t n, int k, 
     GRID_STRIDE(i, n) v[0] += (double)r[i] * (double)z[i];
     block_reduce<OpSum, 1, kThreads>(v);
     if (threadIdx.x == 0) P.rz(k)[blockIdx.x] = v[0];
+}
+
+// warm start at iteration k0: r = b - A x, partials rr(k0-1); with dinv also
+// z = D^-1 r and partials rz(k0-1)
+__global__ __launch_bounds__(kThreads) void pcg_init_warm_kernel(Sell<double> A, int k0, const double *__restrict__ b,
+                                                                 const double *__restrict__ x, double *__restrict__ r,
+                                                                 const double *__restrict__ dinv, double *__restrict__ z,
+                                                                 PcgParts P) {
+    double v[2] = {0.0, 0.0};
+    GRID_STRIDE(i, A.n) {
+        const double ri = b[i] - sell_row(A, x, (int32_t)i);
+        r[i] = ri;
+        if (dinv) {
+            const double zi = dinv[i] * ri;
+            z[i] = zi;
+            v[0] += ri * zi;
+        }
+        v[1] += ri * ri;
+    }
+    block_reduce<OpSum, 2, kThreads>(v);
+    if (threadIdx.x == 0) {
+        if (dinv) P.rz(k0 - 1)[blockIdx.x] = v[0];
+        P.rr(k0 - 1)[blockIdx.x] = v[1];
+    }
 }
 
 // x = 0, r = b (no preconditioner applied), partials of b.b
@@ -309,12 +333,17 @@ void launch_pcg_init(hipStream_t s, int32_t n, const double *b, const double *di
                      double *z, PcgParts P) {
     LAUNCH(pcg_init_kernel, P.G, n, b, dinv, x, r, z, P);
 }
-void launch_pcg_start(hipStream_t s, PcgParts P, PcgState *st, double rtol) {
-    LAUNCH(pcg_start_kernel, 1, P, st, rtol);
+void launch_pcg_start(hipStream_t s, PcgParts P, PcgState *st, double rtol, int k0) {
+    LAUNCH(pcg_start_kernel, 1, P, st, rtol, k0);
+}
+void launch_pcg_init_warm(hipStream_t s, Sell<double> A, int k0, const double *b, const double *x, double *r,
+                          const double *dinv, double *z, PcgParts P) {
+    LAUNCH(pcg_init_warm_kernel, P.G, A, k0, b, x, r, dinv, z, P);
 }
 template <class T>
-void launch_pcg_direction(hipStream_t s, int32_t n, int k, const T *z, T *p, PcgParts P, PcgState *st, bool update) {
-    LAUNCH(pcg_direction_kernel<T>, P.G, n, k, z, p, P, st, update ? 1 : 0);
+void launch_pcg_direction(hipStream_t s, int32_t n, int k, int k0, const T *z, T *p, PcgParts P, PcgState *st,
+                          bool update) {
+    LAUNCH(pcg_direction_kernel<T>, P.G, n, k, k0, z, p, P, st, update ? 1 : 0);
 }
 template <class V, class T>
 void launch_pcg_spmv(hipStream_t s, Sell<V> A, const T *p, T *q, PcgParts P, const PcgState *st) {
@@ -356,7 +385,8 @@ void launch_diag_scaling(hipStream_t s, Sell<double> A, const int32_t *diag_pos,
 }
 
 #define INST(T)                                                                                                   \
-    template void launch_pcg_direction<T>(hipStream_t, int32_t, int, const T *, T *, PcgParts, PcgState *, bool); \
+    template void launch_pcg_direction<T>(hipStream_t, int32_t, int, int, const T *, T *, PcgParts, PcgState *,   \
+                                          bool);                                                                  \
     template void launch_pcg_spmv<T, T>(hipStream_t, Sell<T>, const T *, T *, PcgParts, const PcgState *);        \
     template void launch_pcg_update_xr<T>(hipStream_t, int32_t, int, T *, T *, const T *, const T *, PcgParts,   \
                                           PcgState *);                                                            \

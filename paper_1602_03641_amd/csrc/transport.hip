@@ -423,8 +423,16 @@ __global__ __launch_bounds__(256) void transport_step_kernel(int32_t nrow, const
     const int32_t sl = i / kSliceRows, lane = i % kSliceRows;
     const int64_t b0 = slice_ptr[sl], b1 = slice_ptr[sl + 1];
     const double ci = c_in[i];
-    double acc = tdiag[i] * ci;
-    for (int64_t q = b0 + lane; q < b1; q += kSliceRows) acc += tval[q] * c_in[tcol[q]];
+    double a0 = tdiag[i] * ci, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t q = b0 + lane;
+    for (; q + 3 * kSliceRows < b1; q += 4 * kSliceRows) {
+        a1 += tval[q] * c_in[tcol[q]];
+        a2 += tval[q + kSliceRows] * c_in[tcol[q + kSliceRows]];
+        a3 += tval[q + 2 * kSliceRows] * c_in[tcol[q + 2 * kSliceRows]];
+        a0 += tval[q + 3 * kSliceRows] * c_in[tcol[q + 3 * kSliceRows]];
+    }
+    for (; q < b1; q += kSliceRows) a1 += tval[q] * c_in[tcol[q]];
+    const double acc = (a0 + a1) + (a2 + a3);
     c_out[i] = (theta == 1.0) ? acc : ci + theta * (acc - ci);
 }
 

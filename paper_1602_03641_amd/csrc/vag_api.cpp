@@ -22,6 +22,10 @@ struct vag_handle {
     DBuf<int32_t> hex8, cell_frac, frac_cell, frac_slot, frac_nodes, node_unk, node_cell_ptr, node_cell,
         node_frac_ptr, node_frac, color_cells, sell_col, diag_pos, slots;
     DBuf<int64_t> sell_ptr;
+    // eliminated fracture-face groups
+    DBuf<int32_t> frac_unk, grp_ptr, grp_face, grp_nptr, grp_node, grp_pos;
+    DBuf<int64_t> grp_off, grp_poff;
+    DBuf<double> Gb;
     DBuf<uint8_t> fmask, dirichlet, frac_node;
     DBuf<int64_t> slot_ptr;
     // numeric inputs
@@ -127,10 +131,11 @@ std::vector<T> host_copy(const T *src, size_t n, vag_mem mem) {
 void check_options(const vag_options &o) {
     if (!(o.rtol > 0) || o.max_iter < 0 || !(o.cfl > 0) || o.check_every <= 0)
         throw Error(VAG_ERR_ARG, "invalid options (rtol, max_iter, cfl or check_every)");
-    if (o.precision != VAG_FP64 && o.precision != VAG_MIXED) throw Error(VAG_ERR_ARG, "unknown precision");
-    if (o.precision == VAG_MIXED && o.precond != VAG_PC_AMG)
-        throw Error(VAG_ERR_UNSUPPORTED, "VAG_MIXED needs the AMG preconditioner");
-    if (o.precision == VAG_MIXED && !(o.inner_rtol > 0 && o.inner_rtol < 1))
+    if (o.precision != VAG_FP64 && o.precision != VAG_MIXED && o.precision != VAG_MIXED_IR)
+        throw Error(VAG_ERR_ARG, "unknown precision");
+    if (o.precision != VAG_FP64 && o.precond != VAG_PC_AMG)
+        throw Error(VAG_ERR_UNSUPPORTED, "mixed precision needs the AMG preconditioner");
+    if (o.precision == VAG_MIXED_IR && !(o.inner_rtol > 0 && o.inner_rtol < 1))
         throw Error(VAG_ERR_ARG, "inner_rtol must lie in (0, 1)");
     if (o.krylov != VAG_CG) throw Error(VAG_ERR_UNSUPPORTED, "only VAG_CG is implemented in this build");
     if (o.precond != VAG_PC_JACOBI && o.precond != VAG_PC_AMG)
@@ -150,7 +155,9 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 
 namespace {
 void precond_apply(vag_handle *h, const double *r, double *z, const PcgState *st) {
-    if (h->opt.precond == VAG_PC_AMG)
+    if (h->opt.precond == VAG_PC_AMG && h->opt.precision == VAG_MIXED)
+        h->amg.apply_mixed(h->stream, r, z, st);
+    else if (h->opt.precond == VAG_PC_AMG)
         h->amg.apply(h->stream, r, z, st);
     else
         launch_jacobi(h->stream, h->S.nunk, h->dinv.p, r, z);
@@ -165,41 +172,59 @@ AmgOptions amg_options(const vag_options &o) {
 }
 
 // Preconditioned CG from x = 0 on the device; the host only queues iterations
-// and reads the state every check_every iterations.
+// and reads the state every check_every iterations.  When the recurrence
+// residual meets rtol but the true residual does not (rounding drift), CG
+// restarts from the current x with the remaining reduction as its target.
 void run_pcg(vag_handle *h) {
     hipStream_t s = h->stream;
     const int32_t n = h->S.nunk;
     const PcgParts P{h->parts.p, pcg_grid(n)};
     PcgState *st = h->pcg.p;
     const bool jacobi = h->opt.precond == VAG_PC_JACOBI;
-    if (jacobi) {
-        launch_pcg_init(s, n, h->b.p, h->dinv.p, h->x.p, h->r.p, h->z.p, P);
-    } else {
-        launch_pcg_init(s, n, h->b.p, nullptr, h->x.p, h->r.p, h->z.p, P);
-        precond_apply(h, h->r.p, h->z.p, nullptr);
-        launch_pcg_dot_rz<double>(s, n, -1, h->r.p, h->z.p, P, nullptr);
-    }
-    launch_pcg_start(s, P, st, h->opt.rtol);
     const Sell<double> A = h->Asell();
-    int k = 0;
     const int max_iter = h->opt.max_iter;
-    for (;;) {
-        const int kend = std::min(k + h->opt.check_every, max_iter);
-        for (; k < kend; ++k) {
-            launch_pcg_direction<double>(s, n, k, h->z.p, h->p.p, P, st, true);
-            launch_pcg_spmv<double, double>(s, A, h->p.p, h->q.p, P, st);
-            if (jacobi) {
-                launch_pcg_update(s, n, k, h->x.p, h->r.p, h->z.p, h->p.p, h->q.p, h->dinv.p, P, st);
-            } else {
-                launch_pcg_update_xr<double>(s, n, k, h->x.p, h->r.p, h->p.p, h->q.p, P, st);
-                precond_apply(h, h->r.p, h->z.p, st);
-                launch_pcg_dot_rz<double>(s, n, k, h->r.p, h->z.p, P, st);
-            }
+    int k = 0, k0 = 0;
+    double rtol = h->opt.rtol, bb = -1.0;
+    for (int restart = 0;; ++restart) {
+        if (restart == 0) {
+            launch_pcg_init(s, n, h->b.p, jacobi ? h->dinv.p : nullptr, h->x.p, h->r.p, h->z.p, P);
+        } else {
+            launch_pcg_init_warm(s, A, k0, h->b.p, h->x.p, h->r.p, jacobi ? h->dinv.p : nullptr, h->z.p, P);
         }
-        if (k >= max_iter) launch_pcg_direction<double>(s, n, k, h->z.p, h->p.p, P, st, false);  // final test only
-        VAG_HIP(hipMemcpyAsync(h->h_pcg, st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+        if (!jacobi) {
+            precond_apply(h, h->r.p, h->z.p, nullptr);
+            launch_pcg_dot_rz<double>(s, n, k0 - 1, h->r.p, h->z.p, P, nullptr);
+        }
+        launch_pcg_start(s, P, st, rtol, k0);
+        for (;;) {
+            const int kend = std::min(k + h->opt.check_every, max_iter);
+            for (; k < kend; ++k) {
+                launch_pcg_direction<double>(s, n, k, k0, h->z.p, h->p.p, P, st, true);
+                launch_pcg_spmv<double, double>(s, A, h->p.p, h->q.p, P, st);
+                if (jacobi) {
+                    launch_pcg_update(s, n, k, h->x.p, h->r.p, h->z.p, h->p.p, h->q.p, h->dinv.p, P, st);
+                } else {
+                    launch_pcg_update_xr<double>(s, n, k, h->x.p, h->r.p, h->p.p, h->q.p, P, st);
+                    precond_apply(h, h->r.p, h->z.p, st);
+                    launch_pcg_dot_rz<double>(s, n, k, h->r.p, h->z.p, P, st);
+                }
+            }
+            if (k >= max_iter) launch_pcg_direction<double>(s, n, k, k0, h->z.p, h->p.p, P, st, false);
+            VAG_HIP(hipMemcpyAsync(h->h_pcg, st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+            VAG_HIP(hipStreamSynchronize(s));
+            if (h->h_pcg->done || k >= max_iter) break;
+        }
+        k = h->h_pcg->iter;
+        if (!h->h_pcg->converged || k >= max_iter || restart >= 3) break;
+        // true residual check
+        launch_residual_norm(s, A, h->x.p, h->b.p, h->q.p, h->rparts.p, h->scal.p);
+        VAG_HIP(hipMemcpyAsync(h->h_scal, h->scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipStreamSynchronize(s));
-        if (h->h_pcg->done || k >= max_iter) break;
+        if (bb < 0) bb = h->h_scal[1];
+        const double rr = h->h_scal[0];
+        if (rr <= h->opt.rtol * h->opt.rtol * bb) break;
+        rtol = std::min(0.5, h->opt.rtol * std::sqrt(bb / rr));
+        k0 = k;
     }
     h->last_inner = h->h_pcg->iter;
     h->last_outer = 1;
@@ -235,19 +260,19 @@ void run_mixed(vag_handle *h) {
         launch_pcg_init_plain<float>(s, n, h->b32.p, h->x32.p, h->r32.p, P);
         h->amg.apply32(s, h->r32.p, h->z32.p, nullptr);
         launch_pcg_dot_rz<float>(s, n, -1, h->r32.p, h->z32.p, P, nullptr);
-        launch_pcg_start(s, P, st, h->opt.inner_rtol);
+        launch_pcg_start(s, P, st, h->opt.inner_rtol, 0);
         const int budget = h->opt.max_iter - inner_total;
         int k = 0;
         for (;;) {
             const int kend = std::min(k + h->opt.check_every, budget);
             for (; k < kend; ++k) {
-                launch_pcg_direction<float>(s, n, k, h->z32.p, h->p32.p, P, st, true);
+                launch_pcg_direction<float>(s, n, k, 0, h->z32.p, h->p32.p, P, st, true);
                 launch_pcg_spmv<float, float>(s, A32, h->p32.p, h->q32.p, P, st);
                 launch_pcg_update_xr<float>(s, n, k, h->x32.p, h->r32.p, h->p32.p, h->q32.p, P, st);
                 h->amg.apply32(s, h->r32.p, h->z32.p, st);
                 launch_pcg_dot_rz<float>(s, n, k, h->r32.p, h->z32.p, P, st);
             }
-            if (k >= budget) launch_pcg_direction<float>(s, n, k, h->z32.p, h->p32.p, P, st, false);
+            if (k >= budget) launch_pcg_direction<float>(s, n, k, 0, h->z32.p, h->p32.p, P, st, false);
             VAG_HIP(hipMemcpyAsync(h->h_pcg, st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
             VAG_HIP(hipStreamSynchronize(s));
             if (h->h_pcg->done || k >= budget) break;
@@ -288,6 +313,7 @@ vag_status vag_default_options(vag_options *o) {
     o->amg_max_levels = 12;
     o->amg_theta = 0.02;
     o->amg_sweeps = 1;
+    o->eliminate_frac_faces = 1;
     return VAG_OK;
 }
 
@@ -313,7 +339,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         auto hex8 = host_copy(mesh->hex8, 8 * (size_t)nc, mem);
         std::vector<int32_t> fnodes = nf ? host_copy(frac->face_nodes, 4 * (size_t)nf, mem) : std::vector<int32_t>();
         auto dir = host_copy(bc->node_dirichlet, (size_t)nn, mem);
-        build_symbolic(nn, nc, nf, hex8.data(), fnodes.data(), dir.data(), h->S);
+        build_symbolic(nn, nc, nf, hex8.data(), fnodes.data(), dir.data(), h->opt.eliminate_frac_faces != 0, h->S);
         const Symbolic &S = h->S;
         h->mu = rock->mu;
 
@@ -337,6 +363,15 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         upload_vec(h, h->diag_pos, S.diag_pos);
         upload_vec(h, h->slot_ptr, S.slot_ptr);
         upload_vec(h, h->slots, S.slots);
+        upload_vec(h, h->frac_unk, S.frac_unk);
+        upload_vec(h, h->grp_ptr, S.grp_ptr);
+        upload_vec(h, h->grp_face, S.grp_face);
+        upload_vec(h, h->grp_nptr, S.grp_nptr);
+        upload_vec(h, h->grp_node, S.grp_node);
+        upload_vec(h, h->grp_pos, S.grp_pos);
+        upload_vec(h, h->grp_off, S.grp_off);
+        upload_vec(h, h->grp_poff, S.grp_poff);
+        h->Gb.alloc(std::max<int64_t>(S.grp_off.back(), 1), h->tr);
 
         upload(h, h->perm, rock->perm, 6 * (size_t)nc, mem);
         upload(h, h->poro, rock->porosity, (size_t)nc, mem);
@@ -352,7 +387,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
             launch_fill(h->stream, nn, 0.0, h->c_bar.p);
         }
 
-        const size_t n = S.nunk;
+        const size_t n = S.nx;  // vectors hold the eliminated faces too
         h->aK.alloc(36 * (size_t)nc, h->tr);
         h->rK.alloc(8 * (size_t)nc, h->tr);
         h->AKK.alloc(nc, h->tr);
@@ -456,6 +491,8 @@ vag_status vag_set_options(vag_handle *h, const vag_options *opt) {
     if (!h || !opt) return VAG_ERR_ARG;
     return guard(h, [&] {
         check_options(*opt);
+        if ((opt->eliminate_frac_faces != 0) != (h->opt.eliminate_frac_faces != 0))
+            throw Error(VAG_ERR_ARG, "eliminate_frac_faces is fixed when the handle is created");
         h->opt = *opt;
     });
 }
@@ -475,15 +512,21 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
         launch_frac_local(s, S.nf, h->xyz.p, h->frac_nodes.p, h->fwidth.p, h->fperm.p, h->mu, h->A5.p, h->area.p);
         // 2. cell elimination, colour by colour
         launch_fill(s, (int64_t)h->A.n, 0.0, h->A.p);  // padding stays 0
-        launch_fill(s, n, 0.0, h->b.p);
+        launch_fill(s, S.nx, 0.0, h->b.p);
+        if (S.ngroup) launch_fill(s, S.grp_off.back(), 0.0, h->Gb.p);
         for (int c = 0; c < S.ncolor; ++c)
-            launch_scatter(s, S.color_ptr[c + 1] - S.color_ptr[c], h->color_cells.p + S.color_ptr[c], S.nc, S.nfree,
+            launch_scatter(s, S.color_ptr[c + 1] - S.color_ptr[c], h->color_cells.p + S.color_ptr[c], S.nc, S.nunk,
                            h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->frac_slot.p, h->frac_nodes.p,
-                           h->node_unk.p, h->p_bar.p, h->aK.p, h->rK.p, h->AKK.p, h->fside.p, h->A5.p,
-                           h->slot_ptr.p, h->slots.p, h->A.p, h->b.p);
+                           h->node_unk.p, h->frac_unk.p, h->p_bar.p, h->aK.p, h->rK.p, h->AKK.p, h->fside.p, h->A5.p,
+                           h->slot_ptr.p, h->slots.p, h->A.p, h->Gb.p, h->b.p);
+        // fracture-face groups onto the nodes, colour by colour
+        for (int c = 0; c < S.ngcolor; ++c)
+            launch_group_elim(s, S.gcolor_ptr[c], S.gcolor_ptr[c + 1] - S.gcolor_ptr[c], S.grp_max_g, S.grp_max_m,
+                              h->grp_ptr.p, h->grp_face.p, h->grp_nptr.p, h->grp_node.p, h->grp_off.p,
+                              h->grp_poff.p, h->grp_pos.p, h->frac_unk.p, h->Gb.p, h->A.p, h->b.p, h->bad.p);
         launch_diag_inv(s, n, h->diag_pos.p, h->A.p, h->dinv.p);
         VAG_HIP(hipEventRecord(h->ev[1], s));
-        if (h->opt.precision == VAG_MIXED) {
+        if (h->opt.precision == VAG_MIXED_IR) {
             // the single-precision hierarchy is built on the symmetrically scaled matrix
             ensure(h->dsc, (size_t)std::max(n, 1), h->tr);
             ensure(h->As, h->A.n, h->tr);
@@ -493,10 +536,11 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
                          amg_options(h->opt));
         } else if (h->opt.precond == VAG_PC_AMG) {
             h->amg.setup(s, h->tr, h->Asell(), (int64_t)h->A.n, amg_options(h->opt));
+            if (h->opt.precision == VAG_MIXED) h->amg.make_fp32(s, h->tr, nullptr);
         }
         VAG_HIP(hipEventRecord(h->ev[2], s));
         // 3. Krylov
-        if (h->opt.precision == VAG_MIXED)
+        if (h->opt.precision == VAG_MIXED_IR)
             run_mixed(h);
         else
             run_pcg(h);
@@ -504,8 +548,10 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
         const PcgState pst = *h->h_pcg;
         converged = pst.converged != 0;
         // 4. recovery and fluxes
+        launch_group_back(s, S.ngroup, h->grp_ptr.p, h->grp_face.p, h->grp_nptr.p, h->grp_node.p, h->grp_off.p,
+                          h->frac_unk.p, h->Gb.p, h->b.p, h->x.p);
         launch_node_pressure(s, S.nn, h->node_unk.p, h->x.p, h->p_bar.p, h->u_node.p);
-        if (S.nf) launch_copy(s, S.nf, h->x.p + S.nfree, h->u_frac.p);
+        if (S.nf) launch_node_pressure(s, S.nf, h->frac_unk.p, h->x.p, h->p_bar.p, h->u_frac.p);  // all mapped
         launch_fill(s, 2 * (int64_t)std::max(S.nf, 1), 0.0, h->F_cell_frac.p);
         launch_cell_flux(s, S.nc, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->aK.p, h->rK.p, h->AKK.p,
                          h->fside.p, h->u_node.p, h->u_frac.p, h->u_cell.p, h->F_cell.p, h->F_cell_frac.p);
@@ -520,6 +566,9 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
         int bad = 0;
         VAG_HIP(hipMemcpyAsync(&bad, h->bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipStreamSynchronize(s));
+        if (bad < 0)
+            throw Error(VAG_ERR_ARG, "fracture-face group " + std::to_string(-1 - bad) +
+                                         " has a face block that is not positive definite");
         if (bad != 0x7f7f7f7f)
             throw Error(VAG_ERR_MESH, "cell " + std::to_string(bad) + " has a non-positive sub-tetrahedron");
         if (info) {
@@ -716,7 +765,7 @@ vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms)
         auto once = [&] {
             switch (kernel) {
                 case VAG_KERNEL_SPMV:  // the Krylov loop's SpMV (with its dot-product partials)
-                    if (h->opt.precision == VAG_MIXED && h->amg.have32)
+                    if (h->opt.precision == VAG_MIXED_IR && h->amg.have32)
                         launch_pcg_spmv<float, float>(s, h->amg.L[0]->A32, h->x32.p, h->q32.p,
                                                       PcgParts{h->parts.p, pcg_grid(S.nunk)}, h->pcg.p + 1);
                     else
@@ -732,7 +781,7 @@ vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms)
                                  h->frac_cell.p, h->aK.p, h->rK.p, h->AKK.p, h->vol.p, h->fside.p, h->bad.p);
                     break;
                 case VAG_KERNEL_PRECOND:
-                    if (h->opt.precision == VAG_MIXED && h->amg.have32)
+                    if (h->opt.precision == VAG_MIXED_IR && h->amg.have32)
                         h->amg.apply32(s, h->r32.p, h->z32.p, nullptr);
                     else
                         precond_apply(h, h->r.p, h->z.p, nullptr);

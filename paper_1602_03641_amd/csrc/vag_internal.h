@@ -46,7 +46,7 @@ __host__ __device__ constexpr int sym5(int i, int j) {
 }
 
 constexpr int kSliceRows = 64;      // SELL slice height = one wavefront
-constexpr int kReduceBlocks = 1024; // fixed grid of the deterministic reductions
+constexpr int kReduceBlocks = 512;  // fixed grid of the deterministic reductions
 constexpr int kReduceThreads = 256;
 
 // ---------------------------------------------------------------------------
@@ -89,7 +89,9 @@ struct DBuf {
 // symbolic phase (host): topology-only data structures
 // ---------------------------------------------------------------------------
 struct Symbolic {
-    int32_t nn = 0, nc = 0, nf = 0, nfree = 0, nunk = 0;
+    // nunk: rows of the assembled system (free nodes, kept fracture faces);
+    // nx: all nodal and face unknowns (eliminated faces numbered after nunk)
+    int32_t nn = 0, nc = 0, nf = 0, nfree = 0, nunk = 0, nx = 0;
     int64_t nnz = 0;
     std::vector<uint8_t> fmask;        // [nc] bit f = local face f is a fracture face
     std::vector<int32_t> cell_frac;    // [nc*6] fracture index of local face, -1
@@ -105,12 +107,35 @@ struct Symbolic {
     std::vector<int64_t> sell_ptr;                   // same pattern in sliced ELL
     std::vector<int32_t> sell_col, csr2sell, diag_pos;  // diag_pos: SELL position of a_ii
     std::vector<int64_t> slot_ptr;                   // [nc+1]
-    std::vector<int32_t> slots;                      // per cell m*m SELL positions (-1 Dirichlet row, -2 Dirichlet col)
+    std::vector<int32_t> slots;                      // per cell m*m positions (see below)
+    std::vector<int32_t> frac_unk;                   // [nf] unknown index of sigma (>= nunk: eliminated)
+    // Fracture-face groups eliminated onto the nodes: faces linked through a
+    // shared cell, ordered by colour (groups of one colour share no free node).
+    // Group G: faces grp_face[grp_ptr[G]..], free nodes of its cells
+    // grp_node[grp_nptr[G]..] (system unknowns, ascending), a dense block of
+    // g x (g + m) values at grp_off[G], and the system positions of its m x m
+    // node pairs at grp_pos[grp_poff[G]..].
+    int32_t ngroup = 0, ngcolor = 0, grp_max_g = 0, grp_max_m = 0;
+    std::vector<int32_t> grp_ptr, grp_face, grp_nptr, grp_node, grp_pos, gcolor_ptr;
+    std::vector<int64_t> grp_off, grp_poff;
 };
 
+// Limits of an eliminated fracture-face group (larger groups stay unknowns).
+constexpr int kGroupMaxFaces = 32;
+constexpr int kGroupMaxNodes = 64;
+
 // Builds the symbolic data; throws vag::Error on invalid input.
+// With eliminate, fracture-face groups within the limits above are
+// eliminated; otherwise every face stays an unknown.
+// Slot codes of a cell's local pair (row a, column b), local order: 8 nodes,
+// then fracture faces by local face index:
+//   >= 0  position in the system values, or, for the row of an eliminated
+//         face, in the dense group blocks;
+//   -1    nothing stored (Dirichlet row, or a node row's column of an
+//         eliminated face, which the group block holds transposed);
+//   -2    Dirichlet column: goes to the right-hand side of the row.
 void build_symbolic(int64_t nn, int64_t nc, int64_t nf, const int32_t *hex8,
-                    const int32_t *frac_nodes, const uint8_t *dirichlet, Symbolic &S);
+                    const int32_t *frac_nodes, const uint8_t *dirichlet, bool eliminate, Symbolic &S);
 
 // ---------------------------------------------------------------------------
 // kernel launchers (defined in the .hip files)
@@ -147,12 +172,22 @@ void launch_local(hipStream_t s, int32_t nc, const double *xyz, const int32_t *h
                   double *aK, double *rK, double *AKK, double *vol, double *fside, int *bad_cell);
 void launch_frac_local(hipStream_t s, int32_t nf, const double *xyz, const int32_t *frac_nodes,
                        const double *width, const double *perm, double mu, double *A5, double *area);
-void launch_scatter(hipStream_t s, int32_t ncell_color, const int32_t *cells, int32_t nc, int32_t nfree,
+void launch_scatter(hipStream_t s, int32_t ncell_color, const int32_t *cells, int32_t nc, int32_t nsys,
                     const int32_t *hex8, const uint8_t *fmask, const int32_t *cell_frac,
                     const int32_t *frac_cell, const int32_t *frac_slot, const int32_t *frac_nodes,
-                    const int32_t *node_unk, const double *p_bar, const double *aK, const double *rK,
-                    const double *AKK, const double *fside, const double *A5, const int64_t *slot_ptr,
-                    const int32_t *slots, double *A, double *b);
+                    const int32_t *node_unk, const int32_t *frac_unk, const double *p_bar, const double *aK,
+                    const double *rK, const double *AKK, const double *fside, const double *A5,
+                    const int64_t *slot_ptr, const int32_t *slots, double *A, double *Gb, double *b);
+// Eliminates groups [first, first+ngroup) (one colour) onto the node rows.
+// bad receives -1-G for a group whose face block is not positive definite.
+void launch_group_elim(hipStream_t s, int32_t first, int32_t ngroup, int max_g, int max_m, const int32_t *grp_ptr,
+                       const int32_t *grp_face, const int32_t *grp_nptr, const int32_t *grp_node,
+                       const int64_t *grp_off, const int64_t *grp_poff, const int32_t *grp_pos,
+                       const int32_t *frac_unk, double *Gb, double *A, double *b, int *bad);
+// x of the eliminated faces from the solved node unknowns.
+void launch_group_back(hipStream_t s, int32_t ngroup, const int32_t *grp_ptr, const int32_t *grp_face,
+                       const int32_t *grp_nptr, const int32_t *grp_node, const int64_t *grp_off,
+                       const int32_t *frac_unk, const double *Gb, const double *b, double *x);
 void launch_diag_inv(hipStream_t s, int32_t n, const int32_t *diag_pos, const double *A, double *dinv);
 
 // Krylov
@@ -166,11 +201,15 @@ void launch_residual_norm(hipStream_t s, Sell<double> A, const double *x, const 
 // x = 0, r = b, parts rr(-1) = b.b; with dinv also z = D^-1 b, p = z and parts rz(-1)
 void launch_pcg_init(hipStream_t s, int32_t n, const double *b, const double *dinv, double *x, double *r,
                      double *z, PcgParts P);
-// one block: tolerance from rr(-1), state reset
-void launch_pcg_start(hipStream_t s, PcgParts P, PcgState *st, double rtol);
+// one block: tolerance rtol^2 rr(k0-1), state reset to iteration k0
+void launch_pcg_start(hipStream_t s, PcgParts P, PcgState *st, double rtol, int k0);
+// warm start at iteration k0 from the current x (see krylov.hip)
+void launch_pcg_init_warm(hipStream_t s, Sell<double> A, int k0, const double *b, const double *x, double *r,
+                          const double *dinv, double *z, PcgParts P);
 // convergence test on rr(k-1); then p = z + beta p (beta = rz(k-1)/rz(k-2), 0 at k = 0)
 template <class T>
-void launch_pcg_direction(hipStream_t s, int32_t n, int k, const T *z, T *p, PcgParts P, PcgState *st, bool update);
+void launch_pcg_direction(hipStream_t s, int32_t n, int k, int k0, const T *z, T *p, PcgParts P, PcgState *st,
+                          bool update);
 // q = A p, partials of p.q
 template <class V, class T>
 void launch_pcg_spmv(hipStream_t s, Sell<V> A, const T *p, T *q, PcgParts P, const PcgState *st);

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libvag.so")
 VAG_OK, VAG_WARN_NOT_CONVERGED = 0, 1
 VAG_ERR_ARG, VAG_ERR_MESH, VAG_ERR_UNSUPPORTED, VAG_ERR_OOM, VAG_ERR_HIP, VAG_ERR_STATE = -1, -2, -3, -4, -5, -6
 VAG_MEM_HOST, VAG_MEM_DEVICE = 0, 1
-VAG_FP64, VAG_MIXED = 0, 1
+VAG_FP64, VAG_MIXED, VAG_MIXED_IR = 0, 1, 2
 VAG_CG, VAG_GMRES = 0, 1
 VAG_PC_JACOBI, VAG_PC_AMG = 0, 1
 VAG_KERNEL_SPMV, VAG_KERNEL_TRANSPORT_STEP, VAG_KERNEL_LOCAL, VAG_KERNEL_PRECOND = 0, 1, 2, 3
@@ -53,7 +53,7 @@ class vag_options(C.Structure):
                 ("inner_rtol", C.c_double), ("max_iter", C.c_int), ("gmres_restart", C.c_int),
                 ("check_every", C.c_int), ("cfl", C.c_double), ("amg_coarse_size", C.c_int),
                 ("amg_max_levels", C.c_int), ("amg_theta", C.c_double), ("amg_sweeps", C.c_int),
-                ("reserved", C.c_int * 8)]
+                ("eliminate_frac_faces", C.c_int), ("reserved", C.c_int * 7)]
 
 
 class vag_solve_info(C.Structure):

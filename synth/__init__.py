@@ -14,6 +14,7 @@ from .meshes import (  # noqa: F401
     config4_job,
     config5,
     cartesian_problem,
+    planes_problem,
     random_problem,
     e1_problem,
     e2_problem,

@@ -213,20 +213,28 @@ def _assemble(name, dims, xyz, hex8, faces, ratios, perm, df=0.01, lam_m=1.0, **
         poro=np.ones(len(hex8)), mu=1.0, **kw)
 
 
-def cartesian_problem(n, planes=(), ratio=1e4, df=0.01, jitter=0.0, aniso_sigma=None,
-                      seed=0, name=None, **kw):
-    """Cube of n^3 cells; ``planes`` = [(axis, plane, a_lo, a_hi, b_lo, b_hi), ...]."""
-    dims = (n, n, n)
+def planes_problem(dims, planes=(), ratio=1e4, df=0.01, jitter=0.0, aniso_sigma=None,
+                   seed=0, name=None, **kw):
+    """Box of dims cells; ``planes`` = [(axis, plane, a_lo, a_hi, b_lo, b_hi), ...]."""
+    dims = tuple(int(d) for d in dims)
     xyz, hex8 = structured_hex(*dims)
+    nc = dims[0] * dims[1] * dims[2]
     rng = np.random.default_rng(seed)
     if jitter > 0:
         xyz = jitter_nodes(xyz, dims, jitter, rng)
-    perm = lognormal_tensors(n ** 3, aniso_sigma, rng) if aniso_sigma else isotropic(n ** 3)
+    perm = lognormal_tensors(nc, aniso_sigma, rng) if aniso_sigma else isotropic(nc)
     patches = [(plane_faces(dims, *p), ratio) for p in planes]
     faces, ratios = merge_patches(patches)
     d, pb, cb = x_dirichlet(dims, len(xyz), xyz)
-    return _assemble(name or f"cart{n}", dims, xyz, hex8, faces, ratios, perm, df=df,
+    return _assemble(name or f"box{dims}", dims, xyz, hex8, faces, ratios, perm, df=df,
                      dirichlet=d, p_bar=pb, c_bar=cb, **kw)
+
+
+def cartesian_problem(n, planes=(), ratio=1e4, df=0.01, jitter=0.0, aniso_sigma=None,
+                      seed=0, name=None, **kw):
+    """Cube of n^3 cells; ``planes`` = [(axis, plane, a_lo, a_hi, b_lo, b_hi), ...]."""
+    return planes_problem((n, n, n), planes, ratio=ratio, df=df, jitter=jitter, aniso_sigma=aniso_sigma,
+                          seed=seed, name=name or f"cart{n}", **kw)
 
 
 def random_problem(dims, seed, jitter=0.2, aniso_sigma=1.0, n_patches=3,

@@ -18,6 +18,8 @@ import pytest
 import oracle
 import synth
 
+import schur_ref
+
 pytestmark = pytest.mark.gpu
 
 
@@ -93,9 +95,10 @@ def test_config1_parity():
 
 
 def test_config1_system_entries():
-    """The assembled eliminated system equals the oracle's entry by entry."""
+    """With the fracture faces kept, the assembled cell-eliminated system equals
+    the oracle's entry by entry (same pattern, same unknown order)."""
     p = synth.config1()
-    g = gpu_run(p, n_steps=0)
+    g = gpu_run(p, n_steps=0, eliminate_frac_faces=0)
     rp, col, val, b = g["handle"].system()
     A, bo = oracle.system(p)
     np.testing.assert_array_equal(rp, A.indptr)
@@ -103,6 +106,30 @@ def test_config1_system_entries():
     scale = np.abs(A.data).max()
     assert np.abs(val - A.data).max() <= 1e-13 * scale
     assert np.abs(b - bo).max() <= 1e-13 * max(np.abs(bo).max(), 1e-300)
+
+
+def check_eliminated_system(p, g):
+    """The library's face-eliminated system equals the dense elimination of the
+    oracle's system (tests/schur_ref.py)."""
+    rp, col, val, b = g["handle"].system()
+    A, bo = oracle.system(p)
+    n_free = int((p.dirichlet == 0).sum())
+    S, bs, kept, elim = schur_ref.eliminate(A, bo, n_free)
+    n = len(kept)
+    assert len(rp) == n + 1
+    G = schur_ref.csr_to_dense(rp, col, val, n)
+    scale = np.abs(S).max()
+    assert np.abs(G - S).max() <= 1e-12 * scale
+    assert np.abs(b - bs).max() <= 1e-12 * max(np.abs(bs).max(), 1e-300)
+    return len(elim)
+
+
+def test_config1_system_eliminated():
+    """Every fracture face of config 1 is its own group and is eliminated."""
+    p = synth.config1()
+    g = gpu_run(p, n_steps=0)
+    assert check_eliminated_system(p, g) == p.n_frac
+    assert g["info"]["n_unknowns"] == int((p.dirichlet == 0).sum())
 
 
 @pytest.mark.parametrize("dims,seed,patches", [((9, 7, 5), 1, 4), ((6, 11, 4), 2, 6), ((13, 5, 6), 3, 8),
@@ -114,12 +141,57 @@ def test_random_parity(dims, seed, patches):
     p = synth.random_problem(dims, seed, n_patches=patches, n_steps=30)
     g = gpu_run(p, rtol=1e-13, max_iter=20000)
     o = oracle.run(p, rtol=1e-13)
-    # system entries
+    check_eliminated_system(p, g)
+    compare(p, g, o)
+
+
+def test_random_parity_faces_kept():
+    """The faces-kept route: system entry by entry and results."""
+    p = synth.random_problem((9, 7, 5), 1, n_patches=6, n_steps=30)
+    g = gpu_run(p, rtol=1e-13, max_iter=20000, eliminate_frac_faces=0)
+    o = oracle.run(p, rtol=1e-13)
     rp, col, val, b = g["handle"].system()
     A, bo = oracle.system(p)
     np.testing.assert_array_equal(col, A.indices)
     assert np.abs(val - A.data).max() <= 1e-12 * np.abs(A.data).max()
     compare(p, g, o)
+
+
+def stacked_problem():
+    """A chain of 39 fracture faces through consecutive cells (too large a
+    group: its faces stay unknowns), three intersecting planes (groups of 4
+    along the intersection lines, a larger group at the triple point) and
+    boundary fractures, on a jittered anisotropic 40x7x6 box."""
+    planes = [(0, x, 2, 3, 2, 3) for x in range(1, 40)]
+    planes += [(0, 20, 3, 7, 3, 6), (1, 5, 15, 25, 0, 6), (2, 4, 15, 25, 3, 7), (1, 0, 30, 36, 1, 5)]
+    return synth.planes_problem((40, 7, 6), planes, ratio=1e4, jitter=0.2, aniso_sigma=1.0, seed=11,
+                                name="stacked", rtol=1e-13, cfl=0.9, n_steps=30)
+
+
+def test_stacked_groups_parity():
+    p = stacked_problem()
+    g = gpu_run(p, rtol=1e-13, max_iter=20000)
+    o = oracle.run(p, rtol=1e-13)
+    A, _ = oracle.system(p)
+    n_free = int((p.dirichlet == 0).sum())
+    sizes = sorted(len(f) for f, _ in schur_ref.face_groups(A, n_free))
+    assert sizes[-1] == 39 and 4 in sizes and sizes[-2] > 4
+    n_elim = check_eliminated_system(p, g)
+    assert 0 < n_elim < p.n_frac
+    compare(p, g, o)
+
+
+def test_eliminated_equals_kept():
+    """Both routes give the same discrete solution."""
+    p = synth.random_problem((8, 6, 5), 5, n_patches=10, n_steps=20)
+    a = gpu_run(p, rtol=1e-13, max_iter=20000)
+    b = gpu_run(p, rtol=1e-13, max_iter=20000, eliminate_frac_faces=0)
+    assert a["info"]["n_unknowns"] < b["info"]["n_unknowns"]
+    for k in ("u_node", "u_cell", "u_frac"):
+        assert rel_l2(a[k], b[k]) <= 1e-10, k
+    scale = np.abs(b["F_cell"]).max()
+    for k in ("F_cell", "F_frac", "F_cell_frac"):
+        assert flux_err(a[k], b[k], scale) <= 1e-8, k
 
 
 def test_e1_time_grid_parity():
@@ -256,28 +328,43 @@ def test_amg_config2_full_size():
 # ---------------------------------------------------------------------------
 # mixed precision: FP32 AMG + FP32 inner CG under FP64 iterative refinement
 # ---------------------------------------------------------------------------
-def _mixed(**kw):
+def _mixed(ir=False, **kw):
     from paper_1602_03641_amd import vag
-    return dict(precond=vag.VAG_PC_AMG, precision=vag.VAG_MIXED, **kw)
+    return dict(precond=vag.VAG_PC_AMG, precision=vag.VAG_MIXED_IR if ir else vag.VAG_MIXED, **kw)
 
 
 @pytest.mark.parametrize("name", ["config1", "random"])
-def test_mixed_reaches_fp64_parity(name):
-    """Refinement to rtol 1e-12 recovers the FP64 solution: same parity bar."""
+@pytest.mark.parametrize("ir", [False, True])
+def test_mixed_reaches_fp64_parity(name, ir):
+    """FP32 hierarchy (and, with refinement, FP32 inner CG): the FP64 residual
+    still reaches the tolerance and the solution meets the FP64 parity bar.
+    On the 1e6-contrast mesh the attainable FP64 residual is about 1e-11
+    (||A|| ||x|| eps / ||b||), so that case is solved to 1e-10."""
     p = synth.config1() if name == "config1" else synth.random_problem((14, 12, 10), 6, n_patches=8, n_steps=20)
-    g = gpu_run(p, rtol=1e-12, inner_rtol=1e-3, max_iter=5000, **_mixed())
+    rtol = 1e-12 if name == "config1" else 1e-10
+    g = gpu_run(p, rtol=rtol, inner_rtol=1e-3, max_iter=5000, **_mixed(ir))
     o = oracle.run(p, rtol=1e-13)
     info = g["info"]
-    assert info["status"] == 0 and info["rel_residual"] <= 1e-12
-    assert info["outer_iterations"] >= 2
+    assert info["status"] == 0 and info["rel_residual"] <= rtol
+    if ir:
+        assert info["outer_iterations"] >= 2
     compare(p, g, o)
+
+
+def test_mixed_same_iterations_as_fp64():
+    """An FP32 V-cycle preconditions FP64 CG as well as the FP64 V-cycle."""
+    p = synth.config2()
+    a = gpu_run(p, rtol=1e-8, max_iter=2000, n_steps=0, **_amg())["info"]
+    b = gpu_run(p, rtol=1e-8, max_iter=2000, n_steps=0, **_mixed())["info"]
+    print("fp64 vs mixed iterations:", a["iterations"], b["iterations"])
+    assert b["iterations"] <= a["iterations"] + 3
 
 
 def test_mixed_config2_error_stated():
     """Benchmark tolerance (1e-8): the FP64 residual meets it and the error
     against the FP64 oracle is reported per result."""
     p = synth.config2()
-    g = gpu_run(p, rtol=1e-8, inner_rtol=1e-4, max_iter=2000, **_mixed())
+    g = gpu_run(p, rtol=1e-8, max_iter=2000, **_mixed())
     o = oracle.run(p, rtol=1e-12)
     info = g["info"]
     e_p = rel_l2(g["u_node"], o["darcy"]["u_node"])
