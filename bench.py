@@ -25,11 +25,25 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(h, sinfo, tinfo):
+def algorithmic_bytes(h, sinfo, tinfo, levels=None, precision="fp64"):
     n, nnz = sinfo["n_unknowns"], sinfo["nnz"]
     spmv = 12 * nnz + 4 * (n + 1) + 16 * n                       # CSR FP64: val+col, row_ptr, x, y
     step = 12 * tinfo["t_nnz"] + 24 * tinfo["n_rows"]            # upwind sweep: entries, diag, c in/out
-    return dict(spmv=spmv, transport_step=step)
+    out = dict(spmv=spmv, transport_step=step)
+    if levels:
+        # one V-cycle: per level two matrix passes (residual, smoothing sweep),
+        # about 13 vector passes plus the aggregate maps, the coarse vector;
+        # the coarsest level is a dense product
+        v = 4 if precision in ("mixed", "mixed_ir") else 8      # matrix value bytes
+        w = 4 if precision == "mixed_ir" else 8                  # vector value bytes
+        b = 0
+        for i, (rows, nz, _) in enumerate(levels[:-1]):
+            nc = levels[i + 1][0]
+            b += 2 * (v + 4) * nz + 13 * rows * w + 8 * rows + nc * w
+        rows = levels[-1][0]
+        b += rows * rows * w + 2 * rows * w
+        out["vcycle"] = b
+    return out
 
 
 def cpu_baseline(prob, budget_s=30.0):
@@ -44,6 +58,58 @@ def cpu_baseline(prob, budget_s=30.0):
                       f"{dt:.2f} s"}
 
 
+def serving_bench(vag, synth, n_jobs, workers, budget, seed=4):
+    """Config-4 serving stream: n_jobs jittered n^3 jobs (n in [16, 96], 1-20
+    patches, one ratio per job, 100 steps).  Saturation runs (all jobs at t=0)
+    give the throughput of each mode; Poisson arrivals at 0.7 x the FP64
+    saturation rate give p50/p99 latency (scheduled arrival -> outputs on the
+    host), the same arrival times for both modes."""
+    import time as _t
+    t0 = _t.perf_counter()
+    jobs = [synth.config4_job(j) for j in range(n_jobs)]
+    gen_s = _t.perf_counter() - t0
+    modes = {"fp64": dict(precond=vag.VAG_PC_AMG, precision=vag.VAG_FP64, rtol=1e-8, max_iter=20000),
+             "mixed": dict(precond=vag.VAG_PC_AMG, precision=vag.VAG_MIXED, rtol=1e-8, max_iter=20000)}
+
+    def run(mode, arrivals):
+        srv = vag.Server(hbm_budget=budget, n_workers=workers)
+        try:
+            base = srv.clock()
+            ids = []
+            for p, ta in zip(jobs, arrivals):
+                while srv.clock() - base < ta:
+                    _t.sleep(min(1e-3, max(0.0, ta - (srv.clock() - base))))
+                ids.append(srv.submit(p, n_steps=p.n_steps, **modes[mode]))
+            res = [srv.wait(i) for i in ids]
+            st = srv.stats()
+        finally:
+            srv.close()
+        bad = [r["message"] for r in res if r["status"] != 0]
+        if bad:
+            raise RuntimeError(f"serving job failed: {bad[0]}")
+        lat = np.array([r["t_end"] - (base + ta) for r, ta in zip(res, arrivals)])
+        span = max(r["t_end"] for r in res) - base
+        return dict(jobs_per_s=round(len(res) / span, 3), makespan_s=round(span, 3),
+                    p50_ms=round(1e3 * float(np.percentile(lat, 50)), 2),
+                    p99_ms=round(1e3 * float(np.percentile(lat, 99)), 2),
+                    mean_create_ms=round(float(np.mean([r["ms_create"] for r in res])), 2),
+                    mean_gpu_solve_ms=round(float(np.mean([r["solve"]["ms_assembly"] + r["solve"]["ms_setup"] +
+                                                           r["solve"]["ms_solve"] + r["solve"]["ms_fluxes"]
+                                                           for r in res])), 2),
+                    mean_iterations=round(float(np.mean([r["solve"]["iterations"] for r in res])), 1),
+                    peak_GB=round(st["peak_bytes_in_use"] / 1e9, 2), budget_GB=round(st["budget"] / 1e9, 2))
+
+    zero = [0.0] * n_jobs
+    out = {"jobs": n_jobs, "workers": workers, "job_generation_s": round(gen_s, 1)}
+    out["saturation"] = {m: run(m, zero) for m in modes}
+    lam = 0.7 * out["saturation"]["fp64"]["jobs_per_s"]
+    rng = np.random.default_rng(seed)
+    arrivals = list(np.cumsum(rng.exponential(1.0 / lam, n_jobs)))
+    out["poisson_rate_jobs_per_s"] = round(lam, 3)
+    out["poisson"] = {m: run(m, arrivals) for m in modes}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,7 +118,12 @@ def main():
     ap.add_argument("--precond", choices=["jacobi", "amg"], default=os.environ.get("VAG_BENCH_PRECOND", "amg"))
     ap.add_argument("--precision", choices=["fp64", "mixed", "mixed_ir"], default="fp64")
     ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--keep-faces", action="store_true", help="fracture faces stay unknowns (no group elimination)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-jobs", type=int, default=int(os.environ.get("VAG_BENCH_SERVING_JOBS", "0")),
+                    help="config-4 serving stream of this many jobs after the timed steps (0: skip)")
+    ap.add_argument("--serving-workers", type=int, default=4)
+    ap.add_argument("--serving-budget-gb", type=float, default=0.0, help="0: 80%% of free device memory")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is a design note, "
@@ -66,7 +137,8 @@ def main():
     prob = synth.config2(n=args.n)
     opts = dict(rtol=prob.rtol, cfl=prob.cfl, max_iter=50000,
                 precond=vag.VAG_PC_AMG if args.precond == "amg" else vag.VAG_PC_JACOBI,
-                precision={"fp64": vag.VAG_FP64, "mixed": vag.VAG_MIXED, "mixed_ir": vag.VAG_MIXED_IR}[args.precision])
+                precision={"fp64": vag.VAG_FP64, "mixed": vag.VAG_MIXED, "mixed_ir": vag.VAG_MIXED_IR}[args.precision],
+                eliminate_frac_faces=0 if args.keep_faces else 1)
     t0 = time.perf_counter()
     h = vag.Handle(prob, **opts)
     torch.cuda.synchronize()
@@ -88,9 +160,11 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
 
     # roofline of the dominant kernel: per-launch time from HIP events on the handle's stream
-    ab = algorithmic_bytes(h, sinfo, tinfo)
+    levels = h.amg_levels() if args.precond == "amg" else None
+    ab = algorithmic_bytes(h, sinfo, tinfo, levels, args.precision)
     ms_spmv = h.benchmark_kernel(vag.VAG_KERNEL_SPMV, 100)
     ms_step = h.benchmark_kernel(vag.VAG_KERNEL_TRANSPORT_STEP, 100)
+    ms_prec = h.benchmark_kernel(vag.VAG_KERNEL_PRECOND, 50)
     n_spmv = sinfo["iterations"] + 1
     share = {"spmv": ms_spmv * n_spmv, "transport_step": ms_step * tinfo["n_steps"]}
     dom = max(share, key=share.get)
@@ -101,7 +175,16 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "bytes_per_launch": ab[dom], "ms_per_launch": ms_dom,
                 "other": {"spmv_GBs": round(ab["spmv"] / (ms_spmv * 1e-3) / 1e9, 1),
-                          "transport_step_GBs": round(ab["transport_step"] / (ms_step * 1e-3) / 1e9, 1)}}
+                          "transport_step_GBs": round(ab["transport_step"] / (ms_step * 1e-3) / 1e9, 1),
+                          "precond_ms": round(ms_prec, 4)}}
+    if "vcycle" in ab:
+        roofline["other"]["vcycle_GBs"] = round(ab["vcycle"] / (ms_prec * 1e-3) / 1e9, 1)
+        roofline["other"]["vcycle_bytes"] = ab["vcycle"]
+
+    serving = None
+    if args.serving_jobs > 0:
+        serving = serving_bench(vag, synth, args.serving_jobs, args.serving_workers,
+                                int(args.serving_budget_gb * 1e9))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -114,14 +197,15 @@ def main():
         "config": {"workload": f"config2: cartesian {args.n}^3 hexahedra, 4 clipped face fractures, "
                                f"contrast 1e4, CG rtol {prob.rtol:g}, {prob.n_steps} upwind steps",
                    "precond": args.precond, "precision": args.precision,
+                   "fracture_faces": "kept" if args.keep_faces else "eliminated",
                    "n_unknowns": sinfo["n_unknowns"], "nnz": sinfo["nnz"], "n_frac": prob.n_frac},
         "iterations": sinfo["iterations"], "rel_residual": sinfo["rel_residual"],
         "phase_ms": {k: round(sinfo[k], 3) for k in ("ms_assembly", "ms_setup", "ms_solve", "ms_fluxes")}
         | {"transport_setup": round(tinfo["ms_setup"], 3), "transport_steps": round(tinfo["ms_steps"], 3)},
         "symbolic_s": round(symbolic_s, 3),
-        "amg_levels": h.amg_levels() if args.precond == "amg" else None,
+        "amg_levels": levels,
         "outer_iterations": sinfo["outer_iterations"],
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -50,7 +50,9 @@ typedef enum {
     VAG_ERR_UNSUPPORTED = -3,  /* valid request this build does not implement */
     VAG_ERR_OOM = -4,          /* device allocation failed */
     VAG_ERR_HIP = -5,          /* HIP runtime error */
-    VAG_ERR_STATE = -6         /* call out of order (e.g. transport before a pressure solve) */
+    VAG_ERR_STATE = -6,        /* call out of order (e.g. transport before a pressure solve) */
+    VAG_ERR_TIMEOUT = -7,      /* vag_server_wait: the job has not finished in time */
+    VAG_ERR_CANCELLED = -8     /* the job was cancelled before it started */
 } vag_status;
 
 typedef enum { VAG_MEM_HOST = 0, VAG_MEM_DEVICE = 1 } vag_mem;
@@ -201,6 +203,10 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
 vag_status vag_update(vag_handle *h, const vag_rock *rock, const vag_fractures *frac_props,
                       const double *p_bar, const double *c_bar, vag_mem mem);
 
+/* Binds the handle to another HIP stream (NULL: the null stream).  The
+ * caller orders it after the work already queued on the old stream. */
+vag_status vag_set_stream(vag_handle *h, void *hip_stream);
+
 /* Replaces the solver options of a handle (takes effect at the next solve). */
 vag_status vag_set_options(vag_handle *h, const vag_options *opt);
 
@@ -272,9 +278,10 @@ vag_status vag_get_system(vag_handle *h, int64_t *row_ptr, int64_t *col, double 
  */
 vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms_per_launch);
 
-/* AMG hierarchy of the last solve: number of levels, rows and stored entries
- * (sliced ELL incl. padding) per level, for up to max_levels levels. */
-vag_status vag_amg_levels(vag_handle *h, int *nlev, int64_t *rows, int64_t *stored, int max_levels);
+/* AMG hierarchy of the last solve: number of levels and, per level (up to
+ * max_levels; any array may be NULL), rows, nonzero entries and stored
+ * entries (sliced ELL including padding). */
+vag_status vag_amg_levels(vag_handle *h, int *nlev, int64_t *rows, int64_t *nnz, int64_t *stored, int max_levels);
 
 /* Device bytes held by the handle. */
 size_t vag_footprint_bytes(const vag_handle *h);
@@ -285,6 +292,95 @@ const char *vag_last_error(const vag_handle *h);
 
 /* Releases all device and host memory of the handle. */
 void vag_destroy(vag_handle *h);
+
+/*
+ * Upper bound of the device bytes a handle of these sizes holds after a solve
+ * and a transport call with these options (opt NULL = defaults); used for
+ * admission by footprint.
+ */
+size_t vag_estimate_footprint(int64_t n_nodes, int64_t n_cells, int64_t n_frac, const vag_options *opt);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of independent Darcy + transport jobs.       */
+/* ------------------------------------------------------------------------ */
+/*
+ * A server owns n_workers host threads, each with its own HIP stream on the
+ * device that is current when the server is created.  Submitted jobs wait in
+ * one FIFO queue; the head job starts on the first free worker as soon as its
+ * estimated footprint (vag_estimate_footprint) fits in what the running jobs
+ * and the cached handles leave of hbm_budget.  Jobs on different workers run
+ * concurrently, so their kernels overlap on the device; a job's own kernels
+ * are the same, in the same order, as on a lone handle, so its results are
+ * bitwise those of the job run alone.
+ *
+ * A job with a nonzero mesh_key keeps its handle (matrices, AMG hierarchy and
+ * all buffers) resident after it finishes; a later job with the same key and
+ * the same sizes reuses it with vag_update (topology and fracture set must be
+ * the same: the key is the caller's promise), skipping the symbolic phase and
+ * the allocations.  Idle cached handles count against the budget and are
+ * destroyed, least recently used first, when a job needs their room.
+ */
+typedef struct vag_server vag_server;
+
+typedef struct {
+    const vag_mesh *mesh;
+    const vag_fractures *frac;      /* NULL: no fracture */
+    const vag_rock *rock;
+    const vag_bc *bc;
+    const vag_options *opt;         /* NULL: defaults */
+    int64_t n_steps;                /* transport after the solve, as vag_transport */
+    double t_final;
+    uint64_t mesh_key;              /* 0: no handle reuse */
+    /* Host output buffers, written by the worker; NULL = not wanted.  They must
+     * stay valid until vag_server_wait returns for this job. */
+    double *u_node, *u_cell, *u_frac;   /* [n_nodes], [n_cells], [n_frac] */
+    double *c_cell, *c_frac, *c_node;   /* concentrations after the steps */
+} vag_job;
+
+typedef struct {
+    int status;                     /* vag_status of the job */
+    char message[200];              /* vag_last_error text when status != VAG_OK */
+    vag_solve_info solve;
+    vag_transport_info transport;
+    double t_submit, t_start, t_end;  /* seconds on the server's steady clock */
+    int worker;                     /* worker that ran the job, -1 if it never ran */
+    int reused;                     /* 1 if a cached handle was reused */
+    size_t footprint_estimate, footprint_bytes;
+    double ms_create;               /* wall time of vag_create (host symbolic phase, uploads) */
+    double ms_run;                  /* wall time from the start of the job to its outputs on the host */
+} vag_job_result;
+
+typedef struct {
+    int64_t submitted, queued, running, finished;
+    size_t budget, bytes_in_use, peak_bytes_in_use, cached_bytes;
+    int cached_handles;
+} vag_server_stats;
+
+/* hbm_budget 0: 80 % of the free device memory at creation.  n_workers in
+ * [1, 16].  Errors: VAG_ERR_ARG, VAG_ERR_HIP. */
+vag_status vag_server_create(size_t hbm_budget, int n_workers, vag_server **out);
+
+/* Copies the job's input arrays (host memory) and queues it; returns at once.
+ * VAG_ERR_OOM when the job's estimate exceeds the whole budget, VAG_ERR_ARG
+ * for missing inputs. */
+vag_status vag_server_submit(vag_server *s, const vag_job *job, uint64_t *job_id);
+
+/* Waits up to timeout_s seconds (< 0: no limit) for the job.  VAG_OK: *res is
+ * filled, the outputs are written and the id is released.  VAG_ERR_TIMEOUT:
+ * still queued or running.  VAG_ERR_ARG: unknown id. */
+vag_status vag_server_wait(vag_server *s, uint64_t job_id, double timeout_s, vag_job_result *res);
+
+/* Cancels a job that has not started (its wait then reports
+ * VAG_ERR_CANCELLED); VAG_ERR_STATE if it already started. */
+vag_status vag_server_cancel(vag_server *s, uint64_t job_id);
+
+vag_status vag_server_get_stats(vag_server *s, vag_server_stats *st);
+
+/* Seconds on the server's steady clock (the clock of t_submit etc.). */
+double vag_server_clock(vag_server *s);
+
+/* Cancels queued jobs, waits for running ones, releases everything. */
+void vag_server_destroy(vag_server *s);
 
 #ifdef __cplusplus
 }

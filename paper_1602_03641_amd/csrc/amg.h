@@ -24,7 +24,9 @@ void amg_launch_collapse(hipStream_t s, Sell<double> A, const int32_t *agg, int3
 void amg_launch_galerkin(hipStream_t s, Sell<double> A, const int32_t *Jcol, const double *apv, const int32_t *mptr,
                          const int32_t *mrows, int32_t nc, int mode, int32_t *big, int32_t *rowlen,
                          const int64_t *cptr, int32_t *ccol, double *cval, int *overflow);
-void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t *width, int64_t *ptr);
+// slice widths and pointers from row lengths; adds the number of entries to *nnz
+void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t *width, int64_t *ptr,
+                       unsigned long long *nnz);
 void amg_launch_slice_tail(hipStream_t s, int32_t n, const int64_t *ptr, int32_t *col, double *val);
 void amg_launch_dense_inverse(hipStream_t s, Sell<double> A, double *D);
 template <class V, class X>
@@ -65,10 +67,10 @@ struct AmgLevel {
 
 struct AmgOptions {
     double theta = 0.02;
-    int coarse_size = 256;
+    int coarse_size = 128;
     int max_levels = 12;
     int mis_rounds = 32;
-    int dense_max = 1024;
+    int dense_max = 384;  // Gauss-Jordan in one workgroup: O(n^3), keep n small
     int coarse_sweeps = 4;
 };
 
@@ -81,6 +83,7 @@ class Amg {
     double op_complexity = 1.0;
     DBuf<double> Ainv;
     DBuf<float> Ainv32;
+    DBuf<unsigned long long> level_nnz;  // entries (without padding) of each coarse level
 
     // Builds the hierarchy for A0 (n0 rows); host-synchronises a few times per level.
     void setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, const AmgOptions &o);

@@ -449,12 +449,20 @@ __global__ __launch_bounds__(64) void galerkin_kernel(Sell<double> A, const int3
 
 // slice widths (max row length of each 64-row slice)
 __global__ __launch_bounds__(64) void slice_width_kernel(int32_t n, const int32_t *__restrict__ rowlen,
-                                                         int32_t *__restrict__ width) {
+                                                         int32_t *__restrict__ width,
+                                                         unsigned long long *__restrict__ nnz) {
     const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
     int c = i < n ? rowlen[i] : 0;
+    int t = c;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) c = max(c, __shfl_down(c, o, 64));
-    if (threadIdx.x == 0) width[blockIdx.x] = c;
+    for (int o = 32; o > 0; o >>= 1) {
+        c = max(c, __shfl_down(c, o, 64));
+        t += __shfl_down(t, o, 64);
+    }
+    if (threadIdx.x == 0) {
+        width[blockIdx.x] = c;
+        atomicAdd(nnz, (unsigned long long)t);  // integer count: order-independent
+    }
 }
 // rows beyond n in the last slice: padding pointing at row 0
 __global__ __launch_bounds__(64) void slice_tail_kernel(int32_t n, const int64_t *__restrict__ ptr,
@@ -561,15 +569,19 @@ __global__ __launch_bounds__(kAT) void vc_sweep_kernel(Sell<V> A, const X *__res
         out[i] = y[i] + dinv[i] * (b[i] - s);
     }
 }
-// dense coarse solve x = Ainv b
+// dense coarse solve x = Ainv b: one wavefront per row, lanes along the
+// (contiguous) row, fixed-order wave reduction
 template <class X>
 __global__ __launch_bounds__(kAT) void vc_dense_kernel(int32_t n, const X *__restrict__ Ainv, const X *__restrict__ b,
                                                        X *__restrict__ x, const PcgState *st) {
     if (st && st->done) return;
-    GS(i, n) {
-        X s = 0;
-        for (int32_t j = 0; j < n; ++j) s += Ainv[i * n + j] * b[j];
-        x[i] = s;
+    const int lane = threadIdx.x & 63;
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n;
+         i += ((int64_t)gridDim.x * blockDim.x) >> 6) {
+        double s = 0.0;
+        for (int32_t j = lane; j < n; j += 64) s += (double)Ainv[i * n + j] * (double)b[j];
+        s = wave_reduce<OpSum>(s);
+        if (lane == 0) x[i] = (X)s;
     }
 }
 // conversions for the single-precision hierarchy
@@ -651,9 +663,10 @@ void amg_launch_galerkin(hipStream_t s, Sell<double> A, const int32_t *Jcol, con
     ALAUNCH(galerkin_kernel<8192>, nc, 64, A, Jcol, apv, mptr, mrows, nc, mode, big, rowlen, cptr, ccol, cval,
             overflow);
 }
-void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t *width, int64_t *ptr) {
+void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t *width, int64_t *ptr,
+                       unsigned long long *nnz) {
     const int32_t ns = (n + 63) / 64;
-    if (ns > 0) ALAUNCH(slice_width_kernel, ns, 64, n, rowlen, width);
+    if (ns > 0) ALAUNCH(slice_width_kernel, ns, 64, n, rowlen, width, nnz);
     launch_slice_scan(s, ns, width, ptr);
 }
 void amg_launch_slice_tail(hipStream_t s, int32_t n, const int64_t *ptr, int32_t *col, double *val) {
@@ -682,7 +695,7 @@ void amg_launch_post(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const 
 }
 template <class X>
 void amg_launch_dense(hipStream_t s, int32_t n, const X *Ainv, const X *b, X *x, const PcgState *st) {
-    ALAUNCH(vc_dense_kernel<X>, gridv(n), kAT, n, Ainv, b, x, st);
+    ALAUNCH(vc_dense_kernel<X>, gridv((int64_t)n * 64), kAT, n, Ainv, b, x, st);
 }
 template <class V, class X>
 void amg_launch_sweep(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, X *out, const PcgState *st) {

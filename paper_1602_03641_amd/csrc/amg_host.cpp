@@ -23,6 +23,8 @@ void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, co
     ensure(jcol_, (size_t)stored0, tr);
     ensure(apv_, (size_t)stored0, tr);
     ensure(counters_, 64, tr);
+    ensure(level_nnz, (size_t)std::max(o.max_levels, 1), tr);
+    VAG_HIP(hipMemsetAsync(level_nnz.p, 0, level_nnz.n * sizeof(unsigned long long), s));
     if (L.empty()) L.emplace_back(new AmgLevel());
     L[0]->n = n0;
     L[0]->A = A0;
@@ -69,7 +71,7 @@ void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, co
         ensure(cv.ptr, (size_t)ns + 1, tr);
         amg_launch_galerkin(s, lv.A, apj_.p, apv_.p, lv.mptr.p, lv.mrows.p, nc, 0, big_.p, rowlen_.p, nullptr,
                             nullptr, nullptr, counters_.p + 63);
-        amg_launch_slices(s, nc, rowlen_.p, width_.p, cv.ptr.p);
+        amg_launch_slices(s, nc, rowlen_.p, width_.p, cv.ptr.p, level_nnz.p + l + 1);
         int64_t hv[2];
         VAG_HIP(hipMemcpyAsync(&hv[0], cv.ptr.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipMemcpyAsync(h_ + 2, counters_.p + 63, sizeof(int32_t), hipMemcpyDeviceToHost, s));

@@ -18,6 +18,8 @@
 //  - node -> (cell, slot) and node -> (fracture, vertex) adjacency.
 #include <algorithm>
 #include <array>
+#include <exception>
+#include <thread>
 #include <unordered_map>
 
 #include "vag_internal.h"
@@ -25,6 +27,37 @@
 namespace vag {
 
 namespace {
+
+// Runs f(t, begin, end) over [0, n) split into contiguous chunks, one per
+// thread (at most 16, at least 32768 items each); the first exception thrown
+// by a chunk is rethrown.
+template <class F>
+void parallel_chunks(int64_t n, F &&f) {
+    const int64_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const int T = (int)std::max<int64_t>(1, std::min<int64_t>(hw, n / 32768));
+    if (T == 1) {
+        f(0, (int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    std::vector<std::exception_ptr> err(T);
+    for (int t = 0; t < T; ++t)
+        th.emplace_back([&, t] {
+            try {
+                f(t, n * t / T, n * (t + 1) / T);
+            } catch (...) {
+                err[t] = std::current_exception();
+            }
+        });
+    for (auto &x : th) x.join();
+    for (auto &e : err)
+        if (e) std::rethrow_exception(e);
+}
+
+int chunk_count(int64_t n) {
+    const int64_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(hw, n / 32768));
+}
 
 struct Key4 {
     std::array<int32_t, 4> v;
@@ -307,70 +340,90 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
             for (int32_t q = S.grp_nptr[G]; q < S.grp_nptr[G + 1]; ++q) ngp[fill[S.grp_node[q]]++] = G;
     }
 
-    auto cell_unknowns = [&](int32_t K, int32_t *u) {
-        int m = 0;
-        for (int a = 0; a < 8; ++a) u[m++] = S.node_unk[hex8[8 * (int64_t)K + a]];
-        for (int lf = 0; lf < 6; ++lf)
-            if (S.fmask[K] >> lf & 1) u[m++] = S.frac_unk[S.cell_frac[6 * (size_t)K + lf]];
-        return m;
+    // unknowns of each cell: 8 nodes, then its fracture faces by local face
+    std::vector<int32_t> cu(14 * (size_t)nc);
+    std::vector<uint8_t> cm(nc);
+    parallel_chunks(nc, [&](int, int64_t k0, int64_t k1) {
+        for (int32_t K = (int32_t)k0; K < (int32_t)k1; ++K) {
+            int32_t *u = cu.data() + 14 * (size_t)K;
+            int m = 0;
+            for (int a = 0; a < 8; ++a) u[m++] = S.node_unk[hex8[8 * (int64_t)K + a]];
+            for (int lf = 0; lf < 6; ++lf)
+                if (S.fmask[K] >> lf & 1) u[m++] = S.frac_unk[S.cell_frac[6 * (size_t)K + lf]];
+            cm[K] = (uint8_t)m;
+        }
+    });
+    // local index of fracture face f in cell K
+    auto face_local = [&](int32_t K, int32_t f) {
+        for (int lf = 0, j = 8; lf < 6; ++lf)
+            if (S.fmask[K] >> lf & 1) {
+                if (S.cell_frac[6 * (size_t)K + lf] == f) return j;
+                ++j;
+            }
+        return -1;
     };
 
-    // CSR pattern: row = free node or kept fracture face; a node also couples
-    // to every free node of each eliminated group it belongs to (fill)
+    // CSR pattern, rows in unknown order (node rows by node index, then kept
+    // faces by face index): row = free node or kept fracture face; a node
+    // also couples to every free node of each eliminated group it belongs to
+    // (fill)
     S.row_ptr.assign((size_t)S.nunk + 1, 0);
-    std::vector<int32_t> marker((size_t)S.nunk, -1);
-    std::vector<int32_t> cols;
-    cols.reserve(128);
-    // two passes: count then fill
-    for (int pass = 0; pass < 2; ++pass) {
-        if (pass == 1) {
-            for (int32_t r = 0; r < S.nunk; ++r) S.row_ptr[r + 1] += S.row_ptr[r];
-            if (S.row_ptr[S.nunk] < 0 || (int64_t)S.row_ptr[S.nunk] >= INT32_MAX)
-                throw Error(VAG_ERR_UNSUPPORTED, "system has more than 2^31 nonzeros");
-            S.col.resize(S.row_ptr[S.nunk]);
-            std::fill(marker.begin(), marker.end(), -1);
-        }
-        auto add = [&](int32_t row, int32_t c) {
-            if (c >= 0 && c < S.nunk && marker[c] != row) {
-                marker[c] = row;
-                cols.push_back(c);
-            }
-        };
-        auto finish_row = [&](int32_t row) {
-            if (pass == 0) {
-                S.row_ptr[row + 1] = (int32_t)cols.size();
-            } else {
+    {
+        // rows are built in chunks of nodes (then of faces), each chunk into
+        // its own column list, then concatenated in row order
+        const int Tn = chunk_count(nn), Tf = chunk_count(nf);
+        std::vector<std::vector<int32_t>> part(Tn + Tf);
+        auto build_rows = [&](std::vector<int32_t> &out, bool faces, int64_t i0, int64_t i1) {
+            std::vector<int32_t> marker((size_t)S.nunk, -1);
+            std::vector<int32_t> cols;
+            cols.reserve(128);
+            auto add = [&](int32_t row, int32_t c) {
+                if (c >= 0 && c < S.nunk && marker[c] != row) {
+                    marker[c] = row;
+                    cols.push_back(c);
+                }
+            };
+            auto add_cell = [&](int32_t row, int32_t K) {
+                const int32_t *u = cu.data() + 14 * (size_t)K;
+                for (int i = 0; i < cm[K]; ++i) add(row, u[i]);
+            };
+            for (int64_t i = i0; i < i1; ++i) {
+                int32_t row;
+                cols.clear();
+                if (!faces) {
+                    const int32_t s = (int32_t)i;
+                    row = S.node_unk[s];
+                    if (row < 0) continue;
+                    for (int32_t q = S.node_cell_ptr[s]; q < S.node_cell_ptr[s + 1]; ++q)
+                        add_cell(row, S.node_cell[q] >> 3);
+                    for (int32_t q = ngp_ptr[row]; q < ngp_ptr[row + 1]; ++q) {
+                        const int32_t G = ngp[q];
+                        for (int32_t k = S.grp_nptr[G]; k < S.grp_nptr[G + 1]; ++k) add(row, S.grp_node[k]);
+                    }
+                } else {
+                    const int32_t f = (int32_t)i;
+                    row = S.frac_unk[f];
+                    if (row >= S.nunk) continue;
+                    for (int side = 0; side < 2; ++side)
+                        if (S.frac_cell[2 * (size_t)f + side] >= 0) add_cell(row, S.frac_cell[2 * (size_t)f + side]);
+                }
                 std::sort(cols.begin(), cols.end());
-                std::copy(cols.begin(), cols.end(), S.col.begin() + S.row_ptr[row]);
+                out.insert(out.end(), cols.begin(), cols.end());
+                S.row_ptr[row + 1] = (int32_t)cols.size();
             }
         };
-        for (int32_t s = 0; s < nn; ++s) {
-            const int32_t row = S.node_unk[s];
-            if (row < 0) continue;
-            cols.clear();
-            for (int32_t q = S.node_cell_ptr[s]; q < S.node_cell_ptr[s + 1]; ++q) {
-                int32_t u[14];
-                const int m = cell_unknowns(S.node_cell[q] >> 3, u);
-                for (int i = 0; i < m; ++i) add(row, u[i]);
-            }
-            for (int32_t q = ngp_ptr[row]; q < ngp_ptr[row + 1]; ++q) {
-                const int32_t G = ngp[q];
-                for (int32_t k = S.grp_nptr[G]; k < S.grp_nptr[G + 1]; ++k) add(row, S.grp_node[k]);
-            }
-            finish_row(row);
-        }
-        for (int32_t f = 0; f < nf; ++f) {
-            const int32_t row = S.frac_unk[f];
-            if (row >= S.nunk) continue;
-            cols.clear();
-            for (int side = 0; side < 2; ++side) {
-                const int32_t K = S.frac_cell[2 * (size_t)f + side];
-                if (K < 0) continue;
-                int32_t u[14];
-                const int m = cell_unknowns(K, u);
-                for (int i = 0; i < m; ++i) add(row, u[i]);
-            }
-            finish_row(row);
+        parallel_chunks(nn, [&](int t, int64_t i0, int64_t i1) { build_rows(part[t], false, i0, i1); });
+        parallel_chunks(nf, [&](int t, int64_t i0, int64_t i1) { build_rows(part[Tn + t], true, i0, i1); });
+        int64_t total = 0;
+        for (auto &v : part) total += (int64_t)v.size();
+        if (total >= INT32_MAX) throw Error(VAG_ERR_UNSUPPORTED, "system has more than 2^31 nonzeros");
+        for (int32_t r = 0; r < S.nunk; ++r) S.row_ptr[r + 1] += S.row_ptr[r];
+        S.col.resize(total);
+        int64_t off = 0;
+        for (auto &v : part) {
+            std::copy(v.begin(), v.end(), S.col.begin() + off);
+            off += (int64_t)v.size();
+            std::vector<int32_t>().swap(v);
         }
     }
     S.nnz = S.row_ptr[S.nunk];
@@ -388,90 +441,138 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
         }
         if (S.sell_ptr[nslice] >= INT32_MAX)
             throw Error(VAG_ERR_UNSUPPORTED, "padded system has more than 2^31 entries");
-        S.sell_col.assign(S.sell_ptr[nslice], 0);
-        S.csr2sell.assign(S.nnz, -1);
-        for (int64_t sl = 0; sl < nslice; ++sl) {
-            const int32_t w = (int32_t)((S.sell_ptr[sl + 1] - S.sell_ptr[sl]) / kSliceRows);
-            for (int lane = 0; lane < kSliceRows; ++lane) {
-                const int64_t r = sl * kSliceRows + lane;
-                for (int32_t k = 0; k < w; ++k) {
-                    const int64_t pos = S.sell_ptr[sl] + (int64_t)k * kSliceRows + lane;
-                    if (r < n && k < S.row_ptr[r + 1] - S.row_ptr[r]) {
-                        S.sell_col[pos] = S.col[S.row_ptr[r] + k];
-                        S.csr2sell[S.row_ptr[r] + k] = (int32_t)pos;
-                    } else {
-                        S.sell_col[pos] = r < n ? (int32_t)r : 0;  // padding: own row, value 0
+        S.sell_col.resize(S.sell_ptr[nslice]);
+        S.csr2sell.resize(S.nnz);
+        parallel_chunks(nslice, [&](int, int64_t s0, int64_t s1) {
+            for (int64_t sl = s0; sl < s1; ++sl) {
+                const int32_t w = (int32_t)((S.sell_ptr[sl + 1] - S.sell_ptr[sl]) / kSliceRows);
+                for (int lane = 0; lane < kSliceRows; ++lane) {
+                    const int64_t r = sl * kSliceRows + lane;
+                    const int32_t len = r < n ? S.row_ptr[r + 1] - S.row_ptr[r] : 0;
+                    const int32_t pad = r < n ? (int32_t)r : 0;  // padding: own row, value 0
+                    int64_t pos = S.sell_ptr[sl] + lane;
+                    for (int32_t k = 0; k < w; ++k, pos += kSliceRows) {
+                        if (k < len) {
+                            S.sell_col[pos] = S.col[S.row_ptr[r] + k];
+                            S.csr2sell[S.row_ptr[r] + k] = (int32_t)pos;
+                        } else {
+                            S.sell_col[pos] = pad;
+                        }
                     }
                 }
             }
-        }
+        });
     }
     S.diag_pos.assign(S.nunk, -1);
-    for (int32_t r = 0; r < S.nunk; ++r)
-        for (int32_t q = S.row_ptr[r]; q < S.row_ptr[r + 1]; ++q)
-            if (S.col[q] == r) S.diag_pos[r] = S.csr2sell[q];
+    parallel_chunks(S.nunk, [&](int, int64_t r0, int64_t r1) {
+        for (int32_t r = (int32_t)r0; r < (int32_t)r1; ++r)
+            for (int32_t q = S.row_ptr[r]; q < S.row_ptr[r + 1]; ++q)
+                if (S.col[q] == r) S.diag_pos[r] = S.csr2sell[q];
+    });
 
-    auto sell_pos = [&](int32_t r, int32_t c) {
-        const int32_t *c0 = S.col.data() + S.row_ptr[r];
-        const int32_t *c1 = S.col.data() + S.row_ptr[r + 1];
-        const int32_t *it = std::lower_bound(c0, c1, c);
-        if (it == c1 || *it != c) throw Error(VAG_ERR_ARG, "internal: pattern misses an entry");
-        return S.csr2sell[it - S.col.data()];
+    // slot maps, row by row: posmap[c] = CSR index of column c in the row
+    S.slot_ptr.assign((size_t)nc + 1, 0);
+    for (int32_t K = 0; K < nc; ++K) S.slot_ptr[K + 1] = S.slot_ptr[K] + (int64_t)cm[K] * cm[K];
+    S.slots.assign(S.slot_ptr[nc], -1);
+    auto slot_rows = [&](bool faces, int64_t i0, int64_t i1) {
+        std::vector<int32_t> posmap((size_t)S.nunk, -1);
+        auto fill_row = [&](int32_t K, int a) {
+            const int m = cm[K];
+            const int32_t *u = cu.data() + 14 * (size_t)K;
+            int32_t *out = S.slots.data() + S.slot_ptr[K] + a * m;
+            for (int b = 0; b < m; ++b) {
+                const int32_t c = u[b];
+                if (c < 0) out[b] = -2;
+                else if (c >= S.nunk) out[b] = -1;
+                else {
+                    if (posmap[c] < 0) throw Error(VAG_ERR_ARG, "internal: pattern misses an entry");
+                    out[b] = S.csr2sell[posmap[c]];
+                }
+            }
+        };
+        auto set_row = [&](int32_t row, bool on) {
+            for (int32_t q = S.row_ptr[row]; q < S.row_ptr[row + 1]; ++q) posmap[S.col[q]] = on ? q : -1;
+        };
+        for (int64_t i = i0; i < i1; ++i) {
+            if (!faces) {
+                const int32_t s = (int32_t)i, row = S.node_unk[s];
+                if (row < 0) continue;
+                set_row(row, true);
+                for (int32_t q = S.node_cell_ptr[s]; q < S.node_cell_ptr[s + 1]; ++q)
+                    fill_row(S.node_cell[q] >> 3, S.node_cell[q] & 7);
+                set_row(row, false);
+            } else {
+                const int32_t f = (int32_t)i, row = S.frac_unk[f];
+                if (row >= S.nunk) continue;
+                set_row(row, true);
+                for (int side = 0; side < 2; ++side) {
+                    const int32_t K = S.frac_cell[2 * (size_t)f + side];
+                    if (K >= 0) fill_row(K, face_local(K, f));
+                }
+                set_row(row, false);
+            }
+        }
     };
+    parallel_chunks(nn, [&](int, int64_t i0, int64_t i1) { slot_rows(false, i0, i1); });
+    parallel_chunks(nf, [&](int, int64_t i0, int64_t i1) { slot_rows(true, i0, i1); });
+    // rows of eliminated faces: positions in the dense group blocks
     auto node_local = [&](int32_t G, int32_t u) {
         const int32_t *b0 = S.grp_node.data() + S.grp_nptr[G];
         const int32_t *b1 = S.grp_node.data() + S.grp_nptr[G + 1];
         return (int32_t)(std::lower_bound(b0, b1, u) - b0);
     };
-
-    // slot maps
-    S.slot_ptr.assign((size_t)nc + 1, 0);
-    for (int32_t K = 0; K < nc; ++K) {
-        int m = 8 + __builtin_popcount(S.fmask[K]);
-        S.slot_ptr[K + 1] = S.slot_ptr[K] + m * m;
-    }
-    S.slots.resize(S.slot_ptr[nc]);
-    for (int32_t K = 0; K < nc; ++K) {
-        int32_t u[14], fid[14];
-        int m = cell_unknowns(K, u);
-        for (int a = 0, lf = 0; a < m; ++a) {
-            fid[a] = -1;
-            if (a >= 8) {
-                while (!(S.fmask[K] >> lf & 1)) ++lf;
-                fid[a] = S.cell_frac[6 * (size_t)K + lf++];
+    for (int32_t G = 0; G < S.ngroup; ++G) {
+        const int32_t g = S.grp_ptr[G + 1] - S.grp_ptr[G];
+        const int32_t W = g + S.grp_nptr[G + 1] - S.grp_nptr[G];
+        for (int32_t q = S.grp_ptr[G]; q < S.grp_ptr[G + 1]; ++q) {
+            const int32_t f = S.grp_face[q];
+            for (int side = 0; side < 2; ++side) {
+                const int32_t K = S.frac_cell[2 * (size_t)f + side];
+                if (K < 0) continue;
+                const int m = cm[K];
+                const int a = face_local(K, f);
+                const int32_t *u = cu.data() + 14 * (size_t)K;
+                int32_t *out = S.slots.data() + S.slot_ptr[K] + a * m;
+                for (int b = 0; b < m; ++b) {
+                    if (u[b] < 0) {
+                        out[b] = -2;
+                        continue;
+                    }
+                    int32_t col;
+                    if (u[b] >= S.nunk) {
+                        col = -1;  // local index of the cell's face at position b
+                        for (int lf = 0, j = 8; lf < 6; ++lf)
+                            if (S.fmask[K] >> lf & 1) {
+                                if (j == b) col = face_loc[S.cell_frac[6 * (size_t)K + lf]];
+                                ++j;
+                            }
+                    } else {
+                        col = g + node_local(G, u[b]);
+                    }
+                    const int64_t off = S.grp_off[G] + (int64_t)face_loc[f] * W + col;
+                    if (off >= INT32_MAX) throw Error(VAG_ERR_UNSUPPORTED, "fracture-face groups too large");
+                    out[b] = (int32_t)off;
+                }
             }
         }
-        int32_t *out = S.slots.data() + S.slot_ptr[K];
-        for (int a = 0; a < m; ++a)
-            for (int b = 0; b < m; ++b) {
-                int32_t v;
-                if (u[a] < 0) {
-                    v = -1;
-                } else if (u[b] < 0) {
-                    v = -2;
-                } else if (u[a] >= S.nunk) {
-                    const int32_t G = face_grp[fid[a]];
-                    const int32_t g = S.grp_ptr[G + 1] - S.grp_ptr[G];
-                    const int32_t W = g + S.grp_nptr[G + 1] - S.grp_nptr[G];
-                    const int32_t col = u[b] >= S.nunk ? face_loc[fid[b]] : g + node_local(G, u[b]);
-                    const int64_t off = S.grp_off[G] + (int64_t)face_loc[fid[a]] * W + col;
-                    if (off >= INT32_MAX) throw Error(VAG_ERR_UNSUPPORTED, "fracture-face groups too large");
-                    v = (int32_t)off;
-                } else if (u[b] >= S.nunk) {
-                    v = -1;
-                } else {
-                    v = sell_pos(u[a], u[b]);
-                }
-                out[a * m + b] = v;
-            }
     }
     // system positions of the node pairs of each group
     S.grp_pos.resize(S.grp_poff[S.ngroup]);
-    for (int32_t G = 0; G < S.ngroup; ++G) {
-        const int32_t m = S.grp_nptr[G + 1] - S.grp_nptr[G];
-        const int32_t *B = S.grp_node.data() + S.grp_nptr[G];
-        for (int32_t p = 0; p < m; ++p)
-            for (int32_t q = 0; q < m; ++q) S.grp_pos[S.grp_poff[G] + (int64_t)p * m + q] = sell_pos(B[p], B[q]);
+    {
+        std::vector<int32_t> posmap((size_t)S.nunk, -1);
+        for (int32_t G = 0; G < S.ngroup; ++G) {
+            const int32_t m = S.grp_nptr[G + 1] - S.grp_nptr[G];
+            const int32_t *B = S.grp_node.data() + S.grp_nptr[G];
+            for (int32_t p = 0; p < m; ++p) {
+                const int32_t r = B[p];
+                for (int32_t q = S.row_ptr[r]; q < S.row_ptr[r + 1]; ++q) posmap[S.col[q]] = q;
+                for (int32_t q = 0; q < m; ++q) {
+                    if (posmap[B[q]] < 0) throw Error(VAG_ERR_ARG, "internal: pattern misses a group entry");
+                    S.grp_pos[S.grp_poff[G] + (int64_t)p * m + q] = S.csr2sell[posmap[B[q]]];
+                }
+                for (int32_t q = S.row_ptr[r]; q < S.row_ptr[r + 1]; ++q) posmap[S.col[q]] = -1;
+            }
+        }
     }
 
     // greedy colouring: cells sharing a node get different colours

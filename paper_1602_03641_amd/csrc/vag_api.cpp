@@ -5,6 +5,7 @@
 #include <cstring>
 
 #include "amg.h"
+#include "gmres.h"
 #include "vag_internal.h"
 
 using namespace vag;
@@ -50,6 +51,11 @@ struct vag_handle {
     Amg amg;
     DBuf<float> b32, x32, r32, z32, p32, q32;  // inner single-precision solve (VAG_MIXED)
     DBuf<double> dsc, As;                      // D^-1/2 and the scaled matrix D^-1/2 A D^-1/2
+    // GMRES(m) work: FP64 basis (VAG_FP64 / VAG_MIXED) or FP32 basis (inner solves of VAG_MIXED_IR)
+    DBuf<double> gmV, gmw, gmt, gmparts, gmnparts, gmhd;
+    DBuf<float> gmV32, gmw32, gmt32;
+    double *h_gm = nullptr;
+    int h_gm_m = 0;
     int last_outer = 1, last_inner = 0;
     PcgState *h_pcg = nullptr;
     double *h_scal = nullptr;
@@ -63,6 +69,7 @@ struct vag_handle {
         if (h_pcg) (void)hipHostFree(h_pcg);
         if (h_scal) (void)hipHostFree(h_scal);
         if (h_cnt) (void)hipHostFree(h_cnt);
+        if (h_gm) (void)hipHostFree(h_gm);
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
     }
@@ -137,7 +144,9 @@ void check_options(const vag_options &o) {
         throw Error(VAG_ERR_UNSUPPORTED, "mixed precision needs the AMG preconditioner");
     if (o.precision == VAG_MIXED_IR && !(o.inner_rtol > 0 && o.inner_rtol < 1))
         throw Error(VAG_ERR_ARG, "inner_rtol must lie in (0, 1)");
-    if (o.krylov != VAG_CG) throw Error(VAG_ERR_UNSUPPORTED, "only VAG_CG is implemented in this build");
+    if (o.krylov != VAG_CG && o.krylov != VAG_GMRES) throw Error(VAG_ERR_ARG, "unknown Krylov method");
+    if (o.krylov == VAG_GMRES && (o.gmres_restart < 1 || o.gmres_restart > 1024))
+        throw Error(VAG_ERR_ARG, "gmres_restart must lie in [1, 1024]");
     if (o.precond != VAG_PC_JACOBI && o.precond != VAG_PC_AMG)
         throw Error(VAG_ERR_ARG, "unknown preconditioner");
 }
@@ -230,6 +239,55 @@ void run_pcg(vag_handle *h) {
     h->last_outer = 1;
 }
 
+// Scratch of GMRES(m) on n unknowns with vectors of type T.
+template <class T>
+GmresWork<T> gmres_work(vag_handle *h, int32_t n, DBuf<T> &V, DBuf<T> &w, DBuf<T> &t) {
+    const int m = h->opt.gmres_restart;
+    Tracker &tr = h->tr;
+    ensure(V, (size_t)(m + 1) * (size_t)std::max(n, 1), tr);
+    ensure(w, (size_t)std::max(n, 1), tr);
+    ensure(t, (size_t)std::max(n, 1), tr);
+    ensure(h->gmparts, (size_t)(m + 1) * gmres_grid(n), tr);
+    ensure(h->gmnparts, (size_t)gmres_grid(n), tr);
+    ensure(h->gmhd, (size_t)3 * (m + 1) + 1, tr);
+    if (h->h_gm_m < m) {
+        if (h->h_gm) VAG_HIP(hipHostFree(h->h_gm));
+        h->h_gm = nullptr;
+        VAG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_gm), (3 * (size_t)(m + 1) + 1) * sizeof(double)));
+        h->h_gm_m = m;
+    }
+    GmresWork<T> W;
+    W.V = V.p;
+    W.w = w.p;
+    W.t = t.p;
+    W.parts = h->gmparts.p;
+    W.nparts = h->gmnparts.p;
+    W.hd = h->gmhd.p;
+    W.hh = h->h_gm;
+    return W;
+}
+
+// Right-preconditioned GMRES(m) from x = 0 in FP64 (the preconditioner may be
+// the FP32 hierarchy of VAG_MIXED).
+void run_gmres(vag_handle *h) {
+    hipStream_t s = h->stream;
+    const int32_t n = h->S.nunk;
+    const GmresWork<double> W = gmres_work<double>(h, n, h->gmV, h->gmw, h->gmt);
+    launch_fill(s, n, 0.0, h->x.p);
+    launch_residual_norm(s, h->Asell(), h->x.p, h->b.p, h->r.p, h->rparts.p, h->scal.p);
+    VAG_HIP(hipMemcpyAsync(h->h_scal, h->scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    VAG_HIP(hipStreamSynchronize(s));
+    const double tol = h->opt.rtol * std::sqrt(h->h_scal[1]);
+    const GmresResult R = gmres_solve<double, double>(
+        s, h->Asell(), h->b.p, h->x.p, tol, h->opt.gmres_restart, h->opt.max_iter, W,
+        [&](const double *in, double *out) { precond_apply(h, in, out, nullptr); });
+    h->h_pcg->iter = R.iterations;
+    h->h_pcg->converged = R.converged;
+    h->h_pcg->done = 1;
+    h->last_inner = R.iterations;
+    h->last_outer = 1;
+}
+
 // FP64 iterative refinement: r = b - A x in FP64.  With S = D^-1/2 the
 // correction solves (S A S) d = S r / ||S r|| by CG in FP32 with the FP32
 // hierarchy of S A S to inner_rtol, then x += ||S r|| S d in FP64.  The scaling
@@ -257,6 +315,22 @@ void run_mixed(vag_handle *h) {
         ++outer;
         launch_scaled_norm(s, n, h->dsc.p, h->r.p, h->rparts.p, h->scal.p + 2);
         launch_scale_to_float(s, n, h->dsc.p, h->r.p, h->scal.p + 2, h->b32.p);
+        if (h->opt.krylov == VAG_GMRES) {
+            // inner FP32 GMRES(m) on the scaled system, ||b32|| = 1
+            const GmresWork<float> W = gmres_work<float>(h, n, h->gmV32, h->gmw32, h->gmt32);
+            VAG_HIP(hipMemsetAsync(h->x32.p, 0, (size_t)n * sizeof(float), s));
+            const GmresResult R = gmres_solve<float, float>(
+                s, A32, h->b32.p, h->x32.p, h->opt.inner_rtol, h->opt.gmres_restart, h->opt.max_iter - inner_total,
+                W, [&](const float *in, float *out) { h->amg.apply32(s, in, out, nullptr); });
+            inner_total += std::max(R.iterations, 1);
+            launch_correct(s, n, h->x.p, h->dsc.p, h->x32.p, h->scal.p + 2);
+            launch_residual_norm(s, h->Asell(), h->x.p, h->b.p, h->r.p, h->rparts.p, h->scal.p);
+            VAG_HIP(hipMemcpyAsync(h->h_scal, h->scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            VAG_HIP(hipStreamSynchronize(s));
+            rr = h->h_scal[0];
+            converged = (rr <= tol2);
+            continue;
+        }
         launch_pcg_init_plain<float>(s, n, h->b32.p, h->x32.p, h->r32.p, P);
         h->amg.apply32(s, h->r32.p, h->z32.p, nullptr);
         launch_pcg_dot_rz<float>(s, n, -1, h->r32.p, h->z32.p, P, nullptr);
@@ -309,7 +383,7 @@ vag_status vag_default_options(vag_options *o) {
     o->gmres_restart = 100;
     o->check_every = 16;
     o->cfl = 0.9;
-    o->amg_coarse_size = 500;
+    o->amg_coarse_size = 128;
     o->amg_max_levels = 12;
     o->amg_theta = 0.02;
     o->amg_sweeps = 1;
@@ -487,6 +561,12 @@ vag_status vag_set_fluxes(vag_handle *h, const double *F_cell, const double *F_c
     });
 }
 
+vag_status vag_set_stream(vag_handle *h, void *hip_stream) {
+    if (!h) return VAG_ERR_ARG;
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return VAG_OK;
+}
+
 vag_status vag_set_options(vag_handle *h, const vag_options *opt) {
     if (!h || !opt) return VAG_ERR_ARG;
     return guard(h, [&] {
@@ -542,6 +622,8 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
         // 3. Krylov
         if (h->opt.precision == VAG_MIXED_IR)
             run_mixed(h);
+        else if (h->opt.krylov == VAG_GMRES)
+            run_gmres(h);
         else
             run_pcg(h);
         VAG_HIP(hipEventRecord(h->ev[3], s));
@@ -799,17 +881,54 @@ vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms)
     });
 }
 
-vag_status vag_amg_levels(vag_handle *h, int *nlev, int64_t *rows, int64_t *stored, int max_levels) {
+vag_status vag_amg_levels(vag_handle *h, int *nlev, int64_t *rows, int64_t *nnz, int64_t *stored, int max_levels) {
     if (!h || !nlev) return VAG_ERR_ARG;
-    *nlev = h->opt.precond == VAG_PC_AMG ? h->amg.nlev : 0;
-    for (int l = 0; l < *nlev && l < max_levels; ++l) {
-        if (rows) rows[l] = h->amg.L[l]->n;
-        if (stored) stored[l] = h->amg.L[l]->stored;
-    }
-    return VAG_OK;
+    return guard(h, [&] {
+        *nlev = h->opt.precond == VAG_PC_AMG && h->solved ? h->amg.nlev : 0;
+        std::vector<unsigned long long> cnt(std::max(*nlev, 1), 0);
+        if (*nlev > 1 && nnz) {
+            VAG_HIP(hipMemcpyAsync(cnt.data(), h->amg.level_nnz.p, *nlev * sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, h->stream));
+            VAG_HIP(hipStreamSynchronize(h->stream));
+        }
+        for (int l = 0; l < *nlev && l < max_levels; ++l) {
+            if (rows) rows[l] = h->amg.L[l]->n;
+            if (stored) stored[l] = h->amg.L[l]->stored;
+            if (nnz) nnz[l] = l == 0 ? h->S.nnz : (int64_t)cnt[l];
+        }
+    });
 }
 
 size_t vag_footprint_bytes(const vag_handle *h) { return h ? h->tr.bytes : 0; }
+
+size_t vag_estimate_footprint(int64_t nn, int64_t nc, int64_t nf, const vag_options *opt) {
+    vag_options o;
+    if (opt) o = *opt; else vag_default_options(&o);
+    if (nn <= 0 || nc <= 0 || nf < 0) return 0;
+    const double Nn = (double)nn, Nc = (double)nc, Nf = (double)nf, Nx = Nn + Nf;
+    // system entries: at most 27 per node row plus the couplings of the
+    // fracture faces (face rows, their columns and the group fill); sliced
+    // ELL padding
+    const double nnz = 27.0 * Nn + 64.0 * Nf;
+    const double S = 1.4 * nnz + 4096.0;
+    double b = 0.0;
+    b += 24 * Nn + 97 * Nc + 72 * Nf + 14 * Nn + 12.0 * S / 64;    // topology, adjacency
+    b += 4 * S + 4 * (64 * Nc + 58 * Nf) + 8 * Nc;                 // pattern, slot maps
+    b += 3000.0 * Nf;                                               // fracture-face groups
+    b += 56 * Nc + 24 * Nf + 16 * Nn;                               // rock, fracture, boundary data
+    b += 376 * Nc + 304 * Nf + 8 * S + 16 * Nx;                     // local matrices, system
+    b += 40 * Nx + 64.0 * 1024;                                     // Krylov vectors and partials
+    b += 88 * Nc + 56 * Nf + 16 * Nn;                               // pressures, fluxes, porous volumes
+    const double nrow = Nn + Nc + Nf, tst = 2.0 * (8 * Nc + 6 * Nf) + 64.0 * 16;
+    b += 24 * nrow + 12 * tst + 12 * nrow / 64;                     // transport
+    if (o.precond == VAG_PC_AMG) {
+        double amg = 96 * Nx + 17 * S + 0.15 * (12 * S + 96 * Nx);
+        if (o.precision == VAG_MIXED) amg += 4.6 * S + 40 * Nx;
+        if (o.precision == VAG_MIXED_IR) amg += 8 * S + 8 * Nx + 4.6 * S + 64 * Nx;
+        b += 1.125 * amg + 1.5 * 1024 * 1024;                       // + dense coarsest inverse
+    }
+    return (size_t)(1.15 * b) + ((size_t)1 << 20);
+}
 
 const char *vag_last_error(const vag_handle *h) { return h ? h->err.c_str() : g_create_error.c_str(); }
 

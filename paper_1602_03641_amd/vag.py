@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libvag.so")
 
 VAG_OK, VAG_WARN_NOT_CONVERGED = 0, 1
 VAG_ERR_ARG, VAG_ERR_MESH, VAG_ERR_UNSUPPORTED, VAG_ERR_OOM, VAG_ERR_HIP, VAG_ERR_STATE = -1, -2, -3, -4, -5, -6
+VAG_ERR_TIMEOUT, VAG_ERR_CANCELLED = -7, -8
 VAG_MEM_HOST, VAG_MEM_DEVICE = 0, 1
 VAG_FP64, VAG_MIXED, VAG_MIXED_IR = 0, 1, 2
 VAG_CG, VAG_GMRES = 0, 1
@@ -27,7 +28,8 @@ VAG_PC_JACOBI, VAG_PC_AMG = 0, 1
 VAG_KERNEL_SPMV, VAG_KERNEL_TRANSPORT_STEP, VAG_KERNEL_LOCAL, VAG_KERNEL_PRECOND = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "VAG_OK", 1: "VAG_WARN_NOT_CONVERGED", -1: "VAG_ERR_ARG", -2: "VAG_ERR_MESH",
-                -3: "VAG_ERR_UNSUPPORTED", -4: "VAG_ERR_OOM", -5: "VAG_ERR_HIP", -6: "VAG_ERR_STATE"}
+                -3: "VAG_ERR_UNSUPPORTED", -4: "VAG_ERR_OOM", -5: "VAG_ERR_HIP", -6: "VAG_ERR_STATE",
+                -7: "VAG_ERR_TIMEOUT", -8: "VAG_ERR_CANCELLED"}
 
 vp = C.c_void_p
 
@@ -77,6 +79,37 @@ class vag_transport_info(C.Structure):
         return d
 
 
+class vag_job(C.Structure):
+    _fields_ = [("mesh", C.POINTER(vag_mesh)), ("frac", C.POINTER(vag_fractures)), ("rock", C.POINTER(vag_rock)),
+                ("bc", C.POINTER(vag_bc)), ("opt", C.POINTER(vag_options)), ("n_steps", C.c_int64),
+                ("t_final", C.c_double), ("mesh_key", C.c_uint64),
+                ("u_node", vp), ("u_cell", vp), ("u_frac", vp), ("c_cell", vp), ("c_frac", vp), ("c_node", vp)]
+
+
+class vag_job_result(C.Structure):
+    _fields_ = [("status", C.c_int), ("message", C.c_char * 200), ("solve", vag_solve_info),
+                ("transport", vag_transport_info), ("t_submit", C.c_double), ("t_start", C.c_double),
+                ("t_end", C.c_double), ("worker", C.c_int), ("reused", C.c_int),
+                ("footprint_estimate", C.c_size_t), ("footprint_bytes", C.c_size_t),
+                ("ms_create", C.c_double), ("ms_run", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["message"] = self.message.decode(errors="replace")
+        d["solve"] = self.solve.as_dict()
+        d["transport"] = self.transport.as_dict()
+        return d
+
+
+class vag_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("queued", C.c_int64), ("running", C.c_int64), ("finished", C.c_int64),
+                ("budget", C.c_size_t), ("bytes_in_use", C.c_size_t), ("peak_bytes_in_use", C.c_size_t),
+                ("cached_bytes", C.c_size_t), ("cached_handles", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # name -> (argtypes, restype)
 _SIGS = {
     "vag_version": ([], C.c_char_p),
@@ -84,6 +117,7 @@ _SIGS = {
     "vag_create": ([C.POINTER(vag_mesh), C.POINTER(vag_fractures), C.POINTER(vag_rock), C.POINTER(vag_bc),
                     C.POINTER(vag_options), C.c_int, vp, C.POINTER(vp)], C.c_int),
     "vag_update": ([vp, C.POINTER(vag_rock), C.POINTER(vag_fractures), vp, vp, C.c_int], C.c_int),
+    "vag_set_stream": ([vp, vp], C.c_int),
     "vag_set_options": ([vp, C.POINTER(vag_options)], C.c_int),
     "vag_solve_pressure": ([vp, C.POINTER(vag_solve_info)], C.c_int),
     "vag_transport": ([vp, C.c_int64, C.c_double, vp, vp, vp, C.c_int, C.POINTER(vag_transport_info)], C.c_int),
@@ -95,10 +129,18 @@ _SIGS = {
     "vag_system_size": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "vag_get_system": ([vp, vp, vp, vp, vp, C.c_int], C.c_int),
     "vag_benchmark_kernel": ([vp, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
-    "vag_amg_levels": ([vp, C.POINTER(C.c_int), vp, vp, C.c_int], C.c_int),
+    "vag_amg_levels": ([vp, C.POINTER(C.c_int), vp, vp, vp, C.c_int], C.c_int),
     "vag_footprint_bytes": ([vp], C.c_size_t),
     "vag_last_error": ([vp], C.c_char_p),
     "vag_destroy": ([vp], None),
+    "vag_estimate_footprint": ([C.c_int64, C.c_int64, C.c_int64, C.POINTER(vag_options)], C.c_size_t),
+    "vag_server_create": ([C.c_size_t, C.c_int, C.POINTER(vp)], C.c_int),
+    "vag_server_submit": ([vp, C.POINTER(vag_job), C.POINTER(C.c_uint64)], C.c_int),
+    "vag_server_wait": ([vp, C.c_uint64, C.c_double, C.POINTER(vag_job_result)], C.c_int),
+    "vag_server_cancel": ([vp, C.c_uint64], C.c_int),
+    "vag_server_get_stats": ([vp, C.POINTER(vag_server_stats)], C.c_int),
+    "vag_server_clock": ([vp], C.c_double),
+    "vag_server_destroy": ([vp], None),
 }
 
 _lib = None
@@ -269,12 +311,12 @@ class Handle:
         return ms.value
 
     def amg_levels(self):
+        """[(rows, nonzeros, stored entries)] per level of the last solve's hierarchy."""
         nl = C.c_int()
-        rows = np.zeros(32, np.int64)
-        stored = np.zeros(32, np.int64)
-        self._check(load().vag_amg_levels(self.h, C.byref(nl), rows.ctypes.data_as(C.c_void_p),
-                                          stored.ctypes.data_as(C.c_void_p), 32))
-        return [(int(rows[i]), int(stored[i])) for i in range(nl.value)]
+        rows, nnz, stored = (np.zeros(32, np.int64) for _ in range(3))
+        p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+        self._check(load().vag_amg_levels(self.h, C.byref(nl), p(rows), p(nnz), p(stored), 32))
+        return [(int(rows[i]), int(nnz[i]), int(stored[i])) for i in range(nl.value)]
 
     def footprint_bytes(self):
         return int(load().vag_footprint_bytes(self.h))
@@ -282,3 +324,89 @@ class Handle:
 
 def to_numpy(d):
     return {k: v.detach().cpu().numpy() if hasattr(v, "detach") else v for k, v in d.items()}
+
+
+def estimate_footprint(prob, **opt_kw):
+    o = default_options(**opt_kw)
+    return int(load().vag_estimate_footprint(int(prob.xyz.shape[0]), int(prob.hex8.shape[0]),
+                                             int(np.asarray(prob.frac_nodes).reshape(-1, 4).shape[0]), C.byref(o)))
+
+
+class Server:
+    """Owns a vag_server.  Jobs are problem descriptions (numpy arrays, host
+    memory); results come back as numpy arrays with the job's timing."""
+
+    OUTPUTS = ("u_node", "u_cell", "u_frac", "c_cell", "c_frac", "c_node")
+
+    def __init__(self, hbm_budget=0, n_workers=4):
+        lib = load()
+        s = C.c_void_p()
+        st = lib.vag_server_create(C.c_size_t(int(hbm_budget)), int(n_workers), C.byref(s))
+        if st != VAG_OK:
+            raise VagError(st, "vag_server_create failed")
+        self.s = s
+        self._jobs = {}
+
+    def submit(self, prob, n_steps=0, t_final=0.0, mesh_key=0, outputs=OUTPUTS, **opt_kw):
+        """Queues one job; returns its id.  The server copies the inputs."""
+        nn, nc = int(prob.xyz.shape[0]), int(prob.hex8.shape[0])
+        fn = np.ascontiguousarray(np.asarray(prob.frac_nodes, np.int32).reshape(-1, 4))
+        nf = fn.shape[0]
+        keep = dict(
+            xyz=np.ascontiguousarray(prob.xyz, np.float64), hex8=np.ascontiguousarray(prob.hex8, np.int32), fn=fn,
+            fw=np.ascontiguousarray(prob.frac_width, np.float64), fk=np.ascontiguousarray(prob.frac_perm, np.float64),
+            fp=np.ascontiguousarray(prob.frac_poro, np.float64), perm=np.ascontiguousarray(prob.perm, np.float64),
+            poro=np.ascontiguousarray(prob.poro, np.float64), dir=np.ascontiguousarray(prob.dirichlet, np.uint8),
+            pb=np.ascontiguousarray(prob.p_bar, np.float64), cb=np.ascontiguousarray(prob.c_bar, np.float64))
+        p = lambda a: a.ctypes.data_as(C.c_void_p) if a.size else None  # noqa: E731
+        mesh = vag_mesh(nn, nc, p(keep["xyz"]), p(keep["hex8"]))
+        frac = vag_fractures(nf, p(keep["fn"]), p(keep["fw"]), p(keep["fk"]), p(keep["fp"]))
+        rock = vag_rock(p(keep["perm"]), p(keep["poro"]), float(prob.mu))
+        bc = vag_bc(p(keep["dir"]), p(keep["pb"]), p(keep["cb"]))
+        opt = default_options(**opt_kw)
+        sizes = dict(u_node=nn, u_cell=nc, u_frac=nf, c_cell=nc, c_frac=nf, c_node=nn)
+        outs = {k: np.empty(sizes[k]) for k in outputs}
+        job = vag_job(C.pointer(mesh), C.pointer(frac), C.pointer(rock), C.pointer(bc), C.pointer(opt),
+                      int(n_steps), float(t_final), int(mesh_key),
+                      *[p(outs[k]) if k in outs else None for k in self.OUTPUTS])
+        jid = C.c_uint64()
+        st = load().vag_server_submit(self.s, C.byref(job), C.byref(jid))
+        if st != VAG_OK:
+            raise VagError(st, "vag_server_submit failed")
+        self._jobs[jid.value] = outs  # output buffers stay alive until wait()
+        return jid.value
+
+    def wait(self, job_id, timeout=-1.0):
+        """Result dict (status, timing, solve/transport info, output arrays),
+        or None on timeout."""
+        res = vag_job_result()
+        st = load().vag_server_wait(self.s, C.c_uint64(job_id), float(timeout), C.byref(res))
+        if st == VAG_ERR_TIMEOUT:
+            return None
+        if st != VAG_OK:
+            raise VagError(st, f"vag_server_wait({job_id})")
+        d = res.as_dict()
+        d.update(self._jobs.pop(job_id))
+        return d
+
+    def cancel(self, job_id):
+        return load().vag_server_cancel(self.s, C.c_uint64(job_id))
+
+    def stats(self):
+        st = vag_server_stats()
+        load().vag_server_get_stats(self.s, C.byref(st))
+        return st.as_dict()
+
+    def clock(self):
+        return load().vag_server_clock(self.s)
+
+    def close(self):
+        if getattr(self, "s", None):
+            load().vag_server_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

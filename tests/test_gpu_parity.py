@@ -396,3 +396,65 @@ def test_transport_parity_identical_fluxes(kind):
     gc = vag.to_numpy(h.concentration())
     for k in ("c_cell", "c_frac", "c_node"):
         assert np.abs(gc[k] - oc[k]).max() <= 1e-12, k
+
+
+# ---------------------------------------------------------------------------
+# GMRES(m) with CGS2 (right preconditioning)
+# ---------------------------------------------------------------------------
+def _gmres(**kw):
+    from paper_1602_03641_amd import vag
+    return dict(krylov=vag.VAG_GMRES, **kw)
+
+
+@pytest.mark.parametrize("precond,precision", [("jacobi", "fp64"), ("amg", "fp64"), ("amg", "mixed")])
+def test_gmres_parity(precond, precision):
+    from paper_1602_03641_amd import vag
+    p = synth.random_problem((10, 8, 7), 8, n_patches=6, n_steps=20)
+    pc = vag.VAG_PC_JACOBI if precond == "jacobi" else vag.VAG_PC_AMG
+    pr = vag.VAG_FP64 if precision == "fp64" else vag.VAG_MIXED
+    g = gpu_run(p, rtol=1e-12, max_iter=20000, gmres_restart=100, precond=pc, precision=pr, **_gmres())
+    o = oracle.run(p, rtol=1e-13)
+    assert g["info"]["status"] == 0 and g["info"]["rel_residual"] <= 1e-12
+    compare(p, g, o)
+
+
+def test_gmres_short_restart():
+    """GMRES(5): many restarts, same solution."""
+    from paper_1602_03641_amd import vag
+    p = synth.random_problem((9, 7, 6), 9, n_patches=4, n_steps=10)
+    g = gpu_run(p, rtol=1e-12, max_iter=20000, gmres_restart=5, precond=vag.VAG_PC_AMG, **_gmres())
+    o = oracle.run(p, rtol=1e-13)
+    assert g["info"]["status"] == 0 and g["info"]["iterations"] > 5
+    compare(p, g, o)
+
+
+def oracle_certificate(p, g):
+    """||b - A x|| / ||b|| of the library's pressures in the oracle's own
+    cell-eliminated system (free nodes, every fracture face), in FP64."""
+    A, b = oracle.system(p)
+    free = p.dirichlet == 0
+    x = np.concatenate([g["u_node"][free], g["u_frac"]])
+    return float(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
+
+
+def test_gmres_refinement_fp32_inner():
+    """FP64 refinement around FP32 GMRES with the FP32 hierarchy (the mixed
+    scheme of the 128^3 workload, to its tolerance 1e-8), on a scaled-down
+    instance of its generator: the oracle's own system certifies the result."""
+    from paper_1602_03641_amd import vag
+    p = synth.config3(n=20, n_patches=10)
+    g = gpu_run(p, n_steps=0, rtol=1e-8, inner_rtol=1e-2, max_iter=20000, gmres_restart=60,
+                precond=vag.VAG_PC_AMG, precision=vag.VAG_MIXED_IR, **_gmres())
+    info = g["info"]
+    print(f"gmres ir: {info}")
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-8 and info["outer_iterations"] >= 2
+    assert oracle_certificate(p, g) <= 1.5e-8
+
+
+def test_gmres_matches_cg():
+    from paper_1602_03641_amd import vag
+    p = synth.random_problem((12, 9, 8), 10, n_patches=7, n_steps=0)
+    a = gpu_run(p, rtol=1e-13, max_iter=20000, precond=vag.VAG_PC_AMG)
+    b = gpu_run(p, rtol=1e-13, max_iter=20000, precond=vag.VAG_PC_AMG, **_gmres())
+    assert rel_l2(a["u_node"], b["u_node"]) <= 1e-8
+    assert oracle_certificate(p, b) <= 1e-12

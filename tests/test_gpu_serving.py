@@ -1,0 +1,181 @@
+"""GPU tests of the serving loop (vag_server_*): every job's result is the same
+alone and in the mix (bitwise: a job runs the same kernels in the same order on
+its own handle whatever else is on the device), admission by footprint keeps
+the bytes in use within the budget, the footprint estimate bounds the real
+footprint, cached handles are reused, cancel and out-of-memory rejection.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+OUT = ("u_node", "u_cell", "u_frac", "c_cell", "c_frac", "c_node")
+
+
+def _vag():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_03641_amd import vag
+    return vag
+
+
+def _jobs(k=10):
+    """Mixed sizes, contrasts and fracture counts; several exceed one block."""
+    jobs = []
+    for j in range(k):
+        rng = np.random.default_rng([44, j])
+        n = int(rng.integers(5, 19))
+        dims = (n, int(rng.integers(4, 15)), int(rng.integers(4, 12)))
+        p = synth.random_problem(dims, 100 + j, n_patches=int(rng.integers(1, 9)), n_steps=int(rng.integers(5, 40)))
+        jobs.append(p)
+    return jobs
+
+
+def _opts(mode):
+    from paper_1602_03641_amd import vag
+    if mode == "fp64":
+        return dict(precond=vag.VAG_PC_AMG, precision=vag.VAG_FP64, rtol=1e-10, max_iter=5000)
+    return dict(precond=vag.VAG_PC_AMG, precision=vag.VAG_MIXED, rtol=1e-10, max_iter=5000)
+
+
+def _run(vag, jobs, mode, workers, together, budget=0):
+    srv = vag.Server(hbm_budget=budget, n_workers=workers)
+    try:
+        res = []
+        if together:
+            ids = [srv.submit(p, n_steps=p.n_steps, **_opts(mode)) for p in jobs]
+            res = [srv.wait(i) for i in ids]
+        else:
+            for p in jobs:
+                res.append(srv.wait(srv.submit(p, n_steps=p.n_steps, **_opts(mode))))
+        stats = srv.stats()
+    finally:
+        srv.close()
+    return res, stats
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_alone_equals_mix_bitwise(mode):
+    vag = _vag()
+    jobs = _jobs(10)
+    alone, _ = _run(vag, jobs, mode, workers=1, together=False)
+    mix, stats = _run(vag, jobs, mode, workers=4, together=True)
+    assert stats["finished"] == len(jobs) and stats["bytes_in_use"] == 0
+    overlap = 0
+    for a, m in zip(alone, mix):
+        assert a["status"] == 0 and m["status"] == 0, (a["message"], m["message"])
+        for k in OUT:
+            np.testing.assert_array_equal(a[k], m[k], err_msg=k)
+        assert a["solve"]["iterations"] == m["solve"]["iterations"]
+    # the jobs of the mix did overlap in time
+    iv = sorted((m["t_start"], m["t_end"]) for m in mix)
+    overlap = sum(1 for i in range(1, len(iv)) if iv[i][0] < max(e for _, e in iv[:i]))
+    assert overlap > 0
+    print(f"{mode}: {overlap} of {len(mix)} jobs started while another was running")
+
+
+def test_served_job_matches_handle_and_oracle():
+    vag = _vag()
+    p = synth.random_problem((9, 7, 6), 3, n_patches=5, n_steps=25)
+    srv = vag.Server(n_workers=2)
+    try:
+        r = srv.wait(srv.submit(p, n_steps=p.n_steps, rtol=1e-13, max_iter=20000))
+    finally:
+        srv.close()
+    assert r["status"] == 0
+    h = vag.Handle(p, rtol=1e-13, max_iter=20000)
+    h.solve_pressure()
+    h.transport(n_steps=p.n_steps)
+    d = vag.to_numpy(h.pressure()) | vag.to_numpy(h.concentration())
+    for k in OUT:
+        np.testing.assert_array_equal(r[k], d[k], err_msg=k)
+    o = oracle.run(p, rtol=1e-13)
+    u = o["darcy"]["u_node"]
+    assert np.linalg.norm(r["u_node"] - u) <= 1e-8 * np.linalg.norm(u)
+    assert np.abs(r["c_cell"] - o["c_cell"]).max() <= 1e-10
+
+
+def test_admission_respects_budget():
+    vag = _vag()
+    jobs = _jobs(8)
+    est = [vag.estimate_footprint(p, **_opts("fp64")) for p in jobs]
+    budget = int(2.2 * max(est))
+    res, stats = _run(vag, jobs, "fp64", workers=4, together=True, budget=budget)
+    assert all(r["status"] == 0 for r in res)
+    assert stats["peak_bytes_in_use"] <= budget
+    # at no time did the running jobs' estimates exceed the budget
+    ev = sorted([(r["t_start"], 1, r["footprint_estimate"]) for r in res] +
+                [(r["t_end"], 0, -r["footprint_estimate"]) for r in res])
+    cur = 0
+    for _, _, b in ev:
+        cur += b
+        assert cur <= budget
+
+
+def test_footprint_estimate_bounds_actual():
+    vag = _vag()
+    for mode in ("fp64", "mixed"):
+        for p in _jobs(6) + [synth.config4_job(3, n_range=(20, 28)), synth.config4_job(5, n_range=(40, 48))]:
+            srv = vag.Server(n_workers=1)
+            try:
+                r = srv.wait(srv.submit(p, n_steps=3, **_opts(mode)))
+            finally:
+                srv.close()
+            assert r["status"] == 0
+            assert r["footprint_bytes"] <= r["footprint_estimate"], (p.name, mode, r["footprint_bytes"])
+            if r["footprint_bytes"] > 20e6:  # tightness, once the fixed part no longer dominates
+                assert r["footprint_estimate"] <= 3 * r["footprint_bytes"], (p.name, mode)
+
+
+def test_oom_rejected_at_submit():
+    vag = _vag()
+    p = _jobs(1)[0]
+    srv = vag.Server(hbm_budget=1 << 20, n_workers=1)
+    try:
+        with pytest.raises(vag.VagError) as e:
+            srv.submit(p, n_steps=2)
+        assert e.value.status == vag.VAG_ERR_OOM
+    finally:
+        srv.close()
+
+
+def test_cancel_queued_job():
+    vag = _vag()
+    jobs = _jobs(4)
+    srv = vag.Server(n_workers=1)
+    try:
+        ids = [srv.submit(p, n_steps=p.n_steps) for p in jobs]
+        st = srv.cancel(ids[-1])
+        res = [srv.wait(i) for i in ids]
+    finally:
+        srv.close()
+    if st == vag.VAG_OK:
+        assert res[-1]["status"] == vag.VAG_ERR_CANCELLED and res[-1]["worker"] == -1
+    else:  # it had already started
+        assert st == vag.VAG_ERR_STATE and res[-1]["status"] == 0
+    assert all(r["status"] == 0 for r in res[:-1])
+
+
+def test_cached_handle_reused_with_new_data():
+    vag = _vag()
+    p = synth.random_problem((8, 6, 5), 21, n_patches=4, n_steps=10)
+    q = synth.random_problem((8, 6, 5), 21, n_patches=4, n_steps=10)
+    q.perm = q.perm * 3.0
+    q.p_bar = q.p_bar * 2.0
+    srv = vag.Server(n_workers=2)
+    try:
+        r1 = srv.wait(srv.submit(p, n_steps=10, mesh_key=77, **_opts("fp64")))
+        r2 = srv.wait(srv.submit(q, n_steps=10, mesh_key=77, **_opts("fp64")))
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert r1["reused"] == 0 and r2["reused"] == 1
+    assert st["cached_handles"] == 1
+    fresh, _ = _run(vag, [q], "fp64", workers=1, together=False)
+    for k in OUT:
+        np.testing.assert_array_equal(r2[k], fresh[0][k], err_msg=k)
+    assert not np.array_equal(r1["u_node"], r2["u_node"])
