@@ -80,7 +80,11 @@ def serving_bench(vag, synth, n_jobs, workers, budget, seed=4):
                 while srv.clock() - base < ta:
                     _t.sleep(min(1e-3, max(0.0, ta - (srv.clock() - base))))
                 ids.append(srv.submit(p, n_steps=p.n_steps, **modes[mode]))
-            res = [srv.wait(i) for i in ids]
+            res = []
+            for i in ids:
+                res.append(srv.wait(i))
+                if len(res) % 16 == 0:
+                    log(f"serving {mode}: {len(res)}/{len(ids)} jobs done")
             st = srv.stats()
         finally:
             srv.close()
@@ -99,6 +103,7 @@ def serving_bench(vag, synth, n_jobs, workers, budget, seed=4):
                     mean_iterations=round(float(np.mean([r["solve"]["iterations"] for r in res])), 1),
                     peak_GB=round(st["peak_bytes_in_use"] / 1e9, 2), budget_GB=round(st["budget"] / 1e9, 2))
 
+    log(f"serving: {n_jobs} jobs generated in {gen_s:.1f} s")
     zero = [0.0] * n_jobs
     out = {"jobs": n_jobs, "workers": workers, "job_generation_s": round(gen_s, 1)}
     out["saturation"] = {m: run(m, zero) for m in modes}
@@ -110,21 +115,56 @@ def serving_bench(vag, synth, n_jobs, workers, budget, seed=4):
     return out
 
 
+def log(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def describe(args, prob):
+    n = args.n
+    if args.workload == "config2":
+        return (f"config2: cartesian {n}^3 hexahedra, 4 clipped face fractures, contrast 1e4, "
+                f"{args.krylov.upper()} rtol {prob.rtol:g}, {prob.n_steps} upwind steps")
+    if args.workload == "config3":
+        return (f"config3: jittered {n}^3 hexahedra, lognormal anisotropic tensors, 40 face patches "
+                f"(contrasts 1e2/1e4/1e6), {args.krylov.upper()} rtol {prob.rtol:g}, {prob.n_steps} upwind steps")
+    return (f"config5: jittered {n}^3 hexahedra, lognormal anisotropic tensors, 200 face patches at 1e6, "
+            f"{args.krylov.upper()} rtol {prob.rtol:g}, {prob.n_steps} upwind steps")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precond", choices=["jacobi", "amg"], default=os.environ.get("VAG_BENCH_PRECOND", "amg"))
-    ap.add_argument("--precision", choices=["fp64", "mixed", "mixed_ir"], default="fp64")
-    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--workload", choices=["config2", "config3", "config5"], default="config2",
+                    help="config2: 64^3, 4 clipped fractures (the headline); config3: jittered anisotropic 128^3, "
+                         "40 patches, FP32-AMG GMRES with FP64 refinement; config5: 192^3, 200 patches at 1e6, "
+                         "FP32-AMG CG with FP64 refinement")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "mixed_ir"], default=None)
+    ap.add_argument("--krylov", choices=["cg", "gmres"], default=None)
+    ap.add_argument("--n", type=int, default=None, help="cells per side (default: the workload's)")
     ap.add_argument("--keep-faces", action="store_true", help="fracture faces stay unknowns (no group elimination)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=int(os.environ.get("VAG_BENCH_SERVING_JOBS", "0")),
                     help="config-4 serving stream of this many jobs after the timed steps (0: skip)")
     ap.add_argument("--serving-workers", type=int, default=4)
     ap.add_argument("--serving-budget-gb", type=float, default=0.0, help="0: 80%% of free device memory")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="only copy a buffer of this many MiB 5 times (calibrates the HBM byte counters), then exit")
     args = ap.parse_args()
+    if args.copy_probe_mb > 0:
+        import torch
+        n = args.copy_probe_mb * (1 << 20) // 8
+        src = torch.arange(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 8 * n, "copy_probe_bytes_written": 8 * n, "launches": 5}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is a design note, "
               "not part of this build", file=sys.stderr)
@@ -134,10 +174,18 @@ def main():
     import synth
     from paper_1602_03641_amd import vag
 
-    prob = synth.config2(n=args.n)
-    opts = dict(rtol=prob.rtol, cfl=prob.cfl, max_iter=50000,
+    defaults = {"config2": (64, "fp64", "cg"), "config3": (128, "mixed", "cg"), "config5": (192, "mixed", "cg")}
+    n_def, prec_def, kry_def = defaults[args.workload]
+    args.n = args.n or n_def
+    args.precision = args.precision or prec_def
+    args.krylov = args.krylov or kry_def
+    log(f"generating {args.workload} n={args.n}")
+    prob = getattr(synth, args.workload)(n=args.n)
+    log(f"{len(prob.hex8)} cells, {prob.n_frac} fracture faces; creating the handle")
+    opts = dict(rtol=prob.rtol, cfl=prob.cfl, max_iter=50000, inner_rtol=1e-2, gmres_restart=100,
                 precond=vag.VAG_PC_AMG if args.precond == "amg" else vag.VAG_PC_JACOBI,
                 precision={"fp64": vag.VAG_FP64, "mixed": vag.VAG_MIXED, "mixed_ir": vag.VAG_MIXED_IR}[args.precision],
+                krylov=vag.VAG_GMRES if args.krylov == "gmres" else vag.VAG_CG,
                 eliminate_frac_faces=0 if args.keep_faces else 1)
     t0 = time.perf_counter()
     h = vag.Handle(prob, **opts)
@@ -149,12 +197,16 @@ def main():
         t = h.transport(n_steps=prob.n_steps)
         return s, t
 
+    log(f"symbolic phase and uploads {symbolic_s:.2f} s; warmup")
     for _ in range(args.warmup):
         sinfo, tinfo = step()
+        log(f"warmup step: {sinfo['iterations']} iterations, residual {sinfo['rel_residual']:.2e}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         sinfo, tinfo = step()
+        if args.steps <= 5 or k % 5 == 4:
+            log(f"timed step {k + 1}/{args.steps}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
@@ -181,22 +233,24 @@ def main():
         roofline["other"]["vcycle_GBs"] = round(ab["vcycle"] / (ms_prec * 1e-3) / 1e9, 1)
         roofline["other"]["vcycle_bytes"] = ab["vcycle"]
 
+    log("kernel timings done")
     serving = None
     if args.serving_jobs > 0:
+        log(f"serving stream of {args.serving_jobs} jobs")
         serving = serving_bench(vag, synth, args.serving_jobs, args.serving_workers,
                                 int(args.serving_budget_gb * 1e9))
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "config2":
+        log("oracle baseline")
         cpu = cpu_baseline(prob)
 
     out = {
         "metric": "Darcy+transport solves/sec", "value": round(args.steps / elapsed, 4), "unit": "solves/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"config2: cartesian {args.n}^3 hexahedra, 4 clipped face fractures, "
-                               f"contrast 1e4, CG rtol {prob.rtol:g}, {prob.n_steps} upwind steps",
-                   "precond": args.precond, "precision": args.precision,
+        "config": {"workload": describe(args, prob),
+                   "precond": args.precond, "precision": args.precision, "krylov": args.krylov,
                    "fracture_faces": "kept" if args.keep_faces else "eliminated",
                    "n_unknowns": sinfo["n_unknowns"], "nnz": sinfo["nnz"], "n_frac": prob.n_frac},
         "iterations": sinfo["iterations"], "rel_residual": sinfo["rel_residual"],

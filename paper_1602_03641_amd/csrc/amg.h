@@ -28,16 +28,25 @@ void amg_launch_galerkin(hipStream_t s, Sell<double> A, const int32_t *Jcol, con
 void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t *width, int64_t *ptr,
                        unsigned long long *nnz);
 void amg_launch_slice_tail(hipStream_t s, int32_t n, const int64_t *ptr, int32_t *col, double *val);
-void amg_launch_dense_inverse(hipStream_t s, Sell<double> A, double *D);
+// D = A^-1 (dense, row-major); work holds 128 * A.n doubles
+void amg_launch_dense_inverse(hipStream_t s, Sell<double> A, double *D, double *work);
 template <class V, class X>
 void amg_launch_pre(hipStream_t s, Sell<V> A, const X *dinv, const X *b, X *x, X *r, const PcgState *st);
+// bc = R r; with xc also xc = D_c^-1 bc
 template <class X>
 void amg_launch_restrict(hipStream_t s, int32_t nc, const int32_t *mptr, const int32_t *mrows, const X *r, X *bc,
-                         const PcgState *st);
-// y = x + P e, then out = y + M^-1 (b - A y)
+                         const X *dinv_c, X *xc, const PcgState *st);
+// r = b - A x
+template <class V, class X>
+void amg_launch_resid(hipStream_t s, Sell<V> A, const X *b, const X *x, X *r, const PcgState *st);
+// y = x + P e, then out = y + M^-1 (b - A y); with rz, partials of b . out
 template <class V, class X>
 void amg_launch_post(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, const int32_t *agg,
-                     const X *e, X *y, X *out, const PcgState *st);
+                     const X *e, X *y, X *out, double *rz, const PcgState *st);
+// the same with x = D^-1 b and y formed on the fly (one kernel)
+template <class V, class X>
+void amg_launch_post_fused(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const int32_t *agg, const X *e,
+                           X *out, const PcgState *st);
 template <class X>
 void amg_launch_dense(hipStream_t s, int32_t n, const X *Ainv, const X *b, X *x, const PcgState *st);
 template <class V, class X>
@@ -67,10 +76,10 @@ struct AmgLevel {
 
 struct AmgOptions {
     double theta = 0.02;
-    int coarse_size = 128;
+    int coarse_size = 500;
     int max_levels = 12;
     int mis_rounds = 32;
-    int dense_max = 384;  // Gauss-Jordan in one workgroup: O(n^3), keep n small
+    int dense_max = 1024;
     int coarse_sweeps = 4;
 };
 
@@ -81,7 +90,7 @@ class Amg {
     bool dense = false;
     bool have32 = false;
     double op_complexity = 1.0;
-    DBuf<double> Ainv;
+    DBuf<double> Ainv, gj_work;
     DBuf<float> Ainv32;
     DBuf<unsigned long long> level_nnz;  // entries (without padding) of each coarse level
 
@@ -89,11 +98,18 @@ class Amg {
     void setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, const AmgOptions &o);
     // Single-precision copy of every level (values, smoother, coarse inverse).
     void make_fp32(hipStream_t s, Tracker &tr, const int32_t *A0col);
-    // z = M^-1 r, one V-cycle (FP64 or FP32); st may be null
-    void apply(hipStream_t s, const double *r, double *z, const PcgState *st);
+    // z = M^-1 r, one V-cycle (FP64 or FP32); st may be null.  With x_ready
+    // the caller has already written D^-1 r into L[0]->xa (the first
+    // smoothing iterate); with rz, the last sweep also writes the block
+    // partials of r . z there.
+    void apply(hipStream_t s, const double *r, double *z, const PcgState *st, bool x_ready = false,
+               double *rz = nullptr);
     void apply32(hipStream_t s, const float *r, float *z, const PcgState *st);
     // FP32 matrices, FP64 vectors
-    void apply_mixed(hipStream_t s, const double *r, double *z, const PcgState *st);
+    void apply_mixed(hipStream_t s, const double *r, double *z, const PcgState *st, bool x_ready = false,
+                     double *rz = nullptr);
+    // levels at or below this many rows prolongate and smooth in one kernel
+    static constexpr int32_t kFusedPostRows = 65536;
 
   private:
     DBuf<uint64_t> T_, T1_;
@@ -105,7 +121,7 @@ class Amg {
     int32_t *h_ = nullptr;  // pinned host scratch
     AmgOptions o_;
     template <class V, class X>
-    void cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bool fp32);
+    void cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bool x_ready, double *rz);
 
   public:
     ~Amg();

@@ -17,6 +17,8 @@
 // Smoother: l1-Jacobi, M = diag(sum_j |a_ij|), convergent for any SPD matrix.
 // Cycle: symmetric V-cycle (one pre- and one post-sweep), the coarsest level
 // solved by a dense inverse formed on the device by Gauss-Jordan elimination.
+#include <algorithm>
+
 #include "reduce.h"
 #include "sell.h"
 
@@ -489,30 +491,84 @@ __global__ __launch_bounds__(kAT) void dense_scatter_kernel(Sell<double> A, doub
         for (int64_t q = b0 + (i & 63); q < b1; q += 64) D[i * A.n + A.col[q]] += A.val[q];
     }
 }
-// In-place Gauss-Jordan inversion of an SPD matrix (no pivoting needed), one block.
-__global__ __launch_bounds__(1024) void gauss_jordan_kernel(int32_t n, double *__restrict__ M) {
-    __shared__ double pivrow_inv;
-    for (int32_t p = 0; p < n; ++p) {
-        if (threadIdx.x == 0) pivrow_inv = 1.0 / M[(int64_t)p * n + p];
+// In-place blocked Gauss-Jordan inversion of an SPD matrix (no pivoting
+// needed: every pivot block is a Schur complement of an SPD matrix, hence SPD).
+// With P the next kGJ pivots, R the other indices and B = M[P,P]^-1 the block
+// step is
+//   M[P,P] = B,  M[P,R] = B M[P,R],  M[R,P] = -M[R,P] B,
+//   M[R,R] = M[R,R] + M[R,P]_new M[P,R]_old,
+// done by three kernels: the k x k inverse in LDS (one workgroup), the two
+// panels (old M[P,R] saved aside), the rank-k update of M[R,R].
+constexpr int kGJ = 64;
+
+// B = M[P,P]^-1 in LDS (k <= kGJ), written back in place
+__global__ __launch_bounds__(256) void gj_pivot_kernel(int32_t n, int32_t p0, int32_t k, double *__restrict__ M) {
+    __shared__ double L[kGJ][kGJ + 1];
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) L[e / k][e % k] = M[(int64_t)(p0 + e / k) * n + p0 + e % k];
+    __syncthreads();
+    for (int p = 0; p < k; ++p) {
+        const double pinv = 1.0 / L[p][p];
         __syncthreads();
-        const double pinv = pivrow_inv;
-        // scale pivot row
-        for (int32_t j = threadIdx.x; j < n; j += blockDim.x)
-            if (j != p) M[(int64_t)p * n + j] *= pinv;
-        __syncthreads();
-        // eliminate column p from the other rows: a wavefront per row, lanes along the row
-        for (int32_t i = threadIdx.x >> 6; i < n; i += blockDim.x >> 6) {
-            if (i == p) continue;
-            const double mip = M[(int64_t)i * n + p];
-            for (int32_t j = threadIdx.x & 63; j < n; j += 64)
-                if (j != p) M[(int64_t)i * n + j] -= mip * M[(int64_t)p * n + j];
+        for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+            const int i = e / k, j = e % k;
+            if (i != p && j != p) L[i][j] -= L[i][p] * L[p][j] * pinv;
         }
         __syncthreads();
-        for (int32_t i = threadIdx.x; i < n; i += blockDim.x)
-            if (i != p) M[(int64_t)i * n + p] *= -pinv;
+        for (int e = threadIdx.x; e < k; e += blockDim.x) {
+            if (e != p) {
+                L[e][p] = -L[e][p] * pinv;
+                L[p][e] = L[p][e] * pinv;
+            }
+        }
         __syncthreads();
-        if (threadIdx.x == 0) M[(int64_t)p * n + p] = pinv;
+        if (threadIdx.x == 0) L[p][p] = pinv;
         __syncthreads();
+    }
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) M[(int64_t)(p0 + e / k) * n + p0 + e % k] = L[e / k][e % k];
+}
+
+// saves the panels: oc[l][t] = M[p0+l][t], orow[t][l] = M[t][p0+l] (t outside P)
+__global__ __launch_bounds__(256) void gj_save_kernel(int32_t n, int32_t p0, int32_t k, const double *__restrict__ M,
+                                                      double *__restrict__ oc, double *__restrict__ orow) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)n * k;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = e / k;
+        const int l = (int)(e % k);
+        if (t >= p0 && t < p0 + k) continue;
+        oc[(int64_t)l * n + t] = M[(int64_t)(p0 + l) * n + t];
+        orow[t * k + l] = M[t * n + p0 + l];
+    }
+}
+
+// M[P,t] = B oc[.,t] and M[t,P] = -orow[t,.] B, one (t, l) pair per thread
+__global__ __launch_bounds__(256) void gj_panel_kernel(int32_t n, int32_t p0, int32_t k, double *__restrict__ M,
+                                                       const double *__restrict__ oc,
+                                                       const double *__restrict__ orow) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)n * k;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = e / k;
+        const int l = (int)(e % k);
+        if (t >= p0 && t < p0 + k) continue;
+        double sc = 0.0, sr = 0.0;
+        for (int q = 0; q < k; ++q) {
+            sc += M[(int64_t)(p0 + l) * n + p0 + q] * oc[(int64_t)q * n + t];
+            sr += orow[t * k + q] * M[(int64_t)(p0 + q) * n + p0 + l];
+        }
+        M[(int64_t)(p0 + l) * n + t] = sc;
+        M[t * n + p0 + l] = -sr;
+    }
+}
+
+// M[i][j] += sum_l M[i][p0+l] oc[l][j] for i, j outside P
+__global__ __launch_bounds__(256) void gj_update_kernel(int32_t n, int32_t p0, int32_t k, double *__restrict__ M,
+                                                        const double *__restrict__ oc) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)n * n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / n, j = e % n;
+        if ((i >= p0 && i < p0 + k) || (j >= p0 && j < p0 + k)) continue;
+        double s = M[e];
+        for (int l = 0; l < k; ++l) s += M[i * n + p0 + l] * oc[(int64_t)l * n + j];
+        M[e] = s;
     }
 }
 
@@ -535,10 +591,12 @@ __global__ __launch_bounds__(kAT) void vc_resid_kernel(Sell<V> A, const X *__res
 }
 // b_c[I] = sum of r over aggregate I: one wavefront per coarse row, members
 // strided over the lanes and combined by a fixed shuffle tree
+// With xc, also the first smoothing iterate of the coarse level, xc = D_c^-1 bc.
 template <class X>
 __global__ __launch_bounds__(kAT) void vc_restrict_kernel(int32_t nc, const int32_t *__restrict__ mptr,
                                                           const int32_t *__restrict__ mrows, const X *__restrict__ r,
-                                                          X *__restrict__ bc, const PcgState *st) {
+                                                          X *__restrict__ bc, const X *__restrict__ dinv_c,
+                                                          X *__restrict__ xc, const PcgState *st) {
     if (st && st->done) return;
     const int lane = threadIdx.x & 63;
     const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -548,7 +606,10 @@ __global__ __launch_bounds__(kAT) void vc_restrict_kernel(int32_t nc, const int3
         for (int32_t t = mptr[I] + lane; t < mptr[I + 1]; t += 64) s += r[mrows[t]];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-        if (lane == 0) bc[I] = s;
+        if (lane == 0) {
+            bc[I] = s;
+            if (xc) xc[I] = dinv_c[I] * s;
+        }
     }
 }
 // y = x + P e (injection from the aggregate)
@@ -559,14 +620,37 @@ __global__ __launch_bounds__(kAT) void vc_prolong_kernel(int32_t n, const X *__r
     if (st && st->done) return;
     GS(i, n) y[i] = x[i] + e[agg[i]];
 }
-// out = y + M^-1 (b - A y)
+// out = y + M^-1 (b - A y); with rz, also the block partials of b . out (the
+// CG scalar r.z when this is the last sweep of a V-cycle on level 0)
 template <class V, class X>
 __global__ __launch_bounds__(kAT) void vc_sweep_kernel(Sell<V> A, const X *__restrict__ dinv, const X *__restrict__ b,
-                                                       const X *__restrict__ y, X *__restrict__ out, const PcgState *st) {
+                                                       const X *__restrict__ y, X *__restrict__ out,
+                                                       double *__restrict__ rz, const PcgState *st) {
     if (st && st->done) return;
+    double v[1] = {0.0};
     GS(i, A.n) {
         const X s = sell_row_apply<V, X>(A, (int32_t)i, [&](int32_t j) { return y[j]; });
-        out[i] = y[i] + dinv[i] * (b[i] - s);
+        const X o = y[i] + dinv[i] * (b[i] - s);
+        out[i] = o;
+        v[0] += (double)b[i] * (double)o;
+    }
+    if (rz) {
+        block_reduce<OpSum, 1, kAT>(v);
+        if (threadIdx.x == 0) rz[blockIdx.x] = v[0];
+    }
+}
+// prolongation and sweep in one pass (small levels): y = x + P e with
+// x = D^-1 b formed on the fly, out = y + D^-1 (b - A y)
+template <class V, class X>
+__global__ __launch_bounds__(kAT) void vc_post_fused_kernel(Sell<V> A, const X *__restrict__ dinv,
+                                                            const X *__restrict__ b, const int32_t *__restrict__ agg,
+                                                            const X *__restrict__ e, X *__restrict__ out,
+                                                            const PcgState *st) {
+    if (st && st->done) return;
+    GS(i, A.n) {
+        const X s = sell_row_apply<V, X>(A, (int32_t)i, [&](int32_t j) { return dinv[j] * b[j] + e[agg[j]]; });
+        const X yi = dinv[i] * b[i] + e[agg[i]];
+        out[i] = yi + dinv[i] * (b[i] - s);
     }
 }
 // dense coarse solve x = Ainv b: one wavefront per row, lanes along the
@@ -672,10 +756,20 @@ void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t 
 void amg_launch_slice_tail(hipStream_t s, int32_t n, const int64_t *ptr, int32_t *col, double *val) {
     if (n & 63) ALAUNCH(slice_tail_kernel, 1, 64, n, ptr, col, val);
 }
-void amg_launch_dense_inverse(hipStream_t s, Sell<double> A, double *D) {
-    ALAUNCH(dense_from_sell_kernel, gridv((int64_t)A.n * A.n), kAT, A, D);
-    ALAUNCH(dense_scatter_kernel, gridv(A.n), kAT, A, D);
-    ALAUNCH(gauss_jordan_kernel, 1, 1024, A.n, D);
+void amg_launch_dense_inverse(hipStream_t s, Sell<double> A, double *D, double *work) {
+    const int32_t n = A.n;
+    ALAUNCH(dense_from_sell_kernel, gridv((int64_t)n * n), kAT, A, D);
+    ALAUNCH(dense_scatter_kernel, gridv(n), kAT, A, D);
+    const unsigned gu = (unsigned)std::min<int64_t>(((int64_t)n * n + 255) / 256, 4096);
+    const unsigned gp = (unsigned)std::min<int64_t>(((int64_t)n * kGJ + 255) / 256, 4096);
+    double *oc = work, *orow = work + (int64_t)kGJ * n;
+    for (int32_t p0 = 0; p0 < n; p0 += kGJ) {
+        const int32_t k = std::min(kGJ, n - p0);
+        ALAUNCH(gj_pivot_kernel, 1, 256, n, p0, k, D);
+        ALAUNCH(gj_save_kernel, gp, 256, n, p0, k, D, oc, orow);
+        ALAUNCH(gj_panel_kernel, gp, 256, n, p0, k, D, oc, orow);
+        ALAUNCH(gj_update_kernel, gu, 256, n, p0, k, D, oc);
+    }
 }
 template <class V, class X>
 void amg_launch_pre(hipStream_t s, Sell<V> A, const X *dinv, const X *b, X *x, X *r, const PcgState *st) {
@@ -684,14 +778,23 @@ void amg_launch_pre(hipStream_t s, Sell<V> A, const X *dinv, const X *b, X *x, X
 }
 template <class X>
 void amg_launch_restrict(hipStream_t s, int32_t nc, const int32_t *mptr, const int32_t *mrows, const X *r, X *bc,
-                         const PcgState *st) {
-    ALAUNCH(vc_restrict_kernel<X>, reduce_grid((int64_t)nc * 64, kAT), kAT, nc, mptr, mrows, r, bc, st);
+                         const X *dinv_c, X *xc, const PcgState *st) {
+    ALAUNCH(vc_restrict_kernel<X>, reduce_grid((int64_t)nc * 64, kAT), kAT, nc, mptr, mrows, r, bc, dinv_c, xc, st);
+}
+template <class V, class X>
+void amg_launch_resid(hipStream_t s, Sell<V> A, const X *b, const X *x, X *r, const PcgState *st) {
+    ALAUNCH((vc_resid_kernel<V, X>), gridv(A.n), kAT, A, b, x, r, st);
+}
+template <class V, class X>
+void amg_launch_post_fused(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const int32_t *agg, const X *e,
+                           X *out, const PcgState *st) {
+    ALAUNCH((vc_post_fused_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, agg, e, out, st);
 }
 template <class V, class X>
 void amg_launch_post(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, const int32_t *agg, const X *e,
-                     X *y, X *out, const PcgState *st) {
+                     X *y, X *out, double *rz, const PcgState *st) {
     ALAUNCH(vc_prolong_kernel<X>, gridv(A.n), kAT, A.n, x, agg, e, y, st);
-    ALAUNCH((vc_sweep_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, y, out, st);
+    ALAUNCH((vc_sweep_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, y, out, rz, st);
 }
 template <class X>
 void amg_launch_dense(hipStream_t s, int32_t n, const X *Ainv, const X *b, X *x, const PcgState *st) {
@@ -699,7 +802,7 @@ void amg_launch_dense(hipStream_t s, int32_t n, const X *Ainv, const X *b, X *x,
 }
 template <class V, class X>
 void amg_launch_sweep(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, X *out, const PcgState *st) {
-    ALAUNCH((vc_sweep_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, x, out, st);
+    ALAUNCH((vc_sweep_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, x, out, nullptr, st);
 }
 void launch_to_float(hipStream_t s, int64_t n, const double *a, float *b) {
     if (n > 0) ALAUNCH(to_float_kernel, gridv(n), kAT, n, a, b);
@@ -708,32 +811,23 @@ void launch_to_double(hipStream_t s, int64_t n, const float *a, double *b) {
     if (n > 0) ALAUNCH(to_double_kernel, gridv(n), kAT, n, a, b);
 }
 
-template void amg_launch_pre<double, double>(hipStream_t, Sell<double>, const double *, const double *, double *,
-                                             double *, const PcgState *);
-template void amg_launch_pre<float, double>(hipStream_t, Sell<float>, const double *, const double *, double *,
-                                            double *, const PcgState *);
-template void amg_launch_post<float, double>(hipStream_t, Sell<float>, const double *, const double *,
-                                             const double *, const int32_t *, const double *, double *, double *,
-                                             const PcgState *);
-template void amg_launch_sweep<float, double>(hipStream_t, Sell<float>, const double *, const double *,
-                                              const double *, double *, const PcgState *);
-template void amg_launch_pre<float, float>(hipStream_t, Sell<float>, const float *, const float *, float *, float *,
-                                           const PcgState *);
+#define VC_INST(V, X)                                                                                            \
+    template void amg_launch_pre<V, X>(hipStream_t, Sell<V>, const X *, const X *, X *, X *, const PcgState *);    \
+    template void amg_launch_resid<V, X>(hipStream_t, Sell<V>, const X *, const X *, X *, const PcgState *);       \
+    template void amg_launch_post<V, X>(hipStream_t, Sell<V>, const X *, const X *, const X *, const int32_t *,    \
+                                        const X *, X *, X *, double *, const PcgState *);                          \
+    template void amg_launch_post_fused<V, X>(hipStream_t, Sell<V>, const X *, const X *, const int32_t *,         \
+                                              const X *, X *, const PcgState *);                                   \
+    template void amg_launch_sweep<V, X>(hipStream_t, Sell<V>, const X *, const X *, const X *, X *,               \
+                                         const PcgState *);
+VC_INST(double, double)
+VC_INST(float, double)
+VC_INST(float, float)
 template void amg_launch_restrict<double>(hipStream_t, int32_t, const int32_t *, const int32_t *, const double *,
-                                          double *, const PcgState *);
+                                          double *, const double *, double *, const PcgState *);
 template void amg_launch_restrict<float>(hipStream_t, int32_t, const int32_t *, const int32_t *, const float *,
-                                         float *, const PcgState *);
-template void amg_launch_post<double, double>(hipStream_t, Sell<double>, const double *, const double *,
-                                              const double *, const int32_t *, const double *, double *, double *,
-                                              const PcgState *);
-template void amg_launch_post<float, float>(hipStream_t, Sell<float>, const float *, const float *, const float *,
-                                            const int32_t *, const float *, float *, float *, const PcgState *);
+                                         float *, const float *, float *, const PcgState *);
 template void amg_launch_dense<double>(hipStream_t, int32_t, const double *, const double *, double *,
                                        const PcgState *);
 template void amg_launch_dense<float>(hipStream_t, int32_t, const float *, const float *, float *, const PcgState *);
-template void amg_launch_sweep<double, double>(hipStream_t, Sell<double>, const double *, const double *,
-                                               const double *, double *, const PcgState *);
-template void amg_launch_sweep<float, float>(hipStream_t, Sell<float>, const float *, const float *, const float *,
-                                             float *, const PcgState *);
-
 }  // namespace vag

@@ -100,7 +100,8 @@ void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, co
     }
     if (cl.n <= o.dense_max && cl.n > 0) {
         ensure(Ainv, (size_t)cl.n * cl.n, tr);
-        amg_launch_dense_inverse(s, cl.A, Ainv.p);
+        ensure(gj_work, (size_t)128 * cl.n, tr);
+        amg_launch_dense_inverse(s, cl.A, Ainv.p, gj_work.p);
         dense = true;
     }
 }
@@ -123,9 +124,10 @@ void Amg::make_fp32(hipStream_t s, Tracker &tr, const int32_t *) {
     have32 = true;
 }
 
-// V-cycle on level l: out = M_l^-1 b
+// V-cycle on level l: out = M_l^-1 b.  x_ready: xa already holds D^-1 b (the
+// first smoothing iterate), written by the kernel that produced b.
 template <class V, class X>
-void Amg::cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bool fp32) {
+void Amg::cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bool x_ready, double *rz) {
     AmgLevel &lv = *L[l];
     Sell<V> A;
     const X *dinv;
@@ -147,7 +149,7 @@ void Amg::cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bo
             amg_launch_dense<X>(s, lv.n, Ai, b, out, st);
         } else {
             // a few l1-Jacobi sweeps from zero, ping-ponging between xa and out
-            amg_launch_pre<V, X>(s, A, dinv, b, xa, r, st);
+            if (!x_ready) amg_launch_pre<V, X>(s, A, dinv, b, xa, r, st);
             X *src = xa, *dst = out;
             for (int k = 1; k < o_.coarse_sweeps; ++k) {
                 amg_launch_sweep<V, X>(s, A, dinv, b, src, dst, st);
@@ -158,30 +160,43 @@ void Amg::cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bo
         return;
     }
     AmgLevel &cv = *L[l + 1];
-    X *bc, *ec;
+    X *bc, *ec, *xc;
+    const X *dinv_c;
     if constexpr (sizeof(X) == 4) {
         bc = cv.b32.p;
         ec = cv.xb32.p;
+        xc = cv.xa32.p;
+        dinv_c = cv.dinv32.p;
     } else {
         bc = cv.b.p;
         ec = cv.xb.p;
+        xc = cv.xa.p;
+        dinv_c = cv.dinv.p;
     }
-    amg_launch_pre<V, X>(s, A, dinv, b, xa, r, st);
-    amg_launch_restrict<X>(s, cv.n, lv.mptr.p, lv.mrows.p, r, bc, st);
-    cycle<V, X>(s, l + 1, bc, ec, st, fp32);
-    amg_launch_post<V, X>(s, A, dinv, b, xa, lv.agg.p, ec, r, out, st);  // r reused for y
+    const bool coarse_x = !(l + 1 == nlev - 1 && dense);  // the dense solve needs no iterate
+    if (x_ready)
+        amg_launch_resid<V, X>(s, A, b, xa, r, st);
+    else
+        amg_launch_pre<V, X>(s, A, dinv, b, xa, r, st);
+    amg_launch_restrict<X>(s, cv.n, lv.mptr.p, lv.mrows.p, r, bc, coarse_x ? dinv_c : nullptr,
+                           coarse_x ? xc : nullptr, st);
+    cycle<V, X>(s, l + 1, bc, ec, st, coarse_x, nullptr);
+    if (lv.n <= kFusedPostRows && !rz)
+        amg_launch_post_fused<V, X>(s, A, dinv, b, lv.agg.p, ec, out, st);
+    else
+        amg_launch_post<V, X>(s, A, dinv, b, xa, lv.agg.p, ec, r, out, rz, st);  // r reused for y
 }
 
-void Amg::apply(hipStream_t s, const double *r, double *z, const PcgState *st) {
-    cycle<double, double>(s, 0, r, z, st, false);
+void Amg::apply(hipStream_t s, const double *r, double *z, const PcgState *st, bool x_ready, double *rz) {
+    cycle<double, double>(s, 0, r, z, st, x_ready, rz);
 }
 
 void Amg::apply32(hipStream_t s, const float *r, float *z, const PcgState *st) {
-    cycle<float, float>(s, 0, r, z, st, true);
+    cycle<float, float>(s, 0, r, z, st, false, nullptr);
 }
 
-void Amg::apply_mixed(hipStream_t s, const double *r, double *z, const PcgState *st) {
-    cycle<float, double>(s, 0, r, z, st, true);
+void Amg::apply_mixed(hipStream_t s, const double *r, double *z, const PcgState *st, bool x_ready, double *rz) {
+    cycle<float, double>(s, 0, r, z, st, x_ready, rz);
 }
 
 }  // namespace vag

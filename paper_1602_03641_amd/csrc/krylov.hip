@@ -188,7 +188,8 @@ __global__ __launch_bounds__(kThreads) void pcg_update_kernel(int32_t n, int k, 
 template <class T>
 __global__ __launch_bounds__(kThreads) void pcg_update_xr_kernel(int32_t n, int k, T *__restrict__ x,
                                                                  T *__restrict__ r, const T *__restrict__ p,
-                                                                 const T *__restrict__ q, PcgParts P, PcgState *st) {
+                                                                 const T *__restrict__ q, PcgParts P, PcgState *st,
+                                                                 const T *__restrict__ dinv, T *__restrict__ x0) {
     if (st->done) return;
     const double alpha = sum_parts<OpSum, kThreads>(P.rz(k - 1), P.G) / sum_parts<OpSum, kThreads>(P.pq(), P.G);
     const T a = (T)alpha;
@@ -197,6 +198,7 @@ __global__ __launch_bounds__(kThreads) void pcg_update_xr_kernel(int32_t n, int 
         x[i] += a * p[i];
         const T ri = r[i] - a * q[i];
         r[i] = ri;
+        if (x0) x0[i] = dinv[i] * ri;  // first smoothing iterate of the preconditioner
         v[0] += (double)ri * (double)ri;
     }
     block_reduce<OpSum, 1, kThreads>(v);
@@ -355,8 +357,8 @@ void launch_pcg_update(hipStream_t s, int32_t n, int k, double *x, double *r, do
 }
 template <class T>
 void launch_pcg_update_xr(hipStream_t s, int32_t n, int k, T *x, T *r, const T *p, const T *q, PcgParts P,
-                          PcgState *st) {
-    LAUNCH(pcg_update_xr_kernel<T>, P.G, n, k, x, r, p, q, P, st);
+                          PcgState *st, const T *dinv, T *x0) {
+    LAUNCH(pcg_update_xr_kernel<T>, P.G, n, k, x, r, p, q, P, st, dinv, x0);
 }
 template <class T>
 void launch_pcg_dot_rz(hipStream_t s, int32_t n, int k, const T *r, const T *z, PcgParts P, const PcgState *st) {
@@ -389,7 +391,7 @@ void launch_diag_scaling(hipStream_t s, Sell<double> A, const int32_t *diag_pos,
                                           bool);                                                                  \
     template void launch_pcg_spmv<T, T>(hipStream_t, Sell<T>, const T *, T *, PcgParts, const PcgState *);        \
     template void launch_pcg_update_xr<T>(hipStream_t, int32_t, int, T *, T *, const T *, const T *, PcgParts,   \
-                                          PcgState *);                                                            \
+                                          PcgState *, const T *, T *);                                            \
     template void launch_pcg_dot_rz<T>(hipStream_t, int32_t, int, const T *, const T *, PcgParts,                 \
                                        const PcgState *);                                                         \
     template void launch_pcg_init_plain<T>(hipStream_t, int32_t, const T *, T *, T *, PcgParts);

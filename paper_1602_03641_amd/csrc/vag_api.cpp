@@ -151,8 +151,9 @@ void check_options(const vag_options &o) {
         throw Error(VAG_ERR_ARG, "unknown preconditioner");
 }
 
-// z = M^{-1} r for the handle's preconditioner
-void precond_apply(vag_handle *h, const double *r, double *z, const PcgState *st);
+// z = M^{-1} r for the handle's preconditioner (see Amg::apply for x_ready, rz)
+void precond_apply(vag_handle *h, const double *r, double *z, const PcgState *st, bool x_ready = false,
+                   double *rz = nullptr);
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
     float ms = 0.f;
@@ -163,11 +164,11 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 }  // namespace
 
 namespace {
-void precond_apply(vag_handle *h, const double *r, double *z, const PcgState *st) {
+void precond_apply(vag_handle *h, const double *r, double *z, const PcgState *st, bool x_ready, double *rz) {
     if (h->opt.precond == VAG_PC_AMG && h->opt.precision == VAG_MIXED)
-        h->amg.apply_mixed(h->stream, r, z, st);
+        h->amg.apply_mixed(h->stream, r, z, st, x_ready, rz);
     else if (h->opt.precond == VAG_PC_AMG)
-        h->amg.apply(h->stream, r, z, st);
+        h->amg.apply(h->stream, r, z, st, x_ready, rz);
     else
         launch_jacobi(h->stream, h->S.nunk, h->dinv.p, r, z);
 }
@@ -190,6 +191,7 @@ void run_pcg(vag_handle *h) {
     const PcgParts P{h->parts.p, pcg_grid(n)};
     PcgState *st = h->pcg.p;
     const bool jacobi = h->opt.precond == VAG_PC_JACOBI;
+    const bool fused = !jacobi && h->amg.nlev > 1;
     const Sell<double> A = h->Asell();
     const int max_iter = h->opt.max_iter;
     int k = 0, k0 = 0;
@@ -213,9 +215,17 @@ void run_pcg(vag_handle *h) {
                 if (jacobi) {
                     launch_pcg_update(s, n, k, h->x.p, h->r.p, h->z.p, h->p.p, h->q.p, h->dinv.p, P, st);
                 } else {
-                    launch_pcg_update_xr<double>(s, n, k, h->x.p, h->r.p, h->p.p, h->q.p, P, st);
-                    precond_apply(h, h->r.p, h->z.p, st);
-                    launch_pcg_dot_rz<double>(s, n, k, h->r.p, h->z.p, P, st);
+                    if (fused) {
+                        // the update also writes the V-cycle's first iterate D^-1 r, and
+                        // the V-cycle's last sweep the partials of r.z
+                        launch_pcg_update_xr<double>(s, n, k, h->x.p, h->r.p, h->p.p, h->q.p, P, st,
+                                                     h->amg.L[0]->dinv.p, h->amg.L[0]->xa.p);
+                        precond_apply(h, h->r.p, h->z.p, st, true, P.rz(k));
+                    } else {
+                        launch_pcg_update_xr<double>(s, n, k, h->x.p, h->r.p, h->p.p, h->q.p, P, st);
+                        precond_apply(h, h->r.p, h->z.p, st);
+                        launch_pcg_dot_rz<double>(s, n, k, h->r.p, h->z.p, P, st);
+                    }
                 }
             }
             if (k >= max_iter) launch_pcg_direction<double>(s, n, k, k0, h->z.p, h->p.p, P, st, false);
@@ -383,7 +393,7 @@ vag_status vag_default_options(vag_options *o) {
     o->gmres_restart = 100;
     o->check_every = 16;
     o->cfl = 0.9;
-    o->amg_coarse_size = 128;
+    o->amg_coarse_size = 500;
     o->amg_max_levels = 12;
     o->amg_theta = 0.02;
     o->amg_sweeps = 1;

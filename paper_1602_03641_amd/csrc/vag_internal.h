@@ -219,7 +219,7 @@ void launch_pcg_update(hipStream_t s, int32_t n, int k, double *x, double *r, do
 // same without the preconditioner: partials rr(k) only
 template <class T>
 void launch_pcg_update_xr(hipStream_t s, int32_t n, int k, T *x, T *r, const T *p, const T *q, PcgParts P,
-                          PcgState *st);
+                          PcgState *st, const T *dinv = nullptr, T *x0 = nullptr);
 // partials rz(k) = r.z
 template <class T>
 void launch_pcg_dot_rz(hipStream_t s, int32_t n, int k, const T *r, const T *z, PcgParts P, const PcgState *st);
