@@ -115,6 +115,20 @@ def serving_bench(vag, synth, n_jobs, workers, budget, seed=4):
     return out
 
 
+def pmc_traffic(kernel, workload):
+    """Counter-measured HBM bytes per dispatch of `kernel` (FETCH_SIZE and
+    WRITE_SIZE, calibrated by a copy of known size), from the committed
+    rocprofv3 summary of this workload; None where none was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        cells = [c.strip().strip("`") for c in line.split("|")]
+        if len(cells) > 5 and cells[1] == f"vag::{kernel}":
+            return int(cells[5])
+    return None
+
+
 def log(msg):
     """Progress on stderr (the JSON line alone goes to stdout)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
@@ -224,7 +238,9 @@ def main():
     achieved = ab[dom] / (ms_dom * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "pcg_spmv_kernel" if dom == "spmv" else "transport_step_kernel",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": pmc_traffic("pcg_spmv_kernel<double, double>" if dom == "spmv" else "transport_step_kernel",
+                                       {"config2": "config2_64cubed"}.get(args.workload, "") if args.n == n_def else ""),
                 "bytes_per_launch": ab[dom], "ms_per_launch": ms_dom,
                 "other": {"spmv_GBs": round(ab["spmv"] / (ms_spmv * 1e-3) / 1e9, 1),
                           "transport_step_GBs": round(ab["transport_step"] / (ms_step * 1e-3) / 1e9, 1),

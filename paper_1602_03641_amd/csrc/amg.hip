@@ -317,24 +317,80 @@ __global__ __launch_bounds__(kAT) void agg_col_kernel(Sell<double> A, const int3
 // slot k together, so the passes are coalesced.
 __global__ __launch_bounds__(kAT) void ap_collapse_kernel(Sell<double> A, const int32_t *__restrict__ Jcol,
                                                           int32_t *__restrict__ apJ, double *__restrict__ apv) {
+    constexpr int kSet = 16;  // distinct aggregates kept in registers; more: slow path
     GS(i, A.n) {
         const int64_t b0 = A.ptr[i >> 6] + (i & 63), b1 = A.ptr[(i >> 6) + 1];
         int64_t out = b0;
-        int32_t last = -1;
-        for (;;) {
-            int32_t jm = INT32_MAX;
-            for (int64_t q = b0; q < b1; q += 64) {
-                const int32_t J = Jcol[q];
-                if (J > last && J < jm && A.val[q] != 0.0) jm = J;
+        // one pass: per distinct aggregate, the sum of the row's entries in entry order
+        int32_t J[kSet];
+        double v[kSet];
+        int cnt = 0;
+        bool spill = false;
+#pragma unroll
+        for (int t = 0; t < kSet; ++t) {
+            J[t] = INT32_MAX;
+            v[t] = 0.0;
+        }
+        for (int64_t q = b0; q < b1 && !spill; q += 64) {
+            const double a = A.val[q];
+            if (a == 0.0) continue;
+            const int32_t c = Jcol[q];
+            bool found = false;
+#pragma unroll
+            for (int t = 0; t < kSet; ++t)
+                if (J[t] == c) {
+                    v[t] += a;
+                    found = true;
+                }
+            if (!found) {
+                if (cnt == kSet) {
+                    spill = true;
+                } else {
+#pragma unroll
+                    for (int t = 0; t < kSet; ++t)
+                        if (t == cnt) {
+                            J[t] = c;
+                            v[t] = a;
+                        }
+                    ++cnt;
+                }
             }
-            if (jm == INT32_MAX) break;
-            double sum = 0.0;
-            for (int64_t q = b0; q < b1; q += 64)
-                if (Jcol[q] == jm) sum += A.val[q];
-            apJ[out] = jm;
-            apv[out] = sum;
-            out += 64;
-            last = jm;
+        }
+        if (!spill) {
+            // ascending aggregate order (selection of the next larger key)
+            int32_t last = -1;
+            for (int k = 0; k < cnt; ++k) {
+                int32_t jm = INT32_MAX;
+                double vm = 0.0;
+#pragma unroll
+                for (int t = 0; t < kSet; ++t)
+                    if (J[t] > last && J[t] < jm) {
+                        jm = J[t];
+                        vm = v[t];
+                    }
+                apJ[out] = jm;
+                apv[out] = vm;
+                out += 64;
+                last = jm;
+            }
+        } else {
+            // many distinct aggregates: repeated minimum extraction over the row
+            int32_t last = -1;
+            for (;;) {
+                int32_t jm = INT32_MAX;
+                for (int64_t q = b0; q < b1; q += 64) {
+                    const int32_t c = Jcol[q];
+                    if (c > last && c < jm && A.val[q] != 0.0) jm = c;
+                }
+                if (jm == INT32_MAX) break;
+                double sum = 0.0;
+                for (int64_t q = b0; q < b1; q += 64)
+                    if (Jcol[q] == jm) sum += A.val[q];
+                apJ[out] = jm;
+                apv[out] = sum;
+                out += 64;
+                last = jm;
+            }
         }
         for (; out < b1; out += 64) {
             apJ[out] = (int32_t)i;
@@ -501,30 +557,43 @@ __global__ __launch_bounds__(kAT) void dense_scatter_kernel(Sell<double> A, doub
 // panels (old M[P,R] saved aside), the rank-k update of M[R,R].
 constexpr int kGJ = 64;
 
-// B = M[P,P]^-1 in LDS (k <= kGJ), written back in place
+// B = M[P,P]^-1 in LDS (k <= kGJ), written back in place.  256 threads as a
+// 16 x 16 grid, each owning a 4 x 4 tile of the block.
 __global__ __launch_bounds__(256) void gj_pivot_kernel(int32_t n, int32_t p0, int32_t k, double *__restrict__ M) {
     __shared__ double L[kGJ][kGJ + 1];
-    for (int e = threadIdx.x; e < k * k; e += blockDim.x) L[e / k][e % k] = M[(int64_t)(p0 + e / k) * n + p0 + e % k];
+    __shared__ double colp[kGJ], rowp[kGJ];
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    for (int e = threadIdx.x; e < kGJ * kGJ; e += 256) {
+        const int i = e >> 6, j = e & 63;
+        // identity outside the k x k block keeps the padding inert
+        L[i][j] = (i < k && j < k) ? M[(int64_t)(p0 + i) * n + p0 + j] : (i == j ? 1.0 : 0.0);
+    }
     __syncthreads();
     for (int p = 0; p < k; ++p) {
-        const double pinv = 1.0 / L[p][p];
-        __syncthreads();
-        for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
-            const int i = e / k, j = e % k;
-            if (i != p && j != p) L[i][j] -= L[i][p] * L[p][j] * pinv;
+        if (threadIdx.x < kGJ) {
+            colp[threadIdx.x] = L[threadIdx.x][p];
+        } else if (threadIdx.x < 2 * kGJ) {
+            rowp[threadIdx.x - kGJ] = L[p][threadIdx.x - kGJ];
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < k; e += blockDim.x) {
-            if (e != p) {
-                L[e][p] = -L[e][p] * pinv;
-                L[p][e] = L[p][e] * pinv;
+        const double pinv = 1.0 / colp[p];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int i = ty * 4 + a;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int j = tx * 4 + c;
+                double x = L[i][j];
+                if (i == p && j == p) x = pinv;
+                else if (i == p) x = rowp[j] * pinv;
+                else if (j == p) x = -colp[i] * pinv;
+                else x -= colp[i] * rowp[j] * pinv;
+                L[i][j] = x;
             }
         }
         __syncthreads();
-        if (threadIdx.x == 0) L[p][p] = pinv;
-        __syncthreads();
     }
-    for (int e = threadIdx.x; e < k * k; e += blockDim.x) M[(int64_t)(p0 + e / k) * n + p0 + e % k] = L[e / k][e % k];
+    for (int e = threadIdx.x; e < k * k; e += 256) M[(int64_t)(p0 + e / k) * n + p0 + e % k] = L[e / k][e % k];
 }
 
 // saves the panels: oc[l][t] = M[p0+l][t], orow[t][l] = M[t][p0+l] (t outside P)

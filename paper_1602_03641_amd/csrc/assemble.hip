@@ -19,6 +19,8 @@
 //   fside[nf*2][6] per (fracture face, side): a_{sigma,sigma}, a_{sigma,s} for
 //               the face's 4 nodes in the cell's local face order, r_sigma
 //   A5[nf][25]  fracture 5x5 over (sigma, input nodes 0..3)
+#include <climits>
+
 #include "vag_internal.h"
 
 namespace vag {
@@ -198,118 +200,206 @@ __global__ __launch_bounds__(256) void vag_frac_kernel(int32_t nf, const double 
     area[f] = A;
 }
 
-// Adds v at the position given by a slot code; a Dirichlet column goes to b.
-__device__ inline void put(int32_t slot, double v, int32_t row, double pb, double *__restrict__ A,
-                           double *__restrict__ b) {
-    if (slot >= 0)
-        A[slot] += v;
-    else if (slot == -2)
-        b[row] -= v * pb;
+// ---------------------------------------------------------------------------
+// Assembly of the cell-eliminated system, row by row: the thread of a row
+// gathers the entries of M_K = a - r r^T / A_KK from the cells of its node
+// (or face) and the fracture blocks of its faces, in a fixed order, and adds
+// them at the positions found by binary search in the row's sorted columns.
+// Each row is written by one thread only: no atomics, no colouring, and the
+// summation order does not depend on timing.
+// ---------------------------------------------------------------------------
+
+// vertex index of cell node a on local face f, or -1
+__device__ inline int face_vertex(int f, int a) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (hexf(f, i) == a) return i;
+    return -1;
 }
 
-// Scatters M_K = a - r r^T / A_KK of the cells of one colour.  Rows of an
-// eliminated fracture face go to the dense group blocks Gb instead of A.
-__global__ __launch_bounds__(128) void vag_scatter_kernel(
-    int32_t ncell, const int32_t *__restrict__ cells, int32_t nc, int32_t nsys,
-    const int32_t *__restrict__ hex8, const uint8_t *__restrict__ fmask,
-    const int32_t *__restrict__ cell_frac, const int32_t *__restrict__ frac_cell,
-    const int32_t *__restrict__ frac_slot, const int32_t *__restrict__ frac_nodes,
-    const int32_t *__restrict__ node_unk, const int32_t *__restrict__ frac_unk, const double *__restrict__ p_bar,
-    const double *__restrict__ aK, const double *__restrict__ rK, const double *__restrict__ AKK,
-    const double *__restrict__ fside, const double *__restrict__ A5, const int64_t *__restrict__ slot_ptr,
-    const int32_t *__restrict__ slots, double *__restrict__ A, double *__restrict__ Gb, double *__restrict__ b) {
-    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ncell) return;
-    const int32_t K = cells[t];
-    const unsigned mask = fmask[K];
-    const int m = 8 + __popc(mask);
-    const int32_t *sl = slots + slot_ptr[K];
-    const double inv = 1.0 / AKK[K];
-    int32_t nid[8], row[8];
-    double r[8], pb[8];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-        nid[a] = hex8[8 * (int64_t)K + a];
-        row[a] = node_unk[nid[a]];
-        pb[a] = row[a] < 0 ? p_bar[nid[a]] : 0.0;
-        r[a] = rK[(int64_t)a * nc + K];
+// position of column c in row r (real entries, sorted), -1 if absent
+__device__ inline int64_t sell_find(const AsmArgs &g, int32_t r, int32_t c) {
+    const int64_t base = g.sell_ptr[r >> 6] + (r & 63);
+    int lo = 0, hi = g.row_len[r];
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (g.sell_col[base + 64 * (int64_t)mid] < c) lo = mid + 1; else hi = mid;
     }
-    // node-node block of M_K = a - r r^T / A_KK
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-        if (row[a] < 0) continue;
-#pragma unroll
+    if (lo < g.row_len[r] && g.sell_col[base + 64 * (int64_t)lo] == c) return base + 64 * (int64_t)lo;
+    return -1;
+}
+
+// Adds v to (r, column unknown c) of the system; c < 0: Dirichlet column of
+// node `node`, to the right-hand side; c >= nsys: an eliminated face, held
+// by its group block instead (nothing to do).
+__device__ inline void add_sys(const AsmArgs &g, int32_t r, int32_t c, int32_t node, double v, double &rhs) {
+    if (c < 0) {
+        rhs -= v * g.p_bar[node];
+    } else if (c < g.nsys) {
+        const int64_t q = sell_find(g, r, c);
+        if (q >= 0) g.A[q] += v; else atomicMin(g.bad, INT_MIN);
+    }
+}
+
+__global__ __launch_bounds__(128) void asm_node_rows_kernel(AsmArgs g) {
+    const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= g.nfree) return;
+    const int32_t s = g.unk_node[r];
+    double rhs = 0.0;
+    // cells of the node: row a of M_K
+    for (int32_t q = g.node_cell_ptr[s]; q < g.node_cell_ptr[s + 1]; ++q) {
+        const int32_t K = g.node_cell[q] >> 3;
+        const int a = g.node_cell[q] & 7;
+        const double inv = 1.0 / g.AKK[K];
+        const double ra = g.rK[(int64_t)a * g.nc + K];
         for (int c = 0; c < 8; ++c) {
-            const double v = aK[(int64_t)sym8(a, c) * nc + K] - r[a] * r[c] * inv;
-            put(sl[a * m + c], v, row[a], pb[c], A, b);
+            const int32_t node = g.hex8[8 * (int64_t)K + c];
+            const double v = g.aK[(int64_t)sym8(a, c) * g.nc + K] - ra * g.rK[(int64_t)c * g.nc + K] * inv;
+            add_sys(g, r, g.node_unk[node], node, v, rhs);
+        }
+        const unsigned mask = g.fmask[K];
+        for (int f = 0; f < 6; ++f) {
+            if (!((mask >> f) & 1u)) continue;
+            const int32_t sig = g.cell_frac[6 * (int64_t)K + f];
+            const int sd = g.frac_cell[2 * (int64_t)sig] == K ? 0 : 1;
+            const double *o = g.fside + (2 * (int64_t)sig + sd) * 6;
+            const int i = face_vertex(f, a);
+            const double v = (i >= 0 ? o[1 + i] : 0.0) - ra * o[5] * inv;
+            add_sys(g, r, g.frac_unk[sig], -1, v, rhs);
         }
     }
-    if (!mask) return;
-    // fracture-face rows and columns of M_K
-    double rs[6];
-    int32_t sig[6];
-    int sd[6];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-        rs[f] = 0.0;
-        sig[f] = -1;
-        sd[f] = 0;
-        if ((mask >> f) & 1u) {
-            sig[f] = cell_frac[6 * (int64_t)K + f];
-            sd[f] = (frac_cell[2 * (int64_t)sig[f]] == K) ? 0 : 1;
-            rs[f] = fside[(2 * (int64_t)sig[f] + sd[f]) * 6 + 5];
+    // fracture blocks of the faces the node is a vertex of: row 1+i of the 5x5 block
+    for (int32_t q = g.node_frac_ptr[s]; q < g.node_frac_ptr[s + 1]; ++q) {
+        const int32_t sig = g.node_frac[q] >> 2;
+        const int i = g.node_frac[q] & 3;
+        const double *M = g.A5 + 25 * (int64_t)sig + 5 * (1 + i);
+        add_sys(g, r, g.frac_unk[sig], -1, M[0], rhs);
+        for (int k = 0; k < 4; ++k) {
+            const int32_t node = g.frac_nodes[4 * (int64_t)sig + k];
+            add_sys(g, r, g.node_unk[node], node, M[1 + k], rhs);
         }
     }
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-        if (!((mask >> f) & 1u)) continue;
-        const int j = 8 + __popc(mask & ((1u << f) - 1u));
-        const int32_t frow = frac_unk[sig[f]];
-        double *Af = frow >= nsys ? Gb : A;  // row of sigma
-        const double *o = fside + (2 * (int64_t)sig[f] + sd[f]) * 6;
-        double af[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) af[c] = 0.0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) af[hexf(f, i)] = o[1 + i];
-#pragma unroll
+    g.b[r] += rhs;
+}
+
+// Row of fracture face sig (kept: system row r; eliminated: row of its group
+// block).  blk = null for a kept face.
+__device__ inline void asm_face_row(const AsmArgs &g, int32_t sig, int32_t r, double *blk, int32_t G, double &rhs) {
+    int gsize = 0, W = 0;
+    const int32_t *B = nullptr;
+    int m = 0;
+    if (blk) {
+        gsize = g.grp_ptr[G + 1] - g.grp_ptr[G];
+        m = g.grp_nptr[G + 1] - g.grp_nptr[G];
+        W = gsize + m;
+        B = g.grp_node + g.grp_nptr[G];
+    }
+    // adds v to column unknown c (node `node` or face sig2)
+    auto put = [&](int32_t c, int32_t node, int32_t sig2, double v) {
+        if (!blk) {
+            add_sys(g, r, c, node, v, rhs);
+        } else if (c < 0) {
+            rhs -= v * g.p_bar[node];
+        } else if (c >= g.nsys) {
+            blk[g.face_loc[sig2]] += v;
+        } else {
+            int lo = 0, hi = m;  // free node: its index in the group's sorted node list
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (B[mid] < c) lo = mid + 1; else hi = mid;
+            }
+            if (lo < m && B[lo] == c) blk[gsize + lo] += v; else atomicMin(g.bad, INT_MIN);
+        }
+    };
+    (void)W;
+    for (int side = 0; side < 2; ++side) {
+        const int32_t K = g.frac_cell[2 * (int64_t)sig + side];
+        if (K < 0) continue;
+        int f = 0;
+        while (f < 6 && g.cell_frac[6 * (int64_t)K + f] != sig) ++f;
+        const unsigned mask = g.fmask[K];
+        const double inv = 1.0 / g.AKK[K];
+        const double *o = g.fside + (2 * (int64_t)sig + side) * 6;
+        const double rs = o[5];
         for (int c = 0; c < 8; ++c) {
-            const double v = af[c] - rs[f] * r[c] * inv;
-            put(sl[j * m + c], v, frow, pb[c], Af, b);   // row sigma, column node c
-            put(sl[c * m + j], v, row[c], 0.0, A, b);    // row node c, column sigma (-1: not stored)
+            const int32_t node = g.hex8[8 * (int64_t)K + c];
+            const int i = face_vertex(f, c);
+            const double v = (i >= 0 ? o[1 + i] : 0.0) - rs * g.rK[(int64_t)c * g.nc + K] * inv;
+            put(g.node_unk[node], node, -1, v);
         }
-#pragma unroll
         for (int f2 = 0; f2 < 6; ++f2) {
             if (!((mask >> f2) & 1u)) continue;
-            const int j2 = 8 + __popc(mask & ((1u << f2) - 1u));
-            const double v = (f2 == f ? o[0] : 0.0) - rs[f] * rs[f2] * inv;
-            put(sl[j * m + j2], v, frow, 0.0, Af, b);
+            const int32_t sig2 = g.cell_frac[6 * (int64_t)K + f2];
+            const int sd2 = g.frac_cell[2 * (int64_t)sig2] == K ? 0 : 1;
+            const double v = (f2 == f ? o[0] : 0.0) - rs * g.fside[(2 * (int64_t)sig2 + sd2) * 6 + 5] * inv;
+            put(g.frac_unk[sig2], -1, sig2, v);
         }
-        // fracture block of sigma, added by its lower-index cell:
-        // (sigma,sigma) += R, (sigma,s) = (s,sigma) += -rho_s, (s,s') += a_sigma
-        if (sd[f] == 0) {
-            const double *M = A5 + 25 * (int64_t)sig[f];
-            int q[4];
-            int32_t fn[4];
-            double fpb[4];
-            int32_t frw[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                q[i] = frac_slot[4 * (int64_t)sig[f] + i];
-                fn[i] = frac_nodes[4 * (int64_t)sig[f] + i];
-                frw[i] = node_unk[fn[i]];
-                fpb[i] = frw[i] < 0 ? p_bar[fn[i]] : 0.0;
-            }
-            put(sl[j * m + j], M[0], frow, 0.0, Af, b);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                put(sl[j * m + q[i]], M[1 + i], frow, fpb[i], Af, b);
-                if (frw[i] < 0) continue;
-                put(sl[q[i] * m + j], M[5 * (1 + i)], frw[i], 0.0, A, b);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) put(sl[q[i] * m + q[k]], M[5 * (1 + i) + 1 + k], frw[i], fpb[k], A, b);
-            }
-        }
+    }
+    // fracture block: row 0 of the 5x5 block
+    const double *M = g.A5 + 25 * (int64_t)sig;
+    put(g.frac_unk[sig], -1, sig, M[0]);
+    for (int k = 0; k < 4; ++k) {
+        const int32_t node = g.frac_nodes[4 * (int64_t)sig + k];
+        put(g.node_unk[node], node, -1, M[1 + k]);
+    }
+}
+
+__global__ __launch_bounds__(128) void asm_face_rows_kernel(AsmArgs g, int32_t nkept) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nkept) return;
+    const int32_t r = g.nfree + t;
+    double rhs = 0.0;
+    asm_face_row(g, g.unk_face[t], r, nullptr, -1, rhs);
+    g.b[r] += rhs;
+}
+
+// rows of eliminated faces into the dense group blocks [A_GG | A_GB], b_G
+__global__ __launch_bounds__(128) void asm_elim_rows_kernel(AsmArgs g, int32_t nelim) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nelim) return;
+    const int32_t sig = g.grp_face[t];
+    const int32_t G = g.face_grp[sig];
+    const int gsize = g.grp_ptr[G + 1] - g.grp_ptr[G];
+    const int W = gsize + g.grp_nptr[G + 1] - g.grp_nptr[G];
+    double *blk = g.Gb + g.grp_off[G] + (int64_t)g.face_loc[sig] * W;
+    double rhs = 0.0;
+    asm_face_row(g, sig, -1, blk, G, rhs);
+    g.b[g.frac_unk[sig]] += rhs;
+}
+
+// Fills the sliced-ELL columns from the CSR pattern (one thread per slice
+// lane), the real row lengths and the diagonal positions.
+__global__ __launch_bounds__(256) void sell_fill_kernel(int32_t n, int64_t nslice, const int32_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const int64_t *__restrict__ sell_ptr,
+                                                        int32_t *__restrict__ sell_col, int32_t *__restrict__ row_len,
+                                                        int32_t *__restrict__ diag_pos) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nslice * 64) return;
+    const int64_t sl = t >> 6;
+    const int32_t r = (int32_t)t;
+    const int32_t w = (int32_t)((sell_ptr[sl + 1] - sell_ptr[sl]) / 64);
+    const int32_t len = r < n ? row_ptr[r + 1] - row_ptr[r] : 0;
+    const int32_t pad = r < n ? r : 0;  // padding: own row, value 0
+    int64_t pos = sell_ptr[sl] + (t & 63);
+    for (int32_t k = 0; k < w; ++k, pos += 64) {
+        const int32_t c = k < len ? col[row_ptr[r] + k] : pad;
+        sell_col[pos] = c;
+        if (k < len && c == r) diag_pos[r] = (int32_t)pos;
+    }
+    if (r < n) row_len[r] = len;
+}
+
+// system positions of the node pairs of each eliminated group
+__global__ __launch_bounds__(64) void grp_pos_kernel(AsmArgs g, const int64_t *__restrict__ grp_poff,
+                                                     int32_t *__restrict__ grp_pos) {
+    const int32_t G = blockIdx.x;
+    const int m = g.grp_nptr[G + 1] - g.grp_nptr[G];
+    const int32_t *B = g.grp_node + g.grp_nptr[G];
+    for (int e = threadIdx.x; e < m * m; e += 64) {
+        const int64_t q = sell_find(g, B[e / m], B[e % m]);
+        if (q < 0) atomicMin(g.bad, INT_MIN);
+        grp_pos[grp_poff[G] + e] = q < 0 ? 0 : (int32_t)q;
     }
 }
 
@@ -445,16 +535,26 @@ void launch_frac_local(hipStream_t s, int32_t nf, const double *xyz, const int32
     VAG_HIP(hipGetLastError());
 }
 
-void launch_scatter(hipStream_t s, int32_t ncell_color, const int32_t *cells, int32_t nc, int32_t nsys,
-                    const int32_t *hex8, const uint8_t *fmask, const int32_t *cell_frac,
-                    const int32_t *frac_cell, const int32_t *frac_slot, const int32_t *frac_nodes,
-                    const int32_t *node_unk, const int32_t *frac_unk, const double *p_bar, const double *aK,
-                    const double *rK, const double *AKK, const double *fside, const double *A5,
-                    const int64_t *slot_ptr, const int32_t *slots, double *A, double *Gb, double *b) {
-    if (ncell_color <= 0) return;
-    hipLaunchKernelGGL(vag_scatter_kernel, dim3(nblk(ncell_color, 128)), dim3(128), 0, s, ncell_color,
-                       cells, nc, nsys, hex8, fmask, cell_frac, frac_cell, frac_slot, frac_nodes, node_unk,
-                       frac_unk, p_bar, aK, rK, AKK, fside, A5, slot_ptr, slots, A, Gb, b);
+void launch_assemble(hipStream_t s, const AsmArgs &g, int32_t nkept, int32_t nelim) {
+    if (g.nfree > 0) hipLaunchKernelGGL(asm_node_rows_kernel, dim3(nblk(g.nfree, 128)), dim3(128), 0, s, g);
+    VAG_HIP(hipGetLastError());
+    if (nkept > 0) hipLaunchKernelGGL(asm_face_rows_kernel, dim3(nblk(nkept, 128)), dim3(128), 0, s, g, nkept);
+    VAG_HIP(hipGetLastError());
+    if (nelim > 0) hipLaunchKernelGGL(asm_elim_rows_kernel, dim3(nblk(nelim, 128)), dim3(128), 0, s, g, nelim);
+    VAG_HIP(hipGetLastError());
+}
+
+void launch_sell_fill(hipStream_t s, int32_t n, int64_t nslice, const int32_t *row_ptr, const int32_t *col,
+                      const int64_t *sell_ptr, int32_t *sell_col, int32_t *row_len, int32_t *diag_pos) {
+    if (nslice <= 0) return;
+    hipLaunchKernelGGL(sell_fill_kernel, dim3(nblk(nslice * 64, 256)), dim3(256), 0, s, n, nslice, row_ptr, col,
+                       sell_ptr, sell_col, row_len, diag_pos);
+    VAG_HIP(hipGetLastError());
+}
+
+void launch_grp_pos(hipStream_t s, const AsmArgs &g, int32_t ngroup, const int64_t *grp_poff, int32_t *grp_pos) {
+    if (ngroup <= 0) return;
+    hipLaunchKernelGGL(grp_pos_kernel, dim3(ngroup), dim3(64), 0, s, g, grp_poff, grp_pos);
     VAG_HIP(hipGetLastError());
 }
 

@@ -12,10 +12,9 @@
 //    faces) are pairwise coupled after eliminating u_K, so the pattern is the
 //    union over cells of these cliques, plus the node cliques of the
 //    eliminated groups,
-//  - greedy cell colouring such that cells of one colour share no node: the
-//    assembly scatters one colour at a time without atomics (deterministic),
-//  - per-cell slot maps: position in the CSR values of each local pair,
-//  - node -> (cell, slot) and node -> (fracture, vertex) adjacency.
+//  - sliced-ELL slice pointers of that pattern (the device fills the columns),
+//  - node -> (cell, slot) and node -> (fracture, vertex) adjacency, used by the
+//    row-by-row assembly and by the transport.
 #include <algorithm>
 #include <array>
 #include <exception>
@@ -353,15 +352,6 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
             cm[K] = (uint8_t)m;
         }
     });
-    // local index of fracture face f in cell K
-    auto face_local = [&](int32_t K, int32_t f) {
-        for (int lf = 0, j = 8; lf < 6; ++lf)
-            if (S.fmask[K] >> lf & 1) {
-                if (S.cell_frac[6 * (size_t)K + lf] == f) return j;
-                ++j;
-            }
-        return -1;
-    };
 
     // CSR pattern, rows in unknown order (node rows by node index, then kept
     // faces by face index): row = free node or kept fracture face; a node
@@ -428,7 +418,8 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
     }
     S.nnz = S.row_ptr[S.nunk];
 
-    // sliced ELL copy of the pattern (64-row slices, column-major in a slice)
+    // sliced ELL slice pointers (64-row slices, width = longest row); the
+    // column array itself is filled on the device from the CSR pattern
     {
         const int32_t n = S.nunk;
         const int64_t nslice = (n + kSliceRows - 1) / kSliceRows;
@@ -441,170 +432,17 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
         }
         if (S.sell_ptr[nslice] >= INT32_MAX)
             throw Error(VAG_ERR_UNSUPPORTED, "padded system has more than 2^31 entries");
-        S.sell_col.resize(S.sell_ptr[nslice]);
-        S.csr2sell.resize(S.nnz);
-        parallel_chunks(nslice, [&](int, int64_t s0, int64_t s1) {
-            for (int64_t sl = s0; sl < s1; ++sl) {
-                const int32_t w = (int32_t)((S.sell_ptr[sl + 1] - S.sell_ptr[sl]) / kSliceRows);
-                for (int lane = 0; lane < kSliceRows; ++lane) {
-                    const int64_t r = sl * kSliceRows + lane;
-                    const int32_t len = r < n ? S.row_ptr[r + 1] - S.row_ptr[r] : 0;
-                    const int32_t pad = r < n ? (int32_t)r : 0;  // padding: own row, value 0
-                    int64_t pos = S.sell_ptr[sl] + lane;
-                    for (int32_t k = 0; k < w; ++k, pos += kSliceRows) {
-                        if (k < len) {
-                            S.sell_col[pos] = S.col[S.row_ptr[r] + k];
-                            S.csr2sell[S.row_ptr[r] + k] = (int32_t)pos;
-                        } else {
-                            S.sell_col[pos] = pad;
-                        }
-                    }
-                }
-            }
-        });
-    }
-    S.diag_pos.assign(S.nunk, -1);
-    parallel_chunks(S.nunk, [&](int, int64_t r0, int64_t r1) {
-        for (int32_t r = (int32_t)r0; r < (int32_t)r1; ++r)
-            for (int32_t q = S.row_ptr[r]; q < S.row_ptr[r + 1]; ++q)
-                if (S.col[q] == r) S.diag_pos[r] = S.csr2sell[q];
-    });
-
-    // slot maps, row by row: posmap[c] = CSR index of column c in the row
-    S.slot_ptr.assign((size_t)nc + 1, 0);
-    for (int32_t K = 0; K < nc; ++K) S.slot_ptr[K + 1] = S.slot_ptr[K] + (int64_t)cm[K] * cm[K];
-    S.slots.assign(S.slot_ptr[nc], -1);
-    auto slot_rows = [&](bool faces, int64_t i0, int64_t i1) {
-        std::vector<int32_t> posmap((size_t)S.nunk, -1);
-        auto fill_row = [&](int32_t K, int a) {
-            const int m = cm[K];
-            const int32_t *u = cu.data() + 14 * (size_t)K;
-            int32_t *out = S.slots.data() + S.slot_ptr[K] + a * m;
-            for (int b = 0; b < m; ++b) {
-                const int32_t c = u[b];
-                if (c < 0) out[b] = -2;
-                else if (c >= S.nunk) out[b] = -1;
-                else {
-                    if (posmap[c] < 0) throw Error(VAG_ERR_ARG, "internal: pattern misses an entry");
-                    out[b] = S.csr2sell[posmap[c]];
-                }
-            }
-        };
-        auto set_row = [&](int32_t row, bool on) {
-            for (int32_t q = S.row_ptr[row]; q < S.row_ptr[row + 1]; ++q) posmap[S.col[q]] = on ? q : -1;
-        };
-        for (int64_t i = i0; i < i1; ++i) {
-            if (!faces) {
-                const int32_t s = (int32_t)i, row = S.node_unk[s];
-                if (row < 0) continue;
-                set_row(row, true);
-                for (int32_t q = S.node_cell_ptr[s]; q < S.node_cell_ptr[s + 1]; ++q)
-                    fill_row(S.node_cell[q] >> 3, S.node_cell[q] & 7);
-                set_row(row, false);
-            } else {
-                const int32_t f = (int32_t)i, row = S.frac_unk[f];
-                if (row >= S.nunk) continue;
-                set_row(row, true);
-                for (int side = 0; side < 2; ++side) {
-                    const int32_t K = S.frac_cell[2 * (size_t)f + side];
-                    if (K >= 0) fill_row(K, face_local(K, f));
-                }
-                set_row(row, false);
-            }
-        }
-    };
-    parallel_chunks(nn, [&](int, int64_t i0, int64_t i1) { slot_rows(false, i0, i1); });
-    parallel_chunks(nf, [&](int, int64_t i0, int64_t i1) { slot_rows(true, i0, i1); });
-    // rows of eliminated faces: positions in the dense group blocks
-    auto node_local = [&](int32_t G, int32_t u) {
-        const int32_t *b0 = S.grp_node.data() + S.grp_nptr[G];
-        const int32_t *b1 = S.grp_node.data() + S.grp_nptr[G + 1];
-        return (int32_t)(std::lower_bound(b0, b1, u) - b0);
-    };
-    for (int32_t G = 0; G < S.ngroup; ++G) {
-        const int32_t g = S.grp_ptr[G + 1] - S.grp_ptr[G];
-        const int32_t W = g + S.grp_nptr[G + 1] - S.grp_nptr[G];
-        for (int32_t q = S.grp_ptr[G]; q < S.grp_ptr[G + 1]; ++q) {
-            const int32_t f = S.grp_face[q];
-            for (int side = 0; side < 2; ++side) {
-                const int32_t K = S.frac_cell[2 * (size_t)f + side];
-                if (K < 0) continue;
-                const int m = cm[K];
-                const int a = face_local(K, f);
-                const int32_t *u = cu.data() + 14 * (size_t)K;
-                int32_t *out = S.slots.data() + S.slot_ptr[K] + a * m;
-                for (int b = 0; b < m; ++b) {
-                    if (u[b] < 0) {
-                        out[b] = -2;
-                        continue;
-                    }
-                    int32_t col;
-                    if (u[b] >= S.nunk) {
-                        col = -1;  // local index of the cell's face at position b
-                        for (int lf = 0, j = 8; lf < 6; ++lf)
-                            if (S.fmask[K] >> lf & 1) {
-                                if (j == b) col = face_loc[S.cell_frac[6 * (size_t)K + lf]];
-                                ++j;
-                            }
-                    } else {
-                        col = g + node_local(G, u[b]);
-                    }
-                    const int64_t off = S.grp_off[G] + (int64_t)face_loc[f] * W + col;
-                    if (off >= INT32_MAX) throw Error(VAG_ERR_UNSUPPORTED, "fracture-face groups too large");
-                    out[b] = (int32_t)off;
-                }
-            }
-        }
-    }
-    // system positions of the node pairs of each group
-    S.grp_pos.resize(S.grp_poff[S.ngroup]);
-    {
-        std::vector<int32_t> posmap((size_t)S.nunk, -1);
-        for (int32_t G = 0; G < S.ngroup; ++G) {
-            const int32_t m = S.grp_nptr[G + 1] - S.grp_nptr[G];
-            const int32_t *B = S.grp_node.data() + S.grp_nptr[G];
-            for (int32_t p = 0; p < m; ++p) {
-                const int32_t r = B[p];
-                for (int32_t q = S.row_ptr[r]; q < S.row_ptr[r + 1]; ++q) posmap[S.col[q]] = q;
-                for (int32_t q = 0; q < m; ++q) {
-                    if (posmap[B[q]] < 0) throw Error(VAG_ERR_ARG, "internal: pattern misses a group entry");
-                    S.grp_pos[S.grp_poff[G] + (int64_t)p * m + q] = S.csr2sell[posmap[B[q]]];
-                }
-                for (int32_t q = S.row_ptr[r]; q < S.row_ptr[r + 1]; ++q) posmap[S.col[q]] = -1;
-            }
-        }
     }
 
-    // greedy colouring: cells sharing a node get different colours
-    std::vector<int32_t> color(nc, -1);
-    std::vector<int32_t> seen(64, -1);
-    int ncolor = 0;
-    for (int32_t K = 0; K < nc; ++K) {
-        for (int a = 0; a < 8; ++a) {
-            int32_t s = hex8[8 * (int64_t)K + a];
-            for (int32_t q = S.node_cell_ptr[s]; q < S.node_cell_ptr[s + 1]; ++q) {
-                int32_t L = S.node_cell[q] >> 3;
-                if (color[L] >= 0) {
-                    if (color[L] >= (int)seen.size()) seen.resize(color[L] + 1, -1);
-                    seen[color[L]] = K;
-                }
-            }
-        }
-        int c = 0;
-        while (c < (int)seen.size() && seen[c] == K) ++c;
-        color[K] = c;
-        ncolor = std::max(ncolor, c + 1);
-        if (c >= (int)seen.size()) seen.resize(c + 1, -1);
-    }
-    S.ncolor = ncolor;
-    S.color_ptr.assign(ncolor + 1, 0);
-    for (int32_t K = 0; K < nc; ++K) S.color_ptr[color[K] + 1]++;
-    for (int c = 0; c < ncolor; ++c) S.color_ptr[c + 1] += S.color_ptr[c];
-    S.color_cells.resize(nc);
-    {
-        std::vector<int32_t> fill(S.color_ptr.begin(), S.color_ptr.end() - 1);
-        for (int32_t K = 0; K < nc; ++K) S.color_cells[fill[color[K]]++] = K;
-    }
+    // row -> node or kept face, face -> (group, local index)
+    S.unk_node.assign(nfree, -1);
+    for (int32_t s = 0; s < nn; ++s)
+        if (S.node_unk[s] >= 0) S.unk_node[S.node_unk[s]] = s;
+    S.unk_face.assign(S.nunk - nfree, -1);
+    for (int32_t f = 0; f < nf; ++f)
+        if (S.frac_unk[f] < S.nunk) S.unk_face[S.frac_unk[f] - nfree] = f;
+    S.face_grp = std::move(face_grp);
+    S.face_loc = std::move(face_loc);
 }
 
 }  // namespace vag

@@ -1,6 +1,7 @@
 // C-ABI of libvag: handle lifecycle and orchestration of the device phases.
 // Every entry point catches internal errors and returns a vag_status.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 
@@ -21,14 +22,13 @@ struct vag_handle {
     // topology
     DBuf<double> xyz;
     DBuf<int32_t> hex8, cell_frac, frac_cell, frac_slot, frac_nodes, node_unk, node_cell_ptr, node_cell,
-        node_frac_ptr, node_frac, color_cells, sell_col, diag_pos, slots;
+        node_frac_ptr, node_frac, sell_col, row_len, diag_pos, unk_node, unk_face;
     DBuf<int64_t> sell_ptr;
     // eliminated fracture-face groups
-    DBuf<int32_t> frac_unk, grp_ptr, grp_face, grp_nptr, grp_node, grp_pos;
+    DBuf<int32_t> frac_unk, grp_ptr, grp_face, grp_nptr, grp_node, grp_pos, face_grp, face_loc;
     DBuf<int64_t> grp_off, grp_poff;
     DBuf<double> Gb;
     DBuf<uint8_t> fmask, dirichlet, frac_node;
-    DBuf<int64_t> slot_ptr;
     // numeric inputs
     DBuf<double> perm, poro, fwidth, fperm, fporo, p_bar, c_bar;
     // assembly
@@ -154,6 +154,49 @@ void check_options(const vag_options &o) {
 // z = M^{-1} r for the handle's preconditioner (see Amg::apply for x_ready, rz)
 void precond_apply(vag_handle *h, const double *r, double *z, const PcgState *st, bool x_ready = false,
                    double *rz = nullptr);
+
+// device pointers of the assembly kernels
+AsmArgs asm_args(vag_handle *h) {
+    const Symbolic &S = h->S;
+    AsmArgs g{};
+    g.nc = S.nc;
+    g.nfree = S.nfree;
+    g.nsys = S.nunk;
+    g.hex8 = h->hex8.p;
+    g.node_unk = h->node_unk.p;
+    g.frac_unk = h->frac_unk.p;
+    g.unk_node = h->unk_node.p;
+    g.unk_face = h->unk_face.p;
+    g.node_cell_ptr = h->node_cell_ptr.p;
+    g.node_cell = h->node_cell.p;
+    g.node_frac_ptr = h->node_frac_ptr.p;
+    g.node_frac = h->node_frac.p;
+    g.fmask = h->fmask.p;
+    g.cell_frac = h->cell_frac.p;
+    g.frac_cell = h->frac_cell.p;
+    g.frac_nodes = h->frac_nodes.p;
+    g.aK = h->aK.p;
+    g.rK = h->rK.p;
+    g.AKK = h->AKK.p;
+    g.fside = h->fside.p;
+    g.A5 = h->A5.p;
+    g.p_bar = h->p_bar.p;
+    g.sell_ptr = h->sell_ptr.p;
+    g.sell_col = h->sell_col.p;
+    g.row_len = h->row_len.p;
+    g.grp_ptr = h->grp_ptr.p;
+    g.grp_face = h->grp_face.p;
+    g.grp_nptr = h->grp_nptr.p;
+    g.grp_node = h->grp_node.p;
+    g.face_grp = h->face_grp.p;
+    g.face_loc = h->face_loc.p;
+    g.grp_off = h->grp_off.p;
+    g.A = h->A.p;
+    g.Gb = h->Gb.p;
+    g.b = h->b.p;
+    g.bad = h->bad.p;
+    return g;
+}
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
     float ms = 0.f;
@@ -441,20 +484,31 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         upload_vec(h, h->node_cell, S.node_cell);
         upload_vec(h, h->node_frac_ptr, S.node_frac_ptr);
         upload_vec(h, h->node_frac, S.node_frac);
-        upload_vec(h, h->color_cells, S.color_cells);
         upload_vec(h, h->sell_ptr, S.sell_ptr);
-        upload_vec(h, h->sell_col, S.sell_col);
-        upload_vec(h, h->diag_pos, S.diag_pos);
-        upload_vec(h, h->slot_ptr, S.slot_ptr);
-        upload_vec(h, h->slots, S.slots);
+        upload_vec(h, h->unk_node, S.unk_node);
+        upload_vec(h, h->unk_face, S.unk_face);
         upload_vec(h, h->frac_unk, S.frac_unk);
+        upload_vec(h, h->face_grp, S.face_grp);
+        upload_vec(h, h->face_loc, S.face_loc);
         upload_vec(h, h->grp_ptr, S.grp_ptr);
         upload_vec(h, h->grp_face, S.grp_face);
         upload_vec(h, h->grp_nptr, S.grp_nptr);
         upload_vec(h, h->grp_node, S.grp_node);
-        upload_vec(h, h->grp_pos, S.grp_pos);
         upload_vec(h, h->grp_off, S.grp_off);
         upload_vec(h, h->grp_poff, S.grp_poff);
+        {
+            // sliced-ELL columns from the CSR pattern, on the device
+            DBuf<int32_t> rp, cl;
+            upload_vec(h, rp, S.row_ptr);
+            upload_vec(h, cl, S.col);
+            const int64_t nslice = (int64_t)S.sell_ptr.size() - 1;
+            h->sell_col.alloc(std::max<int64_t>(S.sell_ptr.back(), 1), h->tr);
+            h->row_len.alloc(std::max(S.nunk, 1), h->tr);
+            h->diag_pos.alloc(std::max(S.nunk, 1), h->tr);
+            launch_sell_fill(h->stream, S.nunk, nslice, rp.p, cl.p, h->sell_ptr.p, h->sell_col.p, h->row_len.p,
+                             h->diag_pos.p);
+            VAG_HIP(hipStreamSynchronize(h->stream));
+        }
         h->Gb.alloc(std::max<int64_t>(S.grp_off.back(), 1), h->tr);
 
         upload(h, h->perm, rock->perm, 6 * (size_t)nc, mem);
@@ -479,7 +533,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         h->fside.alloc(12 * (size_t)std::max<int64_t>(nf, 1), h->tr);
         h->A5.alloc(25 * (size_t)std::max<int64_t>(nf, 1), h->tr);
         h->area.alloc(std::max<int64_t>(nf, 1), h->tr);
-        h->A.alloc(S.sell_col.size(), h->tr);
+        h->A.alloc(std::max<int64_t>(S.sell_ptr.back(), 1), h->tr);
         h->b.alloc(n, h->tr);
         h->dinv.alloc(n, h->tr);
         h->bad.alloc(1, h->tr);
@@ -511,7 +565,14 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         VAG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_pcg), sizeof(PcgState)));
         VAG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_scal), 16 * sizeof(double)));
         for (auto &e : h->ev) VAG_HIP(hipEventCreate(&e));
+        // system positions of the eliminated groups' node pairs
+        h->grp_pos.alloc(std::max<int64_t>(S.grp_poff.back(), 1), h->tr);
+        VAG_HIP(hipMemsetAsync(h->bad.p, 0x7f, sizeof(int), h->stream));
+        launch_grp_pos(h->stream, asm_args(h), S.ngroup, h->grp_poff.p, h->grp_pos.p);
+        int bad = 0;
+        VAG_HIP(hipMemcpyAsync(&bad, h->bad.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
         VAG_HIP(hipStreamSynchronize(h->stream));
+        if (bad != 0x7f7f7f7f) throw Error(VAG_ERR_ARG, "internal: a group's node pair is missing from the pattern");
     });
     if (st != VAG_OK) {
         g_create_error = h->err;
@@ -604,11 +665,7 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
         launch_fill(s, (int64_t)h->A.n, 0.0, h->A.p);  // padding stays 0
         launch_fill(s, S.nx, 0.0, h->b.p);
         if (S.ngroup) launch_fill(s, S.grp_off.back(), 0.0, h->Gb.p);
-        for (int c = 0; c < S.ncolor; ++c)
-            launch_scatter(s, S.color_ptr[c + 1] - S.color_ptr[c], h->color_cells.p + S.color_ptr[c], S.nc, S.nunk,
-                           h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->frac_slot.p, h->frac_nodes.p,
-                           h->node_unk.p, h->frac_unk.p, h->p_bar.p, h->aK.p, h->rK.p, h->AKK.p, h->fside.p, h->A5.p,
-                           h->slot_ptr.p, h->slots.p, h->A.p, h->Gb.p, h->b.p);
+        launch_assemble(s, asm_args(h), S.nunk - S.nfree, S.grp_ptr.empty() ? 0 : S.grp_ptr.back());
         // fracture-face groups onto the nodes, colour by colour
         for (int c = 0; c < S.ngcolor; ++c)
             launch_group_elim(s, S.gcolor_ptr[c], S.gcolor_ptr[c + 1] - S.gcolor_ptr[c], S.grp_max_g, S.grp_max_m,
@@ -658,6 +715,7 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
         int bad = 0;
         VAG_HIP(hipMemcpyAsync(&bad, h->bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipStreamSynchronize(s));
+        if (bad == INT_MIN) throw Error(VAG_ERR_ARG, "internal: an assembled entry is missing from the pattern");
         if (bad < 0)
             throw Error(VAG_ERR_ARG, "fracture-face group " + std::to_string(-1 - bad) +
                                          " has a face block that is not positive definite");
@@ -835,7 +893,10 @@ vag_status vag_get_system(vag_handle *h, int64_t *row_ptr, int64_t *col, double 
         std::vector<double> sv(h->A.n), cv(S.nnz);
         VAG_HIP(hipMemcpyAsync(sv.data(), h->A.p, sv.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
         VAG_HIP(hipStreamSynchronize(h->stream));
-        for (int64_t q = 0; q < S.nnz; ++q) cv[q] = sv[S.csr2sell[q]];
+        // entry k of row r sits at sell_ptr[r/64] + 64 k + r%64, in the CSR order
+        for (int32_t r = 0; r < S.nunk; ++r)
+            for (int32_t k = 0; k < S.row_ptr[r + 1] - S.row_ptr[r]; ++k)
+                cv[S.row_ptr[r] + k] = sv[S.sell_ptr[r >> 6] + 64 * (int64_t)k + (r & 63)];
         hipMemcpyKind k = mem == VAG_MEM_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
         if (row_ptr) VAG_HIP(hipMemcpy(row_ptr, rp.data(), rp.size() * sizeof(int64_t), k));
         if (col) VAG_HIP(hipMemcpy(col, cl.data(), cl.size() * sizeof(int64_t), k));

@@ -101,13 +101,10 @@ struct Symbolic {
     std::vector<uint8_t> frac_node;    // [nn] node of some fracture face
     std::vector<int32_t> node_cell_ptr, node_cell;  // node -> cell*8+slot, ascending
     std::vector<int32_t> node_frac_ptr, node_frac;  // node -> frac*4+i, ascending
-    int ncolor = 0;
-    std::vector<int32_t> color_ptr, color_cells;     // cells grouped by colour
-    std::vector<int32_t> row_ptr, col;               // CSR pattern of the eliminated system
-    std::vector<int64_t> sell_ptr;                   // same pattern in sliced ELL
-    std::vector<int32_t> sell_col, csr2sell, diag_pos;  // diag_pos: SELL position of a_ii
-    std::vector<int64_t> slot_ptr;                   // [nc+1]
-    std::vector<int32_t> slots;                      // per cell m*m positions (see below)
+    std::vector<int32_t> row_ptr, col;               // CSR pattern of the eliminated system (sorted rows)
+    std::vector<int64_t> sell_ptr;                   // sliced-ELL slice pointers of that pattern
+    std::vector<int32_t> unk_node, unk_face;         // row -> free node (rows < nfree), -> kept face
+    std::vector<int32_t> face_grp, face_loc;         // [nf] eliminated group of sigma and index in it, or -1
     std::vector<int32_t> frac_unk;                   // [nf] unknown index of sigma (>= nunk: eliminated)
     // Fracture-face groups eliminated onto the nodes: faces linked through a
     // shared cell, ordered by colour (groups of one colour share no free node).
@@ -127,13 +124,6 @@ constexpr int kGroupMaxNodes = 64;
 // Builds the symbolic data; throws vag::Error on invalid input.
 // With eliminate, fracture-face groups within the limits above are
 // eliminated; otherwise every face stays an unknown.
-// Slot codes of a cell's local pair (row a, column b), local order: 8 nodes,
-// then fracture faces by local face index:
-//   >= 0  position in the system values, or, for the row of an eliminated
-//         face, in the dense group blocks;
-//   -1    nothing stored (Dirichlet row, or a node row's column of an
-//         eliminated face, which the group block holds transposed);
-//   -2    Dirichlet column: goes to the right-hand side of the row.
 void build_symbolic(int64_t nn, int64_t nc, int64_t nf, const int32_t *hex8,
                     const int32_t *frac_nodes, const uint8_t *dirichlet, bool eliminate, Symbolic &S);
 
@@ -172,12 +162,28 @@ void launch_local(hipStream_t s, int32_t nc, const double *xyz, const int32_t *h
                   double *aK, double *rK, double *AKK, double *vol, double *fside, int *bad_cell);
 void launch_frac_local(hipStream_t s, int32_t nf, const double *xyz, const int32_t *frac_nodes,
                        const double *width, const double *perm, double mu, double *A5, double *area);
-void launch_scatter(hipStream_t s, int32_t ncell_color, const int32_t *cells, int32_t nc, int32_t nsys,
-                    const int32_t *hex8, const uint8_t *fmask, const int32_t *cell_frac,
-                    const int32_t *frac_cell, const int32_t *frac_slot, const int32_t *frac_nodes,
-                    const int32_t *node_unk, const int32_t *frac_unk, const double *p_bar, const double *aK,
-                    const double *rK, const double *AKK, const double *fside, const double *A5,
-                    const int64_t *slot_ptr, const int32_t *slots, double *A, double *Gb, double *b);
+// Arguments of the row-by-row assembly kernels (device pointers).
+struct AsmArgs {
+    int32_t nc, nfree, nsys;
+    const int32_t *hex8, *node_unk, *frac_unk, *unk_node, *unk_face;
+    const int32_t *node_cell_ptr, *node_cell, *node_frac_ptr, *node_frac;
+    const uint8_t *fmask;
+    const int32_t *cell_frac, *frac_cell, *frac_nodes;
+    const double *aK, *rK, *AKK, *fside, *A5, *p_bar;
+    const int64_t *sell_ptr;
+    const int32_t *sell_col, *row_len;
+    const int32_t *grp_ptr, *grp_face, *grp_nptr, *grp_node, *face_grp, *face_loc;
+    const int64_t *grp_off;
+    double *A, *Gb, *b;
+    int *bad;  // receives INT_MIN if a position is missing from the pattern
+};
+// Node rows, kept-face rows, eliminated-face rows (into the group blocks).
+void launch_assemble(hipStream_t s, const AsmArgs &g, int32_t nkept, int32_t nelim);
+// Sliced-ELL columns, row lengths and diagonal positions from the CSR pattern.
+void launch_sell_fill(hipStream_t s, int32_t n, int64_t nslice, const int32_t *row_ptr, const int32_t *col,
+                      const int64_t *sell_ptr, int32_t *sell_col, int32_t *row_len, int32_t *diag_pos);
+// System positions of the node pairs of each eliminated group.
+void launch_grp_pos(hipStream_t s, const AsmArgs &g, int32_t ngroup, const int64_t *grp_poff, int32_t *grp_pos);
 // Eliminates groups [first, first+ngroup) (one colour) onto the node rows.
 // bad receives -1-G for a group whose face block is not positive definite.
 void launch_group_elim(hipStream_t s, int32_t first, int32_t ngroup, int max_g, int max_m, const int32_t *grp_ptr,
