@@ -160,10 +160,11 @@ def main():
     ap.add_argument("--krylov", choices=["cg", "gmres"], default=None)
     ap.add_argument("--n", type=int, default=None, help="cells per side (default: the workload's)")
     ap.add_argument("--keep-faces", action="store_true", help="fracture faces stay unknowns (no group elimination)")
+    ap.add_argument("--amg-sweeps", type=int, default=0, help="l1-Jacobi sweeps on the coarse levels (0: default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving-jobs", type=int, default=int(os.environ.get("VAG_BENCH_SERVING_JOBS", "0")),
+    ap.add_argument("--serving-jobs", type=int, default=int(os.environ.get("VAG_BENCH_SERVING_JOBS", "256")),
                     help="config-4 serving stream of this many jobs after the timed steps (0: skip)")
-    ap.add_argument("--serving-workers", type=int, default=4)
+    ap.add_argument("--serving-workers", type=int, default=8)
     ap.add_argument("--serving-budget-gb", type=float, default=0.0, help="0: 80%% of free device memory")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only copy a buffer of this many MiB 5 times (calibrates the HBM byte counters), then exit")
@@ -201,6 +202,8 @@ def main():
                 precision={"fp64": vag.VAG_FP64, "mixed": vag.VAG_MIXED, "mixed_ir": vag.VAG_MIXED_IR}[args.precision],
                 krylov=vag.VAG_GMRES if args.krylov == "gmres" else vag.VAG_CG,
                 eliminate_frac_faces=0 if args.keep_faces else 1)
+    if args.amg_sweeps > 0:
+        opts["amg_sweeps"] = args.amg_sweeps
     t0 = time.perf_counter()
     h = vag.Handle(prob, **opts)
     torch.cuda.synchronize()
@@ -251,7 +254,7 @@ def main():
 
     log("kernel timings done")
     serving = None
-    if args.serving_jobs > 0:
+    if args.serving_jobs > 0 and args.workload == "config2":
         log(f"serving stream of {args.serving_jobs} jobs")
         serving = serving_bench(vag, synth, args.serving_jobs, args.serving_workers,
                                 int(args.serving_budget_gb * 1e9))
@@ -275,6 +278,9 @@ def main():
         "symbolic_s": round(symbolic_s, 3),
         "amg_levels": levels,
         "outer_iterations": sinfo["outer_iterations"],
+        "system": {"rows": sinfo["n_unknowns"], "nnz": sinfo["nnz"],
+                   "stored": levels[0][2] if levels else None},
+        "upwind_operator": {"rows": tinfo["n_rows"], "nnz": tinfo["t_nnz"], "stored": tinfo["t_stored"]},
         "roofline": roofline, "cpu_baseline": cpu, "serving": serving,
     }
     print(json.dumps(out), flush=True)

@@ -128,7 +128,8 @@ typedef struct {
     int amg_coarse_size;    /* stop coarsening below this many unknowns */
     int amg_max_levels;
     double amg_theta;       /* strength threshold |a_ij| >= theta sqrt(a_ii a_jj) */
-    int amg_sweeps;         /* pre- and post-smoothing Jacobi sweeps */
+    int amg_sweeps;         /* l1-Jacobi sweeps before and after the coarse correction on
+                               the coarse levels (the finest level has one of each) */
     int eliminate_frac_faces;  /* 1: eliminate fracture-face groups onto the nodes
                                   (fixed at vag_create); 0: faces stay unknowns */
     int reserved[7];
@@ -266,7 +267,8 @@ vag_status vag_system_size(vag_handle *h, int64_t *n, int64_t *nnz);
 
 /* Copies the assembled system (after a solve): CSR row_ptr[n+1], col[nnz]
  * (int64), val[nnz], b[n].  Unknown order: free nodes by node index, then the
- * fracture faces that are not eliminated, by face index. */
+ * fracture faces that are not eliminated, by face index (the device stores the
+ * rows in another order, sorted by length inside windows). */
 vag_status vag_get_system(vag_handle *h, int64_t *row_ptr, int64_t *col, double *val, double *b,
                           vag_mem mem);
 

@@ -80,7 +80,8 @@ struct AmgOptions {
     int max_levels = 12;
     int mis_rounds = 32;
     int dense_max = 1024;
-    int coarse_sweeps = 4;
+    int coarse_sweeps = 4;  // sweeps of the coarsest level when it is not inverted
+    int sweeps = 1;         // sweeps before and after the correction on levels >= 1
 };
 
 class Amg {

@@ -25,12 +25,17 @@
 namespace vag {
 
 constexpr int kAT = 256;
+constexpr int kRzThreads = kKrylovThreads;  // the r.z sweep writes Krylov partials
 constexpr int kCap = 8192;  // candidate entries per coarse row held in LDS
 
 #define GS(i, n) \
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
-static inline unsigned gridv(int64_t n) { return reduce_grid(n, kAT); }
+// full grid for the grid-stride kernels (no reduction partials)
+static inline unsigned gridv(int64_t n) {
+    const int64_t b = (n + kAT - 1) / kAT;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 1 << 20));
+}
 
 __device__ inline uint32_t mix32(uint32_t x) {
     x ^= x >> 16;
@@ -557,43 +562,67 @@ __global__ __launch_bounds__(kAT) void dense_scatter_kernel(Sell<double> A, doub
 // panels (old M[P,R] saved aside), the rank-k update of M[R,R].
 constexpr int kGJ = 64;
 
-// B = M[P,P]^-1 in LDS (k <= kGJ), written back in place.  256 threads as a
-// 16 x 16 grid, each owning a 4 x 4 tile of the block.
+// B = M[P,P]^-1 (k <= kGJ), written back in place.  256 threads as a 16 x 16
+// grid, each keeping a 4 x 4 tile of the (identity-padded) 64 x 64 block in
+// registers; per pivot the owners publish the pivot column and row in LDS
+// (double-buffered, one barrier per pivot).
 __global__ __launch_bounds__(256) void gj_pivot_kernel(int32_t n, int32_t p0, int32_t k, double *__restrict__ M) {
-    __shared__ double L[kGJ][kGJ + 1];
-    __shared__ double colp[kGJ], rowp[kGJ];
+    __shared__ double colp[2][kGJ], rowp[2][kGJ];
     const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-    for (int e = threadIdx.x; e < kGJ * kGJ; e += 256) {
-        const int i = e >> 6, j = e & 63;
-        // identity outside the k x k block keeps the padding inert
-        L[i][j] = (i < k && j < k) ? M[(int64_t)(p0 + i) * n + p0 + j] : (i == j ? 1.0 : 0.0);
-    }
-    __syncthreads();
+    double t[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = ty * 4 + a, j = tx * 4 + c;
+            t[a][c] = (i < k && j < k) ? M[(int64_t)(p0 + i) * n + p0 + j] : (i == j ? 1.0 : 0.0);
+        }
     for (int p = 0; p < k; ++p) {
-        if (threadIdx.x < kGJ) {
-            colp[threadIdx.x] = L[threadIdx.x][p];
-        } else if (threadIdx.x < 2 * kGJ) {
-            rowp[threadIdx.x - kGJ] = L[p][threadIdx.x - kGJ];
+        const int buf = p & 1;
+        // owners of column p and of row p publish them
+        if (tx == (p >> 2)) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (c == (p & 3)) colp[buf][ty * 4 + a] = t[a][c];
+        }
+        if (ty == (p >> 2)) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (a == (p & 3)) rowp[buf][tx * 4 + c] = t[a][c];
         }
         __syncthreads();
-        const double pinv = 1.0 / colp[p];
+        const double pinv = 1.0 / colp[buf][p];
+        double cp[4], rw[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) cp[a] = colp[buf][ty * 4 + a];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) rw[c] = rowp[buf][tx * 4 + c];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             const int i = ty * 4 + a;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int j = tx * 4 + c;
-                double x = L[i][j];
+                double x = t[a][c];
                 if (i == p && j == p) x = pinv;
-                else if (i == p) x = rowp[j] * pinv;
-                else if (j == p) x = -colp[i] * pinv;
-                else x -= colp[i] * rowp[j] * pinv;
-                L[i][j] = x;
+                else if (i == p) x = rw[c] * pinv;
+                else if (j == p) x = -cp[a] * pinv;
+                else x -= cp[a] * rw[c] * pinv;
+                t[a][c] = x;
             }
         }
-        __syncthreads();
     }
-    for (int e = threadIdx.x; e < k * k; e += 256) M[(int64_t)(p0 + e / k) * n + p0 + e % k] = L[e / k][e % k];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = ty * 4 + a, j = tx * 4 + c;
+            if (i < k && j < k) M[(int64_t)(p0 + i) * n + p0 + j] = t[a][c];
+        }
 }
 
 // saves the panels: oc[l][t] = M[p0+l][t], orow[t][l] = M[t][p0+l] (t outside P)
@@ -692,7 +721,7 @@ __global__ __launch_bounds__(kAT) void vc_prolong_kernel(int32_t n, const X *__r
 // out = y + M^-1 (b - A y); with rz, also the block partials of b . out (the
 // CG scalar r.z when this is the last sweep of a V-cycle on level 0)
 template <class V, class X>
-__global__ __launch_bounds__(kAT) void vc_sweep_kernel(Sell<V> A, const X *__restrict__ dinv, const X *__restrict__ b,
+__global__ __launch_bounds__(kRzThreads) void vc_sweep_kernel(Sell<V> A, const X *__restrict__ dinv, const X *__restrict__ b,
                                                        const X *__restrict__ y, X *__restrict__ out,
                                                        double *__restrict__ rz, const PcgState *st) {
     if (st && st->done) return;
@@ -704,7 +733,7 @@ __global__ __launch_bounds__(kAT) void vc_sweep_kernel(Sell<V> A, const X *__res
         v[0] += (double)b[i] * (double)o;
     }
     if (rz) {
-        block_reduce<OpSum, 1, kAT>(v);
+        block_reduce<OpSum, 1, kRzThreads>(v);
         if (threadIdx.x == 0) rz[blockIdx.x] = v[0];
     }
 }
@@ -863,7 +892,11 @@ template <class V, class X>
 void amg_launch_post(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, const int32_t *agg, const X *e,
                      X *y, X *out, double *rz, const PcgState *st) {
     ALAUNCH(vc_prolong_kernel<X>, gridv(A.n), kAT, A.n, x, agg, e, y, st);
-    ALAUNCH((vc_sweep_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, y, out, rz, st);
+    // with rz the partials must match the Krylov kernels' grid and block size
+    if (rz)
+        ALAUNCH((vc_sweep_kernel<V, X>), reduce_grid(A.n, kRzThreads), kRzThreads, A, dinv, b, y, out, rz, st);
+    else
+        ALAUNCH((vc_sweep_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, y, out, nullptr, st);
 }
 template <class X>
 void amg_launch_dense(hipStream_t s, int32_t n, const X *Ainv, const X *b, X *x, const PcgState *st) {

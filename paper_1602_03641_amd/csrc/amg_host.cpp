@@ -174,17 +174,42 @@ void Amg::cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bo
         dinv_c = cv.dinv.p;
     }
     const bool coarse_x = !(l + 1 == nlev - 1 && dense);  // the dense solve needs no iterate
-    if (x_ready)
-        amg_launch_resid<V, X>(s, A, b, xa, r, st);
-    else
-        amg_launch_pre<V, X>(s, A, dinv, b, xa, r, st);
-    amg_launch_restrict<X>(s, cv.n, lv.mptr.p, lv.mrows.p, r, bc, coarse_x ? dinv_c : nullptr,
+    // sweeps on this level: one on the finest, o_.sweeps on the coarser ones
+    // (the same number before and after the coarse correction: symmetric)
+    const int nu = l == 0 ? 1 : std::max(1, o_.sweeps);
+    if (nu == 1) {
+        if (x_ready)
+            amg_launch_resid<V, X>(s, A, b, xa, r, st);
+        else
+            amg_launch_pre<V, X>(s, A, dinv, b, xa, r, st);
+        amg_launch_restrict<X>(s, cv.n, lv.mptr.p, lv.mrows.p, r, bc, coarse_x ? dinv_c : nullptr,
+                               coarse_x ? xc : nullptr, st);
+        cycle<V, X>(s, l + 1, bc, ec, st, coarse_x, nullptr);
+        if (lv.n <= kFusedPostRows && !rz)
+            amg_launch_post_fused<V, X>(s, A, dinv, b, lv.agg.p, ec, out, st);
+        else
+            amg_launch_post<V, X>(s, A, dinv, b, xa, lv.agg.p, ec, r, out, rz, st);  // r reused for y
+        return;
+    }
+    // nu pre-sweeps ping-ponging between xa and r, residual into the other
+    X *xs = xa, *tmp = r;
+    if (!x_ready) amg_launch_pre<V, X>(s, A, dinv, b, xa, r, st);  // xa = D^-1 b (r: discarded)
+    for (int k = 1; k < nu; ++k) {
+        amg_launch_sweep<V, X>(s, A, dinv, b, xs, tmp, st);
+        std::swap(xs, tmp);
+    }
+    amg_launch_resid<V, X>(s, A, b, xs, tmp, st);
+    amg_launch_restrict<X>(s, cv.n, lv.mptr.p, lv.mrows.p, tmp, bc, coarse_x ? dinv_c : nullptr,
                            coarse_x ? xc : nullptr, st);
     cycle<V, X>(s, l + 1, bc, ec, st, coarse_x, nullptr);
-    if (lv.n <= kFusedPostRows && !rz)
-        amg_launch_post_fused<V, X>(s, A, dinv, b, lv.agg.p, ec, out, st);
-    else
-        amg_launch_post<V, X>(s, A, dinv, b, xa, lv.agg.p, ec, r, out, rz, st);  // r reused for y
+    // y = x + P e into tmp and the first post-sweep into xs, then nu - 1
+    // more sweeps, the last one into out (levels >= 1 only: no r.z partials)
+    amg_launch_post<V, X>(s, A, dinv, b, xs, lv.agg.p, ec, tmp, xs, nullptr, st);
+    X *src = xs, *dst = tmp;
+    for (int k = 1; k < nu; ++k) {
+        amg_launch_sweep<V, X>(s, A, dinv, b, src, k == nu - 1 ? out : dst, st);
+        std::swap(src, dst);
+    }
 }
 
 void Amg::apply(hipStream_t s, const double *r, double *z, const PcgState *st, bool x_ready, double *rz) {

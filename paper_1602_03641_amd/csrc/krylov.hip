@@ -18,7 +18,7 @@
 
 namespace vag {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = kKrylovThreads;
 
 int pcg_grid(int64_t n) { return (int)reduce_grid(n, kThreads); }
 

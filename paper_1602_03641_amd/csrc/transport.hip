@@ -270,22 +270,42 @@ __global__ __launch_bounds__(kSliceRows) void upwind_count_kernel(
     const int32_t *__restrict__ frac_cell, const uint8_t *__restrict__ dirichlet, const int32_t *__restrict__ ncp,
     const int32_t *__restrict__ ncl, const int32_t *__restrict__ nfp, const int32_t *__restrict__ nfl,
     const double *__restrict__ F_cell, const double *__restrict__ F_cell_frac, const double *__restrict__ F_frac,
-    int32_t *__restrict__ slice_width, unsigned long long *__restrict__ nnz_total) {
+    int32_t *__restrict__ slice_width, uint16_t *__restrict__ meta, unsigned long long *__restrict__ nnz_total) {
     // one block = one wavefront = one slice
-    const int64_t i = (int64_t)blockIdx.x * kSliceRows + threadIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kSliceRows + lane;
     const int64_t total = (int64_t)nc + nf + nn;
     int c = 0;
     if (i < total)
         c = upwind_row_count(i, nc, nf, fmask, cell_frac, frac_cell, dirichlet, ncp, ncl, nfp, nfl, F_cell,
                              F_cell_frac, F_frac);
+    // sort the slice's rows by entry count, longest first (ties: lower lane
+    // first), with a bitonic network over the wavefront: slot l then holds
+    // the l-th longest row, so the lanes that run out of entries are the last
+    // ones and whole cache lines of padding are never read
+    int key = (c << 8) | (63 - lane);  // larger key = longer row, then lower lane
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int other = __shfl_xor(key, j, 64);
+            const bool up = ((lane & k) == 0);          // descending in this k-block
+            const bool lower = ((lane & j) == 0);
+            const int hi = max(key, other), lo = min(key, other);
+            key = (lower == up) ? hi : lo;
+        }
+    }
+    const int cnt = key >> 8, src = 63 - (key & 255);
+    meta[(int64_t)blockIdx.x * kSliceRows + lane] = (uint16_t)((src << 8) | cnt);
     int sum = c;
+    int w = cnt;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-        c = max(c, __shfl_down(c, o, 64));
+        w = max(w, __shfl_down(w, o, 64));
         sum += __shfl_down(sum, o, 64);
     }
-    if (threadIdx.x == 0) {
-        slice_width[blockIdx.x] = c;
+    if (lane == 0) {
+        slice_width[blockIdx.x] = w;
         atomicAdd(nnz_total, (unsigned long long)sum);  // integer sum: order-independent
     }
 }
@@ -325,9 +345,11 @@ __global__ __launch_bounds__(kSliceRows) void upwind_fill_kernel(
     const int32_t *__restrict__ ncl, const int32_t *__restrict__ nfp, const int32_t *__restrict__ nfl,
     const double *__restrict__ F_cell, const double *__restrict__ F_cell_frac, const double *__restrict__ F_frac,
     const double *__restrict__ phi_cell, const double *__restrict__ phi_frac, const double *__restrict__ phi_node,
-    const double *__restrict__ dtp, const int64_t *__restrict__ slice_ptr, int32_t *__restrict__ tcol,
-    double *__restrict__ tval, double *__restrict__ tdiag) {
-    const int64_t i = (int64_t)blockIdx.x * kSliceRows + threadIdx.x;
+    const double *__restrict__ dtp, const int64_t *__restrict__ slice_ptr, const uint16_t *__restrict__ meta,
+    int32_t *__restrict__ tcol, double *__restrict__ tval, double *__restrict__ tdiag) {
+    // slot threadIdx.x of the slice holds the row named by its meta entry
+    const int src = meta[(int64_t)blockIdx.x * kSliceRows + threadIdx.x] >> 8;
+    const int64_t i = (int64_t)blockIdx.x * kSliceRows + src;
     const int64_t total = (int64_t)nc + nf + nn;
     const int64_t base = slice_ptr[blockIdx.x] + threadIdx.x;
     const int width = (int)((slice_ptr[blockIdx.x + 1] - slice_ptr[blockIdx.x]) / kSliceRows);
@@ -411,17 +433,22 @@ __global__ __launch_bounds__(kSliceRows) void upwind_fill_kernel(
     tdiag[i] = d;
 }
 
-// c_out = c + theta (T c - c); theta = 1 is the plain step
+// c_out = c + theta (T c - c); theta = 1 is the plain step.  Slot t of a
+// slice holds row (slice, meta >> 8) with meta & 255 entries.
 __global__ __launch_bounds__(256) void transport_step_kernel(int32_t nrow, const int64_t *__restrict__ slice_ptr,
+                                                             const uint16_t *__restrict__ meta,
                                                              const int32_t *__restrict__ tcol,
                                                              const double *__restrict__ tval,
                                                              const double *__restrict__ tdiag,
                                                              const double *__restrict__ c_in,
                                                              double *__restrict__ c_out, double theta) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t sl = t / kSliceRows, lane = t % kSliceRows;
+    if ((int64_t)sl * kSliceRows >= nrow) return;
+    const uint16_t m = meta[t];
+    const int32_t i = sl * kSliceRows + (m >> 8);
     if (i >= nrow) return;
-    const int32_t sl = i / kSliceRows, lane = i % kSliceRows;
-    const int64_t b0 = slice_ptr[sl], b1 = slice_ptr[sl + 1];
+    const int64_t b0 = slice_ptr[sl], b1 = b0 + (int64_t)(m & 255) * kSliceRows;
     const double ci = c_in[i];
     double a0 = tdiag[i] * ci, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int64_t q = b0 + lane;
@@ -495,11 +522,12 @@ void launch_upwind_count(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, cons
                          const int32_t *cell_frac, const int32_t *frac_cell, const uint8_t *dirichlet,
                          const int32_t *node_cell_ptr, const int32_t *node_cell, const int32_t *node_frac_ptr,
                          const int32_t *node_frac, const double *F_cell, const double *F_cell_frac,
-                         const double *F_frac, int32_t *slice_width, unsigned long long *nnz_total) {
+                         const double *F_frac, int32_t *slice_width, uint16_t *meta,
+                         unsigned long long *nnz_total) {
     const int64_t total = (int64_t)nc + nf + nn;
     hipLaunchKernelGGL(upwind_count_kernel, dim3(nb(total, kSliceRows)), dim3(kSliceRows), 0, s, nc, nf, nn, fmask,
                        cell_frac, frac_cell, dirichlet, node_cell_ptr, node_cell, node_frac_ptr, node_frac, F_cell,
-                       F_cell_frac, F_frac, slice_width, nnz_total);
+                       F_cell_frac, F_frac, slice_width, meta, nnz_total);
     VAG_HIP(hipGetLastError());
 }
 void launch_slice_scan(hipStream_t s, int32_t nslice, const int32_t *slice_width, int64_t *slice_ptr) {
@@ -512,19 +540,21 @@ void launch_upwind_fill(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const
                         const int32_t *node_cell, const int32_t *node_frac_ptr, const int32_t *node_frac,
                         const double *F_cell, const double *F_cell_frac, const double *F_frac,
                         const double *phi_cell, const double *phi_frac, const double *phi_node, const double *dt,
-                        const int64_t *slice_ptr, int32_t *tcol, double *tval, double *tdiag) {
+                        const int64_t *slice_ptr, const uint16_t *meta, int32_t *tcol, double *tval,
+                        double *tdiag) {
     const int64_t total = (int64_t)nc + nf + nn;
     hipLaunchKernelGGL(upwind_fill_kernel, dim3(nb(total, kSliceRows)), dim3(kSliceRows), 0, s, nc, nf, nn, hex8,
                        fmask, cell_frac, frac_cell, frac_nodes, dirichlet, node_cell_ptr, node_cell, node_frac_ptr,
-                       node_frac, F_cell, F_cell_frac, F_frac, phi_cell, phi_frac, phi_node, dt, slice_ptr, tcol,
-                       tval, tdiag);
+                       node_frac, F_cell, F_cell_frac, F_frac, phi_cell, phi_frac, phi_node, dt, slice_ptr, meta,
+                       tcol, tval, tdiag);
     VAG_HIP(hipGetLastError());
 }
-void launch_transport_step(hipStream_t s, int32_t nrow, const int64_t *slice_ptr, const int32_t *tcol,
-                           const double *tval, const double *tdiag, const double *c_in, double *c_out,
-                           double theta) {
-    hipLaunchKernelGGL(transport_step_kernel, dim3(nb(nrow, 256)), dim3(256), 0, s, nrow, slice_ptr, tcol, tval,
-                       tdiag, c_in, c_out, theta);
+void launch_transport_step(hipStream_t s, int32_t nrow, const int64_t *slice_ptr, const uint16_t *meta,
+                           const int32_t *tcol, const double *tval, const double *tdiag, const double *c_in,
+                           double *c_out, double theta) {
+    const int64_t slots = (int64_t)((nrow + kSliceRows - 1) / kSliceRows) * kSliceRows;
+    hipLaunchKernelGGL(transport_step_kernel, dim3(nb(slots, 256)), dim3(256), 0, s, nrow, slice_ptr, meta, tcol,
+                       tval, tdiag, c_in, c_out, theta);
     VAG_HIP(hipGetLastError());
 }
 void launch_set_dirichlet(hipStream_t s, int32_t nn, int32_t offset, const uint8_t *dirichlet, const double *c_bar,

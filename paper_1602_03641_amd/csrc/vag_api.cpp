@@ -41,6 +41,7 @@ struct vag_handle {
     DBuf<double> u_node, u_cell, u_frac, F_cell, F_cell_frac, F_frac, phi_cell, phi_frac, phi_node;
     // transport
     DBuf<int32_t> slice_width, tcol;
+    DBuf<uint16_t> tmeta;
     DBuf<int64_t> slice_ptr;
     DBuf<double> tval, tdiag, cbuf0, cbuf1, dt4;
     DBuf<unsigned long long> cnt;
@@ -221,6 +222,7 @@ AmgOptions amg_options(const vag_options &o) {
     if (o.amg_theta > 0) a.theta = o.amg_theta;
     if (o.amg_coarse_size > 0) a.coarse_size = o.amg_coarse_size;
     if (o.amg_max_levels > 0) a.max_levels = o.amg_max_levels;
+    if (o.amg_sweeps > 0) a.sweeps = o.amg_sweeps;
     return a;
 }
 
@@ -277,7 +279,7 @@ void run_pcg(vag_handle *h) {
             if (h->h_pcg->done || k >= max_iter) break;
         }
         k = h->h_pcg->iter;
-        if (!h->h_pcg->converged || k >= max_iter || restart >= 3) break;
+        if (!h->h_pcg->converged || k >= max_iter) break;
         // true residual check
         launch_residual_norm(s, A, h->x.p, h->b.p, h->q.p, h->rparts.p, h->scal.p);
         VAG_HIP(hipMemcpyAsync(h->h_scal, h->scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -285,6 +287,10 @@ void run_pcg(vag_handle *h) {
         if (bb < 0) bb = h->h_scal[1];
         const double rr = h->h_scal[0];
         if (rr <= h->opt.rtol * h->opt.rtol * bb) break;
+        if (restart >= 3) {  // the true residual stays above rtol (rounding floor): report it
+            h->h_pcg->converged = 0;
+            break;
+        }
         rtol = std::min(0.5, h->opt.rtol * std::sqrt(bb / rr));
         k0 = k;
     }
@@ -439,7 +445,7 @@ vag_status vag_default_options(vag_options *o) {
     o->amg_coarse_size = 500;
     o->amg_max_levels = 12;
     o->amg_theta = 0.02;
-    o->amg_sweeps = 1;
+    o->amg_sweeps = 2;
     o->eliminate_frac_faces = 1;
     return VAG_OK;
 }
@@ -555,6 +561,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         const int64_t nrow = nc + nf + nn;
         const int64_t nslice = (nrow + kSliceRows - 1) / kSliceRows;
         h->slice_width.alloc(nslice, h->tr);
+        h->tmeta.alloc((size_t)nslice * kSliceRows, h->tr);
         h->slice_ptr.alloc(nslice + 1, h->tr);
         h->tdiag.alloc(nrow, h->tr);
         h->cbuf0.alloc(nrow, h->tr);
@@ -764,7 +771,7 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
         VAG_HIP(hipMemsetAsync(h->cnt.p, 0, sizeof(unsigned long long), s));
         launch_upwind_count(s, S.nc, S.nf, S.nn, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
                             h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
-                            h->F_cell_frac.p, h->F_frac.p, h->slice_width.p, h->cnt.p);
+                            h->F_cell_frac.p, h->F_frac.p, h->slice_width.p, h->tmeta.p, h->cnt.p);
         launch_slice_scan(s, nslice, h->slice_width.p, h->slice_ptr.p);
         int64_t total = 0;
         VAG_HIP(hipMemcpyAsync(&total, h->slice_ptr.p + nslice, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -781,7 +788,7 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
         launch_upwind_fill(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p,
                            h->frac_nodes.p, h->dirichlet.p, h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p,
                            h->node_frac.p, h->F_cell.p, h->F_cell_frac.p, h->F_frac.p, h->phi_cell.p, h->phi_frac.p,
-                           h->phi_node.p, h->dt4.p, h->slice_ptr.p, h->tcol.p, h->tval.p, h->tdiag.p);
+                           h->phi_node.p, h->dt4.p, h->slice_ptr.p, h->tmeta.p, h->tcol.p, h->tval.p, h->tdiag.p);
         // initial state
         if (c0_cell || c0_frac || c0_node) {
             if (!c0_cell || !c0_node || (S.nf && !c0_frac))
@@ -809,7 +816,7 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
         VAG_HIP(hipEventRecord(h->ev[6], s));
         for (int64_t k = 0; k < N; ++k) {
             const double th = (k == N - 1) ? theta_last : 1.0;
-            launch_transport_step(s, (int32_t)nrow, h->slice_ptr.p, h->tcol.p, h->tval.p, h->tdiag.p, h->c_cur(),
+            launch_transport_step(s, (int32_t)nrow, h->slice_ptr.p, h->tmeta.p, h->tcol.p, h->tval.p, h->tdiag.p, h->c_cur(),
                                   h->c_next(), th);
             h->cur ^= 1;
         }
@@ -889,20 +896,38 @@ vag_status vag_get_system(vag_handle *h, int64_t *row_ptr, int64_t *col, double 
     return guard(h, [&] {
         if (!h->solved) throw Error(VAG_ERR_STATE, "no pressure solve yet");
         const Symbolic &S = h->S;
-        std::vector<int64_t> rp(S.row_ptr.begin(), S.row_ptr.end()), cl(S.col.begin(), S.col.end());
-        std::vector<double> sv(h->A.n), cv(S.nnz);
+        const int32_t n = S.nunk;
+        std::vector<double> sv(h->A.n), bv(std::max(n, 1));
         VAG_HIP(hipMemcpyAsync(sv.data(), h->A.p, sv.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        VAG_HIP(hipMemcpyAsync(bv.data(), h->b.p, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
         VAG_HIP(hipStreamSynchronize(h->stream));
-        // entry k of row r sits at sell_ptr[r/64] + 64 k + r%64, in the CSR order
-        for (int32_t r = 0; r < S.nunk; ++r)
+        // back to the natural order (free nodes by node index, then kept faces
+        // by face index); entry k of stored row r sits at sell_ptr[r/64] + 64 k + r%64
+        std::vector<int64_t> rp(n + 1, 0), cl(S.nnz);
+        std::vector<double> cv(S.nnz), bo(std::max(n, 1));
+        for (int32_t o = 0; o < n; ++o) {
+            const int32_t r = S.sys_new[o];
+            rp[o + 1] = rp[o] + (S.row_ptr[r + 1] - S.row_ptr[r]);
+        }
+        std::vector<std::pair<int32_t, double>> row;
+        for (int32_t o = 0; o < n; ++o) {
+            const int32_t r = S.sys_new[o];
+            row.clear();
             for (int32_t k = 0; k < S.row_ptr[r + 1] - S.row_ptr[r]; ++k)
-                cv[S.row_ptr[r] + k] = sv[S.sell_ptr[r >> 6] + 64 * (int64_t)k + (r & 63)];
+                row.emplace_back(S.sys_old[S.col[S.row_ptr[r] + k]],
+                                 sv[S.sell_ptr[r >> 6] + 64 * (int64_t)k + (r & 63)]);
+            std::sort(row.begin(), row.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+            for (size_t k = 0; k < row.size(); ++k) {
+                cl[rp[o] + k] = row[k].first;
+                cv[rp[o] + k] = row[k].second;
+            }
+            bo[o] = bv[r];
+        }
         hipMemcpyKind k = mem == VAG_MEM_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
         if (row_ptr) VAG_HIP(hipMemcpy(row_ptr, rp.data(), rp.size() * sizeof(int64_t), k));
         if (col) VAG_HIP(hipMemcpy(col, cl.data(), cl.size() * sizeof(int64_t), k));
         if (val) VAG_HIP(hipMemcpy(val, cv.data(), cv.size() * sizeof(double), k));
-        download(h, b, h->b, S.nunk, mem);
-        VAG_HIP(hipStreamSynchronize(h->stream));
+        if (b) VAG_HIP(hipMemcpy(b, bo.data(), (size_t)n * sizeof(double), k));
     });
 }
 
@@ -926,7 +951,7 @@ vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms)
                                                         PcgParts{h->parts.p, pcg_grid(S.nunk)}, h->pcg.p + 1);
                     break;
                 case VAG_KERNEL_TRANSPORT_STEP:  // reads the current state, writes the spare buffer
-                    launch_transport_step(s, (int32_t)nrow, h->slice_ptr.p, h->tcol.p, h->tval.p, h->tdiag.p,
+                    launch_transport_step(s, (int32_t)nrow, h->slice_ptr.p, h->tmeta.p, h->tcol.p, h->tval.p, h->tdiag.p,
                                           h->c_cur(), h->c_next(), 1.0);
                     break;
                 case VAG_KERNEL_LOCAL:

@@ -48,6 +48,7 @@ __host__ __device__ constexpr int sym5(int i, int j) {
 constexpr int kSliceRows = 64;      // SELL slice height = one wavefront
 constexpr int kReduceBlocks = 512;  // fixed grid of the deterministic reductions
 constexpr int kReduceThreads = 256;
+constexpr int kKrylovThreads = 1024;  // block size of the Krylov kernels (and of their partials' producers)
 
 // ---------------------------------------------------------------------------
 // device buffer
@@ -104,6 +105,7 @@ struct Symbolic {
     std::vector<int32_t> row_ptr, col;               // CSR pattern of the eliminated system (sorted rows)
     std::vector<int64_t> sell_ptr;                   // sliced-ELL slice pointers of that pattern
     std::vector<int32_t> unk_node, unk_face;         // row -> free node (rows < nfree), -> kept face
+    std::vector<int32_t> sys_old, sys_new;           // system row renumbering: new -> natural, natural -> new
     std::vector<int32_t> face_grp, face_loc;         // [nf] eliminated group of sigma and index in it, or -1
     std::vector<int32_t> frac_unk;                   // [nf] unknown index of sigma (>= nunk: eliminated)
     // Fracture-face groups eliminated onto the nodes: faces linked through a
@@ -116,6 +118,9 @@ struct Symbolic {
     std::vector<int32_t> grp_ptr, grp_face, grp_nptr, grp_node, grp_pos, gcolor_ptr;
     std::vector<int64_t> grp_off, grp_poff;
 };
+
+// Rows are sorted by length inside windows of this many rows (slice padding).
+constexpr int kSortWindow = 512;
 
 // Limits of an eliminated fracture-face group (larger groups stay unknowns).
 constexpr int kGroupMaxFaces = 32;
@@ -267,7 +272,7 @@ void launch_upwind_count(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, cons
                          const int32_t *node_cell_ptr, const int32_t *node_cell,
                          const int32_t *node_frac_ptr, const int32_t *node_frac, const double *F_cell,
                          const double *F_cell_frac, const double *F_frac, int32_t *slice_width,
-                         unsigned long long *nnz_total);
+                         uint16_t *meta, unsigned long long *nnz_total);
 void launch_slice_scan(hipStream_t s, int32_t nslice, const int32_t *slice_width, int64_t *slice_ptr);
 void launch_upwind_fill(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,
                         const uint8_t *fmask, const int32_t *cell_frac, const int32_t *frac_cell,
@@ -275,11 +280,13 @@ void launch_upwind_fill(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const
                         const int32_t *node_cell, const int32_t *node_frac_ptr, const int32_t *node_frac,
                         const double *F_cell, const double *F_cell_frac, const double *F_frac,
                         const double *phi_cell, const double *phi_frac, const double *phi_node,
-                        const double *dt, const int64_t *slice_ptr, int32_t *tcol, double *tval,
-                        double *tdiag);
-void launch_transport_step(hipStream_t s, int32_t nrow, const int64_t *slice_ptr, const int32_t *tcol,
-                           const double *tval, const double *tdiag, const double *c_in, double *c_out,
-                           double theta);
+                        const double *dt, const int64_t *slice_ptr, const uint16_t *meta, int32_t *tcol,
+                        double *tval, double *tdiag);
+// meta[slot] = (lane of the row in its slice) << 8 | entry count: the rows of
+// a slice are stored longest first
+void launch_transport_step(hipStream_t s, int32_t nrow, const int64_t *slice_ptr, const uint16_t *meta,
+                           const int32_t *tcol, const double *tval, const double *tdiag, const double *c_in,
+                           double *c_out, double theta);
 void launch_set_dirichlet(hipStream_t s, int32_t nn, int32_t offset, const uint8_t *dirichlet,
                           const double *c_bar, double *c);
 
