@@ -25,13 +25,15 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(h, sinfo, tinfo, levels=None, precision="fp64"):
+def algorithmic_bytes(h, sinfo, tinfo, levels=None, precision="fp64", sweeps=2):
     n, nnz = sinfo["n_unknowns"], sinfo["nnz"]
     spmv = 12 * nnz + 4 * (n + 1) + 16 * n                       # CSR FP64: val+col, row_ptr, x, y
     step = 12 * tinfo["t_nnz"] + 24 * tinfo["n_rows"]            # upwind sweep: entries, diag, c in/out
     out = dict(spmv=spmv, transport_step=step)
     if levels:
-        # one V-cycle: per level two matrix passes (residual, smoothing sweep),
+        # one V-cycle: two matrix passes on the finest level (residual,
+        # smoothing sweep) and 2 * sweeps on the coarser ones (sweeps - 1
+        # pre-sweeps after the first iterate, residual, sweeps post-sweeps),
         # about 13 vector passes plus the aggregate maps, the coarse vector;
         # the coarsest level is a dense product
         v = 4 if precision in ("mixed", "mixed_ir") else 8      # matrix value bytes
@@ -39,7 +41,8 @@ def algorithmic_bytes(h, sinfo, tinfo, levels=None, precision="fp64"):
         b = 0
         for i, (rows, nz, _) in enumerate(levels[:-1]):
             nc = levels[i + 1][0]
-            b += 2 * (v + 4) * nz + 13 * rows * w + 8 * rows + nc * w
+            passes = 2 if i == 0 else 2 * max(1, sweeps)
+            b += passes * (v + 4) * nz + 13 * rows * w + 8 * rows + nc * w
         rows = levels[-1][0]
         b += rows * rows * w + 2 * rows * w
         out["vcycle"] = b
@@ -230,7 +233,7 @@ def main():
 
     # roofline of the dominant kernel: per-launch time from HIP events on the handle's stream
     levels = h.amg_levels() if args.precond == "amg" else None
-    ab = algorithmic_bytes(h, sinfo, tinfo, levels, args.precision)
+    ab = algorithmic_bytes(h, sinfo, tinfo, levels, args.precision, args.amg_sweeps if args.amg_sweeps > 0 else 2)
     ms_spmv = h.benchmark_kernel(vag.VAG_KERNEL_SPMV, 100)
     ms_step = h.benchmark_kernel(vag.VAG_KERNEL_TRANSPORT_STEP, 100)
     ms_prec = h.benchmark_kernel(vag.VAG_KERNEL_PRECOND, 50)

@@ -8,6 +8,10 @@
 
 namespace vag {
 
+// levels of at most this many rows run their V-cycle kernels with several
+// lanes per row
+constexpr int32_t kSmallRows = 65536;
+
 // kernel launchers (amg.hip)
 void amg_launch_diag(hipStream_t s, Sell<double> A, double *diag, double *dinv);
 void amg_launch_mis(hipStream_t s, Sell<double> A, const double *diag, double theta, int rounds, uint64_t *T,
@@ -19,11 +23,12 @@ void amg_launch_lonely(hipStream_t s, int32_t n, const int32_t *lonely, const in
                        int32_t *agg);
 void amg_launch_members(hipStream_t s, int32_t n, int32_t nc, const int32_t *agg, int32_t *cnt, int32_t *ptr,
                         int32_t *cursor, int32_t *tmp, int32_t *rows, int32_t *scan_tmp);
+// row i of A P into the first apn[i] slots of (apJ, apv); nspill zeroed by the caller
 void amg_launch_collapse(hipStream_t s, Sell<double> A, const int32_t *agg, int32_t *Jcol, int32_t *apJ,
-                         double *apv);
-void amg_launch_galerkin(hipStream_t s, Sell<double> A, const int32_t *Jcol, const double *apv, const int32_t *mptr,
-                         const int32_t *mrows, int32_t nc, int mode, int32_t *big, int32_t *rowlen,
-                         const int64_t *cptr, int32_t *ccol, double *cval, int *overflow);
+                         double *apv, int32_t *apn, int32_t *spill, int *nspill);
+void amg_launch_galerkin(hipStream_t s, Sell<double> A, const int32_t *Jcol, const double *apv, const int32_t *apn,
+                         const int32_t *mptr, const int32_t *mrows, int32_t nc, int mode, int32_t *big,
+                         int32_t *rowlen, const int64_t *cptr, int32_t *ccol, double *cval, int *overflow);
 // slice widths and pointers from row lengths; adds the number of entries to *nnz
 void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t *width, int64_t *ptr,
                        unsigned long long *nnz);
@@ -51,6 +56,11 @@ template <class X>
 void amg_launch_dense(hipStream_t s, int32_t n, const X *Ainv, const X *b, X *x, const PcgState *st);
 template <class V, class X>
 void amg_launch_sweep(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, X *out, const PcgState *st);
+// levels of at most kSmallRows rows: out = y + D^-1 (b - A y) with y = x + P e
+// in one kernel (out must not alias x)
+template <class V, class X>
+void amg_launch_post_x(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, const int32_t *agg,
+                       const X *e, X *out, const PcgState *st);
 void launch_to_float(hipStream_t s, int64_t n, const double *a, float *b);
 void launch_to_double(hipStream_t s, int64_t n, const float *a, double *b);
 
@@ -110,11 +120,11 @@ class Amg {
     void apply_mixed(hipStream_t s, const double *r, double *z, const PcgState *st, bool x_ready = false,
                      double *rz = nullptr);
     // levels at or below this many rows prolongate and smooth in one kernel
-    static constexpr int32_t kFusedPostRows = 65536;
+    static constexpr int32_t kFusedPostRows = kSmallRows;
 
   private:
     DBuf<uint64_t> T_, T1_;
-    DBuf<int32_t> flag_, rid_, agg1_, lonely_, lid_, cnt_, cursor_, rowlen_, width_, big_, mtmp_, stmp_, jcol_;
+    DBuf<int32_t> flag_, rid_, agg1_, lonely_, lid_, cnt_, cursor_, rowlen_, width_, big_, mtmp_, stmp_, jcol_, apn_, spill_;
     DBuf<double> apv_;
     DBuf<int32_t> apj_;
     DBuf<uint8_t> strong_;

@@ -19,6 +19,7 @@
 // solved by a dense inverse formed on the device by Gauss-Jordan elimination.
 #include <algorithm>
 
+#include "amg.h"
 #include "reduce.h"
 #include "sell.h"
 
@@ -316,27 +317,28 @@ __global__ __launch_bounds__(kAT) void agg_col_kernel(Sell<double> A, const int3
     }
 }
 // Row i of A P (P = aggregate indicator): the distinct aggregates of the row's
-// columns, in increasing order, each with the sum of its entries (in column
-// order), written to the row's first slots of (apJ, apv); the remaining slots
-// get value 0, which later passes skip like padding.  The lanes of a wave scan
-// slot k together, so the passes are coalesced.
+// columns, in increasing order, each with the sum of its entries (in entry
+// order); the nonzero sums go to the row's first apn[i] slots of (apJ, apv).
+// The lanes of a wave scan slot k together, so the passes are coalesced.  A
+// row with more than kSet distinct aggregates is appended to the spill list
+// and collapsed by ap_spill_kernel instead.
+constexpr int kSet = 16;
 __global__ __launch_bounds__(kAT) void ap_collapse_kernel(Sell<double> A, const int32_t *__restrict__ Jcol,
-                                                          int32_t *__restrict__ apJ, double *__restrict__ apv) {
-    constexpr int kSet = 16;  // distinct aggregates kept in registers; more: slow path
+                                                          int32_t *__restrict__ apJ, double *__restrict__ apv,
+                                                          int32_t *__restrict__ apn, int32_t *__restrict__ spill,
+                                                          int *__restrict__ nspill) {
     GS(i, A.n) {
         const int64_t b0 = A.ptr[i >> 6] + (i & 63), b1 = A.ptr[(i >> 6) + 1];
-        int64_t out = b0;
-        // one pass: per distinct aggregate, the sum of the row's entries in entry order
         int32_t J[kSet];
         double v[kSet];
         int cnt = 0;
-        bool spill = false;
+        bool over = false;
 #pragma unroll
         for (int t = 0; t < kSet; ++t) {
             J[t] = INT32_MAX;
             v[t] = 0.0;
         }
-        for (int64_t q = b0; q < b1 && !spill; q += 64) {
+        for (int64_t q = b0; q < b1 && !over; q += 64) {
             const double a = A.val[q];
             if (a == 0.0) continue;
             const int32_t c = Jcol[q];
@@ -349,7 +351,7 @@ __global__ __launch_bounds__(kAT) void ap_collapse_kernel(Sell<double> A, const 
                 }
             if (!found) {
                 if (cnt == kSet) {
-                    spill = true;
+                    over = true;
                 } else {
 #pragma unroll
                     for (int t = 0; t < kSet; ++t)
@@ -361,55 +363,158 @@ __global__ __launch_bounds__(kAT) void ap_collapse_kernel(Sell<double> A, const 
                 }
             }
         }
-        if (!spill) {
-            // ascending aggregate order (selection of the next larger key)
-            int32_t last = -1;
-            for (int k = 0; k < cnt; ++k) {
-                int32_t jm = INT32_MAX;
-                double vm = 0.0;
+        if (over) {
+            spill[atomicAdd(nspill, 1)] = (int32_t)i;  // list order is irrelevant: rows are independent
+            continue;
+        }
+        // ascending aggregate order (selection of the next larger key)
+        int64_t out = b0;
+        int32_t last = -1;
+        int written = 0;
+        for (int k = 0; k < cnt; ++k) {
+            int32_t jm = INT32_MAX;
+            double vm = 0.0;
 #pragma unroll
-                for (int t = 0; t < kSet; ++t)
-                    if (J[t] > last && J[t] < jm) {
-                        jm = J[t];
-                        vm = v[t];
-                    }
-                apJ[out] = jm;
-                apv[out] = vm;
-                out += 64;
-                last = jm;
-            }
-        } else {
-            // many distinct aggregates: repeated minimum extraction over the row
-            int32_t last = -1;
-            for (;;) {
-                int32_t jm = INT32_MAX;
-                for (int64_t q = b0; q < b1; q += 64) {
-                    const int32_t c = Jcol[q];
-                    if (c > last && c < jm && A.val[q] != 0.0) jm = c;
+            for (int t = 0; t < kSet; ++t)
+                if (J[t] > last && J[t] < jm) {
+                    jm = J[t];
+                    vm = v[t];
                 }
-                if (jm == INT32_MAX) break;
-                double sum = 0.0;
-                for (int64_t q = b0; q < b1; q += 64)
-                    if (Jcol[q] == jm) sum += A.val[q];
-                apJ[out] = jm;
-                apv[out] = sum;
-                out += 64;
-                last = jm;
+            last = jm;
+            if (vm == 0.0) continue;
+            apJ[out] = jm;
+            apv[out] = vm;
+            out += 64;
+            ++written;
+        }
+        apn[i] = written;
+    }
+}
+
+// The spilled rows of ap_collapse_kernel, one wavefront per row: the row's
+// entries as keys (aggregate, slot) sorted in LDS, then one sum per run of
+// equal aggregates in slot order (the order of the fast path).  Rows with more
+// than CAP entries fall back to repeated minimum extraction by one lane.
+template <int CAP>
+__global__ __launch_bounds__(64) void ap_spill_kernel(Sell<double> A, const int32_t *__restrict__ Jcol,
+                                                      int32_t *__restrict__ apJ, double *__restrict__ apv,
+                                                      int32_t *__restrict__ apn, const int32_t *__restrict__ spill,
+                                                      const int *__restrict__ nspill) {
+    __shared__ uint64_t key[CAP];
+    const int lane = threadIdx.x;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int ns = *nspill;
+    for (int it = blockIdx.x; it < ns; it += gridDim.x) {
+        const int32_t r = spill[it];
+        const int64_t b0 = A.ptr[r >> 6] + (r & 63);
+        const int w = (int)((A.ptr[(r >> 6) + 1] - A.ptr[r >> 6]) >> 6);
+        int m = 0;
+        for (int k0 = 0; k0 < w && m <= CAP; k0 += 64) {
+            const int k = k0 + lane;
+            bool keep = false;
+            uint64_t kv = 0;
+            if (k < w) {
+                const int64_t q = b0 + (int64_t)k * 64;
+                if (A.val[q] != 0.0) {
+                    keep = true;
+                    kv = ((uint64_t)(uint32_t)Jcol[q] << 32) | (uint64_t)(uint32_t)k;
+                }
             }
+            const uint64_t mask = __ballot(keep);
+            const int off = __popcll(mask & below);
+            if (keep && m + off < CAP) key[m + off] = kv;
+            m += __popcll(mask);
         }
-        for (; out < b1; out += 64) {
-            apJ[out] = (int32_t)i;
-            apv[out] = 0.0;
+        if (m > CAP) {
+            if (lane == 0) {
+                int32_t last = -1;
+                int written = 0;
+                int64_t out = b0;
+                for (;;) {
+                    int32_t jm = INT32_MAX;
+                    for (int k = 0; k < w; ++k) {
+                        const int64_t q = b0 + (int64_t)k * 64;
+                        const int32_t c = Jcol[q];
+                        if (c > last && c < jm && A.val[q] != 0.0) jm = c;
+                    }
+                    if (jm == INT32_MAX) break;
+                    double sum = 0.0;
+                    for (int k = 0; k < w; ++k) {
+                        const int64_t q = b0 + (int64_t)k * 64;
+                        const double a = A.val[q];
+                        if (a != 0.0 && Jcol[q] == jm) sum += a;
+                    }
+                    last = jm;
+                    if (sum == 0.0) continue;
+                    apJ[out] = jm;
+                    apv[out] = sum;
+                    out += 64;
+                    ++written;
+                }
+                apn[r] = written;
+            }
+            __syncthreads();
+            continue;
         }
+        int mp = 1;
+        while (mp < m) mp <<= 1;
+        for (int k = m + lane; k < mp; k += 64) key[k] = ~0ull;
+        __syncthreads();
+        for (int k = 2; k <= mp; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = lane; i < mp; i += 64) {
+                    const int p = i ^ j;
+                    if (p > i) {
+                        const uint64_t a = key[i], b = key[p];
+                        const bool up = (i & k) == 0;
+                        if ((a > b) == up) {
+                            key[i] = b;
+                            key[p] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        // runs of equal aggregates: lane-contiguous chunks, nonzero sums ranked by a wave scan
+        const int C = (m + 63) / 64;
+        const int lo = min(m, lane * C), hi = min(m, lo + C);
+        int nh = 0;
+        for (int t = lo; t < hi; ++t) {
+            if (!(t == 0 || (key[t] >> 32) != (key[t - 1] >> 32))) continue;
+            const uint32_t Jt = (uint32_t)(key[t] >> 32);
+            double s = 0.0;
+            for (int u = t; u < m && (uint32_t)(key[u] >> 32) == Jt; ++u) s += A.val[b0 + (int64_t)(uint32_t)key[u] * 64];
+            nh += s != 0.0;
+        }
+        int incl = nh;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        int rank = incl - nh;
+        for (int t = lo; t < hi; ++t) {
+            if (!(t == 0 || (key[t] >> 32) != (key[t - 1] >> 32))) continue;
+            const uint32_t Jt = (uint32_t)(key[t] >> 32);
+            double s = 0.0;
+            for (int u = t; u < m && (uint32_t)(key[u] >> 32) == Jt; ++u) s += A.val[b0 + (int64_t)(uint32_t)key[u] * 64];
+            if (s == 0.0) continue;
+            apJ[b0 + (int64_t)rank * 64] = (int32_t)Jt;
+            apv[b0 + (int64_t)rank * 64] = s;
+            ++rank;
+        }
+        if (lane == 63) apn[r] = incl;
+        __syncthreads();
     }
 }
 
 // mode 0: rowlen[I] = number of coarse columns; mode 1: write them (SELL).
-// Candidates are the nonzero collapsed entries of the aggregate's rows.
-// Rows with more than CAP candidates set big[I] and are redone with the larger CAP.
+// Candidates are the collapsed entries (apn[r] of them) of the aggregate's
+// rows r, gathered with one member row per lane.  Rows with more than CAP
+// candidates set big[I] and are redone with the larger CAP.
 template <int CAP>
 __global__ __launch_bounds__(64) void galerkin_kernel(Sell<double> A, const int32_t *__restrict__ Jcol,
-                                                      const double *__restrict__ apv,
+                                                      const double *__restrict__ apv, const int32_t *__restrict__ apn,
                                                       const int32_t *__restrict__ mptr, const int32_t *__restrict__ mrows,
                                                       int32_t nc, int mode, int32_t *__restrict__ big,
                                                       int32_t *__restrict__ rowlen, const int64_t *__restrict__ cptr,
@@ -422,32 +527,33 @@ __global__ __launch_bounds__(64) void galerkin_kernel(Sell<double> A, const int3
     if (CAP > 2048 && !big[I]) return;
     int m = 0;
     bool over = false;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int32_t t = mptr[I]; t < mptr[I + 1] && !over; ++t) {
-        const int32_t r = mrows[t];
-        const int64_t b0 = A.ptr[r >> 6], b1 = A.ptr[(r >> 6) + 1];
-        const int w = (int)((b1 - b0) >> 6);
-        for (int k0 = 0; k0 < w; k0 += 64) {
-            const int k = k0 + lane;
-            bool keep = false;
-            uint64_t kv = 0;
-            if (k < w) {
-                const int64_t q = b0 + (int64_t)k * 64 + (r & 63);
-                if (apv[q] != 0.0) {
-                    keep = true;
-                    kv = ((uint64_t)(uint32_t)Jcol[q] << 32) | (uint64_t)(uint32_t)q;
-                }
-            }
-            const uint64_t mask = __ballot(keep);
-            const int off = __popcll(mask & below);
-            const int cnt = __popcll(mask);
-            if (m + cnt > CAP) {
-                over = true;
-                break;
-            }
-            if (keep) key[m + off] = kv;
-            m += cnt;
+    const int32_t t1 = mptr[I + 1];
+    for (int32_t t0 = mptr[I]; t0 < t1; t0 += 64) {
+        const int32_t t = t0 + lane;
+        int c = 0;
+        int64_t b = 0;
+        if (t < t1) {
+            const int32_t r = mrows[t];
+            b = A.ptr[r >> 6] + (r & 63);
+            c = apn[r];
         }
+        int incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        const int tot = __shfl(incl, 63, 64);
+        if (m + tot > CAP) {
+            over = true;
+            break;
+        }
+        const int off = m + incl - c;
+        for (int k = 0; k < c; ++k) {
+            const int64_t q = b + (int64_t)k * 64;
+            key[off + k] = ((uint64_t)(uint32_t)Jcol[q] << 32) | (uint64_t)(uint32_t)q;
+        }
+        m += tot;
     }
     if (over) {
         if (lane == 0) {
@@ -575,24 +681,31 @@ __global__ __launch_bounds__(256) void gj_pivot_kernel(int32_t n, int32_t p0, in
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int i = ty * 4 + a, j = tx * 4 + c;
-            t[a][c] = (i < k && j < k) ? M[(int64_t)(p0 + i) * n + p0 + j] : (i == j ? 1.0 : 0.0);
+            // every lane loads (the padding from the block's first entry) so the
+            // sixteen loads are in flight together
+            const bool in = i < k && j < k;
+            const double x = M[(int64_t)(p0 + (in ? i : 0)) * n + p0 + (in ? j : 0)];
+            t[a][c] = in ? x : (i == j ? 1.0 : 0.0);
         }
     for (int p = 0; p < k; ++p) {
         const int buf = p & 1;
         // owners of column p and of row p publish them
-        if (tx == (p >> 2)) {
+        {
+            const int q = p & 3;
+            // the thread's entries in column p (one per tile row) and row p (one per tile column)
+            double cv[4], rv[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 4; ++a) cv[a] = q == 0 ? t[a][0] : q == 1 ? t[a][1] : q == 2 ? t[a][2] : t[a][3];
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if (c == (p & 3)) colp[buf][ty * 4 + a] = t[a][c];
-        }
-        if (ty == (p >> 2)) {
+            for (int c = 0; c < 4; ++c) rv[c] = q == 0 ? t[0][c] : q == 1 ? t[1][c] : q == 2 ? t[2][c] : t[3][c];
+            if (tx == (p >> 2)) {
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+                for (int a = 0; a < 4; ++a) colp[buf][ty * 4 + a] = cv[a];
+            }
+            if (ty == (p >> 2)) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if (a == (p & 3)) rowp[buf][tx * 4 + c] = t[a][c];
+                for (int c = 0; c < 4; ++c) rowp[buf][tx * 4 + c] = rv[c];
+            }
         }
         __syncthreads();
         const double pinv = 1.0 / colp[buf][p];
@@ -601,18 +714,18 @@ __global__ __launch_bounds__(256) void gj_pivot_kernel(int32_t n, int32_t p0, in
         for (int a = 0; a < 4; ++a) cp[a] = colp[buf][ty * 4 + a];
 #pragma unroll
         for (int c = 0; c < 4; ++c) rw[c] = rowp[buf][tx * 4 + c];
+        // branch-free: the sweep update everywhere, then row p, column p and
+        // the pivot itself by selects
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            const int i = ty * 4 + a;
+            const bool ip = (ty * 4 + a) == p;
+            const double ca = cp[a] * pinv;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const int j = tx * 4 + c;
-                double x = t[a][c];
-                if (i == p && j == p) x = pinv;
-                else if (i == p) x = rw[c] * pinv;
-                else if (j == p) x = -cp[a] * pinv;
-                else x -= cp[a] * rw[c] * pinv;
-                t[a][c] = x;
+                const bool jp = (tx * 4 + c) == p;
+                const double upd = t[a][c] - ca * rw[c];
+                const double rowv = rw[c] * pinv;
+                t[a][c] = ip ? (jp ? pinv : rowv) : (jp ? -ca : upd);
             }
         }
     }
@@ -751,6 +864,61 @@ __global__ __launch_bounds__(kAT) void vc_post_fused_kernel(Sell<V> A, const X *
         out[i] = yi + dinv[i] * (b[i] - s);
     }
 }
+// Small levels (at most kSmallRows rows): kG lanes per row, lane g taking the
+// row's slots g, g + kG, ..., the kG partial sums combined by a fixed
+// butterfly, so a row's gathers are spread over several lanes and fewer
+// dependent loads sit on one lane.  The lanes of one slot index read
+// consecutive rows (coalesced).  MODE 0: out = b - A x.  MODE 1: out = x +
+// D^-1 (b - A x).  MODE 2: with y = D^-1 b + P e, out = y + D^-1 (b - A y).
+// MODE 3: with y = x + P e, out = y + D^-1 (b - A y).
+constexpr int kG = 4;
+constexpr int kRowsPerWave = 64 / kG;
+template <int MODE, class V, class X>
+__global__ __launch_bounds__(kAT) void vc_small_kernel(Sell<V> A, const X *__restrict__ dinv,
+                                                       const X *__restrict__ b, const X *__restrict__ x,
+                                                       const int32_t *__restrict__ agg, const X *__restrict__ e,
+                                                       X *__restrict__ out, const PcgState *st) {
+    if (st && st->done) return;
+    const int lane = threadIdx.x & 63;
+    const int g = lane / kRowsPerWave, rr = lane % kRowsPerWave;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    auto f = [&](int32_t j) -> X {
+        if constexpr (MODE <= 1) return x[j];
+        else if constexpr (MODE == 2) return dinv[j] * b[j] + e[agg[j]];
+        else return x[j] + e[agg[j]];
+    };
+    for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w * kRowsPerWave < A.n; w += nw) {
+        const int32_t i = (int32_t)(w * kRowsPerWave) + rr;
+        X s0 = 0, s1 = 0;
+        if (i < A.n) {
+            const int64_t b1 = A.ptr[(i >> 6) + 1];
+            int64_t q = A.ptr[i >> 6] + (i & 63) + (int64_t)g * 64;
+            for (; q + kG * 64 < b1; q += 2 * kG * 64) {
+                s0 += (X)A.val[q] * f(A.col[q]);
+                s1 += (X)A.val[q + kG * 64] * f(A.col[q + kG * 64]);
+            }
+            if (q < b1) s0 += (X)A.val[q] * f(A.col[q]);
+        }
+        X sum = s0 + s1;
+#pragma unroll
+        for (int o = kRowsPerWave; o < 64; o <<= 1) sum += __shfl_xor(sum, o, 64);
+        if (g == 0 && i < A.n) {
+            if constexpr (MODE == 0) {
+                out[i] = b[i] - sum;
+            } else {
+                X yi;
+                if constexpr (MODE == 1) yi = x[i];
+                else if constexpr (MODE == 2) yi = dinv[i] * b[i] + e[agg[i]];
+                else yi = x[i] + e[agg[i]];
+                out[i] = yi + dinv[i] * (b[i] - sum);
+            }
+        }
+    }
+}
+static inline unsigned grid_small(int32_t n) {
+    return (unsigned)std::max<int64_t>(1, ((int64_t)n * kG + kAT - 1) / kAT);
+}
+
 // dense coarse solve x = Ainv b: one wavefront per row, lanes along the
 // (contiguous) row, fixed-order wave reduction
 template <class X>
@@ -832,17 +1000,18 @@ void amg_launch_members(hipStream_t s, int32_t n, int32_t nc, const int32_t *agg
     ALAUNCH(members_rank_kernel, reduce_grid((int64_t)nc * 64, kAT), kAT, nc, ptr, tmp, rows);
 }
 void amg_launch_collapse(hipStream_t s, Sell<double> A, const int32_t *agg, int32_t *Jcol, int32_t *apJ,
-                         double *apv) {
+                         double *apv, int32_t *apn, int32_t *spill, int *nspill) {
     ALAUNCH(agg_col_kernel, gridv(A.n), kAT, A, agg, Jcol);
-    ALAUNCH(ap_collapse_kernel, gridv(A.n), kAT, A, Jcol, apJ, apv);
+    ALAUNCH(ap_collapse_kernel, gridv(A.n), kAT, A, Jcol, apJ, apv, apn, spill, nspill);
+    ALAUNCH(ap_spill_kernel<1024>, 2048, 64, A, Jcol, apJ, apv, apn, spill, nspill);
 }
-void amg_launch_galerkin(hipStream_t s, Sell<double> A, const int32_t *Jcol, const double *apv, const int32_t *mptr,
-                         const int32_t *mrows, int32_t nc, int mode, int32_t *big, int32_t *rowlen,
-                         const int64_t *cptr, int32_t *ccol, double *cval, int *overflow) {
+void amg_launch_galerkin(hipStream_t s, Sell<double> A, const int32_t *Jcol, const double *apv, const int32_t *apn,
+                         const int32_t *mptr, const int32_t *mrows, int32_t nc, int mode, int32_t *big,
+                         int32_t *rowlen, const int64_t *cptr, int32_t *ccol, double *cval, int *overflow) {
     if (nc <= 0) return;
-    ALAUNCH(galerkin_kernel<2048>, nc, 64, A, Jcol, apv, mptr, mrows, nc, mode, big, rowlen, cptr, ccol, cval,
+    ALAUNCH(galerkin_kernel<2048>, nc, 64, A, Jcol, apv, apn, mptr, mrows, nc, mode, big, rowlen, cptr, ccol, cval,
             overflow);
-    ALAUNCH(galerkin_kernel<8192>, nc, 64, A, Jcol, apv, mptr, mrows, nc, mode, big, rowlen, cptr, ccol, cval,
+    ALAUNCH(galerkin_kernel<8192>, nc, 64, A, Jcol, apv, apn, mptr, mrows, nc, mode, big, rowlen, cptr, ccol, cval,
             overflow);
 }
 void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t *width, int64_t *ptr,
@@ -872,21 +1041,33 @@ void amg_launch_dense_inverse(hipStream_t s, Sell<double> A, double *D, double *
 template <class V, class X>
 void amg_launch_pre(hipStream_t s, Sell<V> A, const X *dinv, const X *b, X *x, X *r, const PcgState *st) {
     ALAUNCH(vc_scale_kernel<X>, gridv(A.n), kAT, A.n, dinv, b, x, st);
-    ALAUNCH((vc_resid_kernel<V, X>), gridv(A.n), kAT, A, b, x, r, st);
+    amg_launch_resid<V, X>(s, A, b, x, r, st);
 }
 template <class X>
 void amg_launch_restrict(hipStream_t s, int32_t nc, const int32_t *mptr, const int32_t *mrows, const X *r, X *bc,
                          const X *dinv_c, X *xc, const PcgState *st) {
-    ALAUNCH(vc_restrict_kernel<X>, reduce_grid((int64_t)nc * 64, kAT), kAT, nc, mptr, mrows, r, bc, dinv_c, xc, st);
+    ALAUNCH(vc_restrict_kernel<X>, gridv((int64_t)nc * 64), kAT, nc, mptr, mrows, r, bc, dinv_c, xc, st);
 }
 template <class V, class X>
 void amg_launch_resid(hipStream_t s, Sell<V> A, const X *b, const X *x, X *r, const PcgState *st) {
-    ALAUNCH((vc_resid_kernel<V, X>), gridv(A.n), kAT, A, b, x, r, st);
+    if (A.n <= kSmallRows)
+        ALAUNCH((vc_small_kernel<0, V, X>), grid_small(A.n), kAT, A, (const X *)nullptr, b, x, (const int32_t *)nullptr,
+                (const X *)nullptr, r, st);
+    else
+        ALAUNCH((vc_resid_kernel<V, X>), gridv(A.n), kAT, A, b, x, r, st);
 }
 template <class V, class X>
 void amg_launch_post_fused(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const int32_t *agg, const X *e,
                            X *out, const PcgState *st) {
-    ALAUNCH((vc_post_fused_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, agg, e, out, st);
+    if (A.n <= kSmallRows)
+        ALAUNCH((vc_small_kernel<2, V, X>), grid_small(A.n), kAT, A, dinv, b, (const X *)nullptr, agg, e, out, st);
+    else
+        ALAUNCH((vc_post_fused_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, agg, e, out, st);
+}
+template <class V, class X>
+void amg_launch_post_x(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, const int32_t *agg,
+                       const X *e, X *out, const PcgState *st) {
+    ALAUNCH((vc_small_kernel<3, V, X>), grid_small(A.n), kAT, A, dinv, b, x, agg, e, out, st);
 }
 template <class V, class X>
 void amg_launch_post(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, const int32_t *agg, const X *e,
@@ -904,7 +1085,11 @@ void amg_launch_dense(hipStream_t s, int32_t n, const X *Ainv, const X *b, X *x,
 }
 template <class V, class X>
 void amg_launch_sweep(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, X *out, const PcgState *st) {
-    ALAUNCH((vc_sweep_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, x, out, nullptr, st);
+    if (A.n <= kSmallRows)
+        ALAUNCH((vc_small_kernel<1, V, X>), grid_small(A.n), kAT, A, dinv, b, x, (const int32_t *)nullptr,
+                (const X *)nullptr, out, st);
+    else
+        ALAUNCH((vc_sweep_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, x, out, nullptr, st);
 }
 void launch_to_float(hipStream_t s, int64_t n, const double *a, float *b) {
     if (n > 0) ALAUNCH(to_float_kernel, gridv(n), kAT, n, a, b);
@@ -920,6 +1105,8 @@ void launch_to_double(hipStream_t s, int64_t n, const float *a, double *b) {
                                         const X *, X *, X *, double *, const PcgState *);                          \
     template void amg_launch_post_fused<V, X>(hipStream_t, Sell<V>, const X *, const X *, const int32_t *,         \
                                               const X *, X *, const PcgState *);                                   \
+    template void amg_launch_post_x<V, X>(hipStream_t, Sell<V>, const X *, const X *, const X *, const int32_t *,  \
+                                          const X *, X *, const PcgState *);                                       \
     template void amg_launch_sweep<V, X>(hipStream_t, Sell<V>, const X *, const X *, const X *, X *,               \
                                          const PcgState *);
 VC_INST(double, double)

@@ -19,6 +19,8 @@ void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, co
     ensure(width_, (size_t)n0 / 64 + 2, tr);
     ensure(big_, (size_t)n0 + 1, tr);
     ensure(mtmp_, (size_t)n0 + 1, tr);
+    ensure(apn_, (size_t)n0, tr);
+    ensure(spill_, (size_t)n0, tr);
     ensure(stmp_, 2 * ((size_t)n0 / 1024 + 4), tr);
     ensure(jcol_, (size_t)stored0, tr);
     ensure(apv_, (size_t)stored0, tr);
@@ -64,12 +66,12 @@ void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, co
         ensure(jcol_, (size_t)lv.stored, tr);
         ensure(apv_, (size_t)lv.stored, tr);
         ensure(apj_, (size_t)lv.stored, tr);
-        amg_launch_collapse(s, lv.A, lv.agg.p, jcol_.p, apj_.p, apv_.p);
+        amg_launch_collapse(s, lv.A, lv.agg.p, jcol_.p, apj_.p, apv_.p, apn_.p, spill_.p, counters_.p + 62);
         if ((int)L.size() <= l + 1) L.emplace_back(new AmgLevel());
         AmgLevel &cv = *L[l + 1];
         const int32_t ns = (nc + 63) / 64;
         ensure(cv.ptr, (size_t)ns + 1, tr);
-        amg_launch_galerkin(s, lv.A, apj_.p, apv_.p, lv.mptr.p, lv.mrows.p, nc, 0, big_.p, rowlen_.p, nullptr,
+        amg_launch_galerkin(s, lv.A, apj_.p, apv_.p, apn_.p, lv.mptr.p, lv.mrows.p, nc, 0, big_.p, rowlen_.p, nullptr,
                             nullptr, nullptr, counters_.p + 63);
         amg_launch_slices(s, nc, rowlen_.p, width_.p, cv.ptr.p, level_nnz.p + l + 1);
         int64_t hv[2];
@@ -80,7 +82,7 @@ void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, co
         const int64_t stored = hv[0];
         ensure(cv.col, (size_t)stored, tr);
         ensure(cv.val, (size_t)stored, tr);
-        amg_launch_galerkin(s, lv.A, apj_.p, apv_.p, lv.mptr.p, lv.mrows.p, nc, 1, big_.p, rowlen_.p, cv.ptr.p,
+        amg_launch_galerkin(s, lv.A, apj_.p, apv_.p, apn_.p, lv.mptr.p, lv.mrows.p, nc, 1, big_.p, rowlen_.p, cv.ptr.p,
                             cv.col.p, cv.val.p, counters_.p + 63);
         amg_launch_slice_tail(s, nc, cv.ptr.p, cv.col.p, cv.val.p);
         cv.n = nc;
@@ -202,10 +204,16 @@ void Amg::cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bo
     amg_launch_restrict<X>(s, cv.n, lv.mptr.p, lv.mrows.p, tmp, bc, coarse_x ? dinv_c : nullptr,
                            coarse_x ? xc : nullptr, st);
     cycle<V, X>(s, l + 1, bc, ec, st, coarse_x, nullptr);
-    // y = x + P e into tmp and the first post-sweep into xs, then nu - 1
-    // more sweeps, the last one into out (levels >= 1 only: no r.z partials)
-    amg_launch_post<V, X>(s, A, dinv, b, xs, lv.agg.p, ec, tmp, xs, nullptr, st);
+    // the first post-sweep from y = x + P e (small levels: one kernel into tmp;
+    // otherwise y into tmp and the sweep into xs), then nu - 1 more sweeps,
+    // the last one into out (levels >= 1 only: no r.z partials)
     X *src = xs, *dst = tmp;
+    if (lv.n <= kSmallRows) {
+        amg_launch_post_x<V, X>(s, A, dinv, b, xs, lv.agg.p, ec, tmp, st);
+        std::swap(src, dst);
+    } else {
+        amg_launch_post<V, X>(s, A, dinv, b, xs, lv.agg.p, ec, tmp, xs, nullptr, st);
+    }
     for (int k = 1; k < nu; ++k) {
         amg_launch_sweep<V, X>(s, A, dinv, b, src, k == nu - 1 ? out : dst, st);
         std::swap(src, dst);

@@ -1018,7 +1018,7 @@ size_t vag_estimate_footprint(int64_t nn, int64_t nc, int64_t nf, const vag_opti
     const double nrow = Nn + Nc + Nf, tst = 2.0 * (8 * Nc + 6 * Nf) + 64.0 * 16;
     b += 24 * nrow + 12 * tst + 12 * nrow / 64;                     // transport
     if (o.precond == VAG_PC_AMG) {
-        double amg = 96 * Nx + 17 * S + 0.15 * (12 * S + 96 * Nx);
+        double amg = 104 * Nx + 17 * S + 0.15 * (12 * S + 104 * Nx);
         if (o.precision == VAG_MIXED) amg += 4.6 * S + 40 * Nx;
         if (o.precision == VAG_MIXED_IR) amg += 8 * S + 8 * Nx + 4.6 * S + 64 * Nx;
         b += 1.125 * amg + 1.5 * 1024 * 1024;                       // + dense coarsest inverse
