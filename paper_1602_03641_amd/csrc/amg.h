@@ -14,8 +14,12 @@ constexpr int32_t kSmallRows = 65536;
 
 // kernel launchers (amg.hip)
 void amg_launch_diag(hipStream_t s, Sell<double> A, double *diag, double *dinv);
-void amg_launch_mis(hipStream_t s, Sell<double> A, const double *diag, double theta, int rounds, uint64_t *T,
-                    uint64_t *T1, int *undecided, int32_t *flag, int32_t *hpin, uint8_t *strongq);
+// roots of the coarsening (flag); scol: a stored-size scratch array;
+// undecided: rounds * kCntSlots * kCntStride zeroed counters; hcnt: pinned
+// host memory of kCntSlots * kCntStride ints
+constexpr int kCntSlots = 16, kCntStride = 32, kMisRounds = 48;
+void amg_launch_mis(hipStream_t s, Sell<double> A, const double *diag, double theta, int rounds, uint32_t *T,
+                    uint32_t *T1, int *undecided, int32_t *flag, int *hcnt, int32_t *scol);
 void amg_launch_scan(hipStream_t s, int32_t n, const int32_t *in, int32_t *out, int32_t *tmp);
 void amg_launch_aggregate(hipStream_t s, Sell<double> A, const double *diag, double theta, const int32_t *root,
                           const int32_t *rid, int32_t *agg1, int32_t *agg, int32_t *lonely);
@@ -29,8 +33,9 @@ void amg_launch_collapse(hipStream_t s, Sell<double> A, const int32_t *agg, int3
 void amg_launch_galerkin(hipStream_t s, Sell<double> A, const int32_t *Jcol, const double *apv, const int32_t *apn,
                          const int32_t *mptr, const int32_t *mrows, int32_t nc, int mode, int32_t *big,
                          int32_t *rowlen, const int64_t *cptr, int32_t *ccol, double *cval, int *overflow);
-// slice widths and pointers from row lengths; adds the number of entries to *nnz
-void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t *width, int64_t *ptr,
+// slice widths and pointers from row lengths; *nnz = the number of entries
+// (cnt: one int per slice, scratch)
+void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t *width, int32_t *cnt, int64_t *ptr,
                        unsigned long long *nnz);
 void amg_launch_slice_tail(hipStream_t s, int32_t n, const int64_t *ptr, int32_t *col, double *val);
 // D = A^-1 (dense, row-major); work holds 128 * A.n doubles
@@ -123,13 +128,12 @@ class Amg {
     static constexpr int32_t kFusedPostRows = kSmallRows;
 
   private:
-    DBuf<uint64_t> T_, T1_;
-    DBuf<int32_t> flag_, rid_, agg1_, lonely_, lid_, cnt_, cursor_, rowlen_, width_, big_, mtmp_, stmp_, jcol_, apn_, spill_;
+    DBuf<uint32_t> T_, T1_;
+    DBuf<int32_t> flag_, rid_, agg1_, lonely_, lid_, cnt_, cursor_, rowlen_, width_, big_, mtmp_, stmp_, jcol_, apn_, spill_, scnt_;
     DBuf<double> apv_;
     DBuf<int32_t> apj_;
-    DBuf<uint8_t> strong_;
-    DBuf<int> counters_;
-    int32_t *h_ = nullptr;  // pinned host scratch
+    DBuf<int> counters_, mis_cnt_;
+    int32_t *h_ = nullptr;  // pinned host scratch, 1024 ints
     AmgOptions o_;
     template <class V, class X>
     void cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bool x_ready, double *rz);

@@ -4,9 +4,10 @@
 // Coarsening (one level):
 //   strength   j is a strong neighbour of i if |a_ij| >= theta sqrt(|a_ii a_jj|)
 //   roots      a distance-2 maximal independent set of the strength graph,
-//              found by rounds of 2-hop max propagation of (state, hash, index)
-//              keys; a fixed number of rounds, later rounds exit at once when
-//              nothing is left undecided (no host synchronisation)
+//              found by rounds of 2-hop max propagation of (state, priority)
+//              keys, the priority a bijective hash of the row index; later
+//              rounds exit at once when nothing is left undecided (the host
+//              looks every fourth round)
 //   aggregates each root starts one; other nodes join their strongest root
 //              neighbour, then the strongest already-aggregated neighbour
 //   P          piecewise-constant interpolation (one 1 per row)
@@ -38,15 +39,20 @@ static inline unsigned gridv(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 1 << 20));
 }
 
-__device__ inline uint32_t mix32(uint32_t x) {
-    x ^= x >> 16;
-    x *= 0x7feb352du;
+// A bijection of [0, 2^30): odd multipliers and right xor-shifts are each
+// invertible modulo 2^30, so distinct rows get distinct priorities.
+__device__ inline uint32_t perm30(uint32_t x) {
+    constexpr uint32_t kM = (1u << 30) - 1;
+    x &= kM;
+    x = (x * 0x2c1b3c6du) & kM;
     x ^= x >> 15;
-    x *= 0x846ca68bu;
-    x ^= x >> 16;
+    x = (x * 0x297a2d39u) & kM;
+    x ^= x >> 13;
     return x;
 }
-__device__ inline int rank_of(uint64_t t) { return (int)(t >> 62); }
+// MIS keys: state in the top two bits (2 root, 1 undecided, 0 out), the
+// row's priority below
+__device__ inline int rank_of(uint32_t t) { return (int)(t >> 30); }
 
 template <class V>
 __device__ inline bool strong(const V *val, const int32_t *col, int64_t q, int32_t i, double di,
@@ -75,63 +81,91 @@ __global__ __launch_bounds__(kAT) void amg_diag_kernel(Sell<double> A, double *_
     }
 }
 
-// strong[q] = 1 if entry q is a strong off-diagonal coupling
+// scol[q] = column of entry q if it is a strong off-diagonal coupling, else
+// the row itself (so the MIS passes gather without branches: a row's own key
+// never changes a maximum that already includes it)
 __global__ __launch_bounds__(kAT) void strength_kernel(Sell<double> A, const double *__restrict__ diag, double theta,
-                                                       uint8_t *__restrict__ strongq) {
+                                                       int32_t *__restrict__ scol) {
     GS(i, A.n) {
         const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
         const double di = diag[i];
         for (int64_t q = b0 + (i & 63); q < b1; q += 64) {
             int32_t j;
             double s;
-            strongq[q] = strong(A.val, A.col, q, (int32_t)i, di, diag, theta, j, s) ? 1 : 0;
+            scol[q] = strong(A.val, A.col, q, (int32_t)i, di, diag, theta, j, s) ? j : (int32_t)i;
         }
     }
 }
 
-__global__ __launch_bounds__(kAT) void mis_init_kernel(int32_t n, uint64_t *__restrict__ T) {
-    GS(i, n) T[i] = (1ull << 62) | ((uint64_t)(mix32((uint32_t)i) & 0x3fffffffu) << 32) | (uint64_t)(uint32_t)i;
+__global__ __launch_bounds__(kAT) void mis_init_kernel(int32_t n, uint32_t *__restrict__ T) {
+    GS(i, n) T[i] = (1u << 30) | perm30((uint32_t)i);
+}
+
+// max of key[] over row i and its strong neighbours, four gathers in flight
+__device__ inline uint32_t strong_max(const int64_t *__restrict__ ptr, const int32_t *__restrict__ scol, int32_t i,
+                                      const uint32_t *__restrict__ key) {
+    const int64_t b1 = ptr[(i >> 6) + 1];
+    int64_t q = ptr[i >> 6] + (i & 63);
+    uint32_t m0 = key[i], m1 = 0, m2 = 0, m3 = 0;
+    for (; q + 192 < b1; q += 256) {
+        m0 = max(m0, key[scol[q]]);
+        m1 = max(m1, key[scol[q + 64]]);
+        m2 = max(m2, key[scol[q + 128]]);
+        m3 = max(m3, key[scol[q + 192]]);
+    }
+    for (; q < b1; q += 64) m0 = max(m0, key[scol[q]]);
+    return max(max(m0, m1), max(m2, m3));
+}
+
+// Per-round counts of undecided rows, spread over kCntSlots counters 128 bytes
+// apart: device-wide atomics on one address serialise, and thousands of
+// blocks adding to a single counter cost more than the round itself.
+__device__ inline bool any_count(const int *__restrict__ c) {
+    const int lane = threadIdx.x & 63;
+    const int v = lane < kCntSlots ? c[lane * kCntStride] : 0;
+    return __ballot(v != 0) != 0;
 }
 
 // Tout[i] = max of T over {i} and its strong neighbours
-__global__ __launch_bounds__(kAT) void mis_max_kernel(Sell<double> A, const uint8_t *__restrict__ strongq,
-                                                      const uint64_t *__restrict__ Tin, uint64_t *__restrict__ Tout,
-                                                      const int *__restrict__ active) {
-    if (active && *active == 0) return;
-    GS(i, A.n) {
-        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
-        uint64_t m = Tin[i];
-        for (int64_t q = b0 + (i & 63); q < b1; q += 64)
-            if (strongq[q]) m = max(m, Tin[A.col[q]]);
-        Tout[i] = m;
-    }
+__global__ __launch_bounds__(kAT) void mis_max_kernel(int32_t n, const int64_t *__restrict__ ptr,
+                                                      const int32_t *__restrict__ scol, const uint32_t *__restrict__ Tin,
+                                                      uint32_t *__restrict__ Tout, const int *__restrict__ active) {
+    if (active && !any_count(active)) return;
+    GS(i, n) Tout[i] = strong_max(ptr, scol, (int32_t)i, Tin);
 }
 
 // second hop, then the decision of undecided nodes
-__global__ __launch_bounds__(kAT) void mis_select_kernel(Sell<double> A, const uint8_t *__restrict__ strongq,
-                                                         const uint64_t *__restrict__ T1, uint64_t *__restrict__ T,
+__global__ __launch_bounds__(kAT) void mis_select_kernel(int32_t n, const int64_t *__restrict__ ptr,
+                                                         const int32_t *__restrict__ scol,
+                                                         const uint32_t *__restrict__ T1, uint32_t *__restrict__ T,
                                                          int *__restrict__ undecided, const int *__restrict__ active) {
-    if (active && *active == 0) return;
+    __shared__ int wc[kAT / 64];
+    if (active && !any_count(active)) return;  // uniform over the block: every wave reads the same counters
     int cnt = 0;
-    GS(i, A.n) {
-        const uint64_t own = T[i];
+    GS(i, n) {
+        const uint32_t own = T[i];
         if (rank_of(own) != 1) continue;
-        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
-        uint64_t m = T1[i];
-        for (int64_t q = b0 + (i & 63); q < b1; q += 64)
-            if (strongq[q]) m = max(m, T1[A.col[q]]);
+        const uint32_t m = strong_max(ptr, scol, (int32_t)i, T1);
         if (m == own)
-            T[i] = (own & ~(3ull << 62)) | (2ull << 62);  // root
+            T[i] = (own & ((1u << 30) - 1)) | (2u << 30);  // root
         else if (rank_of(m) == 2)
-            T[i] = own & ~(3ull << 62);  // a root lies within distance 2
+            T[i] = own & ((1u << 30) - 1);  // a root lies within distance 2
         else
             ++cnt;
     }
-    if (cnt) atomicAdd(undecided, cnt);  // integer count, order-independent
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kAT / 64; ++w) t += wc[w];
+        if (t) atomicAdd(undecided + (blockIdx.x % kCntSlots) * kCntStride, t);  // integer count, order-independent
+    }
 }
 
 // roots (and nodes left undecided) flagged 1
-__global__ __launch_bounds__(kAT) void mis_flag_kernel(int32_t n, const uint64_t *__restrict__ T,
+__global__ __launch_bounds__(kAT) void mis_flag_kernel(int32_t n, const uint32_t *__restrict__ T,
                                                        int32_t *__restrict__ flag) {
     GS(i, n) flag[i] = rank_of(T[i]) >= 1 ? 1 : 0;
 }
@@ -618,8 +652,7 @@ __global__ __launch_bounds__(64) void galerkin_kernel(Sell<double> A, const int3
 
 // slice widths (max row length of each 64-row slice)
 __global__ __launch_bounds__(64) void slice_width_kernel(int32_t n, const int32_t *__restrict__ rowlen,
-                                                         int32_t *__restrict__ width,
-                                                         unsigned long long *__restrict__ nnz) {
+                                                         int32_t *__restrict__ width, int32_t *__restrict__ cnt) {
     const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
     int c = i < n ? rowlen[i] : 0;
     int t = c;
@@ -630,7 +663,7 @@ __global__ __launch_bounds__(64) void slice_width_kernel(int32_t n, const int32_
     }
     if (threadIdx.x == 0) {
         width[blockIdx.x] = c;
-        atomicAdd(nnz, (unsigned long long)t);  // integer count: order-independent
+        cnt[blockIdx.x] = t;
     }
 }
 // rows beyond n in the last slice: padding pointing at row 0
@@ -660,20 +693,42 @@ __global__ __launch_bounds__(kAT) void dense_scatter_kernel(Sell<double> A, doub
 }
 // In-place blocked Gauss-Jordan inversion of an SPD matrix (no pivoting
 // needed: every pivot block is a Schur complement of an SPD matrix, hence SPD).
-// With P the next kGJ pivots, R the other indices and B = M[P,P]^-1 the block
-// step is
-//   M[P,P] = B,  M[P,R] = B M[P,R],  M[R,P] = -M[R,P] B,
-//   M[R,R] = M[R,R] + M[R,P]_new M[P,R]_old,
-// done by three kernels: the k x k inverse in LDS (one workgroup), the two
-// panels (old M[P,R] saved aside), the rank-k update of M[R,R].
+// With P the next kGJ indices, R the others and B = M[P,P]^-1 the block step
+// is
+//   V = B M[P,R],  W = M[R,P] B,
+//   M[R,R] = M[R,R] - M[R,P] V,  M[P,R] = V,  M[R,P] = -W,  M[P,P] = B,
+// done by four kernels: the kGJ x kGJ inverse in one workgroup, the two
+// panels V and W (64 x 64 tiles in LDS), the update of M[R,R] (64 x 64
+// output tiles, the operands staged in LDS), and the write-back of the
+// panels.  Only M[P,*] and M[*,P] are read before the write-back, so the
+// update needs no copy of the old panels.
 constexpr int kGJ = 64;
+constexpr int kQ = 4;  // pivots eliminated together inside the diagonal block
 
 // B = M[P,P]^-1 (k <= kGJ), written back in place.  256 threads as a 16 x 16
 // grid, each keeping a 4 x 4 tile of the (identity-padded) 64 x 64 block in
-// registers; per pivot the owners publish the pivot column and row in LDS
-// (double-buffered, one barrier per pivot).
+// registers.  The elimination takes kQ pivots per step: the owners publish
+// the kQ pivot rows and columns in LDS (double-buffered, one barrier per
+// step), every thread inverts the kQ x kQ pivot block itself and updates its
+// tile by the block rule above, restricted to the diagonal block.
+__device__ inline void inv4(double b[kQ][kQ]) {
+#pragma unroll
+    for (int p = 0; p < kQ; ++p) {
+        const double pinv = 1.0 / b[p][p];
+        double pr[kQ];  // the pivot row before this step
+#pragma unroll
+        for (int j = 0; j < kQ; ++j) pr[j] = b[p][j];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const double ca = b[i][p] * pinv;
+#pragma unroll
+            for (int j = 0; j < kQ; ++j)
+                b[i][j] = (i == p) ? (j == p ? pinv : pr[j] * pinv) : (j == p ? -ca : b[i][j] - ca * pr[j]);
+        }
+    }
+}
 __global__ __launch_bounds__(256) void gj_pivot_kernel(int32_t n, int32_t p0, int32_t k, double *__restrict__ M) {
-    __shared__ double colp[2][kGJ], rowp[2][kGJ];
+    __shared__ double rowp[2][kQ][kGJ], colp[2][kGJ][kQ];
     const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
     double t[4][4];
 #pragma unroll
@@ -687,47 +742,61 @@ __global__ __launch_bounds__(256) void gj_pivot_kernel(int32_t n, int32_t p0, in
             const double x = M[(int64_t)(p0 + (in ? i : 0)) * n + p0 + (in ? j : 0)];
             t[a][c] = in ? x : (i == j ? 1.0 : 0.0);
         }
-    for (int p = 0; p < k; ++p) {
-        const int buf = p & 1;
-        // owners of column p and of row p publish them
-        {
-            const int q = p & 3;
-            // the thread's entries in column p (one per tile row) and row p (one per tile column)
-            double cv[4], rv[4];
+    const int nsteps = (k + kQ - 1) / kQ;
+    for (int pb = 0; pb < nsteps; ++pb) {
+        const int buf = pb & 1;
+        if (ty == pb) {
 #pragma unroll
-            for (int a = 0; a < 4; ++a) cv[a] = q == 0 ? t[a][0] : q == 1 ? t[a][1] : q == 2 ? t[a][2] : t[a][3];
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) rv[c] = q == 0 ? t[0][c] : q == 1 ? t[1][c] : q == 2 ? t[2][c] : t[3][c];
-            if (tx == (p >> 2)) {
+                for (int c = 0; c < 4; ++c) rowp[buf][a][tx * 4 + c] = t[a][c];
+        }
+        if (tx == pb) {
 #pragma unroll
-                for (int a = 0; a < 4; ++a) colp[buf][ty * 4 + a] = cv[a];
-            }
-            if (ty == (p >> 2)) {
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) rowp[buf][tx * 4 + c] = rv[c];
-            }
+                for (int c = 0; c < 4; ++c) colp[buf][ty * 4 + a][c] = t[a][c];
         }
         __syncthreads();
-        const double pinv = 1.0 / colp[buf][p];
-        double cp[4], rw[4];
+        double B[kQ][kQ], C[4][kQ], R[kQ][4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) cp[a] = colp[buf][ty * 4 + a];
+        for (int a = 0; a < kQ; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) rw[c] = rowp[buf][tx * 4 + c];
-        // branch-free: the sweep update everywhere, then row p, column p and
-        // the pivot itself by selects
+            for (int c = 0; c < kQ; ++c) B[a][c] = rowp[buf][a][pb * 4 + c];
+        inv4(B);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const bool ip = (ty * 4 + a) == p;
-            const double ca = cp[a] * pinv;
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < kQ; ++c) C[a][c] = colp[buf][ty * 4 + a][c];
+#pragma unroll
+        for (int a = 0; a < kQ; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) R[a][c] = rowp[buf][a][tx * 4 + c];
+        // CB = C B (rows of the tile against the pivot block)
+        double CB[4][kQ];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < kQ; ++c) {
+                double v = 0.0;
+#pragma unroll
+                for (int m = 0; m < kQ; ++m) v += C[a][m] * B[m][c];
+                CB[a][c] = v;
+            }
+        const bool ip = ty == pb, jp = tx == pb;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const bool jp = (tx * 4 + c) == p;
-                const double upd = t[a][c] - ca * rw[c];
-                const double rowv = rw[c] * pinv;
-                t[a][c] = ip ? (jp ? pinv : rowv) : (jp ? -ca : upd);
+                double upd = t[a][c], br = 0.0;
+#pragma unroll
+                for (int m = 0; m < kQ; ++m) {
+                    upd -= CB[a][m] * R[m][c];
+                    br += B[a][m] * R[m][c];
+                }
+                const double bb = a < kQ && c < kQ ? B[a & (kQ - 1)][c & (kQ - 1)] : 0.0;
+                t[a][c] = ip ? (jp ? bb : br) : (jp ? -CB[a][c & (kQ - 1)] : upd);
             }
-        }
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -738,48 +807,129 @@ __global__ __launch_bounds__(256) void gj_pivot_kernel(int32_t n, int32_t p0, in
         }
 }
 
-// saves the panels: oc[l][t] = M[p0+l][t], orow[t][l] = M[t][p0+l] (t outside P)
-__global__ __launch_bounds__(256) void gj_save_kernel(int32_t n, int32_t p0, int32_t k, const double *__restrict__ M,
-                                                      double *__restrict__ oc, double *__restrict__ orow) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)n * k;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t t = e / k;
-        const int l = (int)(e % k);
-        if (t >= p0 && t < p0 + k) continue;
-        oc[(int64_t)l * n + t] = M[(int64_t)(p0 + l) * n + t];
-        orow[t * k + l] = M[t * n + p0 + l];
+// Panels of the step, 64 x 64 tiles: blockIdx.y == 0: V[l][t] = sum_m B[l][m]
+// M[p0+m][t] (64 x n, row-major); blockIdx.y == 1: W[t][l] = sum_m M[t][p0+m]
+// B[m][l] (n x 64, row-major).  Tiles of P itself are skipped.
+__global__ __launch_bounds__(256) void gj_panel_kernel(int32_t n, int32_t p0, int32_t k,
+                                                       const double *__restrict__ M, double *__restrict__ V,
+                                                       double *__restrict__ W) {
+    __shared__ double Bs[kGJ][kGJ + 1], Ps[kGJ][kGJ + 1];
+    const int32_t t0 = blockIdx.x * kGJ;
+    if (t0 == p0) return;
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    const bool left = blockIdx.y == 1;
+    // Bs = B (zero-padded), Ps = the panel tile: M[P, T] (V) or M[T, P] (W)
+    // a fixed trip count, unrolled, so that all the tile loads are in flight together
+#pragma unroll
+    for (int it = 0; it < kGJ * kGJ / 256; ++it) {
+        const int e = threadIdx.x + it * 256;
+        const int r = e >> 6, c = e & 63;
+        // clamped addresses and selects rather than conditional loads, so that the
+        // loads of all iterations are issued before the first wait
+        const bool ib = r < k && c < k;
+        const double bv = M[(int64_t)(p0 + (ib ? r : 0)) * n + p0 + (ib ? c : 0)];
+        Bs[r][c] = ib ? bv : 0.0;
+        const bool ip = left ? (t0 + r < n && c < k) : (r < k && t0 + c < n);
+        const int64_t row = left ? (ip ? t0 + r : p0) : p0 + (ip ? r : 0);
+        const int64_t col = left ? p0 + (ip ? c : 0) : (ip ? t0 + c : p0);
+        const double pv = M[row * n + col];
+        Ps[r][c] = ip ? pv : 0.0;
     }
-}
-
-// M[P,t] = B oc[.,t] and M[t,P] = -orow[t,.] B, one (t, l) pair per thread
-__global__ __launch_bounds__(256) void gj_panel_kernel(int32_t n, int32_t p0, int32_t k, double *__restrict__ M,
-                                                       const double *__restrict__ oc,
-                                                       const double *__restrict__ orow) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)n * k;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t t = e / k;
-        const int l = (int)(e % k);
-        if (t >= p0 && t < p0 + k) continue;
-        double sc = 0.0, sr = 0.0;
-        for (int q = 0; q < k; ++q) {
-            sc += M[(int64_t)(p0 + l) * n + p0 + q] * oc[(int64_t)q * n + t];
-            sr += orow[t * k + q] * M[(int64_t)(p0 + q) * n + p0 + l];
+    __syncthreads();
+    double acc[4][4] = {};
+    if (!left) {
+        // V tile: rows l (4 ty + a), columns t (4 tx + c)
+        for (int m = 0; m < k; ++m) {
+            double bv[4], pv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) bv[a] = Bs[ty * 4 + a][m];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) pv[c] = Ps[m][tx * 4 + c];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[a][c] += bv[a] * pv[c];
         }
-        M[(int64_t)(p0 + l) * n + t] = sc;
-        M[t * n + p0 + l] = -sr;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int l = ty * 4 + a, t = t0 + tx * 4 + c;
+                if (l < k && t < n) V[(int64_t)l * n + t] = acc[a][c];
+            }
+    } else {
+        // W tile: rows t (4 ty + a), columns l (4 tx + c)
+        for (int m = 0; m < k; ++m) {
+            double pv[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) pv[a] = Ps[ty * 4 + a][m];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) bv[c] = Bs[m][tx * 4 + c];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[a][c] += pv[a] * bv[c];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int t = t0 + ty * 4 + a, l = tx * 4 + c;
+                if (t < n && l < k) W[(int64_t)t * kGJ + l] = acc[a][c];
+            }
     }
 }
 
-// M[i][j] += sum_l M[i][p0+l] oc[l][j] for i, j outside P
+// M[i][j] -= sum_l M[i][p0+l] V[l][j] for i, j outside P, one 64 x 64 output
+// tile per workgroup
 __global__ __launch_bounds__(256) void gj_update_kernel(int32_t n, int32_t p0, int32_t k, double *__restrict__ M,
-                                                        const double *__restrict__ oc) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)n * n;
+                                                        const double *__restrict__ V) {
+    __shared__ double Ls[kGJ][kGJ + 1], Vs[kGJ][kGJ + 1];
+    const int32_t i0 = blockIdx.y * kGJ, j0 = blockIdx.x * kGJ;
+    if (i0 == p0 || j0 == p0) return;
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+#pragma unroll
+    for (int it = 0; it < kGJ * kGJ / 256; ++it) {
+        const int e = threadIdx.x + it * 256;
+        const int r = e >> 6, c = e & 63;
+        const bool il = i0 + r < n && c < k, iv = r < k && j0 + c < n;
+        const double lv = M[(int64_t)(il ? i0 + r : p0) * n + p0 + (il ? c : 0)];
+        const double vv = V[(int64_t)(iv ? r : 0) * n + (iv ? j0 + c : 0)];
+        Ls[r][c] = il ? lv : 0.0;
+        Vs[r][c] = iv ? vv : 0.0;
+    }
+    __syncthreads();
+    double acc[4][4] = {};
+    for (int l = 0; l < k; ++l) {
+        double lv[4], vv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) lv[a] = Ls[ty * 4 + a][l];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) vv[c] = Vs[l][tx * 4 + c];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[a][c] += lv[a] * vv[c];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = i0 + ty * 4 + a, j = j0 + tx * 4 + c;
+            if (i < n && j < n) M[(int64_t)i * n + j] -= acc[a][c];
+        }
+}
+
+// M[P,t] = V[.,t] and M[t,P] = -W[t,.] for t outside P
+__global__ __launch_bounds__(256) void gj_writeback_kernel(int32_t n, int32_t p0, int32_t k, double *__restrict__ M,
+                                                           const double *__restrict__ V, const double *__restrict__ W) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)n * k;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / n, j = e % n;
-        if ((i >= p0 && i < p0 + k) || (j >= p0 && j < p0 + k)) continue;
-        double s = M[e];
-        for (int l = 0; l < k; ++l) s += M[i * n + p0 + l] * oc[(int64_t)l * n + j];
-        M[e] = s;
+        const int l = (int)(e / n);
+        const int64_t t = e % n;
+        if (t >= p0 && t < p0 + k) continue;
+        M[(int64_t)(p0 + l) * n + t] = V[(int64_t)l * n + t];
+        M[t * n + p0 + l] = -W[t * kGJ + l];
     }
 }
 
@@ -954,19 +1104,21 @@ __global__ __launch_bounds__(kAT) void to_double_kernel(int64_t n, const float *
 void amg_launch_diag(hipStream_t s, Sell<double> A, double *diag, double *dinv) {
     if (A.n > 0) ALAUNCH(amg_diag_kernel, gridv(A.n), kAT, A, diag, dinv);
 }
-void amg_launch_mis(hipStream_t s, Sell<double> A, const double *diag, double theta, int rounds, uint64_t *T,
-                    uint64_t *T1, int *undecided /* [rounds] zeroed */, int32_t *flag, int32_t *hpin,
-                    uint8_t *strongq) {
-    ALAUNCH(strength_kernel, gridv(A.n), kAT, A, diag, theta, strongq);
+void amg_launch_mis(hipStream_t s, Sell<double> A, const double *diag, double theta, int rounds, uint32_t *T,
+                    uint32_t *T1, int *undecided, int32_t *flag, int *hcnt, int32_t *scol) {
+    ALAUNCH(strength_kernel, gridv(A.n), kAT, A, diag, theta, scol);
     ALAUNCH(mis_init_kernel, gridv(A.n), kAT, A.n, T);
     for (int r = 0; r < rounds; ++r) {
-        const int *active = r ? undecided + r - 1 : nullptr;
-        ALAUNCH(mis_max_kernel, gridv(A.n), kAT, A, strongq, T, T1, active);
-        ALAUNCH(mis_select_kernel, gridv(A.n), kAT, A, strongq, T1, T, undecided + r, active);
+        int *cur = undecided + (int64_t)r * kCntSlots * kCntStride;
+        const int *active = r ? cur - kCntSlots * kCntStride : nullptr;
+        ALAUNCH(mis_max_kernel, gridv(A.n), kAT, A.n, A.ptr, scol, T, T1, active);
+        ALAUNCH(mis_select_kernel, gridv(A.n), kAT, A.n, A.ptr, scol, T1, T, cur, active);
         if ((r & 3) == 3 && r + 1 < rounds) {  // stop queueing rounds once nothing is undecided
-            VAG_HIP(hipMemcpyAsync(hpin, undecided + r, sizeof(int), hipMemcpyDeviceToHost, s));
+            VAG_HIP(hipMemcpyAsync(hcnt, cur, kCntSlots * kCntStride * sizeof(int), hipMemcpyDeviceToHost, s));
             VAG_HIP(hipStreamSynchronize(s));
-            if (*hpin == 0) break;
+            bool any = false;
+            for (int k = 0; k < kCntSlots; ++k) any = any || hcnt[k * kCntStride] != 0;
+            if (!any) break;
         }
     }
     ALAUNCH(mis_flag_kernel, gridv(A.n), kAT, A.n, T, flag);
@@ -1014,11 +1166,11 @@ void amg_launch_galerkin(hipStream_t s, Sell<double> A, const int32_t *Jcol, con
     ALAUNCH(galerkin_kernel<8192>, nc, 64, A, Jcol, apv, apn, mptr, mrows, nc, mode, big, rowlen, cptr, ccol, cval,
             overflow);
 }
-void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t *width, int64_t *ptr,
+void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t *width, int32_t *cnt, int64_t *ptr,
                        unsigned long long *nnz) {
     const int32_t ns = (n + 63) / 64;
-    if (ns > 0) ALAUNCH(slice_width_kernel, ns, 64, n, rowlen, width, nnz);
-    launch_slice_scan(s, ns, width, ptr);
+    if (ns > 0) ALAUNCH(slice_width_kernel, ns, 64, n, rowlen, width, cnt);
+    launch_slice_scan(s, ns, width, ptr, cnt, nnz);
 }
 void amg_launch_slice_tail(hipStream_t s, int32_t n, const int64_t *ptr, int32_t *col, double *val) {
     if (n & 63) ALAUNCH(slice_tail_kernel, 1, 64, n, ptr, col, val);
@@ -1027,15 +1179,19 @@ void amg_launch_dense_inverse(hipStream_t s, Sell<double> A, double *D, double *
     const int32_t n = A.n;
     ALAUNCH(dense_from_sell_kernel, gridv((int64_t)n * n), kAT, A, D);
     ALAUNCH(dense_scatter_kernel, gridv(n), kAT, A, D);
-    const unsigned gu = (unsigned)std::min<int64_t>(((int64_t)n * n + 255) / 256, 4096);
-    const unsigned gp = (unsigned)std::min<int64_t>(((int64_t)n * kGJ + 255) / 256, 4096);
-    double *oc = work, *orow = work + (int64_t)kGJ * n;
+    const unsigned nt = (unsigned)((n + kGJ - 1) / kGJ);
+    const unsigned gw = (unsigned)std::min<int64_t>(((int64_t)n * kGJ + 255) / 256, 4096);
+    double *V = work, *W = work + (int64_t)kGJ * n;
     for (int32_t p0 = 0; p0 < n; p0 += kGJ) {
         const int32_t k = std::min(kGJ, n - p0);
         ALAUNCH(gj_pivot_kernel, 1, 256, n, p0, k, D);
-        ALAUNCH(gj_save_kernel, gp, 256, n, p0, k, D, oc, orow);
-        ALAUNCH(gj_panel_kernel, gp, 256, n, p0, k, D, oc, orow);
-        ALAUNCH(gj_update_kernel, gu, 256, n, p0, k, D, oc);
+        if (nt > 1) {
+            hipLaunchKernelGGL(gj_panel_kernel, dim3(nt, 2), dim3(256), 0, s, n, p0, k, D, V, W);
+            VAG_HIP(hipGetLastError());
+            hipLaunchKernelGGL(gj_update_kernel, dim3(nt, nt), dim3(256), 0, s, n, p0, k, D, V);
+            VAG_HIP(hipGetLastError());
+            ALAUNCH(gj_writeback_kernel, gw, 256, n, p0, k, D, V, W);
+        }
     }
 }
 template <class V, class X>

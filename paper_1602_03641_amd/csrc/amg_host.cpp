@@ -11,8 +11,10 @@ Amg::~Amg() {
 
 void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, const AmgOptions &o) {
     o_ = o;
-    if (!h_) VAG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_), 16 * sizeof(int64_t)));
+    if (!h_) VAG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_), 1024 * sizeof(int32_t)));
     const int32_t n0 = A0.n;
+    // the coarsening keys hold a row's priority in 30 bits
+    if (n0 >= (1 << 30)) throw Error(VAG_ERR_UNSUPPORTED, "AMG: more than 2^30 - 1 rows");
     ensure(T_, n0, tr);
     ensure(T1_, n0, tr);
     for (auto *b : {&flag_, &rid_, &agg1_, &lonely_, &lid_, &cnt_, &cursor_, &rowlen_}) ensure(*b, (size_t)n0 + 1, tr);
@@ -25,6 +27,8 @@ void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, co
     ensure(jcol_, (size_t)stored0, tr);
     ensure(apv_, (size_t)stored0, tr);
     ensure(counters_, 64, tr);
+    ensure(mis_cnt_, (size_t)kMisRounds * kCntSlots * kCntStride, tr);
+    ensure(scnt_, (size_t)n0 / 64 + 2, tr);
     ensure(level_nnz, (size_t)std::max(o.max_levels, 1), tr);
     VAG_HIP(hipMemsetAsync(level_nnz.p, 0, level_nnz.n * sizeof(unsigned long long), s));
     if (L.empty()) L.emplace_back(new AmgLevel());
@@ -44,9 +48,10 @@ void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, co
         if (n <= o.coarse_size || l + 1 >= o.max_levels) break;
         // aggregation
         VAG_HIP(hipMemsetAsync(counters_.p, 0, 64 * sizeof(int), s));
-        ensure(strong_, (size_t)lv.stored, tr);
-        amg_launch_mis(s, lv.A, lv.diag.p, o.theta, std::min(o.mis_rounds, 48), T_.p, T1_.p, counters_.p, flag_.p,
-                       h_ + 8, strong_.p);
+        VAG_HIP(hipMemsetAsync(mis_cnt_.p, 0, mis_cnt_.n * sizeof(int), s));
+        ensure(jcol_, (size_t)lv.stored, tr);  // the strong columns until the collapse reuses it
+        amg_launch_mis(s, lv.A, lv.diag.p, o.theta, std::min(o.mis_rounds, kMisRounds), T_.p, T1_.p, mis_cnt_.p,
+                       flag_.p, h_ + 64, jcol_.p);
         amg_launch_scan(s, n, flag_.p, rid_.p, stmp_.p);
         ensure(lv.agg, n, tr);
         amg_launch_aggregate(s, lv.A, lv.diag.p, o.theta, flag_.p, rid_.p, agg1_.p, lv.agg.p, lonely_.p);
@@ -73,7 +78,7 @@ void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, co
         ensure(cv.ptr, (size_t)ns + 1, tr);
         amg_launch_galerkin(s, lv.A, apj_.p, apv_.p, apn_.p, lv.mptr.p, lv.mrows.p, nc, 0, big_.p, rowlen_.p, nullptr,
                             nullptr, nullptr, counters_.p + 63);
-        amg_launch_slices(s, nc, rowlen_.p, width_.p, cv.ptr.p, level_nnz.p + l + 1);
+        amg_launch_slices(s, nc, rowlen_.p, width_.p, scnt_.p, cv.ptr.p, level_nnz.p + l + 1);
         int64_t hv[2];
         VAG_HIP(hipMemcpyAsync(&hv[0], cv.ptr.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipMemcpyAsync(h_ + 2, counters_.p + 63, sizeof(int32_t), hipMemcpyDeviceToHost, s));

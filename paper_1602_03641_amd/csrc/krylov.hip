@@ -15,6 +15,7 @@
 // `done` flag makes every later kernel return at once: the host queues many
 // iterations and reads the flag only now and then.
 #include "reduce.h"
+#include "sell.h"
 
 namespace vag {
 
@@ -24,18 +25,7 @@ int pcg_grid(int64_t n) { return (int)reduce_grid(n, kThreads); }
 
 template <class V, class X>
 __device__ inline double sell_row(const Sell<V> &A, const X *__restrict__ x, int32_t row) {
-    const int64_t b1 = A.ptr[(row >> 6) + 1];
-    int64_t q = A.ptr[row >> 6] + (row & 63);
-    // four independent chains keep several gathers in flight
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    for (; q + 192 < b1; q += 256) {
-        s0 += (double)A.val[q] * (double)x[A.col[q]];
-        s1 += (double)A.val[q + 64] * (double)x[A.col[q + 64]];
-        s2 += (double)A.val[q + 128] * (double)x[A.col[q + 128]];
-        s3 += (double)A.val[q + 192] * (double)x[A.col[q + 192]];
-    }
-    for (; q < b1; q += 64) s0 += (double)A.val[q] * (double)x[A.col[q]];
-    return (s0 + s1) + (s2 + s3);
+    return sell_row_apply<V, double>(A, row, [&](int32_t j) { return (double)x[j]; });
 }
 
 #define GRID_STRIDE(i, n) \

@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kSliceRows) void upwind_count_kernel(
     const int32_t *__restrict__ frac_cell, const uint8_t *__restrict__ dirichlet, const int32_t *__restrict__ ncp,
     const int32_t *__restrict__ ncl, const int32_t *__restrict__ nfp, const int32_t *__restrict__ nfl,
     const double *__restrict__ F_cell, const double *__restrict__ F_cell_frac, const double *__restrict__ F_frac,
-    int32_t *__restrict__ slice_width, uint16_t *__restrict__ meta, unsigned long long *__restrict__ nnz_total) {
+    int32_t *__restrict__ slice_width, uint16_t *__restrict__ meta, int32_t *__restrict__ slice_nnz) {
     // one block = one wavefront = one slice
     const int lane = threadIdx.x;
     const int64_t i = (int64_t)blockIdx.x * kSliceRows + lane;
@@ -306,32 +306,45 @@ __global__ __launch_bounds__(kSliceRows) void upwind_count_kernel(
     }
     if (lane == 0) {
         slice_width[blockIdx.x] = w;
-        atomicAdd(nnz_total, (unsigned long long)sum);  // integer sum: order-independent
+        slice_nnz[blockIdx.x] = sum;
     }
 }
 
-// exclusive scan of 64 * width over the slices, one block
+// exclusive scan of 64 * width over the slices, one block; with cnt, also
+// *total = sum of cnt (the entries without padding)
 __global__ __launch_bounds__(1024) void slice_scan_kernel(int32_t nslice, const int32_t *__restrict__ w,
-                                                          int64_t *__restrict__ ptr) {
-    __shared__ int64_t part[1024];
-    const int t = threadIdx.x;
+                                                          int64_t *__restrict__ ptr, const int32_t *__restrict__ cnt,
+                                                          unsigned long long *__restrict__ total) {
+    __shared__ int64_t wsum[16], csum[16];
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const int32_t chunk = (nslice + 1023) / 1024;
     const int32_t lo = min(nslice, t * chunk), hi = min(nslice, lo + chunk);
-    int64_t s = 0;
-    for (int32_t k = lo; k < hi; ++k) s += (int64_t)w[k] * kSliceRows;
-    part[t] = s;
-    __syncthreads();
-    if (t == 0) {
-        int64_t run = 0;
-        for (int k = 0; k < 1024; ++k) {
-            const int64_t v = part[k];
-            part[k] = run;
-            run += v;
-        }
-        ptr[nslice] = run;
+    int64_t s = 0, c = 0;
+    for (int32_t k = lo; k < hi; ++k) {
+        s += (int64_t)w[k] * kSliceRows;
+        if (cnt) c += cnt[k];
     }
+    // inclusive scan over the block: within each wavefront, then over the 16 wavefront totals
+    int64_t v = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if (lane == 63) wsum[wid] = v;
+    if (lane == 0) csum[wid] = c;
     __syncthreads();
-    int64_t run = part[t];
+    int64_t before = 0;
+    for (int k = 0; k < wid; ++k) before += wsum[k];
+    if (t == 1023) ptr[nslice] = before + v;
+    if (t == 0 && total) {
+        unsigned long long tc = 0;
+        for (int k = 0; k < 16; ++k) tc += (unsigned long long)csum[k];
+        *total = tc;
+    }
+    int64_t run = before + v - s;
     for (int32_t k = lo; k < hi; ++k) {
         ptr[k] = run;
         run += (int64_t)w[k] * kSliceRows;
@@ -522,16 +535,16 @@ void launch_upwind_count(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, cons
                          const int32_t *cell_frac, const int32_t *frac_cell, const uint8_t *dirichlet,
                          const int32_t *node_cell_ptr, const int32_t *node_cell, const int32_t *node_frac_ptr,
                          const int32_t *node_frac, const double *F_cell, const double *F_cell_frac,
-                         const double *F_frac, int32_t *slice_width, uint16_t *meta,
-                         unsigned long long *nnz_total) {
+                         const double *F_frac, int32_t *slice_width, uint16_t *meta, int32_t *slice_nnz) {
     const int64_t total = (int64_t)nc + nf + nn;
     hipLaunchKernelGGL(upwind_count_kernel, dim3(nb(total, kSliceRows)), dim3(kSliceRows), 0, s, nc, nf, nn, fmask,
                        cell_frac, frac_cell, dirichlet, node_cell_ptr, node_cell, node_frac_ptr, node_frac, F_cell,
-                       F_cell_frac, F_frac, slice_width, meta, nnz_total);
+                       F_cell_frac, F_frac, slice_width, meta, slice_nnz);
     VAG_HIP(hipGetLastError());
 }
-void launch_slice_scan(hipStream_t s, int32_t nslice, const int32_t *slice_width, int64_t *slice_ptr) {
-    hipLaunchKernelGGL(slice_scan_kernel, dim3(1), dim3(1024), 0, s, nslice, slice_width, slice_ptr);
+void launch_slice_scan(hipStream_t s, int32_t nslice, const int32_t *slice_width, int64_t *slice_ptr,
+                       const int32_t *slice_nnz, unsigned long long *total) {
+    hipLaunchKernelGGL(slice_scan_kernel, dim3(1), dim3(1024), 0, s, nslice, slice_width, slice_ptr, slice_nnz, total);
     VAG_HIP(hipGetLastError());
 }
 void launch_upwind_fill(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,

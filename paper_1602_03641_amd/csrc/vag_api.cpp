@@ -40,7 +40,7 @@ struct vag_handle {
     // results
     DBuf<double> u_node, u_cell, u_frac, F_cell, F_cell_frac, F_frac, phi_cell, phi_frac, phi_node;
     // transport
-    DBuf<int32_t> slice_width, tcol;
+    DBuf<int32_t> slice_width, slice_nnz, tcol;
     DBuf<uint16_t> tmeta;
     DBuf<int64_t> slice_ptr;
     DBuf<double> tval, tdiag, cbuf0, cbuf1, dt4;
@@ -561,6 +561,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         const int64_t nrow = nc + nf + nn;
         const int64_t nslice = (nrow + kSliceRows - 1) / kSliceRows;
         h->slice_width.alloc(nslice, h->tr);
+        h->slice_nnz.alloc(nslice, h->tr);
         h->tmeta.alloc((size_t)nslice * kSliceRows, h->tr);
         h->slice_ptr.alloc(nslice + 1, h->tr);
         h->tdiag.alloc(nrow, h->tr);
@@ -768,11 +769,10 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
                    h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
                    h->F_cell_frac.p, h->F_frac.p, h->phi_cell.p, h->phi_frac.p, h->phi_node.p, h->opt.cfl,
                    h->rparts.p, h->dt4.p);
-        VAG_HIP(hipMemsetAsync(h->cnt.p, 0, sizeof(unsigned long long), s));
         launch_upwind_count(s, S.nc, S.nf, S.nn, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
                             h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
-                            h->F_cell_frac.p, h->F_frac.p, h->slice_width.p, h->tmeta.p, h->cnt.p);
-        launch_slice_scan(s, nslice, h->slice_width.p, h->slice_ptr.p);
+                            h->F_cell_frac.p, h->F_frac.p, h->slice_width.p, h->tmeta.p, h->slice_nnz.p);
+        launch_slice_scan(s, nslice, h->slice_width.p, h->slice_ptr.p, h->slice_nnz.p, h->cnt.p);
         int64_t total = 0;
         VAG_HIP(hipMemcpyAsync(&total, h->slice_ptr.p + nslice, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipMemcpyAsync(h->h_cnt, h->cnt.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));

@@ -272,8 +272,10 @@ void launch_upwind_count(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, cons
                          const int32_t *node_cell_ptr, const int32_t *node_cell,
                          const int32_t *node_frac_ptr, const int32_t *node_frac, const double *F_cell,
                          const double *F_cell_frac, const double *F_frac, int32_t *slice_width,
-                         uint16_t *meta, unsigned long long *nnz_total);
-void launch_slice_scan(hipStream_t s, int32_t nslice, const int32_t *slice_width, int64_t *slice_ptr);
+                         uint16_t *meta, int32_t *slice_nnz);
+// slice_ptr = exclusive scan of 64 * width; with slice_nnz, *total = its sum
+void launch_slice_scan(hipStream_t s, int32_t nslice, const int32_t *slice_width, int64_t *slice_ptr,
+                       const int32_t *slice_nnz = nullptr, unsigned long long *total = nullptr);
 void launch_upwind_fill(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,
                         const uint8_t *fmask, const int32_t *cell_frac, const int32_t *frac_cell,
                         const int32_t *frac_nodes, const uint8_t *dirichlet, const int32_t *node_cell_ptr,
