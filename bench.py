@@ -42,7 +42,8 @@ def algorithmic_bytes(h, sinfo, tinfo, levels=None, precision="fp64", sweeps=2):
         for i, (rows, nz, _) in enumerate(levels[:-1]):
             nc = levels[i + 1][0]
             passes = 2 if i == 0 else 2 * max(1, sweeps)
-            b += passes * (v + 4) * nz + 13 * rows * w + 8 * rows + nc * w
+            dg = 8 * rows if v == 4 else 0  # FP32 levels keep their diagonal in FP64
+            b += passes * ((v + 4) * nz + dg) + 13 * rows * w + 8 * rows + nc * w
         rows = levels[-1][0]
         b += rows * rows * w + 2 * rows * w
         out["vcycle"] = b

@@ -67,6 +67,8 @@ template <class V, class X>
 void amg_launch_post_x(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, const int32_t *agg,
                        const X *e, X *out, const PcgState *st);
 void launch_to_float(hipStream_t s, int64_t n, const double *a, float *b);
+// FP32 off-diagonal values and an FP64 diagonal that keeps each row sum
+void launch_to_float_rowsum(hipStream_t s, Sell<double> A, float *v32, double *dg);
 void launch_to_double(hipStream_t s, int64_t n, const float *a, double *b);
 
 // grow-only device buffer (keeps its allocation across solves)
@@ -86,6 +88,7 @@ struct AmgLevel {
     DBuf<int32_t> agg, mptr, mrows; // aggregation to the next level
     DBuf<double> b, xa, xb, r;      // cycle vectors
     DBuf<float> val32, dinv32, b32, xa32, xb32, r32;
+    DBuf<double> dg32;  // FP64 diagonal of the FP32 copy (row sums kept)
     Sell<float> A32;
 };
 

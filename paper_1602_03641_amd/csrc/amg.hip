@@ -1053,6 +1053,7 @@ __global__ __launch_bounds__(kAT) void vc_small_kernel(Sell<V> A, const X *__res
 #pragma unroll
         for (int o = kRowsPerWave; o < 64; o <<= 1) sum += __shfl_xor(sum, o, 64);
         if (g == 0 && i < A.n) {
+            if (A.dg) sum += (X)A.dg[i] * f(i);
             if constexpr (MODE == 0) {
                 out[i] = b[i] - sum;
             } else {
@@ -1087,6 +1088,31 @@ __global__ __launch_bounds__(kAT) void vc_dense_kernel(int32_t n, const X *__res
 // conversions for the single-precision hierarchy
 __global__ __launch_bounds__(kAT) void to_float_kernel(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
     GS(i, n) b[i] = (float)a[i];
+}
+// FP32 copy of a level's matrix that keeps every row sum: the off-diagonal
+// entries are rounded to FP32 and the diagonal, kept apart in FP64, absorbs
+// their rounding (dg_i = sum_j a_ij - sum_{j != i} fl32(a_ij)).  The rounding
+// error is then a Laplacian-like matrix with zero row sums: it leaves the
+// constant vector alone and perturbs each coupling by a relative 2^-24, so
+// the near-null (smooth) modes that the coarse levels must resolve are kept.
+__global__ __launch_bounds__(kAT) void to_float_rowsum_kernel(Sell<double> A, float *__restrict__ v32,
+                                                              double *__restrict__ dg) {
+    GS(i, A.n) {
+        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
+        double s = 0.0, so = 0.0;
+        for (int64_t q = b0 + (i & 63); q < b1; q += 64) {
+            const double a = A.val[q];
+            s += a;
+            if (A.col[q] == i) {
+                v32[q] = 0.0f;
+            } else {
+                const float f = (float)a;
+                v32[q] = f;
+                so += (double)f;
+            }
+        }
+        dg[i] = s - so;
+    }
 }
 __global__ __launch_bounds__(kAT) void to_double_kernel(int64_t n, const float *__restrict__ a, double *__restrict__ b) {
     GS(i, n) b[i] = (double)a[i];
@@ -1249,6 +1275,9 @@ void amg_launch_sweep(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const
 }
 void launch_to_float(hipStream_t s, int64_t n, const double *a, float *b) {
     if (n > 0) ALAUNCH(to_float_kernel, gridv(n), kAT, n, a, b);
+}
+void launch_to_float_rowsum(hipStream_t s, Sell<double> A, float *v32, double *dg) {
+    if (A.n > 0) ALAUNCH(to_float_rowsum_kernel, gridv(A.n), kAT, A, v32, dg);
 }
 void launch_to_double(hipStream_t s, int64_t n, const float *a, double *b) {
     if (n > 0) ALAUNCH(to_double_kernel, gridv(n), kAT, n, a, b);

@@ -117,11 +117,12 @@ void Amg::make_fp32(hipStream_t s, Tracker &tr, const int32_t *) {
     for (int l = 0; l < nlev; ++l) {
         AmgLevel &lv = *L[l];
         ensure(lv.val32, (size_t)lv.stored, tr);
-        launch_to_float(s, lv.stored, lv.A.val, lv.val32.p);
+        ensure(lv.dg32, lv.n, tr);
+        launch_to_float_rowsum(s, lv.A, lv.val32.p, lv.dg32.p);
         ensure(lv.dinv32, lv.n, tr);
         launch_to_float(s, lv.n, lv.dinv.p, lv.dinv32.p);
         for (auto *v : {&lv.b32, &lv.xa32, &lv.xb32, &lv.r32}) ensure(*v, lv.n, tr);
-        lv.A32 = Sell<float>{lv.n, lv.A.ptr, lv.A.col, lv.val32.p};
+        lv.A32 = Sell<float>{lv.n, lv.A.ptr, lv.A.col, lv.val32.p, lv.dg32.p};
     }
     if (dense) {
         const int32_t nc = L[nlev - 1]->n;

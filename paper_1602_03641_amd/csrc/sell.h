@@ -26,6 +26,7 @@ __device__ inline Acc sell_row_apply(const Sell<V> &A, int32_t row, F f) {
     for (int w = kChains / 2; w > 0; w >>= 1)
 #pragma unroll
         for (int c = 0; c < w; ++c) s[c] += s[c + w];
+    if (A.dg) s[0] += (Acc)A.dg[row] * f(row);
     return s[0];
 }
 

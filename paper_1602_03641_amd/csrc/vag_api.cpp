@@ -1019,8 +1019,8 @@ size_t vag_estimate_footprint(int64_t nn, int64_t nc, int64_t nf, const vag_opti
     b += 24 * nrow + 12 * tst + 12 * nrow / 64;                     // transport
     if (o.precond == VAG_PC_AMG) {
         double amg = 104 * Nx + 17 * S + 0.15 * (12 * S + 104 * Nx);
-        if (o.precision == VAG_MIXED) amg += 4.6 * S + 40 * Nx;
-        if (o.precision == VAG_MIXED_IR) amg += 8 * S + 8 * Nx + 4.6 * S + 64 * Nx;
+        if (o.precision == VAG_MIXED) amg += 4.6 * S + 50 * Nx;
+        if (o.precision == VAG_MIXED_IR) amg += 8 * S + 8 * Nx + 4.6 * S + 74 * Nx;
         b += 1.125 * amg + 1.5 * 1024 * 1024;                       // + dense coarsest inverse
     }
     return (size_t)(1.15 * b) + ((size_t)1 << 20);

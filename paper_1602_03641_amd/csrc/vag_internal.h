@@ -144,6 +144,9 @@ struct Sell {
     const int64_t *ptr = nullptr;
     const int32_t *col = nullptr;
     const V *val = nullptr;
+    // optional diagonal held apart in FP64 (the stored diagonal entries are
+    // then zero): the FP32 copies keep each row's FP64 row sum this way
+    const double *dg = nullptr;
 };
 
 struct PcgState {       // device-resident scalars of a Krylov solve
