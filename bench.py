@@ -51,15 +51,52 @@ def algorithmic_bytes(h, sinfo, tinfo, levels=None, precision="fp64", sweeps=2):
 
 
 def cpu_baseline(prob, budget_s=30.0):
-    """The oracle, as it stands, on one full solve of the same workload."""
+    """The oracle, as it stands, on one full solve of the same workload;
+    returns the baseline record and the oracle's result."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
-    oracle.run(prob, rtol=prob.rtol)
+    res = oracle.run(prob, rtol=prob.rtol)
     dt = time.perf_counter() - t0
     return {"value": 1.0 / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
             "sample": f"one full solve of {prob.name} (Jacobi-PCG to rtol {prob.rtol:g} + {prob.n_steps} steps), "
-                      f"{dt:.2f} s"}
+                      f"{dt:.2f} s"}, res
+
+
+def results(vag, h):
+    """Pressures and concentrations of a handle, on the host."""
+    return vag.to_numpy(h.pressure()) | vag.to_numpy(h.concentration())
+
+
+def rel_l2(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0))
+
+
+def differences(r, ref):
+    """Relative L2 pressure and max-abs concentration differences."""
+    return {"u_node_rel_l2": rel_l2(r["u_node"], ref["u_node"]),
+            "u_frac_rel_l2": rel_l2(r["u_frac"], ref["u_frac"]) if len(ref["u_frac"]) else 0.0,
+            "c_cell_max_abs": float(np.abs(r["c_cell"] - ref["c_cell"]).max()),
+            "c_node_max_abs": float(np.abs(r["c_node"] - ref["c_node"]).max())}
+
+
+def copy_bandwidth(torch, mib=512, reps=20):
+    """Achievable device copy rate (read + write bytes per second), GB/s."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 16.0 * n / (ms * 1e-3) / 1e9
 
 
 def serving_bench(vag, synth, n_jobs, workers, budget, seed=4):
@@ -256,7 +293,37 @@ def main():
         roofline["other"]["vcycle_GBs"] = round(ab["vcycle"] / (ms_prec * 1e-3) / 1e9, 1)
         roofline["other"]["vcycle_bytes"] = ab["vcycle"]
 
+    copy_gbs = copy_bandwidth(torch)
+    roofline["other"]["copy_GBs"] = round(copy_gbs, 1)
+    roofline["other"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
     log("kernel timings done")
+    gpu_res = results(vag, h)
+
+    # the same workload in the other precision (FP64 <-> FP32 hierarchy), timed the same way
+    other, other_res = None, None
+    if args.precond == "amg" and args.workload == "config2" and args.precision in ("fp64", "mixed"):
+        alt = "mixed" if args.precision == "fp64" else "fp64"
+        h2 = vag.Handle(prob, **(opts | {"precision": vag.VAG_MIXED if alt == "mixed" else vag.VAG_FP64}))
+        for _ in range(args.warmup):
+            h2.solve_pressure()
+            h2.transport(n_steps=prob.n_steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            s2 = h2.solve_pressure()
+            h2.transport(n_steps=prob.n_steps)
+        torch.cuda.synchronize()
+        el2 = time.perf_counter() - t1
+        ms_prec2 = h2.benchmark_kernel(vag.VAG_KERNEL_PRECOND, 50)
+        ab2 = algorithmic_bytes(h2, s2, tinfo, h2.amg_levels(), alt, args.amg_sweeps if args.amg_sweeps > 0 else 2)
+        other = {"precision": alt, "value": round(args.steps / el2, 4), "iterations": s2["iterations"],
+                 "rel_residual": s2["rel_residual"], "ms_solve": round(s2["ms_solve"], 3),
+                 "vcycle_GBs": round(ab2["vcycle"] / (ms_prec2 * 1e-3) / 1e9, 1),
+                 "difference_to_headline": None}
+        other_res = results(vag, h2)
+        other["difference_to_headline"] = differences(other_res, gpu_res)
+        del h2
+        log(f"{alt}: {other['value']} solves/s")
     serving = None
     if args.serving_jobs > 0 and args.workload == "config2":
         log(f"serving stream of {args.serving_jobs} jobs")
@@ -264,9 +331,15 @@ def main():
                                 int(args.serving_budget_gb * 1e9))
 
     cpu = None
+    vs_oracle = None
     if not args.no_cpu_baseline and args.workload == "config2":
         log("oracle baseline")
-        cpu = cpu_baseline(prob)
+        cpu, ores = cpu_baseline(prob)
+        oref = {"u_node": ores["darcy"]["u_node"], "u_frac": ores["darcy"]["u_frac"],
+                "c_cell": ores["c_cell"], "c_node": ores["c_node"]}
+        vs_oracle = {"note": f"both sides solved to rtol {prob.rtol:g}", args.precision: differences(gpu_res, oref)}
+        if other is not None:
+            vs_oracle[other["precision"]] = differences(other_res, oref)
 
     out = {
         "metric": "Darcy+transport solves/sec", "value": round(args.steps / elapsed, 4), "unit": "solves/s",
@@ -285,7 +358,8 @@ def main():
         "system": {"rows": sinfo["n_unknowns"], "nnz": sinfo["nnz"],
                    "stored": levels[0][2] if levels else None},
         "upwind_operator": {"rows": tinfo["n_rows"], "nnz": tinfo["t_nnz"], "stored": tinfo["t_stored"]},
-        "roofline": roofline, "cpu_baseline": cpu, "serving": serving,
+        "roofline": roofline, "cpu_baseline": cpu, "other_precision": other, "vs_oracle": vs_oracle,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

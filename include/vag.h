@@ -204,8 +204,9 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
 vag_status vag_update(vag_handle *h, const vag_rock *rock, const vag_fractures *frac_props,
                       const double *p_bar, const double *c_bar, vag_mem mem);
 
-/* Binds the handle to another HIP stream (NULL: the null stream).  The
- * caller orders it after the work already queued on the old stream. */
+/* Binds the handle to another HIP stream (NULL: the null stream).  Waits for
+ * the work already queued on the old stream first: the handle's device
+ * buffers are allocated and freed in the order of its stream. */
 vag_status vag_set_stream(vag_handle *h, void *hip_stream);
 
 /* Replaces the solver options of a handle (takes effect at the next solve). */
@@ -292,8 +293,15 @@ size_t vag_footprint_bytes(const vag_handle *h);
  * failed vag_create in this thread. */
 const char *vag_last_error(const vag_handle *h);
 
-/* Releases all device and host memory of the handle. */
+/* Releases the handle.  Its device memory goes back to the library's
+ * per-device pool and its pinned host blocks to the library's free list,
+ * both kept for later handles of the process (vag_trim_memory returns the
+ * unused device memory to the system). */
 void vag_destroy(vag_handle *h);
+
+/* Returns the unused blocks of the current device's pool to the system.
+ * Waits for the device to be idle first.  Errors: VAG_ERR_HIP. */
+vag_status vag_trim_memory(void);
 
 /*
  * Upper bound of the device bytes a handle of these sizes holds after a solve

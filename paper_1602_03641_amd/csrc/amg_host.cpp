@@ -6,12 +6,12 @@
 namespace vag {
 
 Amg::~Amg() {
-    if (h_) (void)hipHostFree(h_);
+    pinned_put(h_, 1024 * sizeof(int32_t));
 }
 
 void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, const AmgOptions &o) {
     o_ = o;
-    if (!h_) VAG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_), 1024 * sizeof(int32_t)));
+    if (!h_) h_ = static_cast<int32_t *>(pinned_get(1024 * sizeof(int32_t)));
     const int32_t n0 = A0.n;
     // the coarsening keys hold a row's priority in 30 bits
     if (n0 >= (1 << 30)) throw Error(VAG_ERR_UNSUPPORTED, "AMG: more than 2^30 - 1 rows");

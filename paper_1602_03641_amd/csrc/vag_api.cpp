@@ -5,11 +5,73 @@
 #include <cmath>
 #include <cstring>
 
+#include <map>
+#include <mutex>
+
 #include "amg.h"
 #include "gmres.h"
 #include "vag_internal.h"
 
 using namespace vag;
+
+namespace vag {
+
+hipMemPool_t device_pool() {
+    static std::mutex mu;
+    static hipMemPool_t pools[64] = {};
+    int dev = 0;
+    VAG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) throw Error(VAG_ERR_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!pools[dev]) {
+        hipMemPoolProps props{};
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t p = nullptr;
+        VAG_HIP(hipMemPoolCreate(&p, &props));
+        // keep freed blocks for reuse instead of returning them at every synchronisation
+        uint64_t keep = UINT64_MAX;
+        VAG_HIP(hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep));
+        pools[dev] = p;
+    }
+    return pools[dev];
+}
+
+namespace {
+std::mutex g_pinned_mu;
+std::multimap<size_t, void *> g_pinned_free;  // size class -> free blocks
+size_t pinned_class(size_t bytes) {
+    size_t c = 256;
+    while (c < bytes) c <<= 1;
+    return c;
+}
+}  // namespace
+
+void *pinned_get(size_t bytes) {
+    const size_t c = pinned_class(bytes);
+    {
+        std::lock_guard<std::mutex> lk(g_pinned_mu);
+        auto it = g_pinned_free.find(c);
+        if (it != g_pinned_free.end()) {
+            void *p = it->second;
+            g_pinned_free.erase(it);
+            return p;
+        }
+    }
+    void *p = nullptr;
+    VAG_HIP(hipHostMalloc(&p, c));
+    return p;
+}
+
+void pinned_put(void *p, size_t bytes) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    g_pinned_free.emplace(pinned_class(bytes), p);
+}
+
+}  // namespace vag
 
 struct vag_handle {
     hipStream_t stream = nullptr;
@@ -67,10 +129,10 @@ struct vag_handle {
     double *c_next() { return cur ? cbuf0.p : cbuf1.p; }
 
     ~vag_handle() {
-        if (h_pcg) (void)hipHostFree(h_pcg);
-        if (h_scal) (void)hipHostFree(h_scal);
-        if (h_cnt) (void)hipHostFree(h_cnt);
-        if (h_gm) (void)hipHostFree(h_gm);
+        pinned_put(h_pcg, sizeof(PcgState));
+        pinned_put(h_scal, 16 * sizeof(double));
+        pinned_put(h_cnt, sizeof(unsigned long long));
+        pinned_put(h_gm, (3 * (size_t)(h_gm_m + 1) + 1) * sizeof(double));
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
     }
@@ -310,9 +372,9 @@ GmresWork<T> gmres_work(vag_handle *h, int32_t n, DBuf<T> &V, DBuf<T> &w, DBuf<T
     ensure(h->gmnparts, (size_t)gmres_grid(n), tr);
     ensure(h->gmhd, (size_t)3 * (m + 1) + 1, tr);
     if (h->h_gm_m < m) {
-        if (h->h_gm) VAG_HIP(hipHostFree(h->h_gm));
+        pinned_put(h->h_gm, (3 * (size_t)(h->h_gm_m + 1) + 1) * sizeof(double));
         h->h_gm = nullptr;
-        VAG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_gm), (3 * (size_t)(m + 1) + 1) * sizeof(double)));
+        h->h_gm = static_cast<double *>(pinned_get((3 * (size_t)(m + 1) + 1) * sizeof(double)));
         h->h_gm_m = m;
     }
     GmresWork<T> W;
@@ -465,6 +527,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         if (!mesh || !rock || !bc) throw Error(VAG_ERR_ARG, "mesh, rock and bc are required");
         if (!(rock->mu > 0)) throw Error(VAG_ERR_ARG, "viscosity must be positive");
         h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+        h->tr.stream = h->stream;
         if (opt) h->opt = *opt; else vag_default_options(&h->opt);
         check_options(h->opt);
         const int64_t nn = mesh->n_nodes, nc = mesh->n_cells, nf = frac ? frac->n_frac : 0;
@@ -569,9 +632,9 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         h->cbuf1.alloc(nrow, h->tr);
         h->dt4.alloc(4, h->tr);
         h->cnt.alloc(1, h->tr);
-        VAG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_cnt), sizeof(unsigned long long)));
-        VAG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_pcg), sizeof(PcgState)));
-        VAG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->h_scal), 16 * sizeof(double)));
+        h->h_cnt = static_cast<unsigned long long *>(pinned_get(sizeof(unsigned long long)));
+        h->h_pcg = static_cast<PcgState *>(pinned_get(sizeof(PcgState)));
+        h->h_scal = static_cast<double *>(pinned_get(16 * sizeof(double)));
         for (auto &e : h->ev) VAG_HIP(hipEventCreate(&e));
         // system positions of the eliminated groups' node pairs
         h->grp_pos.alloc(std::max<int64_t>(S.grp_poff.back(), 1), h->tr);
@@ -642,8 +705,12 @@ vag_status vag_set_fluxes(vag_handle *h, const double *F_cell, const double *F_c
 
 vag_status vag_set_stream(vag_handle *h, void *hip_stream) {
     if (!h) return VAG_ERR_ARG;
-    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    return VAG_OK;
+    return guard(h, [&] {
+        // the buffers are ordered on the old stream: let it drain first
+        VAG_HIP(hipStreamSynchronize(h->stream));
+        h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+        h->tr.stream = h->stream;
+    });
 }
 
 vag_status vag_set_options(vag_handle *h, const vag_options *opt) {
@@ -1027,6 +1094,16 @@ size_t vag_estimate_footprint(int64_t nn, int64_t nc, int64_t nf, const vag_opti
 }
 
 const char *vag_last_error(const vag_handle *h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+vag_status vag_trim_memory(void) {
+    try {
+        VAG_HIP(hipDeviceSynchronize());
+        VAG_HIP(hipMemPoolTrimTo(device_pool(), 0));
+        return VAG_OK;
+    } catch (const Error &e) {
+        return e.status;
+    }
+}
 
 void vag_destroy(vag_handle *h) {
     if (!h) return;

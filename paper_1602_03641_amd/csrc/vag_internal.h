@@ -53,8 +53,20 @@ constexpr int kKrylovThreads = 1024;  // block size of the Krylov kernels (and o
 // ---------------------------------------------------------------------------
 // device buffer
 // ---------------------------------------------------------------------------
+// Device memory comes from a per-device stream-ordered pool that keeps freed
+// blocks for reuse: hipMalloc/hipFree would synchronise the whole device at
+// every handle creation and destruction, serialising independent handles
+// that run side by side on their own streams.  Allocations and frees are
+// ordered on the owning handle's stream.
+hipMemPool_t device_pool();
+// Pinned host blocks from a process-wide free list (same reason: hipHostFree
+// synchronises the device).  bytes must be the size given to pinned_get.
+void *pinned_get(size_t bytes);
+void pinned_put(void *p, size_t bytes);
+
 struct Tracker {
     size_t bytes = 0;
+    hipStream_t stream = nullptr;  // the stream allocations and frees are ordered on
 };
 
 template <class T>
@@ -67,13 +79,13 @@ struct DBuf {
         tr = &t;
         n = count;
         if (count) {
-            VAG_HIP(hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T)));
+            VAG_HIP(hipMallocFromPoolAsync(reinterpret_cast<void **>(&p), count * sizeof(T), device_pool(), t.stream));
             t.bytes += count * sizeof(T);
         }
     }
     void release() {
         if (p) {
-            (void)hipFree(p);
+            (void)hipFreeAsync(p, tr ? tr->stream : nullptr);
             if (tr) tr->bytes -= n * sizeof(T);
         }
         p = nullptr;

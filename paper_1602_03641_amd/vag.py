@@ -118,6 +118,7 @@ _SIGS = {
                     C.POINTER(vag_options), C.c_int, vp, C.POINTER(vp)], C.c_int),
     "vag_update": ([vp, C.POINTER(vag_rock), C.POINTER(vag_fractures), vp, vp, C.c_int], C.c_int),
     "vag_set_stream": ([vp, vp], C.c_int),
+    "vag_trim_memory": ([], C.c_int),
     "vag_set_options": ([vp, C.POINTER(vag_options)], C.c_int),
     "vag_solve_pressure": ([vp, C.POINTER(vag_solve_info)], C.c_int),
     "vag_transport": ([vp, C.c_int64, C.c_double, vp, vp, vp, C.c_int, C.POINTER(vag_transport_info)], C.c_int),
@@ -320,6 +321,13 @@ class Handle:
 
     def footprint_bytes(self):
         return int(load().vag_footprint_bytes(self.h))
+
+
+def trim_memory():
+    """Return the unused blocks of the library's device memory pool to the system."""
+    st = load().vag_trim_memory()
+    if st != VAG_OK:
+        raise VagError(st, "vag_trim_memory failed")
 
 
 def to_numpy(d):

@@ -179,3 +179,23 @@ def test_cached_handle_reused_with_new_data():
     for k in OUT:
         np.testing.assert_array_equal(r2[k], fresh[0][k], err_msg=k)
     assert not np.array_equal(r1["u_node"], r2["u_node"])
+
+
+def test_pool_reuse_and_trim():
+    """Handles created and destroyed in turn reuse the library's pooled device
+    memory; trimming returns the unused blocks and later handles still work."""
+    vag = _vag()
+    p = synth.random_problem((7, 6, 5), 9, n_patches=3, n_steps=5)
+    ref = None
+    for k in range(3):
+        h = vag.Handle(p, rtol=1e-12, max_iter=5000)
+        h.solve_pressure()
+        h.transport(n_steps=5)
+        d = vag.to_numpy(h.pressure()) | vag.to_numpy(h.concentration())
+        h.close()
+        if k == 1:
+            vag.trim_memory()
+        if ref is None:
+            ref = d
+        for key in OUT:
+            np.testing.assert_array_equal(d[key], ref[key], err_msg=key)
