@@ -11,12 +11,15 @@
 //   aggregates each root starts one; other nodes join their strongest root
 //              neighbour, then the strongest already-aggregated neighbour
 //   P          piecewise-constant interpolation (one 1 per row)
-//   A_c        = P^T A P, one wavefront per coarse row: the (coarse column,
-//              fine position) keys of the aggregate's rows are bitonic-sorted
-//              in LDS and each coarse entry sums its fine entries in position
-//              order, so the coarse matrix is bitwise reproducible
+//   A_c        = P^T A P, one wavefront per coarse row: the rows of A P
+//              (each fine row's entries collapsed per aggregate) of the
+//              aggregate's members are gathered as (coarse column, gather
+//              ordinal) keys with their values in LDS, bitonic-sorted, and
+//              each coarse entry sums its candidates in gather order, so the
+//              coarse matrix is bitwise reproducible
 // Smoother: l1-Jacobi, M = diag(sum_j |a_ij|), convergent for any SPD matrix.
-// Cycle: symmetric V-cycle (one pre- and one post-sweep), the coarsest level
+// Cycle: symmetric V-cycle (one pre- and one post-sweep on the finest level,
+// `sweeps` of each on the coarser ones), the coarsest level
 // solved by a dense inverse formed on the device by Gauss-Jordan elimination.
 #include <algorithm>
 
@@ -542,10 +545,151 @@ __global__ __launch_bounds__(64) void ap_spill_kernel(Sell<double> A, const int3
     }
 }
 
-// mode 0: rowlen[I] = number of coarse columns; mode 1: write them (SELL).
-// Candidates are the collapsed entries (apn[r] of them) of the aggregate's
-// rows r, gathered with one member row per lane.  Rows with more than CAP
-// candidates set big[I] and are redone with the larger CAP.
+// Galerkin coarse row I, one wavefront: the collapsed entries (apn[r] of
+// them) of the aggregate's rows r are gathered as (coarse column, value) in
+// gather order, one member row per lane; the distinct columns are found with
+// an LDS hash set, ranked (each rank counts the smaller columns), and each
+// column sums its candidates in gather order (all lanes read candidate k
+// together), so the coarse matrix is bitwise reproducible.  mode 0:
+// rowlen[I] = number of coarse columns, big[I] = 1 for a row this kernel
+// cannot hold; mode 1: write the row (SELL).
+constexpr int kGalCand = 1024, kGalHash = 512, kGalDistinct = 256;
+__global__ __launch_bounds__(64) void galerkin_hash_kernel(Sell<double> A, const int32_t *__restrict__ Jcol,
+                                                           const double *__restrict__ apv,
+                                                           const int32_t *__restrict__ apn,
+                                                           const int32_t *__restrict__ mptr,
+                                                           const int32_t *__restrict__ mrows, int32_t nc, int mode,
+                                                           int32_t *__restrict__ big, int32_t *__restrict__ rowlen,
+                                                           const int64_t *__restrict__ cptr,
+                                                           int32_t *__restrict__ ccol, double *__restrict__ cval) {
+    __shared__ int32_t cj[kGalCand];
+    __shared__ double cv[kGalCand];
+    __shared__ int32_t hs[kGalHash];
+    __shared__ int32_t dist[kGalDistinct];
+    __shared__ int32_t sorted[kGalDistinct];
+    const int32_t I = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (I >= nc) return;
+    if (mode == 1 && big[I]) return;
+    for (int k = lane; k < kGalHash; k += 64) hs[k] = -1;
+    // gather
+    int m = 0;
+    bool over = false;
+    const int32_t t1 = mptr[I + 1];
+    for (int32_t t0 = mptr[I]; t0 < t1; t0 += 64) {
+        const int32_t t = t0 + lane;
+        int c = 0;
+        int64_t b = 0;
+        if (t < t1) {
+            const int32_t r = mrows[t];
+            b = A.ptr[r >> 6] + (r & 63);
+            c = apn[r];
+        }
+        int incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        const int tot = __shfl(incl, 63, 64);
+        if (m + tot > kGalCand) {
+            over = true;
+            break;
+        }
+        const int off = m + incl - c;
+        for (int k = 0; k < c; ++k) {
+            const int64_t q = b + (int64_t)k * 64;
+            cj[off + k] = Jcol[q];
+            cv[off + k] = apv[q];
+        }
+        m += tot;
+    }
+    __syncthreads();
+    // distinct columns: an LDS hash set (linear probing); a set that grows
+    // past kGalDistinct sends the row to the sorting kernel
+    bool full = false;
+    if (!over) {
+        for (int k = lane; k < m; k += 64) {
+            const int32_t J = cj[k];
+            uint32_t h = ((uint32_t)J * 2654435761u) & (kGalHash - 1);
+            for (int probe = 0; probe < kGalHash; ++probe) {
+                const int32_t prev = atomicCAS(&hs[h], -1, J);
+                if (prev == -1 || prev == J) break;
+                h = (h + 1) & (kGalHash - 1);
+            }
+        }
+    }
+    __syncthreads();
+    int nd = 0;
+    if (!over) {
+        // compact the occupied slots
+        for (int k0 = 0; k0 < kGalHash; k0 += 64) {
+            const int32_t J = hs[k0 + lane];
+            const uint64_t mask = __ballot(J >= 0);
+            const int below = __popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+            const int base = nd;
+            if (J >= 0 && base + below < kGalDistinct) dist[base + below] = J;
+            nd += __popcll(mask);
+        }
+        full = nd > kGalDistinct;
+    }
+    if (over || full) {
+        if (mode == 0 && lane == 0) big[I] = 1;
+        return;
+    }
+    if (mode == 0 && lane == 0) big[I] = 0;
+    __syncthreads();
+    // rank sort of the distinct columns
+    for (int i = lane; i < nd; i += 64) {
+        const int32_t J = dist[i];
+        int rank = 0;
+        for (int u = 0; u < nd; ++u) rank += dist[u] < J;
+        sorted[rank] = J;
+    }
+    if (mode == 0) {
+        if (lane == 0) rowlen[I] = nd;
+        return;
+    }
+    __syncthreads();
+    // sums in gather order; lane owns sorted columns lane, lane + 64, ...
+    constexpr int kOwn = kGalDistinct / 64;
+    int32_t own[kOwn];
+    double sum[kOwn];
+#pragma unroll
+    for (int o = 0; o < kOwn; ++o) {
+        own[o] = (lane + 64 * o < nd) ? sorted[lane + 64 * o] : -1;
+        sum[o] = 0.0;
+    }
+    const int nown = (nd + 63) / 64;
+    for (int k = 0; k < m; ++k) {
+        const int32_t J = cj[k];
+        const double v = cv[k];
+#pragma unroll
+        for (int o = 0; o < kOwn; ++o)
+            if (o < nown && own[o] == J) sum[o] += v;
+    }
+    const int64_t base = cptr[I >> 6] + (I & 63);
+#pragma unroll
+    for (int o = 0; o < kOwn; ++o) {
+        const int k = lane + 64 * o;
+        if (k < nd) {
+            ccol[base + (int64_t)k * 64] = own[o];
+            cval[base + (int64_t)k * 64] = sum[o];
+        }
+    }
+    const int w = (int)((cptr[(I >> 6) + 1] - cptr[I >> 6]) >> 6);
+    for (int k = nd + lane; k < w; k += 64) {
+        ccol[base + (int64_t)k * 64] = I;
+        cval[base + (int64_t)k * 64] = 0.0;
+    }
+}
+
+// Coarse rows that the hashed kernel below could not take (more than
+// kGalCand candidates or kGalDistinct distinct columns; big[I] set): the
+// candidates as (coarse column, fine position) keys, bitonic-sorted in LDS,
+// each coarse entry summing its candidates in gather order.  mode 0:
+// rowlen[I] = number of coarse columns; mode 1: write them (SELL).  More
+// than CAP candidates: *overflow.
 template <int CAP>
 __global__ __launch_bounds__(64) void galerkin_kernel(Sell<double> A, const int32_t *__restrict__ Jcol,
                                                       const double *__restrict__ apv, const int32_t *__restrict__ apn,
@@ -558,7 +702,7 @@ __global__ __launch_bounds__(64) void galerkin_kernel(Sell<double> A, const int3
     const int32_t I = blockIdx.x;
     const int lane = threadIdx.x;
     if (I >= nc) return;
-    if (CAP > 2048 && !big[I]) return;
+    if (!big[I]) return;
     int m = 0;
     bool over = false;
     const int32_t t1 = mptr[I + 1];
@@ -591,13 +735,11 @@ __global__ __launch_bounds__(64) void galerkin_kernel(Sell<double> A, const int3
     }
     if (over) {
         if (lane == 0) {
-            if (CAP <= 2048) big[I] = 1;
-            else atomicOr(overflow, 1);
-            if (mode == 0 && CAP > 2048) rowlen[I] = 1;
+            atomicOr(overflow, 1);
+            if (mode == 0) rowlen[I] = 1;
         }
         return;
     }
-    if (CAP <= 2048 && mode == 0 && lane == 0) big[I] = 0;
     int mp = 1;
     while (mp < m) mp <<= 1;
     for (int k = m + lane; k < mp; k += 64) key[k] = ~0ull;
@@ -1187,8 +1329,7 @@ void amg_launch_galerkin(hipStream_t s, Sell<double> A, const int32_t *Jcol, con
                          const int32_t *mptr, const int32_t *mrows, int32_t nc, int mode, int32_t *big,
                          int32_t *rowlen, const int64_t *cptr, int32_t *ccol, double *cval, int *overflow) {
     if (nc <= 0) return;
-    ALAUNCH(galerkin_kernel<2048>, nc, 64, A, Jcol, apv, apn, mptr, mrows, nc, mode, big, rowlen, cptr, ccol, cval,
-            overflow);
+    ALAUNCH(galerkin_hash_kernel, nc, 64, A, Jcol, apv, apn, mptr, mrows, nc, mode, big, rowlen, cptr, ccol, cval);
     ALAUNCH(galerkin_kernel<8192>, nc, 64, A, Jcol, apv, apn, mptr, mrows, nc, mode, big, rowlen, cptr, ccol, cval,
             overflow);
 }

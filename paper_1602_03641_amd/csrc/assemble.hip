@@ -241,11 +241,60 @@ __device__ inline void add_sys(const AsmArgs &g, int32_t r, int32_t c, int32_t n
     }
 }
 
-__global__ __launch_bounds__(128) void asm_node_rows_kernel(AsmArgs g) {
+// Slots of the M_K columns in the node rows (positions found once per handle
+// by binary search; the per-solve assembly then adds at known slots).
+__global__ __launch_bounds__(128) void node_pos_kernel(AsmArgs g, uint16_t *__restrict__ node_pos) {
     const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= g.nfree) return;
     const int32_t s = g.unk_node[r];
+    const int64_t base = g.sell_ptr[r >> 6] + (r & 63);
+    for (int32_t q = g.node_cell_ptr[s]; q < g.node_cell_ptr[s + 1]; ++q) {
+        const int32_t K = g.node_cell[q] >> 3;
+        for (int c = 0; c < 8; ++c) {
+            const int32_t u = g.node_unk[g.hex8[8 * (int64_t)K + c]];
+            uint16_t k = 0xffff;
+            if (u >= 0) {
+                const int64_t p = sell_find(g, r, u);
+                if (p < 0 || (p - base) / 64 >= 0xffff) atomicMin(g.bad, INT_MIN);
+                else k = (uint16_t)((p - base) / 64);
+            }
+            node_pos[8 * (int64_t)q + c] = k;
+        }
+    }
+}
+
+// One thread per node row.  The row's first kAccSlots slots accumulate in
+// LDS (the thread's own column of acc) and are stored once at the end: a
+// read-modify-write of the row in global memory would make every addition
+// wait for the previous one, since the compiler cannot tell the slots apart.
+// Slots beyond kAccSlots (rows next to eliminated fracture groups) are added
+// in global memory, which the caller has zeroed.
+constexpr int kAccSlots = 32;
+__global__ __launch_bounds__(128) void asm_node_rows_kernel(AsmArgs g) {
+    __shared__ double acc[kAccSlots][128];
+    const int tid = threadIdx.x;
+    const int32_t r = blockIdx.x * blockDim.x + tid;
+    if (r >= g.nfree) return;
+    const int32_t s = g.unk_node[r];
+    const int64_t base = g.sell_ptr[r >> 6] + (r & 63);
+    const int w = min(g.row_len[r], kAccSlots);
+    for (int k = 0; k < w; ++k) acc[k][tid] = 0.0;
     double rhs = 0.0;
+    auto put = [&](int k, double v) {
+        if (k < kAccSlots) acc[k][tid] += v;
+        else g.A[base + 64 * (int64_t)k] += v;
+    };
+    // column unknown c (node `node` or a face; c < 0: Dirichlet node; c >= nsys:
+    // an eliminated face, held by its group block)
+    auto put_col = [&](int32_t c, int32_t node, double v) {
+        if (c < 0) {
+            rhs -= v * g.p_bar[node];
+        } else if (c < g.nsys) {
+            const int64_t p = sell_find(g, r, c);
+            if (p >= 0) put((int)((p - base) >> 6), v);
+            else atomicMin(g.bad, INT_MIN);
+        }
+    };
     // cells of the node: row a of M_K
     for (int32_t q = g.node_cell_ptr[s]; q < g.node_cell_ptr[s + 1]; ++q) {
         const int32_t K = g.node_cell[q] >> 3;
@@ -253,9 +302,10 @@ __global__ __launch_bounds__(128) void asm_node_rows_kernel(AsmArgs g) {
         const double inv = 1.0 / g.AKK[K];
         const double ra = g.rK[(int64_t)a * g.nc + K];
         for (int c = 0; c < 8; ++c) {
-            const int32_t node = g.hex8[8 * (int64_t)K + c];
             const double v = g.aK[(int64_t)sym8(a, c) * g.nc + K] - ra * g.rK[(int64_t)c * g.nc + K] * inv;
-            add_sys(g, r, g.node_unk[node], node, v, rhs);
+            const uint16_t k = g.node_pos[8 * (int64_t)q + c];
+            if (k != 0xffff) put(k, v);
+            else rhs -= v * g.p_bar[g.hex8[8 * (int64_t)K + c]];  // Dirichlet column
         }
         const unsigned mask = g.fmask[K];
         for (int f = 0; f < 6; ++f) {
@@ -265,7 +315,7 @@ __global__ __launch_bounds__(128) void asm_node_rows_kernel(AsmArgs g) {
             const double *o = g.fside + (2 * (int64_t)sig + sd) * 6;
             const int i = face_vertex(f, a);
             const double v = (i >= 0 ? o[1 + i] : 0.0) - ra * o[5] * inv;
-            add_sys(g, r, g.frac_unk[sig], -1, v, rhs);
+            put_col(g.frac_unk[sig], -1, v);
         }
     }
     // fracture blocks of the faces the node is a vertex of: row 1+i of the 5x5 block
@@ -273,12 +323,13 @@ __global__ __launch_bounds__(128) void asm_node_rows_kernel(AsmArgs g) {
         const int32_t sig = g.node_frac[q] >> 2;
         const int i = g.node_frac[q] & 3;
         const double *M = g.A5 + 25 * (int64_t)sig + 5 * (1 + i);
-        add_sys(g, r, g.frac_unk[sig], -1, M[0], rhs);
+        put_col(g.frac_unk[sig], -1, M[0]);
         for (int k = 0; k < 4; ++k) {
             const int32_t node = g.frac_nodes[4 * (int64_t)sig + k];
-            add_sys(g, r, g.node_unk[node], node, M[1 + k], rhs);
+            put_col(g.node_unk[node], node, M[1 + k]);
         }
     }
+    for (int k = 0; k < w; ++k) g.A[base + 64 * (int64_t)k] = acc[k][tid];
     g.b[r] += rhs;
 }
 
@@ -532,6 +583,11 @@ void launch_frac_local(hipStream_t s, int32_t nf, const double *xyz, const int32
     if (nf <= 0) return;
     hipLaunchKernelGGL(vag_frac_kernel, dim3(nblk(nf, 256)), dim3(256), 0, s, nf, xyz, frac_nodes, width,
                        perm, 1.0 / mu, A5, area);
+    VAG_HIP(hipGetLastError());
+}
+
+void launch_node_pos(hipStream_t s, const AsmArgs &g, uint16_t *node_pos) {
+    if (g.nfree > 0) hipLaunchKernelGGL(node_pos_kernel, dim3(nblk(g.nfree, 128)), dim3(128), 0, s, g, node_pos);
     VAG_HIP(hipGetLastError());
 }
 

@@ -7,7 +7,7 @@ namespace vag {
 
 // sum_q A[row, q] * f(col_q), kChains independent accumulation chains so that
 // several gathers are in flight per lane.  The summation order is fixed.
-constexpr int kChains = 8;
+constexpr int kChains = 4;
 template <class V, class Acc, class F>
 __device__ inline Acc sell_row_apply(const Sell<V> &A, int32_t row, F f) {
     const int64_t b1 = A.ptr[(row >> 6) + 1];

@@ -88,6 +88,7 @@ struct vag_handle {
     DBuf<int64_t> sell_ptr;
     // eliminated fracture-face groups
     DBuf<int32_t> frac_unk, grp_ptr, grp_face, grp_nptr, grp_node, grp_pos, face_grp, face_loc;
+    DBuf<uint16_t> node_pos;  // slots of the cell-matrix columns in the node rows
     DBuf<int64_t> grp_off, grp_poff;
     DBuf<double> Gb;
     DBuf<uint8_t> fmask, dirichlet, frac_node;
@@ -244,6 +245,7 @@ AsmArgs asm_args(vag_handle *h) {
     g.fside = h->fside.p;
     g.A5 = h->A5.p;
     g.p_bar = h->p_bar.p;
+    g.node_pos = h->node_pos.p;
     g.sell_ptr = h->sell_ptr.p;
     g.sell_col = h->sell_col.p;
     g.row_len = h->row_len.p;
@@ -640,6 +642,9 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         h->grp_pos.alloc(std::max<int64_t>(S.grp_poff.back(), 1), h->tr);
         VAG_HIP(hipMemsetAsync(h->bad.p, 0x7f, sizeof(int), h->stream));
         launch_grp_pos(h->stream, asm_args(h), S.ngroup, h->grp_poff.p, h->grp_pos.p);
+        // slots of the cell-matrix columns in the node rows
+        h->node_pos.alloc(std::max<size_t>(S.node_cell.size() * 8, 1), h->tr);
+        launch_node_pos(h->stream, asm_args(h), h->node_pos.p);
         int bad = 0;
         VAG_HIP(hipMemcpyAsync(&bad, h->bad.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
         VAG_HIP(hipStreamSynchronize(h->stream));

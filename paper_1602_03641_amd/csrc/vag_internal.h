@@ -196,12 +196,17 @@ struct AsmArgs {
     const int64_t *grp_off;
     double *A, *Gb, *b;
     int *bad;  // receives INT_MIN if a position is missing from the pattern
+    // slot of column c of M_K in the row of each node_cell entry q:
+    // node_pos[8 q + c] (0xffff: a Dirichlet column); null before it is built
+    const uint16_t *node_pos;
 };
 // Node rows, kept-face rows, eliminated-face rows (into the group blocks).
 void launch_assemble(hipStream_t s, const AsmArgs &g, int32_t nkept, int32_t nelim);
 // Sliced-ELL columns, row lengths and diagonal positions from the CSR pattern.
 void launch_sell_fill(hipStream_t s, int32_t n, int64_t nslice, const int32_t *row_ptr, const int32_t *col,
                       const int64_t *sell_ptr, int32_t *sell_col, int32_t *row_len, int32_t *diag_pos);
+// node_pos (see AsmArgs) for the rows of the free nodes, once per handle.
+void launch_node_pos(hipStream_t s, const AsmArgs &g, uint16_t *node_pos);
 // System positions of the node pairs of each eliminated group.
 void launch_grp_pos(hipStream_t s, const AsmArgs &g, int32_t ngroup, const int64_t *grp_poff, int32_t *grp_pos);
 // Eliminates groups [first, first+ngroup) (one colour) onto the node rows.
