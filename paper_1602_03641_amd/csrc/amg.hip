@@ -34,7 +34,7 @@ constexpr int kRzThreads = kKrylovThreads;  // the r.z sweep writes Krylov parti
 constexpr int kCap = 8192;  // candidate entries per coarse row held in LDS
 
 #define GS(i, n) \
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
 // full grid for the grid-stride kernels (no reduction partials)
 static inline unsigned gridv(int64_t n) {
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(kAT) void members_fill_kernel(int32_t n, const int3
 __global__ __launch_bounds__(kAT) void members_rank_kernel(int32_t nc, const int32_t *__restrict__ ptr,
                                                            const int32_t *__restrict__ tmp, int32_t *__restrict__ rows) {
     const int lane = threadIdx.x & 63;
-    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t w0 = ((int64_t)xcd_block() * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t I = w0; I < nc; I += nw) {
         const int32_t b = ptr[I], e = ptr[I + 1];
@@ -1092,24 +1092,29 @@ __global__ __launch_bounds__(kAT) void vc_resid_kernel(Sell<V> A, const X *__res
     if (st && st->done) return;
     GS(i, A.n) r[i] = b[i] - sell_row_apply<V, X>(A, (int32_t)i, [&](int32_t j) { return x[j]; });
 }
-// b_c[I] = sum of r over aggregate I: one wavefront per coarse row, members
-// strided over the lanes and combined by a fixed shuffle tree
-// With xc, also the first smoothing iterate of the coarse level, xc = D_c^-1 bc.
+// b_c[I] = sum of r over aggregate I: kRL lanes per coarse row (four coarse
+// rows per wavefront), members strided over the lanes and combined by a fixed
+// shuffle tree.  With xc, also the first smoothing iterate of the coarse
+// level, xc = D_c^-1 bc.
+constexpr int kRL = 16;
 template <class X>
 __global__ __launch_bounds__(kAT) void vc_restrict_kernel(int32_t nc, const int32_t *__restrict__ mptr,
                                                           const int32_t *__restrict__ mrows, const X *__restrict__ r,
                                                           X *__restrict__ bc, const X *__restrict__ dinv_c,
                                                           X *__restrict__ xc, const PcgState *st) {
     if (st && st->done) return;
-    const int lane = threadIdx.x & 63;
-    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t I = w0; I < nc; I += nw) {
+    const int sub = threadIdx.x & (kRL - 1);
+    const int64_t g0 = ((int64_t)xcd_block() * blockDim.x + threadIdx.x) / kRL;
+    const int64_t ng = ((int64_t)gridDim.x * blockDim.x) / kRL;
+    // every lane of a wavefront runs the same number of passes (the shuffles need them all)
+    for (int64_t gb = g0 - (g0 & (64 / kRL - 1)); gb < nc; gb += ng) {
+        const int64_t I = gb + (g0 & (64 / kRL - 1));
         X s = 0;
-        for (int32_t t = mptr[I] + lane; t < mptr[I + 1]; t += 64) s += r[mrows[t]];
+        if (I < nc)
+            for (int32_t t = mptr[I] + sub; t < mptr[I + 1]; t += kRL) s += r[mrows[t]];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-        if (lane == 0) {
+        for (int o = kRL / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (sub == 0 && I < nc) {
             bc[I] = s;
             if (xc) xc[I] = dinv_c[I] * s;
         }
@@ -1179,7 +1184,7 @@ __global__ __launch_bounds__(kAT) void vc_small_kernel(Sell<V> A, const X *__res
         else if constexpr (MODE == 2) return dinv[j] * b[j] + e[agg[j]];
         else return x[j] + e[agg[j]];
     };
-    for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w * kRowsPerWave < A.n; w += nw) {
+    for (int64_t w = ((int64_t)xcd_block() * blockDim.x + threadIdx.x) >> 6; w * kRowsPerWave < A.n; w += nw) {
         const int32_t i = (int32_t)(w * kRowsPerWave) + rr;
         X s0 = 0, s1 = 0;
         if (i < A.n) {
@@ -1219,7 +1224,7 @@ __global__ __launch_bounds__(kAT) void vc_dense_kernel(int32_t n, const X *__res
                                                        X *__restrict__ x, const PcgState *st) {
     if (st && st->done) return;
     const int lane = threadIdx.x & 63;
-    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n;
+    for (int64_t i = ((int64_t)xcd_block() * blockDim.x + threadIdx.x) >> 6; i < n;
          i += ((int64_t)gridDim.x * blockDim.x) >> 6) {
         double s = 0.0;
         for (int32_t j = lane; j < n; j += 64) s += (double)Ainv[i * n + j] * (double)b[j];
@@ -1369,7 +1374,7 @@ void amg_launch_pre(hipStream_t s, Sell<V> A, const X *dinv, const X *b, X *x, X
 template <class X>
 void amg_launch_restrict(hipStream_t s, int32_t nc, const int32_t *mptr, const int32_t *mrows, const X *r, X *bc,
                          const X *dinv_c, X *xc, const PcgState *st) {
-    ALAUNCH(vc_restrict_kernel<X>, gridv((int64_t)nc * 64), kAT, nc, mptr, mrows, r, bc, dinv_c, xc, st);
+    ALAUNCH(vc_restrict_kernel<X>, gridv((int64_t)nc * kRL), kAT, nc, mptr, mrows, r, bc, dinv_c, xc, st);
 }
 template <class V, class X>
 void amg_launch_resid(hipStream_t s, Sell<V> A, const X *b, const X *x, X *r, const PcgState *st) {

@@ -14,7 +14,7 @@ constexpr int kT = 256;
 constexpr int kDots = 8;  // basis vectors per block in the multi-dot kernel
 
 #define GS(i, n) \
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
 template <class V, class T>
 __global__ __launch_bounds__(kT) void gm_spmv_kernel(Sell<V> A, const T *__restrict__ x, T *__restrict__ y) {

@@ -12,6 +12,17 @@
 
 namespace vag {
 
+// The workgroups of a launch are dealt to the 8 XCDs in turn (block b to XCD
+// b mod 8), each XCD with its own L2.  xcd_block() renumbers the blocks so
+// that every XCD receives one contiguous run of block indices: neighbouring
+// rows then share an L2, and the gathers of a row's neighbours (and of an
+// aggregate's members) hit lines that the same XCD has already fetched.  A
+// bijection of [0, gridDim.x).
+__device__ inline unsigned xcd_block() {
+    const unsigned nb = gridDim.x, b = blockIdx.x, q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 struct OpSum {
     __device__ static double id() { return 0.0; }
     __device__ static double op(double a, double b) { return a + b; }

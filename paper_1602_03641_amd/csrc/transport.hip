@@ -455,7 +455,7 @@ __global__ __launch_bounds__(256) void transport_step_kernel(int32_t nrow, const
                                                              const double *__restrict__ tdiag,
                                                              const double *__restrict__ c_in,
                                                              double *__restrict__ c_out, double theta) {
-    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t t = xcd_block() * blockDim.x + threadIdx.x;
     const int32_t sl = t / kSliceRows, lane = t % kSliceRows;
     if ((int64_t)sl * kSliceRows >= nrow) return;
     const uint16_t m = meta[t];
