@@ -166,7 +166,7 @@ def pmc_traffic(kernel, workload):
     for line in open(path):
         cells = [c.strip().strip("`") for c in line.split("|")]
         if len(cells) > 5 and cells[1] == f"vag::{kernel}":
-            return int(cells[5])
+            return int(cells[-2])  # the last column: calibrated bytes per dispatch
     return None
 
 
@@ -284,7 +284,7 @@ def main():
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": pmc_traffic("pcg_spmv_kernel<double, double>" if dom == "spmv" else "transport_step_kernel",
-                                       {"config2": "config2_64cubed"}.get(args.workload, "") if args.n == n_def else ""),
+                                       {"config2": "config2_64cubed", "config3": "config3_128cubed"}.get(args.workload, "") if args.n == n_def else ""),
                 "bytes_per_launch": ab[dom], "ms_per_launch": ms_dom,
                 "other": {"spmv_GBs": round(ab["spmv"] / (ms_spmv * 1e-3) / 1e9, 1),
                           "transport_step_GBs": round(ab["transport_step"] / (ms_step * 1e-3) / 1e9, 1),

@@ -205,8 +205,7 @@ vag_status vag_update(vag_handle *h, const vag_rock *rock, const vag_fractures *
                       const double *p_bar, const double *c_bar, vag_mem mem);
 
 /* Binds the handle to another HIP stream (NULL: the null stream).  Waits for
- * the work already queued on the old stream first: the handle's device
- * buffers are allocated and freed in the order of its stream. */
+ * the work already queued on the old stream first. */
 vag_status vag_set_stream(vag_handle *h, void *hip_stream);
 
 /* Replaces the solver options of a handle (takes effect at the next solve). */
@@ -293,14 +292,14 @@ size_t vag_footprint_bytes(const vag_handle *h);
  * failed vag_create in this thread. */
 const char *vag_last_error(const vag_handle *h);
 
-/* Releases the handle.  Its device memory goes back to the library's
- * per-device pool and its pinned host blocks to the library's free list,
- * both kept for later handles of the process (vag_trim_memory returns the
- * unused device memory to the system). */
+/* Releases the handle (after waiting for its stream).  Its device blocks go
+ * back to the library's per-device cache and its pinned host blocks to the
+ * library's free list, both kept for later handles of the process
+ * (vag_trim_memory returns the cached device blocks to the system). */
 void vag_destroy(vag_handle *h);
 
-/* Returns the unused blocks of the current device's pool to the system.
- * Waits for the device to be idle first.  Errors: VAG_ERR_HIP. */
+/* Returns the cached (unused) device blocks of the current device to the
+ * system.  Waits for the device to be idle first.  Errors: VAG_ERR_HIP. */
 vag_status vag_trim_memory(void);
 
 /*

@@ -7,6 +7,7 @@
 
 #include <map>
 #include <mutex>
+#include <unordered_map>
 
 #include "amg.h"
 #include "gmres.h"
@@ -16,27 +17,86 @@ using namespace vag;
 
 namespace vag {
 
-hipMemPool_t device_pool() {
-    static std::mutex mu;
-    static hipMemPool_t pools[64] = {};
+namespace {
+struct DevCache {
+    std::multimap<size_t, void *> free;          // block size -> free blocks
+    std::unordered_map<void *, size_t> size_of;  // every block handed out or cached
+};
+std::mutex g_dev_mu;
+DevCache g_dev[64];
+int current_device() {
     int dev = 0;
     VAG_HIP(hipGetDevice(&dev));
     if (dev < 0 || dev >= 64) throw Error(VAG_ERR_UNSUPPORTED, "device index beyond 63");
-    std::lock_guard<std::mutex> lk(mu);
-    if (!pools[dev]) {
-        hipMemPoolProps props{};
-        props.allocType = hipMemAllocationTypePinned;
-        props.handleTypes = hipMemHandleTypeNone;
-        props.location.type = hipMemLocationTypeDevice;
-        props.location.id = dev;
-        hipMemPool_t p = nullptr;
-        VAG_HIP(hipMemPoolCreate(&p, &props));
-        // keep freed blocks for reuse instead of returning them at every synchronisation
-        uint64_t keep = UINT64_MAX;
-        VAG_HIP(hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep));
-        pools[dev] = p;
+    return dev;
+}
+}  // namespace
+
+void *dev_alloc(size_t bytes) {
+    const size_t want = (bytes + 4095) & ~(size_t)4095;
+    const int dev = current_device();
+    {
+        std::lock_guard<std::mutex> lk(g_dev_mu);
+        DevCache &c = g_dev[dev];
+        // the smallest cached block that fits, if it wastes at most a quarter
+        auto it = c.free.lower_bound(want);
+        if (it != c.free.end() && it->first <= want + want / 4 + (1u << 16)) {
+            void *p = it->second;
+            c.free.erase(it);
+            return p;
+        }
     }
-    return pools[dev];
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipErrorOutOfMemory) {
+        // give the cached blocks back and try once more
+        (void)hipGetLastError();
+        VAG_HIP(hipDeviceSynchronize());
+        std::vector<void *> drop;
+        {
+            std::lock_guard<std::mutex> lk(g_dev_mu);
+            DevCache &c = g_dev[dev];
+            for (auto &kv : c.free) {
+                drop.push_back(kv.second);
+                c.size_of.erase(kv.second);
+            }
+            c.free.clear();
+        }
+        for (void *q : drop) (void)hipFree(q);
+        e = hipMalloc(&p, want);
+    }
+    VAG_HIP(e);
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    g_dev[dev].size_of[p] = want;
+    return p;
+}
+
+void dev_free(void *p, hipStream_t owner_stream) {
+    if (!p) return;
+    // the owner's queued work may still use the block
+    (void)hipStreamSynchronize(owner_stream);
+    const int dev = current_device();
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    DevCache &c = g_dev[dev];
+    auto it = c.size_of.find(p);
+    if (it == c.size_of.end()) return;  // not ours: leave it alone
+    c.free.emplace(it->second, p);
+}
+
+// Frees the cached blocks of the current device (the device must be idle).
+void dev_trim() {
+    const int dev = current_device();
+    std::vector<void *> drop;
+    {
+        std::lock_guard<std::mutex> lk(g_dev_mu);
+        DevCache &c = g_dev[dev];
+        for (auto &kv : c.free) {
+            drop.push_back(kv.second);
+            c.size_of.erase(kv.second);
+        }
+        c.free.clear();
+    }
+    for (void *q : drop) VAG_HIP(hipFree(q));
 }
 
 namespace {
@@ -176,7 +236,11 @@ void upload(vag_handle *h, DBuf<T> &d, const T *src, size_t n, vag_mem mem) {
 template <class T>
 void upload_vec(vag_handle *h, DBuf<T> &d, const std::vector<T> &v) {
     d.alloc(v.size(), h->tr);
-    if (!v.empty()) VAG_HIP(hipMemcpy(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (v.empty()) return;
+    // on the handle's stream: a worker stream created non-blocking is not
+    // ordered after the null stream that hipMemcpy would use
+    VAG_HIP(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
+    VAG_HIP(hipStreamSynchronize(h->stream));
 }
 
 template <class T>
@@ -187,13 +251,14 @@ void download(vag_handle *h, T *dst, const DBuf<T> &d, size_t n, vag_mem mem) {
 
 // host copy of an input that may live in device memory
 template <class T>
-std::vector<T> host_copy(const T *src, size_t n, vag_mem mem) {
+std::vector<T> host_copy(const T *src, size_t n, vag_mem mem, hipStream_t s) {
     std::vector<T> v(n);
     if (n) {
         if (!src) throw Error(VAG_ERR_ARG, "null input array");
-        if (mem == VAG_MEM_DEVICE)
-            VAG_HIP(hipMemcpy(v.data(), src, n * sizeof(T), hipMemcpyDeviceToHost));
-        else
+        if (mem == VAG_MEM_DEVICE) {
+            VAG_HIP(hipMemcpyAsync(v.data(), src, n * sizeof(T), hipMemcpyDeviceToHost, s));
+            VAG_HIP(hipStreamSynchronize(s));
+        } else
             std::memcpy(v.data(), src, n * sizeof(T));
     }
     return v;
@@ -534,9 +599,10 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         check_options(h->opt);
         const int64_t nn = mesh->n_nodes, nc = mesh->n_cells, nf = frac ? frac->n_frac : 0;
         if (nn <= 0 || nc <= 0 || nf < 0) throw Error(VAG_ERR_ARG, "empty mesh");
-        auto hex8 = host_copy(mesh->hex8, 8 * (size_t)nc, mem);
-        std::vector<int32_t> fnodes = nf ? host_copy(frac->face_nodes, 4 * (size_t)nf, mem) : std::vector<int32_t>();
-        auto dir = host_copy(bc->node_dirichlet, (size_t)nn, mem);
+        auto hex8 = host_copy(mesh->hex8, 8 * (size_t)nc, mem, h->stream);
+        std::vector<int32_t> fnodes =
+            nf ? host_copy(frac->face_nodes, 4 * (size_t)nf, mem, h->stream) : std::vector<int32_t>();
+        auto dir = host_copy(bc->node_dirichlet, (size_t)nn, mem, h->stream);
         build_symbolic(nn, nc, nf, hex8.data(), fnodes.data(), dir.data(), h->opt.eliminate_frac_faces != 0, h->S);
         const Symbolic &S = h->S;
         h->mu = rock->mu;
@@ -613,7 +679,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         h->rparts.alloc(4 * (size_t)kReduceBlocks, h->tr);
         h->scal.alloc(8, h->tr);
         h->pcg.alloc(2, h->tr);
-        VAG_HIP(hipMemset(h->pcg.p, 0, 2 * sizeof(PcgState)));
+        VAG_HIP(hipMemsetAsync(h->pcg.p, 0, 2 * sizeof(PcgState), h->stream));
         h->u_node.alloc(nn, h->tr);
         h->u_cell.alloc(nc, h->tr);
         h->u_frac.alloc(std::max<int64_t>(nf, 1), h->tr);
@@ -711,7 +777,7 @@ vag_status vag_set_fluxes(vag_handle *h, const double *F_cell, const double *F_c
 vag_status vag_set_stream(vag_handle *h, void *hip_stream) {
     if (!h) return VAG_ERR_ARG;
     return guard(h, [&] {
-        // the buffers are ordered on the old stream: let it drain first
+        // the old stream may still use the buffers: let it drain first
         VAG_HIP(hipStreamSynchronize(h->stream));
         h->stream = reinterpret_cast<hipStream_t>(hip_stream);
         h->tr.stream = h->stream;
@@ -996,10 +1062,11 @@ vag_status vag_get_system(vag_handle *h, int64_t *row_ptr, int64_t *col, double 
             bo[o] = bv[r];
         }
         hipMemcpyKind k = mem == VAG_MEM_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
-        if (row_ptr) VAG_HIP(hipMemcpy(row_ptr, rp.data(), rp.size() * sizeof(int64_t), k));
-        if (col) VAG_HIP(hipMemcpy(col, cl.data(), cl.size() * sizeof(int64_t), k));
-        if (val) VAG_HIP(hipMemcpy(val, cv.data(), cv.size() * sizeof(double), k));
-        if (b) VAG_HIP(hipMemcpy(b, bo.data(), (size_t)n * sizeof(double), k));
+        if (row_ptr) VAG_HIP(hipMemcpyAsync(row_ptr, rp.data(), rp.size() * sizeof(int64_t), k, h->stream));
+        if (col) VAG_HIP(hipMemcpyAsync(col, cl.data(), cl.size() * sizeof(int64_t), k, h->stream));
+        if (val) VAG_HIP(hipMemcpyAsync(val, cv.data(), cv.size() * sizeof(double), k, h->stream));
+        if (b) VAG_HIP(hipMemcpyAsync(b, bo.data(), (size_t)n * sizeof(double), k, h->stream));
+        VAG_HIP(hipStreamSynchronize(h->stream));
     });
 }
 
@@ -1103,7 +1170,7 @@ const char *vag_last_error(const vag_handle *h) { return h ? h->err.c_str() : g_
 vag_status vag_trim_memory(void) {
     try {
         VAG_HIP(hipDeviceSynchronize());
-        VAG_HIP(hipMemPoolTrimTo(device_pool(), 0));
+        dev_trim();
         return VAG_OK;
     } catch (const Error &e) {
         return e.status;

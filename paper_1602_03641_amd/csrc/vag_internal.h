@@ -53,12 +53,14 @@ constexpr int kKrylovThreads = 1024;  // block size of the Krylov kernels (and o
 // ---------------------------------------------------------------------------
 // device buffer
 // ---------------------------------------------------------------------------
-// Device memory comes from a per-device stream-ordered pool that keeps freed
-// blocks for reuse: hipMalloc/hipFree would synchronise the whole device at
-// every handle creation and destruction, serialising independent handles
-// that run side by side on their own streams.  Allocations and frees are
-// ordered on the owning handle's stream.
-hipMemPool_t device_pool();
+// Device memory comes from a per-device cache of blocks: hipFree would
+// synchronise the whole device at every handle destruction, serialising the
+// independent handles that run side by side on their own streams.  A block
+// returns to the cache only after the stream of its owner has been
+// synchronised, so no queued kernel of the old owner can touch it once
+// another handle takes it.
+void *dev_alloc(size_t bytes);
+void dev_free(void *p, hipStream_t owner_stream);
 // Pinned host blocks from a process-wide free list (same reason: hipHostFree
 // synchronises the device).  bytes must be the size given to pinned_get.
 void *pinned_get(size_t bytes);
@@ -66,7 +68,7 @@ void pinned_put(void *p, size_t bytes);
 
 struct Tracker {
     size_t bytes = 0;
-    hipStream_t stream = nullptr;  // the stream allocations and frees are ordered on
+    hipStream_t stream = nullptr;  // the stream the buffers are used on
 };
 
 template <class T>
@@ -79,13 +81,13 @@ struct DBuf {
         tr = &t;
         n = count;
         if (count) {
-            VAG_HIP(hipMallocFromPoolAsync(reinterpret_cast<void **>(&p), count * sizeof(T), device_pool(), t.stream));
+            p = static_cast<T *>(dev_alloc(count * sizeof(T)));
             t.bytes += count * sizeof(T);
         }
     }
     void release() {
         if (p) {
-            (void)hipFreeAsync(p, tr ? tr->stream : nullptr);
+            dev_free(p, tr ? tr->stream : nullptr);
             if (tr) tr->bytes -= n * sizeof(T);
         }
         p = nullptr;

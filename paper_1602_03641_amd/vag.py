@@ -324,7 +324,7 @@ class Handle:
 
 
 def trim_memory():
-    """Return the unused blocks of the library's device memory pool to the system."""
+    """Return the library's cached (unused) device blocks to the system."""
     st = load().vag_trim_memory()
     if st != VAG_OK:
         raise VagError(st, "vag_trim_memory failed")

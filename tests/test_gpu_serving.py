@@ -182,8 +182,8 @@ def test_cached_handle_reused_with_new_data():
 
 
 def test_pool_reuse_and_trim():
-    """Handles created and destroyed in turn reuse the library's pooled device
-    memory; trimming returns the unused blocks and later handles still work."""
+    """Handles created and destroyed in turn reuse the library's cached device
+    blocks; trimming returns the unused blocks and later handles still work."""
     vag = _vag()
     p = synth.random_problem((7, 6, 5), 9, n_patches=3, n_steps=5)
     ref = None
