@@ -198,7 +198,7 @@ def main():
                          "40 patches, FP32-AMG GMRES with FP64 refinement; config5: 192^3, 200 patches at 1e6, "
                          "FP32-AMG CG with FP64 refinement")
     ap.add_argument("--precision", choices=["fp64", "mixed", "mixed_ir"], default=None)
-    ap.add_argument("--krylov", choices=["cg", "gmres"], default=None)
+    ap.add_argument("--krylov", choices=["cg", "gmres", "bicgstab"], default=None)
     ap.add_argument("--n", type=int, default=None, help="cells per side (default: the workload's)")
     ap.add_argument("--keep-faces", action="store_true", help="fracture faces stay unknowns (no group elimination)")
     ap.add_argument("--amg-sweeps", type=int, default=0, help="l1-Jacobi sweeps on the coarse levels (0: default)")
@@ -241,7 +241,7 @@ def main():
     opts = dict(rtol=prob.rtol, cfl=prob.cfl, max_iter=50000, inner_rtol=1e-2, gmres_restart=100,
                 precond=vag.VAG_PC_AMG if args.precond == "amg" else vag.VAG_PC_JACOBI,
                 precision={"fp64": vag.VAG_FP64, "mixed": vag.VAG_MIXED, "mixed_ir": vag.VAG_MIXED_IR}[args.precision],
-                krylov=vag.VAG_GMRES if args.krylov == "gmres" else vag.VAG_CG,
+                krylov={"cg": vag.VAG_CG, "gmres": vag.VAG_GMRES, "bicgstab": vag.VAG_BICGSTAB}[args.krylov],
                 eliminate_frac_faces=0 if args.keep_faces else 1)
     if args.amg_sweeps > 0:
         opts["amg_sweeps"] = args.amg_sweeps

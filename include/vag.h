@@ -63,7 +63,11 @@ typedef enum { VAG_MEM_HOST = 0, VAG_MEM_DEVICE = 1 } vag_mem;
  * FP32 hierarchy of the diagonally scaled matrix.  Assembly, elimination,
  * fluxes and transport are FP64 in every mode. */
 typedef enum { VAG_FP64 = 0, VAG_MIXED = 1, VAG_MIXED_IR = 2 } vag_precision;
-typedef enum { VAG_CG = 0, VAG_GMRES = 1 } vag_krylov;
+/* Krylov method for the eliminated system (§5.3 compares CG, GMRES and
+ * BiCGStab): VAG_CG (the system is SPD), VAG_GMRES (restarted GMRES(m), CGS2),
+ * VAG_BICGSTAB (right-preconditioned BiCGStab, FP64 vectors; not with
+ * VAG_MIXED_IR). */
+typedef enum { VAG_CG = 0, VAG_GMRES = 1, VAG_BICGSTAB = 2 } vag_krylov;
 typedef enum { VAG_PC_JACOBI = 0, VAG_PC_AMG = 1 } vag_precond;
 
 /*

@@ -178,6 +178,8 @@ struct vag_handle {
     // GMRES(m) work: FP64 basis (VAG_FP64 / VAG_MIXED) or FP32 basis (inner solves of VAG_MIXED_IR)
     DBuf<double> gmV, gmw, gmt, gmparts, gmnparts, gmhd;
     DBuf<float> gmV32, gmw32, gmt32;
+    // BiCGStab work (p, phat, v are p, z, q)
+    DBuf<double> bcg_rhat, bcg_s, bcg_shat, bcg_t, bcg_parts;
     double *h_gm = nullptr;
     int h_gm_m = 0;
     int last_outer = 1, last_inner = 0;
@@ -273,7 +275,10 @@ void check_options(const vag_options &o) {
         throw Error(VAG_ERR_UNSUPPORTED, "mixed precision needs the AMG preconditioner");
     if (o.precision == VAG_MIXED_IR && !(o.inner_rtol > 0 && o.inner_rtol < 1))
         throw Error(VAG_ERR_ARG, "inner_rtol must lie in (0, 1)");
-    if (o.krylov != VAG_CG && o.krylov != VAG_GMRES) throw Error(VAG_ERR_ARG, "unknown Krylov method");
+    if (o.krylov != VAG_CG && o.krylov != VAG_GMRES && o.krylov != VAG_BICGSTAB)
+        throw Error(VAG_ERR_ARG, "unknown Krylov method");
+    if (o.krylov == VAG_BICGSTAB && o.precision == VAG_MIXED_IR)
+        throw Error(VAG_ERR_UNSUPPORTED, "BiCGStab runs in FP64 (with the FP64 or FP32 hierarchy), not as an inner solver");
     if (o.krylov == VAG_GMRES && (o.gmres_restart < 1 || o.gmres_restart > 1024))
         throw Error(VAG_ERR_ARG, "gmres_restart must lie in [1, 1024]");
     if (o.precond != VAG_PC_JACOBI && o.precond != VAG_PC_AMG)
@@ -410,6 +415,61 @@ void run_pcg(vag_handle *h) {
         k = h->h_pcg->iter;
         if (!h->h_pcg->converged || k >= max_iter) break;
         // true residual check
+        launch_residual_norm(s, A, h->x.p, h->b.p, h->q.p, h->rparts.p, h->scal.p);
+        VAG_HIP(hipMemcpyAsync(h->h_scal, h->scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipStreamSynchronize(s));
+        if (bb < 0) bb = h->h_scal[1];
+        const double rr = h->h_scal[0];
+        if (rr <= h->opt.rtol * h->opt.rtol * bb) break;
+        if (restart >= 3) {  // the true residual stays above rtol (rounding floor): report it
+            h->h_pcg->converged = 0;
+            break;
+        }
+        rtol = std::min(0.5, h->opt.rtol * std::sqrt(bb / rr));
+        k0 = k;
+    }
+    h->last_inner = h->h_pcg->iter;
+    h->last_outer = 1;
+}
+
+// Right-preconditioned BiCGStab from x = 0 with device-resident scalars; the
+// host reads the state every check_every iterations.  A true-residual check
+// and up to three warm restarts, as for CG.
+void run_bicgstab(vag_handle *h) {
+    hipStream_t s = h->stream;
+    const int32_t n = h->S.nunk;
+    const size_t nv = (size_t)std::max(n, 1);
+    for (auto *v : {&h->bcg_rhat, &h->bcg_s, &h->bcg_shat, &h->bcg_t}) ensure(*v, nv, h->tr);
+    ensure(h->bcg_parts, 8 * (size_t)kReduceBlocks, h->tr);
+    double *parts = h->bcg_parts.p;
+    PcgState *st = h->pcg.p;
+    const Sell<double> A = h->Asell();
+    const int max_iter = h->opt.max_iter;
+    int k = 0, k0 = 0;
+    double rtol = h->opt.rtol, bb = -1.0;
+    for (int restart = 0;; ++restart) {
+        launch_bcg_init(s, A, restart == 0, k0, h->b.p, h->x.p, h->r.p, h->bcg_rhat.p, parts);
+        launch_bcg_start(s, n, parts, st, rtol, k0);
+        for (;;) {
+            const int kend = std::min(k + h->opt.check_every, max_iter);
+            for (; k < kend; ++k) {
+                launch_bcg_direction(s, n, k, k0, h->r.p, h->p.p, h->q.p, parts, st, true);
+                precond_apply(h, h->p.p, h->z.p, st);
+                launch_bcg_spmv_v(s, A, h->z.p, h->q.p, h->bcg_rhat.p, parts, st);
+                launch_bcg_s(s, n, k, h->r.p, h->q.p, h->z.p, h->bcg_s.p, h->x.p, parts, st);
+                precond_apply(h, h->bcg_s.p, h->bcg_shat.p, st);
+                launch_bcg_spmv_t(s, A, h->bcg_shat.p, h->bcg_t.p, h->bcg_s.p, parts, st);
+                launch_bcg_update(s, n, k, h->z.p, h->bcg_shat.p, h->bcg_s.p, h->bcg_t.p, h->bcg_rhat.p, h->x.p,
+                                  h->r.p, parts, st);
+            }
+            // convergence test of the last residual without a new direction
+            launch_bcg_direction(s, n, k, k0, h->r.p, h->p.p, h->q.p, parts, st, false);
+            VAG_HIP(hipMemcpyAsync(h->h_pcg, st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+            VAG_HIP(hipStreamSynchronize(s));
+            if (h->h_pcg->done || k >= max_iter) break;
+        }
+        k = h->h_pcg->iter;
+        if (!h->h_pcg->converged || k >= max_iter) break;
         launch_residual_norm(s, A, h->x.p, h->b.p, h->q.p, h->rparts.p, h->scal.p);
         VAG_HIP(hipMemcpyAsync(h->h_scal, h->scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipStreamSynchronize(s));
@@ -837,6 +897,8 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
             run_mixed(h);
         else if (h->opt.krylov == VAG_GMRES)
             run_gmres(h);
+        else if (h->opt.krylov == VAG_BICGSTAB)
+            run_bicgstab(h);
         else
             run_pcg(h);
         VAG_HIP(hipEventRecord(h->ev[3], s));

@@ -223,6 +223,22 @@ void launch_group_back(hipStream_t s, int32_t ngroup, const int32_t *grp_ptr, co
                        const int32_t *frac_unk, const double *Gb, const double *b, double *x);
 void launch_diag_inv(hipStream_t s, int32_t n, const int32_t *diag_pos, const double *A, double *dinv);
 
+// BiCGStab (bicgstab.hip): parts holds 8 * bcg_grid(n) doubles
+int bcg_grid(int64_t n);
+void launch_bcg_init(hipStream_t s, Sell<double> A, bool zero_x, int k0, const double *b, double *x, double *r,
+                     double *rhat, double *parts);
+void launch_bcg_start(hipStream_t s, int32_t n, double *parts, PcgState *st, double rtol, int k0);
+void launch_bcg_direction(hipStream_t s, int32_t n, int k, int k0, const double *r, double *p, const double *v,
+                          double *parts, PcgState *st, bool update);
+void launch_bcg_spmv_v(hipStream_t s, Sell<double> A, const double *phat, double *v, const double *rhat,
+                       double *parts, const PcgState *st);
+void launch_bcg_s(hipStream_t s, int32_t n, int k, const double *r, const double *v, const double *phat, double *sv,
+                  double *x, double *parts, PcgState *st);
+void launch_bcg_spmv_t(hipStream_t s, Sell<double> A, const double *shat, double *t, const double *sv, double *parts,
+                       const PcgState *st);
+void launch_bcg_update(hipStream_t s, int32_t n, int k, const double *phat, const double *shat, const double *sv,
+                       const double *t, const double *rhat, double *x, double *r, double *parts, PcgState *st);
+
 // Krylov
 int pcg_grid(int64_t n);
 void launch_fill(hipStream_t s, int64_t n, double v, double *x);

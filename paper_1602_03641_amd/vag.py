@@ -23,7 +23,7 @@ VAG_ERR_ARG, VAG_ERR_MESH, VAG_ERR_UNSUPPORTED, VAG_ERR_OOM, VAG_ERR_HIP, VAG_ER
 VAG_ERR_TIMEOUT, VAG_ERR_CANCELLED = -7, -8
 VAG_MEM_HOST, VAG_MEM_DEVICE = 0, 1
 VAG_FP64, VAG_MIXED, VAG_MIXED_IR = 0, 1, 2
-VAG_CG, VAG_GMRES = 0, 1
+VAG_CG, VAG_GMRES, VAG_BICGSTAB = 0, 1, 2
 VAG_PC_JACOBI, VAG_PC_AMG = 0, 1
 VAG_KERNEL_SPMV, VAG_KERNEL_TRANSPORT_STEP, VAG_KERNEL_LOCAL, VAG_KERNEL_PRECOND = 0, 1, 2, 3
 

@@ -486,6 +486,52 @@ def test_gmres_matches_cg():
 
 
 # ---------------------------------------------------------------------------
+# BiCGStab (right preconditioning, device-resident scalars)
+# ---------------------------------------------------------------------------
+def _bicgstab(**kw):
+    from paper_1602_03641_amd import vag
+    return dict(krylov=vag.VAG_BICGSTAB, **kw)
+
+
+@pytest.mark.parametrize("precond,precision", [("jacobi", "fp64"), ("amg", "fp64"), ("amg", "mixed")])
+def test_bicgstab_parity(precond, precision):
+    """Jittered anisotropic mesh, contrasts up to 1e6: the oracle's solution."""
+    from paper_1602_03641_amd import vag
+    p = synth.random_problem((10, 8, 7), 8, n_patches=6, n_steps=20)
+    pc = vag.VAG_PC_JACOBI if precond == "jacobi" else vag.VAG_PC_AMG
+    pr = vag.VAG_FP64 if precision == "fp64" else vag.VAG_MIXED
+    g = gpu_run(p, rtol=1e-12, max_iter=20000, precond=pc, precision=pr, **_bicgstab())
+    o = oracle.run(p, rtol=1e-13)
+    assert reached(g["info"], max(1e-12, residual_floor(p, o)))
+    compare(p, g, o)
+
+
+def test_bicgstab_config1_and_rejects_ir():
+    from paper_1602_03641_amd import vag
+    p = synth.config1()
+    g = gpu_run(p, rtol=1e-13, max_iter=5000, precond=vag.VAG_PC_AMG, **_bicgstab())
+    o = oracle.run(p, rtol=1e-13)
+    assert reached(g["info"])
+    compare(p, g, o)
+    with pytest.raises(vag.VagError) as e:
+        vag.Handle(p, precision=vag.VAG_MIXED_IR, **_bicgstab())
+    assert e.value.status == vag.VAG_ERR_UNSUPPORTED
+
+
+def test_bicgstab_matches_cg():
+    """Both Krylov methods solve the oracle's own system to the tolerance."""
+    from paper_1602_03641_amd import vag
+    p = synth.random_problem((12, 9, 8), 10, n_patches=7, n_steps=0)
+    a = gpu_run(p, rtol=1e-11, max_iter=20000, precond=vag.VAG_PC_AMG)
+    b = gpu_run(p, rtol=1e-11, max_iter=20000, precond=vag.VAG_PC_AMG, **_bicgstab())
+    assert a["info"]["status"] == 0 and b["info"]["status"] == 0
+    assert oracle_certificate(p, a) <= 2e-11 and oracle_certificate(p, b) <= 2e-11
+    assert rel_l2(a["u_node"], b["u_node"]) <= 1e-6
+    # two preconditioned products per BiCGStab iteration against one for CG
+    print(f"iterations: CG {a['info']['iterations']}, BiCGStab {b['info']['iterations']}")
+
+
+# ---------------------------------------------------------------------------
 # Scaled-down instances of the 128^3 and 192^3 generators (jitter, full
 # anisotropic tensors, many patches, contrasts up to 1e6): full parity
 # ---------------------------------------------------------------------------
