@@ -136,7 +136,10 @@ typedef struct {
                                the coarse levels (the finest level has one of each) */
     int eliminate_frac_faces;  /* 1: eliminate fracture-face groups onto the nodes
                                   (fixed at vag_create); 0: faces stay unknowns */
-    int reserved[7];
+    int amg_aggregate_hops; /* radius of the aggregates: roots form a distance-2 (2, the
+                               default) or distance-1 (1: smaller aggregates, more levels)
+                               independent set of the strength graph; 0 = default */
+    int reserved[6];
 } vag_options;
 
 typedef struct {

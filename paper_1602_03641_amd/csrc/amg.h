@@ -18,8 +18,8 @@ void amg_launch_diag(hipStream_t s, Sell<double> A, double *diag, double *dinv);
 // undecided: rounds * kCntSlots * kCntStride zeroed counters; hcnt: pinned
 // host memory of kCntSlots * kCntStride ints
 constexpr int kCntSlots = 16, kCntStride = 32, kMisRounds = 48;
-void amg_launch_mis(hipStream_t s, Sell<double> A, const double *diag, double theta, int rounds, uint32_t *T,
-                    uint32_t *T1, int *undecided, int32_t *flag, int *hcnt, int32_t *scol);
+void amg_launch_mis(hipStream_t s, Sell<double> A, const double *diag, double theta, int rounds, int hops,
+                    uint32_t *T, uint32_t *T1, int *undecided, int32_t *flag, int *hcnt, int32_t *scol);
 void amg_launch_scan(hipStream_t s, int32_t n, const int32_t *in, int32_t *out, int32_t *tmp);
 void amg_launch_aggregate(hipStream_t s, Sell<double> A, const double *diag, double theta, const int32_t *root,
                           const int32_t *rid, int32_t *agg1, int32_t *agg, int32_t *lonely);
@@ -100,6 +100,7 @@ struct AmgOptions {
     int dense_max = 1024;
     int coarse_sweeps = 4;  // sweeps of the coarsest level when it is not inverted
     int sweeps = 1;         // sweeps before and after the correction on levels >= 1
+    int hops = 2;           // roots: distance-2 (2) or distance-1 (1) independent set
 };
 
 class Amg {

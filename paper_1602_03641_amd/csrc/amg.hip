@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kAT) void mis_max_kernel(int32_t n, const int64_t *
 }
 
 // second hop, then the decision of undecided nodes
-__global__ __launch_bounds__(kAT) void mis_select_kernel(int32_t n, const int64_t *__restrict__ ptr,
+__global__ __launch_bounds__(kAT) void mis_select_kernel(int32_t n, int hops, const int64_t *__restrict__ ptr,
                                                          const int32_t *__restrict__ scol,
                                                          const uint32_t *__restrict__ T1, uint32_t *__restrict__ T,
                                                          int *__restrict__ undecided, const int *__restrict__ active) {
@@ -148,7 +148,9 @@ __global__ __launch_bounds__(kAT) void mis_select_kernel(int32_t n, const int64_
     GS(i, n) {
         const uint32_t own = T[i];
         if (rank_of(own) != 1) continue;
-        const uint32_t m = strong_max(ptr, scol, (int32_t)i, T1);
+        // two hops: the maximum over the neighbours of the one-hop maxima; one
+        // hop: the one-hop maximum itself
+        const uint32_t m = hops == 2 ? strong_max(ptr, scol, (int32_t)i, T1) : T1[i];
         if (m == own)
             T[i] = (own & ((1u << 30) - 1)) | (2u << 30);  // root
         else if (rank_of(m) == 2)
@@ -1277,15 +1279,15 @@ __global__ __launch_bounds__(kAT) void to_double_kernel(int64_t n, const float *
 void amg_launch_diag(hipStream_t s, Sell<double> A, double *diag, double *dinv) {
     if (A.n > 0) ALAUNCH(amg_diag_kernel, gridv(A.n), kAT, A, diag, dinv);
 }
-void amg_launch_mis(hipStream_t s, Sell<double> A, const double *diag, double theta, int rounds, uint32_t *T,
-                    uint32_t *T1, int *undecided, int32_t *flag, int *hcnt, int32_t *scol) {
+void amg_launch_mis(hipStream_t s, Sell<double> A, const double *diag, double theta, int rounds, int hops,
+                    uint32_t *T, uint32_t *T1, int *undecided, int32_t *flag, int *hcnt, int32_t *scol) {
     ALAUNCH(strength_kernel, gridv(A.n), kAT, A, diag, theta, scol);
     ALAUNCH(mis_init_kernel, gridv(A.n), kAT, A.n, T);
     for (int r = 0; r < rounds; ++r) {
         int *cur = undecided + (int64_t)r * kCntSlots * kCntStride;
         const int *active = r ? cur - kCntSlots * kCntStride : nullptr;
         ALAUNCH(mis_max_kernel, gridv(A.n), kAT, A.n, A.ptr, scol, T, T1, active);
-        ALAUNCH(mis_select_kernel, gridv(A.n), kAT, A.n, A.ptr, scol, T1, T, cur, active);
+        ALAUNCH(mis_select_kernel, gridv(A.n), kAT, A.n, hops, A.ptr, scol, T1, T, cur, active);
         if ((r & 3) == 3 && r + 1 < rounds) {  // stop queueing rounds once nothing is undecided
             VAG_HIP(hipMemcpyAsync(hcnt, cur, kCntSlots * kCntStride * sizeof(int), hipMemcpyDeviceToHost, s));
             VAG_HIP(hipStreamSynchronize(s));

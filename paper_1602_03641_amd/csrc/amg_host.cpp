@@ -50,7 +50,7 @@ void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, co
         VAG_HIP(hipMemsetAsync(counters_.p, 0, 64 * sizeof(int), s));
         VAG_HIP(hipMemsetAsync(mis_cnt_.p, 0, mis_cnt_.n * sizeof(int), s));
         ensure(jcol_, (size_t)lv.stored, tr);  // the strong columns until the collapse reuses it
-        amg_launch_mis(s, lv.A, lv.diag.p, o.theta, std::min(o.mis_rounds, kMisRounds), T_.p, T1_.p, mis_cnt_.p,
+        amg_launch_mis(s, lv.A, lv.diag.p, o.theta, std::min(o.mis_rounds, kMisRounds), o.hops, T_.p, T1_.p, mis_cnt_.p,
                        flag_.p, h_ + 64, jcol_.p);
         amg_launch_scan(s, n, flag_.p, rid_.p, stmp_.p);
         ensure(lv.agg, n, tr);

@@ -275,6 +275,8 @@ void check_options(const vag_options &o) {
         throw Error(VAG_ERR_UNSUPPORTED, "mixed precision needs the AMG preconditioner");
     if (o.precision == VAG_MIXED_IR && !(o.inner_rtol > 0 && o.inner_rtol < 1))
         throw Error(VAG_ERR_ARG, "inner_rtol must lie in (0, 1)");
+    if (o.amg_aggregate_hops < 0 || o.amg_aggregate_hops > 2)
+        throw Error(VAG_ERR_ARG, "amg_aggregate_hops must be 0 (default), 1 or 2");
     if (o.krylov != VAG_CG && o.krylov != VAG_GMRES && o.krylov != VAG_BICGSTAB)
         throw Error(VAG_ERR_ARG, "unknown Krylov method");
     if (o.krylov == VAG_BICGSTAB && o.precision == VAG_MIXED_IR)
@@ -357,6 +359,7 @@ AmgOptions amg_options(const vag_options &o) {
     if (o.amg_coarse_size > 0) a.coarse_size = o.amg_coarse_size;
     if (o.amg_max_levels > 0) a.max_levels = o.amg_max_levels;
     if (o.amg_sweeps > 0) a.sweeps = o.amg_sweeps;
+    if (o.amg_aggregate_hops > 0) a.hops = o.amg_aggregate_hops;
     return a;
 }
 
