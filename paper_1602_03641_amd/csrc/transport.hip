@@ -448,30 +448,77 @@ __global__ __launch_bounds__(kSliceRows) void upwind_fill_kernel(
 
 // c_out = c + theta (T c - c); theta = 1 is the plain step.  Slot t of a
 // slice holds row (slice, meta >> 8) with meta & 255 entries.
-__global__ __launch_bounds__(256) void transport_step_kernel(int32_t nrow, const int64_t *__restrict__ slice_ptr,
-                                                             const uint16_t *__restrict__ meta,
-                                                             const int32_t *__restrict__ tcol,
-                                                             const double *__restrict__ tval,
-                                                             const double *__restrict__ tdiag,
-                                                             const double *__restrict__ c_in,
+// Column compression of the upwind operator, one wavefront per slice: when the
+// columns of a slice's entries lie within 65536 of their minimum, the slice
+// stores 16-bit offsets from that minimum (tbase[slice] = the minimum) and
+// the sweep reads 2 bytes per column instead of 4; otherwise tbase = -1 and
+// the 32-bit columns are read.  Cells and nodes of a slice are neighbours in
+// the mesh, so nearly every slice qualifies.
+__global__ __launch_bounds__(kSliceRows) void upwind_pack_kernel(int32_t nrow, const int64_t *__restrict__ slice_ptr,
+                                                                 const uint16_t *__restrict__ meta,
+                                                                 const int32_t *__restrict__ tcol,
+                                                                 uint16_t *__restrict__ tcol16,
+                                                                 int32_t *__restrict__ tbase) {
+    const int32_t sl = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t t = (int64_t)sl * kSliceRows + lane;
+    const int cnt = ((int64_t)sl * kSliceRows + (meta[t] >> 8) < nrow) ? (meta[t] & 255) : 0;
+    const int64_t b0 = slice_ptr[sl] + lane;
+    int32_t lo = INT32_MAX, hi = -1;
+    for (int k = 0; k < cnt; ++k) {
+        const int32_t c = tcol[b0 + (int64_t)k * kSliceRows];
+        lo = min(lo, c);
+        hi = max(hi, c);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o, 64));
+        hi = max(hi, __shfl_xor(hi, o, 64));
+    }
+    const bool compact = hi < 0 || (int64_t)hi - lo <= 65535;
+    if (compact)
+        for (int k = 0; k < cnt; ++k) {
+            const int64_t q = b0 + (int64_t)k * kSliceRows;
+            tcol16[q] = (uint16_t)(tcol[q] - lo);
+        }
+    if (lane == 0) tbase[sl] = compact ? (hi < 0 ? 0 : lo) : -1;
+}
+
+// One explicit step, c_out = T c_in (theta < 1: the shortened last step of a
+// final-time run, c_in + theta (T c_in - c_in)).  Lane l of slice sl handles
+// the row named by meta[sl*64 + l] and stops after that row's own entries.
+__global__ __launch_bounds__(256) void transport_step_kernel(UpwindOp T, const double *__restrict__ c_in,
                                                              double *__restrict__ c_out, double theta) {
     const int32_t t = xcd_block() * blockDim.x + threadIdx.x;
     const int32_t sl = t / kSliceRows, lane = t % kSliceRows;
-    if ((int64_t)sl * kSliceRows >= nrow) return;
-    const uint16_t m = meta[t];
+    if ((int64_t)sl * kSliceRows >= T.nrow) return;
+    const uint16_t m = T.meta[t];
     const int32_t i = sl * kSliceRows + (m >> 8);
-    if (i >= nrow) return;
-    const int64_t b0 = slice_ptr[sl], b1 = b0 + (int64_t)(m & 255) * kSliceRows;
+    if (i >= T.nrow) return;
+    const int64_t b0 = T.slice_ptr[sl], b1 = b0 + (int64_t)(m & 255) * kSliceRows;
+    const int32_t cb = T.tbase[sl];
     const double ci = c_in[i];
-    double a0 = tdiag[i] * ci, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double a0 = T.tdiag[i] * ci, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int64_t q = b0 + lane;
-    for (; q + 3 * kSliceRows < b1; q += 4 * kSliceRows) {
-        a1 += tval[q] * c_in[tcol[q]];
-        a2 += tval[q + kSliceRows] * c_in[tcol[q + kSliceRows]];
-        a3 += tval[q + 2 * kSliceRows] * c_in[tcol[q + 2 * kSliceRows]];
-        a0 += tval[q + 3 * kSliceRows] * c_in[tcol[q + 3 * kSliceRows]];
+    if (cb >= 0) {  // uniform over the wavefront (one slice)
+        const uint16_t *__restrict__ col = T.tcol16;
+        for (; q + 3 * kSliceRows < b1; q += 4 * kSliceRows) {
+            a1 += T.tval[q] * c_in[cb + col[q]];
+            a2 += T.tval[q + kSliceRows] * c_in[cb + col[q + kSliceRows]];
+            a3 += T.tval[q + 2 * kSliceRows] * c_in[cb + col[q + 2 * kSliceRows]];
+            a0 += T.tval[q + 3 * kSliceRows] * c_in[cb + col[q + 3 * kSliceRows]];
+        }
+        for (; q < b1; q += kSliceRows) a1 += T.tval[q] * c_in[cb + col[q]];
+    } else {
+        const int32_t *__restrict__ col = T.tcol;
+        for (; q + 3 * kSliceRows < b1; q += 4 * kSliceRows) {
+            a1 += T.tval[q] * c_in[col[q]];
+            a2 += T.tval[q + kSliceRows] * c_in[col[q + kSliceRows]];
+            a3 += T.tval[q + 2 * kSliceRows] * c_in[col[q + 2 * kSliceRows]];
+            a0 += T.tval[q + 3 * kSliceRows] * c_in[col[q + 3 * kSliceRows]];
+        }
+        for (; q < b1; q += kSliceRows) a1 += T.tval[q] * c_in[col[q]];
     }
-    for (; q < b1; q += kSliceRows) a1 += tval[q] * c_in[tcol[q]];
     const double acc = (a0 + a1) + (a2 + a3);
     c_out[i] = (theta == 1.0) ? acc : ci + theta * (acc - ci);
 }
@@ -562,12 +609,16 @@ void launch_upwind_fill(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const
                        tcol, tval, tdiag);
     VAG_HIP(hipGetLastError());
 }
-void launch_transport_step(hipStream_t s, int32_t nrow, const int64_t *slice_ptr, const uint16_t *meta,
-                           const int32_t *tcol, const double *tval, const double *tdiag, const double *c_in,
-                           double *c_out, double theta) {
-    const int64_t slots = (int64_t)((nrow + kSliceRows - 1) / kSliceRows) * kSliceRows;
-    hipLaunchKernelGGL(transport_step_kernel, dim3(nb(slots, 256)), dim3(256), 0, s, nrow, slice_ptr, meta, tcol,
-                       tval, tdiag, c_in, c_out, theta);
+void launch_upwind_pack(hipStream_t s, const UpwindOp &T, uint16_t *tcol16, int32_t *tbase) {
+    const int64_t nslice = (T.nrow + kSliceRows - 1) / kSliceRows;
+    if (nslice <= 0) return;
+    hipLaunchKernelGGL(upwind_pack_kernel, dim3((unsigned)nslice), dim3(kSliceRows), 0, s, T.nrow, T.slice_ptr, T.meta,
+                       T.tcol, tcol16, tbase);
+    VAG_HIP(hipGetLastError());
+}
+void launch_transport_step(hipStream_t s, const UpwindOp &T, const double *c_in, double *c_out, double theta) {
+    const int64_t slots = (int64_t)((T.nrow + kSliceRows - 1) / kSliceRows) * kSliceRows;
+    hipLaunchKernelGGL(transport_step_kernel, dim3(nb(slots, 256)), dim3(256), 0, s, T, c_in, c_out, theta);
     VAG_HIP(hipGetLastError());
 }
 void launch_set_dirichlet(hipStream_t s, int32_t nn, int32_t offset, const uint8_t *dirichlet, const double *c_bar,

@@ -163,7 +163,8 @@ struct vag_handle {
     // results
     DBuf<double> u_node, u_cell, u_frac, F_cell, F_cell_frac, F_frac, phi_cell, phi_frac, phi_node;
     // transport
-    DBuf<int32_t> slice_width, slice_nnz, tcol;
+    DBuf<int32_t> slice_width, slice_nnz, tcol, tbase;
+    DBuf<uint16_t> tcol16;
     DBuf<uint16_t> tmeta;
     DBuf<int64_t> slice_ptr;
     DBuf<double> tval, tdiag, cbuf0, cbuf1, dt4;
@@ -188,6 +189,9 @@ struct vag_handle {
     hipEvent_t ev[8] = {};
 
     Sell<double> Asell() const { return Sell<double>{S.nunk, sell_ptr.p, sell_col.p, A.p}; }
+    UpwindOp upwind() const {
+        return UpwindOp{S.nc + S.nf + S.nn, slice_ptr.p, tmeta.p, tcol.p, tcol16.p, tbase.p, tval.p, tdiag.p};
+    }
     double *c_cur() { return cur ? cbuf1.p : cbuf0.p; }
     double *c_next() { return cur ? cbuf0.p : cbuf1.p; }
 
@@ -986,12 +990,15 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
         if (!(dt < INFINITY)) throw Error(VAG_ERR_ARG, "no control volume has an outflow: CFL bound is infinite");
         if ((size_t)total > h->tcol.n) {
             h->tcol.alloc((size_t)total + (size_t)total / 8, h->tr);
+            h->tcol16.alloc((size_t)total + (size_t)total / 8, h->tr);
             h->tval.alloc((size_t)total + (size_t)total / 8, h->tr);
         }
+        ensure(h->tbase, (size_t)std::max<int64_t>(nslice, 1), h->tr);
         launch_upwind_fill(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p,
                            h->frac_nodes.p, h->dirichlet.p, h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p,
                            h->node_frac.p, h->F_cell.p, h->F_cell_frac.p, h->F_frac.p, h->phi_cell.p, h->phi_frac.p,
                            h->phi_node.p, h->dt4.p, h->slice_ptr.p, h->tmeta.p, h->tcol.p, h->tval.p, h->tdiag.p);
+        launch_upwind_pack(s, h->upwind(), h->tcol16.p, h->tbase.p);
         // initial state
         if (c0_cell || c0_frac || c0_node) {
             if (!c0_cell || !c0_node || (S.nf && !c0_frac))
@@ -1019,8 +1026,7 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
         VAG_HIP(hipEventRecord(h->ev[6], s));
         for (int64_t k = 0; k < N; ++k) {
             const double th = (k == N - 1) ? theta_last : 1.0;
-            launch_transport_step(s, (int32_t)nrow, h->slice_ptr.p, h->tmeta.p, h->tcol.p, h->tval.p, h->tdiag.p, h->c_cur(),
-                                  h->c_next(), th);
+            launch_transport_step(s, h->upwind(), h->c_cur(), h->c_next(), th);
             h->cur ^= 1;
         }
         VAG_HIP(hipEventRecord(h->ev[7], s));
@@ -1155,8 +1161,7 @@ vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms)
                                                         PcgParts{h->parts.p, pcg_grid(S.nunk)}, h->pcg.p + 1);
                     break;
                 case VAG_KERNEL_TRANSPORT_STEP:  // reads the current state, writes the spare buffer
-                    launch_transport_step(s, (int32_t)nrow, h->slice_ptr.p, h->tmeta.p, h->tcol.p, h->tval.p, h->tdiag.p,
-                                          h->c_cur(), h->c_next(), 1.0);
+                    launch_transport_step(s, h->upwind(), h->c_cur(), h->c_next(), 1.0);
                     break;
                 case VAG_KERNEL_LOCAL:
                     launch_local(s, S.nc, h->xyz.p, h->hex8.p, h->perm.p, h->mu, h->fmask.p, h->cell_frac.p,

@@ -322,11 +322,21 @@ void launch_upwind_fill(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const
                         const double *phi_cell, const double *phi_frac, const double *phi_node,
                         const double *dt, const int64_t *slice_ptr, const uint16_t *meta, int32_t *tcol,
                         double *tval, double *tdiag);
-// meta[slot] = (lane of the row in its slice) << 8 | entry count: the rows of
-// a slice are stored longest first
-void launch_transport_step(hipStream_t s, int32_t nrow, const int64_t *slice_ptr, const uint16_t *meta,
-                           const int32_t *tcol, const double *tval, const double *tdiag, const double *c_in,
-                           double *c_out, double theta);
+// The upwind operator in sliced ELL: meta[slot] = (lane of the row in its
+// slice) << 8 | entry count (the rows of a slice are stored longest first);
+// 32-bit columns, and 16-bit offsets from tbase[slice] where tbase >= 0.
+struct UpwindOp {
+    int32_t nrow;
+    const int64_t *slice_ptr;
+    const uint16_t *meta;
+    const int32_t *tcol;
+    const uint16_t *tcol16;
+    const int32_t *tbase;
+    const double *tval, *tdiag;
+};
+// tcol16 and tbase from tcol (after launch_upwind_fill)
+void launch_upwind_pack(hipStream_t s, const UpwindOp &T, uint16_t *tcol16, int32_t *tbase);
+void launch_transport_step(hipStream_t s, const UpwindOp &T, const double *c_in, double *c_out, double theta);
 void launch_set_dirichlet(hipStream_t s, int32_t nn, int32_t offset, const uint8_t *dirichlet,
                           const double *c_bar, double *c);
 
