@@ -203,6 +203,7 @@ def main():
     ap.add_argument("--keep-faces", action="store_true", help="fracture faces stay unknowns (no group elimination)")
     ap.add_argument("--amg-sweeps", type=int, default=0, help="l1-Jacobi sweeps on the coarse levels (0: default)")
     ap.add_argument("--amg-hops", type=int, default=0, help="aggregate radius: 2 (default) or 1")
+    ap.add_argument("--amg-kcycle", type=int, default=-1, help="coarse levels with K-cycles (-1: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=int(os.environ.get("VAG_BENCH_SERVING_JOBS", "256")),
                     help="config-4 serving stream of this many jobs after the timed steps (0: skip)")
@@ -248,6 +249,8 @@ def main():
         opts["amg_sweeps"] = args.amg_sweeps
     if args.amg_hops > 0:
         opts["amg_aggregate_hops"] = args.amg_hops
+    if args.amg_kcycle >= 0:
+        opts["amg_kcycle"] = args.amg_kcycle
     t0 = time.perf_counter()
     h = vag.Handle(prob, **opts)
     torch.cuda.synchronize()

@@ -139,7 +139,11 @@ typedef struct {
     int amg_aggregate_hops; /* radius of the aggregates: roots form a distance-2 (2, the
                                default) or distance-1 (1: smaller aggregates, more levels)
                                independent set of the strength graph; 0 = default */
-    int reserved[6];
+    int amg_kcycle;         /* coarse levels 1..amg_kcycle (not the coarsest) take a K-cycle:
+                               two flexible CG steps preconditioned by the V-cycle below, the
+                               outer CG then in its flexible form (CG only; 0: V-cycles;
+                               default 2) */
+    int reserved[5];
 } vag_options;
 
 typedef struct {

@@ -50,9 +50,24 @@ void amg_launch_restrict(hipStream_t s, int32_t nc, const int32_t *mptr, const i
 template <class V, class X>
 void amg_launch_resid(hipStream_t s, Sell<V> A, const X *b, const X *x, X *r, const PcgState *st);
 // y = x + P e, then out = y + M^-1 (b - A y); with rz, partials of b . out
+// (and with zq, of qv . out)
 template <class V, class X>
 void amg_launch_post(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, const int32_t *agg,
-                     const X *e, X *y, X *out, double *rz, const PcgState *st);
+                     const X *e, X *y, X *out, double *rz, const PcgState *st, double *zq = nullptr,
+                     const X *qv = nullptr);
+// K-cycle kernels (see amg.hip); parts: 5 * kc_grid(n) doubles
+int kc_grid(int32_t n);
+template <class V, class X>
+void amg_launch_kc_av(hipStream_t s, Sell<V> A, const X *c, const X *b, X *v, double *parts, const PcgState *st);
+template <class X>
+void amg_launch_kc_rt(hipStream_t s, int32_t n, const X *b, const X *v, const X *dinv, const double *parts, X *rt,
+                      X *xa, const PcgState *st);
+template <class V, class X>
+void amg_launch_kc_aw(hipStream_t s, Sell<V> A, const X *d, const X *v, const X *rt, X *w, double *parts,
+                      const PcgState *st);
+template <class X>
+void amg_launch_kc_combine(hipStream_t s, int32_t n, const X *c, const X *d, const double *parts, X *e,
+                           const PcgState *st);
 // the same with x = D^-1 b and y formed on the fly (one kernel)
 template <class V, class X>
 void amg_launch_post_fused(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const int32_t *agg, const X *e,
@@ -89,6 +104,7 @@ struct AmgLevel {
     DBuf<double> b, xa, xb, r;      // cycle vectors
     DBuf<float> val32, dinv32, b32, xa32, xb32, r32;
     DBuf<double> dg32;  // FP64 diagonal of the FP32 copy (row sums kept)
+    DBuf<double> kc_c, kc_v, kc_rt, kc_d, kc_w, kc_parts;  // K-cycle work of this level
     Sell<float> A32;
 };
 
@@ -101,6 +117,7 @@ struct AmgOptions {
     int coarse_sweeps = 4;  // sweeps of the coarsest level when it is not inverted
     int sweeps = 1;         // sweeps before and after the correction on levels >= 1
     int hops = 2;           // roots: distance-2 (2) or distance-1 (1) independent set
+    int kcycle = 0;         // coarse levels 1..kcycle take the K-cycle (when not the coarsest)
 };
 
 class Amg {
@@ -122,12 +139,16 @@ class Amg {
     // the caller has already written D^-1 r into L[0]->xa (the first
     // smoothing iterate); with rz, the last sweep also writes the block
     // partials of r . z there.
+    // With zq (and qv), the last sweep also writes the partials of qv . z.
+    // K-cycle levels make the preconditioner nonlinear (flexible CG).
     void apply(hipStream_t s, const double *r, double *z, const PcgState *st, bool x_ready = false,
-               double *rz = nullptr);
+               double *rz = nullptr, double *zq = nullptr, const double *qv = nullptr);
     void apply32(hipStream_t s, const float *r, float *z, const PcgState *st);
     // FP32 matrices, FP64 vectors
     void apply_mixed(hipStream_t s, const double *r, double *z, const PcgState *st, bool x_ready = false,
-                     double *rz = nullptr);
+                     double *rz = nullptr, double *zq = nullptr, const double *qv = nullptr);
+    // true when applying the hierarchy runs K-cycles (a nonlinear preconditioner)
+    bool nonlinear() const { return o_.kcycle > 0 && nlev >= 3; }
     // levels at or below this many rows prolongate and smooth in one kernel
     static constexpr int32_t kFusedPostRows = kSmallRows;
 
@@ -139,8 +160,13 @@ class Amg {
     DBuf<int> counters_, mis_cnt_;
     int32_t *h_ = nullptr;  // pinned host scratch, 1024 ints
     AmgOptions o_;
+    double *zq_ = nullptr;        // flexible-CG partials of the current application
+    const double *qv_ = nullptr;
     template <class V, class X>
     void cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bool x_ready, double *rz);
+    // coarse-grid correction of level m: a V-cycle, or a K-cycle (two flexible CG steps)
+    template <class V, class X>
+    void coarse(hipStream_t s, int m, const X *b, X *e, const PcgState *st, bool x_ready);
 
   public:
     ~Amg();

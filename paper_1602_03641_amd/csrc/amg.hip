@@ -1132,21 +1132,28 @@ __global__ __launch_bounds__(kAT) void vc_prolong_kernel(int32_t n, const X *__r
 }
 // out = y + M^-1 (b - A y); with rz, also the block partials of b . out (the
 // CG scalar r.z when this is the last sweep of a V-cycle on level 0)
+// With zq also the partials of qv . out (flexible CG: the new preconditioned
+// residual against the last A p).
 template <class V, class X>
 __global__ __launch_bounds__(kRzThreads) void vc_sweep_kernel(Sell<V> A, const X *__restrict__ dinv, const X *__restrict__ b,
                                                        const X *__restrict__ y, X *__restrict__ out,
-                                                       double *__restrict__ rz, const PcgState *st) {
+                                                       double *__restrict__ rz, double *__restrict__ zq,
+                                                       const X *__restrict__ qv, const PcgState *st) {
     if (st && st->done) return;
-    double v[1] = {0.0};
+    double v[2] = {0.0, 0.0};
     GS(i, A.n) {
         const X s = sell_row_apply<V, X>(A, (int32_t)i, [&](int32_t j) { return y[j]; });
         const X o = y[i] + dinv[i] * (b[i] - s);
         out[i] = o;
         v[0] += (double)b[i] * (double)o;
+        if (zq) v[1] += (double)qv[i] * (double)o;
     }
     if (rz) {
-        block_reduce<OpSum, 1, kRzThreads>(v);
-        if (threadIdx.x == 0) rz[blockIdx.x] = v[0];
+        block_reduce<OpSum, 2, kRzThreads>(v);
+        if (threadIdx.x == 0) {
+            rz[blockIdx.x] = v[0];
+            if (zq) zq[blockIdx.x] = v[1];
+        }
     }
 }
 // prolongation and sweep in one pass (small levels): y = x + P e with
@@ -1217,6 +1224,102 @@ __global__ __launch_bounds__(kAT) void vc_small_kernel(Sell<V> A, const X *__res
 }
 static inline unsigned grid_small(int32_t n) {
     return (unsigned)std::max<int64_t>(1, ((int64_t)n * kG + kAT - 1) / kAT);
+}
+
+// ---------------------------------------------------------------------------
+// K-cycle: on a coarse level m the coarse correction is two steps of a
+// flexible CG on A_m e = b, each preconditioned by the V-cycle from level m
+// (Krylov acceleration of the coarse-grid correction, which unsmoothed
+// aggregation needs to keep its convergence independent of the level count).
+// With c = B(b), v = A c, rho = c.v, alpha1 = c.b / rho, rt = b - alpha1 v,
+// d = B(rt), w = A d, gamma = d.v, beta = d.w - gamma^2 / rho,
+// alpha2 = d.rt / beta:   e = (alpha1 - gamma alpha2 / rho) c + alpha2 d.
+// Scalars are formed by each consuming kernel from per-block partials, in a
+// fixed order.  parts: [c.v | c.b | d.w | d.v | d.rt] x G.
+// ---------------------------------------------------------------------------
+template <class X>
+__device__ inline void kc_scalars(const double *parts, int G, double &rho, double &a1, double &g, double &a2) {
+    rho = sum_parts<OpSum, kAT>(parts, G);
+    const double cb = sum_parts<OpSum, kAT>(parts + G, G);
+    a1 = rho > 0.0 ? cb / rho : 0.0;
+    g = 0.0;
+    a2 = 0.0;
+}
+// v = A c; partials c.v and c.b
+template <class V, class X>
+__global__ __launch_bounds__(kAT) void kc_av_kernel(Sell<V> A, const X *__restrict__ c, const X *__restrict__ b,
+                                                    X *__restrict__ v, double *__restrict__ parts,
+                                                    const PcgState *st) {
+    if (st && st->done) return;
+    double p[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * blockDim.x) {
+        const X vi = sell_row_apply<V, X>(A, (int32_t)i, [&](int32_t j) { return c[j]; });
+        v[i] = vi;
+        p[0] += (double)c[i] * (double)vi;
+        p[1] += (double)c[i] * (double)b[i];
+    }
+    block_reduce<OpSum, 2, kAT>(p);
+    if (threadIdx.x == 0) {
+        parts[blockIdx.x] = p[0];
+        parts[gridDim.x + blockIdx.x] = p[1];
+    }
+}
+// rt = b - alpha1 v, and the next V-cycle's first iterate xa = D^-1 rt
+template <class X>
+__global__ __launch_bounds__(kAT) void kc_rt_kernel(int32_t n, const X *__restrict__ b, const X *__restrict__ v,
+                                                    const X *__restrict__ dinv, const double *__restrict__ parts,
+                                                    X *__restrict__ rt, X *__restrict__ xa, const PcgState *st) {
+    if (st && st->done) return;
+    double rho, a1, g, a2;
+    kc_scalars<X>(parts, gridDim.x, rho, a1, g, a2);
+    const X a = (X)a1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const X r = b[i] - a * v[i];
+        rt[i] = r;
+        xa[i] = dinv[i] * r;
+    }
+}
+// w = A d; partials d.w, d.v, d.rt
+template <class V, class X>
+__global__ __launch_bounds__(kAT) void kc_aw_kernel(Sell<V> A, const X *__restrict__ d, const X *__restrict__ v,
+                                                    const X *__restrict__ rt, X *__restrict__ w,
+                                                    double *__restrict__ parts, const PcgState *st) {
+    if (st && st->done) return;
+    double p[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * blockDim.x) {
+        const X wi = sell_row_apply<V, X>(A, (int32_t)i, [&](int32_t j) { return d[j]; });
+        w[i] = wi;
+        p[0] += (double)d[i] * (double)wi;
+        p[1] += (double)d[i] * (double)v[i];
+        p[2] += (double)d[i] * (double)rt[i];
+    }
+    block_reduce<OpSum, 3, kAT>(p);
+    if (threadIdx.x == 0) {
+        const int G = gridDim.x;
+        parts[2 * G + blockIdx.x] = p[0];
+        parts[3 * G + blockIdx.x] = p[1];
+        parts[4 * G + blockIdx.x] = p[2];
+    }
+}
+// e = (alpha1 - gamma alpha2 / rho) c + alpha2 d
+template <class X>
+__global__ __launch_bounds__(kAT) void kc_combine_kernel(int32_t n, const X *__restrict__ c, const X *__restrict__ d,
+                                                         const double *__restrict__ parts, X *__restrict__ e,
+                                                         const PcgState *st) {
+    if (st && st->done) return;
+    const int G = gridDim.x;
+    double rho, a1, g, a2;
+    kc_scalars<X>(parts, G, rho, a1, g, a2);
+    if (rho > 0.0) {
+        const double dw = sum_parts<OpSum, kAT>(parts + 2 * G, G);
+        g = sum_parts<OpSum, kAT>(parts + 3 * G, G);
+        const double drt = sum_parts<OpSum, kAT>(parts + 4 * G, G);
+        const double beta = dw - g * g / rho;
+        a2 = beta > 0.0 ? drt / beta : 0.0;
+    }
+    const X ac = (X)(rho > 0.0 ? a1 - g * a2 / rho : 0.0), ad = (X)a2;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        e[i] = ac * c[i] + ad * d[i];
 }
 
 // dense coarse solve x = Ainv b: one wavefront per row, lanes along the
@@ -1368,6 +1471,38 @@ void amg_launch_dense_inverse(hipStream_t s, Sell<double> A, double *D, double *
         }
     }
 }
+int kc_grid(int32_t n) { return (int)reduce_grid(n, kAT); }
+template <class V, class X>
+void amg_launch_kc_av(hipStream_t s, Sell<V> A, const X *c, const X *b, X *v, double *parts, const PcgState *st) {
+    ALAUNCH((kc_av_kernel<V, X>), kc_grid(A.n), kAT, A, c, b, v, parts, st);
+}
+template <class X>
+void amg_launch_kc_rt(hipStream_t s, int32_t n, const X *b, const X *v, const X *dinv, const double *parts, X *rt,
+                      X *xa, const PcgState *st) {
+    ALAUNCH(kc_rt_kernel<X>, kc_grid(n), kAT, n, b, v, dinv, parts, rt, xa, st);
+}
+template <class V, class X>
+void amg_launch_kc_aw(hipStream_t s, Sell<V> A, const X *d, const X *v, const X *rt, X *w, double *parts,
+                      const PcgState *st) {
+    ALAUNCH((kc_aw_kernel<V, X>), kc_grid(A.n), kAT, A, d, v, rt, w, parts, st);
+}
+template <class X>
+void amg_launch_kc_combine(hipStream_t s, int32_t n, const X *c, const X *d, const double *parts, X *e,
+                           const PcgState *st) {
+    ALAUNCH(kc_combine_kernel<X>, kc_grid(n), kAT, n, c, d, parts, e, st);
+}
+template void amg_launch_kc_av<double, double>(hipStream_t, Sell<double>, const double *, const double *, double *,
+                                               double *, const PcgState *);
+template void amg_launch_kc_av<float, double>(hipStream_t, Sell<float>, const double *, const double *, double *,
+                                              double *, const PcgState *);
+template void amg_launch_kc_aw<double, double>(hipStream_t, Sell<double>, const double *, const double *,
+                                               const double *, double *, double *, const PcgState *);
+template void amg_launch_kc_aw<float, double>(hipStream_t, Sell<float>, const double *, const double *,
+                                              const double *, double *, double *, const PcgState *);
+template void amg_launch_kc_rt<double>(hipStream_t, int32_t, const double *, const double *, const double *,
+                                       const double *, double *, double *, const PcgState *);
+template void amg_launch_kc_combine<double>(hipStream_t, int32_t, const double *, const double *, const double *,
+                                            double *, const PcgState *);
 template <class V, class X>
 void amg_launch_pre(hipStream_t s, Sell<V> A, const X *dinv, const X *b, X *x, X *r, const PcgState *st) {
     ALAUNCH(vc_scale_kernel<X>, gridv(A.n), kAT, A.n, dinv, b, x, st);
@@ -1401,13 +1536,13 @@ void amg_launch_post_x(hipStream_t s, Sell<V> A, const X *dinv, const X *b, cons
 }
 template <class V, class X>
 void amg_launch_post(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const X *x, const int32_t *agg, const X *e,
-                     X *y, X *out, double *rz, const PcgState *st) {
+                     X *y, X *out, double *rz, const PcgState *st, double *zq, const X *qv) {
     ALAUNCH(vc_prolong_kernel<X>, gridv(A.n), kAT, A.n, x, agg, e, y, st);
     // with rz the partials must match the Krylov kernels' grid and block size
     if (rz)
-        ALAUNCH((vc_sweep_kernel<V, X>), reduce_grid(A.n, kRzThreads), kRzThreads, A, dinv, b, y, out, rz, st);
+        ALAUNCH((vc_sweep_kernel<V, X>), reduce_grid(A.n, kRzThreads), kRzThreads, A, dinv, b, y, out, rz, zq, qv, st);
     else
-        ALAUNCH((vc_sweep_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, y, out, nullptr, st);
+        ALAUNCH((vc_sweep_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, y, out, nullptr, nullptr, nullptr, st);
 }
 template <class X>
 void amg_launch_dense(hipStream_t s, int32_t n, const X *Ainv, const X *b, X *x, const PcgState *st) {
@@ -1419,7 +1554,7 @@ void amg_launch_sweep(hipStream_t s, Sell<V> A, const X *dinv, const X *b, const
         ALAUNCH((vc_small_kernel<1, V, X>), grid_small(A.n), kAT, A, dinv, b, x, (const int32_t *)nullptr,
                 (const X *)nullptr, out, st);
     else
-        ALAUNCH((vc_sweep_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, x, out, nullptr, st);
+        ALAUNCH((vc_sweep_kernel<V, X>), gridv(A.n), kAT, A, dinv, b, x, out, nullptr, nullptr, nullptr, st);
 }
 void launch_to_float(hipStream_t s, int64_t n, const double *a, float *b) {
     if (n > 0) ALAUNCH(to_float_kernel, gridv(n), kAT, n, a, b);
@@ -1435,7 +1570,7 @@ void launch_to_double(hipStream_t s, int64_t n, const float *a, double *b) {
     template void amg_launch_pre<V, X>(hipStream_t, Sell<V>, const X *, const X *, X *, X *, const PcgState *);    \
     template void amg_launch_resid<V, X>(hipStream_t, Sell<V>, const X *, const X *, X *, const PcgState *);       \
     template void amg_launch_post<V, X>(hipStream_t, Sell<V>, const X *, const X *, const X *, const int32_t *,    \
-                                        const X *, X *, X *, double *, const PcgState *);                          \
+                                        const X *, X *, X *, double *, const PcgState *, double *, const X *);     \
     template void amg_launch_post_fused<V, X>(hipStream_t, Sell<V>, const X *, const X *, const int32_t *,         \
                                               const X *, X *, const PcgState *);                                   \
     template void amg_launch_post_x<V, X>(hipStream_t, Sell<V>, const X *, const X *, const X *, const int32_t *,  \

@@ -105,6 +105,12 @@ void Amg::setup(hipStream_t s, Tracker &tr, Sell<double> A0, int64_t stored0, co
     } else {
         for (auto *v : {&L[0]->xa, &L[0]->r}) ensure(*v, n0, tr);
     }
+    // K-cycle work on levels 1 .. kcycle that are not the coarsest
+    for (int m = 1; m < nlev - 1 && m <= o.kcycle; ++m) {
+        AmgLevel &kv = *L[m];
+        for (auto *v : {&kv.kc_c, &kv.kc_v, &kv.kc_rt, &kv.kc_d, &kv.kc_w}) ensure(*v, kv.n, tr);
+        ensure(kv.kc_parts, (size_t)5 * kc_grid(kv.n), tr);
+    }
     if (cl.n <= o.dense_max && cl.n > 0) {
         ensure(Ainv, (size_t)cl.n * cl.n, tr);
         ensure(gj_work, (size_t)128 * cl.n, tr);
@@ -192,11 +198,18 @@ void Amg::cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bo
             amg_launch_pre<V, X>(s, A, dinv, b, xa, r, st);
         amg_launch_restrict<X>(s, cv.n, lv.mptr.p, lv.mrows.p, r, bc, coarse_x ? dinv_c : nullptr,
                                coarse_x ? xc : nullptr, st);
-        cycle<V, X>(s, l + 1, bc, ec, st, coarse_x, nullptr);
-        if (lv.n <= kFusedPostRows && !rz)
+        coarse<V, X>(s, l + 1, bc, ec, st, coarse_x);
+        if (lv.n <= kFusedPostRows && !rz) {
             amg_launch_post_fused<V, X>(s, A, dinv, b, lv.agg.p, ec, out, st);
-        else
-            amg_launch_post<V, X>(s, A, dinv, b, xa, lv.agg.p, ec, r, out, rz, st);  // r reused for y
+        } else {
+            double *zq = nullptr;
+            const X *qv = nullptr;
+            if constexpr (sizeof(X) == 8) {
+                zq = rz ? zq_ : nullptr;
+                qv = zq ? qv_ : nullptr;
+            }
+            amg_launch_post<V, X>(s, A, dinv, b, xa, lv.agg.p, ec, r, out, rz, st, zq, qv);  // r reused for y
+        }
         return;
     }
     // nu pre-sweeps ping-ponging between xa and r, residual into the other
@@ -209,7 +222,7 @@ void Amg::cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bo
     amg_launch_resid<V, X>(s, A, b, xs, tmp, st);
     amg_launch_restrict<X>(s, cv.n, lv.mptr.p, lv.mrows.p, tmp, bc, coarse_x ? dinv_c : nullptr,
                            coarse_x ? xc : nullptr, st);
-    cycle<V, X>(s, l + 1, bc, ec, st, coarse_x, nullptr);
+    coarse<V, X>(s, l + 1, bc, ec, st, coarse_x);
     // the first post-sweep from y = x + P e (small levels: one kernel into tmp;
     // otherwise y into tmp and the sweep into xs), then nu - 1 more sweeps,
     // the last one into out (levels >= 1 only: no r.z partials)
@@ -226,16 +239,46 @@ void Amg::cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bo
     }
 }
 
-void Amg::apply(hipStream_t s, const double *r, double *z, const PcgState *st, bool x_ready, double *rz) {
+template <class V, class X>
+void Amg::coarse(hipStream_t s, int m, const X *b, X *e, const PcgState *st, bool x_ready) {
+    if constexpr (sizeof(X) == 8) {
+        if (m <= o_.kcycle && m < nlev - 1 && x_ready) {
+            // two flexible CG steps on A_m e = b, each preconditioned by a V-cycle from level m
+            AmgLevel &lv = *L[m];
+            Sell<V> A;
+            if constexpr (sizeof(V) == 4) A = lv.A32; else A = lv.A;
+            cycle<V, X>(s, m, b, lv.kc_c.p, st, true, nullptr);                  // c = B b (xa = D^-1 b given)
+            amg_launch_kc_av<V, X>(s, A, lv.kc_c.p, b, lv.kc_v.p, lv.kc_parts.p, st);
+            amg_launch_kc_rt<X>(s, lv.n, b, lv.kc_v.p, lv.dinv.p, lv.kc_parts.p, lv.kc_rt.p, lv.xa.p, st);
+            cycle<V, X>(s, m, lv.kc_rt.p, lv.kc_d.p, st, true, nullptr);          // d = B rt
+            amg_launch_kc_aw<V, X>(s, A, lv.kc_d.p, lv.kc_v.p, lv.kc_rt.p, lv.kc_w.p, lv.kc_parts.p, st);
+            amg_launch_kc_combine<X>(s, lv.n, lv.kc_c.p, lv.kc_d.p, lv.kc_parts.p, e, st);
+            return;
+        }
+    }
+    cycle<V, X>(s, m, b, e, st, x_ready, nullptr);
+}
+
+void Amg::apply(hipStream_t s, const double *r, double *z, const PcgState *st, bool x_ready, double *rz, double *zq,
+                const double *qv) {
+    zq_ = zq;
+    qv_ = qv;
     cycle<double, double>(s, 0, r, z, st, x_ready, rz);
+    zq_ = nullptr;
+    qv_ = nullptr;
 }
 
 void Amg::apply32(hipStream_t s, const float *r, float *z, const PcgState *st) {
     cycle<float, float>(s, 0, r, z, st, false, nullptr);
 }
 
-void Amg::apply_mixed(hipStream_t s, const double *r, double *z, const PcgState *st, bool x_ready, double *rz) {
+void Amg::apply_mixed(hipStream_t s, const double *r, double *z, const PcgState *st, bool x_ready, double *rz,
+                      double *zq, const double *qv) {
+    zq_ = zq;
+    qv_ = qv;
     cycle<float, double>(s, 0, r, z, st, x_ready, rz);
+    zq_ = nullptr;
+    qv_ = nullptr;
 }
 
 }  // namespace vag

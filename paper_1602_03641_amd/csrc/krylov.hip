@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kThreads) void pcg_start_kernel(PcgParts P, PcgStat
 template <class T>
 __global__ __launch_bounds__(kThreads) void pcg_direction_kernel(int32_t n, int k, int k0, const T *__restrict__ z,
                                                                  T *__restrict__ p, PcgParts P, PcgState *st,
-                                                                 int update) {
+                                                                 int update, int flexible) {
     if (st->done) return;
     const double rr = sum_parts<OpSum, kThreads>(P.rr(k - 1), P.G);
     if (rr <= st->tol2) {
@@ -127,7 +127,12 @@ __global__ __launch_bounds__(kThreads) void pcg_direction_kernel(int32_t n, int 
         return;
     }
     double beta = 0.0;
-    if (k > k0) beta = sum_parts<OpSum, kThreads>(P.rz(k - 1), P.G) / sum_parts<OpSum, kThreads>(P.rz(k), P.G);
+    if (k > k0) {
+        if (flexible)
+            beta = -sum_parts<OpSum, kThreads>(P.zq(), P.G) / sum_parts<OpSum, kThreads>(P.pq(), P.G);
+        else
+            beta = sum_parts<OpSum, kThreads>(P.rz(k - 1), P.G) / sum_parts<OpSum, kThreads>(P.rz(k), P.G);
+    }
     if (k == k0) {
         GRID_STRIDE(i, n) p[i] = z[i];
     } else {
@@ -334,8 +339,8 @@ void launch_pcg_init_warm(hipStream_t s, Sell<double> A, int k0, const double *b
 }
 template <class T>
 void launch_pcg_direction(hipStream_t s, int32_t n, int k, int k0, const T *z, T *p, PcgParts P, PcgState *st,
-                          bool update) {
-    LAUNCH(pcg_direction_kernel<T>, P.G, n, k, k0, z, p, P, st, update ? 1 : 0);
+                          bool update, bool flexible) {
+    LAUNCH(pcg_direction_kernel<T>, P.G, n, k, k0, z, p, P, st, update ? 1 : 0, flexible ? 1 : 0);
 }
 template <class V, class T>
 void launch_pcg_spmv(hipStream_t s, Sell<V> A, const T *p, T *q, PcgParts P, const PcgState *st) {
@@ -378,7 +383,7 @@ void launch_diag_scaling(hipStream_t s, Sell<double> A, const int32_t *diag_pos,
 
 #define INST(T)                                                                                                   \
     template void launch_pcg_direction<T>(hipStream_t, int32_t, int, int, const T *, T *, PcgParts, PcgState *,   \
-                                          bool);                                                                  \
+                                          bool, bool);                                                            \
     template void launch_pcg_spmv<T, T>(hipStream_t, Sell<T>, const T *, T *, PcgParts, const PcgState *);        \
     template void launch_pcg_update_xr<T>(hipStream_t, int32_t, int, T *, T *, const T *, const T *, PcgParts,   \
                                           PcgState *, const T *, T *);                                            \

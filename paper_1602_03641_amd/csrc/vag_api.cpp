@@ -279,6 +279,7 @@ void check_options(const vag_options &o) {
         throw Error(VAG_ERR_UNSUPPORTED, "mixed precision needs the AMG preconditioner");
     if (o.precision == VAG_MIXED_IR && !(o.inner_rtol > 0 && o.inner_rtol < 1))
         throw Error(VAG_ERR_ARG, "inner_rtol must lie in (0, 1)");
+    if (o.amg_kcycle < 0 || o.amg_kcycle > 12) throw Error(VAG_ERR_ARG, "amg_kcycle must lie in [0, 12]");
     if (o.amg_aggregate_hops < 0 || o.amg_aggregate_hops > 2)
         throw Error(VAG_ERR_ARG, "amg_aggregate_hops must be 0 (default), 1 or 2");
     if (o.krylov != VAG_CG && o.krylov != VAG_GMRES && o.krylov != VAG_BICGSTAB)
@@ -293,7 +294,7 @@ void check_options(const vag_options &o) {
 
 // z = M^{-1} r for the handle's preconditioner (see Amg::apply for x_ready, rz)
 void precond_apply(vag_handle *h, const double *r, double *z, const PcgState *st, bool x_ready = false,
-                   double *rz = nullptr);
+                   double *rz = nullptr, double *zq = nullptr, const double *qv = nullptr);
 
 // device pointers of the assembly kernels
 AsmArgs asm_args(vag_handle *h) {
@@ -348,11 +349,12 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 }  // namespace
 
 namespace {
-void precond_apply(vag_handle *h, const double *r, double *z, const PcgState *st, bool x_ready, double *rz) {
+void precond_apply(vag_handle *h, const double *r, double *z, const PcgState *st, bool x_ready, double *rz,
+                   double *zq, const double *qv) {
     if (h->opt.precond == VAG_PC_AMG && h->opt.precision == VAG_MIXED)
-        h->amg.apply_mixed(h->stream, r, z, st, x_ready, rz);
+        h->amg.apply_mixed(h->stream, r, z, st, x_ready, rz, zq, qv);
     else if (h->opt.precond == VAG_PC_AMG)
-        h->amg.apply(h->stream, r, z, st, x_ready, rz);
+        h->amg.apply(h->stream, r, z, st, x_ready, rz, zq, qv);
     else
         launch_jacobi(h->stream, h->S.nunk, h->dinv.p, r, z);
 }
@@ -364,6 +366,9 @@ AmgOptions amg_options(const vag_options &o) {
     if (o.amg_max_levels > 0) a.max_levels = o.amg_max_levels;
     if (o.amg_sweeps > 0) a.sweeps = o.amg_sweeps;
     if (o.amg_aggregate_hops > 0) a.hops = o.amg_aggregate_hops;
+    // K-cycles make the preconditioner nonlinear: CG runs in its flexible form;
+    // GMRES, BiCGStab and the FP32 inner solves keep V-cycles
+    a.kcycle = (o.krylov == VAG_CG && o.precision != VAG_MIXED_IR) ? o.amg_kcycle : 0;
     return a;
 }
 
@@ -378,6 +383,7 @@ void run_pcg(vag_handle *h) {
     PcgState *st = h->pcg.p;
     const bool jacobi = h->opt.precond == VAG_PC_JACOBI;
     const bool fused = !jacobi && h->amg.nlev > 1;
+    const bool flexible = fused && h->amg.nonlinear();
     const Sell<double> A = h->Asell();
     const int max_iter = h->opt.max_iter;
     int k = 0, k0 = 0;
@@ -396,7 +402,7 @@ void run_pcg(vag_handle *h) {
         for (;;) {
             const int kend = std::min(k + h->opt.check_every, max_iter);
             for (; k < kend; ++k) {
-                launch_pcg_direction<double>(s, n, k, k0, h->z.p, h->p.p, P, st, true);
+                launch_pcg_direction<double>(s, n, k, k0, h->z.p, h->p.p, P, st, true, flexible);
                 launch_pcg_spmv<double, double>(s, A, h->p.p, h->q.p, P, st);
                 if (jacobi) {
                     launch_pcg_update(s, n, k, h->x.p, h->r.p, h->z.p, h->p.p, h->q.p, h->dinv.p, P, st);
@@ -406,7 +412,8 @@ void run_pcg(vag_handle *h) {
                         // the V-cycle's last sweep the partials of r.z
                         launch_pcg_update_xr<double>(s, n, k, h->x.p, h->r.p, h->p.p, h->q.p, P, st,
                                                      h->amg.L[0]->dinv.p, h->amg.L[0]->xa.p);
-                        precond_apply(h, h->r.p, h->z.p, st, true, P.rz(k));
+                        precond_apply(h, h->r.p, h->z.p, st, true, P.rz(k), flexible ? P.zq() : nullptr,
+                                      flexible ? h->q.p : nullptr);
                     } else {
                         launch_pcg_update_xr<double>(s, n, k, h->x.p, h->r.p, h->p.p, h->q.p, P, st);
                         precond_apply(h, h->r.p, h->z.p, st);
@@ -642,6 +649,7 @@ vag_status vag_default_options(vag_options *o) {
     o->amg_max_levels = 12;
     o->amg_theta = 0.02;
     o->amg_sweeps = 2;
+    o->amg_kcycle = 2;
     o->eliminate_frac_faces = 1;
     return VAG_OK;
 }
@@ -742,7 +750,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         h->dinv.alloc(n, h->tr);
         h->bad.alloc(1, h->tr);
         for (auto *v : {&h->x, &h->r, &h->z, &h->p, &h->q}) v->alloc(n, h->tr);
-        h->parts.alloc(5 * (size_t)kReduceBlocks, h->tr);
+        h->parts.alloc(6 * (size_t)kReduceBlocks, h->tr);
         h->rparts.alloc(4 * (size_t)kReduceBlocks, h->tr);
         h->scal.alloc(8, h->tr);
         h->pcg.alloc(2, h->tr);

@@ -176,6 +176,8 @@ struct PcgParts {
     __host__ __device__ double *pq() const { return base; }
     __host__ __device__ double *rz(int k) const { return base + (size_t)(1 + (k & 1)) * G; }
     __host__ __device__ double *rr(int k) const { return base + (size_t)(3 + (k & 1)) * G; }
+    // flexible CG: z_{k+1} . q_k (written by the preconditioner's last sweep)
+    __host__ __device__ double *zq() const { return base + (size_t)5 * G; }
 };
 
 // assembly
@@ -255,10 +257,12 @@ void launch_pcg_start(hipStream_t s, PcgParts P, PcgState *st, double rtol, int 
 // warm start at iteration k0 from the current x (see krylov.hip)
 void launch_pcg_init_warm(hipStream_t s, Sell<double> A, int k0, const double *b, const double *x, double *r,
                           const double *dinv, double *z, PcgParts P);
-// convergence test on rr(k-1); then p = z + beta p (beta = rz(k-1)/rz(k-2), 0 at k = 0)
+// convergence test on rr(k-1); then p = z + beta p (beta = rz(k-1)/rz(k-2), 0 at k = 0;
+// flexible: beta = -zq/pq, which keeps p A-orthogonal to the previous
+// direction when the preconditioner changes from one application to the next)
 template <class T>
 void launch_pcg_direction(hipStream_t s, int32_t n, int k, int k0, const T *z, T *p, PcgParts P, PcgState *st,
-                          bool update);
+                          bool update, bool flexible = false);
 // q = A p, partials of p.q
 template <class V, class T>
 void launch_pcg_spmv(hipStream_t s, Sell<V> A, const T *p, T *q, PcgParts P, const PcgState *st);

@@ -55,7 +55,8 @@ class vag_options(C.Structure):
                 ("inner_rtol", C.c_double), ("max_iter", C.c_int), ("gmres_restart", C.c_int),
                 ("check_every", C.c_int), ("cfl", C.c_double), ("amg_coarse_size", C.c_int),
                 ("amg_max_levels", C.c_int), ("amg_theta", C.c_double), ("amg_sweeps", C.c_int),
-                ("eliminate_frac_faces", C.c_int), ("amg_aggregate_hops", C.c_int), ("reserved", C.c_int * 6)]
+                ("eliminate_frac_faces", C.c_int), ("amg_aggregate_hops", C.c_int), ("amg_kcycle", C.c_int),
+                ("reserved", C.c_int * 5)]
 
 
 class vag_solve_info(C.Structure):

@@ -37,6 +37,7 @@ def test_version_and_defaults():
     assert vag.load().vag_version().startswith(b"libvag")
     o = vag.default_options()
     assert o.precision == vag.VAG_FP64 and o.rtol == 1e-8 and o.cfl == 0.9
+    assert o.amg_kcycle == 2 and o.amg_aggregate_hops == 0
 
 
 def _host_create(p, **opt):
@@ -100,3 +101,6 @@ def test_bad_indices_and_options():
     p = synth.cartesian_problem(2)
     assert _host_create(p, rtol=-1.0)[0] == vag.VAG_ERR_ARG
     assert _host_create(p, cfl=0.0)[0] == vag.VAG_ERR_ARG
+    assert _host_create(p, amg_kcycle=-1)[0] == vag.VAG_ERR_ARG
+    assert _host_create(p, amg_kcycle=13)[0] == vag.VAG_ERR_ARG
+    assert _host_create(p, amg_aggregate_hops=3)[0] == vag.VAG_ERR_ARG

@@ -593,3 +593,61 @@ def test_amg_coarse_sweeps_parity(sweeps):
     assert g["info"]["iterations"] <= base["info"]["iterations"]
     compare(p, g, o)
 
+
+
+# ---------------------------------------------------------------------------
+# K-cycles on the coarse levels (flexible outer CG)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kcycle", [1, 2, 4])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_kcycle_parity(kcycle, precision):
+    """Two flexible CG steps per visit on levels 1..kcycle (nested: level 2
+    is visited four times per outer iteration at kcycle 2): the outer
+    flexible CG still reaches the oracle's solution, in fewer iterations
+    than with V-cycles alone."""
+    from paper_1602_03641_amd import vag
+    p = synth.random_problem((18, 14, 12), 13, n_patches=9, n_steps=20)
+    pr = vag.VAG_FP64 if precision == "fp64" else vag.VAG_MIXED
+    # distance-1 aggregates and a small coarsest level: five levels or more
+    kw = dict(rtol=1e-12, max_iter=5000, precond=vag.VAG_PC_AMG, precision=pr, amg_coarse_size=20,
+              amg_aggregate_hops=1)
+    g = gpu_run(p, amg_kcycle=kcycle, **kw)
+    v = gpu_run(p, n_steps=0, amg_kcycle=0, **kw)
+    o = oracle.run(p, rtol=1e-13)
+    info = g["info"]
+    print(f"kcycle {kcycle} {precision}: {info['iterations']} iterations "
+          f"(V-cycle {v['info']['iterations']}), levels {info['amg_levels']}")
+    assert info["amg_levels"] >= min(kcycle, 3) + 2
+    assert reached(info, max(1e-12, residual_floor(p, o)))
+    assert info["iterations"] < v["info"]["iterations"]
+    compare(p, g, o)
+
+
+def test_kcycle_config2_fewer_iterations_bitwise():
+    """Benchmark workload at its tolerance: the K-cycle cuts the outer
+    iterations, and two handles give bitwise identical results."""
+    from paper_1602_03641_amd import vag
+    p = synth.config2()
+    kw = dict(rtol=1e-8, max_iter=2000, precond=vag.VAG_PC_AMG, n_steps=0)
+    v = gpu_run(p, amg_kcycle=0, **kw)["info"]
+    a = gpu_run(p, amg_kcycle=2, **kw)
+    b = gpu_run(p, amg_kcycle=2, **kw)
+    print("config2 iterations: V-cycle", v["iterations"], "K-cycle", a["info"]["iterations"])
+    assert a["info"]["status"] == 0 and a["info"]["rel_residual"] <= 1e-8
+    assert a["info"]["iterations"] < v["iterations"]
+    np.testing.assert_array_equal(a["u_node"], b["u_node"])
+    np.testing.assert_array_equal(a["F_cell"], b["F_cell"])
+
+
+def test_kcycle_ignored_where_not_cg():
+    """GMRES, BiCGStab and the FP32 inner CG of refinement keep V-cycles: the
+    option changes nothing there."""
+    from paper_1602_03641_amd import vag
+    p = synth.random_problem((12, 9, 8), 14, n_patches=5, n_steps=0)
+    for kw in (dict(krylov=vag.VAG_GMRES), dict(krylov=vag.VAG_BICGSTAB),
+               dict(precision=vag.VAG_MIXED_IR, inner_rtol=1e-3)):
+        kw.update(rtol=1e-10, max_iter=5000, precond=vag.VAG_PC_AMG, amg_coarse_size=30)
+        a = gpu_run(p, amg_kcycle=0, **kw)
+        b = gpu_run(p, amg_kcycle=3, **kw)
+        assert a["info"]["iterations"] == b["info"]["iterations"]
+        np.testing.assert_array_equal(a["u_node"], b["u_node"])
