@@ -25,29 +25,46 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(h, sinfo, tinfo, levels=None, precision="fp64", sweeps=2):
+def algorithmic_bytes(h, sinfo, tinfo, levels=None, precision="fp64", sweeps=2, kcycle=0):
     n, nnz = sinfo["n_unknowns"], sinfo["nnz"]
     spmv = 12 * nnz + 4 * (n + 1) + 16 * n                       # CSR FP64: val+col, row_ptr, x, y
     step = 12 * tinfo["t_nnz"] + 24 * tinfo["n_rows"]            # upwind sweep: entries, diag, c in/out
     out = dict(spmv=spmv, transport_step=step)
     if levels:
-        # one V-cycle: two matrix passes on the finest level (residual,
-        # smoothing sweep) and 2 * sweeps on the coarser ones (sweeps - 1
-        # pre-sweeps after the first iterate, residual, sweeps post-sweeps),
-        # about 13 vector passes plus the aggregate maps, the coarse vector;
-        # the coarsest level is a dense product
+        # one preconditioner application: on each visit of a level, two matrix
+        # passes on the finest (residual, smoothing sweep) and 2 * sweeps on the
+        # coarser ones (sweeps - 1 pre-sweeps after the first iterate, residual,
+        # sweeps post-sweeps), about 13 vector passes plus the aggregate maps,
+        # the coarse vector; the coarsest level is a dense product.  A K-cycle
+        # on level m (1 <= m <= kcycle, not the coarsest) visits it twice per
+        # visit of level m - 1 and adds two products with A_m and about 15
+        # vector passes.
         v = 4 if precision in ("mixed", "mixed_ir") else 8      # matrix value bytes
         w = 4 if precision == "mixed_ir" else 8                  # vector value bytes
-        b = 0
+        nlev = len(levels)
+        visits, b = 1, 0
         for i, (rows, nz, _) in enumerate(levels[:-1]):
+            dg = 8 * rows if v == 4 else 0  # FP32 levels keep their diagonal in FP64
+            if 1 <= i <= kcycle:
+                b += visits * (2 * ((v + 4) * nz + dg) + 15 * rows * w)
+                visits *= 2
             nc = levels[i + 1][0]
             passes = 2 if i == 0 else 2 * max(1, sweeps)
-            dg = 8 * rows if v == 4 else 0  # FP32 levels keep their diagonal in FP64
-            b += passes * ((v + 4) * nz + dg) + 13 * rows * w + 8 * rows + nc * w
+            b += visits * (passes * ((v + 4) * nz + dg) + 13 * rows * w + 8 * rows + nc * w)
         rows = levels[-1][0]
-        b += rows * rows * w + 2 * rows * w
+        b += visits * (rows * rows * w + 2 * rows * w)
         out["vcycle"] = b
+        out["level_visits"] = visits
     return out
+
+
+def kcycle_levels(vag, opts, args, levels):
+    """Coarse levels that run K-cycles: 1..amg_kcycle below the coarsest, with
+    CG outside and no FP32 inner solve (the library's rule)."""
+    if not levels or args.krylov != "cg" or args.precision == "mixed_ir":
+        return 0
+    k = opts.get("amg_kcycle", vag.default_options().amg_kcycle)
+    return max(0, min(k, len(levels) - 2))
 
 
 def cpu_baseline(prob, budget_s=30.0):
@@ -277,7 +294,8 @@ def main():
 
     # roofline of the dominant kernel: per-launch time from HIP events on the handle's stream
     levels = h.amg_levels() if args.precond == "amg" else None
-    ab = algorithmic_bytes(h, sinfo, tinfo, levels, args.precision, args.amg_sweeps if args.amg_sweeps > 0 else 2)
+    ab = algorithmic_bytes(h, sinfo, tinfo, levels, args.precision, args.amg_sweeps if args.amg_sweeps > 0 else 2,
+                           kcycle_levels(vag, opts, args, levels))
     ms_spmv = h.benchmark_kernel(vag.VAG_KERNEL_SPMV, 100)
     ms_step = h.benchmark_kernel(vag.VAG_KERNEL_TRANSPORT_STEP, 100)
     ms_prec = h.benchmark_kernel(vag.VAG_KERNEL_PRECOND, 50)
@@ -321,7 +339,9 @@ def main():
         torch.cuda.synchronize()
         el2 = time.perf_counter() - t1
         ms_prec2 = h2.benchmark_kernel(vag.VAG_KERNEL_PRECOND, 50)
-        ab2 = algorithmic_bytes(h2, s2, tinfo, h2.amg_levels(), alt, args.amg_sweeps if args.amg_sweeps > 0 else 2)
+        lv2 = h2.amg_levels()
+        ab2 = algorithmic_bytes(h2, s2, tinfo, lv2, alt, args.amg_sweeps if args.amg_sweeps > 0 else 2,
+                                kcycle_levels(vag, opts, args, lv2))
         other = {"precision": alt, "value": round(args.steps / el2, 4), "iterations": s2["iterations"],
                  "rel_residual": s2["rel_residual"], "ms_solve": round(s2["ms_solve"], 3),
                  "vcycle_GBs": round(ab2["vcycle"] / (ms_prec2 * 1e-3) / 1e9, 1),
@@ -353,6 +373,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": describe(args, prob),
                    "precond": args.precond, "precision": args.precision, "krylov": args.krylov,
+                   "amg_kcycle_levels": kcycle_levels(vag, opts, args, levels),
                    "fracture_faces": "kept" if args.keep_faces else "eliminated",
                    "n_unknowns": sinfo["n_unknowns"], "nnz": sinfo["nnz"], "n_frac": prob.n_frac},
         "iterations": sinfo["iterations"], "rel_residual": sinfo["rel_residual"],
