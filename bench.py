@@ -209,7 +209,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precond", choices=["jacobi", "amg"], default=os.environ.get("VAG_BENCH_PRECOND", "amg"))
+    ap.add_argument("--precond", choices=["jacobi", "amg", "bjilu0"], default=os.environ.get("VAG_BENCH_PRECOND", "amg"))
     ap.add_argument("--workload", choices=["config2", "config3", "config5"], default="config2",
                     help="config2: 64^3, 4 clipped fractures (the headline); config3: jittered anisotropic 128^3, "
                          "40 patches, FP32-AMG GMRES with FP64 refinement; config5: 192^3, 200 patches at 1e6, "
@@ -220,6 +220,7 @@ def main():
     ap.add_argument("--keep-faces", action="store_true", help="fracture faces stay unknowns (no group elimination)")
     ap.add_argument("--amg-sweeps", type=int, default=0, help="l1-Jacobi sweeps on the coarse levels (0: default)")
     ap.add_argument("--amg-hops", type=int, default=0, help="aggregate radius: 2 (default) or 1")
+    ap.add_argument("--ilu-block-rows", type=int, default=0, help="block-Jacobi ILU(0) block size (0: default)")
     ap.add_argument("--amg-kcycle", type=int, default=-1, help="coarse levels with K-cycles (-1: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=int(os.environ.get("VAG_BENCH_SERVING_JOBS", "256")),
@@ -252,13 +253,13 @@ def main():
     defaults = {"config2": (64, "fp64", "cg"), "config3": (128, "mixed", "cg"), "config5": (192, "mixed", "cg")}
     n_def, prec_def, kry_def = defaults[args.workload]
     args.n = args.n or n_def
-    args.precision = args.precision or prec_def
-    args.krylov = args.krylov or kry_def
+    args.precision = args.precision or (prec_def if args.precond == "amg" else "fp64")
+    args.krylov = args.krylov or ("bicgstab" if args.precond == "bjilu0" else kry_def)
     log(f"generating {args.workload} n={args.n}")
     prob = getattr(synth, args.workload)(n=args.n)
     log(f"{len(prob.hex8)} cells, {prob.n_frac} fracture faces; creating the handle")
     opts = dict(rtol=prob.rtol, cfl=prob.cfl, max_iter=50000, inner_rtol=1e-2, gmres_restart=100,
-                precond=vag.VAG_PC_AMG if args.precond == "amg" else vag.VAG_PC_JACOBI,
+                precond={"amg": vag.VAG_PC_AMG, "jacobi": vag.VAG_PC_JACOBI, "bjilu0": vag.VAG_PC_BJILU0}[args.precond],
                 precision={"fp64": vag.VAG_FP64, "mixed": vag.VAG_MIXED, "mixed_ir": vag.VAG_MIXED_IR}[args.precision],
                 krylov={"cg": vag.VAG_CG, "gmres": vag.VAG_GMRES, "bicgstab": vag.VAG_BICGSTAB}[args.krylov],
                 eliminate_frac_faces=0 if args.keep_faces else 1)
@@ -268,6 +269,8 @@ def main():
         opts["amg_aggregate_hops"] = args.amg_hops
     if args.amg_kcycle >= 0:
         opts["amg_kcycle"] = args.amg_kcycle
+    if args.ilu_block_rows > 0:
+        opts["ilu_block_rows"] = args.ilu_block_rows
     t0 = time.perf_counter()
     h = vag.Handle(prob, **opts)
     torch.cuda.synchronize()

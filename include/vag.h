@@ -68,7 +68,12 @@ typedef enum { VAG_FP64 = 0, VAG_MIXED = 1, VAG_MIXED_IR = 2 } vag_precision;
  * VAG_BICGSTAB (right-preconditioned BiCGStab, FP64 vectors; not with
  * VAG_MIXED_IR). */
 typedef enum { VAG_CG = 0, VAG_GMRES = 1, VAG_BICGSTAB = 2 } vag_krylov;
-typedef enum { VAG_PC_JACOBI = 0, VAG_PC_AMG = 1 } vag_precond;
+/* Preconditioners (§5.3 compares algebraic multigrid and block Jacobi
+ * ILU(0)): VAG_PC_JACOBI (diagonal), VAG_PC_AMG (aggregation AMG),
+ * VAG_PC_BJILU0 (block Jacobi with an ILU(0) factor per block of
+ * ilu_block_rows consecutive unknowns of the natural order, eliminated in that
+ * order; not symmetric, so GMRES or BiCGStab only, FP64 only). */
+typedef enum { VAG_PC_JACOBI = 0, VAG_PC_AMG = 1, VAG_PC_BJILU0 = 2 } vag_precond;
 
 /*
  * Generalised polyhedral mesh restricted to hexahedra (§3.1).  Each cell lists
@@ -143,7 +148,9 @@ typedef struct {
                                two flexible CG steps preconditioned by the V-cycle below, the
                                outer CG then in its flexible form (CG only; 0: V-cycles;
                                default 2) */
-    int reserved[5];
+    int ilu_block_rows;     /* VAG_PC_BJILU0: unknowns per block, 1..8192 (0: 1024); blocks are
+                               runs of the natural unknown order (vag_get_system's) */
+    int reserved[4];
 } vag_options;
 
 typedef struct {
@@ -275,6 +282,17 @@ vag_status vag_get_concentration(vag_handle *h, double *c_cell, double *c_frac, 
 /* Size of the assembled system of eq eqschur, after the elimination of the
  * fracture-face groups when enabled. */
 vag_status vag_system_size(vag_handle *h, int64_t *n, int64_t *nnz);
+
+/* z = M^-1 r with the preconditioner that the last vag_solve_pressure set up
+ * (Jacobi: D^-1 r; AMG: one cycle from zero, K-cycles included; block-Jacobi
+ * ILU(0): the forward and backward substitutions of every block).  r and z
+ * hold n = vag_system_size values, in the unknown order of vag_get_system,
+ * both in the memory space mem; caller-owned, r is only read.  For tests and
+ * for callers that run a Krylov method of their own; synchronises the
+ * handle's stream and overwrites the Krylov work vectors (the pressures and
+ * fluxes of the last solve are kept).  VAG_ERR_STATE before the first solve,
+ * VAG_ERR_UNSUPPORTED with VAG_MIXED_IR. */
+vag_status vag_apply_preconditioner(vag_handle *h, const double *r, double *z, vag_mem mem);
 
 /* Copies the assembled system (after a solve): CSR row_ptr[n+1], col[nnz]
  * (int64), val[nnz], b[n].  Unknown order: free nodes by node index, then the

@@ -10,6 +10,7 @@
 #include <unordered_map>
 
 #include "amg.h"
+#include "ilu.h"
 #include "gmres.h"
 #include "vag_internal.h"
 
@@ -174,6 +175,8 @@ struct vag_handle {
     bool solved = false, have_flux = false, have_c = false;
 
     Amg amg;
+    Ilu ilu;                 // block-Jacobi ILU(0)
+    DBuf<int> ilu_bad;       // 1 + natural row of a zero pivot, else 0
     DBuf<float> b32, x32, r32, z32, p32, q32;  // inner single-precision solve (VAG_MIXED)
     DBuf<double> dsc, As;                      // D^-1/2 and the scaled matrix D^-1/2 A D^-1/2
     // GMRES(m) work: FP64 basis (VAG_FP64 / VAG_MIXED) or FP32 basis (inner solves of VAG_MIXED_IR)
@@ -288,8 +291,12 @@ void check_options(const vag_options &o) {
         throw Error(VAG_ERR_UNSUPPORTED, "BiCGStab runs in FP64 (with the FP64 or FP32 hierarchy), not as an inner solver");
     if (o.krylov == VAG_GMRES && (o.gmres_restart < 1 || o.gmres_restart > 1024))
         throw Error(VAG_ERR_ARG, "gmres_restart must lie in [1, 1024]");
-    if (o.precond != VAG_PC_JACOBI && o.precond != VAG_PC_AMG)
+    if (o.precond != VAG_PC_JACOBI && o.precond != VAG_PC_AMG && o.precond != VAG_PC_BJILU0)
         throw Error(VAG_ERR_ARG, "unknown preconditioner");
+    if (o.precond == VAG_PC_BJILU0 && o.krylov == VAG_CG)
+        throw Error(VAG_ERR_UNSUPPORTED, "block-Jacobi ILU(0) is not symmetric: use GMRES or BiCGStab");
+    if (o.ilu_block_rows < 0 || o.ilu_block_rows > kIluMaxBlock)
+        throw Error(VAG_ERR_ARG, "ilu_block_rows must lie in [0, " + std::to_string(kIluMaxBlock) + "]");
 }
 
 // z = M^{-1} r for the handle's preconditioner (see Amg::apply for x_ready, rz)
@@ -355,6 +362,8 @@ void precond_apply(vag_handle *h, const double *r, double *z, const PcgState *st
         h->amg.apply_mixed(h->stream, r, z, st, x_ready, rz, zq, qv);
     else if (h->opt.precond == VAG_PC_AMG)
         h->amg.apply(h->stream, r, z, st, x_ready, rz, zq, qv);
+    else if (h->opt.precond == VAG_PC_BJILU0)
+        h->ilu.apply(h->stream, r, z, st);
     else
         launch_jacobi(h->stream, h->S.nunk, h->dinv.p, r, z);
 }
@@ -905,6 +914,12 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
         } else if (h->opt.precond == VAG_PC_AMG) {
             h->amg.setup(s, h->tr, h->Asell(), (int64_t)h->A.n, amg_options(h->opt));
             if (h->opt.precision == VAG_MIXED) h->amg.make_fp32(s, h->tr, nullptr);
+        } else if (h->opt.precond == VAG_PC_BJILU0) {
+            const int B = h->opt.ilu_block_rows > 0 ? h->opt.ilu_block_rows : kIluDefaultBlock;
+            if (!h->ilu.ready(B)) h->ilu.build(s, h->tr, S, B);
+            if (!h->ilu_bad.p) h->ilu_bad.alloc(1, h->tr);
+            VAG_HIP(hipMemsetAsync(h->ilu_bad.p, 0, sizeof(int), s));
+            h->ilu.factor(s, h->A.p, h->ilu_bad.p);
         }
         VAG_HIP(hipEventRecord(h->ev[2], s));
         // 3. Krylov
@@ -935,8 +950,10 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
         // true residual ||b - A x|| / ||b||
         launch_residual_norm(s, h->Asell(), h->x.p, h->b.p, h->r.p, h->rparts.p, h->scal.p);
         VAG_HIP(hipMemcpyAsync(h->h_scal, h->scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        int bad = 0;
+        int bad = 0, ilu_bad = 0;
         VAG_HIP(hipMemcpyAsync(&bad, h->bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        if (h->opt.precond == VAG_PC_BJILU0)
+            VAG_HIP(hipMemcpyAsync(&ilu_bad, h->ilu_bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipStreamSynchronize(s));
         if (bad == INT_MIN) throw Error(VAG_ERR_ARG, "internal: an assembled entry is missing from the pattern");
         if (bad < 0)
@@ -944,6 +961,9 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
                                          " has a face block that is not positive definite");
         if (bad != 0x7f7f7f7f)
             throw Error(VAG_ERR_MESH, "cell " + std::to_string(bad) + " has a non-positive sub-tetrahedron");
+        if (ilu_bad)
+            throw Error(VAG_ERR_UNSUPPORTED, "ILU(0) pivot of system row " + std::to_string(ilu_bad - 1) +
+                                                 " (natural order) is zero or not finite");
         if (info) {
             std::memset(info, 0, sizeof *info);
             info->iterations = pst.iter;
@@ -1194,6 +1214,31 @@ vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms)
     });
 }
 
+vag_status vag_apply_preconditioner(vag_handle *h, const double *r, double *z, vag_mem mem) {
+    if (!h || !r || !z) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        if (!h->solved) throw Error(VAG_ERR_STATE, "no pressure solve yet");
+        if (h->opt.precision == VAG_MIXED_IR)
+            throw Error(VAG_ERR_UNSUPPORTED, "VAG_MIXED_IR preconditions the scaled FP32 system");
+        const Symbolic &S = h->S;
+        const int32_t n = S.nunk;
+        hipStream_t s = h->stream;
+        if (n == 0) return;
+        // natural order <-> device order on the host (a test and debugging entry)
+        const std::vector<double> rn = host_copy(r, (size_t)n, mem, s);
+        std::vector<double> rd((size_t)n), zd((size_t)n), zn((size_t)n);
+        for (int32_t o = 0; o < n; ++o) rd[S.sys_new[o]] = rn[o];
+        VAG_HIP(hipMemcpyAsync(h->r.p, rd.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
+        precond_apply(h, h->r.p, h->z.p, h->pcg.p + 1);
+        VAG_HIP(hipMemcpyAsync(zd.data(), h->z.p, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipStreamSynchronize(s));
+        for (int32_t o = 0; o < n; ++o) zn[o] = zd[S.sys_new[o]];
+        VAG_HIP(hipMemcpyAsync(z, zn.data(), (size_t)n * sizeof(double),
+                               mem == VAG_MEM_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost, s));
+        VAG_HIP(hipStreamSynchronize(s));
+    });
+}
+
 vag_status vag_amg_levels(vag_handle *h, int *nlev, int64_t *rows, int64_t *nnz, int64_t *stored, int max_levels) {
     if (!h || !nlev) return VAG_ERR_ARG;
     return guard(h, [&] {
@@ -1240,6 +1285,7 @@ size_t vag_estimate_footprint(int64_t nn, int64_t nc, int64_t nf, const vag_opti
         if (o.precision == VAG_MIXED_IR) amg += 8 * S + 8 * Nx + 4.6 * S + 74 * Nx;
         b += 1.125 * amg + 1.5 * 1024 * 1024;                       // + dense coarsest inverse
     }
+    if (o.precond == VAG_PC_BJILU0) b += 14 * nnz + 28 * Nx;        // factor entries, rows, schedules
     return (size_t)(1.15 * b) + ((size_t)1 << 20);
 }
 

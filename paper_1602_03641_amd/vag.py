@@ -24,7 +24,7 @@ VAG_ERR_TIMEOUT, VAG_ERR_CANCELLED = -7, -8
 VAG_MEM_HOST, VAG_MEM_DEVICE = 0, 1
 VAG_FP64, VAG_MIXED, VAG_MIXED_IR = 0, 1, 2
 VAG_CG, VAG_GMRES, VAG_BICGSTAB = 0, 1, 2
-VAG_PC_JACOBI, VAG_PC_AMG = 0, 1
+VAG_PC_JACOBI, VAG_PC_AMG, VAG_PC_BJILU0 = 0, 1, 2
 VAG_KERNEL_SPMV, VAG_KERNEL_TRANSPORT_STEP, VAG_KERNEL_LOCAL, VAG_KERNEL_PRECOND = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "VAG_OK", 1: "VAG_WARN_NOT_CONVERGED", -1: "VAG_ERR_ARG", -2: "VAG_ERR_MESH",
@@ -56,7 +56,7 @@ class vag_options(C.Structure):
                 ("check_every", C.c_int), ("cfl", C.c_double), ("amg_coarse_size", C.c_int),
                 ("amg_max_levels", C.c_int), ("amg_theta", C.c_double), ("amg_sweeps", C.c_int),
                 ("eliminate_frac_faces", C.c_int), ("amg_aggregate_hops", C.c_int), ("amg_kcycle", C.c_int),
-                ("reserved", C.c_int * 5)]
+                ("ilu_block_rows", C.c_int), ("reserved", C.c_int * 4)]
 
 
 class vag_solve_info(C.Structure):
@@ -131,6 +131,7 @@ _SIGS = {
     "vag_system_size": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "vag_get_system": ([vp, vp, vp, vp, vp, C.c_int], C.c_int),
     "vag_benchmark_kernel": ([vp, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
+    "vag_apply_preconditioner": ([vp, vp, vp, C.c_int], C.c_int),
     "vag_amg_levels": ([vp, C.POINTER(C.c_int), vp, vp, vp, C.c_int], C.c_int),
     "vag_footprint_bytes": ([vp], C.c_size_t),
     "vag_last_error": ([vp], C.c_char_p),
@@ -306,6 +307,14 @@ class Handle:
         p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
         self._check(load().vag_get_system(self.h, p(rp), p(col), p(val), p(b), VAG_MEM_HOST))
         return rp, col, val, b
+
+    def apply_preconditioner(self, r):
+        """z = M^-1 r (host arrays, the unknown order of system())."""
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        z = np.zeros_like(r)
+        p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+        self._check(load().vag_apply_preconditioner(self.h, p(r), p(z), VAG_MEM_HOST))
+        return z
 
     def benchmark_kernel(self, kernel, reps=50):
         ms = C.c_double()

@@ -104,3 +104,10 @@ def test_bad_indices_and_options():
     assert _host_create(p, amg_kcycle=-1)[0] == vag.VAG_ERR_ARG
     assert _host_create(p, amg_kcycle=13)[0] == vag.VAG_ERR_ARG
     assert _host_create(p, amg_aggregate_hops=3)[0] == vag.VAG_ERR_ARG
+    st, msg = _host_create(p, precond=vag.VAG_PC_BJILU0)  # with CG
+    assert st == vag.VAG_ERR_UNSUPPORTED and "GMRES or BiCGStab" in msg
+    assert _host_create(p, precond=vag.VAG_PC_BJILU0, precision=vag.VAG_MIXED,
+                        krylov=vag.VAG_GMRES)[0] == vag.VAG_ERR_UNSUPPORTED
+    assert _host_create(p, precond=vag.VAG_PC_BJILU0, krylov=vag.VAG_GMRES,
+                        ilu_block_rows=8193)[0] == vag.VAG_ERR_ARG
+    assert _host_create(p, precond=3)[0] == vag.VAG_ERR_ARG

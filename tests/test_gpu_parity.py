@@ -651,3 +651,94 @@ def test_kcycle_ignored_where_not_cg():
         b = gpu_run(p, amg_kcycle=3, **kw)
         assert a["info"]["iterations"] == b["info"]["iterations"]
         np.testing.assert_array_equal(a["u_node"], b["u_node"])
+
+
+# ---------------------------------------------------------------------------
+# block-Jacobi ILU(0) (with GMRES or BiCGStab), and the preconditioner entry
+# ---------------------------------------------------------------------------
+def _same_system_as_oracle(p, h):
+    """The library's system with every fracture face kept has the oracle's
+    unknown order and pattern; returns the oracle's (A, b)."""
+    A, b = oracle.system(p)
+    rp, col, val, _ = h.system()
+    np.testing.assert_array_equal(rp, A.indptr)
+    np.testing.assert_array_equal(col, A.indices)
+    assert np.abs(val - A.data).max() <= 1e-12 * np.abs(A.data).max()
+    return A, b
+
+
+@pytest.mark.parametrize("B", [1, 64, 300, 8192])
+def test_bjilu0_apply_matches_oracle(B):
+    """z = M^-1 r element by element against the oracle's block-Jacobi
+    ILU(0) of its own system (blocks of B unknowns, the last one ragged;
+    B = 1 is Jacobi, 8192 one block)."""
+    from paper_1602_03641_amd import vag
+    from oracle import ilu
+    p = synth.random_problem((11, 9, 8), 15, n_patches=6, n_steps=0, ratios=(1e2, 1e4))
+    g = gpu_run(p, n_steps=0, rtol=1e-10, max_iter=5000, precond=vag.VAG_PC_BJILU0, krylov=vag.VAG_BICGSTAB,
+                ilu_block_rows=B, eliminate_frac_faces=0)
+    assert g["info"]["status"] == 0
+    h = g["handle"]
+    A, _ = _same_system_as_oracle(p, h)
+    rows = ilu.bj_ilu0(A, B)
+    rng = np.random.default_rng(16)
+    for _ in range(2):
+        r = rng.standard_normal(A.shape[0])
+        z = h.apply_preconditioner(r)
+        zr = ilu.bj_ilu0_apply(rows, r)
+        assert np.abs(z - zr).max() <= 1e-11 * np.abs(zr).max()
+
+
+@pytest.mark.parametrize("krylov", ["gmres", "bicgstab"])
+def test_bjilu0_parity(krylov):
+    """Jittered anisotropic mesh, contrasts up to 1e6, fracture faces
+    eliminated: the oracle's solution."""
+    from paper_1602_03641_amd import vag
+    p = synth.random_problem((10, 8, 7), 8, n_patches=6, n_steps=20)
+    kw = _gmres(gmres_restart=200) if krylov == "gmres" else _bicgstab()
+    g = gpu_run(p, rtol=1e-12, max_iter=20000, precond=vag.VAG_PC_BJILU0, ilu_block_rows=128, **kw)
+    o = oracle.run(p, rtol=1e-13)
+    assert reached(g["info"], max(1e-12, residual_floor(p, o)))
+    compare(p, g, o)
+
+
+def test_bjilu0_config1_and_config2():
+    """Config 1 to the parity bar; config 2 at its tolerance, fewer
+    iterations with larger blocks, bitwise reproducible."""
+    from paper_1602_03641_amd import vag
+    p = synth.config1()
+    g = gpu_run(p, rtol=1e-13, max_iter=5000, precond=vag.VAG_PC_BJILU0, **_bicgstab())
+    o = oracle.run(p, rtol=1e-13)
+    assert reached(g["info"])
+    compare(p, g, o)
+    p = synth.config2()
+    kw = dict(n_steps=0, rtol=1e-8, max_iter=20000, precond=vag.VAG_PC_BJILU0, **_bicgstab())
+    small = gpu_run(p, ilu_block_rows=256, **kw)["info"]
+    a = gpu_run(p, ilu_block_rows=4096, **kw)
+    b = gpu_run(p, ilu_block_rows=4096, **kw)
+    print("config2 BiCGStab + BJ-ILU(0) iterations: blocks of 256:", small["iterations"], "of 4096:",
+          a["info"]["iterations"], "ms solve", a["info"]["ms_solve"])
+    assert a["info"]["status"] == 0 and a["info"]["rel_residual"] <= 1e-8
+    assert a["info"]["iterations"] <= small["iterations"]
+    np.testing.assert_array_equal(a["u_node"], b["u_node"])
+
+
+def test_apply_preconditioner_jacobi_and_amg():
+    """Jacobi: z = r / diag(A) of the oracle's system.  AMG with V-cycles:
+    the cycle is a symmetric operator (r . M^-1 s = s . M^-1 r), which CG
+    needs; with K-cycles it is not linear."""
+    from paper_1602_03641_amd import vag
+    p = synth.random_problem((9, 8, 7), 17, n_patches=5, n_steps=0)
+    rng = np.random.default_rng(18)
+    g = gpu_run(p, n_steps=0, rtol=1e-10, max_iter=5000, precond=vag.VAG_PC_JACOBI, eliminate_frac_faces=0)
+    A, _ = _same_system_as_oracle(p, g["handle"])
+    r = rng.standard_normal(A.shape[0])
+    np.testing.assert_allclose(g["handle"].apply_preconditioner(r), r / A.diagonal(), rtol=1e-13)
+    g = gpu_run(p, n_steps=0, rtol=1e-10, max_iter=5000, precond=vag.VAG_PC_AMG, amg_kcycle=0, amg_coarse_size=30)
+    h = g["handle"]
+    n = h.system()[3].size
+    r, s = rng.standard_normal(n), rng.standard_normal(n)
+    zr, zs = h.apply_preconditioner(r), h.apply_preconditioner(s)
+    assert abs(r @ zs - s @ zr) <= 1e-12 * np.linalg.norm(r) * np.linalg.norm(zs)
+    assert r @ zr > 0 and s @ zs > 0
+    np.testing.assert_array_equal(h.apply_preconditioner(r), zr)
