@@ -95,20 +95,35 @@ def galerkin(A, P):
 
 
 def pmis_valid(S, is_coarse):
-    """(independent, lonely): whether no two coarse points are strongly
-    connected (in S or S^T), which the PMIS rule guarantees, and the number
-    of fine points that have strong neighbours but none of them coarse (the
-    rule allows these; they receive an empty interpolation row)."""
-    S = sp.csr_matrix(S)
-    G = (S + S.T).tocsr()
+    """(independent, covered, lonely) of a splitting under the PMIS rule.
+
+    PMIS picks, round after round, undecided points whose measure beats that
+    of every undecided strong neighbour, then makes fine every undecided
+    point that strongly depends on a new coarse point; points that influence
+    no one start fine.  Every splitting it can produce therefore has:
+    independent: no two coarse points depend strongly on each other (the
+    first chosen would have made the other fine; two points chosen in one
+    round are not neighbours); one-way dependence between coarse points
+    chosen in different rounds is allowed;
+    covered: every fine point that strongly influences some point depends
+    strongly on a coarse point.
+    lonely counts the fine points with strong dependencies but no coarse one
+    among them (they receive an empty interpolation row)."""
+    S = sp.csr_matrix(S).astype(bool)
+    M = S.multiply(S.T).tocsr()  # mutual strong dependence
+    lam = np.asarray(S.sum(axis=0)).ravel()  # points that depend on each point
     is_coarse = np.asarray(is_coarse, bool)
-    independent = True
+    independent = covered = True
     lonely = 0
     for i in range(S.shape[0]):
-        nb = G.indices[G.indptr[i]:G.indptr[i + 1]]
-        nb = nb[nb != i]
-        if is_coarse[i] and is_coarse[nb].any():
+        mut = M.indices[M.indptr[i]:M.indptr[i + 1]]
+        dep = S.indices[S.indptr[i]:S.indptr[i + 1]]
+        if is_coarse[i] and is_coarse[mut[mut != i]].any():
             independent = False
-        if not is_coarse[i] and len(nb) and not is_coarse[nb].any():
-            lonely += 1
-    return independent, lonely
+        if not is_coarse[i]:
+            has_c = bool(is_coarse[dep].any())
+            if lam[i] > 0 and not has_c:
+                covered = False
+            if len(dep) and not has_c:
+                lonely += 1
+    return independent, covered, lonely

@@ -51,7 +51,7 @@ def test_constants_preserved_on_zero_row_sums():
     nonempty = np.diff(P.indptr) > 0
     assert nonempty[~cf].sum() > 0.8 * (~cf).sum()
     np.testing.assert_allclose(rs[nonempty], 1.0, rtol=1e-14)
-    ind, lonely = ca.pmis_valid(S, cf)
+    ind, cov, lonely = ca.pmis_valid(S, cf)
     assert ind  # a checkerboard has no two coarse points adjacent on the 5-point graph
 
 
@@ -73,5 +73,10 @@ def test_strength_and_positive_couplings_by_hand():
     # row 2: neighbours 1 (C, -1.0, strong), 3 (F, -0.3), 0 (+0.5)
     np.testing.assert_allclose(P[2, 0], ((1.0 + 0.3) / 1.0) * 1.0 / (2.0 + 0.5), rtol=1e-15)
     assert P[3, 0] == 0.0  # row 3 has no strong coarse neighbour (a_31 = 0)
-    ind, lonely = ca.pmis_valid(sp.csr_matrix(S), cf)
-    assert ind and lonely == 1
+    ind, cov, lonely = ca.pmis_valid(sp.csr_matrix(S), cf)
+    # row 3 depends on 0 and 2 (both fine) and point 2 depends on it: a PMIS
+    # splitting could not leave it fine without a coarse point to lean on
+    assert ind and lonely == 1 and not cov
+    assert ca.pmis_valid(sp.csr_matrix(S), np.array([False, True, False, True]))[:2] == (True, True)
+    # 1 and 2 depend on each other: both coarse is never a PMIS result
+    assert not ca.pmis_valid(sp.csr_matrix(S), np.array([False, True, True, False]))[0]
