@@ -61,7 +61,7 @@ def algorithmic_bytes(h, sinfo, tinfo, levels=None, precision="fp64", sweeps=2, 
 def kcycle_levels(vag, opts, args, levels):
     """Coarse levels that run K-cycles: 1..amg_kcycle below the coarsest, with
     CG outside and no FP32 inner solve (the library's rule)."""
-    if not levels or args.krylov != "cg" or args.precision == "mixed_ir":
+    if not levels or args.krylov != "cg" or args.precision == "mixed_ir" or args.amg_kind == "classical":
         return 0
     k = opts.get("amg_kcycle", vag.default_options().amg_kcycle)
     return max(0, min(k, len(levels) - 2))
@@ -220,6 +220,7 @@ def main():
     ap.add_argument("--keep-faces", action="store_true", help="fracture faces stay unknowns (no group elimination)")
     ap.add_argument("--amg-sweeps", type=int, default=0, help="l1-Jacobi sweeps on the coarse levels (0: default)")
     ap.add_argument("--amg-hops", type=int, default=0, help="aggregate radius: 2 (default) or 1")
+    ap.add_argument("--amg-kind", choices=["aggregation", "classical"], default="aggregation")
     ap.add_argument("--ilu-block-rows", type=int, default=0, help="block-Jacobi ILU(0) block size (0: default)")
     ap.add_argument("--amg-kcycle", type=int, default=-1, help="coarse levels with K-cycles (-1: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -269,6 +270,8 @@ def main():
         opts["amg_aggregate_hops"] = args.amg_hops
     if args.amg_kcycle >= 0:
         opts["amg_kcycle"] = args.amg_kcycle
+    if args.amg_kind == "classical":
+        opts["amg_kind"] = 1
     if args.ilu_block_rows > 0:
         opts["ilu_block_rows"] = args.ilu_block_rows
     t0 = time.perf_counter()
@@ -377,6 +380,7 @@ def main():
         "config": {"workload": describe(args, prob),
                    "precond": args.precond, "precision": args.precision, "krylov": args.krylov,
                    "amg_kcycle_levels": kcycle_levels(vag, opts, args, levels),
+                   "amg_kind": args.amg_kind if args.precond == "amg" else None,
                    "fracture_faces": "kept" if args.keep_faces else "eliminated",
                    "n_unknowns": sinfo["n_unknowns"], "nnz": sinfo["nnz"], "n_frac": prob.n_frac},
         "iterations": sinfo["iterations"], "rel_residual": sinfo["rel_residual"],

@@ -150,7 +150,11 @@ typedef struct {
                                default 2) */
     int ilu_block_rows;     /* VAG_PC_BJILU0: unknowns per block, 1..8192 (0: 1024); blocks are
                                runs of the natural unknown order (vag_get_system's) */
-    int reserved[4];
+    int amg_kind;           /* VAG_PC_AMG: 0 aggregation (default); 1 classical (strength
+                               -a_ij >= amg_strong_theta max_k -a_ik, PMIS coarse points, direct
+                               interpolation, Galerkin R A P; V-cycles, amg_kcycle ignored) */
+    double amg_strong_theta;/* classical strength threshold in (0, 1); 0: 0.25 */
+    int reserved[1];
 } vag_options;
 
 typedef struct {
@@ -313,6 +317,19 @@ vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms_
  * max_levels; any array may be NULL), rows, nonzero entries and stored
  * entries (sliced ELL including padding). */
 vag_status vag_amg_levels(vag_handle *h, int *nlev, int64_t *rows, int64_t *nnz, int64_t *stored, int max_levels);
+
+/* Level `level` of the last solve's AMG hierarchy as host CSR arrays: the
+ * matrix A_l (n x n, columns ascending, slice padding left out) and the
+ * interpolation P_l (n x n_coarse) that carries level l + 1 back to level l
+ * (aggregation: one entry 1 per row; none on the coarsest level), and for the
+ * classical hierarchy the coarse index of each row (-1: fine point; every
+ * entry -1 for aggregation).  Level 0 uses the unknown order of
+ * vag_get_system.  sizes[4] receives n, nnz(A_l), n_coarse, nnz(P_l); call
+ * with null arrays first to size them (caller-owned, any may be NULL).
+ * VAG_ERR_STATE without an AMG solve, VAG_ERR_ARG for a level out of range. */
+vag_status vag_amg_level_csr(vag_handle *h, int level, int64_t *sizes, int64_t *a_ptr, int64_t *a_col,
+                             double *a_val, int64_t *p_ptr, int64_t *p_col, double *p_val,
+                             int32_t *coarse_index);
 
 /* Device bytes held by the handle. */
 size_t vag_footprint_bytes(const vag_handle *h);

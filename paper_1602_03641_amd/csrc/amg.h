@@ -86,6 +86,43 @@ void launch_to_float(hipStream_t s, int64_t n, const double *a, float *b);
 void launch_to_float_rowsum(hipStream_t s, Sell<double> A, float *v32, double *dg);
 void launch_to_double(hipStream_t s, int64_t n, const float *a, double *b);
 
+// classical AMG (amg_classical.hip): product tables hold at most kClCapMax
+// slots per row; rows are processed in chunks of kClChunk
+constexpr int32_t kClCapMax = 16384;
+constexpr int32_t kClChunk = 65536;
+void cl_launch_strength(hipStream_t s, Sell<double> A, double theta, double *m, uint8_t *sf, uint64_t *key,
+                        int8_t *state);
+// one PMIS round (tmp: n bytes); *cnt += blocks that still hold undecided points
+void cl_launch_pmis_round(hipStream_t s, Sell<double> A, const uint8_t *sf, const uint64_t *key, int8_t *st,
+                          int8_t *tmp, int *cnt);
+void cl_launch_pmis_close(hipStream_t s, int32_t n, int8_t *st);
+void cl_launch_interp_count(hipStream_t s, Sell<double> A, const uint8_t *sf, const int8_t *st, int32_t *plen,
+                            int32_t *cflag);
+void cl_launch_interp_fill(hipStream_t s, Sell<double> A, const uint8_t *sf, const int8_t *st, const int32_t *cidx,
+                           const int32_t *pptr, int32_t *pcol, double *pval, int32_t *cfine);
+// rptr null: row lengths into rlen; else the rows
+void cl_launch_transpose(hipStream_t s, Sell<double> A, int32_t nc, const int32_t *cfine, const int8_t *st,
+                         const int32_t *pptr, const int32_t *pcol, const double *pval, int32_t *rlen,
+                         const int32_t *rptr, int32_t *rcol, double *rval);
+void cl_launch_ap_cap(hipStream_t s, Sell<double> A, const int32_t *pptr, int32_t *cap);
+void cl_launch_rap_cap(hipStream_t s, int32_t nc, const int32_t *rptr, const int32_t *rcol, const int32_t *apptr,
+                       int32_t *cap);
+void cl_launch_chunk_sums(hipStream_t s, int32_t n, const int32_t *cap, int64_t *sums);
+// rows [r0, r1) of X Y (X: AX in sliced ELL, or CSR xptr/xcol/xval); tables at
+// hoff[i - r0]; count (rowlen) or fill (CSR optr, or sliced ELL when sell_out)
+void cl_launch_product(hipStream_t s, int32_t r0, int32_t r1, const Sell<double> *AX, const int32_t *xptr,
+                       const int32_t *xcol, const double *xval, const int32_t *yptr, const int32_t *ycol,
+                       const double *yval, const int32_t *cap, const int32_t *hoff, int32_t *hkey, double *hval,
+                       bool fill, int32_t *rowlen, const int64_t *optr, bool sell_out, int32_t *ocol, double *oval,
+                       int *overflow);
+void cl_launch_widen(hipStream_t s, int32_t n, const int32_t *in, int64_t *out);
+template <class X>
+void cl_launch_restrict(hipStream_t s, int32_t nc, const int32_t *rptr, const int32_t *rcol, const double *rval,
+                        const X *r, X *bc, const X *dinv_c, X *xc, const PcgState *st);
+template <class X>
+void cl_launch_prolong(hipStream_t s, int32_t n, const int32_t *pptr, const int32_t *pcol, const double *pval,
+                       const X *x, const X *e, X *y, const PcgState *st);
+
 // grow-only device buffer (keeps its allocation across solves)
 template <class T>
 void ensure(DBuf<T> &b, size_t n, Tracker &t) {
@@ -101,6 +138,8 @@ struct AmgLevel {
     Sell<double> A;                 // view (level 0: the handle's matrix)
     DBuf<double> diag, dinv;
     DBuf<int32_t> agg, mptr, mrows; // aggregation to the next level
+    DBuf<int32_t> pptr, pcol, rptr, rcol;  // classical: interpolation P and R = P^T (CSR)
+    DBuf<double> pval, rval;
     DBuf<double> b, xa, xb, r;      // cycle vectors
     DBuf<float> val32, dinv32, b32, xa32, xb32, r32;
     DBuf<double> dg32;  // FP64 diagonal of the FP32 copy (row sums kept)
@@ -118,6 +157,8 @@ struct AmgOptions {
     int sweeps = 1;         // sweeps before and after the correction on levels >= 1
     int hops = 2;           // roots: distance-2 (2) or distance-1 (1) independent set
     int kcycle = 0;         // coarse levels 1..kcycle take the K-cycle (when not the coarsest)
+    int kind = 0;           // 0: aggregation, 1: classical (PMIS, direct interpolation)
+    double strong_theta = 0.25;  // classical strength threshold
 };
 
 class Amg {
@@ -149,6 +190,7 @@ class Amg {
                      double *rz = nullptr, double *zq = nullptr, const double *qv = nullptr);
     // true when applying the hierarchy runs K-cycles (a nonlinear preconditioner)
     bool nonlinear() const { return o_.kcycle > 0 && nlev >= 3; }
+    bool classical() const { return o_.kind == 1; }
     // levels at or below this many rows prolongate and smooth in one kernel
     static constexpr int32_t kFusedPostRows = kSmallRows;
 
@@ -162,8 +204,25 @@ class Amg {
     AmgOptions o_;
     double *zq_ = nullptr;        // flexible-CG partials of the current application
     const double *qv_ = nullptr;
+    // classical hierarchy: scratch of the setup
+    DBuf<double> cm_, chval_, capval_;
+    DBuf<uint8_t> csf_;
+    DBuf<uint64_t> ckey_;
+    DBuf<int8_t> cst_, cst2_;
+    DBuf<int32_t> cplen_, cflag_, ccidx_, ccfine_, crlen_, ccap_, choff_, chkey_, captr_, capcol_;
+    DBuf<int64_t> captr64_, csums_;
+    void setup_classical(hipStream_t s, Tracker &tr, int64_t stored0);
+    // vectors, K-cycle work and the coarsest inverse once level l is the coarsest
+    void finish_setup(hipStream_t s, Tracker &tr, int l, int64_t stored_total, int64_t stored0);
+    // sparse product X Y in chunks (count: rowlen; fill: into optr/ocol/oval); false on table overflow
+    bool product(hipStream_t s, Tracker &tr, int32_t n, const Sell<double> *AX, const int32_t *xptr,
+                 const int32_t *xcol, const double *xval, const int32_t *yptr, const int32_t *ycol,
+                 const double *yval, bool fill, int32_t *rowlen, const int64_t *optr, bool sell_out, int32_t *ocol,
+                 double *oval);
     template <class V, class X>
     void cycle(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bool x_ready, double *rz);
+    template <class V, class X>
+    void cycle_classical(hipStream_t s, int l, const X *b, X *out, const PcgState *st, bool x_ready);
     // coarse-grid correction of level m: a V-cycle, or a K-cycle (two flexible CG steps)
     template <class V, class X>
     void coarse(hipStream_t s, int m, const X *b, X *e, const PcgState *st, bool x_ready);

@@ -283,6 +283,9 @@ void check_options(const vag_options &o) {
     if (o.precision == VAG_MIXED_IR && !(o.inner_rtol > 0 && o.inner_rtol < 1))
         throw Error(VAG_ERR_ARG, "inner_rtol must lie in (0, 1)");
     if (o.amg_kcycle < 0 || o.amg_kcycle > 12) throw Error(VAG_ERR_ARG, "amg_kcycle must lie in [0, 12]");
+    if (o.amg_kind != 0 && o.amg_kind != 1) throw Error(VAG_ERR_ARG, "amg_kind must be 0 (aggregation) or 1 (classical)");
+    if (!(o.amg_strong_theta >= 0 && o.amg_strong_theta < 1))
+        throw Error(VAG_ERR_ARG, "amg_strong_theta must lie in [0, 1) (0: default)");
     if (o.amg_aggregate_hops < 0 || o.amg_aggregate_hops > 2)
         throw Error(VAG_ERR_ARG, "amg_aggregate_hops must be 0 (default), 1 or 2");
     if (o.krylov != VAG_CG && o.krylov != VAG_GMRES && o.krylov != VAG_BICGSTAB)
@@ -375,6 +378,8 @@ AmgOptions amg_options(const vag_options &o) {
     if (o.amg_max_levels > 0) a.max_levels = o.amg_max_levels;
     if (o.amg_sweeps > 0) a.sweeps = o.amg_sweeps;
     if (o.amg_aggregate_hops > 0) a.hops = o.amg_aggregate_hops;
+    a.kind = o.amg_kind;
+    if (o.amg_strong_theta > 0) a.strong_theta = o.amg_strong_theta;
     // K-cycles make the preconditioner nonlinear: CG runs in its flexible form;
     // GMRES, BiCGStab and the FP32 inner solves keep V-cycles
     a.kcycle = (o.krylov == VAG_CG && o.precision != VAG_MIXED_IR) ? o.amg_kcycle : 0;
@@ -391,7 +396,9 @@ void run_pcg(vag_handle *h) {
     const PcgParts P{h->parts.p, pcg_grid(n)};
     PcgState *st = h->pcg.p;
     const bool jacobi = h->opt.precond == VAG_PC_JACOBI;
-    const bool fused = !jacobi && h->amg.nlev > 1;
+    // the aggregation V-cycle takes D^-1 r from the update kernel and returns
+    // the partials of r.z; the classical one runs apart
+    const bool fused = !jacobi && h->amg.nlev > 1 && !h->amg.classical();
     const bool flexible = fused && h->amg.nonlinear();
     const Sell<double> A = h->Asell();
     const int max_iter = h->opt.max_iter;
@@ -1257,6 +1264,114 @@ vag_status vag_amg_levels(vag_handle *h, int *nlev, int64_t *rows, int64_t *nnz,
     });
 }
 
+vag_status vag_amg_level_csr(vag_handle *h, int level, int64_t *sizes, int64_t *a_ptr, int64_t *a_col,
+                             double *a_val, int64_t *p_ptr, int64_t *p_col, double *p_val, int32_t *coarse_index) {
+    if (!h || !sizes) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        if (!h->solved || h->opt.precond != VAG_PC_AMG) throw Error(VAG_ERR_STATE, "no AMG hierarchy yet");
+        Amg &amg = h->amg;
+        if (level < 0 || level >= amg.nlev) throw Error(VAG_ERR_ARG, "level out of range");
+        hipStream_t s = h->stream;
+        const Symbolic &S = h->S;
+        AmgLevel &lv = *amg.L[level];
+        const int32_t n = lv.n;
+        const bool last = level == amg.nlev - 1;
+        const int32_t nc = last ? 0 : amg.L[level + 1]->n;
+        // level 0 rows and columns go back to the natural order
+        auto nat = [&](int32_t r) { return level == 0 ? S.sys_old[r] : r; };
+        auto dev = [&](int32_t o) { return level == 0 ? S.sys_new[o] : o; };
+        const int64_t ns = (n + 63) / 64;
+        std::vector<int64_t> ptr((size_t)ns + 1);
+        VAG_HIP(hipMemcpyAsync(ptr.data(), lv.A.ptr, ptr.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipStreamSynchronize(s));
+        std::vector<int32_t> col((size_t)ptr[ns]);
+        std::vector<double> val((size_t)ptr[ns]);
+        VAG_HIP(hipMemcpyAsync(col.data(), lv.A.col, col.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipMemcpyAsync(val.data(), lv.A.val, val.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        // interpolation in CSR (device row order)
+        std::vector<int32_t> pp, pc, agg, rp, rc;
+        std::vector<double> pv;
+        if (!last) {
+            if (amg.classical()) {
+                pp.resize((size_t)n + 1);
+                VAG_HIP(hipMemcpyAsync(pp.data(), lv.pptr.p, pp.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                VAG_HIP(hipStreamSynchronize(s));
+                pc.resize((size_t)pp[n]);
+                pv.resize((size_t)pp[n]);
+                VAG_HIP(hipMemcpyAsync(pc.data(), lv.pcol.p, pc.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                VAG_HIP(hipMemcpyAsync(pv.data(), lv.pval.p, pv.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+                rp.resize((size_t)nc + 1);
+                VAG_HIP(hipMemcpyAsync(rp.data(), lv.rptr.p, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                VAG_HIP(hipStreamSynchronize(s));
+                rc.resize((size_t)rp[nc]);
+                VAG_HIP(hipMemcpyAsync(rc.data(), lv.rcol.p, rc.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            } else {
+                agg.resize((size_t)n);
+                VAG_HIP(hipMemcpyAsync(agg.data(), lv.agg.p, agg.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            }
+        }
+        VAG_HIP(hipStreamSynchronize(s));
+        // A: every stored entry except slice padding (the row itself with value 0)
+        std::vector<int64_t> arp((size_t)n + 1, 0);
+        for (int32_t o = 0; o < n; ++o) {
+            const int32_t r = dev(o);
+            const int64_t w = (ptr[r / 64 + 1] - ptr[r / 64]) / 64;
+            int64_t c = 0;
+            for (int64_t j = 0; j < w; ++j) {
+                const int64_t q = ptr[r / 64] + j * 64 + r % 64;
+                c += !(col[q] == r && val[q] == 0.0);
+            }
+            arp[o + 1] = arp[o] + c;
+        }
+        int64_t pnnz = 0;
+        if (!last) pnnz = amg.classical() ? (int64_t)pc.size() : n;
+        sizes[0] = n;
+        sizes[1] = arp[n];
+        sizes[2] = nc;
+        sizes[3] = pnnz;
+        if (a_ptr) std::copy(arp.begin(), arp.end(), a_ptr);
+        if (a_col || a_val)
+            for (int32_t o = 0; o < n; ++o) {
+                const int32_t r = dev(o);
+                const int64_t w = (ptr[r / 64 + 1] - ptr[r / 64]) / 64;
+                std::vector<std::pair<int32_t, double>> e;
+                for (int64_t j = 0; j < w; ++j) {
+                    const int64_t q = ptr[r / 64] + j * 64 + r % 64;
+                    if (!(col[q] == r && val[q] == 0.0)) e.emplace_back(nat(col[q]), val[q]);
+                }
+                std::sort(e.begin(), e.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+                for (size_t k = 0; k < e.size(); ++k) {
+                    if (a_col) a_col[arp[o] + (int64_t)k] = e[k].first;
+                    if (a_val) a_val[arp[o] + (int64_t)k] = e[k].second;
+                }
+            }
+        if (!last && (p_ptr || p_col || p_val)) {
+            int64_t q = 0;
+            for (int32_t o = 0; o < n; ++o) {
+                const int32_t r = dev(o);
+                if (p_ptr) p_ptr[o] = q;
+                if (amg.classical()) {
+                    for (int32_t t = pp[r]; t < pp[r + 1]; ++t, ++q) {
+                        if (p_col) p_col[q] = pc[t];
+                        if (p_val) p_val[q] = pv[t];
+                    }
+                } else {
+                    if (p_col) p_col[q] = agg[r];
+                    if (p_val) p_val[q] = 1.0;
+                    ++q;
+                }
+            }
+            if (p_ptr) p_ptr[n] = q;
+        }
+        if (coarse_index) {
+            std::fill(coarse_index, coarse_index + n, -1);
+            // the first entry of row c of R = P^T is the coarse point itself
+            if (!last && amg.classical())
+                for (int32_t c = 0; c < nc; ++c) coarse_index[nat(rc[rp[c]])] = c;
+        }
+    });
+}
+
 size_t vag_footprint_bytes(const vag_handle *h) { return h ? h->tr.bytes : 0; }
 
 size_t vag_estimate_footprint(int64_t nn, int64_t nc, int64_t nf, const vag_options *opt) {
@@ -1283,6 +1398,8 @@ size_t vag_estimate_footprint(int64_t nn, int64_t nc, int64_t nf, const vag_opti
         double amg = 104 * Nx + 17 * S + 0.15 * (12 * S + 104 * Nx);
         if (o.precision == VAG_MIXED) amg += 4.6 * S + 50 * Nx;
         if (o.precision == VAG_MIXED_IR) amg += 8 * S + 8 * Nx + 4.6 * S + 74 * Nx;
+        if (o.amg_kind == 1)  // denser levels, P, R, A P and the product tables of one chunk of rows
+            amg += 1.5 * amg + 12 * 48 * Nx + 12 * 1024 * std::min(Nx, (double)kClChunk);
         b += 1.125 * amg + 1.5 * 1024 * 1024;                       // + dense coarsest inverse
     }
     if (o.precond == VAG_PC_BJILU0) b += 14 * nnz + 28 * Nx;        // factor entries, rows, schedules

@@ -56,7 +56,8 @@ class vag_options(C.Structure):
                 ("check_every", C.c_int), ("cfl", C.c_double), ("amg_coarse_size", C.c_int),
                 ("amg_max_levels", C.c_int), ("amg_theta", C.c_double), ("amg_sweeps", C.c_int),
                 ("eliminate_frac_faces", C.c_int), ("amg_aggregate_hops", C.c_int), ("amg_kcycle", C.c_int),
-                ("ilu_block_rows", C.c_int), ("reserved", C.c_int * 4)]
+                ("ilu_block_rows", C.c_int), ("amg_kind", C.c_int),
+                ("amg_strong_theta", C.c_double), ("reserved", C.c_int * 1)]
 
 
 class vag_solve_info(C.Structure):
@@ -132,6 +133,7 @@ _SIGS = {
     "vag_get_system": ([vp, vp, vp, vp, vp, C.c_int], C.c_int),
     "vag_benchmark_kernel": ([vp, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
     "vag_apply_preconditioner": ([vp, vp, vp, C.c_int], C.c_int),
+    "vag_amg_level_csr": ([vp, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
     "vag_amg_levels": ([vp, C.POINTER(C.c_int), vp, vp, vp, C.c_int], C.c_int),
     "vag_footprint_bytes": ([vp], C.c_size_t),
     "vag_last_error": ([vp], C.c_char_p),
@@ -315,6 +317,20 @@ class Handle:
         p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
         self._check(load().vag_apply_preconditioner(self.h, p(r), p(z), VAG_MEM_HOST))
         return z
+
+    def amg_level(self, level):
+        """Level `level` of the hierarchy: dict with A (CSR arrays), P (CSR
+        arrays, None on the coarsest level), n_coarse and coarse_index."""
+        sz = np.zeros(4, np.int64)
+        p = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None  # noqa: E731
+        lib = load()
+        self._check(lib.vag_amg_level_csr(self.h, int(level), p(sz), None, None, None, None, None, None, None))
+        n, annz, nc, pnnz = (int(v) for v in sz)
+        ap, ac, av = np.zeros(n + 1, np.int64), np.zeros(annz, np.int64), np.zeros(annz)
+        pp, pc, pv = np.zeros(n + 1, np.int64), np.zeros(pnnz, np.int64), np.zeros(pnnz)
+        ci = np.zeros(n, np.int32)
+        self._check(lib.vag_amg_level_csr(self.h, int(level), p(sz), p(ap), p(ac), p(av), p(pp), p(pc), p(pv), p(ci)))
+        return dict(A=(ap, ac, av), P=(pp, pc, pv) if nc else None, n_coarse=nc, coarse_index=ci)
 
     def benchmark_kernel(self, kernel, reps=50):
         ms = C.c_double()

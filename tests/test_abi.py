@@ -111,3 +111,5 @@ def test_bad_indices_and_options():
     assert _host_create(p, precond=vag.VAG_PC_BJILU0, krylov=vag.VAG_GMRES,
                         ilu_block_rows=8193)[0] == vag.VAG_ERR_ARG
     assert _host_create(p, precond=3)[0] == vag.VAG_ERR_ARG
+    assert _host_create(p, amg_kind=2)[0] == vag.VAG_ERR_ARG
+    assert _host_create(p, amg_strong_theta=1.0)[0] == vag.VAG_ERR_ARG

@@ -742,3 +742,104 @@ def test_apply_preconditioner_jacobi_and_amg():
     assert abs(r @ zs - s @ zr) <= 1e-12 * np.linalg.norm(r) * np.linalg.norm(zs)
     assert r @ zr > 0 and s @ zs > 0
     np.testing.assert_array_equal(h.apply_preconditioner(r), zr)
+
+
+# ---------------------------------------------------------------------------
+# classical AMG (PMIS, direct interpolation) and the exported hierarchy
+# ---------------------------------------------------------------------------
+def _csr(t, shape):
+    import scipy.sparse as sp
+    ptr, col, val = t
+    return sp.csr_matrix((val, col, ptr), shape=shape)
+
+
+def _levels(h):
+    out = []
+    for l in range(len(h.amg_levels())):
+        d = h.amg_level(l)
+        n = len(d["A"][0]) - 1
+        d["Am"] = _csr(d["A"], (n, n))
+        d["Pm"] = _csr(d["P"], (n, d["n_coarse"])) if d["P"] is not None else None
+        out.append(d)
+    return out
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_hierarchy_is_galerkin(kind):
+    """Every coarse operator equals P^T A P of the level above, for the
+    aggregation (kind 0) and the classical (kind 1) hierarchy; level 0 is the
+    oracle's system (faces kept)."""
+    from paper_1602_03641_amd import vag
+    p = synth.random_problem((12, 10, 9), 19, n_patches=6, n_steps=0)
+    g = gpu_run(p, n_steps=0, rtol=1e-10, max_iter=5000, precond=vag.VAG_PC_AMG, amg_kind=kind, amg_coarse_size=40,
+                amg_kcycle=0, eliminate_frac_faces=0)
+    lv = _levels(g["handle"])
+    assert len(lv) >= 3
+    A0, _ = oracle.system(p)
+    assert abs(lv[0]["Am"] - A0).max() <= 1e-12 * abs(A0).max()
+    for a, b in zip(lv[:-1], lv[1:]):
+        G = (a["Pm"].T @ a["Am"] @ a["Pm"]).tocsr()
+        assert abs(G - b["Am"]).max() <= 1e-12 * abs(G).max()
+
+
+def test_classical_interpolation_matches_oracle():
+    """Level 0 of the classical hierarchy on the oracle's own system: the
+    PMIS splitting is valid (no two coarse points depend strongly on each
+    other, every fine point of positive measure depends strongly on a coarse
+    one; it is one of many valid splittings), and for that splitting P
+    equals the oracle's direct interpolation."""
+    from paper_1602_03641_amd import vag
+    from oracle import classical_amg as ca
+    p = synth.random_problem((12, 10, 9), 20, n_patches=6, n_steps=0)
+    g = gpu_run(p, n_steps=0, rtol=1e-10, max_iter=5000, precond=vag.VAG_PC_AMG, amg_kind=1,
+                eliminate_frac_faces=0)
+    d = g["handle"].amg_level(0)
+    A, _ = oracle.system(p)
+    S = ca.strength(A, 0.25)
+    ci = d["coarse_index"]
+    is_c = ci >= 0
+    assert is_c.sum() == d["n_coarse"]
+    independent, covered, lonely = ca.pmis_valid(S, is_c)
+    assert independent and covered
+    print(f"classical level 0: {A.shape[0]} rows, {is_c.sum()} coarse, {lonely} fine without a coarse neighbour")
+    Po = ca.direct_interpolation(A, S, is_c).toarray()
+    # oracle columns: coarse points by increasing index; the library's: ci
+    order = np.argsort(np.where(is_c)[0])
+    gcol_of_ocol = ci[np.where(is_c)[0][order]]
+    Pg = _csr(d["P"], (A.shape[0], d["n_coarse"])).toarray()[:, gcol_of_ocol]
+    np.testing.assert_allclose(Pg, Po, rtol=0, atol=1e-12 * np.abs(Po).max())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_classical_amg_parity(precision):
+    """Classical AMG as the CG preconditioner (and in GMRES): the oracle's
+    solution on a jittered anisotropic mesh with contrasts up to 1e6."""
+    from paper_1602_03641_amd import vag
+    p = synth.random_problem((14, 12, 10), 21, n_patches=8, n_steps=20)
+    pr = vag.VAG_FP64 if precision == "fp64" else vag.VAG_MIXED
+    g = gpu_run(p, rtol=1e-12, max_iter=5000, precond=vag.VAG_PC_AMG, amg_kind=1, precision=pr)
+    o = oracle.run(p, rtol=1e-13)
+    info = g["info"]
+    print(f"classical {precision}: {info['iterations']} iterations, {info['amg_levels']} levels, "
+          f"complexity {info['amg_operator_complexity']:.2f}")
+    assert reached(info, max(1e-12, residual_floor(p, o)))
+    compare(p, g, o)
+    gm = gpu_run(p, rtol=1e-12, max_iter=5000, precond=vag.VAG_PC_AMG, amg_kind=1, precision=pr,
+                 **_gmres(gmres_restart=100))
+    assert reached(gm["info"], max(1e-12, residual_floor(p, o)))
+    compare(p, gm, o)
+
+
+def test_classical_amg_config2():
+    """64^3 benchmark workload at its tolerance; bitwise reproducible."""
+    from paper_1602_03641_amd import vag
+    p = synth.config2()
+    kw = dict(n_steps=0, rtol=1e-8, max_iter=2000, precond=vag.VAG_PC_AMG, amg_kind=1)
+    a = gpu_run(p, **kw)
+    b = gpu_run(p, **kw)
+    info = a["info"]
+    print("classical config2:", {k: info[k] for k in ("iterations", "amg_levels", "amg_operator_complexity",
+                                                       "ms_setup", "ms_solve")})
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-8
+    assert info["iterations"] < 200
+    np.testing.assert_array_equal(a["u_node"], b["u_node"])
