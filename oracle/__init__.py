@@ -37,6 +37,8 @@ class _Problem(C.Structure):
         ("frac_width", C.c_void_p), ("frac_perm", C.c_void_p), ("frac_poro", C.c_void_p),
         ("perm", C.c_void_p), ("poro", C.c_void_p), ("mu", C.c_double),
         ("dirichlet", C.c_void_p), ("p_bar", C.c_void_p), ("c_bar", C.c_void_p),
+        ("n_wells", C.c_int64), ("well_face", C.c_void_p), ("well_wi", C.c_void_p), ("well_pw", C.c_void_p),
+        ("well_q", C.c_void_p), ("well_cinj", C.c_void_p),
     ]
 
 
@@ -63,9 +65,11 @@ def _lib_handle():
         lib.orc_solve_darcy.restype = C.c_int
         lib.orc_porous_volumes.argtypes = [P, vp, vp, vp]
         lib.orc_porous_volumes.restype = C.c_int
-        lib.orc_cfl.argtypes = [P, vp, vp, vp, vp, vp, vp, vp]
+        lib.orc_well_rates.argtypes = [P, vp, vp]
+        lib.orc_well_rates.restype = C.c_int
+        lib.orc_cfl.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.orc_cfl.restype = C.c_int
-        lib.orc_transport.argtypes = [P, vp, vp, vp, vp, vp, vp, C.c_double, C.c_int64, C.c_double,
+        lib.orc_transport.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, C.c_double, C.c_int64, C.c_double,
                                       vp, vp, vp]
         lib.orc_transport.restype = C.c_int
         _lib = lib
@@ -93,10 +97,17 @@ class OracleProblem:
         self.p_bar = np.ascontiguousarray(prob.p_bar, np.float64)
         self.c_bar = np.ascontiguousarray(prob.c_bar, np.float64)
         self.nn, self.nc, self.nf = len(self.xyz), len(self.hex8), len(self.frac_nodes)
+        w = getattr(prob, "wells", None) or {}
+        self.well_face = np.ascontiguousarray(w.get("face", []), np.int32)
+        self.nw = len(self.well_face)
+        self.well_wi, self.well_pw, self.well_q, self.well_cinj = (
+            np.ascontiguousarray(w.get(k, np.zeros(self.nw)), np.float64) for k in ("wi", "pw", "q", "cinj"))
         self.s = _Problem(self.nn, self.nc, self.nf, _ptr(self.xyz), _ptr(self.hex8),
                           _ptr(self.frac_nodes), _ptr(self.frac_width), _ptr(self.frac_perm),
                           _ptr(self.frac_poro), _ptr(self.perm), _ptr(self.poro), float(prob.mu),
-                          _ptr(self.dirichlet), _ptr(self.p_bar), _ptr(self.c_bar))
+                          _ptr(self.dirichlet), _ptr(self.p_bar), _ptr(self.c_bar), self.nw,
+                          _ptr(self.well_face), _ptr(self.well_wi), _ptr(self.well_pw), _ptr(self.well_q),
+                          _ptr(self.well_cinj))
 
     @property
     def ref(self):
@@ -173,6 +184,9 @@ def solve_darcy(prob, rtol=1e-12, max_iter=200000):
         raise ValueError(f"oracle darcy error {st}")
     out["iters"] = it.value
     out["relres"] = rr.value
+    out["well_rate"] = np.zeros(op.nw)
+    if op.nw:
+        _lib_handle().orc_well_rates(op.ref, _ptr(out["u_frac"]), _ptr(out["well_rate"]))
     return out
 
 
@@ -186,11 +200,33 @@ def porous_volumes(prob):
     return out
 
 
+def _rates(op, flux):
+    """Well rates of a flux dict (solve_darcy's, or given); None without wells."""
+    if not op.nw:
+        return None
+    q = flux.get("well_rate")
+    if q is None:
+        raise ValueError("the problem has wells: the fluxes need their well_rate")
+    return np.ascontiguousarray(q, np.float64)
+
+
+def peaceman_wi(dx, dz, df, lam_f, rw):
+    """Well index of a fracture face perforated by a vertical well (§5.5,
+    Peaceman's method on the face expanded to a dx x df x dz box):
+    WI = 2 pi dz lam_f / ln(r0 / rw), r0 = D exp(-2 pi dz / C),
+    C = 4/3 (dx dz / df + dx df / dz + dz df / dx), D = sqrt(dx^2 + df^2) / 2."""
+    C = 4.0 / 3.0 * (dx * dz / df + dx * df / dz + dz * df / dx)
+    D = 0.5 * math.sqrt(dx * dx + df * df)
+    r0 = D * math.exp(-2.0 * math.pi * dz / C)
+    return 2.0 * math.pi * dz * lam_f / math.log(r0 / rw)
+
+
 def cfl_bounds(prob, flux, phi):
     op = _as(prob)
     dt3 = np.zeros(3)
     st = _lib_handle().orc_cfl(op.ref, _ptr(flux["F_cell"]), _ptr(flux["F_cell_frac"]),
-                               _ptr(flux["F_frac"]), _ptr(phi["phi_cell"]), _ptr(phi["phi_frac"]),
+                               _ptr(flux["F_frac"]), _ptr(_rates(op, flux)), _ptr(phi["phi_cell"]),
+                               _ptr(phi["phi_frac"]),
                                _ptr(phi["phi_node"]), _ptr(dt3))
     if st:
         raise ValueError(f"oracle cfl error {st}")
@@ -204,7 +240,7 @@ def transport(prob, flux, phi, dt, n_steps, last_dt=0.0, c0=None):
     c_node = np.zeros(op.nn) if c0 is None else np.array(c0["c_node"], np.float64)
     st = _lib_handle().orc_transport(
         op.ref, _ptr(flux["F_cell"]), _ptr(flux["F_cell_frac"]), _ptr(flux["F_frac"]),
-        _ptr(phi["phi_cell"]), _ptr(phi["phi_frac"]), _ptr(phi["phi_node"]), float(dt),
+        _ptr(_rates(op, flux)), _ptr(phi["phi_cell"]), _ptr(phi["phi_frac"]), _ptr(phi["phi_node"]), float(dt),
         int(n_steps), float(last_dt), _ptr(c_cell), _ptr(c_frac), _ptr(c_node))
     if st:
         raise ValueError(f"oracle transport error {st}")

@@ -442,6 +442,14 @@ static int build_system(const orc_problem *P, orc_system *S) {
             }
         }
     }
+    /* wells (§5.5): the face equation gains the inflow Q = WI (p_w - u_sigma) + q
+     * on its right: WI on the diagonal, WI p_w + q into b */
+    T = (trip *)realloc(T, sizeof(trip) * (size_t)(nt + P->n_wells + 1));
+    for (int64_t k = 0; k < P->n_wells; ++k) {
+        const int64_t row = nfree + P->well_face[k];
+        T[nt].r = row; T[nt].c = row; T[nt].v = P->well_wi[k]; nt++;
+        S->b[row] += P->well_wi[k] * P->well_pw[k] + P->well_q[k];
+    }
     qsort(T, (size_t)nt, sizeof(trip), trip_cmp);
     S->row_ptr = (int64_t *)calloc((size_t)S->n + 1, sizeof(int64_t));
     S->col = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nt > 0 ? nt : 1));
@@ -623,6 +631,13 @@ int orc_solve_darcy(const orc_problem *P, double rtol, int max_iter, double *u_n
     return 0;
 }
 
+/* Flow from each well into its fracture face: Q = WI (p_w - u_sigma) + q. */
+int orc_well_rates(const orc_problem *P, const double *u_frac, double *Q) {
+    for (int64_t k = 0; k < P->n_wells; ++k)
+        Q[k] = P->well_wi[k] * (P->well_pw[k] - u_frac[P->well_face[k]]) + P->well_q[k];
+    return 0;
+}
+
 /*
  * Porous volumes of the control volumes (§3.2.1).  Control volumes are the
  * cells, the fracture faces and the nodes without a Dirichlet flag; Dirichlet
@@ -679,8 +694,8 @@ static double neg(double a) { return a < 0 ? a : 0.0; }
  * minima; the time step is cfl * min of them.
  */
 int orc_cfl(const orc_problem *P, const double *F_cell, const double *F_cell_frac,
-            const double *F_frac, const double *phi_cell, const double *phi_frac,
-            const double *phi_node, double *dt3) {
+            const double *F_frac, const double *well_rate, const double *phi_cell,
+            const double *phi_frac, const double *phi_node, double *dt3) {
     int64_t nn = P->n_nodes, nc = P->n_cells, nf = P->n_frac;
     int32_t *cell_frac = (int32_t *)malloc(sizeof(int32_t) * 6 * (size_t)nc);
     int32_t *frac_cell = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)(nf > 0 ? nf : 1));
@@ -688,6 +703,9 @@ int orc_cfl(const orc_problem *P, const double *F_cell, const double *F_cell_fra
     int st = orc_topology(P, cell_frac, frac_cell, frac_lface);
     if (st) { free(cell_frac); free(frac_cell); free(frac_lface); return st; }
     double *out_node = (double *)calloc((size_t)nn, sizeof(double));
+    /* a producing well takes fluid out of its face */
+    double *out_well = (double *)calloc((size_t)(nf > 0 ? nf : 1), sizeof(double));
+    for (int64_t k = 0; well_rate && k < P->n_wells; ++k) out_well[P->well_face[k]] += pos(-well_rate[k]);
     double dtM = INFINITY, dtF = INFINITY, dtV = INFINITY;
     for (int64_t K = 0; K < nc; ++K) {
         double out = 0;
@@ -711,11 +729,13 @@ int orc_cfl(const orc_problem *P, const double *F_cell, const double *F_cell_fra
         }
         for (int side = 0; side < 2; ++side)
             if (frac_cell[2 * f + side] >= 0) out += pos(-F_cell_frac[2 * f + side]);
+        out += out_well[f];
         if (out > 0) dtF = fmin(dtF, phi_frac[f] / out);
     }
     for (int64_t s = 0; s < nn; ++s)
         if (!P->dirichlet[s] && out_node[s] > 0) dtV = fmin(dtV, phi_node[s] / out_node[s]);
     dt3[0] = dtM; dt3[1] = dtF; dt3[2] = dtV;
+    free(out_well);
     free(out_node); free(cell_frac); free(frac_cell); free(frac_lface);
     return 0;
 }
@@ -731,11 +751,15 @@ int orc_cfl(const orc_problem *P, const double *F_cell, const double *F_cell_fra
  *   cell:   phi_K (c_K^{n+1} - c_K^n)/dt + sum_nu H_{K,nu} = 0
  *   face:   phi_s (c^{n+1} - c^n)/dt + sum_s H_{sigma,s} - sum_K H_{K,sigma} = 0
  *   node:   phi_s (c^{n+1} - c^n)/dt - sum_K H_{K,s} - sum_sigma H_{sigma,s} = 0
+ * A well perforating face sigma with inflow Q adds
+ *   H_w = c_sigma max(-Q, 0) - c_inj max(Q, 0)
+ * to the face's sum: production leaves at the face's concentration,
+ * injection enters at c_inj.
  */
 int orc_transport(const orc_problem *P, const double *F_cell, const double *F_cell_frac,
-                  const double *F_frac, const double *phi_cell, const double *phi_frac,
-                  const double *phi_node, double dt, int64_t n_steps, double last_dt,
-                  double *c_cell, double *c_frac, double *c_node) {
+                  const double *F_frac, const double *well_rate, const double *phi_cell,
+                  const double *phi_frac, const double *phi_node, double dt, int64_t n_steps,
+                  double last_dt, double *c_cell, double *c_frac, double *c_node) {
     int64_t nn = P->n_nodes, nc = P->n_cells, nf = P->n_frac;
     int32_t *cell_frac = (int32_t *)malloc(sizeof(int32_t) * 6 * (size_t)nc);
     int32_t *frac_cell = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)(nf > 0 ? nf : 1));
@@ -778,6 +802,10 @@ int orc_transport(const orc_problem *P, const double *F_cell, const double *F_ce
                 sF[f] += H;
                 sV[s] -= H;
             }
+        for (int64_t k = 0; well_rate && k < P->n_wells; ++k) {
+            const int32_t f = P->well_face[k];
+            sF[f] += c_frac[f] * pos(-well_rate[k]) - P->well_cinj[k] * pos(well_rate[k]);
+        }
         for (int64_t K = 0; K < nc; ++K) c_cell[K] -= h / phi_cell[K] * sK[K];
         for (int64_t f = 0; f < nf; ++f) c_frac[f] -= h / phi_frac[f] * sF[f];
         for (int64_t s = 0; s < nn; ++s)

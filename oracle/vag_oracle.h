@@ -21,6 +21,15 @@ typedef struct {
     const uint8_t *dirichlet;   /* [n_nodes] */
     const double *p_bar;        /* [n_nodes] */
     const double *c_bar;        /* [n_nodes] */
+    /* Peaceman wells perforating fracture faces (§5.5): the flow from the well
+     * into face sigma is Q = WI (p_w - u_sigma) + q, the injected fluid carries
+     * concentration c_inj.  Each face is perforated at most once. */
+    int64_t n_wells;
+    const int32_t *well_face;   /* [n_wells] fracture face index */
+    const double *well_wi;      /* [n_wells] well index WI (0: rate only) */
+    const double *well_pw;      /* [n_wells] well pressure p_w */
+    const double *well_q;       /* [n_wells] imposed rate q (injection > 0) */
+    const double *well_cinj;    /* [n_wells] concentration of injected fluid */
 } orc_problem;
 
 int orc_topology(const orc_problem *P, int32_t *cell_frac, int32_t *frac_cell, int32_t *frac_lface);
@@ -33,11 +42,12 @@ int orc_solve_darcy(const orc_problem *P, double rtol, int max_iter, double *u_n
                     double *u_frac, double *F_cell, double *F_cell_frac, double *F_frac,
                     int *iters, double *relres);
 int orc_porous_volumes(const orc_problem *P, double *phi_cell, double *phi_frac, double *phi_node);
+int orc_well_rates(const orc_problem *P, const double *u_frac, double *Q);
 int orc_cfl(const orc_problem *P, const double *F_cell, const double *F_cell_frac,
-            const double *F_frac, const double *phi_cell, const double *phi_frac,
-            const double *phi_node, double *dt3);
+            const double *F_frac, const double *well_rate, const double *phi_cell,
+            const double *phi_frac, const double *phi_node, double *dt3);
 int orc_transport(const orc_problem *P, const double *F_cell, const double *F_cell_frac,
-                  const double *F_frac, const double *phi_cell, const double *phi_frac,
-                  const double *phi_node, double dt, int64_t n_steps, double last_dt,
-                  double *c_cell, double *c_frac, double *c_node);
+                  const double *F_frac, const double *well_rate, const double *phi_cell,
+                  const double *phi_frac, const double *phi_node, double dt, int64_t n_steps,
+                  double last_dt, double *c_cell, double *c_frac, double *c_node);
 #endif

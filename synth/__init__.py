@@ -16,6 +16,7 @@ from .meshes import (  # noqa: F401
     cartesian_problem,
     planes_problem,
     random_problem,
+    add_wells,
     e1_problem,
     e2_problem,
     CONFIGS,

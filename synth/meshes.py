@@ -46,6 +46,8 @@ class Problem:
     n_steps: int = 50
     t_final: float = 0.0     # > 0: integrate to this time, last step shortened
     meta: dict = field(default_factory=dict)
+    # wells on fracture faces: dict of arrays face, wi, pw, q, cinj (None: no wells)
+    wells: dict = None
 
     @property
     def n_nodes(self) -> int:
@@ -414,3 +416,20 @@ def e2_problem(n, tan1=5 / 8, tan2=1 / 4, lam_f1=200.0, lam_f3=400.0, df=0.01, t
                    n_steps=0, t_final=t_final,
                    meta=dict(tan1=tan1, tan2=tan2, lam_f1=lam_f1, lam_f3=lam_f3, df=df,
                              x0=x0, y0=y0, branch=branch))
+
+
+def add_wells(prob, seed, n_inj=1, n_prod=2, q=0.5, pw=0.3, wi_range=(0.05, 0.2)):
+    """Perforates distinct random fracture faces of prob (in place, returns it):
+    n_inj rate injectors (wi 0, inflow q, injected concentration 1) and n_prod
+    pressure-controlled wells at pressure pw with a well index drawn
+    uniformly in wi_range (they produce where the face pressure exceeds pw)."""
+    rng = np.random.default_rng([17, seed])
+    n = n_inj + n_prod
+    if prob.n_frac < n:
+        raise ValueError("not enough fracture faces for the wells")
+    face = rng.choice(prob.n_frac, size=n, replace=False).astype(np.int32)
+    wi = np.zeros(n)
+    wi[n_inj:] = rng.uniform(*wi_range, size=n_prod)
+    prob.wells = dict(face=face, wi=wi, pw=np.where(np.arange(n) < n_inj, 0.0, pw),
+                      q=np.where(np.arange(n) < n_inj, q, 0.0), cinj=np.where(np.arange(n) < n_inj, 1.0, 0.0))
+    return prob
