@@ -220,6 +220,8 @@ def main():
     ap.add_argument("--keep-faces", action="store_true", help="fracture faces stay unknowns (no group elimination)")
     ap.add_argument("--amg-sweeps", type=int, default=0, help="l1-Jacobi sweeps on the coarse levels (0: default)")
     ap.add_argument("--amg-hops", type=int, default=0, help="aggregate radius: 2 (default) or 1")
+    ap.add_argument("--wells", type=int, default=0,
+                    help="perforate this many fracture faces (one rate injector, the rest at a fixed pressure)")
     ap.add_argument("--amg-kind", choices=["aggregation", "classical"], default="aggregation")
     ap.add_argument("--ilu-block-rows", type=int, default=0, help="block-Jacobi ILU(0) block size (0: default)")
     ap.add_argument("--amg-kcycle", type=int, default=-1, help="coarse levels with K-cycles (-1: library default)")
@@ -258,6 +260,8 @@ def main():
     args.krylov = args.krylov or ("bicgstab" if args.precond == "bjilu0" else kry_def)
     log(f"generating {args.workload} n={args.n}")
     prob = getattr(synth, args.workload)(n=args.n)
+    if args.wells > 0:
+        synth.add_wells(prob, args.n, n_inj=1, n_prod=args.wells - 1)
     log(f"{len(prob.hex8)} cells, {prob.n_frac} fracture faces; creating the handle")
     opts = dict(rtol=prob.rtol, cfl=prob.cfl, max_iter=50000, inner_rtol=1e-2, gmres_restart=100,
                 precond={"amg": vag.VAG_PC_AMG, "jacobi": vag.VAG_PC_JACOBI, "bjilu0": vag.VAG_PC_BJILU0}[args.precond],
@@ -381,6 +385,7 @@ def main():
                    "precond": args.precond, "precision": args.precision, "krylov": args.krylov,
                    "amg_kcycle_levels": kcycle_levels(vag, opts, args, levels),
                    "amg_kind": args.amg_kind if args.precond == "amg" else None,
+                   "wells": args.wells,
                    "fracture_faces": "kept" if args.keep_faces else "eliminated",
                    "n_unknowns": sinfo["n_unknowns"], "nnz": sinfo["nnz"], "n_frac": prob.n_frac},
         "iterations": sinfo["iterations"], "rel_residual": sinfo["rel_residual"],

@@ -264,6 +264,30 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
 vag_status vag_set_fluxes(vag_handle *h, const double *F_cell, const double *F_cell_frac, const double *F_frac,
                           vag_mem mem);
 
+/* Peaceman wells (§5.5) perforating fracture faces: the flow from well k
+ * into face face[k] is Q_k = wi[k] (p_w[k] - u_sigma) + q[k] (wi = 0: a well
+ * at imposed rate q; q = 0: a well at pressure p_w), and the injected fluid
+ * (Q_k > 0) carries concentration c_inj[k]; produced fluid (Q_k < 0) leaves
+ * at the face's concentration and counts in the face's CFL outflow.  Each
+ * face is perforated at most once; wi >= 0; arrays of n values in mem,
+ * copied.  n = 0 removes the wells.  Takes effect at the next
+ * vag_solve_pressure.  VAG_ERR_ARG for a face out of range or perforated
+ * twice, a negative WI or a value that is not finite. */
+vag_status vag_set_wells(vag_handle *h, int64_t n, const int32_t *face, const double *wi, const double *p_w,
+                         const double *q, const double *c_inj, vag_mem mem);
+/* Q_k of the last solve (or of vag_set_well_rates), n values. */
+vag_status vag_get_well_rates(vag_handle *h, double *Q, vag_mem mem);
+/* Well rates for a transport on given fluxes: call after vag_set_fluxes
+ * (which sets them to zero). */
+vag_status vag_set_well_rates(vag_handle *h, const double *Q, vag_mem mem);
+/* Peaceman well index of a fracture face of size dx (along the face) x dz
+ * (along the well) and width d_f with permeability lambda_f, for a well of
+ * radius r_w (§5.5, the face expanded to a dx x d_f x dz box):
+ * 2 pi dz lambda_f / ln(r0 / r_w), r0 = D exp(-2 pi dz / C),
+ * C = 4/3 (dx dz / d_f + dx d_f / dz + dz d_f / dx), D = sqrt(dx^2 + d_f^2) / 2.
+ * 0 for non-positive arguments or r0 <= r_w. */
+double vag_peaceman_wi(double dx, double dz, double d_f, double lambda_f, double r_w);
+
 /* Pressures: u_node[n_nodes] (Dirichlet nodes carry p_bar), u_cell[n_cells],
  * u_frac[n_frac].  Any pointer may be NULL. */
 vag_status vag_get_pressure(vag_handle *h, double *u_node, double *u_cell, double *u_frac,

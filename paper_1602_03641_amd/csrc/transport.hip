@@ -190,8 +190,9 @@ __global__ __launch_bounds__(kT) void cfl_kernel(
     const int32_t *__restrict__ cell_frac, const int32_t *__restrict__ frac_cell,
     const uint8_t *__restrict__ dirichlet, const int32_t *__restrict__ ncp, const int32_t *__restrict__ ncl,
     const int32_t *__restrict__ nfp, const int32_t *__restrict__ nfl, const double *__restrict__ F_cell,
-    const double *__restrict__ F_cell_frac, const double *__restrict__ F_frac, const double *__restrict__ phi_cell,
-    const double *__restrict__ phi_frac, const double *__restrict__ phi_node, double *__restrict__ parts) {
+    const double *__restrict__ F_cell_frac, const double *__restrict__ F_frac, const double *__restrict__ wout,
+    const double *__restrict__ phi_cell, const double *__restrict__ phi_frac, const double *__restrict__ phi_node,
+    double *__restrict__ parts) {
     const double inf = __builtin_inf();
     double v[3] = {inf, inf, inf};
     const int64_t total = (int64_t)nc + nf + nn;
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(kT) void cfl_kernel(
             if (o > 0.0) v[0] = fmin(v[0], phi_cell[K] / o);
         } else if (i < (int64_t)nc + nf) {
             const int32_t f = (int32_t)(i - nc);
-            const double o = frac_out(f, frac_cell, F_frac, F_cell_frac);
+            const double o = frac_out(f, frac_cell, F_frac, F_cell_frac) + (wout ? wout[f] : 0.0);
             if (o > 0.0) v[1] = fmin(v[1], phi_frac[f] / o);
         } else {
             const int32_t s = (int32_t)(i - nc - nf);
@@ -235,7 +236,7 @@ __device__ inline int upwind_row_count(int64_t i, int32_t nc, int32_t nf, const 
                                        const int32_t *cell_frac, const int32_t *frac_cell, const uint8_t *dirichlet,
                                        const int32_t *ncp, const int32_t *ncl, const int32_t *nfp,
                                        const int32_t *nfl, const double *F_cell, const double *F_cell_frac,
-                                       const double *F_frac) {
+                                       const double *F_frac, const double *wsrc) {
     int c = 0;
     if (i < nc) {
         const int32_t K = (int32_t)i;
@@ -255,6 +256,7 @@ __device__ inline int upwind_row_count(int64_t i, int32_t nc, int32_t nf, const 
         for (int k = 0; k < 4; ++k) c += F_frac[4 * (int64_t)f + k] < 0.0;
         for (int side = 0; side < 2; ++side)
             if (frac_cell[2 * (int64_t)f + side] >= 0) c += F_cell_frac[2 * (int64_t)f + side] > 0.0;
+        if (wsrc) c += wsrc[f] > 0.0;  // injection: an entry on the constant control volume
     } else {
         const int32_t s = (int32_t)(i - nc - nf);
         if (!dirichlet[s]) {
@@ -270,7 +272,8 @@ __global__ __launch_bounds__(kSliceRows) void upwind_count_kernel(
     const int32_t *__restrict__ frac_cell, const uint8_t *__restrict__ dirichlet, const int32_t *__restrict__ ncp,
     const int32_t *__restrict__ ncl, const int32_t *__restrict__ nfp, const int32_t *__restrict__ nfl,
     const double *__restrict__ F_cell, const double *__restrict__ F_cell_frac, const double *__restrict__ F_frac,
-    int32_t *__restrict__ slice_width, uint16_t *__restrict__ meta, int32_t *__restrict__ slice_nnz) {
+    const double *__restrict__ wsrc, int32_t *__restrict__ slice_width, uint16_t *__restrict__ meta,
+    int32_t *__restrict__ slice_nnz) {
     // one block = one wavefront = one slice
     const int lane = threadIdx.x;
     const int64_t i = (int64_t)blockIdx.x * kSliceRows + lane;
@@ -278,7 +281,7 @@ __global__ __launch_bounds__(kSliceRows) void upwind_count_kernel(
     int c = 0;
     if (i < total)
         c = upwind_row_count(i, nc, nf, fmask, cell_frac, frac_cell, dirichlet, ncp, ncl, nfp, nfl, F_cell,
-                             F_cell_frac, F_frac);
+                             F_cell_frac, F_frac, wsrc);
     // sort the slice's rows by entry count, longest first (ties: lower lane
     // first), with a bitonic network over the wavefront: slot l then holds
     // the l-th longest row, so the lanes that run out of entries are the last
@@ -357,7 +360,8 @@ __global__ __launch_bounds__(kSliceRows) void upwind_fill_kernel(
     const int32_t *__restrict__ frac_nodes, const uint8_t *__restrict__ dirichlet, const int32_t *__restrict__ ncp,
     const int32_t *__restrict__ ncl, const int32_t *__restrict__ nfp, const int32_t *__restrict__ nfl,
     const double *__restrict__ F_cell, const double *__restrict__ F_cell_frac, const double *__restrict__ F_frac,
-    const double *__restrict__ phi_cell, const double *__restrict__ phi_frac, const double *__restrict__ phi_node,
+    const double *__restrict__ wsrc, const double *__restrict__ wout, const double *__restrict__ phi_cell,
+    const double *__restrict__ phi_frac, const double *__restrict__ phi_node,
     const double *__restrict__ dtp, const int64_t *__restrict__ slice_ptr, const uint16_t *__restrict__ meta,
     int32_t *__restrict__ tcol, double *__restrict__ tval, double *__restrict__ tdiag) {
     // slot threadIdx.x of the slice holds the row named by its meta entry
@@ -420,6 +424,10 @@ __global__ __launch_bounds__(kSliceRows) void upwind_fill_kernel(
             if (F < 0.0) out -= F;
             else if (F > 0.0) emit(K, w * F);
         }
+        // a well: production leaves at c_sigma, injection enters from the
+        // constant control volume (index total, concentration 1)
+        if (wout) out += wout[f];
+        if (wsrc && wsrc[f] > 0.0) emit(total, w * wsrc[f]);
         d = 1.0 - w * out;
     } else {
         const int32_t s = (int32_t)(i - nc - nf);
@@ -568,13 +576,13 @@ void launch_cfl(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t
                 const int32_t *cell_frac, const int32_t *frac_cell, const uint8_t *dirichlet,
                 const int32_t *node_cell_ptr, const int32_t *node_cell, const int32_t *node_frac_ptr,
                 const int32_t *node_frac, const double *F_cell, const double *F_cell_frac, const double *F_frac,
-                const double *phi_cell, const double *phi_frac, const double *phi_node, double cfl,
-                double *parts, double *dt_out) {
+                const double *wout, const double *phi_cell, const double *phi_frac, const double *phi_node,
+                double cfl, double *parts, double *dt_out) {
     const int64_t total = (int64_t)nc + nf + nn;
     const unsigned G = reduce_grid(total, kT);
     hipLaunchKernelGGL(cfl_kernel, dim3(G), dim3(kT), 0, s, nc, nf, nn, hex8, fmask, cell_frac, frac_cell,
                        dirichlet, node_cell_ptr, node_cell, node_frac_ptr, node_frac, F_cell, F_cell_frac, F_frac,
-                       phi_cell, phi_frac, phi_node, parts);
+                       wout, phi_cell, phi_frac, phi_node, parts);
     hipLaunchKernelGGL(cfl_finish_kernel, dim3(1), dim3(kT), 0, s, parts, (int)G, cfl, dt_out);
     VAG_HIP(hipGetLastError());
 }
@@ -582,11 +590,12 @@ void launch_upwind_count(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, cons
                          const int32_t *cell_frac, const int32_t *frac_cell, const uint8_t *dirichlet,
                          const int32_t *node_cell_ptr, const int32_t *node_cell, const int32_t *node_frac_ptr,
                          const int32_t *node_frac, const double *F_cell, const double *F_cell_frac,
-                         const double *F_frac, int32_t *slice_width, uint16_t *meta, int32_t *slice_nnz) {
+                         const double *F_frac, const double *wsrc, int32_t *slice_width, uint16_t *meta,
+                         int32_t *slice_nnz) {
     const int64_t total = (int64_t)nc + nf + nn;
     hipLaunchKernelGGL(upwind_count_kernel, dim3(nb(total, kSliceRows)), dim3(kSliceRows), 0, s, nc, nf, nn, fmask,
                        cell_frac, frac_cell, dirichlet, node_cell_ptr, node_cell, node_frac_ptr, node_frac, F_cell,
-                       F_cell_frac, F_frac, slice_width, meta, slice_nnz);
+                       F_cell_frac, F_frac, wsrc, slice_width, meta, slice_nnz);
     VAG_HIP(hipGetLastError());
 }
 void launch_slice_scan(hipStream_t s, int32_t nslice, const int32_t *slice_width, int64_t *slice_ptr,
@@ -598,15 +607,15 @@ void launch_upwind_fill(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const
                         const uint8_t *fmask, const int32_t *cell_frac, const int32_t *frac_cell,
                         const int32_t *frac_nodes, const uint8_t *dirichlet, const int32_t *node_cell_ptr,
                         const int32_t *node_cell, const int32_t *node_frac_ptr, const int32_t *node_frac,
-                        const double *F_cell, const double *F_cell_frac, const double *F_frac,
-                        const double *phi_cell, const double *phi_frac, const double *phi_node, const double *dt,
-                        const int64_t *slice_ptr, const uint16_t *meta, int32_t *tcol, double *tval,
-                        double *tdiag) {
+                        const double *F_cell, const double *F_cell_frac, const double *F_frac, const double *wsrc,
+                        const double *wout, const double *phi_cell, const double *phi_frac, const double *phi_node,
+                        const double *dt, const int64_t *slice_ptr, const uint16_t *meta, int32_t *tcol,
+                        double *tval, double *tdiag) {
     const int64_t total = (int64_t)nc + nf + nn;
     hipLaunchKernelGGL(upwind_fill_kernel, dim3(nb(total, kSliceRows)), dim3(kSliceRows), 0, s, nc, nf, nn, hex8,
                        fmask, cell_frac, frac_cell, frac_nodes, dirichlet, node_cell_ptr, node_cell, node_frac_ptr,
-                       node_frac, F_cell, F_cell_frac, F_frac, phi_cell, phi_frac, phi_node, dt, slice_ptr, meta,
-                       tcol, tval, tdiag);
+                       node_frac, F_cell, F_cell_frac, F_frac, wsrc, wout, phi_cell, phi_frac, phi_node, dt,
+                       slice_ptr, meta, tcol, tval, tdiag);
     VAG_HIP(hipGetLastError());
 }
 void launch_upwind_pack(hipStream_t s, const UpwindOp &T, uint16_t *tcol16, int32_t *tbase) {

@@ -176,6 +176,12 @@ struct vag_handle {
 
     Amg amg;
     Ilu ilu;                 // block-Jacobi ILU(0)
+    // Peaceman wells: perforations, rates of the last solve, per-face terms
+    int32_t nw = 0;
+    DBuf<int32_t> wface;
+    DBuf<double> wwi, wpw, wq, wcinj, wrate, wgiven, wsrc, wout;
+    const double *well_src() const { return nw ? wsrc.p : nullptr; }
+    const double *well_out() const { return nw ? wout.p : nullptr; }
     DBuf<int> ilu_bad;       // 1 + natural row of a zero pivot, else 0
     DBuf<float> b32, x32, r32, z32, p32, q32;  // inner single-precision solve (VAG_MIXED)
     DBuf<double> dsc, As;                      // D^-1/2 and the scaled matrix D^-1/2 A D^-1/2
@@ -787,8 +793,10 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         h->tmeta.alloc((size_t)nslice * kSliceRows, h->tr);
         h->slice_ptr.alloc(nslice + 1, h->tr);
         h->tdiag.alloc(nrow, h->tr);
-        h->cbuf0.alloc(nrow, h->tr);
-        h->cbuf1.alloc(nrow, h->tr);
+        // one more entry: the constant control volume (concentration 1) that
+        // well injection terms of the upwind operator read
+        h->cbuf0.alloc(nrow + 1, h->tr);
+        h->cbuf1.alloc(nrow + 1, h->tr);
         h->dt4.alloc(4, h->tr);
         h->cnt.alloc(1, h->tr);
         h->h_cnt = static_cast<unsigned long long *>(pinned_get(sizeof(unsigned long long)));
@@ -858,11 +866,94 @@ vag_status vag_set_fluxes(vag_handle *h, const double *F_cell, const double *F_c
         launch_porous(s, S.nc, S.nf, S.nn, h->hex8.p, h->frac_nodes.p, h->dirichlet.p, h->frac_node.p,
                       h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->vol.p, h->poro.p,
                       h->area.p, h->fwidth.p, h->fporo.p, h->phi_cell.p, h->phi_frac.p, h->phi_node.p);
+        if (h->nw) {  // given fluxes come without well rates until vag_set_well_rates
+            launch_fill(s, h->nw, 0.0, h->wrate.p);
+            launch_fill(s, S.nf, 0.0, h->wsrc.p);
+            launch_fill(s, S.nf, 0.0, h->wout.p);
+        }
         VAG_HIP(hipStreamSynchronize(s));
         h->solved = false;
         h->have_flux = true;
         h->have_c = false;
     });
+}
+
+vag_status vag_set_wells(vag_handle *h, int64_t n, const int32_t *face, const double *wi, const double *p_w,
+                         const double *q, const double *c_inj, vag_mem mem) {
+    if (!h || n < 0) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        const Symbolic &S = h->S;
+        hipStream_t s = h->stream;
+        if (n > 0 && (!face || !wi || !p_w || !q || !c_inj)) throw Error(VAG_ERR_ARG, "null well array");
+        if (n > INT32_MAX) throw Error(VAG_ERR_ARG, "too many wells");
+        const std::vector<int32_t> f = host_copy(face, (size_t)n, mem, s);
+        const std::vector<double> a = host_copy(wi, (size_t)n, mem, s), b = host_copy(p_w, (size_t)n, mem, s),
+                                  c = host_copy(q, (size_t)n, mem, s), d = host_copy(c_inj, (size_t)n, mem, s);
+        std::vector<uint8_t> seen((size_t)std::max(S.nf, 1), 0);
+        for (int64_t k = 0; k < n; ++k) {
+            if (f[k] < 0 || f[k] >= S.nf)
+                throw Error(VAG_ERR_ARG, "well " + std::to_string(k) + ": fracture face out of range");
+            if (seen[f[k]]++) throw Error(VAG_ERR_ARG, "fracture face " + std::to_string(f[k]) + " perforated twice");
+            if (!(a[k] >= 0) || !std::isfinite(a[k]) || !std::isfinite(b[k]) || !std::isfinite(c[k]) ||
+                !std::isfinite(d[k]))
+                throw Error(VAG_ERR_ARG, "well " + std::to_string(k) + ": WI must be >= 0 and all values finite");
+        }
+        h->nw = (int32_t)n;
+        if (n) {
+            upload_vec(h, h->wface, f);
+            upload_vec(h, h->wwi, a);
+            upload_vec(h, h->wpw, b);
+            upload_vec(h, h->wq, c);
+            upload_vec(h, h->wcinj, d);
+            h->wrate.alloc((size_t)n, h->tr);
+            h->wgiven.alloc((size_t)n, h->tr);
+            h->wsrc.alloc((size_t)S.nf, h->tr);
+            h->wout.alloc((size_t)S.nf, h->tr);
+            launch_fill(s, n, 0.0, h->wrate.p);
+            launch_fill(s, S.nf, 0.0, h->wsrc.p);
+            launch_fill(s, S.nf, 0.0, h->wout.p);
+            VAG_HIP(hipStreamSynchronize(s));
+        }
+        h->solved = false;
+        h->have_flux = false;
+    });
+}
+
+vag_status vag_get_well_rates(vag_handle *h, double *Q, vag_mem mem) {
+    if (!h || (!Q && h->nw)) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        if (!h->have_flux) throw Error(VAG_ERR_STATE, "no pressure solve (or fluxes) yet");
+        download(h, Q, h->wrate, (size_t)h->nw, mem);
+        VAG_HIP(hipStreamSynchronize(h->stream));
+    });
+}
+
+vag_status vag_set_well_rates(vag_handle *h, const double *Q, vag_mem mem) {
+    if (!h || (!Q && h->nw)) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        if (!h->have_flux) throw Error(VAG_ERR_STATE, "vag_set_well_rates follows vag_set_fluxes");
+        if (!h->nw) return;
+        const Symbolic &S = h->S;
+        hipStream_t s = h->stream;
+        VAG_HIP(hipMemcpyAsync(h->wgiven.p, Q, (size_t)h->nw * sizeof(double), kind_in(mem), s));
+        launch_fill(s, S.nf, 0.0, h->wsrc.p);
+        launch_fill(s, S.nf, 0.0, h->wout.p);
+        launch_well_rates(s, h->nw, h->wface.p, h->wwi.p, h->wpw.p, h->wq.p, h->wcinj.p, h->u_frac.p, h->wgiven.p,
+                          h->wrate.p, h->wsrc.p, h->wout.p);
+        VAG_HIP(hipStreamSynchronize(s));
+        h->have_c = false;
+    });
+}
+
+double vag_peaceman_wi(double dx, double dz, double d_f, double lambda_f, double r_w) {
+    if (!(dx > 0 && dz > 0 && d_f > 0 && lambda_f > 0 && r_w > 0)) return 0.0;
+    // the face expanded to a dx x d_f x dz box: its VAG cell coefficient is
+    // lambda_f C, its corners sit at distance D from the axis
+    const double pi = 3.14159265358979323846;
+    const double C = 4.0 / 3.0 * (dx * dz / d_f + dx * d_f / dz + dz * d_f / dx);
+    const double D = 0.5 * std::sqrt(dx * dx + d_f * d_f);
+    const double lr = std::log(D / r_w) - 2.0 * pi * dz / C;  // ln(r0 / r_w)
+    return lr > 0 ? 2.0 * pi * dz * lambda_f / lr : 0.0;
 }
 
 vag_status vag_set_stream(vag_handle *h, void *hip_stream) {
@@ -903,6 +994,10 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
         launch_fill(s, S.nx, 0.0, h->b.p);
         if (S.ngroup) launch_fill(s, S.grp_off.back(), 0.0, h->Gb.p);
         launch_assemble(s, asm_args(h), S.nunk - S.nfree, S.grp_ptr.empty() ? 0 : S.grp_ptr.back());
+        if (h->nw)
+            launch_well_assemble(s, h->nw, h->wface.p, h->wwi.p, h->wpw.p, h->wq.p,
+                                 WellAsm{S.nunk, h->frac_unk.p, h->diag_pos.p, h->face_grp.p, h->face_loc.p,
+                                         h->grp_ptr.p, h->grp_nptr.p, h->grp_off.p, h->A.p, h->Gb.p, h->b.p});
         // fracture-face groups onto the nodes, colour by colour
         for (int c = 0; c < S.ngcolor; ++c)
             launch_group_elim(s, S.gcolor_ptr[c], S.gcolor_ptr[c + 1] - S.gcolor_ptr[c], S.grp_max_g, S.grp_max_m,
@@ -946,6 +1041,12 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
                           h->frac_unk.p, h->Gb.p, h->b.p, h->x.p);
         launch_node_pressure(s, S.nn, h->node_unk.p, h->x.p, h->p_bar.p, h->u_node.p);
         if (S.nf) launch_node_pressure(s, S.nf, h->frac_unk.p, h->x.p, h->p_bar.p, h->u_frac.p);  // all mapped
+        if (h->nw) {
+            launch_fill(s, S.nf, 0.0, h->wsrc.p);
+            launch_fill(s, S.nf, 0.0, h->wout.p);
+            launch_well_rates(s, h->nw, h->wface.p, h->wwi.p, h->wpw.p, h->wq.p, h->wcinj.p, h->u_frac.p, nullptr,
+                              h->wrate.p, h->wsrc.p, h->wout.p);
+        }
         launch_fill(s, 2 * (int64_t)std::max(S.nf, 1), 0.0, h->F_cell_frac.p);
         launch_cell_flux(s, S.nc, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->aK.p, h->rK.p, h->AKK.p,
                          h->fside.p, h->u_node.p, h->u_frac.p, h->u_cell.p, h->F_cell.p, h->F_cell_frac.p);
@@ -1009,11 +1110,12 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
         VAG_HIP(hipEventRecord(h->ev[5], s));
         launch_cfl(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
                    h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
-                   h->F_cell_frac.p, h->F_frac.p, h->phi_cell.p, h->phi_frac.p, h->phi_node.p, h->opt.cfl,
-                   h->rparts.p, h->dt4.p);
+                   h->F_cell_frac.p, h->F_frac.p, h->well_out(), h->phi_cell.p, h->phi_frac.p, h->phi_node.p,
+                   h->opt.cfl, h->rparts.p, h->dt4.p);
         launch_upwind_count(s, S.nc, S.nf, S.nn, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
                             h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
-                            h->F_cell_frac.p, h->F_frac.p, h->slice_width.p, h->tmeta.p, h->slice_nnz.p);
+                            h->F_cell_frac.p, h->F_frac.p, h->well_src(), h->slice_width.p, h->tmeta.p,
+                            h->slice_nnz.p);
         launch_slice_scan(s, nslice, h->slice_width.p, h->slice_ptr.p, h->slice_nnz.p, h->cnt.p);
         int64_t total = 0;
         VAG_HIP(hipMemcpyAsync(&total, h->slice_ptr.p + nslice, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1031,8 +1133,9 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
         ensure(h->tbase, (size_t)std::max<int64_t>(nslice, 1), h->tr);
         launch_upwind_fill(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p,
                            h->frac_nodes.p, h->dirichlet.p, h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p,
-                           h->node_frac.p, h->F_cell.p, h->F_cell_frac.p, h->F_frac.p, h->phi_cell.p, h->phi_frac.p,
-                           h->phi_node.p, h->dt4.p, h->slice_ptr.p, h->tmeta.p, h->tcol.p, h->tval.p, h->tdiag.p);
+                           h->node_frac.p, h->F_cell.p, h->F_cell_frac.p, h->F_frac.p, h->well_src(), h->well_out(),
+                           h->phi_cell.p, h->phi_frac.p, h->phi_node.p, h->dt4.p, h->slice_ptr.p, h->tmeta.p,
+                           h->tcol.p, h->tval.p, h->tdiag.p);
         launch_upwind_pack(s, h->upwind(), h->tcol16.p, h->tbase.p);
         // initial state
         if (c0_cell || c0_frac || c0_node) {
@@ -1049,6 +1152,8 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
             launch_fill(s, nrow, 0.0, h->cbuf0.p);
         }
         launch_set_dirichlet(s, S.nn, S.nc + S.nf, h->dirichlet.p, h->c_bar.p, h->c_cur());
+        launch_fill(s, 1, 1.0, h->cbuf0.p + nrow);  // the constant control volume
+        launch_fill(s, 1, 1.0, h->cbuf1.p + nrow);
         h->have_c = true;
         int64_t N = n_steps;
         double theta_last = 1.0, last_dt = dt;

@@ -306,14 +306,15 @@ void launch_cfl(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t
                 const uint8_t *fmask, const int32_t *cell_frac, const int32_t *frac_cell,
                 const uint8_t *dirichlet, const int32_t *node_cell_ptr, const int32_t *node_cell,
                 const int32_t *node_frac_ptr, const int32_t *node_frac, const double *F_cell,
-                const double *F_cell_frac, const double *F_frac, const double *phi_cell,
-                const double *phi_frac, const double *phi_node, double cfl, double *parts,
-                double *dt_out /* [4]: dtM, dtF, dtV, dt */);
+                const double *F_cell_frac, const double *F_frac,
+                const double *wout /* [nf] volume produced by a well per face, or null */,
+                const double *phi_cell, const double *phi_frac, const double *phi_node, double cfl,
+                double *parts, double *dt_out /* [4]: dtM, dtF, dtV, dt */);
 void launch_upwind_count(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const uint8_t *fmask,
                          const int32_t *cell_frac, const int32_t *frac_cell, const uint8_t *dirichlet,
                          const int32_t *node_cell_ptr, const int32_t *node_cell,
                          const int32_t *node_frac_ptr, const int32_t *node_frac, const double *F_cell,
-                         const double *F_cell_frac, const double *F_frac, int32_t *slice_width,
+                         const double *F_cell_frac, const double *F_frac, const double *wsrc, int32_t *slice_width,
                          uint16_t *meta, int32_t *slice_nnz);
 // slice_ptr = exclusive scan of 64 * width; with slice_nnz, *total = its sum
 void launch_slice_scan(hipStream_t s, int32_t nslice, const int32_t *slice_width, int64_t *slice_ptr,
@@ -323,7 +324,8 @@ void launch_upwind_fill(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const
                         const int32_t *frac_nodes, const uint8_t *dirichlet, const int32_t *node_cell_ptr,
                         const int32_t *node_cell, const int32_t *node_frac_ptr, const int32_t *node_frac,
                         const double *F_cell, const double *F_cell_frac, const double *F_frac,
-                        const double *phi_cell, const double *phi_frac, const double *phi_node,
+                        const double *wsrc, const double *wout, const double *phi_cell, const double *phi_frac,
+                        const double *phi_node,
                         const double *dt, const int64_t *slice_ptr, const uint16_t *meta, int32_t *tcol,
                         double *tval, double *tdiag);
 // The upwind operator in sliced ELL: meta[slot] = (lane of the row in its
@@ -341,6 +343,21 @@ struct UpwindOp {
 // tcol16 and tbase from tcol (after launch_upwind_fill)
 void launch_upwind_pack(hipStream_t s, const UpwindOp &T, uint16_t *tcol16, int32_t *tbase);
 void launch_transport_step(hipStream_t s, const UpwindOp &T, const double *c_in, double *c_out, double theta);
+// Peaceman wells (wells.hip).  wsrc[f] = c_inj Q^+ (tracer injected into face
+// f per unit time), wout[f] = Q^- (volume produced); the upwind operator's
+// injection entries point at the constant control volume (index nc + nf + nn,
+// concentration 1) that follows the state vector.
+struct WellAsm {
+    int32_t nunk;
+    const int32_t *frac_unk, *diag_pos, *face_grp, *face_loc, *grp_ptr, *grp_nptr;
+    const int64_t *grp_off;
+    double *A, *Gb, *b;
+};
+void launch_well_assemble(hipStream_t s, int32_t nw, const int32_t *wface, const double *wi, const double *pw,
+                          const double *q, const WellAsm &g);
+void launch_well_rates(hipStream_t s, int32_t nw, const int32_t *wface, const double *wi, const double *pw,
+                       const double *q, const double *cinj, const double *u_frac, const double *given, double *rate,
+                       double *fsrc, double *fout);
 void launch_set_dirichlet(hipStream_t s, int32_t nn, int32_t offset, const uint8_t *dirichlet,
                           const double *c_bar, double *c);
 

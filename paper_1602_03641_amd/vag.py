@@ -133,6 +133,10 @@ _SIGS = {
     "vag_get_system": ([vp, vp, vp, vp, vp, C.c_int], C.c_int),
     "vag_benchmark_kernel": ([vp, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
     "vag_apply_preconditioner": ([vp, vp, vp, C.c_int], C.c_int),
+    "vag_set_wells": ([vp, C.c_int64, vp, vp, vp, vp, vp, C.c_int], C.c_int),
+    "vag_get_well_rates": ([vp, vp, C.c_int], C.c_int),
+    "vag_set_well_rates": ([vp, vp, C.c_int], C.c_int),
+    "vag_peaceman_wi": ([C.c_double] * 5, C.c_double),
     "vag_amg_level_csr": ([vp, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
     "vag_amg_levels": ([vp, C.POINTER(C.c_int), vp, vp, vp, C.c_int], C.c_int),
     "vag_footprint_bytes": ([vp], C.c_size_t),
@@ -231,6 +235,10 @@ class Handle:
         if st != VAG_OK:
             raise VagError(st, lib.vag_last_error(None).decode())
         self.h = h
+        self.nw = 0
+        w = getattr(prob, "wells", None)
+        if w:
+            self.set_wells(w["face"], w["wi"], w["pw"], w["q"], w["cinj"])
 
     def _check(self, st):
         if st < 0:
@@ -309,6 +317,25 @@ class Handle:
         p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
         self._check(load().vag_get_system(self.h, p(rp), p(col), p(val), p(b), VAG_MEM_HOST))
         return rp, col, val, b
+
+    def set_wells(self, face, wi, pw, q, cinj):
+        """Peaceman wells on fracture faces (host arrays)."""
+        face = np.ascontiguousarray(face, np.int32)
+        arr = [np.ascontiguousarray(a, np.float64) for a in (wi, pw, q, cinj)]
+        p = lambda a: a.ctypes.data_as(C.c_void_p) if a.size else None  # noqa: E731
+        self._check(load().vag_set_wells(self.h, len(face), p(face), *(p(a) for a in arr), VAG_MEM_HOST))
+        self.nw = len(face)
+
+    def well_rates(self):
+        Q = np.zeros(self.nw)
+        self._check(load().vag_get_well_rates(self.h, Q.ctypes.data_as(C.c_void_p) if self.nw else None,
+                                              VAG_MEM_HOST))
+        return Q
+
+    def set_well_rates(self, Q):
+        Q = np.ascontiguousarray(Q, np.float64)
+        self._check(load().vag_set_well_rates(self.h, Q.ctypes.data_as(C.c_void_p) if Q.size else None,
+                                              VAG_MEM_HOST))
 
     def apply_preconditioner(self, r):
         """z = M^-1 r (host arrays, the unknown order of system())."""
@@ -444,3 +471,8 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def peaceman_wi(dx, dz, d_f, lambda_f, r_w):
+    """Peaceman well index of a fracture face (the library's closed form)."""
+    return float(load().vag_peaceman_wi(dx, dz, d_f, lambda_f, r_w))

@@ -113,3 +113,14 @@ def test_bad_indices_and_options():
     assert _host_create(p, precond=3)[0] == vag.VAG_ERR_ARG
     assert _host_create(p, amg_kind=2)[0] == vag.VAG_ERR_ARG
     assert _host_create(p, amg_strong_theta=1.0)[0] == vag.VAG_ERR_ARG
+
+
+def test_peaceman_index_matches_oracle():
+    """The library's closed-form well index equals the oracle's (which is
+    pinned against the VAG scheme on the box it is derived from)."""
+    import oracle
+    for args in ((3.5, 10.4, 1.0, 1e-11, 0.1), (2.0, 2.0, 0.01, 3.0, 0.1), (7.0, 1.0, 1.0, 2.0, 0.05)):
+        dx, dz, df, lam, rw = args
+        assert vag.peaceman_wi(dx, dz, df, lam, rw) == pytest.approx(oracle.peaceman_wi(dx, dz, df, lam, rw),
+                                                                     rel=1e-13)
+    assert vag.peaceman_wi(-1.0, 1.0, 1.0, 1.0, 0.1) == 0.0

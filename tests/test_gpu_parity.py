@@ -843,3 +843,67 @@ def test_classical_amg_config2():
     assert info["status"] == 0 and info["rel_residual"] <= 1e-8
     assert info["iterations"] < 200
     np.testing.assert_array_equal(a["u_node"], b["u_node"])
+
+
+# ---------------------------------------------------------------------------
+# Peaceman wells on fracture faces
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("eliminate", [1, 0])
+@pytest.mark.parametrize("precond", ["amg", "jacobi"])
+def test_wells_parity(eliminate, precond):
+    """Two rate injectors and two pressure wells: pressures, fluxes, well
+    rates and concentrations against the oracle (fracture faces eliminated
+    or kept: a perforated face inside an eliminated group changes its block)."""
+    from paper_1602_03641_amd import vag
+    p = synth.add_wells(synth.random_problem((12, 10, 8), 33, n_patches=8, n_steps=30, ratios=(1e2, 1e4)), 3,
+                        n_inj=2, n_prod=2)
+    pc = vag.VAG_PC_AMG if precond == "amg" else vag.VAG_PC_JACOBI
+    g = gpu_run(p, rtol=1e-13, max_iter=20000, precond=pc, eliminate_frac_faces=eliminate)
+    o = oracle.run(p, rtol=1e-13)
+    assert reached(g["info"], max(1e-12, residual_floor(p, o)))
+    compare(p, g, o)
+    Q, Qo = g["handle"].well_rates(), o["darcy"]["well_rate"]
+    assert np.abs(Q - Qo).max() <= 1e-8 * np.abs(Qo).max()
+    assert g["tinfo"]["dt"] == pytest.approx(o["dt"], rel=1e-9)
+
+
+def test_wells_transport_identical_fluxes():
+    """Transport with wells on the oracle's fluxes and well rates: only
+    rounding differs."""
+    from paper_1602_03641_amd import vag
+    _torch()
+    p = synth.add_wells(synth.random_problem((11, 9, 8), 34, n_patches=7, n_steps=80), 4, n_inj=2, n_prod=3)
+    od = oracle.solve_darcy(p, rtol=1e-12)
+    phi = oracle.porous_volumes(p)
+    dt = p.cfl * float(np.min(oracle.cfl_bounds(p, od, phi)))
+    oc = oracle.transport(p, od, phi, dt, p.n_steps)
+    h = vag.Handle(p, cfl=p.cfl)
+    h.set_fluxes(od)
+    h.set_well_rates(od["well_rate"])
+    np.testing.assert_array_equal(h.well_rates(), od["well_rate"])
+    t = h.transport(n_steps=p.n_steps)
+    assert t["dt"] == pytest.approx(dt, rel=1e-12)
+    gc = vag.to_numpy(h.concentration())
+    for k in ("c_cell", "c_frac", "c_node"):
+        assert np.abs(gc[k] - oc[k]).max() <= 1e-12, k
+    assert gc["c_frac"][p.wells["face"][0]] > 0.05  # the injected tracer arrived
+
+
+def test_wells_rejected_and_removed():
+    from paper_1602_03641_amd import vag
+    _torch()
+    p = synth.random_problem((6, 5, 5), 35, n_patches=3, n_steps=0)
+    h = vag.Handle(p)
+    one = np.ones(2)
+    for face, wi in (([0, 0], one), ([0, p.n_frac], one), ([0, 1], -one), ([0, 1], np.array([1.0, np.nan]))):
+        with pytest.raises(vag.VagError) as e:
+            h.set_wells(face, wi, one, one, one)
+        assert e.value.status == vag.VAG_ERR_ARG
+    h.solve_pressure()
+    u0 = vag.to_numpy(h.pressure())["u_node"]
+    h.set_wells([1], [0.0], [0.0], [0.4], [1.0])
+    h.solve_pressure()
+    assert np.abs(vag.to_numpy(h.pressure())["u_node"] - u0).max() > 1e-3
+    h.set_wells([], [], [], [], [])
+    h.solve_pressure()
+    np.testing.assert_array_equal(vag.to_numpy(h.pressure())["u_node"], u0)
