@@ -297,7 +297,7 @@ void Amg::make_fp32(hipStream_t s, Tracker &tr, const int32_t *) {
         ensure(lv.dinv32, lv.n, tr);
         launch_to_float(s, lv.n, lv.dinv.p, lv.dinv32.p);
         for (auto *v : {&lv.b32, &lv.xa32, &lv.xb32, &lv.r32}) ensure(*v, lv.n, tr);
-        lv.A32 = Sell<float>{lv.n, lv.A.ptr, lv.A.col, lv.val32.p, lv.dg32.p};
+        lv.A32 = Sell<float>{lv.n, lv.A.ptr, lv.A.col, lv.val32.p, lv.dg32.p, lv.A.col16, lv.A.cbase};
     }
     if (dense) {
         const int32_t nc = L[nlev - 1]->n;

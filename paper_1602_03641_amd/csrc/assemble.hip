@@ -441,6 +441,34 @@ __global__ __launch_bounds__(256) void sell_fill_kernel(int32_t n, int64_t nslic
     if (r < n) row_len[r] = len;
 }
 
+// 16-bit column offsets per slice (one wavefront per slice): when the columns
+// of the slice's rows lie within 65536 of their minimum, col16 = col - min and
+// cbase = min; otherwise cbase = -1 and the row loops read the 32-bit columns.
+// Rows past n (the tail of the last slice) are never evaluated and take offset 0.
+__global__ __launch_bounds__(64) void sell_pack_kernel(int32_t n, const int64_t *__restrict__ ptr,
+                                                       const int32_t *__restrict__ col, uint16_t *__restrict__ col16,
+                                                       int32_t *__restrict__ cbase) {
+    const int64_t sl = blockIdx.x;
+    const int lane = threadIdx.x;
+    const bool live = sl * 64 + lane < n;
+    const int64_t b0 = ptr[sl] + lane, b1 = ptr[sl + 1];
+    int32_t lo = INT32_MAX, hi = -1;
+    if (live)
+        for (int64_t q = b0; q < b1; q += 64) {
+            lo = min(lo, col[q]);
+            hi = max(hi, col[q]);
+        }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o, 64));
+        hi = max(hi, __shfl_xor(hi, o, 64));
+    }
+    const bool compact = hi >= 0 && (int64_t)hi - lo <= 65535;
+    if (compact)
+        for (int64_t q = b0; q < b1; q += 64) col16[q] = live ? (uint16_t)(col[q] - lo) : (uint16_t)0;
+    if (lane == 0) cbase[sl] = compact ? lo : -1;
+}
+
 // system positions of the node pairs of each eliminated group
 __global__ __launch_bounds__(64) void grp_pos_kernel(AsmArgs g, const int64_t *__restrict__ grp_poff,
                                                      int32_t *__restrict__ grp_pos) {
@@ -605,6 +633,14 @@ void launch_sell_fill(hipStream_t s, int32_t n, int64_t nslice, const int32_t *r
     if (nslice <= 0) return;
     hipLaunchKernelGGL(sell_fill_kernel, dim3(nblk(nslice * 64, 256)), dim3(256), 0, s, n, nslice, row_ptr, col,
                        sell_ptr, sell_col, row_len, diag_pos);
+    VAG_HIP(hipGetLastError());
+}
+
+void launch_sell_pack(hipStream_t s, int32_t n, const int64_t *ptr, const int32_t *col, uint16_t *col16,
+                      int32_t *cbase) {
+    const int64_t nslice = ((int64_t)n + 63) / 64;
+    if (nslice <= 0) return;
+    hipLaunchKernelGGL(sell_pack_kernel, dim3((unsigned)nslice), dim3(64), 0, s, n, ptr, col, col16, cbase);
     VAG_HIP(hipGetLastError());
 }
 

@@ -397,7 +397,7 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
                     for (int side = 0; side < 2; ++side)
                         if (S.frac_cell[2 * (size_t)f + side] >= 0) add_cell(row, S.frac_cell[2 * (size_t)f + side]);
                 }
-                std::sort(cols.begin(), cols.end());
+                // unsorted here: the renumbering below sorts every row once
                 out.insert(out.end(), cols.begin(), cols.end());
                 S.row_ptr[row + 1] = (int32_t)cols.size();
             }

@@ -145,7 +145,8 @@ struct vag_handle {
     // topology
     DBuf<double> xyz;
     DBuf<int32_t> hex8, cell_frac, frac_cell, frac_slot, frac_nodes, node_unk, node_cell_ptr, node_cell,
-        node_frac_ptr, node_frac, sell_col, row_len, diag_pos, unk_node, unk_face;
+        node_frac_ptr, node_frac, sell_col, row_len, diag_pos, unk_node, unk_face, sell_cbase;
+    DBuf<uint16_t> sell_col16;  // 16-bit column offsets of the slices that allow them
     DBuf<int64_t> sell_ptr;
     // eliminated fracture-face groups
     DBuf<int32_t> frac_unk, grp_ptr, grp_face, grp_nptr, grp_node, grp_pos, face_grp, face_loc;
@@ -197,7 +198,14 @@ struct vag_handle {
     double *h_scal = nullptr;
     hipEvent_t ev[8] = {};
 
-    Sell<double> Asell() const { return Sell<double>{S.nunk, sell_ptr.p, sell_col.p, A.p}; }
+    Sell<double> Asell() const { return with_col16(A.p); }
+    // the system pattern with the matrix values v (the assembled A or its scaled copy)
+    Sell<double> with_col16(const double *v) const {
+        Sell<double> m{S.nunk, sell_ptr.p, sell_col.p, v};
+        m.col16 = sell_col16.p;
+        m.cbase = sell_cbase.p;
+        return m;
+    }
     UpwindOp upwind() const {
         return UpwindOp{S.nc + S.nf + S.nn, slice_ptr.p, tmeta.p, tcol.p, tcol16.p, tbase.p, tval.p, tdiag.p};
     }
@@ -741,6 +749,9 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
             h->diag_pos.alloc(std::max(S.nunk, 1), h->tr);
             launch_sell_fill(h->stream, S.nunk, nslice, rp.p, cl.p, h->sell_ptr.p, h->sell_col.p, h->row_len.p,
                              h->diag_pos.p);
+            h->sell_col16.alloc(std::max<int64_t>(S.sell_ptr.back(), 1), h->tr);
+            h->sell_cbase.alloc(std::max<int64_t>(nslice, 1), h->tr);
+            launch_sell_pack(h->stream, S.nunk, h->sell_ptr.p, h->sell_col.p, h->sell_col16.p, h->sell_cbase.p);
             VAG_HIP(hipStreamSynchronize(h->stream));
         }
         h->Gb.alloc(std::max<int64_t>(S.grp_off.back(), 1), h->tr);
@@ -1011,8 +1022,7 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
             ensure(h->As, h->A.n, h->tr);
             launch_fill(s, (int64_t)h->A.n, 0.0, h->As.p);
             launch_diag_scaling(s, h->Asell(), h->diag_pos.p, h->dsc.p, h->As.p);
-            h->amg.setup(s, h->tr, Sell<double>{n, h->sell_ptr.p, h->sell_col.p, h->As.p}, (int64_t)h->A.n,
-                         amg_options(h->opt));
+            h->amg.setup(s, h->tr, h->with_col16(h->As.p), (int64_t)h->A.n, amg_options(h->opt));
         } else if (h->opt.precond == VAG_PC_AMG) {
             h->amg.setup(s, h->tr, h->Asell(), (int64_t)h->A.n, amg_options(h->opt));
             if (h->opt.precision == VAG_MIXED) h->amg.make_fp32(s, h->tr, nullptr);

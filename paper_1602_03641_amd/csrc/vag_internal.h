@@ -161,7 +161,16 @@ struct Sell {
     // optional diagonal held apart in FP64 (the stored diagonal entries are
     // then zero): the FP32 copies keep each row's FP64 row sum this way
     const double *dg = nullptr;
+    // optional 16-bit column offsets: where cbase[slice] >= 0 the slice's
+    // columns are cbase[slice] + col16[q] (the row loops read 2 bytes per
+    // entry instead of 4); other kernels keep reading col
+    const uint16_t *col16 = nullptr;
+    const int32_t *cbase = nullptr;
 };
+// col16 and cbase of a sliced-ELL pattern: a slice whose stored columns lie
+// within 65536 of their minimum gets cbase = that minimum, else -1
+void launch_sell_pack(hipStream_t s, int32_t n, const int64_t *ptr, const int32_t *col, uint16_t *col16,
+                      int32_t *cbase);
 
 struct PcgState {       // device-resident scalars of a Krylov solve
     double tol2, bnorm2, rr, pad;

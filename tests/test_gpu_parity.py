@@ -907,3 +907,16 @@ def test_wells_rejected_and_removed():
     h.set_wells([], [], [], [], [])
     h.solve_pressure()
     np.testing.assert_array_equal(vag.to_numpy(h.pressure())["u_node"], u0)
+
+
+def test_wide_planes_mix_column_widths():
+    """181 x 181 x 2 cells: a node plane holds 33 124 nodes, so the slices of
+    the middle plane span more than 65 536 columns and keep 32-bit columns
+    while those of the outer planes take 16-bit offsets; both paths in one
+    solve meet the parity bar."""
+    from paper_1602_03641_amd import vag
+    p = synth.random_problem((181, 181, 2), 36, n_patches=4, n_steps=10, ratios=(1e2,), jitter=0.1)
+    g = gpu_run(p, rtol=1e-11, max_iter=20000, precond=vag.VAG_PC_AMG)
+    o = oracle.run(p, rtol=1e-11)
+    assert g["info"]["status"] == 0
+    compare(p, g, o, p_tol=1e-8, c_tol=1e-9)
