@@ -10,7 +10,7 @@ namespace vag {
 
 // levels of at most this many rows run their V-cycle kernels with several
 // lanes per row
-constexpr int32_t kSmallRows = 65536;
+constexpr int32_t kSmallRows = 131072;
 
 // kernel launchers (amg.hip)
 void amg_launch_diag(hipStream_t s, Sell<double> A, double *diag, double *dinv);
