@@ -219,6 +219,7 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="cells per side (default: the workload's)")
     ap.add_argument("--keep-faces", action="store_true", help="fracture faces stay unknowns (no group elimination)")
     ap.add_argument("--amg-sweeps", type=int, default=0, help="l1-Jacobi sweeps on the coarse levels (0: default)")
+    ap.add_argument("--amg-coarse-size", type=int, default=0, help="stop coarsening below this many rows (0: default)")
     ap.add_argument("--amg-hops", type=int, default=0, help="aggregate radius: 2 (default) or 1")
     ap.add_argument("--wells", type=int, default=0,
                     help="perforate this many fracture faces (one rate injector, the rest at a fixed pressure)")
@@ -272,6 +273,8 @@ def main():
         opts["amg_sweeps"] = args.amg_sweeps
     if args.amg_hops > 0:
         opts["amg_aggregate_hops"] = args.amg_hops
+    if args.amg_coarse_size > 0:
+        opts["amg_coarse_size"] = args.amg_coarse_size
     if args.amg_kcycle >= 0:
         opts["amg_kcycle"] = args.amg_kcycle
     if args.amg_kind == "classical":
@@ -304,7 +307,7 @@ def main():
 
     # roofline of the dominant kernel: per-launch time from HIP events on the handle's stream
     levels = h.amg_levels() if args.precond == "amg" else None
-    ab = algorithmic_bytes(h, sinfo, tinfo, levels, args.precision, args.amg_sweeps if args.amg_sweeps > 0 else 2,
+    ab = algorithmic_bytes(h, sinfo, tinfo, levels, args.precision, args.amg_sweeps if args.amg_sweeps > 0 else vag.default_options().amg_sweeps,
                            kcycle_levels(vag, opts, args, levels))
     ms_spmv = h.benchmark_kernel(vag.VAG_KERNEL_SPMV, 100)
     ms_step = h.benchmark_kernel(vag.VAG_KERNEL_TRANSPORT_STEP, 100)
@@ -350,7 +353,7 @@ def main():
         el2 = time.perf_counter() - t1
         ms_prec2 = h2.benchmark_kernel(vag.VAG_KERNEL_PRECOND, 50)
         lv2 = h2.amg_levels()
-        ab2 = algorithmic_bytes(h2, s2, tinfo, lv2, alt, args.amg_sweeps if args.amg_sweeps > 0 else 2,
+        ab2 = algorithmic_bytes(h2, s2, tinfo, lv2, alt, args.amg_sweeps if args.amg_sweeps > 0 else vag.default_options().amg_sweeps,
                                 kcycle_levels(vag, opts, args, lv2))
         other = {"precision": alt, "value": round(args.steps / el2, 4), "iterations": s2["iterations"],
                  "rel_residual": s2["rel_residual"], "ms_solve": round(s2["ms_solve"], 3),

@@ -138,7 +138,7 @@ typedef struct {
     int amg_max_levels;
     double amg_theta;       /* strength threshold |a_ij| >= theta sqrt(a_ii a_jj) */
     int amg_sweeps;         /* l1-Jacobi sweeps before and after the coarse correction on
-                               the coarse levels (the finest level has one of each) */
+                               the coarse levels (the finest level has one of each); default 1 */
     int eliminate_frac_faces;  /* 1: eliminate fracture-face groups onto the nodes
                                   (fixed at vag_create); 0: faces stay unknowns */
     int amg_aggregate_hops; /* radius of the aggregates: roots form a distance-2 (2, the

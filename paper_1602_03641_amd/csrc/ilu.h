@@ -27,6 +27,10 @@ struct IluArgs {
     // rows[lptr[l] .. lptr[l+1]) (natural indices, a permutation of the block)
     const int32_t *lvb_f, *lptr_f, *rows_f;
     const int32_t *lvb_b, *lptr_b, *rows_b;
+    // per schedule slot, what the substitutions read in one 16-byte load:
+    // forward {row - block start, first entry, diagonal entry, 0},
+    // backward {row - block start, diagonal entry, end of the row, 0}
+    const int4 *slot_f, *slot_b;
     double *fval;           // factor values: L below the diagonal (unit diagonal implied), U from it
 };
 
@@ -51,6 +55,7 @@ private:
     int64_t nent_ = 0;
     IluArgs a_{};
     DBuf<int32_t> fptr_, fsrc_, fdiag_, rdev_, lvb_f_, lptr_f_, rows_f_, lvb_b_, lptr_b_, rows_b_;
+    DBuf<int4> slot_f_, slot_b_;
     DBuf<uint16_t> fcol_;
     DBuf<double> fval_;
 };

@@ -150,6 +150,12 @@ void Ilu::build(hipStream_t s, Tracker &tr, const Symbolic &S, int B) {
     }
     lptr_f.push_back(n);
     lptr_b.push_back(n);
+    std::vector<int4> slot_f(n), slot_b(n);
+    for (int32_t t = 0; t < n; ++t) {
+        const int32_t of = rows_f[t], ob = rows_b[t];
+        slot_f[t] = make_int4(of - (of / B) * B, fptr[of], fdiag[of], 0);
+        slot_b[t] = make_int4(ob - (ob / B) * B, fdiag[ob], fptr[ob + 1], 0);
+    }
     nlev_ = std::max(lvb_f[nblk], lvb_b[nblk]);
     put(s, tr, fptr_, fptr);
     put(s, tr, fcol_, fcol);
@@ -162,12 +168,15 @@ void Ilu::build(hipStream_t s, Tracker &tr, const Symbolic &S, int B) {
     put(s, tr, lvb_b_, lvb_b);
     put(s, tr, lptr_b_, lptr_b);
     put(s, tr, rows_b_, rows_b);
+    put(s, tr, slot_f_, slot_f);
+    put(s, tr, slot_b_, slot_b);
     fval_.alloc(std::max<int64_t>(nent, 1), tr);
     VAG_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
     nent_ = nent;
     B_ = B;
     a_ = IluArgs{n,          B,         nblk,      fptr_.p,   fcol_.p,   fsrc_.p,   fdiag_.p,  rdev_.p,
-                 lvb_f_.p,   lptr_f_.p, rows_f_.p, lvb_b_.p,  lptr_b_.p, rows_b_.p, fval_.p};
+                 lvb_f_.p,   lptr_f_.p, rows_f_.p, lvb_b_.p,  lptr_b_.p, rows_b_.p, slot_f_.p, slot_b_.p,
+                 fval_.p};
 }
 
 // ---------------------------------------------------------------------------
@@ -209,23 +218,27 @@ __global__ __launch_bounds__(kIluThreads) void ilu_solve_kernel(IluArgs g, const
     const int32_t b = blockIdx.x, r0 = b * g.B, r1 = min(g.n, r0 + g.B);
     const int tid = threadIdx.x;
     const double *__restrict__ v = g.fval;
-    // L y = r (unit diagonal)
+    const uint16_t *__restrict__ col = g.fcol;
+    // the block's right-hand side into LDS, all loads in flight at once
+    for (int32_t i = tid; i < r1 - r0; i += kIluThreads) y[i] = r[g.rdev[r0 + i]];
+    __syncthreads();
+    // L y = r (unit diagonal), in place
     for (int32_t l = g.lvb_f[b]; l < g.lvb_f[b + 1]; ++l) {
         for (int32_t t = g.lptr_f[l] + tid; t < g.lptr_f[l + 1]; t += kIluThreads) {
-            const int32_t o = g.rows_f[t], pd = g.fdiag[o];
-            double s = r[g.rdev[o]];
-            for (int32_t p = g.fptr[o]; p < pd; ++p) s -= v[p] * y[g.fcol[p]];
-            y[o - r0] = s;
+            const int4 m = g.slot_f[t];
+            double s = y[m.x];
+            for (int32_t p = m.y; p < m.z; ++p) s -= v[p] * y[col[p]];
+            y[m.x] = s;
         }
         __syncthreads();
     }
     // U z = y, in place
     for (int32_t l = g.lvb_b[b]; l < g.lvb_b[b + 1]; ++l) {
         for (int32_t t = g.lptr_b[l] + tid; t < g.lptr_b[l + 1]; t += kIluThreads) {
-            const int32_t o = g.rows_b[t], pd = g.fdiag[o], p1 = g.fptr[o + 1];
-            double s = y[o - r0];
-            for (int32_t p = pd + 1; p < p1; ++p) s -= v[p] * y[g.fcol[p]];
-            y[o - r0] = s / v[pd];
+            const int4 m = g.slot_b[t];
+            double s = y[m.x];
+            for (int32_t p = m.y + 1; p < m.z; ++p) s -= v[p] * y[col[p]];
+            y[m.x] = s / v[m.y];
         }
         __syncthreads();
     }

@@ -678,7 +678,7 @@ vag_status vag_default_options(vag_options *o) {
     o->amg_coarse_size = 500;
     o->amg_max_levels = 12;
     o->amg_theta = 0.02;
-    o->amg_sweeps = 2;
+    o->amg_sweeps = 1;
     o->amg_kcycle = 2;
     o->eliminate_frac_faces = 1;
     return VAG_OK;
