@@ -14,6 +14,10 @@
  *   - control volumes and porous volumes ................... §3.2.1
  *   - explicit upwind steps and the CFL bound .............. §3.2.2, eqs darcyfluxH,
  *                                                          eq_CFL; §4.3
+ *   - Krylov methods and preconditioners (CG, GMRES,
+ *     BiCGStab; aggregation and classical AMG, block
+ *     Jacobi ILU(0)) ....................................... §5.3
+ *   - Peaceman wells on fracture faces .................... §5.5
  *
  * Conventions
  *   - All entry points are extern "C", take plain pointers and sizes, and never
@@ -47,7 +51,7 @@ typedef enum {
     VAG_WARN_NOT_CONVERGED = 1,
     VAG_ERR_ARG = -1,          /* invalid argument or inconsistent input */
     VAG_ERR_MESH = -2,         /* invalid mesh: non-positive sub-tetrahedron, unknown fracture face */
-    VAG_ERR_UNSUPPORTED = -3,  /* valid request this build does not implement */
+    VAG_ERR_UNSUPPORTED = -3,  /* valid request that the library does not support */
     VAG_ERR_OOM = -4,          /* device allocation failed */
     VAG_ERR_HIP = -5,          /* HIP runtime error */
     VAG_ERR_STATE = -6,        /* call out of order (e.g. transport before a pressure solve) */
