@@ -920,3 +920,31 @@ def test_wide_planes_mix_column_widths():
     o = oracle.run(p, rtol=1e-11)
     assert g["info"]["status"] == 0
     compare(p, g, o, p_tol=1e-8, c_tol=1e-9)
+
+
+def test_switching_solvers_on_one_handle():
+    """One handle through aggregation AMG, classical AMG, BiCGStab with
+    block-Jacobi ILU(0), the FP32 hierarchy and back: every solve reaches the
+    same solution, and the first configuration again gives it bitwise (no
+    state of another solver leaks into a solve)."""
+    from paper_1602_03641_amd import vag
+    _torch()
+    p = synth.random_problem((12, 10, 9), 37, n_patches=6, n_steps=10)
+    h = vag.Handle(p, rtol=1e-12, max_iter=20000, precond=vag.VAG_PC_AMG)
+
+    def solve():
+        info = h.solve_pressure()
+        h.transport(n_steps=p.n_steps)
+        assert info["status"] in (0, 1) and info["rel_residual"] <= 1e-11
+        return {**vag.to_numpy(h.pressure()), **vag.to_numpy(h.concentration())}
+
+    ref = solve()
+    steps = [dict(amg_kind=1), dict(precond=vag.VAG_PC_BJILU0, krylov=vag.VAG_BICGSTAB, amg_kind=0),
+             dict(precond=vag.VAG_PC_AMG, krylov=vag.VAG_CG, precision=vag.VAG_MIXED),
+             dict(krylov=vag.VAG_GMRES, precision=vag.VAG_FP64), dict(krylov=vag.VAG_CG)]
+    for kw in steps:
+        h.set_options(**kw)
+        g = solve()
+        assert rel_l2(g["u_node"], ref["u_node"]) <= 1e-9, kw
+    for k in ("u_node", "u_frac", "c_cell", "c_node"):
+        np.testing.assert_array_equal(g[k], ref[k])
