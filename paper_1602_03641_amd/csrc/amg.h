@@ -104,10 +104,9 @@ void cl_launch_interp_fill(hipStream_t s, Sell<double> A, const uint8_t *sf, con
 void cl_launch_transpose(hipStream_t s, Sell<double> A, int32_t nc, const int32_t *cfine, const int8_t *st,
                          const int32_t *pptr, const int32_t *pcol, const double *pval, int32_t *rlen,
                          const int32_t *rptr, int32_t *rcol, double *rval);
-// table sizes of the rows of A P and R (A P) from their contribution counts >> shrink
-void cl_launch_ap_cap(hipStream_t s, Sell<double> A, const int32_t *pptr, int shrink, int32_t *cap);
+void cl_launch_ap_cap(hipStream_t s, Sell<double> A, const int32_t *pptr, int32_t *cap);
 void cl_launch_rap_cap(hipStream_t s, int32_t nc, const int32_t *rptr, const int32_t *rcol, const int32_t *apptr,
-                       int shrink, int32_t *cap);
+                       int32_t *cap);
 void cl_launch_chunk_sums(hipStream_t s, int32_t n, const int32_t *cap, int64_t *sums);
 // rows [r0, r1) of X Y (X: AX in sliced ELL, or CSR xptr/xcol/xval); tables at
 // hoff[i - r0]; count (rowlen) or fill (CSR optr, or sliced ELL when sell_out)

@@ -236,22 +236,17 @@ __global__ __launch_bounds__(kCT) void cl_transpose_kernel(Sell<double> A, int32
     }
 }
 
-// Table sizes of a product row: the power of two >= 2 x (number of
-// contributions >> shrink), at least 8, at most kClCapMax.  Rows hold far
-// fewer distinct columns than contributions, so the first attempt sizes the
-// tables by a quarter of the count (shrink 2: the tables of a chunk stay in
-// the caches); a row with more distinct columns than its table holds sets
-// *overflow and the product is redone with shrink 0.
-__device__ inline int32_t cl_cap(int64_t bound, int shrink) {
-    const int64_t want = 2 * (bound >> shrink) + 1;
+// Table sizes of a product row: cap = the power of two >= 2 x (number of
+// contributions), at least 8, at most kClCapMax (a row with more distinct
+// columns than its table holds sets *overflow).
+__device__ inline int32_t cl_cap(int64_t bound) {
     int64_t c = 8;
-    while (c < want && c < kClCapMax) c <<= 1;
+    while (c < 2 * bound && c < kClCapMax) c <<= 1;
     return (int32_t)c;
 }
 
 // contributions of row i of A P: sum over A's nonzero entries of |P row|
-__global__ __launch_bounds__(kCT) void cl_ap_cap_kernel(Sell<double> A, const int32_t *pptr, int shrink,
-                                                        int32_t *cap) {
+__global__ __launch_bounds__(kCT) void cl_ap_cap_kernel(Sell<double> A, const int32_t *pptr, int32_t *cap) {
     CL_GS(i, A.n) {
         const int64_t b = sell_at(A.ptr, i);
         const int w = sell_w(A.ptr, i);
@@ -260,17 +255,17 @@ __global__ __launch_bounds__(kCT) void cl_ap_cap_kernel(Sell<double> A, const in
             const int64_t p = b + (int64_t)j * 64;
             if (A.val[p] != 0.0) s += pptr[A.col[p] + 1] - pptr[A.col[p]];
         }
-        cap[i] = cl_cap(s, shrink);
+        cap[i] = cl_cap(s);
     }
 }
 
 // contributions of row c of R (A P)
 __global__ __launch_bounds__(kCT) void cl_rap_cap_kernel(int32_t nc, const int32_t *rptr, const int32_t *rcol,
-                                                         const int32_t *apptr, int shrink, int32_t *cap) {
+                                                         const int32_t *apptr, int32_t *cap) {
     CL_GS(c, nc) {
         int64_t s = 0;
         for (int32_t q = rptr[c]; q < rptr[c + 1]; ++q) s += apptr[rcol[q] + 1] - apptr[rcol[q]];
-        cap[c] = cl_cap(s, shrink);
+        cap[c] = cl_cap(s);
     }
 }
 
@@ -445,12 +440,12 @@ void cl_launch_transpose(hipStream_t s, Sell<double> A, int32_t nc, const int32_
     else
         CLAUNCH(cl_transpose_kernel<true>, cgrid(nc), A, nc, cfine, st, pptr, pcol, pval, rlen, rptr, rcol, rval);
 }
-void cl_launch_ap_cap(hipStream_t s, Sell<double> A, const int32_t *pptr, int shrink, int32_t *cap) {
-    if (A.n > 0) CLAUNCH(cl_ap_cap_kernel, cgrid(A.n), A, pptr, shrink, cap);
+void cl_launch_ap_cap(hipStream_t s, Sell<double> A, const int32_t *pptr, int32_t *cap) {
+    if (A.n > 0) CLAUNCH(cl_ap_cap_kernel, cgrid(A.n), A, pptr, cap);
 }
 void cl_launch_rap_cap(hipStream_t s, int32_t nc, const int32_t *rptr, const int32_t *rcol, const int32_t *apptr,
-                       int shrink, int32_t *cap) {
-    if (nc > 0) CLAUNCH(cl_rap_cap_kernel, cgrid(nc), nc, rptr, rcol, apptr, shrink, cap);
+                       int32_t *cap) {
+    if (nc > 0) CLAUNCH(cl_rap_cap_kernel, cgrid(nc), nc, rptr, rcol, apptr, cap);
 }
 void cl_launch_chunk_sums(hipStream_t s, int32_t n, const int32_t *cap, int64_t *sums) {
     if (n > 0) CLAUNCH(cl_chunk_sum_kernel, (n + kClChunk - 1) / kClChunk, n, cap, sums);

@@ -235,16 +235,10 @@ void Amg::setup_classical(hipStream_t s, Tracker &tr, int64_t stored0) {
                             lv.rcol.p, lv.rval.p);
         // A P (CSR)
         ensure(ccap_, (size_t)std::max(n, nc) + 1, tr);
-        // tables sized by a quarter of the contributions first, by all of them if a row overflows
-        cl_launch_ap_cap(s, lv.A, lv.pptr.p, 2, ccap_.p);
-        bool ok = product(s, tr, n, &lv.A, nullptr, nullptr, nullptr, lv.pptr.p, lv.pcol.p, lv.pval.p, false,
-                          cplen_.p, nullptr, false, nullptr, nullptr);
-        if (!ok) {
-            cl_launch_ap_cap(s, lv.A, lv.pptr.p, 0, ccap_.p);
-            ok = product(s, tr, n, &lv.A, nullptr, nullptr, nullptr, lv.pptr.p, lv.pcol.p, lv.pval.p, false,
-                         cplen_.p, nullptr, false, nullptr, nullptr);
-        }
-        if (!ok) break;  // a row of A P is too wide for its table: stop coarsening here
+        cl_launch_ap_cap(s, lv.A, lv.pptr.p, ccap_.p);
+        if (!product(s, tr, n, &lv.A, nullptr, nullptr, nullptr, lv.pptr.p, lv.pcol.p, lv.pval.p, false, cplen_.p,
+                     nullptr, false, nullptr, nullptr))
+            break;  // a row of A P is too wide for its table: stop coarsening here
         cl_launch_chunk_sums(s, n, cplen_.p, csums_.p);
         {
             const int32_t nch = (n + kClChunk - 1) / kClChunk;
@@ -271,15 +265,10 @@ void Amg::setup_classical(hipStream_t s, Tracker &tr, int64_t stored0) {
         AmgLevel &cv = *L[l + 1];
         const int32_t ns = (nc + 63) / 64;
         ensure(cv.ptr, (size_t)ns + 1, tr);
-        cl_launch_rap_cap(s, nc, lv.rptr.p, lv.rcol.p, captr_.p, 2, ccap_.p);
-        ok = product(s, tr, nc, nullptr, lv.rptr.p, lv.rcol.p, lv.rval.p, captr_.p, capcol_.p, capval_.p, false,
-                     crlen_.p, nullptr, true, nullptr, nullptr);
-        if (!ok) {
-            cl_launch_rap_cap(s, nc, lv.rptr.p, lv.rcol.p, captr_.p, 0, ccap_.p);
-            ok = product(s, tr, nc, nullptr, lv.rptr.p, lv.rcol.p, lv.rval.p, captr_.p, capcol_.p, capval_.p, false,
-                         crlen_.p, nullptr, true, nullptr, nullptr);
-        }
-        if (!ok) break;
+        cl_launch_rap_cap(s, nc, lv.rptr.p, lv.rcol.p, captr_.p, ccap_.p);
+        if (!product(s, tr, nc, nullptr, lv.rptr.p, lv.rcol.p, lv.rval.p, captr_.p, capcol_.p, capval_.p, false,
+                     crlen_.p, nullptr, true, nullptr, nullptr))
+            break;
         amg_launch_slices(s, nc, crlen_.p, width_.p, scnt_.p, cv.ptr.p, level_nnz.p + l + 1);
         int64_t stored = 0;
         VAG_HIP(hipMemcpyAsync(&stored, cv.ptr.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
