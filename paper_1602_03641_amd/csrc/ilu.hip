@@ -12,6 +12,7 @@
 #include <exception>
 #include <thread>
 
+#include "host_parallel.h"
 #include "ilu.h"
 
 namespace vag {
@@ -19,30 +20,6 @@ namespace vag {
 namespace {
 
 constexpr int kIluThreads = 64;
-
-// f(begin, end) over [0, n) in up to 16 host threads
-template <class F>
-void host_parallel(int64_t n, F &&f) {
-    const int64_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    const int T = (int)std::max<int64_t>(1, std::min<int64_t>(hw, n / 4096));
-    if (T == 1) {
-        f((int64_t)0, n);
-        return;
-    }
-    std::vector<std::thread> th;
-    std::vector<std::exception_ptr> err(T);
-    for (int t = 0; t < T; ++t)
-        th.emplace_back([&, t] {
-            try {
-                f(n * t / T, n * (t + 1) / T);
-            } catch (...) {
-                err[t] = std::current_exception();
-            }
-        });
-    for (auto &x : th) x.join();
-    for (auto &e : err)
-        if (e) std::rethrow_exception(e);
-}
 
 template <class T>
 void put(hipStream_t s, Tracker &tr, DBuf<T> &d, const std::vector<T> &v) {
@@ -91,7 +68,7 @@ void Ilu::build(hipStream_t s, Tracker &tr, const Symbolic &S, int B) {
     const int32_t nblk = (n + B - 1) / B;
     // in-block entries of each natural row, by local column
     std::vector<int32_t> cnt(n), fptr((size_t)n + 1, 0);
-    host_parallel(n, [&](int64_t o0, int64_t o1) {
+    parallel_chunks(n, [&](int, int64_t o0, int64_t o1) {
         for (int64_t o = o0; o < o1; ++o) {
             const int32_t r = S.sys_new[o], b0 = (int32_t)(o / B) * B;
             int32_t c = 0;
@@ -101,13 +78,13 @@ void Ilu::build(hipStream_t s, Tracker &tr, const Symbolic &S, int B) {
             }
             cnt[o] = c;
         }
-    });
+    }, 4096);
     for (int32_t o = 0; o < n; ++o) fptr[o + 1] = fptr[o] + cnt[o];
     const int64_t nent = fptr[n];
     std::vector<uint16_t> fcol(nent);
     std::vector<int32_t> fsrc(nent), fdiag(n), rdev(n);
     std::atomic<bool> nodiag{false};
-    host_parallel(n, [&](int64_t o0, int64_t o1) {
+    parallel_chunks(n, [&](int, int64_t o0, int64_t o1) {
         std::vector<std::pair<int32_t, int32_t>> e;
         for (int64_t o = o0; o < o1; ++o) {
             const int32_t r = S.sys_new[o], b0 = (int32_t)(o / B) * B;
@@ -129,18 +106,18 @@ void Ilu::build(hipStream_t s, Tracker &tr, const Symbolic &S, int B) {
             fdiag[o] = d;
             rdev[o] = r;
         }
-    });
+    }, 4096);
     if (nodiag.load()) throw Error(VAG_ERR_ARG, "internal: a system row has no diagonal entry");
     // level schedules, block by block
     std::vector<int32_t> lev(n), rows_f(n), rows_b(n);
     std::vector<std::vector<int32_t>> lf(nblk), lb(nblk);
-    host_parallel(nblk, [&](int64_t b0, int64_t b1) {
+    parallel_chunks(nblk, [&](int, int64_t b0, int64_t b1) {
         for (int64_t b = b0; b < b1; ++b) {
             const int32_t r0 = (int32_t)b * B, r1 = std::min<int32_t>(n, r0 + B);
             block_levels(fptr, fcol, fdiag, r0, r1, true, lev, rows_f, lf[b]);
             block_levels(fptr, fcol, fdiag, r0, r1, false, lev, rows_b, lb[b]);
         }
-    });
+    }, 8);
     std::vector<int32_t> lvb_f(nblk + 1, 0), lvb_b(nblk + 1, 0), lptr_f, lptr_b;
     for (int32_t b = 0; b < nblk; ++b) {
         lvb_f[b + 1] = lvb_f[b] + (int32_t)lf[b].size();

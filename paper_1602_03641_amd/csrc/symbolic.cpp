@@ -21,42 +21,12 @@
 #include <thread>
 #include <unordered_map>
 
+#include "host_parallel.h"
 #include "vag_internal.h"
 
 namespace vag {
 
 namespace {
-
-// Runs f(t, begin, end) over [0, n) split into contiguous chunks, one per
-// thread (at most 16, at least 32768 items each); the first exception thrown
-// by a chunk is rethrown.
-template <class F>
-void parallel_chunks(int64_t n, F &&f) {
-    const int64_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    const int T = (int)std::max<int64_t>(1, std::min<int64_t>(hw, n / 32768));
-    if (T == 1) {
-        f(0, (int64_t)0, n);
-        return;
-    }
-    std::vector<std::thread> th;
-    std::vector<std::exception_ptr> err(T);
-    for (int t = 0; t < T; ++t)
-        th.emplace_back([&, t] {
-            try {
-                f(t, n * t / T, n * (t + 1) / T);
-            } catch (...) {
-                err[t] = std::current_exception();
-            }
-        });
-    for (auto &x : th) x.join();
-    for (auto &e : err)
-        if (e) std::rethrow_exception(e);
-}
-
-int chunk_count(int64_t n) {
-    const int64_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    return (int)std::max<int64_t>(1, std::min<int64_t>(hw, n / 32768));
-}
 
 struct Key4 {
     std::array<int32_t, 4> v;
