@@ -433,3 +433,61 @@ def add_wells(prob, seed, n_inj=1, n_prod=2, q=0.5, pw=0.3, wi_range=(0.05, 0.2)
     prob.wells = dict(face=face, wi=wi, pw=np.where(np.arange(n) < n_inj, 0.0, pw),
                       q=np.where(np.arange(n) < n_inj, q, 0.0), cinj=np.where(np.arange(n) < n_inj, 1.0, 0.0))
     return prob
+
+
+def simplex_cells(dims, kind):
+    """Cells of a structured (nx, ny, nz) grid split into tetrahedra (kind
+    "tet": 6 per hexahedron around its 0-6 diagonal, conforming) or prisms
+    (kind "prism": 2 per hexahedron, split along the 0-2 diagonal of the
+    bottom square), as node tuples in VTK order with positive orientation."""
+    nx, ny, nz = dims
+    cells = []
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                h = [node_index(dims, i, j, k), node_index(dims, i + 1, j, k), node_index(dims, i + 1, j + 1, k),
+                     node_index(dims, i, j + 1, k), node_index(dims, i, j, k + 1), node_index(dims, i + 1, j, k + 1),
+                     node_index(dims, i + 1, j + 1, k + 1), node_index(dims, i, j + 1, k + 1)]
+                if kind == "prism":
+                    cells.append((h[0], h[1], h[2], h[4], h[5], h[6]))
+                    cells.append((h[0], h[2], h[3], h[4], h[6], h[7]))
+                else:
+                    for a, b in ((1, 2), (2, 3), (3, 7), (7, 4), (4, 5), (5, 1)):
+                        cells.append((h[0], h[a], h[b], h[6]))
+    return cells
+
+
+def orient_tets(xyz, cells):
+    """Tetrahedra reordered (two nodes swapped) where needed so that the
+    volume det[p1 - p0, p2 - p0, p3 - p0] / 6 is positive."""
+    out = []
+    for c in cells:
+        if len(c) == 4:
+            p = xyz[list(c)]
+            if np.linalg.det(np.array([p[1] - p[0], p[2] - p[0], p[3] - p[0]])) < 0:
+                c = (c[0], c[2], c[1], c[3])
+        out.append(tuple(c))
+    return out
+
+
+def plane_x_faces(dims, cells, i0):
+    """The cell faces lying on the grid plane x = i0 (triangles for
+    tetrahedra, quadrangles for prisms), each once, nodes in cyclic order."""
+    on = lambda s: s % (dims[0] + 1) == i0  # noqa: E731
+    seen, faces = set(), []
+    for c in cells:
+        pts = [s for s in c if on(s)]
+        want = 3 if len(c) == 4 else 4
+        if len(pts) != want:
+            continue
+        key = tuple(sorted(pts))
+        if key in seen:
+            continue
+        seen.add(key)
+        if want == 4:  # cyclic order of the quadrangle: sort by (z, then y) around its centre
+            js = [(s // (dims[0] + 1)) % (dims[1] + 1) for s in pts]
+            ks = [s // ((dims[0] + 1) * (dims[1] + 1)) for s in pts]
+            cj, ck = np.mean(js), np.mean(ks)
+            pts = [p for _, p in sorted(zip([np.arctan2(k - ck, j - cj) for j, k in zip(js, ks)], pts))]
+        faces.append(tuple(pts))
+    return faces
