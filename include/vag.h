@@ -152,7 +152,7 @@ typedef struct {
                                two flexible CG steps preconditioned by the V-cycle below, the
                                outer CG then in its flexible form (CG only; 0: V-cycles;
                                default 2) */
-    int ilu_block_rows;     /* VAG_PC_BJILU0: unknowns per block, 1..8192 (0: 1024); blocks are
+    int ilu_block_rows;     /* VAG_PC_BJILU0: unknowns per block, 1..8192 (0: 128); blocks are
                                runs of the natural unknown order (vag_get_system's) */
     int amg_kind;           /* VAG_PC_AMG: 0 aggregation (default); 1 classical (strength
                                -a_ij >= amg_strong_theta max_k -a_ik, PMIS coarse points, direct

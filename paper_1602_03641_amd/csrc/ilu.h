@@ -13,7 +13,7 @@
 namespace vag {
 
 constexpr int kIluMaxBlock = 8192;  // rows per block: the solve keeps a block's vector in LDS
-constexpr int kIluDefaultBlock = 1024;
+constexpr int kIluDefaultBlock = 128;
 
 struct IluArgs {
     int32_t n, B, nblk;
