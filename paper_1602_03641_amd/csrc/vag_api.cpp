@@ -204,6 +204,7 @@ struct vag_handle {
         Sell<double> m{S.nunk, sell_ptr.p, sell_col.p, v};
         m.col16 = sell_col16.p;
         m.cbase = sell_cbase.p;
+        m.nt = stream_matrix((int64_t)A.n, sizeof(double));
         return m;
     }
     UpwindOp upwind() const {

@@ -13,6 +13,19 @@
 
 namespace vag {
 
+// Loads of the entries of a large matrix, read once per pass: marked
+// non-temporal so that they do not push out of the caches the vector entries
+// that neighbouring rows gather again.  A matrix that fits the last-level
+// cache (256 MB) together with its vectors is read with ordinary loads, since
+// it is read again by the next pass.
+constexpr int64_t kStreamBytes = int64_t(128) << 20;
+inline bool stream_matrix(int64_t stored, int value_bytes) { return stored * (value_bytes + 4) > kStreamBytes; }
+template <bool NT, class T>
+__device__ __forceinline__ T ld_matrix(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 // ---------------------------------------------------------------------------
 // errors: thrown inside the library, turned into a vag_status at the ABI
 // ---------------------------------------------------------------------------
@@ -166,6 +179,8 @@ struct Sell {
     // entry instead of 4); other kernels keep reading col
     const uint16_t *col16 = nullptr;
     const int32_t *cbase = nullptr;
+    // the row loops read val and the columns with non-temporal loads
+    bool nt = false;
 };
 // col16 and cbase of a sliced-ELL pattern: a slice whose stored columns lie
 // within 65536 of their minimum gets cbase = that minimum, else -1
