@@ -6,6 +6,7 @@ arithmetic, so both the CPU oracle and the GPU library may consume it.
 """
 from .meshes import (  # noqa: F401
     Problem,
+    node_index,
     structured_hex,
     plane_faces,
     config1,

@@ -312,6 +312,88 @@ def test_cfl_uniform_flow_cube():
     assert math.isinf(dt3[1])
 
 
+def _config1_grid():
+    """Config 1 (n = 10, fracture plane i = 5) with the grid indices of its
+    nodes and cells, counted from the logical grid alone."""
+    p = synth.config1()
+    n = 10
+    k, j, i = np.meshgrid(np.arange(n + 1), np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    node_ijk = np.stack([i.ravel(), j.ravel(), k.ravel()], 1)
+    assert (synth.node_index((n, n, n), *node_ijk.T) == np.arange(p.n_nodes)).all()
+    k, j, i = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    cell_ijk = np.stack([i.ravel(), j.ravel(), k.ravel()], 1)
+    return p, n, node_ijk, cell_ijk
+
+
+def test_config1_porous_volumes_closed_form():
+    """Control volumes of config 1, one by one (§3.2.1, volume fractions of
+    the single-rock-type reading: alpha_{K,s} = 1/16 for the free nodes of K
+    that are not fracture nodes, alpha_{sigma,s} = 1/8 for the free nodes of
+    sigma).  With h = 1/10, phi_m = phi_f = 1, d_f = 0.01:
+
+    * a node on the fracture plane takes its porous volume from the fracture
+      faces only, 1/8 of d_f h^2 from each of the m faces around it (4 inside
+      the plane, 2 on a wall edge, 1 at a corner): m d_f h^2 / 8;
+    * any other free node takes 1/16 of h^3 from each of its c cells (8, 4 on
+      a wall, 2 on a wall edge): c h^3 / 16;
+    * a fracture face keeps (1 - 4/8) of its volume: d_f h^2 / 2;
+    * a cell keeps h^3 (1 - q/16) with q its free nodes off the fracture
+      plane: 8 inside (h^3/2), 4 beside the fracture or a Dirichlet plane
+      (3 h^3 / 4);
+    * Dirichlet nodes hold none.
+    Fracture nodes taking a matrix share, or another alpha_{sigma,s}, change
+    these values."""
+    p, n, nijk, cijk = _config1_grid()
+    h, df = 1.0 / n, 0.01
+    phi = oracle.porous_volumes(p)
+    dirichlet = (nijk[:, 0] == 0) | (nijk[:, 0] == n)
+    assert (dirichlet == (p.dirichlet == 1)).all()
+    on_wall = lambda a: (a == 0) | (a == n)  # noqa: E731
+    per_axis = lambda a: np.where(on_wall(a), 1, 2)  # noqa: E731
+    m_faces = per_axis(nijk[:, 1]) * per_axis(nijk[:, 2])
+    n_cells = m_faces * per_axis(nijk[:, 0])
+    frac_node = nijk[:, 0] == n // 2
+    expect_node = np.where(frac_node, m_faces * df * h * h / 8, n_cells * h ** 3 / 16)
+    expect_node[dirichlet] = 0.0
+    np.testing.assert_allclose(phi["phi_node"], expect_node, rtol=1e-12, atol=0)
+    beside = (cijk[:, 0] == n // 2 - 1) | (cijk[:, 0] == n // 2) | (cijk[:, 0] == 0) | (cijk[:, 0] == n - 1)
+    expect_cell = np.where(beside, 0.75, 0.5) * h ** 3
+    np.testing.assert_allclose(phi["phi_cell"], expect_cell, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(phi["phi_frac"], df * h * h / 2, rtol=1e-12, atol=0)
+
+
+def test_config1_cfl_closed_form():
+    """eq eq_CFL on config 1, where u = 1 - x is the exact discrete solution.
+
+    With the cube forms (node block (lambda h/2) I, fracture face diagonal
+    4 lambda h/3 and coupling -lambda h/6 to its nodes, lambda = 1) and
+    u_K - u_s = -+h/2 across a cell:
+    * cells: an interior cell sends h^2/4 through each of its 4 downstream
+      nodes; its volume h^3/2 gives dt_M = h/2.  The cells beside the plane
+      (volume 3h^3/4, outflow h^2) give 3h/4.
+    * fracture faces: F_{sigma,s} = 0, the upstream cell K sends
+      F_{K,sigma} = (4/3 - 4/6) h (h/2) = h^2/3 into sigma, and the
+      downstream cell L receives (-F_{L,sigma})^+ = h^2/3 from it: the only
+      outflow of sigma.  dt_F = (d_f h^2/2) / (h^2/3) = 3 d_f / 2.
+    * nodes: a fracture node sends (h/2 - h/6)(h/2) = h^2/6 into each of its
+      4 downstream cells (2 h^2/3 in total) from d_f h^2/2: 3 d_f / 4; the
+      others h^2 from h^3/2: h/2.
+    Dropping the cell-to-face outflow term leaves sigma without outflow
+    (dt_F infinite)."""
+    p, n, _, _ = _config1_grid()
+    h, df = 1.0 / n, 0.01
+    o = oracle.solve_darcy(p, rtol=1e-14)
+    phi = oracle.porous_volumes(p)
+    dt3 = oracle.cfl_bounds(p, o, phi)
+    assert dt3[0] == pytest.approx(h / 2, rel=1e-9)
+    assert dt3[1] == pytest.approx(1.5 * df, rel=1e-9)
+    assert dt3[2] == pytest.approx(0.75 * df, rel=1e-9)
+    cf, fc, _ = oracle.topology(p)
+    assert (fc >= 0).all()
+    np.testing.assert_allclose(o["F_cell_frac"][:, 0], h * h / 3, rtol=1e-9)
+    np.testing.assert_allclose(o["F_cell_frac"][:, 1], -h * h / 3, rtol=1e-9)
+
+
 def _dirichlet_outflow(p, o, c):
     """sum over Dirichlet nodes s of sum_K H_{K,s} + sum_sigma H_{sigma,s}."""
     cf, fc, _ = oracle.topology(p)
