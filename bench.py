@@ -1,11 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark: Darcy + transport solves per second on one MI355X.
 
-One step = one full pass of the hot path over the resident 64^3 workload
-(four clipped fractures, contrast 1e4): per-cell VAG matrices, cell
-elimination and assembly, preconditioned CG to rtol 1e-8, cell recovery and
-fluxes, porous volumes, CFL step and 200 explicit upwind steps.  The mesh's
-symbolic phase (topology only) is done once before timing and reported apart.
+One step = one full pass of the hot path over the resident workload:
+per-cell VAG matrices, cell elimination and assembly, AMG setup,
+preconditioned CG to rtol 1e-8, cell recovery and fluxes, porous volumes,
+CFL step and the workload's explicit upwind steps.  The mesh's symbolic phase
+(topology only) is done once before timing and reported apart.
+
+The headline workload is the largest single-GPU instance: 192^3 jittered
+hexahedra (7.1 M cells), lognormal anisotropic permeability, 200 face patches
+at contrast 1e6, FP32 AMG hierarchy inside FP64 CG to rtol 1e-8, then 1000
+upwind steps.  The 64^3 four-fracture workload (both precisions, difference
+to the oracle) and the serving stream follow as extra keys.
 
 Prints one JSON line (see the field list at the end of main()).
 """
@@ -68,8 +74,9 @@ def kcycle_levels(vag, opts, args, levels):
 
 
 def cpu_baseline(prob, budget_s=30.0):
-    """The oracle, as it stands, on one full solve of the same workload;
-    returns the baseline record and the oracle's result."""
+    """The oracle, as it stands, on one full solve of the same workload (a
+    size it finishes in seconds); returns the baseline record and the
+    oracle's result."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
@@ -78,6 +85,53 @@ def cpu_baseline(prob, budget_s=30.0):
     return {"value": 1.0 / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
             "sample": f"one full solve of {prob.name} (Jacobi-PCG to rtol {prob.rtol:g} + {prob.n_steps} steps), "
                       f"{dt:.2f} s"}, res
+
+
+def cpu_baseline_sampled(prob, vag, h, dt, n_steps_sample=20, cell_stride=64):
+    """The oracle, as it stands, on a bounded sample of a workload too large
+    for it to solve in minutes (its global assembly sorts one triplet per
+    local-matrix entry, and Jacobi-PCG needs thousands of iterations there):
+
+    * n_steps_sample of the workload's upwind steps on the full mesh, fed the
+      GPU's fluxes and porous volumes (orc_transport, one thread), scaled to
+      the workload's step count;
+    * the local VAG matrices and porous volumes of every cell_stride-th cell
+      (orc_porous_volumes on those cells, one thread), scaled to all cells.
+
+    The value is one solve's worth of these phases; the global assembly and
+    the Jacobi-PCG solve are left out, so it bounds the oracle's rate from
+    above."""
+    import oracle
+    import synth
+    flux = {k: v.cpu().numpy() for k, v in h.fluxes().items()}
+    phi = {k: v.cpu().numpy() for k, v in h.porous_volumes().items()}
+    if prob.wells:
+        flux["well_rate"] = h.well_rates()
+    op = oracle.OracleProblem(prob)
+    log(f"oracle baseline: {n_steps_sample} upwind steps on the full mesh")
+    t0 = time.perf_counter()
+    oracle.transport(op, flux, phi, dt, n_steps_sample)
+    t_steps = time.perf_counter() - t0
+    log(f"oracle baseline: {t_steps:.2f} s; local matrices of every {cell_stride}th cell")
+    cells = np.arange(0, prob.n_cells, cell_stride)
+    used, inv = np.unique(prob.hex8[cells], return_inverse=True)
+    sub = synth.Problem(
+        name=f"{prob.name}-cells/{cell_stride}", dims=prob.dims, xyz=prob.xyz[used],
+        hex8=inv.reshape(-1, 8).astype(np.int32), frac_nodes=np.zeros((0, 4), np.int32),
+        frac_width=np.zeros(0), frac_perm=np.zeros(0), frac_poro=np.zeros(0), perm=prob.perm[cells],
+        poro=prob.poro[cells], mu=prob.mu, dirichlet=prob.dirichlet[used], p_bar=prob.p_bar[used],
+        c_bar=prob.c_bar[used])
+    t0 = time.perf_counter()
+    oracle.porous_volumes(sub)
+    t_cells = time.perf_counter() - t0
+    per_solve = t_steps * prob.n_steps / n_steps_sample + t_cells * prob.n_cells / len(cells)
+    log(f"oracle baseline: {t_cells:.2f} s; {per_solve:.1f} s per solve")
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{prob.name}: {n_steps_sample} of its {prob.n_steps} upwind steps on the full mesh with the "
+                       f"GPU's fluxes ({t_steps:.2f} s) and the local matrices + porous volumes of "
+                       f"{len(cells)} of its {prob.n_cells} cells ({t_cells:.2f} s), scaled to one solve "
+                       f"({per_solve:.1f} s); the oracle's global assembly and Jacobi-PCG solve are left out, "
+                       "so the value is an upper bound of its rate; one thread (these oracle loops are serial)")}
 
 
 def results(vag, h):
@@ -192,6 +246,23 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+PROFILE_NAME = {"config2": "config2_64cubed", "config3": "config3_128cubed", "config5": "config5_192cubed"}
+DEFAULTS = {"config2": (64, "fp64", "cg"), "config3": (128, "mixed", "cg"), "config5": (192, "mixed", "cg")}
+
+
+def profiled_mean_us(kernel, workload):
+    """Mean duration of `kernel` in the committed rocprofv3 kernel statistics
+    of this workload (None where none was taken)."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_kernel_stats.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        cells = [c.strip().strip("`") for c in line.split("|")]
+        if len(cells) > 5 and cells[1] == f"vag::{kernel}":
+            return float(cells[4])
+    return None
+
+
 def describe(args, prob):
     n = args.n
     if args.workload == "config2":
@@ -204,16 +275,136 @@ def describe(args, prob):
             f"{args.krylov.upper()} rtol {prob.rtol:g}, {prob.n_steps} upwind steps")
 
 
+def dtype_of(precision):
+    """The arithmetic the path computes in."""
+    return {"fp64": "f64",
+            "mixed": "f64 (f32 AMG hierarchy values)",
+            "mixed_ir": "f64 refinement around f32 inner Krylov and f32 AMG hierarchy"}[precision]
+
+
+def solver_options(vag, args, prob):
+    opts = dict(rtol=prob.rtol, cfl=prob.cfl, max_iter=50000, inner_rtol=1e-2, gmres_restart=100,
+                precond={"amg": vag.VAG_PC_AMG, "jacobi": vag.VAG_PC_JACOBI, "bjilu0": vag.VAG_PC_BJILU0}[args.precond],
+                precision={"fp64": vag.VAG_FP64, "mixed": vag.VAG_MIXED, "mixed_ir": vag.VAG_MIXED_IR}[args.precision],
+                krylov={"cg": vag.VAG_CG, "gmres": vag.VAG_GMRES, "bicgstab": vag.VAG_BICGSTAB}[args.krylov],
+                eliminate_frac_faces=0 if args.keep_faces else 1)
+    if args.amg_sweeps > 0:
+        opts["amg_sweeps"] = args.amg_sweeps
+    if args.amg_hops > 0:
+        opts["amg_aggregate_hops"] = args.amg_hops
+    if args.amg_coarse_size > 0:
+        opts["amg_coarse_size"] = args.amg_coarse_size
+    if args.amg_kcycle >= 0:
+        opts["amg_kcycle"] = args.amg_kcycle
+    if args.amg_kind == "classical":
+        opts["amg_kind"] = 1
+    if args.ilu_block_rows > 0:
+        opts["ilu_block_rows"] = args.ilu_block_rows
+    return opts
+
+
+def timed_steps(torch, h, prob, steps, warmup, label):
+    """warmup untimed steps, then `steps` timed ones, synchronised on both sides."""
+    def step():
+        return h.solve_pressure(), h.transport(n_steps=prob.n_steps)
+
+    for _ in range(warmup):
+        sinfo, tinfo = step()
+        log(f"{label} warmup step: {sinfo['iterations']} iterations, residual {sinfo['rel_residual']:.2e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        sinfo, tinfo = step()
+        if steps <= 5 or k % 5 == 4:
+            log(f"{label} timed step {k + 1}/{steps}")
+    torch.cuda.synchronize()
+    return sinfo, tinfo, time.perf_counter() - t0
+
+
+def kernel_rates(vag, h, args, opts, sinfo, tinfo, workload, n_is_default):
+    """Roofline of the dominant kernel (per-launch HIP-event time on the
+    handle's stream) and the SpMV / preconditioner rates."""
+    levels = h.amg_levels() if args.precond == "amg" else None
+    ab = algorithmic_bytes(h, sinfo, tinfo, levels, args.precision,
+                           args.amg_sweeps if args.amg_sweeps > 0 else vag.default_options().amg_sweeps,
+                           kcycle_levels(vag, opts, args, levels))
+    ms_spmv = h.benchmark_kernel(vag.VAG_KERNEL_SPMV, 100)
+    ms_step = h.benchmark_kernel(vag.VAG_KERNEL_TRANSPORT_STEP, 100)
+    ms_prec = h.benchmark_kernel(vag.VAG_KERNEL_PRECOND, 50)
+    n_spmv = sinfo["iterations"] + 1
+    share = {"spmv": ms_spmv * n_spmv, "transport_step": ms_step * tinfo["n_steps"]}
+    dom = max(share, key=share.get)
+    ms_dom = ms_spmv if dom == "spmv" else ms_step
+    kname = "pcg_spmv_kernel<double, double>" if dom == "spmv" else "transport_step_kernel"
+    achieved = ab[dom] / (ms_dom * 1e-3) / 1e9
+    prof = PROFILE_NAME.get(workload, "") if n_is_default else ""
+    roofline = {"bound": "hbm", "kernel": kname.split("<")[0],
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": pmc_traffic(kname, prof) if prof else None,
+                "bytes_per_launch": ab[dom], "ms_per_launch": ms_dom,
+                "other": {"spmv_GBs": round(ab["spmv"] / (ms_spmv * 1e-3) / 1e9, 1),
+                          "transport_step_GBs": round(ab["transport_step"] / (ms_step * 1e-3) / 1e9, 1),
+                          "precond_ms": round(ms_prec, 4)}}
+    us_prof = profiled_mean_us(kname, prof) if prof else None
+    if us_prof:
+        roofline["profiled_us_per_launch"] = us_prof
+        roofline["frac_profiled"] = round(ab[dom] / (us_prof * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+    if "vcycle" in ab:
+        roofline["other"]["vcycle_GBs"] = round(ab["vcycle"] / (ms_prec * 1e-3) / 1e9, 1)
+        roofline["other"]["vcycle_frac"] = round(ab["vcycle"] / (ms_prec * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        roofline["other"]["vcycle_bytes"] = ab["vcycle"]
+    return roofline, levels
+
+
+def config2_leg(vag, torch, synth, args):
+    """The 64^3 four-fracture workload in both precisions, with the oracle's
+    full solve beside it (its system and upwind operator fit in the 256 MB
+    last-level cache, so its rates are effective bandwidths, not HBM)."""
+    import copy
+    a2 = copy.copy(args)
+    a2.workload, a2.n = "config2", 64
+    a2.precision = "fp64" if args.precond == "amg" else args.precision
+    prob = synth.config2(n=64)
+    out = {"workload": describe(a2, prob), "rates": "cache-resident: effective bandwidth, not HBM"}
+    res = {}
+    for prec in (["fp64", "mixed"] if args.precond == "amg" else [a2.precision]):
+        a2.precision = prec
+        opts = solver_options(vag, a2, prob)
+        h = vag.Handle(prob, **opts)
+        sinfo, tinfo, el = timed_steps(torch, h, prob, args.steps, min(args.warmup, 3), f"config2 {prec}")
+        rl, _ = kernel_rates(vag, h, a2, opts, sinfo, tinfo, "config2", True)
+        out[prec] = {"value": round(args.steps / el, 4), "ms_per_step": round(1e3 * el / args.steps, 3),
+                     "dtype": dtype_of(prec), "iterations": sinfo["iterations"],
+                     "rel_residual": sinfo["rel_residual"],
+                     "transport_step_GBs": rl["other"]["transport_step_GBs"],
+                     "spmv_GBs": rl["other"]["spmv_GBs"], "vcycle_GBs": rl["other"].get("vcycle_GBs")}
+        res[prec] = results(vag, h)
+        h.close()
+        log(f"config2 {prec}: {out[prec]['value']} solves/s")
+    if len(res) == 2:
+        out["mixed"]["difference_to_fp64"] = differences(res["mixed"], res["fp64"])
+    if not args.no_cpu_baseline:
+        log("config2 oracle baseline")
+        cpu, ores = cpu_baseline(prob)
+        oref = {"u_node": ores["darcy"]["u_node"], "u_frac": ores["darcy"]["u_frac"],
+                "c_cell": ores["c_cell"], "c_node": ores["c_node"]}
+        out["cpu_baseline"] = cpu
+        out["vs_oracle"] = {"note": f"both sides solved to rtol {prob.rtol:g}"} | {
+            k: differences(r, oref) for k, r in res.items()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precond", choices=["jacobi", "amg", "bjilu0"], default=os.environ.get("VAG_BENCH_PRECOND", "amg"))
-    ap.add_argument("--workload", choices=["config2", "config3", "config5"], default="config2",
-                    help="config2: 64^3, 4 clipped fractures (the headline); config3: jittered anisotropic 128^3, "
-                         "40 patches, FP32-AMG GMRES with FP64 refinement; config5: 192^3, 200 patches at 1e6, "
-                         "FP32-AMG CG with FP64 refinement")
+    ap.add_argument("--workload", choices=["config2", "config3", "config5"], default="config5",
+                    help="config5 (the headline): 192^3 jittered anisotropic, 200 patches at 1e6, FP32-AMG CG, "
+                         "1000 steps; config3: jittered anisotropic 128^3, 40 patches; config2: 64^3, 4 clipped "
+                         "fractures")
     ap.add_argument("--precision", choices=["fp64", "mixed", "mixed_ir"], default=None)
     ap.add_argument("--krylov", choices=["cg", "gmres", "bicgstab"], default=None)
     ap.add_argument("--n", type=int, default=None, help="cells per side (default: the workload's)")
@@ -227,6 +418,7 @@ def main():
     ap.add_argument("--ilu-block-rows", type=int, default=0, help="block-Jacobi ILU(0) block size (0: default)")
     ap.add_argument("--amg-kcycle", type=int, default=-1, help="coarse levels with K-cycles (-1: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the config-2 leg and the serving stream")
     ap.add_argument("--serving-jobs", type=int, default=int(os.environ.get("VAG_BENCH_SERVING_JOBS", "256")),
                     help="config-4 serving stream of this many jobs after the timed steps (0: skip)")
     ap.add_argument("--serving-workers", type=int, default=8)
@@ -254,8 +446,7 @@ def main():
     import synth
     from paper_1602_03641_amd import vag
 
-    defaults = {"config2": (64, "fp64", "cg"), "config3": (128, "mixed", "cg"), "config5": (192, "mixed", "cg")}
-    n_def, prec_def, kry_def = defaults[args.workload]
+    n_def, prec_def, kry_def = DEFAULTS[args.workload]
     args.n = args.n or n_def
     args.precision = args.precision or (prec_def if args.precond == "amg" else "fp64")
     args.krylov = args.krylov or ("bicgstab" if args.precond == "bjilu0" else kry_def)
@@ -264,126 +455,50 @@ def main():
     if args.wells > 0:
         synth.add_wells(prob, args.n, n_inj=1, n_prod=args.wells - 1)
     log(f"{len(prob.hex8)} cells, {prob.n_frac} fracture faces; creating the handle")
-    opts = dict(rtol=prob.rtol, cfl=prob.cfl, max_iter=50000, inner_rtol=1e-2, gmres_restart=100,
-                precond={"amg": vag.VAG_PC_AMG, "jacobi": vag.VAG_PC_JACOBI, "bjilu0": vag.VAG_PC_BJILU0}[args.precond],
-                precision={"fp64": vag.VAG_FP64, "mixed": vag.VAG_MIXED, "mixed_ir": vag.VAG_MIXED_IR}[args.precision],
-                krylov={"cg": vag.VAG_CG, "gmres": vag.VAG_GMRES, "bicgstab": vag.VAG_BICGSTAB}[args.krylov],
-                eliminate_frac_faces=0 if args.keep_faces else 1)
-    if args.amg_sweeps > 0:
-        opts["amg_sweeps"] = args.amg_sweeps
-    if args.amg_hops > 0:
-        opts["amg_aggregate_hops"] = args.amg_hops
-    if args.amg_coarse_size > 0:
-        opts["amg_coarse_size"] = args.amg_coarse_size
-    if args.amg_kcycle >= 0:
-        opts["amg_kcycle"] = args.amg_kcycle
-    if args.amg_kind == "classical":
-        opts["amg_kind"] = 1
-    if args.ilu_block_rows > 0:
-        opts["ilu_block_rows"] = args.ilu_block_rows
+    opts = solver_options(vag, args, prob)
     t0 = time.perf_counter()
     h = vag.Handle(prob, **opts)
     torch.cuda.synchronize()
     symbolic_s = time.perf_counter() - t0
-
-    def step():
-        s = h.solve_pressure()
-        t = h.transport(n_steps=prob.n_steps)
-        return s, t
-
     log(f"symbolic phase and uploads {symbolic_s:.2f} s; warmup")
-    for _ in range(args.warmup):
-        sinfo, tinfo = step()
-        log(f"warmup step: {sinfo['iterations']} iterations, residual {sinfo['rel_residual']:.2e}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        sinfo, tinfo = step()
-        if args.steps <= 5 or k % 5 == 4:
-            log(f"timed step {k + 1}/{args.steps}")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    sinfo, tinfo, elapsed = timed_steps(torch, h, prob, args.steps, args.warmup, args.workload)
     ms_per_step = 1e3 * elapsed / args.steps
-
-    # roofline of the dominant kernel: per-launch time from HIP events on the handle's stream
-    levels = h.amg_levels() if args.precond == "amg" else None
-    ab = algorithmic_bytes(h, sinfo, tinfo, levels, args.precision, args.amg_sweeps if args.amg_sweeps > 0 else vag.default_options().amg_sweeps,
-                           kcycle_levels(vag, opts, args, levels))
-    ms_spmv = h.benchmark_kernel(vag.VAG_KERNEL_SPMV, 100)
-    ms_step = h.benchmark_kernel(vag.VAG_KERNEL_TRANSPORT_STEP, 100)
-    ms_prec = h.benchmark_kernel(vag.VAG_KERNEL_PRECOND, 50)
-    n_spmv = sinfo["iterations"] + 1
-    share = {"spmv": ms_spmv * n_spmv, "transport_step": ms_step * tinfo["n_steps"]}
-    dom = max(share, key=share.get)
-    ms_dom = ms_spmv if dom == "spmv" else ms_step
-    achieved = ab[dom] / (ms_dom * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": "pcg_spmv_kernel" if dom == "spmv" else "transport_step_kernel",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": pmc_traffic("pcg_spmv_kernel<double, double>" if dom == "spmv" else "transport_step_kernel",
-                                       {"config2": "config2_64cubed", "config3": "config3_128cubed"}.get(args.workload, "") if args.n == n_def else ""),
-                "bytes_per_launch": ab[dom], "ms_per_launch": ms_dom,
-                "other": {"spmv_GBs": round(ab["spmv"] / (ms_spmv * 1e-3) / 1e9, 1),
-                          "transport_step_GBs": round(ab["transport_step"] / (ms_step * 1e-3) / 1e9, 1),
-                          "precond_ms": round(ms_prec, 4)}}
-    if "vcycle" in ab:
-        roofline["other"]["vcycle_GBs"] = round(ab["vcycle"] / (ms_prec * 1e-3) / 1e9, 1)
-        roofline["other"]["vcycle_bytes"] = ab["vcycle"]
-
+    roofline, levels = kernel_rates(vag, h, args, opts, sinfo, tinfo, args.workload, args.n == n_def)
     copy_gbs = copy_bandwidth(torch)
     roofline["other"]["copy_GBs"] = round(copy_gbs, 1)
-    roofline["other"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    roofline["other"]["frac_of_copy"] = round(roofline["achieved"] / copy_gbs, 4)
     log("kernel timings done")
-    gpu_res = results(vag, h)
 
-    # the same workload in the other precision (FP64 <-> FP32 hierarchy), timed the same way
-    other, other_res = None, None
-    if args.precond == "amg" and args.workload == "config2" and args.precision in ("fp64", "mixed"):
-        alt = "mixed" if args.precision == "fp64" else "fp64"
-        h2 = vag.Handle(prob, **(opts | {"precision": vag.VAG_MIXED if alt == "mixed" else vag.VAG_FP64}))
-        for _ in range(args.warmup):
-            h2.solve_pressure()
-            h2.transport(n_steps=prob.n_steps)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            s2 = h2.solve_pressure()
-            h2.transport(n_steps=prob.n_steps)
-        torch.cuda.synchronize()
-        el2 = time.perf_counter() - t1
-        ms_prec2 = h2.benchmark_kernel(vag.VAG_KERNEL_PRECOND, 50)
-        lv2 = h2.amg_levels()
-        ab2 = algorithmic_bytes(h2, s2, tinfo, lv2, alt, args.amg_sweeps if args.amg_sweeps > 0 else vag.default_options().amg_sweeps,
-                                kcycle_levels(vag, opts, args, lv2))
-        other = {"precision": alt, "value": round(args.steps / el2, 4), "iterations": s2["iterations"],
-                 "rel_residual": s2["rel_residual"], "ms_solve": round(s2["ms_solve"], 3),
-                 "vcycle_GBs": round(ab2["vcycle"] / (ms_prec2 * 1e-3) / 1e9, 1),
-                 "difference_to_headline": None}
-        other_res = results(vag, h2)
-        other["difference_to_headline"] = differences(other_res, gpu_res)
-        del h2
-        log(f"{alt}: {other['value']} solves/s")
+    cpu = None
+    vs_oracle = None
+    if not args.no_cpu_baseline:
+        if args.workload == "config2":
+            log("oracle baseline")
+            cpu, ores = cpu_baseline(prob)
+            gpu_res = results(vag, h)
+            oref = {"u_node": ores["darcy"]["u_node"], "u_frac": ores["darcy"]["u_frac"],
+                    "c_cell": ores["c_cell"], "c_node": ores["c_node"]}
+            vs_oracle = {"note": f"both sides solved to rtol {prob.rtol:g}", args.precision: differences(gpu_res, oref)}
+        else:
+            cpu = cpu_baseline_sampled(prob, vag, h, tinfo["dt"])
+    h.close()
+    del h
+    vag.trim_memory()
+
+    extra = None
     serving = None
-    if args.serving_jobs > 0 and args.workload == "config2":
+    if not args.no_extras and args.workload != "config2":
+        extra = config2_leg(vag, torch, synth, args)
+    if not args.no_extras and args.serving_jobs > 0:
         log(f"serving stream of {args.serving_jobs} jobs")
         serving = serving_bench(vag, synth, args.serving_jobs, args.serving_workers,
                                 int(args.serving_budget_gb * 1e9))
 
-    cpu = None
-    vs_oracle = None
-    if not args.no_cpu_baseline and args.workload == "config2":
-        log("oracle baseline")
-        cpu, ores = cpu_baseline(prob)
-        oref = {"u_node": ores["darcy"]["u_node"], "u_frac": ores["darcy"]["u_frac"],
-                "c_cell": ores["c_cell"], "c_node": ores["c_node"]}
-        vs_oracle = {"note": f"both sides solved to rtol {prob.rtol:g}", args.precision: differences(gpu_res, oref)}
-        if other is not None:
-            vs_oracle[other["precision"]] = differences(other_res, oref)
-
     out = {
         "metric": "Darcy+transport solves/sec", "value": round(args.steps / elapsed, 4), "unit": "solves/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype_of(args.precision),
+        "data": "synthetic",
         "config": {"workload": describe(args, prob),
                    "precond": args.precond, "precision": args.precision, "krylov": args.krylov,
                    "amg_kcycle_levels": kcycle_levels(vag, opts, args, levels),
@@ -400,8 +515,8 @@ def main():
         "system": {"rows": sinfo["n_unknowns"], "nnz": sinfo["nnz"],
                    "stored": levels[0][2] if levels else None},
         "upwind_operator": {"rows": tinfo["n_rows"], "nnz": tinfo["t_nnz"], "stored": tinfo["t_stored"]},
-        "roofline": roofline, "cpu_baseline": cpu, "other_precision": other, "vs_oracle": vs_oracle,
-        "serving": serving,
+        "roofline": roofline, "cpu_baseline": cpu, "vs_oracle": vs_oracle,
+        "config2": extra, "serving": serving,
     }
     print(json.dumps(out), flush=True)
 
