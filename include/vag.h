@@ -260,6 +260,39 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
                          vag_transport_info *info);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * transport of vag_transport (time step dt = cfl * CFL bound, then n_steps
+ * explicit upwind steps, or t_final as there) without the upwind operator that
+ * vag_transport builds in memory it allocates.  Each step gathers the upwind
+ * fluxes of every control volume from the handle's resident Darcy fluxes.
+ * The call allocates nothing: the CFL reduction's partial minima and the time
+ * step live in a static device array of the library (3 * 512 + 8 doubles,
+ * about 12 KB, one copy per device, held until the process ends), the
+ * concentration double buffer is the handle's own (from vag_create).
+ *   c0_cell[n_cells], c0_frac[n_frac], c0_node[n_nodes]: initial state in
+ *       device memory, read only; all NULL = continue from the handle's state
+ *       (zero after a solve).  Dirichlet nodes are held at c_bar.
+ *   c_cell, c_frac, c_node: the state after the steps, device memory,
+ *       caller-owned, same sizes; any may be NULL.  The handle's concentration
+ *       state (vag_get_concentration, a later transport call) is the result
+ *       too.
+ *   info: NULL, or filled as by vag_transport (t_nnz = t_stored = 0).  With
+ *       info or t_final > 0 the call reads dt on the host and synchronises the
+ *       handle's stream; otherwise it only queues work on that stream.
+ * The result equals vag_transport's up to the order of the additions inside
+ * each step.  Every call on a device shares that device's array and the
+ * array keeps the last call's contents (each call writes every value it
+ * reads before reading it), so calls whose work overlaps on one device
+ * (handles on different streams or threads) race: serialise them.
+ * Errors: as vag_transport; VAG_ERR_ARG if the reduction's scratch would
+ * exceed the array.
+ */
+vag_status vag_transport_noalloc(vag_handle *h, int64_t n_steps, double t_final, const double *c0_cell,
+                                 const double *c0_frac, const double *c0_node, double *c_cell, double *c_frac,
+                                 double *c_node, vag_transport_info *info);
+
+/*
  * Transport on given Darcy fluxes (layout of vag_get_fluxes) instead of those
  * of a pressure solve: the fluxes replace the handle's, porous volumes are
  * computed from its geometry and porosities, and vag_transport may follow.

@@ -12,6 +12,8 @@
 // (slices of 64 rows = one wavefront, column-major inside a slice), and every
 // step is one coalesced sweep over it.  Dirichlet nodes keep T_ii = 1, no
 // off-diagonal, so they stay at c_bar.
+#include <mutex>
+
 #include "reduce.h"
 
 namespace vag {
@@ -531,6 +533,114 @@ __global__ __launch_bounds__(256) void transport_step_kernel(UpwindOp T, const d
     c_out[i] = (theta == 1.0) ? acc : ci + theta * (acc - ci);
 }
 
+// One explicit step without the upwind operator (the entry point for callers
+// that cannot allocate): every control volume gathers the upwind fluxes
+// H = c_up F of eq darcyfluxH from the resident Darcy fluxes, one thread per
+// control volume.  Cells read their 8 node fluxes and fracture faces; a
+// fracture face its 4 node fluxes, its (at most 2) cells and its well; a node
+// its cells and faces through the node -> (cell, slot) and node -> (face, slot)
+// lists.  Outflow leaves at the control volume's own concentration, inflow
+// enters at the upstream one's; a well injects c_inj Q^+ (wsrc) and produces
+// Q^- (wout) at the face's concentration.  Dirichlet nodes keep their value
+// (the state holds c_bar there).  The result is the step of
+// transport_step_kernel up to the order of the additions:
+//   c_out = c_in - theta * dt / phi * (sum of the control volume's H).
+__global__ __launch_bounds__(kT) void transport_gather_kernel(
+    int32_t nc, int32_t nf, int32_t nn, const int32_t *__restrict__ hex8, const uint8_t *__restrict__ fmask,
+    const int32_t *__restrict__ cell_frac, const int32_t *__restrict__ frac_cell,
+    const int32_t *__restrict__ frac_nodes, const uint8_t *__restrict__ dirichlet, const int32_t *__restrict__ ncp,
+    const int32_t *__restrict__ ncl, const int32_t *__restrict__ nfp, const int32_t *__restrict__ nfl,
+    const double *__restrict__ F_cell, const double *__restrict__ F_cell_frac, const double *__restrict__ F_frac,
+    const double *__restrict__ wsrc, const double *__restrict__ wout, const double *__restrict__ phi_cell,
+    const double *__restrict__ phi_frac, const double *__restrict__ phi_node, const double *__restrict__ dtp,
+    double theta, const double *__restrict__ c_in, double *__restrict__ c_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t off_f = nc, off_n = (int64_t)nc + nf;
+    if (i >= off_n + nn) return;
+    const double tdt = theta * dtp[3];
+    const double ci = c_in[i];
+    double sum = 0.0;  // sum of the outgoing H of control volume i
+    double phi;
+    if (i < nc) {
+        const int32_t K = (int32_t)i;
+        phi = phi_cell[K];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const double F = F_cell[8 * (int64_t)K + a];
+            sum += F > 0.0 ? ci * F : c_in[off_n + hex8[8 * (int64_t)K + a]] * F;
+        }
+        const unsigned mask = fmask[K];
+        if (mask)
+            for (int f = 0; f < 6; ++f)
+                if ((mask >> f) & 1u) {
+                    const int32_t sg = cell_frac[6 * (int64_t)K + f];
+                    const int side = frac_cell[2 * (int64_t)sg] == K ? 0 : 1;
+                    const double F = F_cell_frac[2 * (int64_t)sg + side];
+                    sum += F > 0.0 ? ci * F : c_in[off_f + sg] * F;
+                }
+    } else if (i < off_n) {
+        const int32_t f = (int32_t)(i - off_f);
+        phi = phi_frac[f];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double F = F_frac[4 * (int64_t)f + q];
+            sum += F > 0.0 ? ci * F : c_in[off_n + frac_nodes[4 * (int64_t)f + q]] * F;
+        }
+        for (int side = 0; side < 2; ++side) {
+            const int32_t K = frac_cell[2 * (int64_t)f + side];
+            if (K < 0) continue;
+            const double F = F_cell_frac[2 * (int64_t)f + side];  // from K into the face
+            sum -= F > 0.0 ? c_in[K] * F : ci * F;
+        }
+        if (wout) sum += ci * wout[f];
+        if (wsrc) sum -= wsrc[f];
+    } else {
+        const int32_t s = (int32_t)(i - off_n);
+        if (dirichlet[s]) {
+            c_out[i] = ci;
+            return;
+        }
+        phi = phi_node[s];
+        for (int32_t q = ncp[s]; q < ncp[s + 1]; ++q) {
+            const double F = F_cell[ncl[q]];  // from cell ncl[q] / 8 into the node
+            sum -= F > 0.0 ? c_in[ncl[q] >> 3] * F : ci * F;
+        }
+        for (int32_t q = nfp[s]; q < nfp[s + 1]; ++q) {
+            const double F = F_frac[nfl[q]];  // from face nfl[q] / 4 into the node
+            sum -= F > 0.0 ? c_in[off_f + (nfl[q] >> 2)] * F : ci * F;
+        }
+    }
+    c_out[i] = ci - (tdt / phi) * sum;
+}
+
+// Scratch of the allocation-free transport entry point: the CFL partial minima
+// (3 per reduction block) and the four values of dt_out.  One copy per device,
+// held until the process ends; host code reaches it only through the address
+// that hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoallocScratchDoubles = 3 * (size_t)kReduceBlocks + 8;
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+double *noalloc_scratch(size_t *doubles) {
+    int dev = 0;
+    VAG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw Error(VAG_ERR_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        VAG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw Error(VAG_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *doubles = kNoallocScratchDoubles;
+    return g_scratch_ptr[dev];
+}
+
 __global__ void set_dirichlet_kernel(int32_t nn, int32_t offset, const uint8_t *__restrict__ dirichlet,
                                      const double *__restrict__ c_bar, double *__restrict__ c) {
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -628,6 +738,21 @@ void launch_upwind_pack(hipStream_t s, const UpwindOp &T, uint16_t *tcol16, int3
 void launch_transport_step(hipStream_t s, const UpwindOp &T, const double *c_in, double *c_out, double theta) {
     const int64_t slots = (int64_t)((T.nrow + kSliceRows - 1) / kSliceRows) * kSliceRows;
     hipLaunchKernelGGL(transport_step_kernel, dim3(nb(slots, 256)), dim3(256), 0, s, T, c_in, c_out, theta);
+    VAG_HIP(hipGetLastError());
+}
+void launch_transport_gather(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,
+                             const uint8_t *fmask, const int32_t *cell_frac, const int32_t *frac_cell,
+                             const int32_t *frac_nodes, const uint8_t *dirichlet, const int32_t *node_cell_ptr,
+                             const int32_t *node_cell, const int32_t *node_frac_ptr, const int32_t *node_frac,
+                             const double *F_cell, const double *F_cell_frac, const double *F_frac,
+                             const double *wsrc, const double *wout, const double *phi_cell, const double *phi_frac,
+                             const double *phi_node, const double *dt, double theta, const double *c_in,
+                             double *c_out) {
+    const int64_t total = (int64_t)nc + nf + nn;
+    if (total <= 0) return;
+    hipLaunchKernelGGL(transport_gather_kernel, dim3(nb(total, kT)), dim3(kT), 0, s, nc, nf, nn, hex8, fmask,
+                       cell_frac, frac_cell, frac_nodes, dirichlet, node_cell_ptr, node_cell, node_frac_ptr, node_frac,
+                       F_cell, F_cell_frac, F_frac, wsrc, wout, phi_cell, phi_frac, phi_node, dt, theta, c_in, c_out);
     VAG_HIP(hipGetLastError());
 }
 void launch_set_dirichlet(hipStream_t s, int32_t nn, int32_t offset, const uint8_t *dirichlet, const double *c_bar,

@@ -174,6 +174,7 @@ struct vag_handle {
     unsigned long long *h_cnt = nullptr;
     int cur = 0;
     bool solved = false, have_flux = false, have_c = false;
+    bool have_op = false;  // the upwind operator of the last vag_transport exists
 
     Amg amg;
     Ilu ilu;                 // block-Jacobi ILU(0)
@@ -1148,6 +1149,7 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
                            h->phi_cell.p, h->phi_frac.p, h->phi_node.p, h->dt4.p, h->slice_ptr.p, h->tmeta.p,
                            h->tcol.p, h->tval.p, h->tdiag.p);
         launch_upwind_pack(s, h->upwind(), h->tcol16.p, h->tbase.p);
+        h->have_op = true;
         // initial state
         if (c0_cell || c0_frac || c0_node) {
             if (!c0_cell || !c0_node || (S.nf && !c0_frac))
@@ -1193,6 +1195,94 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
             info->n_rows = nrow;
             info->t_nnz = h->h_cnt[0];
             info->t_stored = total;
+        }
+    });
+}
+
+vag_status vag_transport_noalloc(vag_handle *h, int64_t n_steps, double t_final, const double *c0_cell,
+                                 const double *c0_frac, const double *c0_node, double *c_cell, double *c_frac,
+                                 double *c_node, vag_transport_info *info) {
+    if (!h) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        if (!h->have_flux)
+            throw Error(VAG_ERR_STATE, "vag_transport_noalloc needs a pressure solve (or vag_set_fluxes) first");
+        if (n_steps < 0 || t_final < 0) throw Error(VAG_ERR_ARG, "negative step count or final time");
+        const Symbolic &S = h->S;
+        hipStream_t s = h->stream;
+        const int64_t nrow = (int64_t)S.nc + S.nf + S.nn;
+        // the CFL reduction's partials (3 per block of its grid) and dt_out
+        size_t cap = 0;
+        double *scr = noalloc_scratch(&cap);
+        const size_t need = 3 * (size_t)kReduceBlocks + 4;
+        if (need > cap)
+            throw Error(VAG_ERR_ARG, "transport scratch of " + std::to_string(need) + " doubles exceeds the " +
+                                         std::to_string(cap) + " of the static array");
+        double *parts = scr, *dt4 = scr + 3 * (size_t)kReduceBlocks;
+        const bool sync_dt = t_final > 0 || info;
+        VAG_HIP(hipEventRecord(h->ev[5], s));
+        launch_cfl(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
+                   h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
+                   h->F_cell_frac.p, h->F_frac.p, h->well_out(), h->phi_cell.p, h->phi_frac.p, h->phi_node.p,
+                   h->opt.cfl, parts, dt4);
+        if (c0_cell || c0_frac || c0_node) {
+            if (!c0_cell || !c0_node || (S.nf && !c0_frac))
+                throw Error(VAG_ERR_ARG, "give all of c0_cell, c0_frac, c0_node or none");
+            h->cur = 0;
+            VAG_HIP(hipMemcpyAsync(h->cbuf0.p, c0_cell, S.nc * sizeof(double), hipMemcpyDeviceToDevice, s));
+            if (S.nf)
+                VAG_HIP(hipMemcpyAsync(h->cbuf0.p + S.nc, c0_frac, S.nf * sizeof(double), hipMemcpyDeviceToDevice,
+                                       s));
+            VAG_HIP(hipMemcpyAsync(h->cbuf0.p + S.nc + S.nf, c0_node, S.nn * sizeof(double),
+                                   hipMemcpyDeviceToDevice, s));
+        } else if (!h->have_c) {
+            h->cur = 0;
+            launch_fill(s, nrow, 0.0, h->cbuf0.p);
+        }
+        launch_set_dirichlet(s, S.nn, S.nc + S.nf, h->dirichlet.p, h->c_bar.p, h->c_cur());
+        h->have_c = true;
+        double dt = 0.0, dtb[3] = {0.0, 0.0, 0.0};
+        if (sync_dt) {
+            VAG_HIP(hipMemcpyAsync(h->h_scal, dt4, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+            VAG_HIP(hipStreamSynchronize(s));
+            dt = h->h_scal[3];
+            for (int i = 0; i < 3; ++i) dtb[i] = h->h_scal[i];
+            if (!(dt < INFINITY)) throw Error(VAG_ERR_ARG, "no control volume has an outflow: CFL bound is infinite");
+        }
+        int64_t N = n_steps;
+        double theta_last = 1.0, last_dt = dt;
+        if (t_final > 0) {
+            N = (int64_t)std::ceil(t_final / dt);
+            if (N < 1) N = 1;
+            last_dt = t_final - (double)(N - 1) * dt;
+            theta_last = last_dt / dt;
+        }
+        VAG_HIP(hipEventRecord(h->ev[6], s));
+        for (int64_t k = 0; k < N; ++k) {
+            const double th = (k == N - 1) ? theta_last : 1.0;
+            launch_transport_gather(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p,
+                                    h->frac_nodes.p, h->dirichlet.p, h->node_cell_ptr.p, h->node_cell.p,
+                                    h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p, h->F_cell_frac.p, h->F_frac.p,
+                                    h->well_src(), h->well_out(), h->phi_cell.p, h->phi_frac.p, h->phi_node.p, dt4,
+                                    th, h->c_cur(), h->c_next());
+            h->cur ^= 1;
+        }
+        const double *c = h->c_cur();
+        if (c_cell) VAG_HIP(hipMemcpyAsync(c_cell, c, S.nc * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (c_frac && S.nf)
+            VAG_HIP(hipMemcpyAsync(c_frac, c + S.nc, S.nf * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (c_node)
+            VAG_HIP(hipMemcpyAsync(c_node, c + S.nc + S.nf, S.nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (info) {
+            VAG_HIP(hipEventRecord(h->ev[7], s));
+            VAG_HIP(hipEventSynchronize(h->ev[7]));
+            std::memset(info, 0, sizeof *info);
+            info->n_steps = N;
+            info->dt = dt;
+            info->last_dt = last_dt;
+            for (int i = 0; i < 3; ++i) info->dt_bounds[i] = dtb[i];
+            info->ms_setup = elapsed(h->ev[5], h->ev[6]);
+            info->ms_steps = elapsed(h->ev[6], h->ev[7]);
+            info->n_rows = nrow;
         }
     });
 }
@@ -1299,7 +1389,7 @@ vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms)
         const Symbolic &S = h->S;
         hipStream_t s = h->stream;
         const int64_t nrow = (int64_t)S.nc + S.nf + S.nn;
-        if (kernel == VAG_KERNEL_TRANSPORT_STEP && !h->have_c)
+        if (kernel == VAG_KERNEL_TRANSPORT_STEP && (!h->have_c || !h->have_op))
             throw Error(VAG_ERR_STATE, "the transport step needs a transport call first");
         auto once = [&] {
             switch (kernel) {

@@ -384,5 +384,19 @@ void launch_well_rates(hipStream_t s, int32_t nw, const int32_t *wface, const do
                        double *fsrc, double *fout);
 void launch_set_dirichlet(hipStream_t s, int32_t nn, int32_t offset, const uint8_t *dirichlet,
                           const double *c_bar, double *c);
+// One explicit step gathered per control volume from the fluxes (no upwind
+// operator); dt = dt[3], theta as in launch_transport_step.
+void launch_transport_gather(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,
+                             const uint8_t *fmask, const int32_t *cell_frac, const int32_t *frac_cell,
+                             const int32_t *frac_nodes, const uint8_t *dirichlet, const int32_t *node_cell_ptr,
+                             const int32_t *node_cell, const int32_t *node_frac_ptr, const int32_t *node_frac,
+                             const double *F_cell, const double *F_cell_frac, const double *F_frac,
+                             const double *wsrc, const double *wout, const double *phi_cell, const double *phi_frac,
+                             const double *phi_node, const double *dt, double theta, const double *c_in,
+                             double *c_out);
+// Device address of the current device's copy of the allocation-free entry
+// point's static scratch array (looked up once per device) and its size in
+// doubles.
+double *noalloc_scratch(size_t *doubles);
 
 }  // namespace vag

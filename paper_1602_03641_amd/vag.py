@@ -124,6 +124,8 @@ _SIGS = {
     "vag_set_options": ([vp, C.POINTER(vag_options)], C.c_int),
     "vag_solve_pressure": ([vp, C.POINTER(vag_solve_info)], C.c_int),
     "vag_transport": ([vp, C.c_int64, C.c_double, vp, vp, vp, C.c_int, C.POINTER(vag_transport_info)], C.c_int),
+    "vag_transport_noalloc": ([vp, C.c_int64, C.c_double, vp, vp, vp, vp, vp, vp,
+                               C.POINTER(vag_transport_info)], C.c_int),
     "vag_set_fluxes": ([vp, vp, vp, vp, C.c_int], C.c_int),
     "vag_get_pressure": ([vp, vp, vp, vp, C.c_int], C.c_int),
     "vag_get_fluxes": ([vp, vp, vp, vp, C.c_int], C.c_int),
@@ -279,6 +281,23 @@ class Handle:
         self._check(load().vag_transport(self.h, int(n_steps), float(t_final), *args, VAG_MEM_DEVICE,
                                          C.byref(info)))
         return info.as_dict()
+
+    def transport_noalloc(self, n_steps=0, t_final=0.0, c0=None, info=True):
+        """vag_transport_noalloc: the steps gathered from the fluxes, with the
+        library's static scratch; returns (concentrations as device tensors,
+        info dict or None)."""
+        args = (None, None, None)
+        if c0 is not None:
+            tt = [self.torch.as_tensor(np.ascontiguousarray(c0[k]) if not hasattr(c0[k], "data_ptr") else c0[k],
+                                       dtype=self.torch.float64, device=self.device)
+                  for k in ("c_cell", "c_frac", "c_node")]
+            self._c0 = tt
+            args = tuple(_dptr(x) for x in tt)
+        out = [self.torch.empty(n, dtype=self.torch.float64, device=self.device) for n in (self.nc, self.nf, self.nn)]
+        ti = vag_transport_info() if info else None
+        self._check(load().vag_transport_noalloc(self.h, int(n_steps), float(t_final), *args,
+                                                 *[_dptr(o) for o in out], C.byref(ti) if info else None))
+        return dict(c_cell=out[0], c_frac=out[1], c_node=out[2]), (ti.as_dict() if info else None)
 
     def set_fluxes(self, flux):
         tt = [self.torch.as_tensor(np.ascontiguousarray(flux[k]), dtype=self.torch.float64, device=self.device)
