@@ -66,8 +66,8 @@ def algorithmic_bytes(h, sinfo, tinfo, levels=None, precision="fp64", sweeps=2, 
 
 def kcycle_levels(vag, opts, args, levels):
     """Coarse levels that run K-cycles: 1..amg_kcycle below the coarsest, with
-    CG outside and no FP32 inner solve (the library's rule)."""
-    if not levels or args.krylov != "cg" or args.precision == "mixed_ir" or args.amg_kind == "classical":
+    CG or GMRES outside and no FP32 inner solve (the library's rule)."""
+    if not levels or args.krylov not in ("cg", "gmres") or args.precision == "mixed_ir" or args.amg_kind == "classical":
         return 0
     k = opts.get("amg_kcycle", vag.default_options().amg_kcycle)
     return max(0, min(k, len(levels) - 2))
@@ -247,7 +247,7 @@ def log(msg):
 
 
 PROFILE_NAME = {"config2": "config2_64cubed", "config3": "config3_128cubed", "config5": "config5_192cubed"}
-DEFAULTS = {"config2": (64, "fp64", "cg"), "config3": (128, "mixed", "cg"), "config5": (192, "mixed", "cg")}
+DEFAULTS = {"config2": (64, "fp64", "cg"), "config3": (128, "mixed", "gmres"), "config5": (192, "mixed", "cg")}
 
 
 def profiled_mean_us(kernel, workload):

@@ -63,12 +63,13 @@ typedef enum { VAG_MEM_HOST = 0, VAG_MEM_DEVICE = 1 } vag_mem;
 
 /* VAG_MIXED: the AMG hierarchy (every level's matrix) is stored and applied in
  * FP32 while the Krylov vectors, the system matrix products and residuals stay
- * FP64.  VAG_MIXED_IR: FP64 iterative refinement around an FP32 CG with the
- * FP32 hierarchy of the diagonally scaled matrix.  Assembly, elimination,
- * fluxes and transport are FP64 in every mode. */
+ * FP64.  VAG_MIXED_IR: FP64 iterative refinement (residual b - A x and update
+ * in FP64) around an FP32 CG or GMRES on the FP32 copy of A, preconditioned
+ * by the FP32 hierarchy.  Assembly, elimination, fluxes and transport are
+ * FP64 in every mode. */
 typedef enum { VAG_FP64 = 0, VAG_MIXED = 1, VAG_MIXED_IR = 2 } vag_precision;
 /* Krylov method for the eliminated system (§5.3 compares CG, GMRES and
- * BiCGStab): VAG_CG (the system is SPD), VAG_GMRES (restarted GMRES(m), CGS2),
+ * BiCGStab): VAG_CG (the system is SPD), VAG_GMRES (restarted flexible GMRES(m), CGS2),
  * VAG_BICGSTAB (right-preconditioned BiCGStab, FP64 vectors; not with
  * VAG_MIXED_IR). */
 typedef enum { VAG_CG = 0, VAG_GMRES = 1, VAG_BICGSTAB = 2 } vag_krylov;
@@ -150,15 +151,17 @@ typedef struct {
                                independent set of the strength graph; 0 = default */
     int amg_kcycle;         /* coarse levels 1..amg_kcycle (not the coarsest) take a K-cycle:
                                two flexible CG steps preconditioned by the V-cycle below, the
-                               outer CG then in its flexible form (CG only; 0: V-cycles;
-                               default 2) */
+                               outer CG then in its flexible form (CG and flexible GMRES, not
+                               with VAG_MIXED_IR; 0: V-cycles; default 2) */
     int ilu_block_rows;     /* VAG_PC_BJILU0: unknowns per block, 1..8192 (0: 128); blocks are
                                runs of the natural unknown order (vag_get_system's) */
     int amg_kind;           /* VAG_PC_AMG: 0 aggregation (default); 1 classical (strength
                                -a_ij >= amg_strong_theta max_k -a_ik, PMIS coarse points, direct
                                interpolation, Galerkin R A P; V-cycles, amg_kcycle ignored) */
     double amg_strong_theta;/* classical strength threshold in (0, 1); 0: 0.25 */
-    int reserved[1];
+    int stream_loads;       /* row loops of the system matrix and the FP32 hierarchy read the
+                               matrix entries with non-temporal loads: 0 for matrices above
+                               128 MB (default), 1 always, 2 never; results are the same */
 } vag_options;
 
 typedef struct {

@@ -63,6 +63,8 @@ def _lib_handle():
         lib.orc_solve_darcy.argtypes = [P, C.c_double, C.c_int, vp, vp, vp, vp, vp, vp,
                                         C.POINTER(C.c_int), C.POINTER(C.c_double)]
         lib.orc_solve_darcy.restype = C.c_int
+        lib.orc_residual.argtypes = [P, vp, vp, vp, vp, vp, vp]
+        lib.orc_residual.restype = C.c_int
         lib.orc_porous_volumes.argtypes = [P, vp, vp, vp]
         lib.orc_porous_volumes.restype = C.c_int
         lib.orc_well_rates.argtypes = [P, vp, vp]
@@ -187,6 +189,25 @@ def solve_darcy(prob, rtol=1e-12, max_iter=200000):
     out["well_rate"] = np.zeros(op.nw)
     if op.nw:
         _lib_handle().orc_well_rates(op.ref, _ptr(out["u_frac"]), _ptr(out["well_rate"]))
+    return out
+
+
+def residual(prob, u_node, u_frac):
+    """Rows of b - A x of the system at the given pressures (the conservation
+    equations of the free nodes and fracture faces, evaluated cell by cell
+    without assembling A) and b itself: dict of res_node, res_frac, b_node,
+    b_frac (0 at Dirichlet nodes) and the relative residual ||b - A x|| / ||b||."""
+    op = _as(prob)
+    u_node = np.ascontiguousarray(u_node, np.float64)
+    u_frac = np.ascontiguousarray(u_frac, np.float64)
+    out = dict(res_node=np.zeros(op.nn), res_frac=np.zeros(op.nf), b_node=np.zeros(op.nn), b_frac=np.zeros(op.nf))
+    st = _lib_handle().orc_residual(op.ref, _ptr(u_node), _ptr(u_frac), _ptr(out["res_node"]), _ptr(out["res_frac"]),
+                                    _ptr(out["b_node"]), _ptr(out["b_frac"]))
+    if st:
+        raise ValueError(f"oracle residual error {st}")
+    r2 = float(out["res_node"] @ out["res_node"] + out["res_frac"] @ out["res_frac"])
+    b2 = float(out["b_node"] @ out["b_node"] + out["b_frac"] @ out["b_frac"])
+    out["rel_residual"] = math.sqrt(r2 / b2) if b2 > 0 else math.sqrt(r2)
     return out
 
 

@@ -631,6 +631,117 @@ int orc_solve_darcy(const orc_problem *P, double rtol, int max_iter, double *u_n
     return 0;
 }
 
+/*
+ * Residual of the system at given node and fracture-face pressures, without
+ * assembling it: the conservation equations of §3.1 for the free nodes and the
+ * fracture faces, written as b - A x of the cell-eliminated system (§4.2,
+ * eq eqschur; faces kept as unknowns).  In each cell, u_K follows from
+ * eq eqschurcell (zero cell source) and the fluxes F_{K,nu} from
+ * eq VAGFluxMatrix; on each fracture face F_{sigma,s} from eq VAGFluxFracture;
+ * a well adds its inflow Q = WI (p_w - u_sigma) + q to its face.
+ *   res_node[s] = sum_K F_{K,s} + sum_sigma F_{sigma,s}          (free nodes)
+ *   res_frac[f] = sum_K F_{K,sigma} - sum_s F_{sigma,s} + Q        (faces)
+ * are the rows of b - A x.  b alone, the rows' Dirichlet columns and well
+ * terms (-sum over Dirichlet nu' of the eliminated entry times p_bar, plus
+ * WI p_w + q), goes to b_node / b_frac.  Dirichlet nodes get 0 in all four.
+ * Inputs: u_node[n_nodes] (read at free nodes; Dirichlet nodes take p_bar),
+ * u_frac[n_frac].  Returns 0, or the error of orc_topology / -3 for a cell
+ * with a non-positive sub-tetrahedron.
+ */
+int orc_residual(const orc_problem *P, const double *u_node, const double *u_frac, double *res_node,
+                 double *res_frac, double *b_node, double *b_frac) {
+    int64_t nn = P->n_nodes, nc = P->n_cells, nf = P->n_frac;
+    int32_t *cell_frac = (int32_t *)malloc(sizeof(int32_t) * 6 * (size_t)nc);
+    int32_t *frac_cell = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)(nf > 0 ? nf : 1));
+    int32_t *frac_lface = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)(nf > 0 ? nf : 1));
+    int st = orc_topology(P, cell_frac, frac_cell, frac_lface);
+    if (st) { free(cell_frac); free(frac_cell); free(frac_lface); return st; }
+    for (int64_t s = 0; s < nn; ++s) res_node[s] = b_node[s] = 0.0;
+    for (int64_t f = 0; f < nf; ++f) res_frac[f] = b_frac[f] = 0.0;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(| : bad)
+    for (int64_t K = 0; K < nc; ++K) {
+        double a[14 * 14];
+        int m;
+        if (orc_cell_matrix(P, K, cell_frac + 6 * K, a, &m, NULL) < 0) { bad = 1; continue; }
+        double u[14], r[14], AKK = 0.0;
+        int32_t node[14], face[14], dir[14];
+        int q = 8;
+        for (int i = 0; i < 8; ++i) {
+            node[i] = P->hex8[8 * K + i];
+            face[i] = -1;
+            dir[i] = P->dirichlet[node[i]] != 0;
+            u[i] = dir[i] ? P->p_bar[node[i]] : u_node[node[i]];
+        }
+        for (int lf = 0; lf < 6; ++lf)
+            if (cell_frac[6 * K + lf] >= 0) {
+                node[q] = -1;
+                face[q] = cell_frac[6 * K + lf];
+                dir[q] = 0;
+                u[q] = u_frac[face[q]];
+                ++q;
+            }
+        for (int i = 0; i < m; ++i) {
+            r[i] = 0.0;
+            for (int j = 0; j < m; ++j) r[i] += a[i * m + j];
+            AKK += r[i];
+        }
+        double uK = 0.0;
+        for (int i = 0; i < m; ++i) uK += r[i] * u[i];
+        uK /= AKK;
+        for (int i = 0; i < m; ++i) {
+            if (dir[i]) continue;
+            double F = 0.0, bD = 0.0;
+            for (int j = 0; j < m; ++j) {
+                F += a[i * m + j] * (uK - u[j]);
+                if (dir[j]) bD -= (a[i * m + j] - r[i] * r[j] / AKK) * u[j];
+            }
+            double *rs = node[i] >= 0 ? res_node + node[i] : res_frac + face[i];
+            double *bs = node[i] >= 0 ? b_node + node[i] : b_frac + face[i];
+#pragma omp atomic
+            *rs += F;
+#pragma omp atomic
+            *bs += bD;
+        }
+    }
+    if (bad) { free(cell_frac); free(frac_cell); free(frac_lface); return -3; }
+    for (int64_t f = 0; f < nf; ++f) {
+        double A5[25];
+        orc_frac_matrix(P, f, A5);
+        double u[5];
+        int dir[5];
+        u[0] = u_frac[f];
+        dir[0] = 0;
+        for (int i = 0; i < 4; ++i) {
+            int32_t sn = P->frac_nodes[4 * f + i];
+            dir[1 + i] = P->dirichlet[sn] != 0;
+            u[1 + i] = dir[1 + i] ? P->p_bar[sn] : u_node[sn];
+        }
+        for (int i = 0; i < 4; ++i) {
+            double F = 0.0;  /* F_{sigma,s_i} */
+            for (int j = 0; j < 4; ++j) F += A5[(1 + i) * 5 + 1 + j] * (u[0] - u[1 + j]);
+            res_frac[f] -= F;
+            if (!dir[1 + i]) res_node[P->frac_nodes[4 * f + i]] += F;
+        }
+        /* b: Dirichlet columns of the face's 5 x 5 block */
+        for (int i = 0; i < 5; ++i) {
+            if (dir[i]) continue;
+            double bD = 0.0;
+            for (int j = 0; j < 5; ++j)
+                if (dir[j]) bD -= A5[i * 5 + j] * u[j];
+            if (i == 0) b_frac[f] += bD;
+            else b_node[P->frac_nodes[4 * f + i - 1]] += bD;
+        }
+    }
+    for (int64_t k = 0; k < P->n_wells; ++k) {
+        const int32_t f = P->well_face[k];
+        res_frac[f] += P->well_wi[k] * (P->well_pw[k] - u_frac[f]) + P->well_q[k];
+        b_frac[f] += P->well_wi[k] * P->well_pw[k] + P->well_q[k];
+    }
+    free(cell_frac); free(frac_cell); free(frac_lface);
+    return 0;
+}
+
 /* Flow from each well into its fracture face: Q = WI (p_w - u_sigma) + q. */
 int orc_well_rates(const orc_problem *P, const double *u_frac, double *Q) {
     for (int64_t k = 0; k < P->n_wells; ++k)

@@ -41,6 +41,8 @@ int orc_system_csr(const orc_problem *P, int64_t *row_ptr, int64_t *col, double 
 int orc_solve_darcy(const orc_problem *P, double rtol, int max_iter, double *u_node, double *u_cell,
                     double *u_frac, double *F_cell, double *F_cell_frac, double *F_frac,
                     int *iters, double *relres);
+int orc_residual(const orc_problem *P, const double *u_node, const double *u_frac, double *res_node,
+                 double *res_frac, double *b_node, double *b_frac);
 int orc_porous_volumes(const orc_problem *P, double *phi_cell, double *phi_frac, double *phi_node);
 int orc_well_rates(const orc_problem *P, const double *u_frac, double *Q);
 int orc_cfl(const orc_problem *P, const double *F_cell, const double *F_cell_frac,

@@ -168,6 +168,7 @@ class Amg {
     bool dense = false;
     bool have32 = false;
     double op_complexity = 1.0;
+    int stream_mode = 0;  // non-temporal matrix loads of the FP32 copies (vag_options.stream_loads)
     DBuf<double> Ainv, gj_work;
     DBuf<float> Ainv32;
     DBuf<unsigned long long> level_nnz;  // entries (without padding) of each coarse level

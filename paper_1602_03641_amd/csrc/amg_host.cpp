@@ -298,7 +298,7 @@ void Amg::make_fp32(hipStream_t s, Tracker &tr, const int32_t *) {
         launch_to_float(s, lv.n, lv.dinv.p, lv.dinv32.p);
         for (auto *v : {&lv.b32, &lv.xa32, &lv.xb32, &lv.r32}) ensure(*v, lv.n, tr);
         lv.A32 = Sell<float>{lv.n, lv.A.ptr, lv.A.col, lv.val32.p, lv.dg32.p, lv.A.col16, lv.A.cbase};
-        lv.A32.nt = stream_matrix(lv.stored, sizeof(float));
+        lv.A32.nt = stream_matrix(lv.stored, sizeof(float), stream_mode);
     }
     if (dense) {
         const int32_t nc = L[nlev - 1]->n;

@@ -1,6 +1,11 @@
-// Restarted right-preconditioned GMRES(m) with CGS2 orthogonalisation (host
-// driver; kernels in gmres.hip).  The small Hessenberg least-squares problem
-// is solved on the host with Givens rotations, one device read per iteration.
+// Restarted flexible GMRES(m) (right preconditioning) with CGS2
+// orthogonalisation (host driver; kernels in gmres.hip).  The preconditioned
+// vectors z_j = M^-1 v_j are kept, and each cycle ends with x += Z y, so the
+// update satisfies A Z = V H exactly as the Arnoldi step built it, even when
+// M^-1 is not exactly linear (an FP32 V-cycle, whose rounding on
+// ill-conditioned coarse levels would otherwise cap the attainable residual;
+// a K-cycle).  The small Hessenberg least-squares problem is solved on the
+// host with Givens rotations, one device read per iteration.
 #pragma once
 
 #include <cmath>
@@ -30,6 +35,7 @@ void launch_gm_residual(hipStream_t s, Sell<V> A, const T *b, const T *x, T *r, 
 template <class T>
 struct GmresWork {
     T *V = nullptr;          // (m+1) * n basis
+    T *Z = nullptr;          // m * n preconditioned basis vectors
     T *w = nullptr, *t = nullptr;
     double *parts = nullptr;  // (m+1) * gmres_grid(n)
     double *nparts = nullptr; // gmres_grid(n)
@@ -73,8 +79,9 @@ GmresResult gmres_solve(hipStream_t s, Sell<V> A, const T *b, T *x, double tol, 
         double est = beta;
         for (; j < m && it < max_iter; ++j, ++it) {
             T *vj = W.V + (int64_t)j * ld;
-            prec(vj, W.t);
-            launch_gm_spmv<V, T>(s, A, W.t, W.w);
+            T *zj = W.Z + (int64_t)j * ld;
+            prec(vj, zj);
+            launch_gm_spmv<V, T>(s, A, zj, W.w);
             launch_gm_orthogonalize<T>(s, n, j + 1, W.V, ld, W.w, W.parts, h1, W.nparts);
             launch_gm_orthogonalize<T>(s, n, j + 1, W.V, ld, W.w, W.parts, h2, W.nparts);
             launch_gm_normalize<T>(s, n, W.nparts, W.w, W.V + (int64_t)(j + 1) * ld, hn);
@@ -102,15 +109,14 @@ GmresResult gmres_solve(hipStream_t s, Sell<V> A, const T *b, T *x, double tol, 
                 break;
             }
         }
-        // y = R^-1 g, x += M^-1 V y
+        // y = R^-1 g, x += Z y
         for (int i = j - 1; i >= 0; --i) {
             double v = g[i];
             for (int k = i + 1; k < j; ++k) v -= R[(size_t)k * (m + 1) + i] * Y[k];
             Y[i] = v / R[(size_t)i * (m + 1) + i];
         }
         VAG_HIP(hipMemcpyAsync(yd, Y, j * sizeof(double), hipMemcpyHostToDevice, s));
-        launch_gm_combine<T>(s, n, j, W.V, ld, yd, W.w);
-        prec(W.w, W.t);
+        launch_gm_combine<T>(s, n, j, W.Z, ld, yd, W.t);
         launch_gm_add<T>(s, n, W.t, x);
         // true residual; restart from it
         launch_gm_residual<V, T>(s, A, b, x, W.w, W.nparts);

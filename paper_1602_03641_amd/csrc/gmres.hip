@@ -1,4 +1,4 @@
-// Kernels of restarted, right-preconditioned GMRES with classical Gram-Schmidt
+// Kernels of restarted flexible GMRES with classical Gram-Schmidt
 // applied twice (CGS2).  The Krylov basis V is stored as (m+1) vectors of
 // length ld, one after the other.  Every reduction goes through per-block
 // partials summed in a fixed order (deterministic); the Hessenberg column is

@@ -252,44 +252,25 @@ __global__ __launch_bounds__(kThreads) void pcg_init_plain_kernel(int32_t n, con
     if (threadIdx.x == 0) P.rr(-1)[blockIdx.x] = v[0];
 }
 
-// mixed precision with the symmetric diagonal scaling S = D^-1/2:
-//   partials of ||S r||^2; r32 = S r / ||S r||; x += ||S r|| S d32
-__global__ __launch_bounds__(kThreads) void scaled_norm_kernel(int32_t n, const double *__restrict__ sc,
-                                                               const double *__restrict__ r,
-                                                               double *__restrict__ parts) {
+// FP64 refinement around an FP32 inner solve:
+//   partials of ||r||^2; r32 = r / ||r||; x += ||r|| d32
+__global__ __launch_bounds__(kThreads) void norm2_kernel(int32_t n, const double *__restrict__ r,
+                                                         double *__restrict__ parts) {
     double v[1] = {0.0};
-    GRID_STRIDE(i, n) {
-        const double t = sc[i] * r[i];
-        v[0] += t * t;
-    }
+    GRID_STRIDE(i, n) v[0] += r[i] * r[i];
     block_partials<OpSum, 1, kThreads>(v, parts, gridDim.x);
 }
-__global__ __launch_bounds__(kThreads) void scale_to_float_kernel(int32_t n, const double *__restrict__ sc,
-                                                                  const double *__restrict__ r,
-                                                                  const double *__restrict__ nrm2,
-                                                                  float *__restrict__ r32) {
+__global__ __launch_bounds__(kThreads) void normalize_to_float_kernel(int32_t n, const double *__restrict__ r,
+                                                                      const double *__restrict__ nrm2,
+                                                                      float *__restrict__ r32) {
     const double s = nrm2[0] > 0.0 ? 1.0 / sqrt(nrm2[0]) : 0.0;
-    GRID_STRIDE(i, n) r32[i] = (float)(sc[i] * r[i] * s);
+    GRID_STRIDE(i, n) r32[i] = (float)(r[i] * s);
 }
 __global__ __launch_bounds__(kThreads) void correct_kernel(int32_t n, double *__restrict__ x,
-                                                           const double *__restrict__ sc,
                                                            const float *__restrict__ d32,
                                                            const double *__restrict__ nrm2) {
     const double s = sqrt(nrm2[0]);
-    GRID_STRIDE(i, n) x[i] += s * sc[i] * (double)d32[i];
-}
-// sc_i = 1/sqrt(a_ii); As = S A S (same sliced-ELL pattern)
-__global__ __launch_bounds__(kThreads) void diag_scale_kernel(int32_t n, const int32_t *__restrict__ diag_pos,
-                                                              const double *__restrict__ A, double *__restrict__ sc) {
-    GRID_STRIDE(i, n) sc[i] = 1.0 / sqrt(A[diag_pos[i]]);
-}
-__global__ __launch_bounds__(kThreads) void scale_matrix_kernel(Sell<double> A, const double *__restrict__ sc,
-                                                                double *__restrict__ As) {
-    GRID_STRIDE(i, A.n) {
-        const int64_t b0 = A.ptr[i >> 6], b1 = A.ptr[(i >> 6) + 1];
-        const double si = sc[i];
-        for (int64_t q = b0 + (i & 63); q < b1; q += 64) As[q] = si * A.val[q] * sc[A.col[q]];
-    }
+    GRID_STRIDE(i, n) x[i] += s * (double)d32[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -363,22 +344,16 @@ template <class T>
 void launch_pcg_init_plain(hipStream_t s, int32_t n, const T *b, T *x, T *r, PcgParts P) {
     LAUNCH(pcg_init_plain_kernel<T>, P.G, n, b, x, r, P);
 }
-void launch_scaled_norm(hipStream_t s, int32_t n, const double *sc, const double *r, double *parts, double *out) {
+void launch_norm2(hipStream_t s, int32_t n, const double *r, double *parts, double *out) {
     const unsigned g = vec_grid(n);
-    LAUNCH(scaled_norm_kernel, g, n, sc, r, parts);
+    LAUNCH(norm2_kernel, g, n, r, parts);
     launch_finalize_sum(s, parts, (int)g, (int)g, 1, out);
 }
-void launch_scale_to_float(hipStream_t s, int32_t n, const double *sc, const double *r, const double *nrm2,
-                           float *r32) {
-    if (n > 0) LAUNCH(scale_to_float_kernel, vec_grid(n), n, sc, r, nrm2, r32);
+void launch_normalize_to_float(hipStream_t s, int32_t n, const double *r, const double *nrm2, float *r32) {
+    if (n > 0) LAUNCH(normalize_to_float_kernel, vec_grid(n), n, r, nrm2, r32);
 }
-void launch_correct(hipStream_t s, int32_t n, double *x, const double *sc, const float *d32, const double *nrm2) {
-    if (n > 0) LAUNCH(correct_kernel, vec_grid(n), n, x, sc, d32, nrm2);
-}
-void launch_diag_scaling(hipStream_t s, Sell<double> A, const int32_t *diag_pos, double *sc, double *As) {
-    if (A.n <= 0) return;
-    LAUNCH(diag_scale_kernel, vec_grid(A.n), A.n, diag_pos, A.val, sc);
-    LAUNCH(scale_matrix_kernel, vec_grid(A.n), A, sc, As);
+void launch_correct(hipStream_t s, int32_t n, double *x, const float *d32, const double *nrm2) {
+    if (n > 0) LAUNCH(correct_kernel, vec_grid(n), n, x, d32, nrm2);
 }
 
 #define INST(T)                                                                                                   \

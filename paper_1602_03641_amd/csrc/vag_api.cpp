@@ -186,10 +186,9 @@ struct vag_handle {
     const double *well_out() const { return nw ? wout.p : nullptr; }
     DBuf<int> ilu_bad;       // 1 + natural row of a zero pivot, else 0
     DBuf<float> b32, x32, r32, z32, p32, q32;  // inner single-precision solve (VAG_MIXED)
-    DBuf<double> dsc, As;                      // D^-1/2 and the scaled matrix D^-1/2 A D^-1/2
     // GMRES(m) work: FP64 basis (VAG_FP64 / VAG_MIXED) or FP32 basis (inner solves of VAG_MIXED_IR)
-    DBuf<double> gmV, gmw, gmt, gmparts, gmnparts, gmhd;
-    DBuf<float> gmV32, gmw32, gmt32;
+    DBuf<double> gmV, gmZ, gmw, gmt, gmparts, gmnparts, gmhd;
+    DBuf<float> gmV32, gmZ32, gmw32, gmt32;
     // BiCGStab work (p, phat, v are p, z, q)
     DBuf<double> bcg_rhat, bcg_s, bcg_shat, bcg_t, bcg_parts;
     double *h_gm = nullptr;
@@ -200,12 +199,12 @@ struct vag_handle {
     hipEvent_t ev[8] = {};
 
     Sell<double> Asell() const { return with_col16(A.p); }
-    // the system pattern with the matrix values v (the assembled A or its scaled copy)
+    // the system pattern with the matrix values v
     Sell<double> with_col16(const double *v) const {
         Sell<double> m{S.nunk, sell_ptr.p, sell_col.p, v};
         m.col16 = sell_col16.p;
         m.cbase = sell_cbase.p;
-        m.nt = stream_matrix((int64_t)A.n, sizeof(double));
+        m.nt = stream_matrix((int64_t)A.n, sizeof(double), opt.stream_loads);
         return m;
     }
     UpwindOp upwind() const {
@@ -306,6 +305,8 @@ void check_options(const vag_options &o) {
         throw Error(VAG_ERR_ARG, "amg_aggregate_hops must be 0 (default), 1 or 2");
     if (o.krylov != VAG_CG && o.krylov != VAG_GMRES && o.krylov != VAG_BICGSTAB)
         throw Error(VAG_ERR_ARG, "unknown Krylov method");
+    if (o.stream_loads < 0 || o.stream_loads > 2)
+        throw Error(VAG_ERR_ARG, "stream_loads must be 0 (automatic), 1 (always) or 2 (never)");
     if (o.krylov == VAG_BICGSTAB && o.precision == VAG_MIXED_IR)
         throw Error(VAG_ERR_UNSUPPORTED, "BiCGStab runs in FP64 (with the FP64 or FP32 hierarchy), not as an inner solver");
     if (o.krylov == VAG_GMRES && (o.gmres_restart < 1 || o.gmres_restart > 1024))
@@ -396,9 +397,9 @@ AmgOptions amg_options(const vag_options &o) {
     if (o.amg_aggregate_hops > 0) a.hops = o.amg_aggregate_hops;
     a.kind = o.amg_kind;
     if (o.amg_strong_theta > 0) a.strong_theta = o.amg_strong_theta;
-    // K-cycles make the preconditioner nonlinear: CG runs in its flexible form;
-    // GMRES, BiCGStab and the FP32 inner solves keep V-cycles
-    a.kcycle = (o.krylov == VAG_CG && o.precision != VAG_MIXED_IR) ? o.amg_kcycle : 0;
+    // K-cycles make the preconditioner nonlinear: CG runs in its flexible form
+    // and GMRES is flexible; BiCGStab and the FP32 inner solves keep V-cycles
+    a.kcycle = ((o.krylov == VAG_CG || o.krylov == VAG_GMRES) && o.precision != VAG_MIXED_IR) ? o.amg_kcycle : 0;
     return a;
 }
 
@@ -535,10 +536,11 @@ void run_bicgstab(vag_handle *h) {
 
 // Scratch of GMRES(m) on n unknowns with vectors of type T.
 template <class T>
-GmresWork<T> gmres_work(vag_handle *h, int32_t n, DBuf<T> &V, DBuf<T> &w, DBuf<T> &t) {
+GmresWork<T> gmres_work(vag_handle *h, int32_t n, DBuf<T> &V, DBuf<T> &Z, DBuf<T> &w, DBuf<T> &t) {
     const int m = h->opt.gmres_restart;
     Tracker &tr = h->tr;
     ensure(V, (size_t)(m + 1) * (size_t)std::max(n, 1), tr);
+    ensure(Z, (size_t)m * (size_t)std::max(n, 1), tr);
     ensure(w, (size_t)std::max(n, 1), tr);
     ensure(t, (size_t)std::max(n, 1), tr);
     ensure(h->gmparts, (size_t)(m + 1) * gmres_grid(n), tr);
@@ -552,6 +554,7 @@ GmresWork<T> gmres_work(vag_handle *h, int32_t n, DBuf<T> &V, DBuf<T> &w, DBuf<T
     }
     GmresWork<T> W;
     W.V = V.p;
+    W.Z = Z.p;
     W.w = w.p;
     W.t = t.p;
     W.parts = h->gmparts.p;
@@ -561,12 +564,12 @@ GmresWork<T> gmres_work(vag_handle *h, int32_t n, DBuf<T> &V, DBuf<T> &w, DBuf<T
     return W;
 }
 
-// Right-preconditioned GMRES(m) from x = 0 in FP64 (the preconditioner may be
+// Flexible GMRES(m) from x = 0 in FP64 (the preconditioner may be
 // the FP32 hierarchy of VAG_MIXED).
 void run_gmres(vag_handle *h) {
     hipStream_t s = h->stream;
     const int32_t n = h->S.nunk;
-    const GmresWork<double> W = gmres_work<double>(h, n, h->gmV, h->gmw, h->gmt);
+    const GmresWork<double> W = gmres_work<double>(h, n, h->gmV, h->gmZ, h->gmw, h->gmt);
     launch_fill(s, n, 0.0, h->x.p);
     launch_residual_norm(s, h->Asell(), h->x.p, h->b.p, h->r.p, h->rparts.p, h->scal.p);
     VAG_HIP(hipMemcpyAsync(h->h_scal, h->scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -582,11 +585,12 @@ void run_gmres(vag_handle *h) {
     h->last_outer = 1;
 }
 
-// FP64 iterative refinement: r = b - A x in FP64.  With S = D^-1/2 the
-// correction solves (S A S) d = S r / ||S r|| by CG in FP32 with the FP32
-// hierarchy of S A S to inner_rtol, then x += ||S r|| S d in FP64.  The scaling
-// makes every FP32 matrix entry O(1) whatever the permeability contrast.
-// Stops when ||r|| <= rtol ||b||.
+// FP64 iterative refinement: r = b - A x in FP64; the correction solves
+// A d = r / ||r|| by CG or GMRES in FP32 (the FP32 copy of A, FP64 diagonal)
+// preconditioned by the FP32 hierarchy of A, to inner_rtol, then x += ||r|| d
+// in FP64.  Stops when ||r|| <= rtol ||b||.  The hierarchy is that of A
+// itself: its piecewise-constant interpolation carries the constants, the
+// near-null space of A, which a diagonally rescaled matrix would not have.
 void run_mixed(vag_handle *h) {
     hipStream_t s = h->stream;
     const int32_t n = h->S.nunk;
@@ -594,6 +598,7 @@ void run_mixed(vag_handle *h) {
     PcgState *st = h->pcg.p;
     Tracker &tr = h->tr;
     for (auto *v : {&h->b32, &h->x32, &h->r32, &h->z32, &h->p32, &h->q32}) ensure(*v, (size_t)std::max(n, 1), tr);
+    h->amg.stream_mode = h->opt.stream_loads;
     h->amg.make_fp32(s, tr, nullptr);
     const Sell<float> A32 = h->amg.L[0]->A32;
     launch_fill(s, n, 0.0, h->x.p);
@@ -607,17 +612,22 @@ void run_mixed(vag_handle *h) {
     bool converged = (rr <= tol2);
     while (!converged && inner_total < h->opt.max_iter) {
         ++outer;
-        launch_scaled_norm(s, n, h->dsc.p, h->r.p, h->rparts.p, h->scal.p + 2);
-        launch_scale_to_float(s, n, h->dsc.p, h->r.p, h->scal.p + 2, h->b32.p);
+        launch_norm2(s, n, h->r.p, h->rparts.p, h->scal.p + 2);
+        launch_normalize_to_float(s, n, h->r.p, h->scal.p + 2, h->b32.p);
         if (h->opt.krylov == VAG_GMRES) {
-            // inner FP32 GMRES(m) on the scaled system, ||b32|| = 1
-            const GmresWork<float> W = gmres_work<float>(h, n, h->gmV32, h->gmw32, h->gmt32);
+            // inner FP32 GMRES, ||b32|| = 1: one cycle of at most m iterations that
+            // stops when the Arnoldi estimate of its residual reaches inner_rtol.
+            // The true FP32 residual of an FP32 iterate cannot fall much below
+            // ||A|| ||x|| eps_32 / ||b|| (about 1e-2 at contrast 1e6), so restarts
+            // from it would stall; the FP64 refinement takes over instead.
+            const GmresWork<float> W = gmres_work<float>(h, n, h->gmV32, h->gmZ32, h->gmw32, h->gmt32);
             VAG_HIP(hipMemsetAsync(h->x32.p, 0, (size_t)n * sizeof(float), s));
+            const int cycle = std::min(h->opt.gmres_restart, h->opt.max_iter - inner_total);
             const GmresResult R = gmres_solve<float, float>(
-                s, A32, h->b32.p, h->x32.p, h->opt.inner_rtol, h->opt.gmres_restart, h->opt.max_iter - inner_total,
-                W, [&](const float *in, float *out) { h->amg.apply32(s, in, out, nullptr); });
+                s, A32, h->b32.p, h->x32.p, h->opt.inner_rtol, h->opt.gmres_restart, cycle, W,
+                [&](const float *in, float *out) { h->amg.apply32(s, in, out, nullptr); });
             inner_total += std::max(R.iterations, 1);
-            launch_correct(s, n, h->x.p, h->dsc.p, h->x32.p, h->scal.p + 2);
+            launch_correct(s, n, h->x.p, h->x32.p, h->scal.p + 2);
             launch_residual_norm(s, h->Asell(), h->x.p, h->b.p, h->r.p, h->rparts.p, h->scal.p);
             VAG_HIP(hipMemcpyAsync(h->h_scal, h->scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
             VAG_HIP(hipStreamSynchronize(s));
@@ -646,7 +656,7 @@ void run_mixed(vag_handle *h) {
             if (h->h_pcg->done || k >= budget) break;
         }
         inner_total += std::max(h->h_pcg->iter, 1);
-        launch_correct(s, n, h->x.p, h->dsc.p, h->x32.p, h->scal.p + 2);
+        launch_correct(s, n, h->x.p, h->x32.p, h->scal.p + 2);
         launch_residual_norm(s, h->Asell(), h->x.p, h->b.p, h->r.p, h->rparts.p, h->scal.p);
         VAG_HIP(hipMemcpyAsync(h->h_scal, h->scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipStreamSynchronize(s));
@@ -1018,15 +1028,9 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
                               h->grp_poff.p, h->grp_pos.p, h->frac_unk.p, h->Gb.p, h->A.p, h->b.p, h->bad.p);
         launch_diag_inv(s, n, h->diag_pos.p, h->A.p, h->dinv.p);
         VAG_HIP(hipEventRecord(h->ev[1], s));
-        if (h->opt.precision == VAG_MIXED_IR) {
-            // the single-precision hierarchy is built on the symmetrically scaled matrix
-            ensure(h->dsc, (size_t)std::max(n, 1), h->tr);
-            ensure(h->As, h->A.n, h->tr);
-            launch_fill(s, (int64_t)h->A.n, 0.0, h->As.p);
-            launch_diag_scaling(s, h->Asell(), h->diag_pos.p, h->dsc.p, h->As.p);
-            h->amg.setup(s, h->tr, h->with_col16(h->As.p), (int64_t)h->A.n, amg_options(h->opt));
-        } else if (h->opt.precond == VAG_PC_AMG) {
+        if (h->opt.precond == VAG_PC_AMG) {
             h->amg.setup(s, h->tr, h->Asell(), (int64_t)h->A.n, amg_options(h->opt));
+            h->amg.stream_mode = h->opt.stream_loads;
             if (h->opt.precision == VAG_MIXED) h->amg.make_fp32(s, h->tr, nullptr);
         } else if (h->opt.precond == VAG_PC_BJILU0) {
             const int B = h->opt.ilu_block_rows > 0 ? h->opt.ilu_block_rows : kIluDefaultBlock;
@@ -1432,7 +1436,7 @@ vag_status vag_apply_preconditioner(vag_handle *h, const double *r, double *z, v
     return guard(h, [&] {
         if (!h->solved) throw Error(VAG_ERR_STATE, "no pressure solve yet");
         if (h->opt.precision == VAG_MIXED_IR)
-            throw Error(VAG_ERR_UNSUPPORTED, "VAG_MIXED_IR preconditions the scaled FP32 system");
+            throw Error(VAG_ERR_UNSUPPORTED, "VAG_MIXED_IR applies its preconditioner to FP32 vectors inside the inner solve");
         const Symbolic &S = h->S;
         const int32_t n = S.nunk;
         hipStream_t s = h->stream;
@@ -1603,12 +1607,16 @@ size_t vag_estimate_footprint(int64_t nn, int64_t nc, int64_t nf, const vag_opti
     if (o.precond == VAG_PC_AMG) {
         double amg = 104 * Nx + 17 * S + 0.15 * (12 * S + 104 * Nx);
         if (o.precision == VAG_MIXED) amg += 4.6 * S + 50 * Nx;
-        if (o.precision == VAG_MIXED_IR) amg += 8 * S + 8 * Nx + 4.6 * S + 74 * Nx;
+        if (o.precision == VAG_MIXED_IR) amg += 4.6 * S + 74 * Nx;
         if (o.amg_kind == 1)  // denser levels, P, R, A P and the product tables of one chunk of rows
             amg += 1.5 * amg + 12 * 48 * Nx + 12 * 1024 * std::min(Nx, (double)kClChunk);
         b += 1.125 * amg + 1.5 * 1024 * 1024;                       // + dense coarsest inverse
     }
     if (o.precond == VAG_PC_BJILU0) b += 14 * nnz + 28 * Nx;        // factor entries, rows, schedules
+    if (o.krylov == VAG_GMRES) {  // flexible GMRES: m + 1 basis vectors, m preconditioned ones, two work vectors
+        const double m = o.gmres_restart > 0 ? o.gmres_restart : 100;
+        b += (2 * m + 3) * Nx * (o.precision == VAG_MIXED_IR ? 4.0 : 8.0) + 8 * (m + 1) * Nx / 256;
+    }
     return (size_t)(1.15 * b) + ((size_t)1 << 20);
 }
 

@@ -19,7 +19,12 @@ namespace vag {
 // cache (256 MB) together with its vectors is read with ordinary loads, since
 // it is read again by the next pass.
 constexpr int64_t kStreamBytes = int64_t(128) << 20;
-inline bool stream_matrix(int64_t stored, int value_bytes) { return stored * (value_bytes + 4) > kStreamBytes; }
+// mode (vag_options.stream_loads): 0 automatic (above kStreamBytes), 1 always, 2 never
+inline bool stream_matrix(int64_t stored, int value_bytes, int mode) {
+    if (mode == 1) return true;
+    if (mode == 2) return false;
+    return stored * (value_bytes + 4) > kStreamBytes;
+}
 template <bool NT, class T>
 __device__ __forceinline__ T ld_matrix(const T *p) {
     if constexpr (NT) return __builtin_nontemporal_load(p);
@@ -303,13 +308,10 @@ void launch_pcg_dot_rz(hipStream_t s, int32_t n, int k, const T *r, const T *z, 
 // x = 0, r = b, partials rr(-1) = b.b
 template <class T>
 void launch_pcg_init_plain(hipStream_t s, int32_t n, const T *b, T *x, T *r, PcgParts P);
-// mixed precision helpers with S = diag(sc) = D^-1/2:  out[0] = ||S r||^2;
-// r32 = S r / ||S r||; x += ||S r|| S d32; As = S A S
-void launch_scaled_norm(hipStream_t s, int32_t n, const double *sc, const double *r, double *parts, double *out);
-void launch_scale_to_float(hipStream_t s, int32_t n, const double *sc, const double *r, const double *nrm2,
-                           float *r32);
-void launch_correct(hipStream_t s, int32_t n, double *x, const double *sc, const float *d32, const double *nrm2);
-void launch_diag_scaling(hipStream_t s, Sell<double> A, const int32_t *diag_pos, double *sc, double *As);
+// FP64 refinement helpers: out[0] = ||r||^2; r32 = r / ||r||; x += ||r|| d32
+void launch_norm2(hipStream_t s, int32_t n, const double *r, double *parts, double *out);
+void launch_normalize_to_float(hipStream_t s, int32_t n, const double *r, const double *nrm2, float *r32);
+void launch_correct(hipStream_t s, int32_t n, double *x, const float *d32, const double *nrm2);
 
 // recovery, fluxes, transport
 void launch_node_pressure(hipStream_t s, int32_t nn, const int32_t *node_unk, const double *x,

@@ -579,3 +579,43 @@ def test_e2_convergence():
     assert em[0] > em[1] > em[2]
     assert ef[0] > ef[1] > ef[2]
     assert ef[2] < 0.05
+
+
+# ---------------------------------------------------------------------------
+# matrix-free residual (the full-size certificate of the GPU solves)
+# ---------------------------------------------------------------------------
+
+def _unknowns(p, res):
+    """Stack free-node and face entries in the assembled system's order."""
+    free = p.dirichlet == 0
+    return np.concatenate([res[0][free], res[1]])
+
+
+@pytest.mark.parametrize("seed,wells", [(0, False), (1, True), (2, False)])
+def test_residual_equals_assembled_system(seed, wells):
+    """orc_residual evaluates the conservation equations cell by cell; the
+    assembled Schur system (triplets summed into CSR, Dirichlet columns moved
+    to b) must give the same b and the same b - A x for any x."""
+    p = synth.random_problem((5, 4, 6), seed, n_patches=4)
+    if wells:
+        synth.add_wells(p, seed, n_inj=1, n_prod=2)
+    A, b = oracle.system(p)
+    rng = np.random.default_rng(seed)
+    free = p.dirichlet == 0
+    u_node = np.where(free, rng.standard_normal(p.n_nodes), 123.0)  # Dirichlet entries are ignored
+    u_frac = rng.standard_normal(p.n_frac)
+    x = np.concatenate([u_node[free], u_frac])
+    r = oracle.residual(p, u_node, u_frac)
+    scale = np.abs(A).max() * (np.abs(x).max() + np.abs(p.p_bar).max())
+    np.testing.assert_allclose(_unknowns(p, (r["b_node"], r["b_frac"])), b, rtol=0, atol=1e-13 * scale)
+    np.testing.assert_allclose(_unknowns(p, (r["res_node"], r["res_frac"])), b - A @ x, rtol=0, atol=1e-13 * scale)
+    assert (r["res_node"][~free] == 0).all() and (r["b_node"][~free] == 0).all()
+
+
+def test_residual_vanishes_on_affine_solution():
+    """Config 1: u = 1 - x at the nodes and 1/2 on the fracture is the exact
+    discrete solution, so every conservation equation holds to rounding."""
+    p = synth.config1()
+    r = oracle.residual(p, 1 - p.xyz[:, 0], np.full(p.n_frac, 0.5))
+    assert r["rel_residual"] < 1e-14
+    assert np.linalg.norm(np.concatenate([r["b_node"], r["b_frac"]])) > 0.1
