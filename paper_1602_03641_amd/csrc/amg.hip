@@ -1447,7 +1447,7 @@ void amg_launch_slices(hipStream_t s, int32_t n, const int32_t *rowlen, int32_t 
                        unsigned long long *nnz) {
     const int32_t ns = (n + 63) / 64;
     if (ns > 0) ALAUNCH(slice_width_kernel, ns, 64, n, rowlen, width, cnt);
-    launch_slice_scan(s, ns, width, ptr, cnt, nnz);
+    launch_slice_scan(s, ns, width, kSliceRows, ptr, cnt, nnz);
 }
 void amg_launch_slice_tail(hipStream_t s, int32_t n, const int64_t *ptr, int32_t *col, double *val) {
     if (n & 63) ALAUNCH(slice_tail_kernel, 1, 64, n, ptr, col, val);

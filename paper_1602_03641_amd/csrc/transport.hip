@@ -8,10 +8,12 @@
 // c^{n+1} = T c^n with, per control volume i and dt/phi_i = w_i,
 //   T_ii = 1 - w_i * (sum of outgoing fluxes), T_ij = w_i * (incoming flux from j).
 // Each pair (K,nu) contributes one off-diagonal, in the row of the downstream
-// control volume.  T is built once per transport call, stored in sliced ELL
-// (slices of 64 rows = one wavefront, column-major inside a slice), and every
-// step is one coalesced sweep over it.  Dirichlet nodes keep T_ii = 1, no
-// off-diagonal, so they stay at c_bar.
+// control volume.  T is built once per transport call in slices of 64 rows
+// (one wavefront), the rows of a slice sorted longest first; level k of a
+// slice holds entry k of its rows that have more than k entries, packed
+// densely (jagged diagonals), so no padding is stored or fetched, and every
+// step is one sweep over it in which each level is a coalesced run of loads.
+// Dirichlet nodes keep T_ii = 1, no off-diagonal, so they stay at c_bar.
 #include <mutex>
 
 #include "reduce.h"
@@ -315,10 +317,11 @@ __global__ __launch_bounds__(kSliceRows) void upwind_count_kernel(
     }
 }
 
-// exclusive scan of 64 * width over the slices, one block; with cnt, also
+// exclusive scan of per_width * w over the slices, one block; with cnt, also
 // *total = sum of cnt (the entries without padding)
 __global__ __launch_bounds__(1024) void slice_scan_kernel(int32_t nslice, const int32_t *__restrict__ w,
-                                                          int64_t *__restrict__ ptr, const int32_t *__restrict__ cnt,
+                                                          int per_width, int64_t *__restrict__ ptr,
+                                                          const int32_t *__restrict__ cnt,
                                                           unsigned long long *__restrict__ total) {
     __shared__ int64_t wsum[16], csum[16];
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
@@ -326,7 +329,7 @@ __global__ __launch_bounds__(1024) void slice_scan_kernel(int32_t nslice, const 
     const int32_t lo = min(nslice, t * chunk), hi = min(nslice, lo + chunk);
     int64_t s = 0, c = 0;
     for (int32_t k = lo; k < hi; ++k) {
-        s += (int64_t)w[k] * kSliceRows;
+        s += (int64_t)w[k] * per_width;
         if (cnt) c += cnt[k];
     }
     // inclusive scan over the block: within each wavefront, then over the 16 wavefront totals
@@ -352,7 +355,7 @@ __global__ __launch_bounds__(1024) void slice_scan_kernel(int32_t nslice, const 
     int64_t run = before + v - s;
     for (int32_t k = lo; k < hi; ++k) {
         ptr[k] = run;
-        run += (int64_t)w[k] * kSliceRows;
+        run += (int64_t)w[k] * per_width;
     }
 }
 
@@ -366,25 +369,38 @@ __global__ __launch_bounds__(kSliceRows) void upwind_fill_kernel(
     const double *__restrict__ phi_frac, const double *__restrict__ phi_node,
     const double *__restrict__ dtp, const int64_t *__restrict__ slice_ptr, const uint16_t *__restrict__ meta,
     int32_t *__restrict__ tcol, double *__restrict__ tval, double *__restrict__ tdiag) {
-    // slot threadIdx.x of the slice holds the row named by its meta entry
-    const int src = meta[(int64_t)blockIdx.x * kSliceRows + threadIdx.x] >> 8;
+    // slot threadIdx.x of the slice holds the row named by its meta entry;
+    // entry k of slot t goes to level_off[k] + t (level k holds the slots with
+    // more than k entries, which the longest-first order puts first)
+    __shared__ uint8_t cnts[kSliceRows];
+    __shared__ int32_t level_off[257];
+    const int lane = threadIdx.x;
+    const uint16_t mt = meta[(int64_t)blockIdx.x * kSliceRows + lane];
+    const int src = mt >> 8;
+    cnts[lane] = (uint8_t)(mt & 255);
+    __syncthreads();
+    const int width = cnts[0];
+    for (int k = lane; k < width; k += kSliceRows) {
+        int c = 0;
+        for (int u = 0; u < kSliceRows; ++u) c += cnts[u] > k;
+        level_off[k + 1] = c;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        level_off[0] = 0;
+        for (int k = 1; k <= width; ++k) level_off[k] += level_off[k - 1];
+    }
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * kSliceRows + src;
     const int64_t total = (int64_t)nc + nf + nn;
-    const int64_t base = slice_ptr[blockIdx.x] + threadIdx.x;
-    const int width = (int)((slice_ptr[blockIdx.x + 1] - slice_ptr[blockIdx.x]) / kSliceRows);
-    if (i >= total) {
-        for (int k = 0; k < width; ++k) {
-            tcol[base + (int64_t)k * kSliceRows] = 0;
-            tval[base + (int64_t)k * kSliceRows] = 0.0;
-        }
-        return;
-    }
+    if (i >= total) return;
+    const int64_t base = slice_ptr[blockIdx.x] + lane;
     const double dt = dtp[3];
     int k = 0;
     double d = 1.0;
     auto emit = [&](int64_t c, double v) {
-        tcol[base + (int64_t)k * kSliceRows] = (int32_t)c;
-        tval[base + (int64_t)k * kSliceRows] = v;
+        tcol[base + level_off[k]] = (int32_t)c;
+        tval[base + level_off[k]] = v;
         ++k;
     };
     const int32_t off_f = nc, off_n = nc + nf;
@@ -449,10 +465,6 @@ __global__ __launch_bounds__(kSliceRows) void upwind_fill_kernel(
             d = 1.0 + w * in_neg;
         }
     }
-    for (; k < width; ++k) {
-        tcol[base + (int64_t)k * kSliceRows] = (int32_t)i;
-        tval[base + (int64_t)k * kSliceRows] = 0.0;
-    }
     tdiag[i] = d;
 }
 
@@ -471,12 +483,10 @@ __global__ __launch_bounds__(kSliceRows) void upwind_pack_kernel(int32_t nrow, c
                                                                  int32_t *__restrict__ tbase) {
     const int32_t sl = blockIdx.x;
     const int lane = threadIdx.x;
-    const int64_t t = (int64_t)sl * kSliceRows + lane;
-    const int cnt = ((int64_t)sl * kSliceRows + (meta[t] >> 8) < nrow) ? (meta[t] & 255) : 0;
-    const int64_t b0 = slice_ptr[sl] + lane;
+    const int64_t b0 = slice_ptr[sl], b1 = slice_ptr[sl + 1];
     int32_t lo = INT32_MAX, hi = -1;
-    for (int k = 0; k < cnt; ++k) {
-        const int32_t c = tcol[b0 + (int64_t)k * kSliceRows];
+    for (int64_t q = b0 + lane; q < b1; q += kSliceRows) {
+        const int32_t c = tcol[q];
         lo = min(lo, c);
         hi = max(hi, c);
     }
@@ -487,50 +497,74 @@ __global__ __launch_bounds__(kSliceRows) void upwind_pack_kernel(int32_t nrow, c
     }
     const bool compact = hi < 0 || (int64_t)hi - lo <= 65535;
     if (compact)
-        for (int k = 0; k < cnt; ++k) {
-            const int64_t q = b0 + (int64_t)k * kSliceRows;
-            tcol16[q] = (uint16_t)(tcol[q] - lo);
-        }
+        for (int64_t q = b0 + lane; q < b1; q += kSliceRows) tcol16[q] = (uint16_t)(tcol[q] - lo);
     if (lane == 0) tbase[sl] = compact ? (hi < 0 ? 0 : lo) : -1;
 }
 
 // One explicit step, c_out = T c_in (theta < 1: the shortened last step of a
 // final-time run, c_in + theta (T c_in - c_in)).  Lane l of slice sl handles
-// the row named by meta[sl*64 + l] and stops after that row's own entries.
+// the row named by meta[sl*64 + l], which has m & 255 entries; level k starts
+// after the entries of the lower levels, whose sizes (the lanes with more than
+// k' entries) a ballot over the wavefront gives, so the packed layout needs
+// no stored level offsets.  Lanes are sorted longest first: lane 0 holds the
+// slice's widest row.
+// The row of one lane: level k of the slice starts at the sum of the sizes of
+// the levels below it (a ballot gives each size: the lanes with more than k
+// entries).  A lane without entry k loads a clamped address inside the slice
+// (lines the wavefront fetches anyway) and adds nothing, so the loop has no
+// branches and keeps the loads of four levels in flight.  A slice without
+// entries (last < level0) has width 0 and loads nothing.
+template <bool C16>
+__device__ __forceinline__ double upwind_row(const UpwindOp &T, const double *__restrict__ c_in, int cnt,
+                                             int width, int64_t level0, int64_t last, int lane, int32_t cb,
+                                             double a0) {
+    double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    auto col = [&](int64_t q) -> int32_t { return C16 ? cb + (int32_t)T.tcol16[q] : T.tcol[q]; };
+    int64_t lv = level0;  // start of level k
+    int k = 0;
+    for (; k + 3 < width; k += 4) {
+        const int n0 = __popcll(__ballot(cnt > k)), n1 = __popcll(__ballot(cnt > k + 1));
+        const int n2 = __popcll(__ballot(cnt > k + 2)), n3 = __popcll(__ballot(cnt > k + 3));
+        const int64_t p0 = lv + lane, p1 = p0 + n0, p2 = p1 + n1, p3 = p2 + n2;
+        const int64_t q0 = p0 < last ? p0 : last, q1 = p1 < last ? p1 : last;
+        const int64_t q2 = p2 < last ? p2 : last, q3 = p3 < last ? p3 : last;
+        // columns, values, then the gathers: twelve loads in flight
+        const int32_t c0 = col(q0), c1 = col(q1), c2 = col(q2), c3 = col(q3);
+        const double v0 = T.tval[q0], v1 = T.tval[q1], v2 = T.tval[q2], v3 = T.tval[q3];
+        const double x0 = c_in[c0], x1 = c_in[c1], x2 = c_in[c2], x3 = c_in[c3];
+        a1 += cnt > k ? v0 * x0 : 0.0;
+        a2 += cnt > k + 1 ? v1 * x1 : 0.0;
+        a3 += cnt > k + 2 ? v2 * x2 : 0.0;
+        a0 += cnt > k + 3 ? v3 * x3 : 0.0;
+        lv += n0 + n1 + n2 + n3;
+    }
+    for (; k < width; ++k) {
+        const int n0 = __popcll(__ballot(cnt > k));
+        const int64_t p0 = lv + lane, q0 = p0 < last ? p0 : last;
+        const double v0 = T.tval[q0] * c_in[col(q0)];
+        a1 += cnt > k ? v0 : 0.0;
+        lv += n0;
+    }
+    return (a0 + a1) + (a2 + a3);
+}
+
 __global__ __launch_bounds__(256) void transport_step_kernel(UpwindOp T, const double *__restrict__ c_in,
                                                              double *__restrict__ c_out, double theta) {
     const int32_t t = xcd_block() * blockDim.x + threadIdx.x;
     const int32_t sl = t / kSliceRows, lane = t % kSliceRows;
-    if ((int64_t)sl * kSliceRows >= T.nrow) return;
+    if ((int64_t)sl * kSliceRows >= T.nrow) return;  // whole wavefronts
     const uint16_t m = T.meta[t];
     const int32_t i = sl * kSliceRows + (m >> 8);
-    if (i >= T.nrow) return;
-    const int64_t b0 = T.slice_ptr[sl], b1 = b0 + (int64_t)(m & 255) * kSliceRows;
+    const bool row = i < T.nrow;
+    const int cnt = row ? (m & 255) : 0;
+    const int width = __shfl(cnt, 0, kSliceRows);
+    const int64_t level0 = T.slice_ptr[sl], last = T.slice_ptr[sl + 1] - 1;
     const int32_t cb = T.tbase[sl];
-    const double ci = c_in[i];
-    double a0 = T.tdiag[i] * ci, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int64_t q = b0 + lane;
-    if (cb >= 0) {  // uniform over the wavefront (one slice)
-        const uint16_t *__restrict__ col = T.tcol16;
-        for (; q + 3 * kSliceRows < b1; q += 4 * kSliceRows) {
-            a1 += T.tval[q] * c_in[cb + col[q]];
-            a2 += T.tval[q + kSliceRows] * c_in[cb + col[q + kSliceRows]];
-            a3 += T.tval[q + 2 * kSliceRows] * c_in[cb + col[q + 2 * kSliceRows]];
-            a0 += T.tval[q + 3 * kSliceRows] * c_in[cb + col[q + 3 * kSliceRows]];
-        }
-        for (; q < b1; q += kSliceRows) a1 += T.tval[q] * c_in[cb + col[q]];
-    } else {
-        const int32_t *__restrict__ col = T.tcol;
-        for (; q + 3 * kSliceRows < b1; q += 4 * kSliceRows) {
-            a1 += T.tval[q] * c_in[col[q]];
-            a2 += T.tval[q + kSliceRows] * c_in[col[q + kSliceRows]];
-            a3 += T.tval[q + 2 * kSliceRows] * c_in[col[q + 2 * kSliceRows]];
-            a0 += T.tval[q + 3 * kSliceRows] * c_in[col[q + 3 * kSliceRows]];
-        }
-        for (; q < b1; q += kSliceRows) a1 += T.tval[q] * c_in[col[q]];
-    }
-    const double acc = (a0 + a1) + (a2 + a3);
-    c_out[i] = (theta == 1.0) ? acc : ci + theta * (acc - ci);
+    const double ci = row ? c_in[i] : 0.0;
+    const double d = row ? T.tdiag[i] * ci : 0.0;
+    const double acc = cb >= 0 ? upwind_row<true>(T, c_in, cnt, width, level0, last, lane, cb, d)
+                               : upwind_row<false>(T, c_in, cnt, width, level0, last, lane, cb, d);
+    if (row) c_out[i] = (theta == 1.0) ? acc : ci + theta * (acc - ci);
 }
 
 // One explicit step without the upwind operator (the entry point for callers
@@ -708,9 +742,10 @@ void launch_upwind_count(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, cons
                        F_cell_frac, F_frac, wsrc, slice_width, meta, slice_nnz);
     VAG_HIP(hipGetLastError());
 }
-void launch_slice_scan(hipStream_t s, int32_t nslice, const int32_t *slice_width, int64_t *slice_ptr,
+void launch_slice_scan(hipStream_t s, int32_t nslice, const int32_t *slice_width, int per_width, int64_t *slice_ptr,
                        const int32_t *slice_nnz, unsigned long long *total) {
-    hipLaunchKernelGGL(slice_scan_kernel, dim3(1), dim3(1024), 0, s, nslice, slice_width, slice_ptr, slice_nnz, total);
+    hipLaunchKernelGGL(slice_scan_kernel, dim3(1), dim3(1024), 0, s, nslice, slice_width, per_width, slice_ptr,
+                       slice_nnz, total);
     VAG_HIP(hipGetLastError());
 }
 void launch_upwind_fill(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,

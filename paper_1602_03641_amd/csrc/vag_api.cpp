@@ -1132,7 +1132,7 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
                             h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
                             h->F_cell_frac.p, h->F_frac.p, h->well_src(), h->slice_width.p, h->tmeta.p,
                             h->slice_nnz.p);
-        launch_slice_scan(s, nslice, h->slice_width.p, h->slice_ptr.p, h->slice_nnz.p, h->cnt.p);
+        launch_slice_scan(s, nslice, h->slice_nnz.p, 1, h->slice_ptr.p, h->slice_nnz.p, h->cnt.p);
         int64_t total = 0;
         VAG_HIP(hipMemcpyAsync(&total, h->slice_ptr.p + nslice, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipMemcpyAsync(h->h_cnt, h->cnt.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));

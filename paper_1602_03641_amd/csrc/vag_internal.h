@@ -342,8 +342,9 @@ void launch_upwind_count(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, cons
                          const int32_t *node_frac_ptr, const int32_t *node_frac, const double *F_cell,
                          const double *F_cell_frac, const double *F_frac, const double *wsrc, int32_t *slice_width,
                          uint16_t *meta, int32_t *slice_nnz);
-// slice_ptr = exclusive scan of 64 * width; with slice_nnz, *total = its sum
-void launch_slice_scan(hipStream_t s, int32_t nslice, const int32_t *slice_width, int64_t *slice_ptr,
+// slice_ptr = exclusive scan of per_width * slice_width (64 for padded
+// sliced ELL, 1 for counts of packed entries); with slice_nnz, *total = its sum
+void launch_slice_scan(hipStream_t s, int32_t nslice, const int32_t *slice_width, int per_width, int64_t *slice_ptr,
                        const int32_t *slice_nnz = nullptr, unsigned long long *total = nullptr);
 void launch_upwind_fill(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,
                         const uint8_t *fmask, const int32_t *cell_frac, const int32_t *frac_cell,
@@ -357,6 +358,10 @@ void launch_upwind_fill(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const
 // The upwind operator in sliced ELL: meta[slot] = (lane of the row in its
 // slice) << 8 | entry count (the rows of a slice are stored longest first);
 // 32-bit columns, and 16-bit offsets from tbase[slice] where tbase >= 0.
+// Upwind operator: 64-row slices (rows sorted longest first, meta = source
+// lane << 8 | entry count per slot), entries packed by level (jagged
+// diagonals) from slice_ptr[slice]; 16-bit columns from tbase[slice] where
+// tbase >= 0, else the 32-bit tcol.
 struct UpwindOp {
     int32_t nrow;
     const int64_t *slice_ptr;
