@@ -81,31 +81,57 @@ typedef enum { VAG_CG = 0, VAG_GMRES = 1, VAG_BICGSTAB = 2 } vag_krylov;
 typedef enum { VAG_PC_JACOBI = 0, VAG_PC_AMG = 1, VAG_PC_BJILU0 = 2 } vag_precond;
 
 /*
- * Generalised polyhedral mesh restricted to hexahedra (§3.1).  Each cell lists
- * its 8 nodes in VTK order (bottom quad counter-clockwise seen from above, then
- * the top quad); faces may be non-planar.  The cell centre is the mean of its
- * nodes and a face centre the mean of its 4 nodes (beta = 1/4).  Every one of
- * the 24 sub-tetrahedra (x_K, x_sigma, edge) must have positive volume.
+ * Generalised polyhedral mesh (§3.1), in one of two forms.
+ *
+ * hex8 != NULL (the fast path): hexahedra, each listing its 8 nodes in VTK
+ * order (bottom quad counter-clockwise seen from above, then the top quad);
+ * faces may be non-planar.  Every one of the 24 sub-tetrahedra (x_K, x_sigma,
+ * edge) must have positive volume.
+ *
+ * hex8 == NULL: general cells given by their faces.  cell_faces lists the
+ * faces of each cell (CSR by cell_face_ptr, 4 to 6 faces), face_nodes the
+ * nodes of each face in cyclic order (CSR by face_node_ptr, 3 or 4 nodes;
+ * consecutive nodes are the face's edges); a face is shared by at most two
+ * cells and may be listed in either orientation.  A cell has 4 to 8 nodes,
+ * the union of its faces' nodes; its local node order is the order in which
+ * they first appear along its faces (cell_faces order, each face's node
+ * order).  This covers the tetrahedra, pyramids, prisms and hexahedra of the
+ * paper's experiments (§5.4, §5.5).  On every face the k sub-tetrahedra
+ * (x_K, x_sigma, s_e, s_e+1) must have volumes of one sign and none zero (a
+ * cell star-shaped with respect to its centre).  Fracture-face groups are
+ * never eliminated on this path (the faces stay unknowns), and
+ * vag_transport_noalloc returns VAG_ERR_UNSUPPORTED.
+ *
+ * In both forms the cell centre is the mean of the cell's nodes and a face
+ * centre the mean of the face's nodes (beta = 1/|V_sigma|).
  */
 typedef struct {
     int64_t n_nodes;
     int64_t n_cells;
     const double *node_xyz;  /* [n_nodes][3] */
-    const int32_t *hex8;     /* [n_cells][8] */
+    const int32_t *hex8;     /* [n_cells][8], or NULL for the general form */
+    /* general form (read when hex8 is NULL) */
+    int64_t n_faces;
+    const int64_t *cell_face_ptr;  /* [n_cells + 1] */
+    const int32_t *cell_faces;     /* [cell_face_ptr[n_cells]] face indices */
+    const int64_t *face_node_ptr;  /* [n_faces + 1] */
+    const int32_t *face_nodes;     /* [face_node_ptr[n_faces]] node indices, cyclic per face */
 } vag_mesh;
 
 /*
- * Fracture faces F_Gamma (§3.1: the fracture network is a union of mesh faces).
- * Each is given by its 4 nodes in cyclic order; it must be a face of one or two
- * cells and listed once.  width = d_f, perm = Lambda_f (isotropic in the
- * plane), porosity = phi_f, each per fracture face.
+ * Fracture faces F_Gamma (§3.1: the fracture network is a union of mesh faces),
+ * each listed once.  With a hex8 mesh each is given by its 4 nodes in cyclic
+ * order (face_nodes) and must be a face of one or two cells; with the general
+ * form by its index in the mesh's face list (face_ids).  width = d_f, perm =
+ * Lambda_f (isotropic in the plane), porosity = phi_f, each per fracture face.
  */
 typedef struct {
     int64_t n_frac;
-    const int32_t *face_nodes;  /* [n_frac][4] */
+    const int32_t *face_nodes;  /* [n_frac][4], hex8 meshes */
     const double *width;        /* [n_frac] */
     const double *perm;         /* [n_frac] */
     const double *porosity;     /* [n_frac] */
+    const int32_t *face_ids;    /* [n_frac], general meshes: indices into the mesh's faces */
 } vag_fractures;
 
 /* Matrix rock: symmetric positive definite Lambda_m per cell packed
@@ -312,7 +338,8 @@ vag_status vag_set_fluxes(vag_handle *h, const double *F_cell, const double *F_c
  * face is perforated at most once; wi >= 0; arrays of n values in mem,
  * copied.  n = 0 removes the wells.  Takes effect at the next
  * vag_solve_pressure.  VAG_ERR_ARG for a face out of range or perforated
- * twice, a negative WI or a value that is not finite. */
+ * twice, a negative WI or a value that is not finite; VAG_ERR_UNSUPPORTED
+ * on a mesh without hex8. */
 vag_status vag_set_wells(vag_handle *h, int64_t n, const int32_t *face, const double *wi, const double *p_w,
                          const double *q, const double *c_inj, vag_mem mem);
 /* Q_k of the last solve (or of vag_set_well_rates), n values. */
@@ -335,9 +362,18 @@ vag_status vag_get_pressure(vag_handle *h, double *u_node, double *u_cell, doubl
 
 /* Fluxes: F_cell[n_cells][8] = F_{K,s} in VTK node order; F_cell_frac[n_frac][2]
  * = F_{K,sigma} for the cells of sigma by ascending cell index (0 for a missing
- * second cell); F_frac[n_frac][4] = F_{sigma,s} in the face's input node order. */
+ * second cell); F_frac[n_frac][4] = F_{sigma,s} in the face's input node order.
+ * General meshes: F_cell holds, cell after cell, F_{K,s} for the cell's nodes
+ * in its local node order (sum over the cells of their node counts values),
+ * F_frac, face after face, F_{sigma,s} for each fracture face's nodes in the
+ * order of face_nodes (sum of their node counts values). */
 vag_status vag_get_fluxes(vag_handle *h, double *F_cell, double *F_cell_frac, double *F_frac,
                           vag_mem mem);
+
+/* Sizes of the F_cell and F_frac arrays of vag_get_fluxes / vag_set_fluxes:
+ * 8 n_cells and 4 n_frac for hex8 meshes, the sums of the cells' and of the
+ * fracture faces' node counts for general meshes. */
+vag_status vag_flux_layout(const vag_handle *h, int64_t *n_cell_flux, int64_t *n_frac_flux);
 
 /* Porous volumes phi_K, phi_sigma, phi_s (0 at Dirichlet nodes). */
 vag_status vag_get_porous_volumes(vag_handle *h, double *phi_cell, double *phi_frac,
@@ -481,7 +517,7 @@ vag_status vag_server_create(size_t hbm_budget, int n_workers, vag_server **out)
 
 /* Copies the job's input arrays (host memory) and queues it; returns at once.
  * VAG_ERR_OOM when the job's estimate exceeds the whole budget, VAG_ERR_ARG
- * for missing inputs. */
+ * for missing inputs, VAG_ERR_UNSUPPORTED for a mesh without hex8. */
 vag_status vag_server_submit(vag_server *s, const vag_job *job, uint64_t *job_id);
 
 /* Waits up to timeout_s seconds (< 0: no limit) for the job.  VAG_OK: *res is

@@ -287,6 +287,7 @@ vag_status vag_server_submit(vag_server *s, const vag_job *job, uint64_t *job_id
     const vag_mesh *m = job->mesh;
     const int64_t nn = m->n_nodes, nc = m->n_cells, nf = job->frac ? job->frac->n_frac : 0;
     if (nn <= 0 || nc <= 0 || nf < 0 || job->n_steps < 0 || job->t_final < 0) return VAG_ERR_ARG;
+    if (!m->hex8) return VAG_ERR_UNSUPPORTED;  // jobs take hex8 meshes
     auto j = std::make_unique<Job>();
     try {
         j->nn = nn;

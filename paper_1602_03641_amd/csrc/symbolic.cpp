@@ -65,6 +65,77 @@ bool same_cycle(const int32_t *a, const int32_t *b) {
 
 }  // namespace
 
+void finish_symbolic_pattern(Symbolic &S) {
+    const int32_t nn = S.nn, nf = S.nf, nfree = S.nfree;
+    // Renumber the system rows so that, inside windows of kSortWindow rows
+    // (node rows and face rows apart), longer rows come first (stable):
+    // slices then hold rows of similar length and carry little padding,
+    // while rows of equal length keep their order and their locality.
+    {
+        const int32_t n = S.nunk;
+        std::vector<int32_t> order(n);
+        for (int32_t r = 0; r < n; ++r) order[r] = r;
+        auto len = [&](int32_t r) { return S.row_ptr[r + 1] - S.row_ptr[r]; };
+        auto sort_block = [&](int32_t b0, int32_t b1) {
+            for (int32_t w0 = b0; w0 < b1; w0 += kSortWindow) {
+                const int32_t w1 = std::min(b1, w0 + kSortWindow);
+                std::stable_sort(order.begin() + w0, order.begin() + w1,
+                                 [&](int32_t x, int32_t y) { return len(x) > len(y); });
+            }
+        };
+        sort_block(0, nfree);
+        sort_block(nfree, n);
+        S.sys_old.assign(order.begin(), order.end());  // new row -> old row
+        S.sys_new.assign(n, -1);                        // old row -> new row
+        for (int32_t r = 0; r < n; ++r) S.sys_new[order[r]] = r;
+        // pattern in the new numbering
+        std::vector<int32_t> rp(n + 1, 0), cl(S.col.size());
+        for (int32_t r = 0; r < n; ++r) rp[r + 1] = rp[r] + len(order[r]);
+        parallel_chunks(n, [&](int, int64_t r0, int64_t r1) {
+            for (int32_t r = (int32_t)r0; r < (int32_t)r1; ++r) {
+                const int32_t o = order[r];
+                int32_t *out = cl.data() + rp[r];
+                for (int32_t q = S.row_ptr[o]; q < S.row_ptr[o + 1]; ++q) *out++ = S.sys_new[S.col[q]];
+                std::sort(cl.data() + rp[r], out);
+            }
+        });
+        S.row_ptr.swap(rp);
+        S.col.swap(cl);
+        for (auto &u : S.node_unk)
+            if (u >= 0) u = S.sys_new[u];
+        for (auto &u : S.frac_unk)
+            if (u < n) u = S.sys_new[u];
+        for (int32_t G = 0; G < S.ngroup; ++G) {
+            for (int32_t q = S.grp_nptr[G]; q < S.grp_nptr[G + 1]; ++q) S.grp_node[q] = S.sys_new[S.grp_node[q]];
+            std::sort(S.grp_node.begin() + S.grp_nptr[G], S.grp_node.begin() + S.grp_nptr[G + 1]);
+        }
+    }
+
+    // sliced ELL slice pointers (64-row slices, width = longest row); the
+    // column array itself is filled on the device from the CSR pattern
+    {
+        const int32_t n = S.nunk;
+        const int64_t nslice = (n + kSliceRows - 1) / kSliceRows;
+        S.sell_ptr.assign(nslice + 1, 0);
+        for (int64_t sl = 0; sl < nslice; ++sl) {
+            int32_t w = 0;
+            for (int32_t r = (int32_t)(sl * kSliceRows); r < std::min<int64_t>(n, (sl + 1) * kSliceRows); ++r)
+                w = std::max(w, S.row_ptr[r + 1] - S.row_ptr[r]);
+            S.sell_ptr[sl + 1] = S.sell_ptr[sl] + (int64_t)w * kSliceRows;
+        }
+        if (S.sell_ptr[nslice] >= INT32_MAX)
+            throw Error(VAG_ERR_UNSUPPORTED, "padded system has more than 2^31 entries");
+    }
+
+    // row -> node or kept face, face -> (group, local index)
+    S.unk_node.assign(nfree, -1);
+    for (int32_t s = 0; s < nn; ++s)
+        if (S.node_unk[s] >= 0) S.unk_node[S.node_unk[s]] = s;
+    S.unk_face.assign(S.nunk - nfree, -1);
+    for (int32_t f = 0; f < nf; ++f)
+        if (S.frac_unk[f] < S.nunk) S.unk_face[S.frac_unk[f] - nfree] = f;
+}
+
 void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex8,
                     const int32_t *frac_nodes, const uint8_t *dirichlet, bool eliminate, Symbolic &S) {
     if (nn64 <= 0 || nc64 <= 0 || nf64 < 0 || nn64 >= INT32_MAX || nc64 >= INT32_MAX / 8 ||
@@ -388,73 +459,7 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
     }
     S.nnz = S.row_ptr[S.nunk];
 
-    // Renumber the system rows so that, inside windows of kSortWindow rows
-    // (node rows and face rows apart), longer rows come first (stable):
-    // slices then hold rows of similar length and carry little padding,
-    // while rows of equal length keep their order and their locality.
-    {
-        const int32_t n = S.nunk;
-        std::vector<int32_t> order(n);
-        for (int32_t r = 0; r < n; ++r) order[r] = r;
-        auto len = [&](int32_t r) { return S.row_ptr[r + 1] - S.row_ptr[r]; };
-        auto sort_block = [&](int32_t b0, int32_t b1) {
-            for (int32_t w0 = b0; w0 < b1; w0 += kSortWindow) {
-                const int32_t w1 = std::min(b1, w0 + kSortWindow);
-                std::stable_sort(order.begin() + w0, order.begin() + w1,
-                                 [&](int32_t x, int32_t y) { return len(x) > len(y); });
-            }
-        };
-        sort_block(0, nfree);
-        sort_block(nfree, n);
-        S.sys_old.assign(order.begin(), order.end());  // new row -> old row
-        S.sys_new.assign(n, -1);                        // old row -> new row
-        for (int32_t r = 0; r < n; ++r) S.sys_new[order[r]] = r;
-        // pattern in the new numbering
-        std::vector<int32_t> rp(n + 1, 0), cl(S.col.size());
-        for (int32_t r = 0; r < n; ++r) rp[r + 1] = rp[r] + len(order[r]);
-        parallel_chunks(n, [&](int, int64_t r0, int64_t r1) {
-            for (int32_t r = (int32_t)r0; r < (int32_t)r1; ++r) {
-                const int32_t o = order[r];
-                int32_t *out = cl.data() + rp[r];
-                for (int32_t q = S.row_ptr[o]; q < S.row_ptr[o + 1]; ++q) *out++ = S.sys_new[S.col[q]];
-                std::sort(cl.data() + rp[r], out);
-            }
-        });
-        S.row_ptr.swap(rp);
-        S.col.swap(cl);
-        for (auto &u : S.node_unk)
-            if (u >= 0) u = S.sys_new[u];
-        for (auto &u : S.frac_unk)
-            if (u < n) u = S.sys_new[u];
-        for (int32_t G = 0; G < S.ngroup; ++G) {
-            for (int32_t q = S.grp_nptr[G]; q < S.grp_nptr[G + 1]; ++q) S.grp_node[q] = S.sys_new[S.grp_node[q]];
-            std::sort(S.grp_node.begin() + S.grp_nptr[G], S.grp_node.begin() + S.grp_nptr[G + 1]);
-        }
-    }
-
-    // sliced ELL slice pointers (64-row slices, width = longest row); the
-    // column array itself is filled on the device from the CSR pattern
-    {
-        const int32_t n = S.nunk;
-        const int64_t nslice = (n + kSliceRows - 1) / kSliceRows;
-        S.sell_ptr.assign(nslice + 1, 0);
-        for (int64_t sl = 0; sl < nslice; ++sl) {
-            int32_t w = 0;
-            for (int32_t r = (int32_t)(sl * kSliceRows); r < std::min<int64_t>(n, (sl + 1) * kSliceRows); ++r)
-                w = std::max(w, S.row_ptr[r + 1] - S.row_ptr[r]);
-            S.sell_ptr[sl + 1] = S.sell_ptr[sl] + (int64_t)w * kSliceRows;
-        }
-        if (S.sell_ptr[nslice] >= INT32_MAX)
-            throw Error(VAG_ERR_UNSUPPORTED, "padded system has more than 2^31 entries");
-    }
-
-    // row -> node or kept face, face -> (group, local index)
-    S.unk_node.assign(nfree, -1);
-    for (int32_t s = 0; s < nn; ++s)
-        if (S.node_unk[s] >= 0) S.unk_node[S.node_unk[s]] = s;
-    S.unk_face.assign(S.nunk - nfree, -1);
-    for (int32_t f = 0; f < nf; ++f)
-        if (S.frac_unk[f] < S.nunk) S.unk_face[S.frac_unk[f] - nfree] = f;
+    finish_symbolic_pattern(S);
     S.face_grp = std::move(face_grp);
     S.face_loc = std::move(face_loc);
 }

@@ -271,21 +271,10 @@ __device__ inline int upwind_row_count(int64_t i, int32_t nc, int32_t nf, const 
     return c;
 }
 
-__global__ __launch_bounds__(kSliceRows) void upwind_count_kernel(
-    int32_t nc, int32_t nf, int32_t nn, const uint8_t *__restrict__ fmask, const int32_t *__restrict__ cell_frac,
-    const int32_t *__restrict__ frac_cell, const uint8_t *__restrict__ dirichlet, const int32_t *__restrict__ ncp,
-    const int32_t *__restrict__ ncl, const int32_t *__restrict__ nfp, const int32_t *__restrict__ nfl,
-    const double *__restrict__ F_cell, const double *__restrict__ F_cell_frac, const double *__restrict__ F_frac,
-    const double *__restrict__ wsrc, int32_t *__restrict__ slice_width, uint16_t *__restrict__ meta,
-    int32_t *__restrict__ slice_nnz) {
-    // one block = one wavefront = one slice
-    const int lane = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * kSliceRows + lane;
-    const int64_t total = (int64_t)nc + nf + nn;
-    int c = 0;
-    if (i < total)
-        c = upwind_row_count(i, nc, nf, fmask, cell_frac, frac_cell, dirichlet, ncp, ncl, nfp, nfl, F_cell,
-                             F_cell_frac, F_frac, wsrc);
+// Sorts the rows of a slice (one wavefront, lane = row in the slice, c = its
+// entry count) longest first and writes meta, the slice's width and count.
+__device__ inline void slice_sort_rows(int c, int lane, int32_t *__restrict__ slice_width,
+                                       uint16_t *__restrict__ meta, int32_t *__restrict__ slice_nnz) {
     // sort the slice's rows by entry count, longest first (ties: lower lane
     // first), with a bitonic network over the wavefront: slot l then holds
     // the l-th longest row, so the lanes that run out of entries are the last
@@ -315,6 +304,24 @@ __global__ __launch_bounds__(kSliceRows) void upwind_count_kernel(
         slice_width[blockIdx.x] = w;
         slice_nnz[blockIdx.x] = sum;
     }
+}
+
+__global__ __launch_bounds__(kSliceRows) void upwind_count_kernel(
+    int32_t nc, int32_t nf, int32_t nn, const uint8_t *__restrict__ fmask, const int32_t *__restrict__ cell_frac,
+    const int32_t *__restrict__ frac_cell, const uint8_t *__restrict__ dirichlet, const int32_t *__restrict__ ncp,
+    const int32_t *__restrict__ ncl, const int32_t *__restrict__ nfp, const int32_t *__restrict__ nfl,
+    const double *__restrict__ F_cell, const double *__restrict__ F_cell_frac, const double *__restrict__ F_frac,
+    const double *__restrict__ wsrc, int32_t *__restrict__ slice_width, uint16_t *__restrict__ meta,
+    int32_t *__restrict__ slice_nnz) {
+    // one block = one wavefront = one slice
+    const int lane = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kSliceRows + lane;
+    const int64_t total = (int64_t)nc + nf + nn;
+    int c = 0;
+    if (i < total)
+        c = upwind_row_count(i, nc, nf, fmask, cell_frac, frac_cell, dirichlet, ncp, ncl, nfp, nfl, F_cell,
+                             F_cell_frac, F_frac, wsrc);
+    slice_sort_rows(c, lane, slice_width, meta, slice_nnz);
 }
 
 // exclusive scan of per_width * w over the slices, one block; with cnt, also
@@ -359,24 +366,13 @@ __global__ __launch_bounds__(1024) void slice_scan_kernel(int32_t nslice, const 
     }
 }
 
-__global__ __launch_bounds__(kSliceRows) void upwind_fill_kernel(
-    int32_t nc, int32_t nf, int32_t nn, const int32_t *__restrict__ hex8, const uint8_t *__restrict__ fmask,
-    const int32_t *__restrict__ cell_frac, const int32_t *__restrict__ frac_cell,
-    const int32_t *__restrict__ frac_nodes, const uint8_t *__restrict__ dirichlet, const int32_t *__restrict__ ncp,
-    const int32_t *__restrict__ ncl, const int32_t *__restrict__ nfp, const int32_t *__restrict__ nfl,
-    const double *__restrict__ F_cell, const double *__restrict__ F_cell_frac, const double *__restrict__ F_frac,
-    const double *__restrict__ wsrc, const double *__restrict__ wout, const double *__restrict__ phi_cell,
-    const double *__restrict__ phi_frac, const double *__restrict__ phi_node,
-    const double *__restrict__ dtp, const int64_t *__restrict__ slice_ptr, const uint16_t *__restrict__ meta,
-    int32_t *__restrict__ tcol, double *__restrict__ tval, double *__restrict__ tdiag) {
-    // slot threadIdx.x of the slice holds the row named by its meta entry;
-    // entry k of slot t goes to level_off[k] + t (level k holds the slots with
-    // more than k entries, which the longest-first order puts first)
-    __shared__ uint8_t cnts[kSliceRows];
-    __shared__ int32_t level_off[257];
+// Slot threadIdx.x of the slice (one block of 64 threads) holds the row named
+// by its meta entry, returned; entry k of slot t goes to level_off[k] + t
+// (level k holds the slots with more than k entries, which the longest-first
+// order puts first).  cnts and level_off are the block's shared arrays.
+__device__ inline int slice_levels(const uint16_t *__restrict__ meta, uint8_t *cnts, int32_t *level_off) {
     const int lane = threadIdx.x;
     const uint16_t mt = meta[(int64_t)blockIdx.x * kSliceRows + lane];
-    const int src = mt >> 8;
     cnts[lane] = (uint8_t)(mt & 255);
     __syncthreads();
     const int width = cnts[0];
@@ -391,6 +387,23 @@ __global__ __launch_bounds__(kSliceRows) void upwind_fill_kernel(
         for (int k = 1; k <= width; ++k) level_off[k] += level_off[k - 1];
     }
     __syncthreads();
+    return mt >> 8;
+}
+
+__global__ __launch_bounds__(kSliceRows) void upwind_fill_kernel(
+    int32_t nc, int32_t nf, int32_t nn, const int32_t *__restrict__ hex8, const uint8_t *__restrict__ fmask,
+    const int32_t *__restrict__ cell_frac, const int32_t *__restrict__ frac_cell,
+    const int32_t *__restrict__ frac_nodes, const uint8_t *__restrict__ dirichlet, const int32_t *__restrict__ ncp,
+    const int32_t *__restrict__ ncl, const int32_t *__restrict__ nfp, const int32_t *__restrict__ nfl,
+    const double *__restrict__ F_cell, const double *__restrict__ F_cell_frac, const double *__restrict__ F_frac,
+    const double *__restrict__ wsrc, const double *__restrict__ wout, const double *__restrict__ phi_cell,
+    const double *__restrict__ phi_frac, const double *__restrict__ phi_node,
+    const double *__restrict__ dtp, const int64_t *__restrict__ slice_ptr, const uint16_t *__restrict__ meta,
+    int32_t *__restrict__ tcol, double *__restrict__ tval, double *__restrict__ tdiag) {
+    __shared__ uint8_t cnts[kSliceRows];
+    __shared__ int32_t level_off[257];
+    const int lane = threadIdx.x;
+    const int src = slice_levels(meta, cnts, level_off);
     const int64_t i = (int64_t)blockIdx.x * kSliceRows + src;
     const int64_t total = (int64_t)nc + nf + nn;
     if (i >= total) return;
@@ -682,6 +695,107 @@ __global__ void set_dirichlet_kernel(int32_t nn, int32_t offset, const uint8_t *
 }
 
 // ---------------------------------------------------------------------------
+// general cells: the same steps on the incidence lists of the control volumes
+// ---------------------------------------------------------------------------
+// Flux F_e leaves the first control volume of edge e when positive; at the
+// far end (edge & 1) it counts with the opposite sign.
+__device__ inline double inc_flux(const GenInc &I, const double *F, int64_t q) {
+    const int32_t e = I.edge[q];
+    const double f = F[e >> 1];
+    return (e & 1) ? -f : f;
+}
+
+__global__ __launch_bounds__(kT) void gen_cfl_kernel(GenInc I, const double *__restrict__ F,
+                                                     const double *__restrict__ wout,
+                                                     const double *__restrict__ phi_cell,
+                                                     const double *__restrict__ phi_frac,
+                                                     const double *__restrict__ phi_node, double *__restrict__ parts) {
+    const double inf = __builtin_inf();
+    double v[3] = {inf, inf, inf};
+    const int64_t off_f = I.nc, off_n = (int64_t)I.nc + I.nf, total = off_n + I.nn;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int kind = i < off_f ? 0 : (i < off_n ? 1 : 2);
+        if (kind == 2 && I.dirichlet[i - off_n]) continue;
+        double o = 0.0;
+        for (int64_t q = I.ptr[i]; q < I.ptr[i + 1]; ++q) o += fmax(inc_flux(I, F, q), 0.0);
+        if (kind == 1 && wout) o += wout[i - off_f];
+        if (o > 0.0) {
+            const double phi = kind == 0 ? phi_cell[i] : (kind == 1 ? phi_frac[i - off_f] : phi_node[i - off_n]);
+            v[kind] = fmin(v[kind], phi / o);
+        }
+    }
+    block_partials<OpMin, 3, kT>(v, parts, gridDim.x);
+}
+
+// entries of row i: one per inflow (negative outgoing flux), plus a well's
+// injection on a fracture face; none for a Dirichlet node
+__device__ inline int gen_row_count(const GenInc &I, const double *F, const double *wsrc, int64_t i) {
+    const int64_t off_f = I.nc, off_n = (int64_t)I.nc + I.nf;
+    if (i >= off_n && I.dirichlet[i - off_n]) return 0;
+    int c = 0;
+    for (int64_t q = I.ptr[i]; q < I.ptr[i + 1]; ++q) c += inc_flux(I, F, q) < 0.0;
+    if (wsrc && i >= off_f && i < off_n) c += wsrc[i - off_f] > 0.0;
+    return c;
+}
+
+__global__ __launch_bounds__(kSliceRows) void gen_upwind_count_kernel(GenInc I, const double *__restrict__ F,
+                                                                      const double *__restrict__ wsrc,
+                                                                      int32_t *__restrict__ slice_width,
+                                                                      uint16_t *__restrict__ meta,
+                                                                      int32_t *__restrict__ slice_nnz) {
+    const int lane = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kSliceRows + lane;
+    const int64_t total = (int64_t)I.nc + I.nf + I.nn;
+    const int c = i < total ? gen_row_count(I, F, wsrc, i) : 0;
+    slice_sort_rows(c, lane, slice_width, meta, slice_nnz);
+}
+
+// Row i of the upwind operator: T_ij = w_i (inflow from j), T_ii = 1 - w_i
+// (outflow), w_i = dt / phi_i; a well's production counts as outflow of its
+// face and its injection as an entry on the constant control volume.
+__global__ __launch_bounds__(kSliceRows) void gen_upwind_fill_kernel(
+    GenInc I, const double *__restrict__ F, const double *__restrict__ wsrc, const double *__restrict__ wout,
+    const double *__restrict__ phi_cell, const double *__restrict__ phi_frac, const double *__restrict__ phi_node,
+    const double *__restrict__ dtp, const int64_t *__restrict__ slice_ptr, const uint16_t *__restrict__ meta,
+    int32_t *__restrict__ tcol, double *__restrict__ tval, double *__restrict__ tdiag) {
+    __shared__ uint8_t cnts[kSliceRows];
+    __shared__ int32_t level_off[257];
+    const int lane = threadIdx.x;
+    const int src = slice_levels(meta, cnts, level_off);
+    const int64_t i = (int64_t)blockIdx.x * kSliceRows + src;
+    const int64_t off_f = I.nc, off_n = (int64_t)I.nc + I.nf, total = off_n + I.nn;
+    if (i >= total) return;
+    const int64_t base = slice_ptr[blockIdx.x] + lane;
+    double d = 1.0;
+    if (!(i >= off_n && I.dirichlet[i - off_n])) {
+        const double phi = i < off_f ? phi_cell[i] : (i < off_n ? phi_frac[i - off_f] : phi_node[i - off_n]);
+        const double w = dtp[3] / phi;
+        double out = 0.0;
+        int k = 0;
+        for (int64_t q = I.ptr[i]; q < I.ptr[i + 1]; ++q) {
+            const double f = inc_flux(I, F, q);
+            if (f > 0.0) {
+                out += f;
+            } else if (f < 0.0) {
+                tcol[base + level_off[k]] = I.other[q];
+                tval[base + level_off[k]] = -w * f;
+                ++k;
+            }
+        }
+        if (i >= off_f && i < off_n) {
+            if (wout) out += wout[i - off_f];
+            if (wsrc && wsrc[i - off_f] > 0.0) {
+                tcol[base + level_off[k]] = (int32_t)total;
+                tval[base + level_off[k]] = w * wsrc[i - off_f];
+                ++k;
+            }
+        }
+        d = 1.0 - w * out;
+    }
+    tdiag[i] = d;
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 void launch_node_pressure(hipStream_t s, int32_t nn, const int32_t *node_unk, const double *x, const double *p_bar,
@@ -793,6 +907,31 @@ void launch_transport_gather(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, 
 void launch_set_dirichlet(hipStream_t s, int32_t nn, int32_t offset, const uint8_t *dirichlet, const double *c_bar,
                           double *c) {
     hipLaunchKernelGGL(set_dirichlet_kernel, dim3(nb(nn, 256)), dim3(256), 0, s, nn, offset, dirichlet, c_bar, c);
+    VAG_HIP(hipGetLastError());
+}
+
+void launch_gen_cfl(hipStream_t s, const GenInc &I, const double *F, const double *wout, const double *phi_cell,
+                    const double *phi_frac, const double *phi_node, double cfl, double *parts, double *dt_out) {
+    const int64_t total = (int64_t)I.nc + I.nf + I.nn;
+    const unsigned G = reduce_grid(total, kT);
+    hipLaunchKernelGGL(gen_cfl_kernel, dim3(G), dim3(kT), 0, s, I, F, wout, phi_cell, phi_frac, phi_node, parts);
+    hipLaunchKernelGGL(cfl_finish_kernel, dim3(1), dim3(kT), 0, s, parts, (int)G, cfl, dt_out);
+    VAG_HIP(hipGetLastError());
+}
+void launch_gen_upwind_count(hipStream_t s, const GenInc &I, const double *F, const double *wsrc,
+                             int32_t *slice_width, uint16_t *meta, int32_t *slice_nnz) {
+    const int64_t total = (int64_t)I.nc + I.nf + I.nn;
+    hipLaunchKernelGGL(gen_upwind_count_kernel, dim3(nb(total, kSliceRows)), dim3(kSliceRows), 0, s, I, F, wsrc,
+                       slice_width, meta, slice_nnz);
+    VAG_HIP(hipGetLastError());
+}
+void launch_gen_upwind_fill(hipStream_t s, const GenInc &I, const double *F, const double *wsrc, const double *wout,
+                            const double *phi_cell, const double *phi_frac, const double *phi_node, const double *dt,
+                            const int64_t *slice_ptr, const uint16_t *meta, int32_t *tcol, double *tval,
+                            double *tdiag) {
+    const int64_t total = (int64_t)I.nc + I.nf + I.nn;
+    hipLaunchKernelGGL(gen_upwind_fill_kernel, dim3(nb(total, kSliceRows)), dim3(kSliceRows), 0, s, I, F, wsrc,
+                       wout, phi_cell, phi_frac, phi_node, dt, slice_ptr, meta, tcol, tval, tdiag);
     VAG_HIP(hipGetLastError());
 }
 

@@ -178,6 +178,27 @@ struct vag_handle {
 
     Amg amg;
     Ilu ilu;                 // block-Jacobi ILU(0)
+    // general cells (mesh given by faces): tables of GenSym on the device,
+    // local values, the cells' a and row sums, the flux array
+    // [cell-node | cell-face | face-node]
+    bool general = false;
+    GenSym G;
+    DBuf<int32_t> g_cnode_ptr, g_cnode, g_fnode_ptr, g_fnode, g_unk_off, g_bcon_ptr, g_bcon_node, g_inc_edge,
+        g_inc_other;
+    DBuf<uint8_t> g_cface_k, g_cface_loc;
+    DBuf<int64_t> g_loc_off, g_con_ptr, g_con, g_bcon, g_inc_ptr;
+    DBuf<double> gloc, ga, gr, Fall;
+    GenMesh gmesh() const {
+        return GenMesh{S.nc, S.nf, S.nn, g_cnode_ptr.p, g_cnode.p, g_cface_k.p, g_cface_loc.p, cell_frac.p,
+                       frac_cell.p, g_fnode_ptr.p, g_fnode.p, g_unk_off.p, g_loc_off.p, G.ncn};
+    }
+    GenInc ginc() const { return GenInc{S.nc, S.nf, S.nn, g_inc_ptr.p, g_inc_edge.p, g_inc_other.p, dirichlet.p}; }
+    // the three flux sections (hexahedra: their own arrays)
+    double *flux_cell() { return general ? Fall.p : F_cell.p; }
+    double *flux_cell_frac() { return general ? Fall.p + G.ncn : F_cell_frac.p; }
+    double *flux_frac() { return general ? Fall.p + G.ncn + 2 * (int64_t)S.nf : F_frac.p; }
+    int64_t n_flux_cell() const { return general ? G.ncn : 8 * (int64_t)S.nc; }
+    int64_t n_flux_frac() const { return general ? G.nfn : 4 * (int64_t)S.nf; }
     // Peaceman wells: perforations, rates of the last solve, per-face terms
     int32_t nw = 0;
     DBuf<int32_t> wface;
@@ -716,28 +737,78 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         check_options(h->opt);
         const int64_t nn = mesh->n_nodes, nc = mesh->n_cells, nf = frac ? frac->n_frac : 0;
         if (nn <= 0 || nc <= 0 || nf < 0) throw Error(VAG_ERR_ARG, "empty mesh");
-        auto hex8 = host_copy(mesh->hex8, 8 * (size_t)nc, mem, h->stream);
-        std::vector<int32_t> fnodes =
-            nf ? host_copy(frac->face_nodes, 4 * (size_t)nf, mem, h->stream) : std::vector<int32_t>();
         auto dir = host_copy(bc->node_dirichlet, (size_t)nn, mem, h->stream);
-        build_symbolic(nn, nc, nf, hex8.data(), fnodes.data(), dir.data(), h->opt.eliminate_frac_faces != 0, h->S);
+        h->general = mesh->hex8 == nullptr;
+        if (!h->general) {
+            auto hex8 = host_copy(mesh->hex8, 8 * (size_t)nc, mem, h->stream);
+            if (nf && !frac->face_nodes) throw Error(VAG_ERR_ARG, "hex8 meshes give fracture faces by face_nodes");
+            std::vector<int32_t> fnodes =
+                nf ? host_copy(frac->face_nodes, 4 * (size_t)nf, mem, h->stream) : std::vector<int32_t>();
+            build_symbolic(nn, nc, nf, hex8.data(), fnodes.data(), dir.data(), h->opt.eliminate_frac_faces != 0,
+                           h->S);
+            upload_vec(h, h->hex8, hex8);
+            upload_vec(h, h->frac_nodes, fnodes);
+            upload_vec(h, h->frac_slot, h->S.frac_slot);
+            upload_vec(h, h->node_cell_ptr, h->S.node_cell_ptr);
+            upload_vec(h, h->node_cell, h->S.node_cell);
+            upload_vec(h, h->node_frac_ptr, h->S.node_frac_ptr);
+            upload_vec(h, h->node_frac, h->S.node_frac);
+        } else {
+            if (!mesh->cell_face_ptr || !mesh->cell_faces || !mesh->face_node_ptr || !mesh->face_nodes ||
+                mesh->n_faces <= 0)
+                throw Error(VAG_ERR_ARG, "a mesh without hex8 needs cell_face_ptr, cell_faces, face_node_ptr, "
+                                         "face_nodes and n_faces");
+            if (nf && !frac->face_ids) throw Error(VAG_ERR_ARG, "general meshes give fracture faces by face_ids");
+            const int64_t nF = mesh->n_faces;
+            if (nF >= INT32_MAX / 4) throw Error(VAG_ERR_ARG, "mesh sizes out of range");
+            const auto cfp = host_copy(mesh->cell_face_ptr, (size_t)nc + 1, mem, h->stream);
+            const auto fnp = host_copy(mesh->face_node_ptr, (size_t)nF + 1, mem, h->stream);
+            if (cfp[0] != 0 || fnp[0] != 0 || cfp[nc] < 0 || fnp[nF] < 0 || cfp[nc] > 6 * (int64_t)nc ||
+                fnp[nF] > 4 * nF)
+                throw Error(VAG_ERR_ARG, "cell_face_ptr / face_node_ptr out of range");
+            for (int64_t K = 0; K < nc; ++K)
+                if (cfp[K + 1] < cfp[K]) throw Error(VAG_ERR_ARG, "cell_face_ptr is not ascending");
+            for (int64_t f = 0; f < nF; ++f)
+                if (fnp[f + 1] < fnp[f]) throw Error(VAG_ERR_ARG, "face_node_ptr is not ascending");
+            const auto cf = host_copy(mesh->cell_faces, (size_t)cfp[nc], mem, h->stream);
+            const auto fnd = host_copy(mesh->face_nodes, (size_t)fnp[nF], mem, h->stream);
+            const std::vector<int32_t> fid =
+                nf ? host_copy(frac->face_ids, (size_t)nf, mem, h->stream) : std::vector<int32_t>();
+            build_symbolic_general(nn, nc, nF, cfp.data(), cf.data(), fnp.data(), fnd.data(), nf, fid.data(),
+                                   dir.data(), h->S, h->G);
+            const GenSym &G = h->G;
+            upload_vec(h, h->g_cnode_ptr, G.cnode_ptr);
+            upload_vec(h, h->g_cnode, G.cnode);
+            upload_vec(h, h->g_cface_k, G.cface_k);
+            upload_vec(h, h->g_cface_loc, G.cface_loc);
+            upload_vec(h, h->g_fnode_ptr, G.fnode_ptr);
+            upload_vec(h, h->g_fnode, G.fnode);
+            upload_vec(h, h->g_unk_off, G.unk_off);
+            upload_vec(h, h->g_loc_off, G.loc_off);
+            upload_vec(h, h->g_con_ptr, G.con_ptr);
+            upload_vec(h, h->g_con, G.con);
+            upload_vec(h, h->g_bcon_ptr, G.bcon_ptr);
+            upload_vec(h, h->g_bcon, G.bcon);
+            upload_vec(h, h->g_bcon_node, G.bcon_node);
+            upload_vec(h, h->g_inc_ptr, G.inc_ptr);
+            upload_vec(h, h->g_inc_edge, G.inc_edge);
+            upload_vec(h, h->g_inc_other, G.inc_other);
+            h->gloc.alloc(std::max<int64_t>(G.loc_off.back(), 1), h->tr);
+            h->ga.alloc(std::max<int64_t>(G.loc_off[nc], 1), h->tr);
+            h->gr.alloc(std::max<int32_t>(G.unk_off.back(), 1), h->tr);
+            h->Fall.alloc(std::max<int64_t>(G.nflux, 1), h->tr);
+            launch_fill(h->stream, std::max<int64_t>(G.nflux, 1), 0.0, h->Fall.p);
+        }
         const Symbolic &S = h->S;
         h->mu = rock->mu;
 
         upload(h, h->xyz, mesh->node_xyz, 3 * (size_t)nn, mem);
-        upload_vec(h, h->hex8, hex8);
-        upload_vec(h, h->frac_nodes, fnodes);
         upload_vec(h, h->dirichlet, dir);
         upload_vec(h, h->fmask, S.fmask);
         upload_vec(h, h->cell_frac, S.cell_frac);
         upload_vec(h, h->frac_cell, S.frac_cell);
-        upload_vec(h, h->frac_slot, S.frac_slot);
         upload_vec(h, h->node_unk, S.node_unk);
         upload_vec(h, h->frac_node, S.frac_node);
-        upload_vec(h, h->node_cell_ptr, S.node_cell_ptr);
-        upload_vec(h, h->node_cell, S.node_cell);
-        upload_vec(h, h->node_frac_ptr, S.node_frac_ptr);
-        upload_vec(h, h->node_frac, S.node_frac);
         upload_vec(h, h->sell_ptr, S.sell_ptr);
         upload_vec(h, h->unk_node, S.unk_node);
         upload_vec(h, h->unk_face, S.unk_face);
@@ -783,12 +854,14 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         }
 
         const size_t n = S.nx;  // vectors hold the eliminated faces too
-        h->aK.alloc(36 * (size_t)nc, h->tr);
-        h->rK.alloc(8 * (size_t)nc, h->tr);
+        if (!h->general) {
+            h->aK.alloc(36 * (size_t)nc, h->tr);
+            h->rK.alloc(8 * (size_t)nc, h->tr);
+            h->fside.alloc(12 * (size_t)std::max<int64_t>(nf, 1), h->tr);
+            h->A5.alloc(25 * (size_t)std::max<int64_t>(nf, 1), h->tr);
+        }
         h->AKK.alloc(nc, h->tr);
         h->vol.alloc(nc, h->tr);
-        h->fside.alloc(12 * (size_t)std::max<int64_t>(nf, 1), h->tr);
-        h->A5.alloc(25 * (size_t)std::max<int64_t>(nf, 1), h->tr);
         h->area.alloc(std::max<int64_t>(nf, 1), h->tr);
         h->A.alloc(std::max<int64_t>(S.sell_ptr.back(), 1), h->tr);
         h->b.alloc(n, h->tr);
@@ -803,9 +876,11 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         h->u_node.alloc(nn, h->tr);
         h->u_cell.alloc(nc, h->tr);
         h->u_frac.alloc(std::max<int64_t>(nf, 1), h->tr);
-        h->F_cell.alloc(8 * (size_t)nc, h->tr);
-        h->F_cell_frac.alloc(2 * (size_t)std::max<int64_t>(nf, 1), h->tr);
-        h->F_frac.alloc(4 * (size_t)std::max<int64_t>(nf, 1), h->tr);
+        if (!h->general) {
+            h->F_cell.alloc(8 * (size_t)nc, h->tr);
+            h->F_cell_frac.alloc(2 * (size_t)std::max<int64_t>(nf, 1), h->tr);
+            h->F_frac.alloc(4 * (size_t)std::max<int64_t>(nf, 1), h->tr);
+        }
         h->phi_cell.alloc(nc, h->tr);
         h->phi_frac.alloc(std::max<int64_t>(nf, 1), h->tr);
         h->phi_node.alloc(nn, h->tr);
@@ -826,6 +901,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         h->h_pcg = static_cast<PcgState *>(pinned_get(sizeof(PcgState)));
         h->h_scal = static_cast<double *>(pinned_get(16 * sizeof(double)));
         for (auto &e : h->ev) VAG_HIP(hipEventCreate(&e));
+        if (h->general) return;
         // system positions of the eliminated groups' node pairs
         h->grp_pos.alloc(std::max<int64_t>(S.grp_poff.back(), 1), h->tr);
         VAG_HIP(hipMemsetAsync(h->bad.p, 0x7f, sizeof(int), h->stream));
@@ -876,19 +952,33 @@ vag_status vag_set_fluxes(vag_handle *h, const double *F_cell, const double *F_c
         const Symbolic &S = h->S;
         hipStream_t s = h->stream;
         if (!F_cell || (S.nf && (!F_cell_frac || !F_frac))) throw Error(VAG_ERR_ARG, "null flux array");
-        VAG_HIP(hipMemcpyAsync(h->F_cell.p, F_cell, 8 * (size_t)S.nc * sizeof(double), kind_in(mem), s));
+        VAG_HIP(hipMemcpyAsync(h->flux_cell(), F_cell, (size_t)h->n_flux_cell() * sizeof(double), kind_in(mem), s));
         if (S.nf) {
-            VAG_HIP(hipMemcpyAsync(h->F_cell_frac.p, F_cell_frac, 2 * (size_t)S.nf * sizeof(double), kind_in(mem), s));
-            VAG_HIP(hipMemcpyAsync(h->F_frac.p, F_frac, 4 * (size_t)S.nf * sizeof(double), kind_in(mem), s));
+            VAG_HIP(hipMemcpyAsync(h->flux_cell_frac(), F_cell_frac, 2 * (size_t)S.nf * sizeof(double), kind_in(mem),
+                                   s));
+            VAG_HIP(hipMemcpyAsync(h->flux_frac(), F_frac, (size_t)h->n_flux_frac() * sizeof(double), kind_in(mem),
+                                   s));
         }
         // cell volumes and face areas come with the local matrices
         VAG_HIP(hipMemsetAsync(h->bad.p, 0x7f, sizeof(int), s));
-        launch_local(s, S.nc, h->xyz.p, h->hex8.p, h->perm.p, h->mu, h->fmask.p, h->cell_frac.p, h->frac_cell.p,
-                     h->aK.p, h->rK.p, h->AKK.p, h->vol.p, h->fside.p, h->bad.p);
-        launch_frac_local(s, S.nf, h->xyz.p, h->frac_nodes.p, h->fwidth.p, h->fperm.p, h->mu, h->A5.p, h->area.p);
-        launch_porous(s, S.nc, S.nf, S.nn, h->hex8.p, h->frac_nodes.p, h->dirichlet.p, h->frac_node.p,
-                      h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->vol.p, h->poro.p,
-                      h->area.p, h->fwidth.p, h->fporo.p, h->phi_cell.p, h->phi_frac.p, h->phi_node.p);
+        if (h->general) {
+            const GenMesh g = h->gmesh();
+            launch_gen_local(s, g, h->xyz.p, h->perm.p, 1.0 / h->mu, h->gloc.p, h->ga.p, h->gr.p, h->AKK.p,
+                             h->vol.p, h->bad.p);
+            launch_gen_frac_local(s, g, h->xyz.p, h->fwidth.p, h->fperm.p, 1.0 / h->mu, h->gloc.p, h->area.p);
+            launch_gen_porous(s, g, h->dirichlet.p, h->frac_node.p, h->g_inc_ptr.p, h->g_inc_other.p, h->vol.p,
+                              h->poro.p, h->area.p, h->fwidth.p, h->fporo.p, h->phi_cell.p, h->phi_frac.p,
+                              h->phi_node.p);
+        } else {
+            launch_local(s, S.nc, h->xyz.p, h->hex8.p, h->perm.p, h->mu, h->fmask.p, h->cell_frac.p,
+                         h->frac_cell.p, h->aK.p, h->rK.p, h->AKK.p, h->vol.p, h->fside.p, h->bad.p);
+            launch_frac_local(s, S.nf, h->xyz.p, h->frac_nodes.p, h->fwidth.p, h->fperm.p, h->mu, h->A5.p,
+                              h->area.p);
+            launch_porous(s, S.nc, S.nf, S.nn, h->hex8.p, h->frac_nodes.p, h->dirichlet.p, h->frac_node.p,
+                          h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->vol.p,
+                          h->poro.p, h->area.p, h->fwidth.p, h->fporo.p, h->phi_cell.p, h->phi_frac.p,
+                          h->phi_node.p);
+        }
         if (h->nw) {  // given fluxes come without well rates until vag_set_well_rates
             launch_fill(s, h->nw, 0.0, h->wrate.p);
             launch_fill(s, S.nf, 0.0, h->wsrc.p);
@@ -908,6 +998,7 @@ vag_status vag_set_wells(vag_handle *h, int64_t n, const int32_t *face, const do
         const Symbolic &S = h->S;
         hipStream_t s = h->stream;
         if (n > 0 && (!face || !wi || !p_w || !q || !c_inj)) throw Error(VAG_ERR_ARG, "null well array");
+        if (n > 0 && h->general) throw Error(VAG_ERR_UNSUPPORTED, "wells take hex8 meshes");
         if (n > INT32_MAX) throw Error(VAG_ERR_ARG, "too many wells");
         const std::vector<int32_t> f = host_copy(face, (size_t)n, mem, s);
         const std::vector<double> a = host_copy(wi, (size_t)n, mem, s), b = host_copy(p_w, (size_t)n, mem, s),
@@ -1009,14 +1100,26 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
         VAG_HIP(hipEventRecord(h->ev[0], s));
         // 1. local matrices and fracture matrices
         VAG_HIP(hipMemsetAsync(h->bad.p, 0x7f, sizeof(int), s));
-        launch_local(s, S.nc, h->xyz.p, h->hex8.p, h->perm.p, h->mu, h->fmask.p, h->cell_frac.p, h->frac_cell.p,
-                     h->aK.p, h->rK.p, h->AKK.p, h->vol.p, h->fside.p, h->bad.p);
-        launch_frac_local(s, S.nf, h->xyz.p, h->frac_nodes.p, h->fwidth.p, h->fperm.p, h->mu, h->A5.p, h->area.p);
-        // 2. cell elimination, colour by colour
-        launch_fill(s, (int64_t)h->A.n, 0.0, h->A.p);  // padding stays 0
-        launch_fill(s, S.nx, 0.0, h->b.p);
-        if (S.ngroup) launch_fill(s, S.grp_off.back(), 0.0, h->Gb.p);
-        launch_assemble(s, asm_args(h), S.nunk - S.nfree, S.grp_ptr.empty() ? 0 : S.grp_ptr.back());
+        if (h->general) {
+            // 2. the Schur blocks gathered into the system, Dirichlet columns to b
+            const GenMesh g = h->gmesh();
+            launch_gen_local(s, g, h->xyz.p, h->perm.p, 1.0 / h->mu, h->gloc.p, h->ga.p, h->gr.p, h->AKK.p,
+                             h->vol.p, h->bad.p);
+            launch_gen_frac_local(s, g, h->xyz.p, h->fwidth.p, h->fperm.p, 1.0 / h->mu, h->gloc.p, h->area.p);
+            launch_gen_assemble(s, S.sell_ptr.back(), h->g_con_ptr.p, h->g_con.p, h->gloc.p, h->A.p);
+            launch_gen_rhs(s, S.nunk, h->g_bcon_ptr.p, h->g_bcon.p, h->g_bcon_node.p, h->gloc.p, h->p_bar.p,
+                           h->b.p);
+        } else {
+            launch_local(s, S.nc, h->xyz.p, h->hex8.p, h->perm.p, h->mu, h->fmask.p, h->cell_frac.p,
+                         h->frac_cell.p, h->aK.p, h->rK.p, h->AKK.p, h->vol.p, h->fside.p, h->bad.p);
+            launch_frac_local(s, S.nf, h->xyz.p, h->frac_nodes.p, h->fwidth.p, h->fperm.p, h->mu, h->A5.p,
+                              h->area.p);
+            // 2. cell elimination, colour by colour
+            launch_fill(s, (int64_t)h->A.n, 0.0, h->A.p);  // padding stays 0
+            launch_fill(s, S.nx, 0.0, h->b.p);
+            if (S.ngroup) launch_fill(s, S.grp_off.back(), 0.0, h->Gb.p);
+            launch_assemble(s, asm_args(h), S.nunk - S.nfree, S.grp_ptr.empty() ? 0 : S.grp_ptr.back());
+        }
         if (h->nw)
             launch_well_assemble(s, h->nw, h->wface.p, h->wwi.p, h->wpw.p, h->wq.p,
                                  WellAsm{S.nunk, h->frac_unk.p, h->diag_pos.p, h->face_grp.p, h->face_loc.p,
@@ -1063,13 +1166,25 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
             launch_well_rates(s, h->nw, h->wface.p, h->wwi.p, h->wpw.p, h->wq.p, h->wcinj.p, h->u_frac.p, nullptr,
                               h->wrate.p, h->wsrc.p, h->wout.p);
         }
-        launch_fill(s, 2 * (int64_t)std::max(S.nf, 1), 0.0, h->F_cell_frac.p);
-        launch_cell_flux(s, S.nc, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->aK.p, h->rK.p, h->AKK.p,
-                         h->fside.p, h->u_node.p, h->u_frac.p, h->u_cell.p, h->F_cell.p, h->F_cell_frac.p);
-        launch_frac_flux(s, S.nf, h->frac_nodes.p, h->A5.p, h->u_node.p, h->u_frac.p, h->F_frac.p);
-        launch_porous(s, S.nc, S.nf, S.nn, h->hex8.p, h->frac_nodes.p, h->dirichlet.p, h->frac_node.p,
-                      h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->vol.p, h->poro.p,
-                      h->area.p, h->fwidth.p, h->fporo.p, h->phi_cell.p, h->phi_frac.p, h->phi_node.p);
+        if (h->general) {
+            const GenMesh g = h->gmesh();
+            launch_fill(s, 2 * (int64_t)S.nf, 0.0, h->flux_cell_frac());  // a missing second cell keeps 0
+            launch_gen_flux(s, g, h->gloc.p, h->ga.p, h->gr.p, h->AKK.p, h->u_node.p, h->u_frac.p, h->u_cell.p,
+                            h->Fall.p);
+            launch_gen_porous(s, g, h->dirichlet.p, h->frac_node.p, h->g_inc_ptr.p, h->g_inc_other.p, h->vol.p,
+                              h->poro.p, h->area.p, h->fwidth.p, h->fporo.p, h->phi_cell.p, h->phi_frac.p,
+                              h->phi_node.p);
+        } else {
+            launch_fill(s, 2 * (int64_t)std::max(S.nf, 1), 0.0, h->F_cell_frac.p);
+            launch_cell_flux(s, S.nc, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->aK.p, h->rK.p,
+                             h->AKK.p, h->fside.p, h->u_node.p, h->u_frac.p, h->u_cell.p, h->F_cell.p,
+                             h->F_cell_frac.p);
+            launch_frac_flux(s, S.nf, h->frac_nodes.p, h->A5.p, h->u_node.p, h->u_frac.p, h->F_frac.p);
+            launch_porous(s, S.nc, S.nf, S.nn, h->hex8.p, h->frac_nodes.p, h->dirichlet.p, h->frac_node.p,
+                          h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->vol.p,
+                          h->poro.p, h->area.p, h->fwidth.p, h->fporo.p, h->phi_cell.p, h->phi_frac.p,
+                          h->phi_node.p);
+        }
         VAG_HIP(hipEventRecord(h->ev[4], s));
         // true residual ||b - A x|| / ||b||
         launch_residual_norm(s, h->Asell(), h->x.p, h->b.p, h->r.p, h->rparts.p, h->scal.p);
@@ -1124,14 +1239,21 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
         const int64_t nrow = (int64_t)S.nc + S.nf + S.nn;
         const int32_t nslice = (int32_t)((nrow + kSliceRows - 1) / kSliceRows);
         VAG_HIP(hipEventRecord(h->ev[5], s));
-        launch_cfl(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
-                   h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
-                   h->F_cell_frac.p, h->F_frac.p, h->well_out(), h->phi_cell.p, h->phi_frac.p, h->phi_node.p,
-                   h->opt.cfl, h->rparts.p, h->dt4.p);
-        launch_upwind_count(s, S.nc, S.nf, S.nn, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
-                            h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
-                            h->F_cell_frac.p, h->F_frac.p, h->well_src(), h->slice_width.p, h->tmeta.p,
-                            h->slice_nnz.p);
+        if (h->general) {
+            launch_gen_cfl(s, h->ginc(), h->Fall.p, h->well_out(), h->phi_cell.p, h->phi_frac.p, h->phi_node.p,
+                           h->opt.cfl, h->rparts.p, h->dt4.p);
+            launch_gen_upwind_count(s, h->ginc(), h->Fall.p, h->well_src(), h->slice_width.p, h->tmeta.p,
+                                    h->slice_nnz.p);
+        } else {
+            launch_cfl(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
+                       h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
+                       h->F_cell_frac.p, h->F_frac.p, h->well_out(), h->phi_cell.p, h->phi_frac.p, h->phi_node.p,
+                       h->opt.cfl, h->rparts.p, h->dt4.p);
+            launch_upwind_count(s, S.nc, S.nf, S.nn, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
+                                h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
+                                h->F_cell_frac.p, h->F_frac.p, h->well_src(), h->slice_width.p, h->tmeta.p,
+                                h->slice_nnz.p);
+        }
         launch_slice_scan(s, nslice, h->slice_nnz.p, 1, h->slice_ptr.p, h->slice_nnz.p, h->cnt.p);
         int64_t total = 0;
         VAG_HIP(hipMemcpyAsync(&total, h->slice_ptr.p + nslice, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1147,11 +1269,16 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
             h->tval.alloc((size_t)total + (size_t)total / 8, h->tr);
         }
         ensure(h->tbase, (size_t)std::max<int64_t>(nslice, 1), h->tr);
-        launch_upwind_fill(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p,
-                           h->frac_nodes.p, h->dirichlet.p, h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p,
-                           h->node_frac.p, h->F_cell.p, h->F_cell_frac.p, h->F_frac.p, h->well_src(), h->well_out(),
-                           h->phi_cell.p, h->phi_frac.p, h->phi_node.p, h->dt4.p, h->slice_ptr.p, h->tmeta.p,
-                           h->tcol.p, h->tval.p, h->tdiag.p);
+        if (h->general)
+            launch_gen_upwind_fill(s, h->ginc(), h->Fall.p, h->well_src(), h->well_out(), h->phi_cell.p,
+                                   h->phi_frac.p, h->phi_node.p, h->dt4.p, h->slice_ptr.p, h->tmeta.p, h->tcol.p,
+                                   h->tval.p, h->tdiag.p);
+        else
+            launch_upwind_fill(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p,
+                               h->frac_nodes.p, h->dirichlet.p, h->node_cell_ptr.p, h->node_cell.p,
+                               h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p, h->F_cell_frac.p, h->F_frac.p,
+                               h->well_src(), h->well_out(), h->phi_cell.p, h->phi_frac.p, h->phi_node.p, h->dt4.p,
+                               h->slice_ptr.p, h->tmeta.p, h->tcol.p, h->tval.p, h->tdiag.p);
         launch_upwind_pack(s, h->upwind(), h->tcol16.p, h->tbase.p);
         h->have_op = true;
         // initial state
@@ -1208,6 +1335,8 @@ vag_status vag_transport_noalloc(vag_handle *h, int64_t n_steps, double t_final,
                                  double *c_node, vag_transport_info *info) {
     if (!h) return VAG_ERR_ARG;
     return guard(h, [&] {
+        if (h->general)
+            throw Error(VAG_ERR_UNSUPPORTED, "vag_transport_noalloc takes hex8 meshes; use vag_transport");
         if (!h->have_flux)
             throw Error(VAG_ERR_STATE, "vag_transport_noalloc needs a pressure solve (or vag_set_fluxes) first");
         if (n_steps < 0 || t_final < 0) throw Error(VAG_ERR_ARG, "negative step count or final time");
@@ -1306,11 +1435,21 @@ vag_status vag_get_fluxes(vag_handle *h, double *F_cell, double *F_cell_frac, do
     if (!h) return VAG_ERR_ARG;
     return guard(h, [&] {
         if (!h->have_flux) throw Error(VAG_ERR_STATE, "no pressure solve yet");
-        download(h, F_cell, h->F_cell, 8 * (size_t)h->S.nc, mem);
-        download(h, F_cell_frac, h->F_cell_frac, 2 * (size_t)h->S.nf, mem);
-        download(h, F_frac, h->F_frac, 4 * (size_t)h->S.nf, mem);
+        auto get = [&](double *dst, const double *src, int64_t n) {
+            if (dst && n > 0) VAG_HIP(hipMemcpyAsync(dst, src, (size_t)n * sizeof(double), kind_out(mem), h->stream));
+        };
+        get(F_cell, h->flux_cell(), h->n_flux_cell());
+        get(F_cell_frac, h->flux_cell_frac(), 2 * (int64_t)h->S.nf);
+        get(F_frac, h->flux_frac(), h->n_flux_frac());
         VAG_HIP(hipStreamSynchronize(h->stream));
     });
+}
+
+vag_status vag_flux_layout(const vag_handle *h, int64_t *n_cell_flux, int64_t *n_frac_flux) {
+    if (!h) return VAG_ERR_ARG;
+    if (n_cell_flux) *n_cell_flux = h->n_flux_cell();
+    if (n_frac_flux) *n_frac_flux = h->n_flux_frac();
+    return VAG_OK;
 }
 
 vag_status vag_get_porous_volumes(vag_handle *h, double *phi_cell, double *phi_frac, double *phi_node,
@@ -1409,8 +1548,12 @@ vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms)
                     launch_transport_step(s, h->upwind(), h->c_cur(), h->c_next(), 1.0);
                     break;
                 case VAG_KERNEL_LOCAL:
-                    launch_local(s, S.nc, h->xyz.p, h->hex8.p, h->perm.p, h->mu, h->fmask.p, h->cell_frac.p,
-                                 h->frac_cell.p, h->aK.p, h->rK.p, h->AKK.p, h->vol.p, h->fside.p, h->bad.p);
+                    if (h->general)
+                        launch_gen_local(s, h->gmesh(), h->xyz.p, h->perm.p, 1.0 / h->mu, h->gloc.p, h->ga.p,
+                                         h->gr.p, h->AKK.p, h->vol.p, h->bad.p);
+                    else
+                        launch_local(s, S.nc, h->xyz.p, h->hex8.p, h->perm.p, h->mu, h->fmask.p, h->cell_frac.p,
+                                     h->frac_cell.p, h->aK.p, h->rK.p, h->AKK.p, h->vol.p, h->fside.p, h->bad.p);
                     break;
                 case VAG_KERNEL_PRECOND:
                     if (h->opt.precision == VAG_MIXED_IR && h->amg.have32)

@@ -151,6 +151,46 @@ struct Symbolic {
     std::vector<int64_t> grp_off, grp_poff;
 };
 
+// General cells (cell -> faces, face -> nodes): what the symbolic phase of a
+// general mesh adds to Symbolic (whose node and face numbering, pattern and
+// renumbering it shares; cell_frac holds 6 entries per cell, frac_cell 2 per
+// fracture face, frac_node the fracture-node flags).
+constexpr int kGenMaxFaces = 6;      // faces of a cell
+constexpr int kGenMaxNodes = 8;      // nodes of a cell
+constexpr int kGenMaxFaceNodes = 4;  // nodes of a face
+struct GenSym {
+    int64_t ncn = 0;                 // sum over cells of their node counts
+    int64_t nfn = 0;                 // sum over fracture faces of their node counts
+    int64_t nflux = 0;               // ncn + 2 nf + nfn: the flux array [cell-node | cell-face | face-node]
+    std::vector<int32_t> cnode_ptr;  // [nc + 1] cell -> its nodes, local order
+    std::vector<int32_t> cnode;      // [ncn] global node indices
+    std::vector<uint8_t> cface_k;    // [6 nc] node count of local face f (0: no such face)
+    std::vector<uint8_t> cface_loc;  // [24 nc] local node indices of local face f, cyclic as given
+    std::vector<int32_t> fnode_ptr;  // [nf + 1] fracture face -> its nodes
+    std::vector<int32_t> fnode;      // [nfn] global node indices, the face's cyclic order
+    std::vector<int32_t> unk_off;    // [nc + 1] prefix of the cells' unknown counts m (row sums r)
+    std::vector<int64_t> loc_off;    // [nc + nf + 1] blocks in the local value array: m x m per cell
+                                     // (the Schur block M), then (k + 1)^2 per fracture face
+    std::vector<int64_t> con_ptr;    // [stored + 1] contributions to each sliced-ELL slot of the system
+    std::vector<int64_t> con;        // local value indices, in a fixed order
+    std::vector<int32_t> bcon_ptr;   // [nunk + 1] Dirichlet-column contributions to each row of b
+    std::vector<int64_t> bcon;       // local value index
+    std::vector<int32_t> bcon_node;  // the Dirichlet node of that column
+    std::vector<int64_t> inc_ptr;    // [nc + nf + nn + 1] control volume -> its fluxes
+    std::vector<int32_t> inc_edge;   // flux index << 1 | 1 if the control volume is the flux's far end
+    std::vector<int32_t> inc_other;  // the control volume at the other end
+};
+// Builds Symbolic and GenSym for a general mesh; throws vag::Error on invalid
+// or unsupported input (sizes of cells and faces, orientation is checked on
+// the device).  face_ids: the fracture faces as face indices.
+void build_symbolic_general(int64_t nn, int64_t nc, int64_t nface, const int64_t *cell_face_ptr,
+                            const int32_t *cell_faces, const int64_t *face_node_ptr, const int32_t *face_nodes,
+                            int64_t nf, const int32_t *face_ids, const uint8_t *dirichlet, Symbolic &S,
+                            GenSym &G);
+// Renumbering of the system rows (longest first inside windows) and the
+// sliced-ELL slice pointers of the CSR pattern in S (shared by both paths).
+void finish_symbolic_pattern(Symbolic &S);
+
 // Rows are sorted by length inside windows of this many rows (slice padding).
 constexpr int kSortWindow = 512;
 
@@ -401,6 +441,50 @@ void launch_transport_gather(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, 
                              const double *wsrc, const double *wout, const double *phi_cell, const double *phi_frac,
                              const double *phi_node, const double *dt, double theta, const double *c_in,
                              double *c_out);
+// General cells (general.hip, transport.hip).  Local value array: the m x m
+// Schur blocks M_K = a - r r^T / A_KK of the cells and the (k+1)^2 fracture
+// blocks, at GenSym::loc_off; ga holds the cells' a with the same offsets,
+// gr their row sums at unk_off.
+struct GenMesh {
+    int32_t nc, nf, nn;
+    const int32_t *cnode_ptr, *cnode;
+    const uint8_t *cface_k, *cface_loc;
+    const int32_t *cell_frac, *frac_cell, *fnode_ptr, *fnode, *unk_off;
+    const int64_t *loc_off;
+    int64_t ncn;  // start of the cell-face section of the flux array (the fracture-face section follows 2 nf later)
+};
+void launch_gen_local(hipStream_t s, const GenMesh &g, const double *xyz, const double *perm, double inv_mu,
+                      double *loc, double *ga, double *gr, double *AKK, double *vol, int *bad_cell);
+void launch_gen_frac_local(hipStream_t s, const GenMesh &g, const double *xyz, const double *fwidth,
+                           const double *fperm, double inv_mu, double *loc, double *area);
+// A at every sliced-ELL slot = sum of its contributions; b = -sum M p_bar over
+// the Dirichlet columns
+void launch_gen_assemble(hipStream_t s, int64_t stored, const int64_t *con_ptr, const int64_t *con,
+                         const double *loc, double *A);
+void launch_gen_rhs(hipStream_t s, int32_t nunk, const int32_t *bcon_ptr, const int64_t *bcon,
+                    const int32_t *bcon_node, const double *loc, const double *p_bar, double *b);
+void launch_gen_flux(hipStream_t s, const GenMesh &g, const double *loc, const double *ga, const double *gr,
+                     const double *AKK, const double *u_node, const double *u_frac, double *u_cell, double *F);
+void launch_gen_porous(hipStream_t s, const GenMesh &g, const uint8_t *dirichlet, const uint8_t *frac_node,
+                       const int64_t *inc_ptr, const int32_t *inc_other, const double *vol, const double *poro,
+                       const double *area, const double *fwidth, const double *fporo, double *phi_cell,
+                       double *phi_frac, double *phi_node);
+// transport on the incidence lists (every control volume alike)
+struct GenInc {
+    int32_t nc, nf, nn;
+    const int64_t *ptr;
+    const int32_t *edge, *other;
+    const uint8_t *dirichlet;
+};
+void launch_gen_cfl(hipStream_t s, const GenInc &I, const double *F, const double *wout, const double *phi_cell,
+                    const double *phi_frac, const double *phi_node, double cfl, double *parts, double *dt_out);
+void launch_gen_upwind_count(hipStream_t s, const GenInc &I, const double *F, const double *wsrc,
+                             int32_t *slice_width, uint16_t *meta, int32_t *slice_nnz);
+void launch_gen_upwind_fill(hipStream_t s, const GenInc &I, const double *F, const double *wsrc, const double *wout,
+                            const double *phi_cell, const double *phi_frac, const double *phi_node, const double *dt,
+                            const int64_t *slice_ptr, const uint16_t *meta, int32_t *tcol, double *tval,
+                            double *tdiag);
+
 // Device address of the current device's copy of the allocation-free entry
 // point's static scratch array (looked up once per device) and its size in
 // doubles.

@@ -35,11 +35,14 @@ vp = C.c_void_p
 
 
 class vag_mesh(C.Structure):
-    _fields_ = [("n_nodes", C.c_int64), ("n_cells", C.c_int64), ("node_xyz", vp), ("hex8", vp)]
+    _fields_ = [("n_nodes", C.c_int64), ("n_cells", C.c_int64), ("node_xyz", vp), ("hex8", vp),
+                ("n_faces", C.c_int64), ("cell_face_ptr", vp), ("cell_faces", vp), ("face_node_ptr", vp),
+                ("face_nodes", vp)]
 
 
 class vag_fractures(C.Structure):
-    _fields_ = [("n_frac", C.c_int64), ("face_nodes", vp), ("width", vp), ("perm", vp), ("porosity", vp)]
+    _fields_ = [("n_frac", C.c_int64), ("face_nodes", vp), ("width", vp), ("perm", vp), ("porosity", vp),
+                ("face_ids", vp)]
 
 
 class vag_rock(C.Structure):
@@ -129,6 +132,7 @@ _SIGS = {
     "vag_set_fluxes": ([vp, vp, vp, vp, C.c_int], C.c_int),
     "vag_get_pressure": ([vp, vp, vp, vp, C.c_int], C.c_int),
     "vag_get_fluxes": ([vp, vp, vp, vp, C.c_int], C.c_int),
+    "vag_flux_layout": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "vag_get_porous_volumes": ([vp, vp, vp, vp, C.c_int], C.c_int),
     "vag_get_concentration": ([vp, vp, vp, vp, C.c_int], C.c_int),
     "vag_system_size": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
@@ -215,18 +219,31 @@ class Handle:
         self.device = torch.device(device)
         lib = load()
         t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=self.device)  # noqa: E731
-        self.nn, self.nc, self.nf = int(prob.xyz.shape[0]), int(prob.hex8.shape[0]), int(prob.frac_nodes.shape[0])
+        # general cells (cell -> faces, face -> nodes) when the problem gives faces
+        self.general = getattr(prob, "face_node_ptr", None) is not None
+        self.nn, self.nc = int(prob.xyz.shape[0]), int(prob.n_cells)
+        self.nf = int(len(prob.frac_face_ids) if self.general else prob.frac_nodes.shape[0])
         self._in = dict(
-            xyz=t(prob.xyz, torch.float64), hex8=t(prob.hex8, torch.int32),
-            frac_nodes=t(np.asarray(prob.frac_nodes).reshape(-1, 4), torch.int32),
+            xyz=t(prob.xyz, torch.float64),
             frac_width=t(prob.frac_width, torch.float64), frac_perm=t(prob.frac_perm, torch.float64),
             frac_poro=t(prob.frac_poro, torch.float64), perm=t(prob.perm, torch.float64),
             poro=t(prob.poro, torch.float64), dirichlet=t(prob.dirichlet, torch.uint8),
             p_bar=t(prob.p_bar, torch.float64), c_bar=t(prob.c_bar, torch.float64))
         i = self._in
-        self.mesh = vag_mesh(self.nn, self.nc, _dptr(i["xyz"]), _dptr(i["hex8"]))
-        self.frac = vag_fractures(self.nf, _dptr(i["frac_nodes"]), _dptr(i["frac_width"]),
-                                  _dptr(i["frac_perm"]), _dptr(i["frac_poro"]))
+        if self.general:
+            i.update(cfp=t(prob.cell_face_ptr, torch.int64), cf=t(prob.cell_faces, torch.int32),
+                     fnp=t(prob.face_node_ptr, torch.int64), fn=t(prob.face_nodes, torch.int32),
+                     fid=t(prob.frac_face_ids, torch.int32))
+            self.mesh = vag_mesh(self.nn, self.nc, _dptr(i["xyz"]), None, int(len(prob.face_node_ptr) - 1),
+                                 _dptr(i["cfp"]), _dptr(i["cf"]), _dptr(i["fnp"]), _dptr(i["fn"]))
+            self.frac = vag_fractures(self.nf, None, _dptr(i["frac_width"]), _dptr(i["frac_perm"]),
+                                      _dptr(i["frac_poro"]), _dptr(i["fid"]))
+        else:
+            i.update(hex8=t(prob.hex8, torch.int32),
+                     frac_nodes=t(np.asarray(prob.frac_nodes).reshape(-1, 4), torch.int32))
+            self.mesh = vag_mesh(self.nn, self.nc, _dptr(i["xyz"]), _dptr(i["hex8"]))
+            self.frac = vag_fractures(self.nf, _dptr(i["frac_nodes"]), _dptr(i["frac_width"]),
+                                      _dptr(i["frac_perm"]), _dptr(i["frac_poro"]))
         self.rock = vag_rock(_dptr(i["perm"]), _dptr(i["poro"]), float(prob.mu))
         self.bc = vag_bc(_dptr(i["dirichlet"]), _dptr(i["p_bar"]), _dptr(i["c_bar"]))
         self.options = options if options is not None else default_options(**opt_kw)
@@ -237,6 +254,9 @@ class Handle:
         if st != VAG_OK:
             raise VagError(st, lib.vag_last_error(None).decode())
         self.h = h
+        ncf, nff = C.c_int64(), C.c_int64()
+        lib.vag_flux_layout(h, C.byref(ncf), C.byref(nff))
+        self.n_cell_flux, self.n_frac_flux = ncf.value, nff.value
         self.nw = 0
         w = getattr(prob, "wells", None)
         if w:
@@ -314,7 +334,13 @@ class Handle:
         return dict(u_node=u_node, u_cell=u_cell, u_frac=u_frac)
 
     def fluxes(self):
-        a, b, c = self._get3(load().vag_get_fluxes, [(self.nc, 8), (self.nf, 2), (self.nf, 4)])
+        """F_cell [n_cells, 8] and F_frac [n_frac, 4] on hexahedra; on general
+        cells both flat (cell after cell, face after face: vag_flux_layout)."""
+        if self.general:
+            shapes = [(self.n_cell_flux,), (self.nf, 2), (self.n_frac_flux,)]
+        else:
+            shapes = [(self.nc, 8), (self.nf, 2), (self.nf, 4)]
+        a, b, c = self._get3(load().vag_get_fluxes, shapes)
         return dict(F_cell=a, F_cell_frac=b, F_frac=c)
 
     def porous_volumes(self):

@@ -21,4 +21,8 @@ from .meshes import (  # noqa: F401
     e1_problem,
     e2_problem,
     CONFIGS,
+    GeneralProblem,
+    general_problem,
+    general_from_hex,
+    faces_of_cells,
 )

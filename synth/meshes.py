@@ -491,3 +491,157 @@ def plane_x_faces(dims, cells, i0):
             pts = [p for _, p in sorted(zip([np.arctan2(k - ck, j - cj) for j, k in zip(js, ks)], pts))]
         faces.append(tuple(pts))
     return faces
+
+
+# ----------------------------------------------------------------------------
+# General cells given by their faces (the mesh form of §3.1)
+# ----------------------------------------------------------------------------
+
+# local faces of VTK cells, each cyclic and outward for a positively
+# oriented cell (hexahedron, prism (wedge), tetrahedron)
+CELL_FACES = {
+    8: [(0, 4, 7, 3), (1, 2, 6, 5), (0, 1, 5, 4), (3, 7, 6, 2), (0, 3, 2, 1), (4, 5, 6, 7)],
+    6: [(0, 2, 1), (3, 4, 5), (0, 1, 4, 3), (1, 2, 5, 4), (0, 3, 5, 2)],
+    4: [(0, 2, 1), (0, 1, 3), (1, 2, 3), (0, 3, 2)],
+}
+
+
+@dataclass
+class GeneralProblem:
+    """A mesh of general cells: cell -> faces (CSR), face -> nodes (CSR, cyclic).
+    ``cells`` keeps each cell's nodes in VTK order (for checkers that work
+    with node tuples); ``frac_face_ids`` index the face list."""
+    name: str
+    xyz: np.ndarray
+    cells: list
+    cell_face_ptr: np.ndarray   # [n_cells + 1] int64
+    cell_faces: np.ndarray      # int32 face ids
+    face_node_ptr: np.ndarray   # [n_faces + 1] int64
+    face_nodes: np.ndarray      # int32, cyclic per face
+    frac_face_ids: np.ndarray   # [n_frac] int32
+    frac_width: np.ndarray
+    frac_perm: np.ndarray
+    frac_poro: np.ndarray
+    perm: np.ndarray            # [n_cells, 6]
+    poro: np.ndarray
+    mu: float
+    dirichlet: np.ndarray
+    p_bar: np.ndarray
+    c_bar: np.ndarray
+    rtol: float = 1e-10
+    cfl: float = 0.9
+    n_steps: int = 20
+    t_final: float = 0.0
+    wells: dict = None
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def n_cells(self) -> int:
+        return len(self.cells)
+
+    @property
+    def n_frac(self) -> int:
+        return int(len(self.frac_face_ids))
+
+    def face(self, f):
+        return tuple(int(v) for v in self.face_nodes[self.face_node_ptr[f]:self.face_node_ptr[f + 1]])
+
+    def frac_faces(self):
+        """The fracture faces as node tuples (the face list's cyclic order)."""
+        return [self.face(f) for f in self.frac_face_ids]
+
+    def cell_node_order(self, K):
+        """The cell's nodes in the order they first appear along its faces."""
+        out = []
+        for q in range(self.cell_face_ptr[K], self.cell_face_ptr[K + 1]):
+            for s in self.face(self.cell_faces[q]):
+                if s not in out:
+                    out.append(s)
+        return out
+
+
+def faces_of_cells(cells, rng=None, shuffle=False, flip=False):
+    """Face list of a conforming mesh of VTK cells: each distinct face once,
+    with the node order of the first cell that has it (reversed at random
+    with ``flip``), and each cell's faces (in local-face order, or shuffled)."""
+    index, fptr, fnodes, cptr, cfaces = {}, [0], [], [0], []
+    for c in cells:
+        local = []
+        for lf in CELL_FACES[len(c)]:
+            nodes = tuple(int(c[v]) for v in lf)
+            key = tuple(sorted(nodes))
+            f = index.get(key)
+            if f is None:
+                f = index[key] = len(fptr) - 1
+                if flip and rng is not None and rng.random() < 0.5:
+                    nodes = nodes[::-1]
+                fnodes.extend(nodes)
+                fptr.append(len(fnodes))
+            local.append(f)
+        if shuffle and rng is not None:
+            local = [local[i] for i in rng.permutation(len(local))]
+        cfaces.extend(local)
+        cptr.append(len(cfaces))
+    return (np.array(cptr, np.int64), np.array(cfaces, np.int32), np.array(fptr, np.int64),
+            np.array(fnodes, np.int32), index)
+
+
+def general_problem(kind, dims, seed, jitter=0.2, aniso_sigma=1.0, frac_plane=None, ratio=1e3, df=0.01,
+                    shuffle=True, flip=True, dirichlet="x", n_steps=20, planar_x=False, name=None):
+    """Unit-box mesh of tetrahedra ("tet"), prisms ("prism") or hexahedra
+    ("hex") on a (nx, ny, nz) grid: interior nodes jittered by U[-jitter h,
+    jitter h] (only in y and z with ``planar_x``, so that x planes stay
+    planar), lognormal anisotropic tensors (sigma aniso_sigma; None =
+    isotropic 1), an optional fracture plane x = frac_plane (grid index) of
+    the cells' faces with Lambda_f = ratio, d_f = df, Dirichlet data p = 1 - x
+    and c = 1 at x = 0, 0 at x = 1 (``dirichlet="x"``) or p = 1 - x + 0.3 y -
+    0.2 z on every boundary node ("all")."""
+    rng = np.random.default_rng([31, seed])
+    xyz, _ = structured_hex(*dims)
+    h = 1.0 / np.array(dims, float)
+    interior = np.all((xyz > 1e-12) & (xyz < 1 - 1e-12), axis=1)
+    axes = slice(1, 3) if planar_x else slice(0, 3)
+    width = 2 if planar_x else 3
+    xyz[interior, axes] += rng.uniform(-jitter, jitter, (int(interior.sum()), width)) * h[axes]
+    if kind == "hex":
+        cells = [tuple(int(v) for v in c) for c in structured_hex(*dims)[1]]
+    else:
+        cells = orient_tets(xyz, simplex_cells(dims, kind))
+    nc = len(cells)
+    perm = lognormal_tensors(nc, aniso_sigma, rng) if aniso_sigma else isotropic(nc)
+    cfp, cf, fnp, fn, index = faces_of_cells(cells, rng, shuffle=shuffle, flip=flip)
+    if frac_plane is not None:
+        on = lambda s: s % (dims[0] + 1) == frac_plane  # noqa: E731
+        fids = [f for key, f in sorted(index.items(), key=lambda kv: kv[1]) if all(on(s) for s in key)]
+    else:
+        fids = []
+    nf = len(fids)
+    if dirichlet == "all":
+        d = (~interior).astype(np.uint8)
+        pb = 1.0 - xyz[:, 0] + 0.3 * xyz[:, 1] - 0.2 * xyz[:, 2]
+    else:
+        d = ((xyz[:, 0] < 1e-12) | (xyz[:, 0] > 1 - 1e-12)).astype(np.uint8)
+        pb = 1.0 - xyz[:, 0]
+    cb = (xyz[:, 0] < 1e-12).astype(float)
+    return GeneralProblem(
+        name=name or f"{kind}{tuple(dims)}-{seed}", xyz=xyz, cells=cells, cell_face_ptr=cfp, cell_faces=cf,
+        face_node_ptr=fnp, face_nodes=fn, frac_face_ids=np.array(fids, np.int32), frac_width=np.full(nf, df),
+        frac_perm=np.full(nf, float(ratio)), frac_poro=np.ones(nf), perm=perm, poro=np.ones(nc), mu=1.0,
+        dirichlet=d, p_bar=pb, c_bar=cb, n_steps=n_steps)
+
+
+def general_from_hex(prob, seed=0, shuffle=True, flip=True):
+    """The same hexahedral problem in the general (faces) form."""
+    rng = np.random.default_rng([37, seed])
+    cells = [tuple(int(v) for v in c) for c in prob.hex8]
+    cfp, cf, fnp, fn, index = faces_of_cells(cells, rng, shuffle=shuffle, flip=flip)
+    fids = np.array([index[tuple(sorted(int(v) for v in f))] for f in np.asarray(prob.frac_nodes).reshape(-1, 4)],
+                    np.int32)
+    return GeneralProblem(
+        name=prob.name + "-faces", xyz=prob.xyz, cells=cells, cell_face_ptr=cfp, cell_faces=cf, face_node_ptr=fnp,
+        face_nodes=fn, frac_face_ids=fids, frac_width=prob.frac_width, frac_perm=prob.frac_perm,
+        frac_poro=prob.frac_poro, perm=prob.perm, poro=prob.poro, mu=prob.mu, dirichlet=prob.dirichlet,
+        p_bar=prob.p_bar, c_bar=prob.c_bar, rtol=prob.rtol, cfl=prob.cfl, n_steps=prob.n_steps)

@@ -126,3 +126,96 @@ def test_peaceman_index_matches_oracle():
         assert vag.peaceman_wi(dx, dz, df, lam, rw) == pytest.approx(oracle.peaceman_wi(dx, dz, df, lam, rw),
                                                                      rel=1e-13)
     assert vag.peaceman_wi(-1.0, 1.0, 1.0, 1.0, 0.1) == 0.0
+
+
+def _host_create_general(q, **opt):
+    """vag_create of a general (faces) problem with host arrays."""
+    lib = vag.load()
+    keep = []
+
+    def ptr(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data_as(C.c_void_p) if a.size else None
+
+    mesh = vag.vag_mesh(q.n_nodes, q.n_cells, ptr(q.xyz, np.float64), None, len(q.face_node_ptr) - 1,
+                        ptr(q.cell_face_ptr, np.int64), ptr(q.cell_faces, np.int32), ptr(q.face_node_ptr, np.int64),
+                        ptr(q.face_nodes, np.int32))
+    fr = vag.vag_fractures(q.n_frac, None, ptr(q.frac_width, np.float64), ptr(q.frac_perm, np.float64),
+                           ptr(q.frac_poro, np.float64), ptr(q.frac_face_ids, np.int32))
+    rock = vag.vag_rock(ptr(q.perm, np.float64), ptr(q.poro, np.float64), q.mu)
+    bc = vag.vag_bc(ptr(q.dirichlet, np.uint8), ptr(q.p_bar, np.float64), ptr(q.c_bar, np.float64))
+    o = vag.default_options(**opt)
+    h = C.c_void_p()
+    st = lib.vag_create(C.byref(mesh), C.byref(fr), C.byref(rock), C.byref(bc), C.byref(o), vag.VAG_MEM_HOST,
+                        None, C.byref(h))
+    assert not h.value
+    return st, lib.vag_last_error(None).decode()
+
+
+def _with_faces(q, fptr, fnodes):
+    import copy
+    r = copy.copy(q)
+    r.face_node_ptr, r.face_nodes = np.asarray(fptr, np.int64), np.asarray(fnodes, np.int32)
+    return r
+
+
+def test_general_descriptor_rejected():
+    """The general (faces) form: host validation before any device work."""
+    q = synth.general_problem("tet", (2, 2, 2), 1, frac_plane=1)
+    # a face with 5 nodes: unsupported
+    fp, fn = q.face_node_ptr.copy(), list(q.face_nodes)
+    extra = [s for s in range(q.n_nodes) if s not in fn[:fp[1]]][:2]
+    fn[fp[1]:fp[1]] = extra
+    fp[1:] += 2
+    st, msg = _host_create_general(_with_faces(q, fp, fn))
+    assert st == vag.VAG_ERR_UNSUPPORTED and "nodes" in msg
+    # a cell with 7 faces: unsupported
+    import copy
+    r = copy.copy(q)
+    cf = list(q.cell_faces)
+    extra = [int(f) for f in range(len(q.face_node_ptr) - 1) if f not in cf[:4]][:3]
+    r.cell_faces = np.array(cf[:4] + extra + cf[4:], np.int32)
+    r.cell_face_ptr = q.cell_face_ptr.copy()
+    r.cell_face_ptr[1:] += 3
+    st, msg = _host_create_general(r)
+    assert st in (vag.VAG_ERR_UNSUPPORTED, vag.VAG_ERR_MESH) and ("faces" in msg or "more than two" in msg)
+    # a face in three cells
+    r = copy.copy(q)
+    cf = np.array(q.cell_faces)
+    f0 = int(cf[0])
+    owners = [K for K in range(q.n_cells) if f0 in cf[q.cell_face_ptr[K]:q.cell_face_ptr[K + 1]]]
+    other = next(K for K in range(q.n_cells) if K not in owners)
+    cf[q.cell_face_ptr[other]] = f0
+    r.cell_faces = cf
+    if len(owners) == 2:
+        st, msg = _host_create_general(r)
+        assert st == vag.VAG_ERR_MESH and "more than two cells" in msg
+    # fracture face index out of range, and listed twice
+    r = copy.copy(q)
+    r.frac_face_ids = np.array([10 ** 6], np.int32)
+    r.frac_width, r.frac_perm, r.frac_poro = np.ones(1), np.ones(1), np.ones(1)
+    st, msg = _host_create_general(r)
+    assert st == vag.VAG_ERR_ARG and "out of range" in msg
+    r.frac_face_ids = np.array([q.frac_face_ids[0]] * 2, np.int32)
+    r.frac_width, r.frac_perm, r.frac_poro = np.ones(2), np.ones(2), np.ones(2)
+    st, msg = _host_create_general(r)
+    assert st == vag.VAG_ERR_ARG and "listed twice" in msg
+
+
+def test_mesh_without_hex8_or_faces_rejected():
+    lib = vag.load()
+    xyz = np.zeros((4, 3))
+    mesh = vag.vag_mesh(4, 1, xyz.ctypes.data_as(C.c_void_p), None)
+    d = np.ones(4, np.uint8)
+    pb = np.zeros(4)
+    perm = np.ones((1, 6))
+    poro = np.ones(1)
+    rock = vag.vag_rock(perm.ctypes.data_as(C.c_void_p), poro.ctypes.data_as(C.c_void_p), 1.0)
+    bc = vag.vag_bc(d.ctypes.data_as(C.c_void_p), pb.ctypes.data_as(C.c_void_p), pb.ctypes.data_as(C.c_void_p))
+    fr = vag.vag_fractures(0, None, None, None, None, None)
+    o = vag.default_options()
+    h = C.c_void_p()
+    st = lib.vag_create(C.byref(mesh), C.byref(fr), C.byref(rock), C.byref(bc), C.byref(o), vag.VAG_MEM_HOST,
+                        None, C.byref(h))
+    assert st == vag.VAG_ERR_ARG and "cell_face_ptr" in lib.vag_last_error(None).decode()
