@@ -134,6 +134,43 @@ def cpu_baseline_sampled(prob, vag, h, dt, n_steps_sample=20, cell_stride=64):
                        "so the value is an upper bound of its rate; one thread (these oracle loops are serial)")}
 
 
+def cpu_baseline_general(prob, synth, kind, cell_stride=2000, small=(8, 8, 8), steps=3):
+    """The general-cell oracle (numpy, loops per cell and per flux) on a
+    bounded sample of a general-cell workload: the local matrices of every
+    cell_stride-th cell of the real mesh, scaled to all cells, and transport
+    steps of the same generator on a small grid, scaled per flux to the
+    workload's fluxes and step count.  The global assembly and solve are left
+    out, so the value bounds the oracle's rate from above."""
+    from oracle import general_cells as gc
+    cells = np.asarray(prob.cells)[::cell_stride]
+    used, inv = np.unique(cells, return_inverse=True)
+    sub = gc.Mesh(prob.xyz[used], inv.reshape(cells.shape), prob.perm[::cell_stride], prob.poro[::cell_stride])
+    t0 = time.perf_counter()
+    for K in range(len(cells)):
+        gc.cell_matrix(sub, K)
+    t_cells = time.perf_counter() - t0
+    q = synth.general_workload(kind, small, 2, n_patches=2)
+    m = gc.Mesh(q.xyz, q.cells, q.perm, q.poro, q.frac_faces(), q.frac_width, q.frac_perm, q.frac_poro, q.dirichlet,
+                q.p_bar, q.c_bar, q.mu)
+    sol = gc.solve_darcy(m)
+    phi = gc.porous_volumes(m, sol)
+    dt = gc.cfl_dt(m, sol, phi, 0.9)
+    t0 = time.perf_counter()
+    gc.transport(m, sol, phi, dt, steps)
+    t_steps = time.perf_counter() - t0
+    n_edges_small = sum(len(c) for c in q.cells) + 2 * q.n_frac + len(np.concatenate(q.frac_faces() or [[]]))
+    n_edges = int(np.asarray(prob.cells).size) + 2 * prob.n_frac + int(sum(len(f) for f in prob.frac_faces()))
+    per_solve = t_cells * prob.n_cells / len(cells) + t_steps / steps / n_edges_small * n_edges * prob.n_steps
+    log(f"general-cell oracle baseline: {per_solve:.1f} s per solve")
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{prob.name}: the general-cell oracle's local matrices of {len(cells)} of its {prob.n_cells} "
+                       f"cells ({t_cells:.2f} s) and {steps} transport steps of the same generator on a "
+                       f"{small[0]}x{small[1]}x{small[2]} grid ({t_steps:.2f} s, {n_edges_small} fluxes), scaled to "
+                       f"all cells and to {n_edges} fluxes x {prob.n_steps} steps ({per_solve:.1f} s); its global "
+                       "assembly and solve are left out, so the value is an upper bound of its rate; one thread "
+                       "(numpy loops)")}
+
+
 def results(vag, h):
     """Pressures and concentrations of a handle, on the host."""
     return vag.to_numpy(h.pressure()) | vag.to_numpy(h.concentration())
@@ -246,8 +283,20 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-PROFILE_NAME = {"config2": "config2_64cubed", "config3": "config3_128cubed", "config5": "config5_192cubed"}
-DEFAULTS = {"config2": (64, "fp64", "cg"), "config3": (128, "mixed", "gmres"), "config5": (192, "mixed", "cg")}
+PROFILE_NAME = {"config2": "config2_64cubed", "config3": "config3_128cubed", "config5": "config5_192cubed",
+                "tet": "tet_96x96x112", "prism": "prism_128cubed"}
+DEFAULTS = {"config2": (64, "fp64", "cg"), "config3": (128, "mixed", "gmres"), "config5": (192, "mixed", "cg"),
+            "tet": (96, "mixed", "cg"), "prism": (128, "mixed", "cg")}
+# general-cell workloads: the grid each is split from (tetrahedra: the size of the paper's tetrahedral
+# mesh, 6.2 M cells and 1.06 M nodes; prisms: 4.2 M cells)
+GENERAL_DIMS = {"tet": lambda n: (n, n, n * 7 // 6), "prism": lambda n: (n, n, n)}
+
+
+def make_problem(synth, workload, n):
+    if workload in GENERAL_DIMS:
+        return synth.general_workload(workload, GENERAL_DIMS[workload](n), 1, n_patches=40, n_steps=200,
+                                      name=f"{workload}{GENERAL_DIMS[workload](n)}")
+    return getattr(synth, workload)(n=n)
 
 
 def profiled_mean_us(kernel, workload):
@@ -271,6 +320,13 @@ def describe(args, prob):
     if args.workload == "config3":
         return (f"config3: jittered {n}^3 hexahedra, lognormal anisotropic tensors, 40 face patches "
                 f"(contrasts 1e2/1e4/1e6), {args.krylov.upper()} rtol {prob.rtol:g}, {prob.n_steps} upwind steps")
+    if args.workload in GENERAL_DIMS:
+        d = GENERAL_DIMS[args.workload](n)
+        what = {"tet": "tetrahedra (6 per grid hexahedron)", "prism": "prisms (2 per grid hexahedron)"}[args.workload]
+        return (f"{args.workload}: jittered {d[0]}x{d[1]}x{d[2]} grid split into {what}, {prob.n_cells} cells and "
+                f"{prob.n_nodes} nodes given by their faces, lognormal anisotropic tensors, 40 face patches "
+                f"(contrasts 1e2/1e4/1e6, {prob.n_frac} fracture faces), {args.krylov.upper()} rtol {prob.rtol:g}, "
+                f"{prob.n_steps} upwind steps")
     return (f"config5: jittered {n}^3 hexahedra, lognormal anisotropic tensors, 200 face patches at 1e6, "
             f"{args.krylov.upper()} rtol {prob.rtol:g}, {prob.n_steps} upwind steps")
 
@@ -401,7 +457,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precond", choices=["jacobi", "amg", "bjilu0"], default=os.environ.get("VAG_BENCH_PRECOND", "amg"))
-    ap.add_argument("--workload", choices=["config2", "config3", "config5"], default="config5",
+    ap.add_argument("--workload", choices=["config2", "config3", "config5", "tet", "prism"], default="config5",
                     help="config5 (the headline): 192^3 jittered anisotropic, 200 patches at 1e6, FP32-AMG CG, "
                          "1000 steps; config3: jittered anisotropic 128^3, 40 patches; config2: 64^3, 4 clipped "
                          "fractures")
@@ -451,10 +507,10 @@ def main():
     args.precision = args.precision or (prec_def if args.precond == "amg" else "fp64")
     args.krylov = args.krylov or ("bicgstab" if args.precond == "bjilu0" else kry_def)
     log(f"generating {args.workload} n={args.n}")
-    prob = getattr(synth, args.workload)(n=args.n)
+    prob = make_problem(synth, args.workload, args.n)
     if args.wells > 0:
         synth.add_wells(prob, args.n, n_inj=1, n_prod=args.wells - 1)
-    log(f"{len(prob.hex8)} cells, {prob.n_frac} fracture faces; creating the handle")
+    log(f"{prob.n_cells} cells, {prob.n_frac} fracture faces; creating the handle")
     opts = solver_options(vag, args, prob)
     t0 = time.perf_counter()
     h = vag.Handle(prob, **opts)
@@ -479,6 +535,8 @@ def main():
             oref = {"u_node": ores["darcy"]["u_node"], "u_frac": ores["darcy"]["u_frac"],
                     "c_cell": ores["c_cell"], "c_node": ores["c_node"]}
             vs_oracle = {"note": f"both sides solved to rtol {prob.rtol:g}", args.precision: differences(gpu_res, oref)}
+        elif args.workload in GENERAL_DIMS:
+            cpu = cpu_baseline_general(prob, synth, args.workload)
         else:
             cpu = cpu_baseline_sampled(prob, vag, h, tinfo["dt"])
     h.close()

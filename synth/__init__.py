@@ -25,4 +25,6 @@ from .meshes import (  # noqa: F401
     general_problem,
     general_from_hex,
     faces_of_cells,
+    general_workload,
+    grid_cells,
 )

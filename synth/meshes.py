@@ -563,30 +563,126 @@ class GeneralProblem:
         return out
 
 
+def grid_cells(dims, kind):
+    """Cells of a structured (nx, ny, nz) grid as an array of VTK node tuples:
+    hexahedra, prisms (2 per hexahedron, split along the 0-2 diagonal of its
+    bottom square) or tetrahedra (6 per hexahedron around its 0-6 diagonal),
+    in the order of ``simplex_cells``."""
+    nx, ny, nz = dims
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    i, j, k = i.ravel(), j.ravel(), k.ravel()
+    n = lambda a, b, c: node_index(dims, a, b, c)  # noqa: E731
+    h = np.stack([n(i, j, k), n(i + 1, j, k), n(i + 1, j + 1, k), n(i, j + 1, k), n(i, j, k + 1),
+                  n(i + 1, j, k + 1), n(i + 1, j + 1, k + 1), n(i, j + 1, k + 1)], axis=1).astype(np.int32)
+    if kind == "hex":
+        return h
+    if kind == "prism":
+        return np.stack([h[:, [0, 1, 2, 4, 5, 6]], h[:, [0, 2, 3, 4, 6, 7]]], axis=1).reshape(-1, 6)
+    pairs = ((1, 2), (2, 3), (3, 7), (7, 4), (4, 5), (5, 1))
+    return np.stack([h[:, [0, a, b, 6]] for a, b in pairs], axis=1).reshape(-1, 4)
+
+
+def orient_tet_array(xyz, cells):
+    """Tetrahedra with nodes 1 and 2 swapped where det[p1-p0, p2-p0, p3-p0] < 0."""
+    cells = np.array(cells)
+    if cells.shape[1] != 4:
+        return cells
+    p = xyz[cells]
+    det = np.einsum("ij,ij->i", p[:, 1] - p[:, 0], np.cross(p[:, 2] - p[:, 0], p[:, 3] - p[:, 0]))
+    neg = det < 0
+    cells[neg, 1], cells[neg, 2] = cells[neg, 2].copy(), cells[neg, 1].copy()
+    return cells
+
+
 def faces_of_cells(cells, rng=None, shuffle=False, flip=False):
-    """Face list of a conforming mesh of VTK cells: each distinct face once,
-    with the node order of the first cell that has it (reversed at random
-    with ``flip``), and each cell's faces (in local-face order, or shuffled)."""
-    index, fptr, fnodes, cptr, cfaces = {}, [0], [], [0], []
-    for c in cells:
-        local = []
-        for lf in CELL_FACES[len(c)]:
-            nodes = tuple(int(c[v]) for v in lf)
-            key = tuple(sorted(nodes))
-            f = index.get(key)
-            if f is None:
-                f = index[key] = len(fptr) - 1
-                if flip and rng is not None and rng.random() < 0.5:
-                    nodes = nodes[::-1]
-                fnodes.extend(nodes)
-                fptr.append(len(fnodes))
-            local.append(f)
-        if shuffle and rng is not None:
-            local = [local[i] for i in rng.permutation(len(local))]
-        cfaces.extend(local)
-        cptr.append(len(cfaces))
-    return (np.array(cptr, np.int64), np.array(cfaces, np.int32), np.array(fptr, np.int64),
-            np.array(fnodes, np.int32), index)
+    """Face list of a conforming mesh of VTK cells (an array, one cell type):
+    each distinct face once, with the node order of its first cell (reversed
+    at random with ``flip``), and each cell's faces in local-face order (or
+    shuffled per cell).  Returns cell_face_ptr, cell_faces, face_node_ptr,
+    face_nodes and, per face, its node key (sorted nodes, -1 padded)."""
+    cells = np.asarray(cells, np.int64)
+    nc, nv = cells.shape
+    table = CELL_FACES[nv]
+    face_id = np.zeros((nc, len(table)), np.int64)
+    ptr_parts, node_parts, key_parts, nfaces = [], [], [], 0
+    for k in (3, 4):
+        lfs = [lf for lf in range(len(table)) if len(table[lf]) == k]
+        if not lfs:
+            continue
+        F = np.stack([cells[:, list(table[lf])] for lf in lfs], axis=1).reshape(-1, k)  # cell-major
+        key = np.sort(F, axis=1)
+        _, first, inv = np.unique(key, axis=0, return_index=True, return_inverse=True)
+        inv = inv.ravel()
+        order = np.argsort(first, kind="stable")  # faces numbered by first appearance
+        rank = np.empty_like(order)
+        rank[order] = np.arange(len(order))
+        nodes = F[first[order]]
+        if flip and rng is not None:
+            rev = rng.random(len(nodes)) < 0.5
+            nodes[rev] = nodes[rev, ::-1]
+        face_id[:, lfs] = (nfaces + rank[inv]).reshape(nc, len(lfs))
+        node_parts.append(nodes.ravel())
+        ptr_parts.append(np.full(len(nodes), k))
+        kp = np.full((len(nodes), 4), -1, np.int64)
+        kp[:, :k] = np.sort(nodes, axis=1)
+        key_parts.append(kp)
+        nfaces += len(nodes)
+    if shuffle and rng is not None:
+        perm = np.argsort(rng.random(face_id.shape), axis=1)
+        face_id = np.take_along_axis(face_id, perm, axis=1)
+    fptr = np.concatenate([[0], np.cumsum(np.concatenate(ptr_parts))]).astype(np.int64)
+    cptr = (np.arange(nc + 1) * len(table)).astype(np.int64)
+    return (cptr, face_id.ravel().astype(np.int32), fptr, np.concatenate(node_parts).astype(np.int32),
+            np.concatenate(key_parts))
+
+
+def _square_keys(dims, keys):
+    """Grid square of each face lying on an axis plane (-1 if none): faces
+    are given by their sorted node keys (-1 padded)."""
+    nx, ny, nz = dims
+    valid = keys >= 0
+    s = np.where(valid, keys, keys[:, :1])
+    g = np.stack([s % (nx + 1), (s // (nx + 1)) % (ny + 1), s // ((nx + 1) * (ny + 1))], axis=-1)  # [f, 4, 3]
+    N = max(dims) + 1
+    out = np.full(len(keys), -1, np.int64)
+    for axis in range(3):
+        a, b = [d for d in range(3) if d != axis]
+        on = np.all(g[:, :, axis] == g[:, :1, axis], axis=1)
+        code = ((axis * N + g[:, 0, axis]) * N + g[:, :, a].min(axis=1)) * N + g[:, :, b].min(axis=1)
+        out = np.where(on & (out < 0), code, out)
+    return out
+
+
+def general_workload(kind, dims, seed, n_patches=40, ratios=(1e2, 1e4, 1e6), jitter=0.2, aniso_sigma=1.0,
+                     df=0.01, n_steps=200, shuffle=False, flip=False, name=None):
+    """Unit-box workload of tetrahedra, prisms or hexahedra (a jittered grid
+    split into cells), lognormal anisotropic tensors, ``n_patches`` random
+    axis-aligned fracture patches (the 128^3 workload's rule) whose cell faces
+    (triangles or quadrangles lying in a patch's grid squares) are fracture
+    faces, Dirichlet p = 1 - x, c = 1 at x = 0 and 0 at x = 1."""
+    rng = np.random.default_rng([41, seed])
+    xyz, _ = structured_hex(*dims)
+    xyz = jitter_nodes(xyz, dims, jitter, rng)
+    cells = orient_tet_array(xyz, grid_cells(dims, kind))
+    nc = len(cells)
+    perm = lognormal_tensors(nc, aniso_sigma, rng) if aniso_sigma else isotropic(nc)
+    quads, ratio = merge_patches(random_patches(dims, n_patches, rng, ratios))
+    cfp, cf, fnp, fn, keys = faces_of_cells(cells, rng, shuffle=shuffle, flip=flip)
+    fkey = _square_keys(dims, keys)
+    qkey = _square_keys(dims, np.sort(quads.astype(np.int64), axis=1)) if len(quads) else np.zeros(0, np.int64)
+    order = np.argsort(qkey)
+    pos = np.searchsorted(qkey[order], fkey)
+    pos = np.minimum(pos, max(len(qkey) - 1, 0))
+    hit = (fkey >= 0) & (len(qkey) > 0) & (qkey[order][pos] == fkey) if len(qkey) else np.zeros(len(fkey), bool)
+    fids = np.nonzero(hit)[0].astype(np.int32)
+    fr = ratio[order][pos[fids]] if len(fids) else np.zeros(0)
+    d, pb, cb = x_dirichlet(dims, len(xyz), xyz)
+    nf = len(fids)
+    return GeneralProblem(
+        name=name or f"{kind}{tuple(dims)}-{seed}", xyz=xyz, cells=cells, cell_face_ptr=cfp, cell_faces=cf,
+        face_node_ptr=fnp, face_nodes=fn, frac_face_ids=fids, frac_width=np.full(nf, df), frac_perm=fr * 1.0,
+        frac_poro=np.ones(nf), perm=perm, poro=np.ones(nc), mu=1.0, dirichlet=d, p_bar=pb, c_bar=cb, rtol=1e-8,
+        cfl=0.9, n_steps=n_steps)
 
 
 def general_problem(kind, dims, seed, jitter=0.2, aniso_sigma=1.0, frac_plane=None, ratio=1e3, df=0.01,
@@ -598,7 +694,8 @@ def general_problem(kind, dims, seed, jitter=0.2, aniso_sigma=1.0, frac_plane=No
     isotropic 1), an optional fracture plane x = frac_plane (grid index) of
     the cells' faces with Lambda_f = ratio, d_f = df, Dirichlet data p = 1 - x
     and c = 1 at x = 0, 0 at x = 1 (``dirichlet="x"``) or p = 1 - x + 0.3 y -
-    0.2 z on every boundary node ("all")."""
+    0.2 z on every boundary node ("all").  Faces are listed in random
+    orientation and each cell's faces in random order (``flip``, ``shuffle``)."""
     rng = np.random.default_rng([31, seed])
     xyz, _ = structured_hex(*dims)
     h = 1.0 / np.array(dims, float)
@@ -606,18 +703,15 @@ def general_problem(kind, dims, seed, jitter=0.2, aniso_sigma=1.0, frac_plane=No
     axes = slice(1, 3) if planar_x else slice(0, 3)
     width = 2 if planar_x else 3
     xyz[interior, axes] += rng.uniform(-jitter, jitter, (int(interior.sum()), width)) * h[axes]
-    if kind == "hex":
-        cells = [tuple(int(v) for v in c) for c in structured_hex(*dims)[1]]
-    else:
-        cells = orient_tets(xyz, simplex_cells(dims, kind))
+    cells = orient_tet_array(xyz, grid_cells(dims, kind))
     nc = len(cells)
     perm = lognormal_tensors(nc, aniso_sigma, rng) if aniso_sigma else isotropic(nc)
-    cfp, cf, fnp, fn, index = faces_of_cells(cells, rng, shuffle=shuffle, flip=flip)
+    cfp, cf, fnp, fn, keys = faces_of_cells(cells, rng, shuffle=shuffle, flip=flip)
     if frac_plane is not None:
-        on = lambda s: s % (dims[0] + 1) == frac_plane  # noqa: E731
-        fids = [f for key, f in sorted(index.items(), key=lambda kv: kv[1]) if all(on(s) for s in key)]
+        on = lambda s: (s < 0) | (s % (dims[0] + 1) == frac_plane)  # noqa: E731
+        fids = np.nonzero(np.all(on(keys), axis=1))[0].astype(np.int32)
     else:
-        fids = []
+        fids = np.zeros(0, np.int32)
     nf = len(fids)
     if dirichlet == "all":
         d = (~interior).astype(np.uint8)
@@ -628,7 +722,7 @@ def general_problem(kind, dims, seed, jitter=0.2, aniso_sigma=1.0, frac_plane=No
     cb = (xyz[:, 0] < 1e-12).astype(float)
     return GeneralProblem(
         name=name or f"{kind}{tuple(dims)}-{seed}", xyz=xyz, cells=cells, cell_face_ptr=cfp, cell_faces=cf,
-        face_node_ptr=fnp, face_nodes=fn, frac_face_ids=np.array(fids, np.int32), frac_width=np.full(nf, df),
+        face_node_ptr=fnp, face_nodes=fn, frac_face_ids=fids, frac_width=np.full(nf, df),
         frac_perm=np.full(nf, float(ratio)), frac_poro=np.ones(nf), perm=perm, poro=np.ones(nc), mu=1.0,
         dirichlet=d, p_bar=pb, c_bar=cb, n_steps=n_steps)
 
@@ -636,9 +730,10 @@ def general_problem(kind, dims, seed, jitter=0.2, aniso_sigma=1.0, frac_plane=No
 def general_from_hex(prob, seed=0, shuffle=True, flip=True):
     """The same hexahedral problem in the general (faces) form."""
     rng = np.random.default_rng([37, seed])
-    cells = [tuple(int(v) for v in c) for c in prob.hex8]
-    cfp, cf, fnp, fn, index = faces_of_cells(cells, rng, shuffle=shuffle, flip=flip)
-    fids = np.array([index[tuple(sorted(int(v) for v in f))] for f in np.asarray(prob.frac_nodes).reshape(-1, 4)],
+    cells = np.asarray(prob.hex8, np.int32)
+    cfp, cf, fnp, fn, keys = faces_of_cells(cells, rng, shuffle=shuffle, flip=flip)
+    look = {tuple(k): f for f, k in enumerate(keys.tolist())}
+    fids = np.array([look[tuple(sorted(int(v) for v in f))] for f in np.asarray(prob.frac_nodes).reshape(-1, 4)],
                     np.int32)
     return GeneralProblem(
         name=prob.name + "-faces", xyz=prob.xyz, cells=cells, cell_face_ptr=cfp, cell_faces=cf, face_node_ptr=fnp,
