@@ -232,8 +232,9 @@ vag_status vag_default_options(vag_options *opt);
 /*
  * Creates a handle: validates the mesh, matches fracture faces to cell faces,
  * numbers the unknowns (free nodes, then fracture faces), builds the sparsity
- * pattern of the cell-eliminated system (eq eqschur), the cell colouring used
- * for conflict-free assembly and the node adjacency used by transport, and
+ * pattern of the cell-eliminated system (eq eqschur) with the slot of every
+ * local-matrix entry in it (each row of the system is then gathered by one
+ * thread, in a fixed order) and the node adjacency used by transport, and
  * copies all data to the device.  hip_stream may be NULL (null stream).
  * With opt->eliminate_frac_faces, the fracture faces are grouped by shared
  * cells (after the cell elimination the face-face block is block diagonal

@@ -5,12 +5,15 @@
 //                    r_nu and A_KK = sum r_nu.
 // vag_frac_kernel    one thread per fracture face: the 5x5 P1 stiffness of
 //                    d_f Lambda_f / mu on the face's 4 triangles (eq VAGFluxFracture).
-// vag_scatter_kernel one thread per cell of one colour: the cell Schur block
-//                    M_K = a - r r^T / A_KK (eq eqschur) and, for fracture
-//                    faces the cell owns (lower cell index), the fracture block,
-//                    added into the CSR values; Dirichlet columns go to b.
-//                    Cells of a colour share no node, so no atomics are needed
-//                    and the summation order is fixed.
+// asm_node_rows_kernel one thread per free-node row: the row gathers, from
+//                    every cell around its node, row s of the cell Schur block
+//                    M_K = a - r r^T / A_KK (eq eqschur) and the couplings to
+//                    the fracture faces of those cells; Dirichlet columns go to
+//                    b.  Each row is written by one thread only, so no atomics
+//                    are needed and the summation order is fixed.
+// asm_face_rows_kernel / asm_elim_rows_kernel  the same gather for the rows
+//                    of kept fracture faces and for the dense blocks of the
+//                    eliminated fracture-face groups.
 //
 // Storage of the local data (structure of arrays, coalesced by cell index):
 //   aK[36][nc]  packed upper triangle of the node block a_{s,s'}

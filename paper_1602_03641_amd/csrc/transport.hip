@@ -563,9 +563,13 @@ __device__ __forceinline__ double upwind_row(const UpwindOp &T, const double *__
 
 __global__ __launch_bounds__(256) void transport_step_kernel(UpwindOp T, const double *__restrict__ c_in,
                                                              double *__restrict__ c_out, double theta) {
-    const int32_t t = xcd_block() * blockDim.x + threadIdx.x;
-    const int32_t sl = t / kSliceRows, lane = t % kSliceRows;
-    if ((int64_t)sl * kSliceRows >= T.nrow) return;  // whole wavefronts
+    // block b runs on XCD b mod 8 (the hardware deals the blocks in turn);
+    // XCD x takes its run of slices [xlo[x], xlo[x+1]), 4 per block
+    const int x = blockIdx.x & 7;
+    const int32_t sl = T.xlo[x] + 4 * (int32_t)(blockIdx.x >> 3) + (int32_t)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kSliceRows - 1);
+    if (sl >= T.xlo[x + 1]) return;  // whole wavefronts
+    const int32_t t = sl * kSliceRows + lane;
     const uint16_t m = T.meta[t];
     const int32_t i = sl * kSliceRows + (m >> 8);
     const bool row = i < T.nrow;
@@ -578,6 +582,23 @@ __global__ __launch_bounds__(256) void transport_step_kernel(UpwindOp T, const d
     const double acc = cb >= 0 ? upwind_row<true>(T, c_in, cnt, width, level0, last, lane, cb, d)
                                : upwind_row<false>(T, c_in, cnt, width, level0, last, lane, cb, d);
     if (row) c_out[i] = (theta == 1.0) ? acc : ci + theta * (acc - ci);
+}
+
+// Cost of the slices before slice s: the bytes the sweep moves for them
+// (12 per entry, 32 per row); xlo[x] = the first slice whose cost reaches
+// x/8 of the total.
+__global__ __launch_bounds__(64) void xcd_split_kernel(int32_t nslice, const int64_t *__restrict__ slice_ptr,
+                                                       int32_t *__restrict__ xlo) {
+    const int x = threadIdx.x;
+    if (x > 8) return;
+    auto cost = [&](int32_t sl) { return 12 * slice_ptr[sl] + 32 * (int64_t)kSliceRows * sl; };
+    const int64_t want = cost(nslice) * x / 8;
+    int32_t lo = 0, hi = nslice;
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        if (cost(mid) < want) lo = mid + 1; else hi = mid;
+    }
+    xlo[x] = x == 8 ? nslice : lo;
 }
 
 // One explicit step without the upwind operator (the entry point for callers
@@ -884,9 +905,15 @@ void launch_upwind_pack(hipStream_t s, const UpwindOp &T, uint16_t *tcol16, int3
                        T.tcol, tcol16, tbase);
     VAG_HIP(hipGetLastError());
 }
+void launch_xcd_split(hipStream_t s, int32_t nslice, const int64_t *slice_ptr, int32_t *xlo) {
+    hipLaunchKernelGGL(xcd_split_kernel, dim3(1), dim3(64), 0, s, nslice, slice_ptr, xlo);
+    VAG_HIP(hipGetLastError());
+}
 void launch_transport_step(hipStream_t s, const UpwindOp &T, const double *c_in, double *c_out, double theta) {
-    const int64_t slots = (int64_t)((T.nrow + kSliceRows - 1) / kSliceRows) * kSliceRows;
-    hipLaunchKernelGGL(transport_step_kernel, dim3(nb(slots, 256)), dim3(256), 0, s, T, c_in, c_out, theta);
+    int32_t per_xcd = 0;  // blocks per XCD: the longest run, 4 slices per block
+    for (int x = 0; x < 8; ++x) per_xcd = std::max(per_xcd, (T.xlo[x + 1] - T.xlo[x] + 3) / 4);
+    if (per_xcd <= 0) return;
+    hipLaunchKernelGGL(transport_step_kernel, dim3(8 * (unsigned)per_xcd), dim3(256), 0, s, T, c_in, c_out, theta);
     VAG_HIP(hipGetLastError());
 }
 void launch_transport_gather(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,

@@ -169,9 +169,14 @@ struct vag_handle {
     DBuf<uint16_t> tcol16;
     DBuf<uint16_t> tmeta;
     DBuf<int64_t> slice_ptr;
+    DBuf<int32_t> xsplit;  // [9] the XCDs' runs of slices of the upwind operator
+    int32_t xlo[9] = {};   // host copy, passed to the sweep by value
     DBuf<double> tval, tdiag, cbuf0, cbuf1, dt4;
     DBuf<unsigned long long> cnt;
+    // pinned: [0] entry count of the upwind operator, from [2] the 9 ints of xsplit
+    static constexpr int kCntWords = 8;
     unsigned long long *h_cnt = nullptr;
+    int32_t *h_xsplit() { return reinterpret_cast<int32_t *>(h_cnt + 2); }
     int cur = 0;
     bool solved = false, have_flux = false, have_c = false;
     bool have_op = false;  // the upwind operator of the last vag_transport exists
@@ -229,7 +234,9 @@ struct vag_handle {
         return m;
     }
     UpwindOp upwind() const {
-        return UpwindOp{S.nc + S.nf + S.nn, slice_ptr.p, tmeta.p, tcol.p, tcol16.p, tbase.p, tval.p, tdiag.p};
+        UpwindOp T{S.nc + S.nf + S.nn, slice_ptr.p, tmeta.p, tcol.p, tcol16.p, tbase.p, tval.p, tdiag.p, {}};
+        for (int x = 0; x < 9; ++x) T.xlo[x] = xlo[x];
+        return T;
     }
     double *c_cur() { return cur ? cbuf1.p : cbuf0.p; }
     double *c_next() { return cur ? cbuf0.p : cbuf1.p; }
@@ -237,7 +244,7 @@ struct vag_handle {
     ~vag_handle() {
         pinned_put(h_pcg, sizeof(PcgState));
         pinned_put(h_scal, 16 * sizeof(double));
-        pinned_put(h_cnt, sizeof(unsigned long long));
+        pinned_put(h_cnt, kCntWords * sizeof(unsigned long long));
         pinned_put(h_gm, (3 * (size_t)(h_gm_m + 1) + 1) * sizeof(double));
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -890,6 +897,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         h->slice_nnz.alloc(nslice, h->tr);
         h->tmeta.alloc((size_t)nslice * kSliceRows, h->tr);
         h->slice_ptr.alloc(nslice + 1, h->tr);
+        h->xsplit.alloc(9, h->tr);
         h->tdiag.alloc(nrow, h->tr);
         // one more entry: the constant control volume (concentration 1) that
         // well injection terms of the upwind operator read
@@ -897,7 +905,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         h->cbuf1.alloc(nrow + 1, h->tr);
         h->dt4.alloc(4, h->tr);
         h->cnt.alloc(1, h->tr);
-        h->h_cnt = static_cast<unsigned long long *>(pinned_get(sizeof(unsigned long long)));
+        h->h_cnt = static_cast<unsigned long long *>(pinned_get(vag_handle::kCntWords * sizeof(unsigned long long)));
         h->h_pcg = static_cast<PcgState *>(pinned_get(sizeof(PcgState)));
         h->h_scal = static_cast<double *>(pinned_get(16 * sizeof(double)));
         for (auto &e : h->ev) VAG_HIP(hipEventCreate(&e));
@@ -1114,7 +1122,7 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
                          h->frac_cell.p, h->aK.p, h->rK.p, h->AKK.p, h->vol.p, h->fside.p, h->bad.p);
             launch_frac_local(s, S.nf, h->xyz.p, h->frac_nodes.p, h->fwidth.p, h->fperm.p, h->mu, h->A5.p,
                               h->area.p);
-            // 2. cell elimination, colour by colour
+            // 2. cell elimination: one thread per row gathers its cells' Schur blocks
             launch_fill(s, (int64_t)h->A.n, 0.0, h->A.p);  // padding stays 0
             launch_fill(s, S.nx, 0.0, h->b.p);
             if (S.ngroup) launch_fill(s, S.grp_off.back(), 0.0, h->Gb.p);
@@ -1255,11 +1263,14 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
                                 h->slice_nnz.p);
         }
         launch_slice_scan(s, nslice, h->slice_nnz.p, 1, h->slice_ptr.p, h->slice_nnz.p, h->cnt.p);
+        launch_xcd_split(s, nslice, h->slice_ptr.p, h->xsplit.p);
         int64_t total = 0;
         VAG_HIP(hipMemcpyAsync(&total, h->slice_ptr.p + nslice, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipMemcpyAsync(h->h_cnt, h->cnt.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipMemcpyAsync(h->h_xsplit(), h->xsplit.p, 9 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipMemcpyAsync(h->h_scal, h->dt4.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipStreamSynchronize(s));
+        for (int x = 0; x < 9; ++x) h->xlo[x] = h->h_xsplit()[x];
         const double dt = h->h_scal[3];
         double dtb[3] = {h->h_scal[0], h->h_scal[1], h->h_scal[2]};
         if (!(dt < INFINITY)) throw Error(VAG_ERR_ARG, "no control volume has an outflow: CFL bound is infinite");

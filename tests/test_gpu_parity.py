@@ -85,6 +85,11 @@ def compare(p, g, o, c_tol=1e-10, p_tol=1e-8, flux_tol=None):
     c_tol = c_tol * max(1.0, p_err / 1e-12)
     assert p_err <= p_tol
     assert rel_l2(g["u_cell"], d["u_cell"]) <= p_tol
+    # element by element as well: a rel-L2 bound alone lets one unknown of a
+    # large vector be off by sqrt(n) times the bound
+    pscale = np.abs(d["u_node"]).max()
+    for k in ("u_node", "u_cell") + (("u_frac",) if p.n_frac else ()):
+        assert np.abs(g[k] - d[k]).max() <= 10 * p_tol * pscale, k
     scale = max(np.abs(d["F_cell"]).max(), np.abs(d["F_frac"]).max() if p.n_frac else 0.0)
     assert flux_err(g["F_cell"], d["F_cell"], scale) <= flux_tol
     if p.n_frac:
@@ -233,7 +238,8 @@ def test_config2_full_size():
 
 
 def test_determinism_bitwise():
-    """Colour-ordered assembly and fixed-shape reductions: two runs agree bit for bit."""
+    """Row-gathered assembly (one thread per row, fixed order) and fixed-shape
+    reductions: two runs agree bit for bit."""
     p = synth.random_problem((8, 6, 7), 9, n_patches=5, n_steps=20)
     a = gpu_run(p, rtol=1e-13)
     b = gpu_run(p, rtol=1e-13)
@@ -788,6 +794,34 @@ def test_hierarchy_is_galerkin(kind):
     for a, b in zip(lv[:-1], lv[1:]):
         G = (a["Pm"].T @ a["Am"] @ a["Pm"]).tocsr()
         assert abs(G - b["Am"]).max() <= 1e-12 * abs(G).max()
+        if kind == 0:
+            _check_aggregates(a["Am"], a["Pm"], theta=0.02)
+
+
+def _check_aggregates(A, P, theta):
+    """Validity of one aggregation level (many aggregations are correct, so
+    the test checks the defining properties, not one particular answer): P
+    is piecewise constant (exactly one entry, 1, per row), no aggregate is
+    empty, and each aggregate is connected in the strength graph (i -> j
+    when |a_ij| >= theta sqrt(|a_ii a_jj|), the rule the members join by)."""
+    import scipy.sparse as sp
+    from scipy.sparse import csgraph
+    P = P.tocsr()
+    assert np.array_equal(np.diff(P.indptr), np.ones(P.shape[0], np.int64))
+    assert np.all(P.data == 1.0)
+    agg = P.indices
+    size = np.bincount(agg, minlength=P.shape[1])
+    assert size.min() >= 1
+    C = A.tocoo()
+    d = A.diagonal()
+    off = C.row != C.col
+    r, c, v = C.row[off], C.col[off], C.data[off]
+    keep = (np.abs(v) >= theta * np.sqrt(np.abs(d[r] * d[c]))) & (agg[r] == agg[c]) & (v != 0)
+    S = sp.csr_matrix((np.ones(int(keep.sum())), (r[keep], c[keep])), shape=A.shape)
+    ncomp, lab = csgraph.connected_components(S, directed=True, connection="weak")
+    assert ncomp == P.shape[1], (ncomp, P.shape[1])
+    # edges join members of one aggregate only, so each component lies in one
+    # aggregate, and as many components as aggregates means each is one piece
 
 
 def test_classical_interpolation_matches_oracle():
