@@ -188,6 +188,14 @@ typedef struct {
     int stream_loads;       /* row loops of the system matrix and the FP32 hierarchy read the
                                matrix entries with non-temporal loads: 0 for matrices above
                                128 MB (default), 1 always, 2 never; results are the same */
+    int alpha_rule;         /* volume fractions of the node control volumes (§3.2.1):
+                               0 (default): every adjacent cell gives a matrix node
+                               alpha_K,s = 1/(2|V_K|) of its pore volume and every adjacent
+                               fracture face gives a fracture node alpha_sigma,s = 1/(2|V_sigma|);
+                               1: the rule for nodes between rock types, only the adjacent
+                               cells (fracture faces) of largest permeability around the node
+                               give their share, the others none (a cell's permeability: the
+                               trace of its tensor over 3; ties all give) */
 } vag_options;
 
 typedef struct {

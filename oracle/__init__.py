@@ -65,7 +65,7 @@ def _lib_handle():
         lib.orc_solve_darcy.restype = C.c_int
         lib.orc_residual.argtypes = [P, vp, vp, vp, vp, vp, vp]
         lib.orc_residual.restype = C.c_int
-        lib.orc_porous_volumes.argtypes = [P, vp, vp, vp]
+        lib.orc_porous_volumes.argtypes = [P, C.c_int, vp, vp, vp]
         lib.orc_porous_volumes.restype = C.c_int
         lib.orc_well_rates.argtypes = [P, vp, vp]
         lib.orc_well_rates.restype = C.c_int
@@ -211,10 +211,12 @@ def residual(prob, u_node, u_frac):
     return out
 
 
-def porous_volumes(prob):
+def porous_volumes(prob, alpha_rule=0):
+    """Porous volumes of §3.2.1; alpha_rule 1: only the largest-permeability
+    cells (fracture faces) around a node give it a share."""
     op = _as(prob)
     out = dict(phi_cell=np.zeros(op.nc), phi_frac=np.zeros(op.nf), phi_node=np.zeros(op.nn))
-    st = _lib_handle().orc_porous_volumes(op.ref, _ptr(out["phi_cell"]), _ptr(out["phi_frac"]),
+    st = _lib_handle().orc_porous_volumes(op.ref, int(alpha_rule), _ptr(out["phi_cell"]), _ptr(out["phi_frac"]),
                                           _ptr(out["phi_node"]))
     if st:
         raise ValueError(f"oracle porous volume error {st}")
@@ -274,7 +276,7 @@ def time_grid(dt, t_final):
     return N, t_final - (N - 1) * dt
 
 
-def run(prob, rtol=None, max_iter=200000, n_steps=None, cfl=None, t_final=None):
+def run(prob, rtol=None, max_iter=200000, n_steps=None, cfl=None, t_final=None, alpha_rule=0):
     """Darcy solve, porous volumes, CFL time step, then the transport steps."""
     op = _as(prob)
     p = op.prob
@@ -283,7 +285,7 @@ def run(prob, rtol=None, max_iter=200000, n_steps=None, cfl=None, t_final=None):
     t_final = p.t_final if t_final is None else t_final
     n_steps = p.n_steps if n_steps is None else n_steps
     darcy = solve_darcy(op, rtol, max_iter)
-    phi = porous_volumes(op)
+    phi = porous_volumes(op, alpha_rule)
     dt3 = cfl_bounds(op, darcy, phi)
     dt = cfl * float(np.min(dt3))
     last = 0.0

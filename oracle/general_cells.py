@@ -262,12 +262,25 @@ def solve_darcy(m):
                 cell_frac=d["cell_frac"], frac_cells=d["frac_cells"], local=d["local"], fmat=d["fmat"])
 
 
-def porous_volumes(m, sol):
-    """phi_K, phi_sigma, phi_s (0 at Dirichlet nodes)."""
+def porous_volumes(m, sol, alpha_rule=0):
+    """phi_K, phi_sigma, phi_s (0 at Dirichlet nodes), §3.2.1 with
+    alpha_{K,s} = 1/(2|V_K|), alpha_{sigma,s} = 1/(2|V_sigma|).  alpha_rule 1:
+    a node takes a share only from the adjacent cells (fracture faces at a
+    fracture node) of largest permeability, a cell's permeability being the
+    trace of its tensor over 3."""
     nn = len(m.xyz)
     frac_node = np.zeros(nn, bool)
     for f in m.frac:
         frac_node[list(f)] = True
+    kcell = [(L[0] + L[1] + L[2]) / 3.0 for L in m.perm]
+    pmax = np.full(nn, -1.0)
+    for K, c in enumerate(m.cells):
+        for s in c:
+            if not frac_node[s]:
+                pmax[s] = max(pmax[s], kcell[K])
+    for f, nodes in enumerate(m.frac):
+        for s in nodes:
+            pmax[s] = max(pmax[s], m.frac_perm[f])
     phi_node = np.zeros(nn)
     phi_cell = np.zeros(len(m.cells))
     for K, c in enumerate(m.cells):
@@ -276,6 +289,8 @@ def porous_volumes(m, sol):
         taken = 0.0
         for s in c:
             if m.dirichlet[s] or frac_node[s]:
+                continue
+            if alpha_rule == 1 and kcell[K] < pmax[s]:
                 continue
             taken += alpha
             phi_node[s] += alpha * pore
@@ -287,6 +302,8 @@ def porous_volumes(m, sol):
         taken = 0.0
         for s in nodes:
             if m.dirichlet[s]:
+                continue
+            if alpha_rule == 1 and m.frac_perm[f] < pmax[s]:
                 continue
             taken += alpha
             phi_node[s] += alpha * pore

@@ -753,26 +753,55 @@ int orc_well_rates(const orc_problem *P, const double *u_frac, double *Q) {
  * Porous volumes of the control volumes (§3.2.1).  Control volumes are the
  * cells, the fracture faces and the nodes without a Dirichlet flag; Dirichlet
  * nodes get 0.  Fracture nodes (nodes of a fracture face) take volume from the
- * fracture faces only; other nodes from the cells.
+ * fracture faces only; other nodes from the cells.  alpha_K,s = 1/16 and
+ * alpha_sigma,s = 1/8 where a share is taken.
+ *
+ * alpha_rule 0: every adjacent cell (fracture face) gives its share.
+ * alpha_rule 1: the rule of §3.2.1 for nodes between rock types: only the
+ * adjacent cells (fracture faces) of largest permeability give a share, the
+ * others none.  A cell's permeability is measured by the trace of its tensor
+ * over 3, a fracture face's by its scalar permeability; all cells (faces)
+ * that reach the largest value give their share.
  */
-int orc_porous_volumes(const orc_problem *P, double *phi_cell, double *phi_frac, double *phi_node) {
+static double perm_measure(const double *L) { return (L[0] + L[1] + L[2]) / 3.0; }
+
+int orc_porous_volumes(const orc_problem *P, int alpha_rule, double *phi_cell, double *phi_frac,
+                       double *phi_node) {
     int64_t nn = P->n_nodes, nc = P->n_cells, nf = P->n_frac;
     const double alpha_cell = 1.0 / 16.0, alpha_frac = 1.0 / 8.0;
     uint8_t *is_frac_node = (uint8_t *)calloc((size_t)nn, 1);
     for (int64_t f = 0; f < nf; ++f)
         for (int i = 0; i < 4; ++i) is_frac_node[P->frac_nodes[4 * f + i]] = 1;
+    /* largest permeability around each node: over the fracture faces at a
+       fracture node, over the cells elsewhere */
+    double *pmax = (double *)malloc(sizeof(double) * (size_t)(nn > 0 ? nn : 1));
+    for (int64_t s = 0; s < nn; ++s) pmax[s] = -1.0;
+    for (int64_t K = 0; K < nc; ++K) {
+        double m = perm_measure(P->perm + 6 * K);
+        for (int i = 0; i < 8; ++i) {
+            int32_t s = P->hex8[8 * K + i];
+            if (!is_frac_node[s] && m > pmax[s]) pmax[s] = m;
+        }
+    }
+    for (int64_t f = 0; f < nf; ++f)
+        for (int i = 0; i < 4; ++i) {
+            int32_t s = P->frac_nodes[4 * f + i];
+            if (P->frac_perm[f] > pmax[s]) pmax[s] = P->frac_perm[f];
+        }
     for (int64_t s = 0; s < nn; ++s) phi_node[s] = 0.0;
     int32_t z6[6] = {-1, -1, -1, -1, -1, -1};
     for (int64_t K = 0; K < nc; ++K) {
         double a[14 * 14];
         int m;
         double vol = orc_cell_matrix(P, K, z6, a, &m, NULL);
-        if (vol < 0) { free(is_frac_node); return -3; }
+        if (vol < 0) { free(is_frac_node); free(pmax); return -3; }
         double pore = vol * P->poro[K];
+        double perm = perm_measure(P->perm + 6 * K);
         double sum_alpha = 0;
         for (int i = 0; i < 8; ++i) {
             int32_t s = P->hex8[8 * K + i];
             if (P->dirichlet[s] || is_frac_node[s]) continue;
+            if (alpha_rule == 1 && perm < pmax[s]) continue;
             sum_alpha += alpha_cell;
             phi_node[s] += alpha_cell * pore;
         }
@@ -786,12 +815,14 @@ int orc_porous_volumes(const orc_problem *P, double *phi_cell, double *phi_frac,
         for (int i = 0; i < 4; ++i) {
             int32_t s = P->frac_nodes[4 * f + i];
             if (P->dirichlet[s]) continue;
+            if (alpha_rule == 1 && P->frac_perm[f] < pmax[s]) continue;
             sum_alpha += alpha_frac;
             phi_node[s] += alpha_frac * pore;
         }
         phi_frac[f] = (1.0 - sum_alpha) * pore;
     }
     free(is_frac_node);
+    free(pmax);
     return 0;
 }
 

@@ -43,7 +43,8 @@ int orc_solve_darcy(const orc_problem *P, double rtol, int max_iter, double *u_n
                     int *iters, double *relres);
 int orc_residual(const orc_problem *P, const double *u_node, const double *u_frac, double *res_node,
                  double *res_frac, double *b_node, double *b_frac);
-int orc_porous_volumes(const orc_problem *P, double *phi_cell, double *phi_frac, double *phi_node);
+int orc_porous_volumes(const orc_problem *P, int alpha_rule, double *phi_cell, double *phi_frac,
+                       double *phi_node);
 int orc_well_rates(const orc_problem *P, const double *u_frac, double *Q);
 int orc_cfl(const orc_problem *P, const double *F_cell, const double *F_cell_frac,
             const double *F_frac, const double *well_rate, const double *phi_cell,

@@ -282,11 +282,14 @@ __global__ __launch_bounds__(256) void gen_frac_flux_kernel(GenMesh g, const dou
     }
 }
 
+// With pmax, a cell (fracture face) gives a node its share only if its
+// permeability reaches pmax[node] (§3.2.1, nodes between rock types).
 __global__ __launch_bounds__(256) void gen_porous_kernel(
     GenMesh g, const uint8_t *__restrict__ dirichlet, const uint8_t *__restrict__ frac_node,
     const int64_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc_other, const double *__restrict__ vol,
     const double *__restrict__ poro, const double *__restrict__ area, const double *__restrict__ fwidth,
-    const double *__restrict__ fporo, double *__restrict__ phi_cell, double *__restrict__ phi_frac,
+    const double *__restrict__ fporo, const double *__restrict__ perm, const double *__restrict__ fperm,
+    const double *__restrict__ pmax, double *__restrict__ phi_cell, double *__restrict__ phi_frac,
     double *__restrict__ phi_node) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t off_f = g.nc, off_n = (int64_t)g.nc + g.nf;
@@ -294,18 +297,21 @@ __global__ __launch_bounds__(256) void gen_porous_kernel(
     if (i < off_f) {
         const int32_t K = (int32_t)i, p0 = g.cnode_ptr[K], nv = g.cnode_ptr[K + 1] - p0;
         const double alpha = 0.5 / nv;
+        const double mK = pmax ? perm_measure(perm, K) : 0.0;
         double sa = 0.0;
         for (int a = 0; a < nv; ++a) {
             const int32_t s = g.cnode[p0 + a];
-            if (!dirichlet[s] && !frac_node[s]) sa += alpha;
+            if (!dirichlet[s] && !frac_node[s] && (!pmax || mK >= pmax[s])) sa += alpha;
         }
         phi_cell[K] = (1.0 - sa) * (vol[K] * poro[K]);
     } else if (i < off_n) {
         const int32_t f = (int32_t)(i - off_f), p0 = g.fnode_ptr[f], k = g.fnode_ptr[f + 1] - p0;
         const double alpha = 0.5 / k;
         double sa = 0.0;
-        for (int a = 0; a < k; ++a)
-            if (!dirichlet[g.fnode[p0 + a]]) sa += alpha;
+        for (int a = 0; a < k; ++a) {
+            const int32_t s = g.fnode[p0 + a];
+            if (!dirichlet[s] && (!pmax || fperm[f] >= pmax[s])) sa += alpha;
+        }
         phi_frac[f] = (1.0 - sa) * (fwidth[f] * area[f] * fporo[f]);
     } else {
         // a node takes 1/(2 |V|) of each adjacent control volume it draws
@@ -317,10 +323,12 @@ __global__ __launch_bounds__(256) void gen_porous_kernel(
             for (int64_t q = inc_ptr[i]; q < inc_ptr[i + 1]; ++q) {
                 const int32_t o = inc_other[q];
                 if (o < off_f && !fn) {
+                    if (pmax && perm_measure(perm, o) < pmax[s]) continue;
                     const int nv = g.cnode_ptr[o + 1] - g.cnode_ptr[o];
                     p += (0.5 / nv) * (vol[o] * poro[o]);
                 } else if (o >= off_f && o < off_n && fn) {
                     const int32_t f = o - (int32_t)off_f;
+                    if (pmax && fperm[f] < pmax[s]) continue;
                     const int k = g.fnode_ptr[f + 1] - g.fnode_ptr[f];
                     p += (0.5 / k) * (fwidth[f] * area[f] * fporo[f]);
                 }
@@ -328,6 +336,26 @@ __global__ __launch_bounds__(256) void gen_porous_kernel(
         }
         phi_node[s] = p;
     }
+}
+
+// the largest permeability around each node, from its incidence list
+__global__ __launch_bounds__(256) void gen_node_pmax_kernel(GenMesh g, const uint8_t *__restrict__ frac_node,
+                                                            const int64_t *__restrict__ inc_ptr,
+                                                            const int32_t *__restrict__ inc_other,
+                                                            const double *__restrict__ perm,
+                                                            const double *__restrict__ fperm,
+                                                            double *__restrict__ pmax) {
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.nn) return;
+    const int64_t off_f = g.nc, off_n = (int64_t)g.nc + g.nf, i = off_n + s;
+    const bool fn = frac_node[s] != 0;
+    double m = -1.0;
+    for (int64_t q = inc_ptr[i]; q < inc_ptr[i + 1]; ++q) {
+        const int32_t o = inc_other[q];
+        if (o < off_f && !fn) m = fmax(m, perm_measure(perm, o));
+        else if (o >= off_f && o < off_n && fn) m = fmax(m, fperm[o - off_f]);
+    }
+    pmax[s] = m;
 }
 
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -370,11 +398,19 @@ void launch_gen_flux(hipStream_t s, const GenMesh &g, const double *loc, const d
 }
 void launch_gen_porous(hipStream_t s, const GenMesh &g, const uint8_t *dirichlet, const uint8_t *frac_node,
                        const int64_t *inc_ptr, const int32_t *inc_other, const double *vol, const double *poro,
-                       const double *area, const double *fwidth, const double *fporo, double *phi_cell,
-                       double *phi_frac, double *phi_node) {
+                       const double *area, const double *fwidth, const double *fporo, const double *perm,
+                       const double *fperm, const double *pmax, double *phi_cell, double *phi_frac,
+                       double *phi_node) {
     const int64_t total = (int64_t)g.nc + g.nf + g.nn;
     hipLaunchKernelGGL(gen_porous_kernel, dim3(nblk(total, 256)), dim3(256), 0, s, g, dirichlet, frac_node, inc_ptr,
-                       inc_other, vol, poro, area, fwidth, fporo, phi_cell, phi_frac, phi_node);
+                       inc_other, vol, poro, area, fwidth, fporo, perm, fperm, pmax, phi_cell, phi_frac, phi_node);
+    VAG_HIP(hipGetLastError());
+}
+void launch_gen_node_pmax(hipStream_t s, const GenMesh &g, const uint8_t *frac_node, const int64_t *inc_ptr,
+                          const int32_t *inc_other, const double *perm, const double *fperm, double *pmax) {
+    if (g.nn <= 0) return;
+    hipLaunchKernelGGL(gen_node_pmax_kernel, dim3(nblk(g.nn, 256)), dim3(256), 0, s, g, frac_node, inc_ptr,
+                       inc_other, perm, fperm, pmax);
     VAG_HIP(hipGetLastError());
 }
 

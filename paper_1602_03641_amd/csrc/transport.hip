@@ -110,30 +110,36 @@ __global__ __launch_bounds__(kT) void frac_flux_kernel(int32_t nf, const int32_t
 
 // Porous volumes with alpha_{K,s} = 1/16 and alpha_{sigma,s} = 1/8: matrix
 // nodes take 1/16 of each adjacent cell, fracture nodes 1/8 of each adjacent
-// fracture face, Dirichlet nodes nothing.
+// fracture face, Dirichlet nodes nothing.  With pmax, a cell (fracture face)
+// gives a node its share only if its permeability reaches pmax[node] (§3.2.1,
+// nodes between rock types).
 __global__ __launch_bounds__(kT) void porous_kernel(
     int32_t nc, int32_t nf, int32_t nn, const int32_t *__restrict__ hex8, const int32_t *__restrict__ frac_nodes,
     const uint8_t *__restrict__ dirichlet, const uint8_t *__restrict__ frac_node,
     const int32_t *__restrict__ ncp, const int32_t *__restrict__ ncl, const int32_t *__restrict__ nfp,
     const int32_t *__restrict__ nfl, const double *__restrict__ vol, const double *__restrict__ poro,
     const double *__restrict__ area, const double *__restrict__ fwidth, const double *__restrict__ fporo,
+    const double *__restrict__ perm, const double *__restrict__ fperm, const double *__restrict__ pmax,
     double *__restrict__ phi_cell, double *__restrict__ phi_frac, double *__restrict__ phi_node) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nc) {
         const int32_t K = (int32_t)i;
+        const double mK = pmax ? perm_measure(perm, K) : 0.0;
         double sa = 0.0;
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
             const int32_t s = hex8[8 * (int64_t)K + a];
-            if (!dirichlet[s] && !frac_node[s]) sa += 1.0 / 16.0;
+            if (!dirichlet[s] && !frac_node[s] && (!pmax || mK >= pmax[s])) sa += 1.0 / 16.0;
         }
         phi_cell[K] = (1.0 - sa) * (vol[K] * poro[K]);
     } else if (i < (int64_t)nc + nf) {
         const int32_t f = (int32_t)(i - nc);
         double sa = 0.0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (!dirichlet[frac_nodes[4 * (int64_t)f + k]]) sa += 1.0 / 8.0;
+        for (int k = 0; k < 4; ++k) {
+            const int32_t s = frac_nodes[4 * (int64_t)f + k];
+            if (!dirichlet[s] && (!pmax || fperm[f] >= pmax[s])) sa += 1.0 / 8.0;
+        }
         phi_frac[f] = (1.0 - sa) * (fwidth[f] * area[f] * fporo[f]);
     } else if (i < (int64_t)nc + nf + nn) {
         const int32_t s = (int32_t)(i - nc - nf);
@@ -142,17 +148,32 @@ __global__ __launch_bounds__(kT) void porous_kernel(
             if (frac_node[s]) {
                 for (int32_t q = nfp[s]; q < nfp[s + 1]; ++q) {
                     const int32_t f = nfl[q] >> 2;
-                    p += (1.0 / 8.0) * (fwidth[f] * area[f] * fporo[f]);
+                    if (!pmax || fperm[f] >= pmax[s]) p += (1.0 / 8.0) * (fwidth[f] * area[f] * fporo[f]);
                 }
             } else {
                 for (int32_t q = ncp[s]; q < ncp[s + 1]; ++q) {
                     const int32_t K = ncl[q] >> 3;
-                    p += (1.0 / 16.0) * (vol[K] * poro[K]);
+                    if (!pmax || perm_measure(perm, K) >= pmax[s]) p += (1.0 / 16.0) * (vol[K] * poro[K]);
                 }
             }
         }
         phi_node[s] = p;
     }
+}
+
+__global__ __launch_bounds__(kT) void node_pmax_kernel(int32_t nn, const uint8_t *__restrict__ frac_node,
+                                                       const int32_t *__restrict__ ncp, const int32_t *__restrict__ ncl,
+                                                       const int32_t *__restrict__ nfp, const int32_t *__restrict__ nfl,
+                                                       const double *__restrict__ perm,
+                                                       const double *__restrict__ fperm, double *__restrict__ pmax) {
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nn) return;
+    double m = -1.0;
+    if (frac_node[s])
+        for (int32_t q = nfp[s]; q < nfp[s + 1]; ++q) m = fmax(m, fperm[nfl[q] >> 2]);
+    else
+        for (int32_t q = ncp[s]; q < ncp[s + 1]; ++q) m = fmax(m, perm_measure(perm, ncl[q] >> 3));
+    pmax[s] = m;
 }
 
 // Sum of outgoing fluxes of a control volume (denominators of eq eq_CFL).
@@ -843,12 +864,20 @@ void launch_porous(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int3
                    const int32_t *frac_nodes, const uint8_t *dirichlet, const uint8_t *frac_node,
                    const int32_t *node_cell_ptr, const int32_t *node_cell, const int32_t *node_frac_ptr,
                    const int32_t *node_frac, const double *vol, const double *poro, const double *area,
-                   const double *fwidth, const double *fporo, double *phi_cell, double *phi_frac,
-                   double *phi_node) {
+                   const double *fwidth, const double *fporo, const double *perm, const double *fperm,
+                   const double *pmax, double *phi_cell, double *phi_frac, double *phi_node) {
     const int64_t total = (int64_t)nc + nf + nn;
     hipLaunchKernelGGL(porous_kernel, dim3(nb(total, kT)), dim3(kT), 0, s, nc, nf, nn, hex8, frac_nodes, dirichlet,
                        frac_node, node_cell_ptr, node_cell, node_frac_ptr, node_frac, vol, poro, area, fwidth,
-                       fporo, phi_cell, phi_frac, phi_node);
+                       fporo, perm, fperm, pmax, phi_cell, phi_frac, phi_node);
+    VAG_HIP(hipGetLastError());
+}
+void launch_node_pmax(hipStream_t s, int32_t nn, const uint8_t *frac_node, const int32_t *node_cell_ptr,
+                      const int32_t *node_cell, const int32_t *node_frac_ptr, const int32_t *node_frac,
+                      const double *perm, const double *fperm, double *pmax) {
+    if (nn <= 0) return;
+    hipLaunchKernelGGL(node_pmax_kernel, dim3(nb(nn, kT)), dim3(kT), 0, s, nn, frac_node, node_cell_ptr, node_cell,
+                       node_frac_ptr, node_frac, perm, fperm, pmax);
     VAG_HIP(hipGetLastError());
 }
 void launch_cfl(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8, const uint8_t *fmask,

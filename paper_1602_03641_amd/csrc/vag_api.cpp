@@ -170,6 +170,7 @@ struct vag_handle {
     DBuf<uint16_t> tmeta;
     DBuf<int64_t> slice_ptr;
     DBuf<int32_t> xsplit;  // [9] the XCDs' runs of slices of the upwind operator
+    DBuf<double> pmax;     // [nn] largest permeability around each node (alpha_rule 1)
     int32_t xlo[9] = {};   // host copy, passed to the sweep by value
     DBuf<double> tval, tdiag, cbuf0, cbuf1, dt4;
     DBuf<unsigned long long> cnt;
@@ -335,6 +336,8 @@ void check_options(const vag_options &o) {
         throw Error(VAG_ERR_ARG, "unknown Krylov method");
     if (o.stream_loads < 0 || o.stream_loads > 2)
         throw Error(VAG_ERR_ARG, "stream_loads must be 0 (automatic), 1 (always) or 2 (never)");
+    if (o.alpha_rule < 0 || o.alpha_rule > 1)
+        throw Error(VAG_ERR_ARG, "alpha_rule must be 0 (every adjacent cell or face) or 1 (largest permeability)");
     if (o.krylov == VAG_BICGSTAB && o.precision == VAG_MIXED_IR)
         throw Error(VAG_ERR_UNSUPPORTED, "BiCGStab runs in FP64 (with the FP64 or FP32 hierarchy), not as an inner solver");
     if (o.krylov == VAG_GMRES && (o.gmres_restart < 1 || o.gmres_restart > 1024))
@@ -697,6 +700,32 @@ void run_mixed(vag_handle *h) {
     h->last_inner = inner_total;
     h->last_outer = outer;
 }
+
+// Porous volumes of the control volumes (§3.2.1) on the handle's stream;
+// with alpha_rule 1 the largest permeability around each node first.
+void porous_volumes(vag_handle *h, hipStream_t s) {
+    const Symbolic &S = h->S;
+    const double *pmax = nullptr;
+    if (h->opt.alpha_rule == 1) {
+        ensure(h->pmax, (size_t)std::max(S.nn, 1), h->tr);
+        if (h->general)
+            launch_gen_node_pmax(s, h->gmesh(), h->frac_node.p, h->g_inc_ptr.p, h->g_inc_other.p, h->perm.p,
+                                 h->fperm.p, h->pmax.p);
+        else
+            launch_node_pmax(s, S.nn, h->frac_node.p, h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p,
+                             h->node_frac.p, h->perm.p, h->fperm.p, h->pmax.p);
+        pmax = h->pmax.p;
+    }
+    if (h->general)
+        launch_gen_porous(s, h->gmesh(), h->dirichlet.p, h->frac_node.p, h->g_inc_ptr.p, h->g_inc_other.p, h->vol.p,
+                          h->poro.p, h->area.p, h->fwidth.p, h->fporo.p, h->perm.p, h->fperm.p, pmax, h->phi_cell.p,
+                          h->phi_frac.p, h->phi_node.p);
+    else
+        launch_porous(s, S.nc, S.nf, S.nn, h->hex8.p, h->frac_nodes.p, h->dirichlet.p, h->frac_node.p,
+                      h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->vol.p, h->poro.p,
+                      h->area.p, h->fwidth.p, h->fporo.p, h->perm.p, h->fperm.p, pmax, h->phi_cell.p, h->phi_frac.p,
+                      h->phi_node.p);
+}
 }  // namespace
 
 extern "C" {
@@ -974,18 +1003,13 @@ vag_status vag_set_fluxes(vag_handle *h, const double *F_cell, const double *F_c
             launch_gen_local(s, g, h->xyz.p, h->perm.p, 1.0 / h->mu, h->gloc.p, h->ga.p, h->gr.p, h->AKK.p,
                              h->vol.p, h->bad.p);
             launch_gen_frac_local(s, g, h->xyz.p, h->fwidth.p, h->fperm.p, 1.0 / h->mu, h->gloc.p, h->area.p);
-            launch_gen_porous(s, g, h->dirichlet.p, h->frac_node.p, h->g_inc_ptr.p, h->g_inc_other.p, h->vol.p,
-                              h->poro.p, h->area.p, h->fwidth.p, h->fporo.p, h->phi_cell.p, h->phi_frac.p,
-                              h->phi_node.p);
+            porous_volumes(h, s);
         } else {
             launch_local(s, S.nc, h->xyz.p, h->hex8.p, h->perm.p, h->mu, h->fmask.p, h->cell_frac.p,
                          h->frac_cell.p, h->aK.p, h->rK.p, h->AKK.p, h->vol.p, h->fside.p, h->bad.p);
             launch_frac_local(s, S.nf, h->xyz.p, h->frac_nodes.p, h->fwidth.p, h->fperm.p, h->mu, h->A5.p,
                               h->area.p);
-            launch_porous(s, S.nc, S.nf, S.nn, h->hex8.p, h->frac_nodes.p, h->dirichlet.p, h->frac_node.p,
-                          h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->vol.p,
-                          h->poro.p, h->area.p, h->fwidth.p, h->fporo.p, h->phi_cell.p, h->phi_frac.p,
-                          h->phi_node.p);
+            porous_volumes(h, s);
         }
         if (h->nw) {  // given fluxes come without well rates until vag_set_well_rates
             launch_fill(s, h->nw, 0.0, h->wrate.p);
@@ -1179,19 +1203,14 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
             launch_fill(s, 2 * (int64_t)S.nf, 0.0, h->flux_cell_frac());  // a missing second cell keeps 0
             launch_gen_flux(s, g, h->gloc.p, h->ga.p, h->gr.p, h->AKK.p, h->u_node.p, h->u_frac.p, h->u_cell.p,
                             h->Fall.p);
-            launch_gen_porous(s, g, h->dirichlet.p, h->frac_node.p, h->g_inc_ptr.p, h->g_inc_other.p, h->vol.p,
-                              h->poro.p, h->area.p, h->fwidth.p, h->fporo.p, h->phi_cell.p, h->phi_frac.p,
-                              h->phi_node.p);
+            porous_volumes(h, s);
         } else {
             launch_fill(s, 2 * (int64_t)std::max(S.nf, 1), 0.0, h->F_cell_frac.p);
             launch_cell_flux(s, S.nc, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->aK.p, h->rK.p,
                              h->AKK.p, h->fside.p, h->u_node.p, h->u_frac.p, h->u_cell.p, h->F_cell.p,
                              h->F_cell_frac.p);
             launch_frac_flux(s, S.nf, h->frac_nodes.p, h->A5.p, h->u_node.p, h->u_frac.p, h->F_frac.p);
-            launch_porous(s, S.nc, S.nf, S.nn, h->hex8.p, h->frac_nodes.p, h->dirichlet.p, h->frac_node.p,
-                          h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->vol.p,
-                          h->poro.p, h->area.p, h->fwidth.p, h->fporo.p, h->phi_cell.p, h->phi_frac.p,
-                          h->phi_node.p);
+            porous_volumes(h, s);
         }
         VAG_HIP(hipEventRecord(h->ev[4], s));
         // true residual ||b - A x|| / ||b||
@@ -1756,6 +1775,7 @@ size_t vag_estimate_footprint(int64_t nn, int64_t nc, int64_t nf, const vag_opti
     b += 376 * Nc + 304 * Nf + 8 * S + 16 * Nx;                     // local matrices, system
     b += 40 * Nx + 64.0 * 1024;                                     // Krylov vectors and partials
     b += 88 * Nc + 56 * Nf + 16 * Nn;                               // pressures, fluxes, porous volumes
+    if (o.alpha_rule == 1) b += 8 * Nn;                             // largest permeability per node
     const double nrow = Nn + Nc + Nf, tst = 2.0 * (8 * Nc + 6 * Nf) + 64.0 * 16;
     b += 24 * nrow + 12 * tst + 12 * nrow / 64;                     // transport
     if (o.precond == VAG_PC_AMG) {

@@ -362,12 +362,24 @@ void launch_cell_flux(hipStream_t s, int32_t nc, const int32_t *hex8, const uint
                       const double *u_frac, double *u_cell, double *F_cell, double *F_cell_frac);
 void launch_frac_flux(hipStream_t s, int32_t nf, const int32_t *frac_nodes, const double *A5,
                       const double *u_node, const double *u_frac, double *F_frac);
+// Porous volumes (§3.2.1).  pmax == nullptr: every adjacent cell (fracture
+// face) gives a node its share; else only those whose permeability reaches
+// pmax[node] (launch_node_pmax), the rule for nodes between rock types.
 void launch_porous(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,
                    const int32_t *frac_nodes, const uint8_t *dirichlet, const uint8_t *frac_node,
                    const int32_t *node_cell_ptr, const int32_t *node_cell, const int32_t *node_frac_ptr,
                    const int32_t *node_frac, const double *vol, const double *poro, const double *area,
-                   const double *fwidth, const double *fporo, double *phi_cell, double *phi_frac,
-                   double *phi_node);
+                   const double *fwidth, const double *fporo, const double *perm, const double *fperm,
+                   const double *pmax, double *phi_cell, double *phi_frac, double *phi_node);
+// pmax[s]: the largest permeability around node s, over the fracture faces at
+// a fracture node, over the cells elsewhere (a cell's permeability: the trace
+// of its tensor over 3)
+void launch_node_pmax(hipStream_t s, int32_t nn, const uint8_t *frac_node, const int32_t *node_cell_ptr,
+                      const int32_t *node_cell, const int32_t *node_frac_ptr, const int32_t *node_frac,
+                      const double *perm, const double *fperm, double *pmax);
+__device__ __forceinline__ double perm_measure(const double *perm, int64_t K) {
+    return (perm[6 * K] + perm[6 * K + 1] + perm[6 * K + 2]) / 3.0;
+}
 void launch_cfl(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,
                 const uint8_t *fmask, const int32_t *cell_frac, const int32_t *frac_cell,
                 const uint8_t *dirichlet, const int32_t *node_cell_ptr, const int32_t *node_cell,
@@ -470,8 +482,11 @@ void launch_gen_flux(hipStream_t s, const GenMesh &g, const double *loc, const d
                      const double *AKK, const double *u_node, const double *u_frac, double *u_cell, double *F);
 void launch_gen_porous(hipStream_t s, const GenMesh &g, const uint8_t *dirichlet, const uint8_t *frac_node,
                        const int64_t *inc_ptr, const int32_t *inc_other, const double *vol, const double *poro,
-                       const double *area, const double *fwidth, const double *fporo, double *phi_cell,
-                       double *phi_frac, double *phi_node);
+                       const double *area, const double *fwidth, const double *fporo, const double *perm,
+                       const double *fperm, const double *pmax, double *phi_cell, double *phi_frac,
+                       double *phi_node);
+void launch_gen_node_pmax(hipStream_t s, const GenMesh &g, const uint8_t *frac_node, const int64_t *inc_ptr,
+                          const int32_t *inc_other, const double *perm, const double *fperm, double *pmax);
 // transport on the incidence lists (every control volume alike)
 struct GenInc {
     int32_t nc, nf, nn;

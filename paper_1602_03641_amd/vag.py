@@ -60,7 +60,8 @@ class vag_options(C.Structure):
                 ("amg_max_levels", C.c_int), ("amg_theta", C.c_double), ("amg_sweeps", C.c_int),
                 ("eliminate_frac_faces", C.c_int), ("amg_aggregate_hops", C.c_int), ("amg_kcycle", C.c_int),
                 ("ilu_block_rows", C.c_int), ("amg_kind", C.c_int),
-                ("amg_strong_theta", C.c_double), ("stream_loads", C.c_int)]
+                ("amg_strong_theta", C.c_double), ("stream_loads", C.c_int),
+                ("alpha_rule", C.c_int)]
 
 
 class vag_solve_info(C.Structure):

@@ -115,6 +115,8 @@ def test_bad_indices_and_options():
     assert _host_create(p, amg_strong_theta=1.0)[0] == vag.VAG_ERR_ARG
     assert _host_create(p, stream_loads=3)[0] == vag.VAG_ERR_ARG
     assert _host_create(p, stream_loads=-1)[0] == vag.VAG_ERR_ARG
+    assert _host_create(p, alpha_rule=2)[0] == vag.VAG_ERR_ARG
+    assert _host_create(p, alpha_rule=-1)[0] == vag.VAG_ERR_ARG
 
 
 def test_peaceman_index_matches_oracle():

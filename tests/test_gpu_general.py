@@ -115,6 +115,35 @@ def test_general_cells_parity(kind, dims, seed, precond):
     h.close()
 
 
+@pytest.mark.parametrize("kind,dims,seed", [("tet", (8, 7, 6), 11), ("prism", (9, 7, 6), 12)])
+def test_general_alpha_rule_parity(kind, dims, seed):
+    """alpha_rule = 1 (§3.2.1, only the largest-permeability cells or fracture
+    faces around a node give it a share) on lognormal tensors and fracture
+    faces of two permeabilities: porous volumes to 1e-13 against the oracle's
+    rule, then the time step and transport on the oracle's fluxes."""
+    p = synth.general_problem(kind, dims, seed, frac_plane=dims[0] // 2, ratio=1e3)
+    fy = np.array([p.xyz[list(p.face(f))][:, 1].mean() for f in p.frac_face_ids])
+    p.frac_perm[fy > 0.5] *= 30.0
+    h, info, vag = gpu(p, precond=1, alpha_rule=1)
+    m = oracle_mesh(p)
+    sol = gc.solve_darcy(m)
+    phi = gc.porous_volumes(m, sol, alpha_rule=1)
+    gphi = vag.to_numpy(h.porous_volumes())
+    for k in ("phi_cell", "phi_frac", "phi_node"):
+        np.testing.assert_allclose(gphi[k], phi[k], rtol=1e-13, atol=1e-18, err_msg=k)
+    base = gc.porous_volumes(m, sol)
+    assert np.abs(phi["phi_node"] - base["phi_node"]).max() > 1e-3 * np.abs(base["phi_node"]).max()
+    h.set_fluxes(oracle_fluxes_flat(p, sol))
+    t = h.transport(n_steps=p.n_steps)
+    dt = gc.cfl_dt(m, sol, phi, p.cfl)
+    assert t["dt"] == pytest.approx(dt, rel=1e-13)
+    oc = gc.transport(m, sol, phi, t["dt"], p.n_steps)
+    gcn = vag.to_numpy(h.concentration())
+    for k in ("c_cell", "c_frac", "c_node"):
+        assert np.abs(gcn[k] - oc[k]).max(initial=0.0) <= 1e-12, k
+    h.close()
+
+
 @pytest.mark.parametrize("kind", ["tet", "prism"])
 def test_general_affine_exact(kind):
     """Affine Dirichlet data on every boundary node and a constant tensor:

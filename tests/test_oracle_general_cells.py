@@ -48,6 +48,22 @@ def test_hexahedra_equal_the_c_oracle():
         np.testing.assert_allclose(c[k], o[k], rtol=0, atol=1e-9)
 
 
+def test_alpha_rule_hexahedra_equal_the_c_oracle():
+    """The largest-permeability rule of §3.2.1 on hexahedra with lognormal
+    tensors (every node between rock types) and fracture patches of several
+    permeabilities: the numpy oracle's porous volumes equal the C oracle's,
+    whose rule is pinned by closed forms."""
+    p = synth.random_problem((6, 5, 4), 43, n_patches=4, n_steps=0)
+    m = gc.Mesh.from_problem(p)
+    s = gc.solve_darcy(m)
+    a = oracle.porous_volumes(p, 1)
+    phi = gc.porous_volumes(m, s, alpha_rule=1)
+    for k in ("phi_cell", "phi_frac", "phi_node"):
+        np.testing.assert_allclose(phi[k], a[k], rtol=1e-13, atol=1e-16)
+    b = oracle.porous_volumes(p, 0)
+    assert np.abs(a["phi_node"] - b["phi_node"]).max() > 1e-3 * np.abs(b["phi_node"]).max()
+
+
 def _general_mesh(kind, dims, seed, aniso=True, frac=False, dirichlet_all=True):
     xyz, _ = sm.structured_hex(*dims)
     rng = np.random.default_rng(seed)

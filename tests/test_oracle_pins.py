@@ -362,6 +362,63 @@ def test_config1_porous_volumes_closed_form():
     np.testing.assert_allclose(phi["phi_frac"], df * h * h / 2, rtol=1e-12, atol=0)
 
 
+def test_alpha_rule_ties_reduce_to_single_rock_type():
+    """§3.2.1's largest-permeability rule on config 1, one matrix rock type
+    and one fracture permeability: every cell (face) around a node ties for
+    the largest permeability, so every one gives its share and the porous
+    volumes are those of the single-rock-type reading, bit for bit."""
+    p = synth.config1()
+    a, b = oracle.porous_volumes(p, 0), oracle.porous_volumes(p, 1)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_alpha_rule_two_rock_types_closed_form():
+    """§3.2.1's rule for nodes between rock types, control volume by control
+    volume on config 1 (h = 1/10, d_f = 0.01) with the cells of x-index >= 7
+    at permeability 10 I (the rest I) and the fracture faces above y = 1/2
+    at 100 times the others' permeability:
+
+    * a node of the rock interface i = 7 takes 1/16 of h^3 from the c_r cells
+      on its high side only (4 inside, 2 on a wall, 1 on a wall edge);
+    * a cell of index 6 gives nothing to its 4 nodes at i = 7 and keeps
+      (1 - 4/16) h^3, a cell of index 7 gives to all 8: h^3/2;
+    * a fracture node on the line j = 5 takes 1/8 of d_f h^2 from the faces
+      above it only (2 inside the plane, 1 on a wall);
+    * a fracture face just below the line gives nothing to its 2 nodes on
+      it: (1 - 2/8) d_f h^2; the other faces keep d_f h^2 / 2;
+    * every other control volume is as with one rock type.
+    Taking the lowest-permeability cells, or the largest over the wrong
+    neighbours, or comparing with > instead of >=, changes these values."""
+    p, n, nijk, cijk = _config1_grid()
+    h, df = 1.0 / n, 0.01
+    hi_cell = cijk[:, 0] >= 7
+    p.perm[hi_cell] = [10.0, 10.0, 10.0, 0.0, 0.0, 0.0]
+    fy = p.xyz[np.asarray(p.frac_nodes).reshape(-1, 4)][:, :, 1].mean(1)
+    hi_face = fy > 0.5
+    p.frac_perm[hi_face] *= 100.0
+    phi = oracle.porous_volumes(p, 1)
+    base = oracle.porous_volumes(synth.config1(), 0)
+    on_wall = lambda a: (a == 0) | (a == n)  # noqa: E731
+    per_axis = lambda a: np.where(on_wall(a), 1, 2)  # noqa: E731
+    expect_node = base["phi_node"].copy()
+    iface = nijk[:, 0] == 7
+    expect_node[iface] = per_axis(nijk[iface, 1]) * per_axis(nijk[iface, 2]) * h ** 3 / 16
+    line = (nijk[:, 0] == n // 2) & (nijk[:, 1] == n // 2)
+    expect_node[line] = per_axis(nijk[line, 2]) * df * h * h / 8
+    np.testing.assert_allclose(phi["phi_node"], expect_node, rtol=1e-12, atol=0)
+    expect_cell = base["phi_cell"].copy()
+    expect_cell[cijk[:, 0] == 6] = 0.75 * h ** 3
+    expect_cell[cijk[:, 0] == 7] = 0.5 * h ** 3
+    np.testing.assert_allclose(phi["phi_cell"], expect_cell, rtol=1e-12, atol=0)
+    below = (fy > 0.5 - h) & (fy < 0.5)
+    expect_frac = np.where(below, 0.75, 0.5) * df * h * h
+    np.testing.assert_allclose(phi["phi_frac"], expect_frac, rtol=1e-12, atol=0)
+    # shares only move between control volumes: the total is unchanged
+    total = sum(v.sum() for v in phi.values())
+    assert total == pytest.approx(sum(v.sum() for v in base.values()), rel=1e-13)
+
+
 def test_config1_cfl_closed_form():
     """eq eq_CFL on config 1, where u = 1 - x is the exact discrete solution.
 
