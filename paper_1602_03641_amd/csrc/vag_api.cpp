@@ -169,13 +169,13 @@ struct vag_handle {
     DBuf<uint16_t> tcol16;
     DBuf<uint16_t> tmeta;
     DBuf<int64_t> slice_ptr;
-    DBuf<int32_t> xsplit;  // [9] the XCDs' runs of slices of the upwind operator
+    DBuf<int32_t> xsplit;  // [18] the XCDs' runs of slices of the upwind operator (xlo, then ylo)
     DBuf<double> pmax;     // [nn] largest permeability around each node (alpha_rule 1)
-    int32_t xlo[9] = {};   // host copy, passed to the sweep by value
+    int32_t xlo[18] = {};  // host copy, passed to the sweep by value
     DBuf<double> tval, tdiag, cbuf0, cbuf1, dt4;
     DBuf<unsigned long long> cnt;
-    // pinned: [0] entry count of the upwind operator, from [2] the 9 ints of xsplit
-    static constexpr int kCntWords = 8;
+    // pinned: [0] entry count of the upwind operator, from [2] the 18 ints of xsplit
+    static constexpr int kCntWords = 16;
     unsigned long long *h_cnt = nullptr;
     int32_t *h_xsplit() { return reinterpret_cast<int32_t *>(h_cnt + 2); }
     int cur = 0;
@@ -235,8 +235,11 @@ struct vag_handle {
         return m;
     }
     UpwindOp upwind() const {
-        UpwindOp T{S.nc + S.nf + S.nn, slice_ptr.p, tmeta.p, tcol.p, tcol16.p, tbase.p, tval.p, tdiag.p, {}};
-        for (int x = 0; x < 9; ++x) T.xlo[x] = xlo[x];
+        UpwindOp T{S.nc + S.nf + S.nn, slice_ptr.p, tmeta.p, tcol.p, tcol16.p, tbase.p, tval.p, tdiag.p, {}, {}};
+        for (int x = 0; x < 9; ++x) {
+            T.xlo[x] = xlo[x];
+            T.ylo[x] = xlo[9 + x];
+        }
         return T;
     }
     double *c_cur() { return cur ? cbuf1.p : cbuf0.p; }
@@ -926,7 +929,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         h->slice_nnz.alloc(nslice, h->tr);
         h->tmeta.alloc((size_t)nslice * kSliceRows, h->tr);
         h->slice_ptr.alloc(nslice + 1, h->tr);
-        h->xsplit.alloc(9, h->tr);
+        h->xsplit.alloc(18, h->tr);
         h->tdiag.alloc(nrow, h->tr);
         // one more entry: the constant control volume (concentration 1) that
         // well injection terms of the upwind operator read
@@ -1282,14 +1285,16 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
                                 h->slice_nnz.p);
         }
         launch_slice_scan(s, nslice, h->slice_nnz.p, 1, h->slice_ptr.p, h->slice_nnz.p, h->cnt.p);
-        launch_xcd_split(s, nslice, h->slice_ptr.p, h->xsplit.p);
+        // segment A: the slices of cells and fracture faces, B: of nodes
+        launch_xcd_split(s, nslice, (int32_t)((S.nc + (int64_t)S.nf + kSliceRows - 1) / kSliceRows), h->slice_ptr.p,
+                         h->xsplit.p);
         int64_t total = 0;
         VAG_HIP(hipMemcpyAsync(&total, h->slice_ptr.p + nslice, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipMemcpyAsync(h->h_cnt, h->cnt.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-        VAG_HIP(hipMemcpyAsync(h->h_xsplit(), h->xsplit.p, 9 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipMemcpyAsync(h->h_xsplit(), h->xsplit.p, 18 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipMemcpyAsync(h->h_scal, h->dt4.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
         VAG_HIP(hipStreamSynchronize(s));
-        for (int x = 0; x < 9; ++x) h->xlo[x] = h->h_xsplit()[x];
+        for (int x = 0; x < 18; ++x) h->xlo[x] = h->h_xsplit()[x];
         const double dt = h->h_scal[3];
         double dtb[3] = {h->h_scal[0], h->h_scal[1], h->h_scal[2]};
         if (!(dt < INFINITY)) throw Error(VAG_ERR_ARG, "no control volume has an outflow: CFL bound is infinite");

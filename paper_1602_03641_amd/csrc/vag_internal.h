@@ -410,10 +410,16 @@ void launch_upwind_fill(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const
 // Upwind operator: 64-row slices (rows sorted longest first, meta = source
 // lane << 8 | entry count per slot), entries packed by level (jagged
 // diagonals) from slice_ptr[slice]; 16-bit columns from tbase[slice] where
-// tbase >= 0, else the 32-bit tcol.  XCD x of the 8 sweeps the slices
-// [xlo[x], xlo[x+1]), contiguous runs of equal cost (bytes moved), so that a
-// mesh whose rows differ in length along the numbering (cells of 4 nodes
-// before nodes of 24 cells) keeps every XCD equally busy.
+// tbase >= 0, else the 32-bit tcol.
+// The sweep splits the slices into two segments, A = [0, sa) (cells and
+// fracture faces) and B = [sa, nslice) (nodes), and gives XCD x of the 8 the
+// slices [xlo[x], xlo[x+1]) of A and [ylo[x], ylo[x+1]) of B, runs of equal
+// cost (bytes moved) in each segment.  The XCD interleaves its two runs in
+// proportion, so that the cells and the nodes of one region of the mesh
+// (both numbered along the mesh) are swept together and the gathers of each
+// hit the lines the other has brought into that XCD's L2; the cost balance
+// keeps every XCD equally busy when rows differ in length along the
+// numbering (cells of 4 nodes, nodes of 24 cells).
 struct UpwindOp {
     int32_t nrow;
     const int64_t *slice_ptr;
@@ -422,12 +428,12 @@ struct UpwindOp {
     const uint16_t *tcol16;
     const int32_t *tbase;
     const double *tval, *tdiag;
-    int32_t xlo[9];
+    int32_t xlo[9], ylo[9];
 };
 // tcol16 and tbase from tcol (after launch_upwind_fill)
 void launch_upwind_pack(hipStream_t s, const UpwindOp &T, uint16_t *tcol16, int32_t *tbase);
-// xlo[0..8] of the slices from slice_ptr (after the slice scan)
-void launch_xcd_split(hipStream_t s, int32_t nslice, const int64_t *slice_ptr, int32_t *xlo);
+// xlo[0..8] and ylo[0..8] (at xlo + 9) from slice_ptr (after the slice scan)
+void launch_xcd_split(hipStream_t s, int32_t nslice, int32_t sa, const int64_t *slice_ptr, int32_t *xlo);
 void launch_transport_step(hipStream_t s, const UpwindOp &T, const double *c_in, double *c_out, double theta);
 // Peaceman wells (wells.hip).  wsrc[f] = c_inj Q^+ (tracer injected into face
 // f per unit time), wout[f] = Q^- (volume produced); the upwind operator's
