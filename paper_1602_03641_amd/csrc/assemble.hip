@@ -444,32 +444,50 @@ __global__ __launch_bounds__(256) void sell_fill_kernel(int32_t n, int64_t nslic
     if (r < n) row_len[r] = len;
 }
 
-// 16-bit column offsets per slice (one wavefront per slice): when the columns
-// of the slice's rows lie within 65536 of their minimum, col16 = col - min and
-// cbase = min; otherwise cbase = -1 and the row loops read the 32-bit columns.
-// Rows past n (the tail of the last slice) are never evaluated and take offset 0.
+// 16-bit column offsets (one wavefront per slice).  Level k of a slice (entry
+// k of each of its 64 rows, one group of 64 stored entries) gets its own base,
+// the least column among the level's real entries: in a slice of rows of one
+// pattern a level holds the neighbours in one direction, whose columns lie
+// close together even where the slice as a whole spans more than 65536
+// columns (the z-stride of a 192^3 node numbering is 37249).  When every
+// level's real columns lie within 65536 of its base, col16 = col - base and
+// cbase[group] = base; otherwise all of the slice's groups get cbase = -1 and
+// the row loops read the 32-bit columns.  Padding entries (past a row's
+// length, value 0) and rows past n take offset 0: the level's base, a valid
+// column.
 __global__ __launch_bounds__(64) void sell_pack_kernel(int32_t n, const int64_t *__restrict__ ptr,
-                                                       const int32_t *__restrict__ col, uint16_t *__restrict__ col16,
-                                                       int32_t *__restrict__ cbase) {
+                                                       const int32_t *__restrict__ col,
+                                                       const int32_t *__restrict__ row_len,
+                                                       uint16_t *__restrict__ col16, int32_t *__restrict__ cbase) {
     const int64_t sl = blockIdx.x;
     const int lane = threadIdx.x;
-    const bool live = sl * 64 + lane < n;
-    const int64_t b0 = ptr[sl] + lane, b1 = ptr[sl + 1];
-    int32_t lo = INT32_MAX, hi = -1;
-    if (live)
-        for (int64_t q = b0; q < b1; q += 64) {
-            lo = min(lo, col[q]);
-            hi = max(hi, col[q]);
-        }
+    const int64_t r = sl * 64 + lane;
+    const int len = r < n ? row_len[r] : 0;
+    const int64_t b0 = ptr[sl], width = (ptr[sl + 1] - b0) / 64;
+    auto level = [&](int64_t k, int32_t &lo, int32_t &hi) {
+        const bool real = k < len;
+        const int32_t c = real ? col[b0 + 64 * k + lane] : 0;
+        lo = real ? c : INT32_MAX;
+        hi = real ? c : -1;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        lo = min(lo, __shfl_xor(lo, o, 64));
-        hi = max(hi, __shfl_xor(hi, o, 64));
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = min(lo, __shfl_xor(lo, o, 64));
+            hi = max(hi, __shfl_xor(hi, o, 64));
+        }
+        return c;
+    };
+    bool compact = true;
+    for (int64_t k = 0; k < width; ++k) {
+        int32_t lo, hi;
+        level(k, lo, hi);
+        compact = compact && hi >= 0 && (int64_t)hi - lo <= 65535;
     }
-    const bool compact = hi >= 0 && (int64_t)hi - lo <= 65535;
-    if (compact)
-        for (int64_t q = b0; q < b1; q += 64) col16[q] = live ? (uint16_t)(col[q] - lo) : (uint16_t)0;
-    if (lane == 0) cbase[sl] = compact ? lo : -1;
+    for (int64_t k = 0; k < width; ++k) {
+        int32_t lo, hi;
+        const int32_t c = level(k, lo, hi);
+        if (compact) col16[b0 + 64 * k + lane] = k < len ? (uint16_t)(c - lo) : (uint16_t)0;
+        if (lane == 0) cbase[(b0 >> 6) + k] = compact ? lo : -1;
+    }
 }
 
 // system positions of the node pairs of each eliminated group
@@ -639,11 +657,11 @@ void launch_sell_fill(hipStream_t s, int32_t n, int64_t nslice, const int32_t *r
     VAG_HIP(hipGetLastError());
 }
 
-void launch_sell_pack(hipStream_t s, int32_t n, const int64_t *ptr, const int32_t *col, uint16_t *col16,
-                      int32_t *cbase) {
+void launch_sell_pack(hipStream_t s, int32_t n, const int64_t *ptr, const int32_t *col, const int32_t *row_len,
+                      uint16_t *col16, int32_t *cbase) {
     const int64_t nslice = ((int64_t)n + 63) / 64;
     if (nslice <= 0) return;
-    hipLaunchKernelGGL(sell_pack_kernel, dim3((unsigned)nslice), dim3(64), 0, s, n, ptr, col, col16, cbase);
+    hipLaunchKernelGGL(sell_pack_kernel, dim3((unsigned)nslice), dim3(64), 0, s, n, ptr, col, row_len, col16, cbase);
     VAG_HIP(hipGetLastError());
 }
 

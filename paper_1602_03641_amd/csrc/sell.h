@@ -21,17 +21,21 @@ __device__ inline void sell_row_chains(const Sell<V> &A, int64_t q, int64_t b1, 
 
 template <class V, class Acc, class F>
 __device__ inline Acc sell_row_apply(const Sell<V> &A, int32_t row, F f) {
-    const int64_t b1 = A.ptr[(row >> 6) + 1];
-    const int64_t q = A.ptr[row >> 6] + (row & 63);
+    const int64_t b0 = A.ptr[row >> 6], b1 = A.ptr[(row >> 6) + 1];
+    const int64_t q = b0 + (row & 63);
     Acc s[kChains];
 #pragma unroll
     for (int c = 0; c < kChains; ++c) s[c] = 0;
-    const int32_t cb = A.col16 ? A.cbase[row >> 6] : -1;  // uniform over a slice (one wavefront)
+    // the slice's first group says whether its columns are 16-bit; p / 64 is
+    // the same for every lane of the wavefront (the slice's level)
+    const int32_t cb = A.col16 && b1 > b0 ? A.cbase[b0 >> 6] : -1;
     if (cb >= 0) {
         if (A.nt)
-            sell_row_chains<true, V, Acc>(A, q, b1, s, f, [&](int64_t p) { return cb + (int32_t)ld_matrix<true>(&A.col16[p]); });
+            sell_row_chains<true, V, Acc>(A, q, b1, s, f, [&](int64_t p) {
+                return A.cbase[p >> 6] + (int32_t)ld_matrix<true>(&A.col16[p]);
+            });
         else
-            sell_row_chains<false, V, Acc>(A, q, b1, s, f, [&](int64_t p) { return cb + (int32_t)A.col16[p]; });
+            sell_row_chains<false, V, Acc>(A, q, b1, s, f, [&](int64_t p) { return A.cbase[p >> 6] + (int32_t)A.col16[p]; });
     } else {
         if (A.nt)
             sell_row_chains<true, V, Acc>(A, q, b1, s, f, [&](int64_t p) { return ld_matrix<true>(&A.col[p]); });

@@ -872,8 +872,9 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
             launch_sell_fill(h->stream, S.nunk, nslice, rp.p, cl.p, h->sell_ptr.p, h->sell_col.p, h->row_len.p,
                              h->diag_pos.p);
             h->sell_col16.alloc(std::max<int64_t>(S.sell_ptr.back(), 1), h->tr);
-            h->sell_cbase.alloc(std::max<int64_t>(nslice, 1), h->tr);
-            launch_sell_pack(h->stream, S.nunk, h->sell_ptr.p, h->sell_col.p, h->sell_col16.p, h->sell_cbase.p);
+            h->sell_cbase.alloc(std::max<int64_t>(S.sell_ptr.back() / 64, 1), h->tr);
+            launch_sell_pack(h->stream, S.nunk, h->sell_ptr.p, h->sell_col.p, h->row_len.p, h->sell_col16.p,
+                             h->sell_cbase.p);
             VAG_HIP(hipStreamSynchronize(h->stream));
         }
         h->Gb.alloc(std::max<int64_t>(S.grp_off.back(), 1), h->tr);

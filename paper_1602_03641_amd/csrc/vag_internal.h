@@ -219,18 +219,20 @@ struct Sell {
     // optional diagonal held apart in FP64 (the stored diagonal entries are
     // then zero): the FP32 copies keep each row's FP64 row sum this way
     const double *dg = nullptr;
-    // optional 16-bit column offsets: where cbase[slice] >= 0 the slice's
-    // columns are cbase[slice] + col16[q] (the row loops read 2 bytes per
-    // entry instead of 4); other kernels keep reading col
+    // optional 16-bit column offsets, one base per group of 64 stored entries
+    // (one level of a slice): where the slice's first group has cbase >= 0,
+    // the column of entry q is cbase[q / 64] + col16[q] (the row loops read 2
+    // bytes per entry instead of 4); other kernels keep reading col
     const uint16_t *col16 = nullptr;
     const int32_t *cbase = nullptr;
     // the row loops read val and the columns with non-temporal loads
     bool nt = false;
 };
-// col16 and cbase of a sliced-ELL pattern: a slice whose stored columns lie
-// within 65536 of their minimum gets cbase = that minimum, else -1
-void launch_sell_pack(hipStream_t s, int32_t n, const int64_t *ptr, const int32_t *col, uint16_t *col16,
-                      int32_t *cbase);
+// col16 and cbase (one per 64 stored entries) of a sliced-ELL pattern: a
+// slice each of whose levels holds real columns within 65536 of the level's
+// least gets that least as the level's base, else -1 for all its levels
+void launch_sell_pack(hipStream_t s, int32_t n, const int64_t *ptr, const int32_t *col, const int32_t *row_len,
+                      uint16_t *col16, int32_t *cbase);
 
 struct PcgState {       // device-resident scalars of a Krylov solve
     double tol2, bnorm2, rr, pad;
