@@ -19,6 +19,7 @@
 #include <array>
 #include <exception>
 #include <thread>
+#include <memory>
 #include <unordered_map>
 
 #include "host_parallel.h"
@@ -65,38 +66,67 @@ bool same_cycle(const int32_t *a, const int32_t *b) {
 
 }  // namespace
 
-void finish_symbolic_pattern(Symbolic &S) {
+namespace {
+// sorts a short row in place (rows hold at most a few dozen columns)
+inline void sort_row(int32_t *b, int32_t *e) {
+    if (e - b > 48) {
+        std::sort(b, e);
+        return;
+    }
+    for (int32_t *i = b + 1; i < e; ++i) {
+        const int32_t v = *i;
+        int32_t *j = i;
+        for (; j > b && j[-1] > v; --j) *j = j[-1];
+        *j = v;
+    }
+}
+}  // namespace
+
+void finish_symbolic_pattern(Symbolic &S, const std::vector<const int32_t *> *row_src) {
     const int32_t nn = S.nn, nf = S.nf, nfree = S.nfree;
     // Renumber the system rows so that, inside windows of kSortWindow rows
     // (node rows and face rows apart), longer rows come first (stable):
     // slices then hold rows of similar length and carry little padding,
     // while rows of equal length keep their order and their locality.
+    // Old row o lists its columns at row_src[o] (or in S.col from
+    // S.row_ptr[o]), unsorted and in the old numbering.
     {
         const int32_t n = S.nunk;
         std::vector<int32_t> order(n);
-        for (int32_t r = 0; r < n; ++r) order[r] = r;
         auto len = [&](int32_t r) { return S.row_ptr[r + 1] - S.row_ptr[r]; };
-        auto sort_block = [&](int32_t b0, int32_t b1) {
-            for (int32_t w0 = b0; w0 < b1; w0 += kSortWindow) {
-                const int32_t w1 = std::min(b1, w0 + kSortWindow);
-                std::stable_sort(order.begin() + w0, order.begin() + w1,
-                                 [&](int32_t x, int32_t y) { return len(x) > len(y); });
-            }
+        // a counting sort by decreasing length inside each window (stable)
+        auto windows = [&](int32_t b0, int32_t b1) {
+            const int64_t nw = ((int64_t)b1 - b0 + kSortWindow - 1) / kSortWindow;
+            parallel_chunks(nw, [&](int, int64_t w0, int64_t w1) {
+                std::vector<int32_t> cnt;
+                for (int64_t w = w0; w < w1; ++w) {
+                    const int32_t r0 = b0 + (int32_t)(w * kSortWindow), r1 = std::min(b1, r0 + kSortWindow);
+                    int32_t lmax = 0;
+                    for (int32_t r = r0; r < r1; ++r) lmax = std::max(lmax, len(r));
+                    cnt.assign((size_t)lmax + 2, 0);
+                    for (int32_t r = r0; r < r1; ++r) cnt[lmax - len(r) + 1]++;
+                    for (int32_t l = 0; l <= lmax; ++l) cnt[l + 1] += cnt[l];
+                    for (int32_t r = r0; r < r1; ++r) order[r0 + cnt[lmax - len(r)]++] = r;
+                }
+            }, 64);
         };
-        sort_block(0, nfree);
-        sort_block(nfree, n);
+        windows(0, nfree);
+        windows(nfree, n);
         S.sys_old.assign(order.begin(), order.end());  // new row -> old row
         S.sys_new.assign(n, -1);                        // old row -> new row
         for (int32_t r = 0; r < n; ++r) S.sys_new[order[r]] = r;
         // pattern in the new numbering
-        std::vector<int32_t> rp(n + 1, 0), cl(S.col.size());
+        std::vector<int32_t> rp(n + 1);
+        rp[0] = 0;
         for (int32_t r = 0; r < n; ++r) rp[r + 1] = rp[r] + len(order[r]);
+        uvector<int32_t> cl((size_t)rp[n]);
         parallel_chunks(n, [&](int, int64_t r0, int64_t r1) {
             for (int32_t r = (int32_t)r0; r < (int32_t)r1; ++r) {
                 const int32_t o = order[r];
+                const int32_t *src = row_src ? (*row_src)[o] : S.col.data() + S.row_ptr[o];
                 int32_t *out = cl.data() + rp[r];
-                for (int32_t q = S.row_ptr[o]; q < S.row_ptr[o + 1]; ++q) *out++ = S.sys_new[S.col[q]];
-                std::sort(cl.data() + rp[r], out);
+                for (int32_t k = 0; k < len(o); ++k) out[k] = S.sys_new[src[k]];
+                sort_row(out, out + len(o));
             }
         });
         S.row_ptr.swap(rp);
@@ -381,8 +411,8 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
     }
 
     // unknowns of each cell: 8 nodes, then its fracture faces by local face
-    std::vector<int32_t> cu(14 * (size_t)nc);
-    std::vector<uint8_t> cm(nc);
+    uvector<int32_t> cu(14 * (size_t)nc);
+    uvector<uint8_t> cm(nc);
     parallel_chunks(nc, [&](int, int64_t k0, int64_t k1) {
         for (int32_t K = (int32_t)k0; K < (int32_t)k1; ++K) {
             int32_t *u = cu.data() + 14 * (size_t)K;
@@ -399,15 +429,18 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
     // also couples to every free node of each eliminated group it belongs to
     // (fill)
     S.row_ptr.assign((size_t)S.nunk + 1, 0);
+    // rows are built in chunks of nodes (then of faces), each chunk into its
+    // own column list; the renumbering reads every row from there
+    std::vector<std::vector<int32_t>> part;
+    std::vector<const int32_t *> row_src;
     {
-        // rows are built in chunks of nodes (then of faces), each chunk into
-        // its own column list, then concatenated in row order
         const int Tn = chunk_count(nn), Tf = chunk_count(nf);
-        std::vector<std::vector<int32_t>> part(Tn + Tf);
+        part.resize(Tn + Tf);
         auto build_rows = [&](std::vector<int32_t> &out, bool faces, int64_t i0, int64_t i1) {
             std::vector<int32_t> marker((size_t)S.nunk, -1);
             std::vector<int32_t> cols;
             cols.reserve(128);
+            out.reserve((size_t)(i1 - i0) * (faces ? 20 : 28));
             auto add = [&](int32_t row, int32_t c) {
                 if (c >= 0 && c < S.nunk && marker[c] != row) {
                     marker[c] = row;
@@ -438,7 +471,7 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
                     for (int side = 0; side < 2; ++side)
                         if (S.frac_cell[2 * (size_t)f + side] >= 0) add_cell(row, S.frac_cell[2 * (size_t)f + side]);
                 }
-                // unsorted here: the renumbering below sorts every row once
+                // unsorted here: the renumbering sorts every row once
                 out.insert(out.end(), cols.begin(), cols.end());
                 S.row_ptr[row + 1] = (int32_t)cols.size();
             }
@@ -448,18 +481,27 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
         int64_t total = 0;
         for (auto &v : part) total += (int64_t)v.size();
         if (total >= INT32_MAX) throw Error(VAG_ERR_UNSUPPORTED, "system has more than 2^31 nonzeros");
-        for (int32_t r = 0; r < S.nunk; ++r) S.row_ptr[r + 1] += S.row_ptr[r];
-        S.col.resize(total);
-        int64_t off = 0;
-        for (auto &v : part) {
-            std::copy(v.begin(), v.end(), S.col.begin() + off);
-            off += (int64_t)v.size();
-            std::vector<int32_t>().swap(v);
+        // where each row's list starts in its chunk's buffer (rows of a chunk
+        // are consecutive unknowns: node_unk and frac_unk increase with the
+        // node and face index)
+        row_src.assign((size_t)S.nunk, nullptr);
+        for (int t = 0; t < Tn + Tf; ++t) {
+            const bool faces = t >= Tn;
+            const int T = faces ? Tf : Tn, c = faces ? t - Tn : t;
+            const int64_t n_items = faces ? nf : nn, i0 = n_items * c / T, i1 = n_items * (c + 1) / T;
+            const int32_t *p = part[t].data();
+            for (int64_t i = i0; i < i1; ++i) {
+                const int32_t row = faces ? (S.frac_unk[i] < S.nunk ? S.frac_unk[i] : -1) : S.node_unk[i];
+                if (row < 0) continue;
+                row_src[row] = p;
+                p += S.row_ptr[row + 1];
+            }
         }
+        for (int32_t r = 0; r < S.nunk; ++r) S.row_ptr[r + 1] += S.row_ptr[r];
     }
     S.nnz = S.row_ptr[S.nunk];
 
-    finish_symbolic_pattern(S);
+    finish_symbolic_pattern(S, &row_src);
     S.face_grp = std::move(face_grp);
     S.face_loc = std::move(face_loc);
 }

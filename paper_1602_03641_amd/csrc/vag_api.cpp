@@ -289,8 +289,8 @@ void upload(vag_handle *h, DBuf<T> &d, const T *src, size_t n, vag_mem mem) {
     if (mem == VAG_MEM_HOST) VAG_HIP(hipStreamSynchronize(h->stream));
 }
 
-template <class T>
-void upload_vec(vag_handle *h, DBuf<T> &d, const std::vector<T> &v) {
+template <class T, class A>
+void upload_vec(vag_handle *h, DBuf<T> &d, const std::vector<T, A> &v) {
     d.alloc(v.size(), h->tr);
     if (v.empty()) return;
     // on the handle's stream: a worker stream created non-blocking is not

@@ -5,8 +5,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <stdexcept>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "vag.h"
@@ -121,6 +123,29 @@ struct DBuf {
 // ---------------------------------------------------------------------------
 // symbolic phase (host): topology-only data structures
 // ---------------------------------------------------------------------------
+// A std::vector whose resize leaves new elements uninitialised (no zero
+// fill), for large host arrays written in full right afterwards.
+template <class T>
+struct DefaultInitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = DefaultInitAlloc<U>;
+    };
+    DefaultInitAlloc() = default;
+    template <class U>
+    DefaultInitAlloc(const DefaultInitAlloc<U> &) noexcept {}
+    template <class U>
+    void construct(U *p) noexcept {
+        ::new ((void *)p) U;
+    }
+    template <class U, class... A>
+    void construct(U *p, A &&...a) {
+        ::new ((void *)p) U(std::forward<A>(a)...);
+    }
+};
+template <class T>
+using uvector = std::vector<T, DefaultInitAlloc<T>>;
+
 struct Symbolic {
     // nunk: rows of the assembled system (free nodes, kept fracture faces);
     // nx: all nodal and face unknowns (eliminated faces numbered after nunk)
@@ -134,7 +159,8 @@ struct Symbolic {
     std::vector<uint8_t> frac_node;    // [nn] node of some fracture face
     std::vector<int32_t> node_cell_ptr, node_cell;  // node -> cell*8+slot, ascending
     std::vector<int32_t> node_frac_ptr, node_frac;  // node -> frac*4+i, ascending
-    std::vector<int32_t> row_ptr, col;               // CSR pattern of the eliminated system (sorted rows)
+    std::vector<int32_t> row_ptr;                    // CSR pattern of the eliminated system (sorted rows)
+    uvector<int32_t> col;
     std::vector<int64_t> sell_ptr;                   // sliced-ELL slice pointers of that pattern
     std::vector<int32_t> unk_node, unk_face;         // row -> free node (rows < nfree), -> kept face
     std::vector<int32_t> sys_old, sys_new;           // system row renumbering: new -> natural, natural -> new
@@ -189,7 +215,7 @@ void build_symbolic_general(int64_t nn, int64_t nc, int64_t nface, const int64_t
                             GenSym &G);
 // Renumbering of the system rows (longest first inside windows) and the
 // sliced-ELL slice pointers of the CSR pattern in S (shared by both paths).
-void finish_symbolic_pattern(Symbolic &S);
+void finish_symbolic_pattern(Symbolic &S, const std::vector<const int32_t *> *row_src = nullptr);
 
 // Rows are sorted by length inside windows of this many rows (slice padding).
 constexpr int kSortWindow = 512;
