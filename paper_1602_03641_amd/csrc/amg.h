@@ -149,7 +149,7 @@ struct AmgLevel {
 
 struct AmgOptions {
     double theta = 0.02;
-    int coarse_size = 500;
+    int coarse_size = 1000;
     int max_levels = 12;
     int mis_rounds = 32;
     int dense_max = 1024;

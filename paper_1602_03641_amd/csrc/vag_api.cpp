@@ -747,7 +747,7 @@ vag_status vag_default_options(vag_options *o) {
     o->gmres_restart = 100;
     o->check_every = 16;
     o->cfl = 0.9;
-    o->amg_coarse_size = 500;
+    o->amg_coarse_size = 1000;
     o->amg_max_levels = 12;
     o->amg_theta = 0.02;
     o->amg_sweeps = 1;
@@ -1790,7 +1790,11 @@ size_t vag_estimate_footprint(int64_t nn, int64_t nc, int64_t nf, const vag_opti
         if (o.precision == VAG_MIXED_IR) amg += 4.6 * S + 74 * Nx;
         if (o.amg_kind == 1)  // denser levels, P, R, A P and the product tables of one chunk of rows
             amg += 1.5 * amg + 12 * 48 * Nx + 12 * 1024 * std::min(Nx, (double)kClChunk);
-        b += 1.125 * amg + 1.5 * 1024 * 1024;                       // + dense coarsest inverse
+        // the dense inverse of the coarsest level (FP64, and FP32 for the mixed
+        // modes) and its elimination workspace: at most coarse_size rows
+        const double cs = o.amg_coarse_size > 0 ? o.amg_coarse_size : 1000.0;
+        const double d = std::min(Nx, std::min(cs, 1024.0));
+        b += 1.125 * amg + 12.0 * d * d + 1024.0 * d + 0.5 * 1024 * 1024;
     }
     if (o.precond == VAG_PC_BJILU0) b += 14 * nnz + 28 * Nx;        // factor entries, rows, schedules
     if (o.krylov == VAG_GMRES) {  // flexible GMRES: m + 1 basis vectors, m preconditioned ones, two work vectors
