@@ -407,7 +407,9 @@ def test_mixed_same_iterations_as_fp64():
 
 def test_mixed_config2_error_stated():
     """Benchmark tolerance (1e-8): the FP64 residual meets it and the error
-    against the FP64 oracle is reported per result."""
+    against the FP64 oracle is reported per result.  The pressures meet the
+    1e-8 relative-L2 bar (measured: about 3e-10), and the concentrations the
+    scaled bar of compare() (1e-10 times the pressure gap over 1e-12)."""
     p = synth.config2()
     g = gpu_run(p, rtol=1e-8, max_iter=2000, **_mixed())
     o = oracle.run(p, rtol=1e-12)
@@ -417,7 +419,8 @@ def test_mixed_config2_error_stated():
     print(f"mixed config2: inner={info['iterations']} outer={info['outer_iterations']} "
           f"res={info['rel_residual']:.2e} pressure relL2={e_p:.2e} conc maxabs={e_c:.2e}")
     assert info["status"] == 0 and info["rel_residual"] <= 1e-8
-    assert e_p <= 1e-6
+    assert e_p <= 1e-8
+    assert e_c <= 1e-10 * max(1.0, e_p / 1e-12)
 
 
 @pytest.mark.parametrize("kind", ["random_1e6", "config2"])
