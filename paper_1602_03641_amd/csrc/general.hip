@@ -48,15 +48,21 @@ __device__ inline V3 node(const double *xyz, int32_t s) {
 
 }  // namespace
 
+// NV, NF, FK: the most nodes, faces and face nodes of a cell in the mesh, so
+// that the thread's arrays (the local matrix over at most NV + NF unknowns)
+// are no larger than the mesh needs: a tetrahedral mesh keeps 8 x 8 instead of
+// 14 x 14 per thread
+template <int NV, int NF, int FK>
 __global__ __launch_bounds__(128) void gen_local_kernel(GenMesh g, const double *__restrict__ xyz,
                                                         const double *__restrict__ perm, double inv_mu,
                                                         double *__restrict__ loc, double *__restrict__ ga,
                                                         double *__restrict__ gr, double *__restrict__ AKKo,
                                                         double *__restrict__ volo, int *__restrict__ bad_cell) {
+    constexpr int kM = NV + NF;
     const int32_t K = blockIdx.x * blockDim.x + threadIdx.x;
     if (K >= g.nc) return;
     const int32_t p0 = g.cnode_ptr[K], nv = g.cnode_ptr[K + 1] - p0;
-    V3 X[kGenMaxNodes];
+    V3 X[NV];
     V3 xK = {0, 0, 0};
     for (int i = 0; i < nv; ++i) {
         X[i] = node(xyz, g.cnode[p0 + i]);
@@ -70,17 +76,17 @@ __global__ __launch_bounds__(128) void gen_local_kernel(GenMesh g, const double 
     double L[6];
     for (int i = 0; i < 6; ++i) L[i] = perm[6 * (int64_t)K + i] * inv_mu;
     // unknowns: the nodes (local order), then the fracture faces by local face
-    int fu[kGenMaxFaces];
+    int fu[NF];
     int m = nv;
-    for (int f = 0; f < kGenMaxFaces; ++f) fu[f] = g.cell_frac[kGenMaxFaces * (int64_t)K + f] >= 0 ? m++ : -1;
-    double a[kMaxM * kMaxM];
-    for (int i = 0; i < kMaxM * kMaxM; ++i) a[i] = 0.0;
+    for (int f = 0; f < NF; ++f) fu[f] = g.cell_frac[kGenMaxFaces * (int64_t)K + f] >= 0 ? m++ : -1;
+    double a[kM * kM];
+    for (int i = 0; i < kM * kM; ++i) a[i] = 0.0;
     double vol = 0.0;
     bool bad = false;
-    for (int f = 0; f < kGenMaxFaces; ++f) {
+    for (int f = 0; f < NF; ++f) {
         const int k = g.cface_k[kGenMaxFaces * (int64_t)K + f];
         if (k == 0) continue;
-        int ln[kGenMaxFaceNodes];
+        int ln[FK];
         V3 xs = {0, 0, 0};
         for (int i = 0; i < k; ++i) {
             ln[i] = g.cface_loc[(kGenMaxFaces * (int64_t)K + f) * kGenMaxFaceNodes + i];
@@ -100,9 +106,9 @@ __global__ __launch_bounds__(128) void gen_local_kernel(GenMesh g, const double 
         // stiffness over (face centre, face nodes) from the face's sub-tetrahedra;
         // with J = [x_sigma - x_K, s1 - x_K, s2 - x_K] the gradients of the
         // barycentric coordinates of x_sigma, s1, s2 are (b x c, c x a, a x b) / det
-        double S[(kGenMaxFaceNodes + 1) * (kGenMaxFaceNodes + 1)];
-        for (int i = 0; i < (kGenMaxFaceNodes + 1) * (kGenMaxFaceNodes + 1); ++i) S[i] = 0.0;
-        constexpr int W = kGenMaxFaceNodes + 1;
+        constexpr int W = FK + 1;
+        double S[W * W];
+        for (int i = 0; i < W * W; ++i) S[i] = 0.0;
         for (int e = 0; e < k; ++e) {
             const int i1 = 1 + e, i2 = 1 + (e + 1) % k;
             const V3 b = sub(X[ln[e]], xK), c = sub(X[ln[(e + 1) % k]], xK);
@@ -129,23 +135,23 @@ __global__ __launch_bounds__(128) void gen_local_kernel(GenMesh g, const double 
             const double be = 1.0 / k;
             for (int i = 0; i < k; ++i)
                 for (int j = 0; j < k; ++j)
-                    a[ln[i] * kMaxM + ln[j]] +=
+                    a[ln[i] * kM + ln[j]] +=
                         S[(1 + i) * W + 1 + j] + be * (S[1 + i] + S[1 + j]) + be * be * S[0];
         } else {
             const int t = fu[f];
             for (int i = 0; i < k; ++i) {
-                for (int j = 0; j < k; ++j) a[ln[i] * kMaxM + ln[j]] += S[(1 + i) * W + 1 + j];
-                a[t * kMaxM + ln[i]] += S[1 + i];
-                a[ln[i] * kMaxM + t] += S[1 + i];
+                for (int j = 0; j < k; ++j) a[ln[i] * kM + ln[j]] += S[(1 + i) * W + 1 + j];
+                a[t * kM + ln[i]] += S[1 + i];
+                a[ln[i] * kM + t] += S[1 + i];
             }
-            a[t * kMaxM + t] += S[0];
+            a[t * kM + t] += S[0];
         }
     }
-    double r[kMaxM];
+    double r[kM];
     double akk = 0.0;
     for (int i = 0; i < m; ++i) {
         double t = 0.0;
-        for (int j = 0; j < m; ++j) t += a[i * kMaxM + j];
+        for (int j = 0; j < m; ++j) t += a[i * kM + j];
         r[i] = t;
         akk += t;
     }
@@ -153,8 +159,8 @@ __global__ __launch_bounds__(128) void gen_local_kernel(GenMesh g, const double 
     for (int i = 0; i < m; ++i) {
         gr[g.unk_off[K] + i] = r[i];
         for (int j = 0; j < m; ++j) {
-            ga[off + i * m + j] = a[i * kMaxM + j];
-            loc[off + i * m + j] = a[i * kMaxM + j] - r[i] * r[j] / akk;
+            ga[off + i * m + j] = a[i * kM + j];
+            loc[off + i * m + j] = a[i * kM + j] - r[i] * r[j] / akk;
         }
     }
     AKKo[K] = akk;
@@ -363,8 +369,16 @@ static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / 
 void launch_gen_local(hipStream_t s, const GenMesh &g, const double *xyz, const double *perm, double inv_mu,
                       double *loc, double *ga, double *gr, double *AKK, double *vol, int *bad_cell) {
     if (g.nc <= 0) return;
-    hipLaunchKernelGGL(gen_local_kernel, dim3(nblk(g.nc, 128)), dim3(128), 0, s, g, xyz, perm, inv_mu, loc, ga, gr,
-                       AKK, vol, bad_cell);
+    const dim3 G(nblk(g.nc, 128)), B(128);
+    if (g.max_nv <= 4 && g.max_nf <= 4 && g.max_fk <= 3)  // tetrahedra
+        hipLaunchKernelGGL((gen_local_kernel<4, 4, 3>), G, B, 0, s, g, xyz, perm, inv_mu, loc, ga, gr, AKK, vol,
+                           bad_cell);
+    else if (g.max_nv <= 6 && g.max_nf <= 5)  // prisms, pyramids (and tetrahedra)
+        hipLaunchKernelGGL((gen_local_kernel<6, 5, kGenMaxFaceNodes>), G, B, 0, s, g, xyz, perm, inv_mu, loc, ga,
+                           gr, AKK, vol, bad_cell);
+    else
+        hipLaunchKernelGGL((gen_local_kernel<kGenMaxNodes, kGenMaxFaces, kGenMaxFaceNodes>), G, B, 0, s, g, xyz,
+                           perm, inv_mu, loc, ga, gr, AKK, vol, bad_cell);
     VAG_HIP(hipGetLastError());
 }
 void launch_gen_frac_local(hipStream_t s, const GenMesh &g, const double *xyz, const double *fwidth,

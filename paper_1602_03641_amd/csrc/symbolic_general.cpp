@@ -95,6 +95,9 @@ void build_symbolic_general(int64_t nn64, int64_t nc64, int64_t nface64, const i
         }
         if (G.cnode.size() - base < 4) throw Error(VAG_ERR_MESH, "cell " + std::to_string(K) + " has fewer than 4 nodes");
         G.cnode_ptr[K + 1] = (int32_t)G.cnode.size();
+        G.max_nv = std::max(G.max_nv, (int)(G.cnode.size() - base));
+        G.max_nf = std::max(G.max_nf, lf);
+        for (int f = 0; f < lf; ++f) G.max_fk = std::max(G.max_fk, (int)G.cface_k[kGenMaxFaces * (size_t)K + f]);
     }
     G.ncn = (int64_t)G.cnode.size();
 

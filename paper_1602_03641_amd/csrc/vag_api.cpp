@@ -195,8 +195,9 @@ struct vag_handle {
     DBuf<int64_t> g_loc_off, g_con_ptr, g_con, g_bcon, g_inc_ptr;
     DBuf<double> gloc, ga, gr, Fall;
     GenMesh gmesh() const {
-        return GenMesh{S.nc, S.nf, S.nn, g_cnode_ptr.p, g_cnode.p, g_cface_k.p, g_cface_loc.p, cell_frac.p,
-                       frac_cell.p, g_fnode_ptr.p, g_fnode.p, g_unk_off.p, g_loc_off.p, G.ncn};
+        return GenMesh{S.nc,        S.nf,      S.nn,      G.max_nv,      G.max_nf,      G.max_fk,
+                       g_cnode_ptr.p, g_cnode.p, g_cface_k.p, g_cface_loc.p, cell_frac.p, frac_cell.p,
+                       g_fnode_ptr.p, g_fnode.p, g_unk_off.p, g_loc_off.p, G.ncn};
     }
     GenInc ginc() const { return GenInc{S.nc, S.nf, S.nn, g_inc_ptr.p, g_inc_edge.p, g_inc_other.p, dirichlet.p}; }
     // the three flux sections (hexahedra: their own arrays)

@@ -188,6 +188,7 @@ struct GenSym {
     int64_t ncn = 0;                 // sum over cells of their node counts
     int64_t nfn = 0;                 // sum over fracture faces of their node counts
     int64_t nflux = 0;               // ncn + 2 nf + nfn: the flux array [cell-node | cell-face | face-node]
+    int max_nv = 0, max_nf = 0, max_fk = 0;  // the most nodes, faces and face nodes of a cell
     std::vector<int32_t> cnode_ptr;  // [nc + 1] cell -> its nodes, local order
     std::vector<int32_t> cnode;      // [ncn] global node indices
     std::vector<uint8_t> cface_k;    // [6 nc] node count of local face f (0: no such face)
@@ -496,6 +497,7 @@ void launch_transport_gather(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, 
 // gr their row sums at unk_off.
 struct GenMesh {
     int32_t nc, nf, nn;
+    int max_nv, max_nf, max_fk;  // the largest cell shape (sizes the local-matrix kernel's arrays)
     const int32_t *cnode_ptr, *cnode;
     const uint8_t *cface_k, *cface_loc;
     const int32_t *cell_frac, *frac_cell, *fnode_ptr, *fnode, *unk_off;
