@@ -583,16 +583,20 @@ __device__ __forceinline__ double upwind_row(const UpwindOp &T, const double *__
 }
 
 __global__ __launch_bounds__(256) void transport_step_kernel(UpwindOp T, const double *__restrict__ c_in,
-                                                             double *__restrict__ c_out, double theta) {
+                                                             double *__restrict__ c_out, double theta, int backward) {
     // block b runs on XCD b mod 8 (the hardware deals the blocks in turn);
     // item q of XCD x is its run of A slices and its run of B slices merged
     // in proportion: item q is an A slice iff floor((q+1) a / w) >
-    // floor(q a / w), and floor(q a / w) A slices come before it
+    // floor(q a / w), and floor(q a / w) A slices come before it.  Every
+    // other step sweeps each XCD's run backwards, so that it starts on the
+    // slices the previous step read last, which the last-level cache still
+    // holds.
     const int x = blockIdx.x & 7;
-    const int32_t q = 4 * (int32_t)(blockIdx.x >> 3) + (int32_t)(threadIdx.x >> 6);
+    const int32_t q0 = 4 * (int32_t)(blockIdx.x >> 3) + (int32_t)(threadIdx.x >> 6);
     const int32_t a = T.xlo[x + 1] - T.xlo[x], w = a + T.ylo[x + 1] - T.ylo[x];
     const int lane = threadIdx.x & (kSliceRows - 1);
-    if (q >= w) return;  // whole wavefronts
+    if (q0 >= w) return;  // whole wavefronts
+    const int32_t q = backward ? w - 1 - q0 : q0;
     const int32_t na = (int32_t)((int64_t)q * a / w);
     const int32_t sl = (int32_t)((int64_t)(q + 1) * a / w) > na ? T.xlo[x] + na : T.ylo[x] + (q - na);
     const int32_t t = sl * kSliceRows + lane;
@@ -956,12 +960,14 @@ void launch_xcd_split(hipStream_t s, int32_t nslice, int32_t sa, const int64_t *
     hipLaunchKernelGGL(xcd_split_kernel, dim3(1), dim3(64), 0, s, nslice, sa, slice_ptr, xlo);
     VAG_HIP(hipGetLastError());
 }
-void launch_transport_step(hipStream_t s, const UpwindOp &T, const double *c_in, double *c_out, double theta) {
+void launch_transport_step(hipStream_t s, const UpwindOp &T, const double *c_in, double *c_out, double theta,
+                           bool backward) {
     int32_t per_xcd = 0;  // blocks per XCD: the longest merged run, 4 slices per block
     for (int x = 0; x < 8; ++x)
         per_xcd = std::max(per_xcd, (T.xlo[x + 1] - T.xlo[x] + T.ylo[x + 1] - T.ylo[x] + 3) / 4);
     if (per_xcd <= 0) return;
-    hipLaunchKernelGGL(transport_step_kernel, dim3(8 * (unsigned)per_xcd), dim3(256), 0, s, T, c_in, c_out, theta);
+    hipLaunchKernelGGL(transport_step_kernel, dim3(8 * (unsigned)per_xcd), dim3(256), 0, s, T, c_in, c_out, theta,
+                       backward ? 1 : 0);
     VAG_HIP(hipGetLastError());
 }
 void launch_transport_gather(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,

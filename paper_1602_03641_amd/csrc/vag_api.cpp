@@ -1347,7 +1347,7 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
         VAG_HIP(hipEventRecord(h->ev[6], s));
         for (int64_t k = 0; k < N; ++k) {
             const double th = (k == N - 1) ? theta_last : 1.0;
-            launch_transport_step(s, h->upwind(), h->c_cur(), h->c_next(), th);
+            launch_transport_step(s, h->upwind(), h->c_cur(), h->c_next(), th, (k & 1) != 0);
             h->cur ^= 1;
         }
         VAG_HIP(hipEventRecord(h->ev[7], s));
@@ -1571,7 +1571,9 @@ vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms)
         const int64_t nrow = (int64_t)S.nc + S.nf + S.nn;
         if (kernel == VAG_KERNEL_TRANSPORT_STEP && (!h->have_c || !h->have_op))
             throw Error(VAG_ERR_STATE, "the transport step needs a transport call first");
+        int rep = 0;
         auto once = [&] {
+            ++rep;
             switch (kernel) {
                 case VAG_KERNEL_SPMV:  // the Krylov loop's SpMV (with its dot-product partials)
                     if (h->opt.precision == VAG_MIXED_IR && h->amg.have32)
@@ -1581,8 +1583,9 @@ vag_status vag_benchmark_kernel(vag_handle *h, int kernel, int reps, double *ms)
                         launch_pcg_spmv<double, double>(s, h->Asell(), h->x.p, h->q.p,
                                                         PcgParts{h->parts.p, pcg_grid(S.nunk)}, h->pcg.p + 1);
                     break;
-                case VAG_KERNEL_TRANSPORT_STEP:  // reads the current state, writes the spare buffer
-                    launch_transport_step(s, h->upwind(), h->c_cur(), h->c_next(), 1.0);
+                case VAG_KERNEL_TRANSPORT_STEP:  // reads the current state, writes the spare buffer;
+                    // the sweep direction alternates as in vag_transport
+                    launch_transport_step(s, h->upwind(), h->c_cur(), h->c_next(), 1.0, (rep & 1) == 0);
                     break;
                 case VAG_KERNEL_LOCAL:
                     if (h->general)

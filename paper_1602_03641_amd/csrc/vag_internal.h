@@ -463,7 +463,9 @@ struct UpwindOp {
 void launch_upwind_pack(hipStream_t s, const UpwindOp &T, uint16_t *tcol16, int32_t *tbase);
 // xlo[0..8] and ylo[0..8] (at xlo + 9) from slice_ptr (after the slice scan)
 void launch_xcd_split(hipStream_t s, int32_t nslice, int32_t sa, const int64_t *slice_ptr, int32_t *xlo);
-void launch_transport_step(hipStream_t s, const UpwindOp &T, const double *c_in, double *c_out, double theta);
+// backward: sweep each XCD's slices in reverse order (alternate steps)
+void launch_transport_step(hipStream_t s, const UpwindOp &T, const double *c_in, double *c_out, double theta,
+                           bool backward);
 // Peaceman wells (wells.hip).  wsrc[f] = c_inj Q^+ (tracer injected into face
 // f per unit time), wout[f] = Q^- (volume produced); the upwind operator's
 // injection entries point at the constant control volume (index nc + nf + nn,
