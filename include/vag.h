@@ -346,9 +346,10 @@ vag_status vag_set_fluxes(vag_handle *h, const double *F_cell, const double *F_c
  * at the face's concentration and counts in the face's CFL outflow.  Each
  * face is perforated at most once; wi >= 0; arrays of n values in mem,
  * copied.  n = 0 removes the wells.  Takes effect at the next
- * vag_solve_pressure.  VAG_ERR_ARG for a face out of range or perforated
- * twice, a negative WI or a value that is not finite; VAG_ERR_UNSUPPORTED
- * on a mesh without hex8. */
+ * vag_solve_pressure.  Hexahedral and general meshes alike: face[k] indexes
+ * the fracture faces in the order vag_fractures lists them.  VAG_ERR_ARG
+ * for a face out of range or perforated twice, a negative WI or a value that
+ * is not finite. */
 vag_status vag_set_wells(vag_handle *h, int64_t n, const int32_t *face, const double *wi, const double *p_w,
                          const double *q, const double *c_inj, vag_mem mem);
 /* Q_k of the last solve (or of vag_set_well_rates), n values. */

@@ -20,7 +20,11 @@ mix of these cells, in plain numpy (small meshes), following the same steps:
   nodes and fracture faces, the cell values by eq eqschurcell, the fluxes;
 * porous volumes with alpha_{K,s} = 1 / (2 |V_K|) and alpha_{sigma,s} =
   1 / (2 |V_sigma|) (reading C7: 1/16 and 1/8 on hexahedra and quadrangles);
-* the CFL bound and the explicit upwind steps of §3.2.2.
+* the CFL bound and the explicit upwind steps of §3.2.2;
+* Peaceman wells on fracture faces (§5.5): a well k perforating face sigma
+  brings the inflow Q_k = WI_k (p_w,k - u_sigma) + q_k into sigma's
+  conservation equation; in transport a producer (Q_k < 0) takes c_sigma |Q_k|
+  out of sigma and counts in its outflow, an injector brings c_inj,k Q_k.
 
 Cells are given as tuples of node indices in VTK order: 4 (tetrahedron:
 base triangle, apex), 6 (prism: bottom triangle, top triangle above it) or
@@ -46,7 +50,7 @@ class Mesh:
     """A mesh of general cells with fracture faces and boundary data."""
 
     def __init__(self, xyz, cells, perm, poro, frac_faces=(), frac_width=(), frac_perm=(), frac_poro=(),
-                 dirichlet=None, p_bar=None, c_bar=None, mu=1.0):
+                 dirichlet=None, p_bar=None, c_bar=None, mu=1.0, wells=None):
         self.xyz = np.asarray(xyz, float)
         self.cells = [tuple(int(v) for v in c) for c in cells]
         self.perm = np.asarray(perm, float).reshape(-1, 6)
@@ -60,12 +64,19 @@ class Mesh:
         self.p_bar = np.zeros(nn) if p_bar is None else np.asarray(p_bar, float)
         self.c_bar = np.zeros(nn) if c_bar is None else np.asarray(c_bar, float)
         self.mu = float(mu)
+        w = wells or {}
+        self.well_face = np.asarray(w.get("face", []), np.int64)
+        self.well_wi, self.well_pw, self.well_q, self.well_cinj = (
+            np.asarray(w.get(k, []), float) for k in ("wi", "pw", "q", "cinj"))
+        if len(set(self.well_face.tolist())) != len(self.well_face) or np.any(self.well_face < 0) or \
+                np.any(self.well_face >= len(self.frac)):
+            raise ValueError("a well must perforate a distinct fracture face")
 
     @classmethod
     def from_problem(cls, p):
         """The hexahedral problems of the synthetic generators."""
         return cls(p.xyz, p.hex8, p.perm, p.poro, np.asarray(p.frac_nodes).reshape(-1, 4), p.frac_width,
-                   p.frac_perm, p.frac_poro, p.dirichlet, p.p_bar, p.c_bar, p.mu)
+                   p.frac_perm, p.frac_poro, p.dirichlet, p.p_bar, p.c_bar, p.mu, getattr(p, "wells", None))
 
 
 def _tensor(p6):
@@ -227,6 +238,11 @@ def system(m):
                     vals.append(A5[i, j])
                 else:
                     b[ui] -= A5[i, j] * m.p_bar[ids[j]]
+    for k, f in enumerate(m.well_face):  # Q_k = WI (p_w - u_sigma) + q enters sigma's row
+        rows.append(nfree + f)
+        cols.append(nfree + f)
+        vals.append(m.well_wi[k])
+        b[nfree + f] += m.well_wi[k] * m.well_pw[k] + m.well_q[k]
     A = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
     A.sum_duplicates()
     return A, b, dict(cell_frac=cell_frac, frac_cells=frac_cells, node_unk=node_unk, nfree=nfree,
@@ -236,7 +252,7 @@ def system(m):
 def solve_darcy(m):
     """Pressures (nodes, cells, fracture faces) and fluxes: F_cell[K] lists
     F_{K,s} per cell node then F_{K,sigma} per fracture face of K; F_frac[f]
-    lists F_{sigma,s} per face node."""
+    lists F_{sigma,s} per face node; well_rate[k] = Q_k."""
     A, b, d = system(m)
     x = spla.spsolve(A.tocsc(), b) if A.shape[0] else np.zeros(0)
     nn, nf = len(m.xyz), len(m.frac)
@@ -258,7 +274,9 @@ def solve_darcy(m):
         A5, _ = d["fmat"][f]
         us = u_node[list(m.frac[f])]
         F_frac.append(A5[1:, 1:] @ (u_frac[f] - us))
-    return dict(u_node=u_node, u_cell=u_cell, u_frac=u_frac, F_cell=F_cell, F_frac=F_frac, A=A, b=b, x=x,
+    well_rate = m.well_wi * (m.well_pw - u_frac[m.well_face]) + m.well_q
+    return dict(u_node=u_node, u_cell=u_cell, u_frac=u_frac, F_cell=F_cell, F_frac=F_frac, well_rate=well_rate,
+                A=A, b=b, x=x,
                 cell_frac=d["cell_frac"], frac_cells=d["frac_cells"], local=d["local"], fmat=d["fmat"])
 
 
@@ -333,7 +351,8 @@ def _edges(m, sol):
 
 def cfl_dt(m, sol, phi, cfl):
     """cfl x min over control volumes of porous volume / outgoing flux (the
-    Dirichlet nodes excluded)."""
+    Dirichlet nodes excluded); a producing well's |Q_k| counts as outflow of
+    its face."""
     nc, nf, nn = len(m.cells), len(m.frac), len(m.xyz)
     out = np.zeros(nc + nf + nn)
     for i, j, F in _edges(m, sol):
@@ -341,26 +360,40 @@ def cfl_dt(m, sol, phi, cfl):
             out[i] += F
         else:
             out[j] -= F
+    for f, Q in zip(m.well_face, _well_rates(m, sol)):
+        out[nc + f] += max(-Q, 0.0)
     vol = np.concatenate([phi["phi_cell"], phi["phi_frac"], phi["phi_node"]])
     ok = out > 0
     ok[nc + nf:] &= m.dirichlet == 0
     return cfl * float(np.min(vol[ok] / out[ok]))
 
 
+def _well_rates(m, sol):
+    Q = sol.get("well_rate")
+    if len(m.well_face) and Q is None:
+        raise ValueError("the mesh has wells: the fluxes need their well_rate")
+    return np.zeros(0) if Q is None else np.asarray(Q, float)
+
+
 def transport(m, sol, phi, dt, n_steps):
-    """Explicit upwind steps from c = 0 (Dirichlet nodes at c_bar)."""
+    """Explicit upwind steps from c = 0 (Dirichlet nodes at c_bar); wells as
+    sources c_inj Q^+ and sinks c_sigma Q^- of their faces."""
     nc, nf, nn = len(m.cells), len(m.frac), len(m.xyz)
     c = np.zeros(nc + nf + nn)
     dn = np.where(m.dirichlet == 1)[0]
     c[nc + nf + dn] = m.c_bar[dn]
     vol = np.concatenate([phi["phi_cell"], phi["phi_frac"], phi["phi_node"]])
     edges = _edges(m, sol)
+    wrate = _well_rates(m, sol)
     for _ in range(n_steps):
         s = np.zeros_like(c)
         for i, j, F in edges:
             H = c[i] * max(F, 0.0) + c[j] * min(F, 0.0)
             s[i] += H
             s[j] -= H
+        for k, f in enumerate(m.well_face):
+            Q = wrate[k]
+            s[nc + f] += c[nc + f] * max(-Q, 0.0) - m.well_cinj[k] * max(Q, 0.0)
         upd = np.ones(len(c), bool)
         upd[nc + nf + dn] = False
         c[upd] -= dt / vol[upd] * s[upd]

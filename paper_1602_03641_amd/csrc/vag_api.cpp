@@ -1035,7 +1035,6 @@ vag_status vag_set_wells(vag_handle *h, int64_t n, const int32_t *face, const do
         const Symbolic &S = h->S;
         hipStream_t s = h->stream;
         if (n > 0 && (!face || !wi || !p_w || !q || !c_inj)) throw Error(VAG_ERR_ARG, "null well array");
-        if (n > 0 && h->general) throw Error(VAG_ERR_UNSUPPORTED, "wells take hex8 meshes");
         if (n > INT32_MAX) throw Error(VAG_ERR_ARG, "too many wells");
         const std::vector<int32_t> f = host_copy(face, (size_t)n, mem, s);
         const std::vector<double> a = host_copy(wi, (size_t)n, mem, s), b = host_copy(p_w, (size_t)n, mem, s),

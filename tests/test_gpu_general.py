@@ -11,7 +11,10 @@ of the scheme on general cells (oracle/general_cells.py), through the C-ABI.
 - transport on the oracle's fluxes: concentrations max-abs <= 1e-12;
 - affine pressures exact on a jittered anisotropic tetrahedral mesh;
 - a hexahedral mesh given by its faces equals the hex8 path (system entry by
-  entry with the fracture faces kept, pressures, fluxes, transport).
+  entry with the fracture faces kept, pressures, fluxes, transport);
+- Peaceman wells on the fracture faces of tetrahedral and prismatic meshes
+  (§5.5): pressures, fluxes and well rates against the oracle, then the time
+  step and transport on the oracle's fluxes and well rates.
 Meshes are jittered, faces listed in random orientation and order per cell.
 """
 import numpy as np
@@ -38,7 +41,7 @@ def rel_l2(a, b):
 
 def oracle_mesh(p):
     return gc.Mesh(p.xyz, p.cells, p.perm, p.poro, p.frac_faces(), p.frac_width, p.frac_perm, p.frac_poro,
-                   p.dirichlet, p.p_bar, p.c_bar, p.mu)
+                   p.dirichlet, p.p_bar, p.c_bar, p.mu, p.wells)
 
 
 def flux_maps(p, sol):
@@ -219,6 +222,47 @@ def test_hex_faces_equal_hex8_path():
         assert np.abs(cg_[k] - c8[k]).max() <= 1e-12, k
     h8.close()
     hg.close()
+
+
+@pytest.mark.parametrize("kind,dims,seed", [("prism", (10, 8, 6), 21), ("tet", (8, 7, 6), 22)])
+@pytest.mark.parametrize("precond", ["jacobi", "amg"])
+def test_general_wells_parity(kind, dims, seed, precond):
+    """Two rate injectors and two pressure wells on a fracture plane of a
+    jittered anisotropic mesh."""
+    p = synth.add_wells(synth.general_problem(kind, dims, seed, frac_plane=dims[0] // 2, ratio=1e3, n_steps=40),
+                        seed, n_inj=2, n_prod=2)
+    h, info, vag = gpu(p, precond={"jacobi": 0, "amg": 1}[precond])
+    print(f"{kind}{dims} wells: {p.n_cells} cells, {p.n_frac} fracture faces, {info['iterations']} iterations")
+    assert info["status"] in (0, 1) and info["rel_residual"] <= 1e-11
+    m = oracle_mesh(p)
+    assert len(m.well_face) == 4
+    sol = gc.solve_darcy(m)
+    g = vag.to_numpy(h.pressure())
+    for k in ("u_node", "u_cell", "u_frac"):
+        assert rel_l2(g[k], sol[k]) <= 1e-8, k
+    Q, Qo = h.well_rates(), sol["well_rate"]
+    assert np.abs(Q - Qo).max() <= 1e-8 * np.abs(Qo).max()
+    assert np.all(Qo[:2] > 0) and np.all(Qo[2:] < 0)  # the producers produce
+    of = oracle_fluxes_flat(p, sol)
+    gf = vag.to_numpy(h.fluxes())
+    scale = max(np.abs(of["F_cell"]).max(), np.abs(of["F_frac"]).max(initial=0.0))
+    for k in ("F_cell", "F_cell_frac", "F_frac"):
+        assert np.abs(gf[k] - of[k]).max(initial=0.0) <= 1e-8 * scale, k
+    phi = gc.porous_volumes(m, sol)
+    t0 = h.transport(n_steps=0)
+    assert t0["dt"] == pytest.approx(gc.cfl_dt(m, sol, phi, p.cfl), rel=1e-8)
+    # transport on the oracle's fluxes and well rates
+    h.set_fluxes(of)
+    h.set_well_rates(Qo)
+    np.testing.assert_array_equal(h.well_rates(), Qo)
+    t = h.transport(n_steps=p.n_steps)
+    assert t["dt"] == pytest.approx(gc.cfl_dt(m, sol, phi, p.cfl), rel=1e-13)
+    oc = gc.transport(m, sol, phi, t["dt"], p.n_steps)
+    gcn = vag.to_numpy(h.concentration())
+    for k in ("c_cell", "c_frac", "c_node"):
+        assert np.abs(gcn[k] - oc[k]).max(initial=0.0) <= 1e-12, k
+    assert gcn["c_frac"][p.wells["face"][0]] > 0.05  # the injected tracer arrived
+    h.close()
 
 
 def test_general_noalloc_unsupported():
