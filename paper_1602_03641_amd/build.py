@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvag.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["symbolic.cpp", "symbolic_general.cpp", "general.hip", "assemble.hip", "krylov.hip", "gmres.hip", "bicgstab.hip", "ilu.hip", "amg.hip", "amg_classical.hip", "amg_host.cpp", "transport.hip", "wells.hip", "vag_api.cpp", "server.cpp"]
+SOURCES = ["symbolic.cpp", "symbolic_general.cpp", "general.hip", "assemble.hip", "krylov.hip", "gmres.hip", "bicgstab.hip", "ilu.hip", "amg.hip", "amg_classical.hip", "amg_host.cpp", "transport.hip", "wells.hip", "pattern.hip", "vag_api.cpp", "server.cpp"]
 ARCH = os.environ.get("VAG_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

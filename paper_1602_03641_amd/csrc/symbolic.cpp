@@ -82,7 +82,27 @@ inline void sort_row(int32_t *b, int32_t *e) {
 }
 }  // namespace
 
-void finish_symbolic_pattern(Symbolic &S, const std::vector<const int32_t *> *row_src) {
+namespace {
+// the rows in the system numbering, sorted: new row r is natural row
+// order[r], whose columns (natural numbering) src(o) lists
+template <class Src>
+uvector<int32_t> sorted_rows(const Symbolic &S, const std::vector<int32_t> &rp, const Src &src) {
+    const int32_t n = S.nunk;
+    uvector<int32_t> cl((size_t)rp[n]);
+    parallel_chunks(n, [&](int, int64_t r0, int64_t r1) {
+        for (int32_t r = (int32_t)r0; r < (int32_t)r1; ++r) {
+            const int32_t *in = src(S.sys_old[r]);
+            int32_t *out = cl.data() + rp[r];
+            const int32_t len = rp[r + 1] - rp[r];
+            for (int32_t k = 0; k < len; ++k) out[k] = S.sys_new[in[k]];
+            sort_row(out, out + len);
+        }
+    });
+    return cl;
+}
+}  // namespace
+
+void finish_symbolic_pattern(Symbolic &S, const std::vector<const int32_t *> *row_src, bool columns) {
     const int32_t nn = S.nn, nf = S.nf, nfree = S.nfree;
     // Renumber the system rows so that, inside windows of kSortWindow rows
     // (node rows and face rows apart), longer rows come first (stable):
@@ -115,22 +135,20 @@ void finish_symbolic_pattern(Symbolic &S, const std::vector<const int32_t *> *ro
         S.sys_old.assign(order.begin(), order.end());  // new row -> old row
         S.sys_new.assign(n, -1);                        // old row -> new row
         for (int32_t r = 0; r < n; ++r) S.sys_new[order[r]] = r;
-        // pattern in the new numbering
+        // row pointers in the new numbering
         std::vector<int32_t> rp(n + 1);
         rp[0] = 0;
         for (int32_t r = 0; r < n; ++r) rp[r + 1] = rp[r] + len(order[r]);
-        uvector<int32_t> cl((size_t)rp[n]);
-        parallel_chunks(n, [&](int, int64_t r0, int64_t r1) {
-            for (int32_t r = (int32_t)r0; r < (int32_t)r1; ++r) {
-                const int32_t o = order[r];
-                const int32_t *src = row_src ? (*row_src)[o] : S.col.data() + S.row_ptr[o];
-                int32_t *out = cl.data() + rp[r];
-                for (int32_t k = 0; k < len(o); ++k) out[k] = S.sys_new[src[k]];
-                sort_row(out, out + len(o));
-            }
-        });
+        if (columns) {
+            uvector<int32_t> cl = row_src ? sorted_rows(S, rp, [&](int32_t o) { return (*row_src)[o]; })
+                                          : sorted_rows(S, rp, [&](int32_t o) { return S.col.data() + S.row_ptr[o]; });
+            S.col.swap(cl);
+            S.col_on_host = true;
+        } else {
+            S.col = uvector<int32_t>();  // the device builds the columns
+            S.col_on_host = false;
+        }
         S.row_ptr.swap(rp);
-        S.col.swap(cl);
         for (auto &u : S.node_unk)
             if (u >= 0) u = S.sys_new[u];
         for (auto &u : S.frac_unk)
@@ -167,7 +185,8 @@ void finish_symbolic_pattern(Symbolic &S, const std::vector<const int32_t *> *ro
 }
 
 void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex8,
-                    const int32_t *frac_nodes, const uint8_t *dirichlet, bool eliminate, Symbolic &S) {
+                    const int32_t *frac_nodes, const uint8_t *dirichlet, bool eliminate, Symbolic &S,
+                    bool rows_on_device) {
     if (nn64 <= 0 || nc64 <= 0 || nf64 < 0 || nn64 >= INT32_MAX || nc64 >= INT32_MAX / 8 ||
         nf64 >= INT32_MAX / 4)
         throw Error(VAG_ERR_ARG, "mesh sizes out of range");
@@ -176,9 +195,19 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
     S.nc = nc;
     S.nf = nf;
 
-    for (int64_t i = 0; i < 8 * (int64_t)nc; ++i)
-        if (hex8[i] < 0 || hex8[i] >= nn)
-            throw Error(VAG_ERR_ARG, "hex8 node index out of range at cell " + std::to_string(i / 8));
+    {
+        // the first cell (in index order) naming a node out of range
+        std::vector<int64_t> bad((size_t)chunk_count(nc), INT64_MAX);
+        parallel_chunks(nc, [&](int t, int64_t k0, int64_t k1) {
+            for (int64_t i = 8 * k0; i < 8 * k1; ++i)
+                if (hex8[i] < 0 || hex8[i] >= nn) {
+                    bad[t] = i / 8;
+                    return;
+                }
+        });
+        const int64_t K = *std::min_element(bad.begin(), bad.end());
+        if (K != INT64_MAX) throw Error(VAG_ERR_ARG, "hex8 node index out of range at cell " + std::to_string(K));
+    }
     for (int64_t i = 0; i < 4 * (int64_t)nf; ++i)
         if (frac_nodes[i] < 0 || frac_nodes[i] >= nn)
             throw Error(VAG_ERR_ARG, "fracture face node index out of range at face " + std::to_string(i / 4));
@@ -190,47 +219,47 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
     S.node_cell.resize(S.node_cell_ptr[nn]);
     {
         std::vector<int32_t> fill(S.node_cell_ptr.begin(), S.node_cell_ptr.end() - 1);
-        for (int32_t K = 0; K < nc; ++K)
-            for (int a = 0; a < 8; ++a) S.node_cell[fill[hex8[8 * (int64_t)K + a]]++] = K * 8 + a;
+        for (int64_t i = 0; i < 8 * (int64_t)nc; ++i) S.node_cell[fill[hex8[i]]++] = (int32_t)i;  // K * 8 + a
     }
 
-    // fracture faces: match against cell faces
+    // fracture faces: each matched against the faces of the cells around its
+    // first node (cells in ascending order, then local faces in order)
     S.frac_node.assign(nn, 0);
     for (int64_t i = 0; i < 4 * (int64_t)nf; ++i) S.frac_node[frac_nodes[i]] = 1;
-    std::unordered_map<Key4, int32_t, Key4Hash> fmap;
-    fmap.reserve((size_t)nf * 2 + 1);
-    for (int32_t f = 0; f < nf; ++f) {
-        const int32_t *fn = frac_nodes + 4 * (int64_t)f;
-        Key4 k = sorted_key(fn);
-        if (k.v[0] == k.v[1] || k.v[1] == k.v[2] || k.v[2] == k.v[3])
-            throw Error(VAG_ERR_ARG, "fracture face " + std::to_string(f) + " repeats a node");
-        if (!fmap.emplace(k, f).second)
-            throw Error(VAG_ERR_ARG, "fracture face " + std::to_string(f) + " is listed twice");
+    {
+        std::unordered_map<Key4, int32_t, Key4Hash> fmap;
+        fmap.reserve((size_t)nf * 2 + 1);
+        for (int32_t f = 0; f < nf; ++f) {
+            const int32_t *fn = frac_nodes + 4 * (int64_t)f;
+            Key4 k = sorted_key(fn);
+            if (k.v[0] == k.v[1] || k.v[1] == k.v[2] || k.v[2] == k.v[3])
+                throw Error(VAG_ERR_ARG, "fracture face " + std::to_string(f) + " repeats a node");
+            if (!fmap.emplace(k, f).second)
+                throw Error(VAG_ERR_ARG, "fracture face " + std::to_string(f) + " is listed twice");
+        }
     }
     S.fmask.assign(nc, 0);
     S.cell_frac.assign(6 * (size_t)nc, -1);
     S.frac_cell.assign(2 * (size_t)nf, -1);
-    if (nf > 0) {
-        for (int32_t K = 0; K < nc; ++K) {
+    for (int32_t f = 0; f < nf; ++f) {
+        const int32_t *fn = frac_nodes + 4 * (int64_t)f;
+        const Key4 key = sorted_key(fn);
+        int32_t prev = -1;
+        for (int32_t q = S.node_cell_ptr[fn[0]]; q < S.node_cell_ptr[fn[0] + 1]; ++q) {
+            const int32_t K = S.node_cell[q] >> 3;
+            if (K == prev) continue;  // a cell that names the node twice
+            prev = K;
             const int32_t *cn = hex8 + 8 * (int64_t)K;
             for (int lf = 0; lf < 6; ++lf) {
-                int32_t q[4];
-                bool all = true;
-                for (int i = 0; i < 4; ++i) {
-                    q[i] = cn[hexf(lf, i)];
-                    all &= S.frac_node[q[i]] != 0;
-                }
-                if (!all) continue;
-                auto it = fmap.find(sorted_key(q));
-                if (it == fmap.end()) continue;
-                int32_t f = it->second;
-                if (!same_cycle(q, frac_nodes + 4 * (int64_t)f))
-                    throw Error(VAG_ERR_MESH, "fracture face " + std::to_string(f) +
-                                                  " nodes are not in cyclic order");
-                int side = S.frac_cell[2 * (size_t)f] < 0 ? 0 : (S.frac_cell[2 * (size_t)f + 1] < 0 ? 1 : 2);
+                int32_t c[4];
+                for (int i = 0; i < 4; ++i) c[i] = cn[hexf(lf, i)];
+                if (!(sorted_key(c) == key)) continue;
+                if (!same_cycle(c, fn))
+                    throw Error(VAG_ERR_MESH, "fracture face " + std::to_string(f) + " nodes are not in cyclic order");
+                const int side = S.frac_cell[2 * (size_t)f] < 0 ? 0 : (S.frac_cell[2 * (size_t)f + 1] < 0 ? 1 : 2);
                 if (side == 2)
                     throw Error(VAG_ERR_MESH, "fracture face " + std::to_string(f) + " has more than two cells");
-                S.frac_cell[2 * (size_t)f + side] = K;  // cells visited in ascending order
+                S.frac_cell[2 * (size_t)f + side] = K;
                 S.cell_frac[6 * (size_t)K + lf] = f;
                 S.fmask[K] |= (uint8_t)(1u << lf);
             }
@@ -265,19 +294,15 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
         while (uf[f] != f) f = uf[f] = uf[uf[f]];
         return f;
     };
-    for (int32_t K = 0; K < nc; ++K) {
-        int32_t first = -1;
-        for (int lf = 0; lf < 6; ++lf) {
-            if (!(S.fmask[K] >> lf & 1)) continue;
-            const int32_t f = S.cell_frac[6 * (size_t)K + lf];
-            if (first < 0) {
-                first = f;
-            } else {
-                const int32_t a = find(first), b = find(f);
-                if (a != b) uf[std::max(a, b)] = std::min(a, b);
-            }
+    for (int32_t f = 0; f < nf; ++f)
+        for (int side = 0; side < 2; ++side) {
+            const int32_t K = S.frac_cell[2 * (size_t)f + side];
+            if (K < 0) continue;
+            int lf = 0;
+            while (!(S.fmask[K] >> lf & 1)) ++lf;  // K's first fracture face
+            const int32_t a = find(S.cell_frac[6 * (size_t)K + lf]), b = find(f);
+            if (a != b) uf[std::max(a, b)] = std::min(a, b);
         }
-    }
 
     // free nodes first
     S.node_unk.assign(nn, -1);
@@ -400,7 +425,8 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
         }
     }
     // node (system unknown) -> eliminated groups, for the fill of the pattern
-    std::vector<int32_t> ngp_ptr(nfree + 1, 0), ngp;
+    std::vector<int32_t> &ngp_ptr = S.node_grp_ptr, &ngp = S.node_grp;
+    ngp_ptr.assign(nfree + 1, 0);
     for (int32_t q = 0; q < (int32_t)S.grp_node.size(); ++q) ngp_ptr[S.grp_node[q] + 1]++;
     for (int32_t u = 0; u < nfree; ++u) ngp_ptr[u + 1] += ngp_ptr[u];
     ngp.resize(ngp_ptr[nfree]);
@@ -409,6 +435,9 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
         for (int32_t G = 0; G < S.ngroup; ++G)
             for (int32_t q = S.grp_nptr[G]; q < S.grp_nptr[G + 1]; ++q) ngp[fill[S.grp_node[q]]++] = G;
     }
+    S.face_grp = std::move(face_grp);
+    S.face_loc = std::move(face_loc);
+    if (rows_on_device) return;  // finish_symbolic_lengths follows, with the device's row lengths
 
     // unknowns of each cell: 8 nodes, then its fracture faces by local face
     uvector<int32_t> cu(14 * (size_t)nc);
@@ -502,8 +531,19 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
     S.nnz = S.row_ptr[S.nunk];
 
     finish_symbolic_pattern(S, &row_src);
-    S.face_grp = std::move(face_grp);
-    S.face_loc = std::move(face_loc);
+}
+
+void finish_symbolic_lengths(Symbolic &S, const int32_t *len) {
+    const int32_t n = S.nunk;
+    S.row_ptr.assign((size_t)n + 1, 0);
+    int64_t total = 0;
+    for (int32_t r = 0; r < n; ++r) {
+        total += len[r];
+        if (len[r] < 1 || total >= INT32_MAX) throw Error(VAG_ERR_UNSUPPORTED, "system has more than 2^31 nonzeros");
+        S.row_ptr[r + 1] = (int32_t)total;
+    }
+    S.nnz = total;
+    finish_symbolic_pattern(S, nullptr, false);
 }
 
 }  // namespace vag

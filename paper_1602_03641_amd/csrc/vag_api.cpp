@@ -757,6 +757,82 @@ vag_status vag_default_options(vag_options *o) {
     return VAG_OK;
 }
 
+namespace {
+// The system pattern of a hexahedral mesh, built on the device from what the
+// host symbolic phase left (natural numbering): row bounds, scan, rows and
+// their lengths; the host then renumbers the rows from the lengths alone
+// (finish_symbolic_lengths), and the rows are mapped and sorted into rp/cl
+// (CSR, system numbering).  Needs h->hex8 and the node -> cell lists on the
+// device; uploads fmask, cell_frac and frac_cell for good.
+void device_pattern(vag_handle *h, DBuf<int32_t> &rp, DBuf<int32_t> &cl) {
+    Symbolic &S = h->S;
+    hipStream_t s = h->stream;
+    const int32_t n = S.nunk;
+    upload_vec(h, h->fmask, S.fmask);
+    upload_vec(h, h->cell_frac, S.cell_frac);
+    upload_vec(h, h->frac_cell, S.frac_cell);
+    std::vector<int32_t> len((size_t)n);
+    DBuf<int32_t> raw;
+    DBuf<int64_t> off;
+    if (n > 0) {
+        DBuf<int32_t> nu, fu, ngp_ptr, ngp, gnp, gn, ub, dlen;
+        upload_vec(h, nu, S.node_unk);
+        upload_vec(h, fu, S.frac_unk);
+        upload_vec(h, ngp_ptr, S.node_grp_ptr);
+        upload_vec(h, ngp, S.node_grp);
+        upload_vec(h, gnp, S.grp_nptr);
+        upload_vec(h, gn, S.grp_node);
+        const PatArgs g{S.nn,     S.nf,        n,         h->hex8.p,       h->node_cell_ptr.p,
+                        h->node_cell.p, nu.p,  fu.p,      h->cell_frac.p,  h->frac_cell.p,
+                        h->fmask.p, ngp_ptr.p, ngp.p,     gnp.p,           gn.p};
+        ub.alloc(n, h->tr);
+        dlen.alloc(n, h->tr);
+        off.alloc((size_t)n + 1, h->tr);
+        launch_pattern_bound(s, g, ub.p);
+        launch_slice_scan(s, n, ub.p, 1, off.p, nullptr, nullptr);
+        int64_t total = 0;
+        VAG_HIP(hipMemcpyAsync(&total, off.p + n, sizeof total, hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipStreamSynchronize(s));
+        raw.alloc((size_t)std::max<int64_t>(total, 1), h->tr);
+        launch_pattern_rows(s, g, off.p, raw.p, dlen.p);
+        VAG_HIP(hipMemcpyAsync(len.data(), dlen.p, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        VAG_HIP(hipStreamSynchronize(s));
+    }
+    finish_symbolic_lengths(S, len.data());
+    upload_vec(h, rp, S.row_ptr);
+    cl.alloc((size_t)std::max<int64_t>(S.nnz, 1), h->tr);
+    if (n > 0) {
+        DBuf<int32_t> so, sn;
+        upload_vec(h, so, S.sys_old);
+        upload_vec(h, sn, S.sys_new);
+        launch_pattern_sort(s, n, rp.p, so.p, off.p, raw.p, sn.p, cl.p);
+        VAG_HIP(hipStreamSynchronize(s));  // before the temporaries go
+    }
+}
+
+// The sorted CSR columns on the host for the few host consumers (the
+// block-ILU build, the system export), read back from the sliced-ELL columns
+// where the device built the pattern.
+void host_pattern(vag_handle *h) {
+    Symbolic &S = h->S;
+    if (S.col_on_host) return;
+    const int32_t n = S.nunk;
+    std::vector<int32_t> sc((size_t)std::max<int64_t>(S.sell_ptr.back(), 1)), rl((size_t)std::max(n, 1));
+    VAG_HIP(hipMemcpyAsync(sc.data(), h->sell_col.p, sc.size() * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    VAG_HIP(hipMemcpyAsync(rl.data(), h->row_len.p, rl.size() * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    VAG_HIP(hipStreamSynchronize(h->stream));
+    uvector<int32_t> col((size_t)S.nnz);
+    for (int32_t r = 0; r < n; ++r) {
+        const int32_t len = S.row_ptr[r + 1] - S.row_ptr[r];
+        if (rl[r] != len) throw Error(VAG_ERR_HIP, "device pattern does not match its row lengths");
+        const int64_t base = S.sell_ptr[r / kSliceRows] + r % kSliceRows;
+        for (int32_t k = 0; k < len; ++k) col[(size_t)S.row_ptr[r] + k] = sc[base + (int64_t)k * kSliceRows];
+    }
+    S.col.swap(col);
+    S.col_on_host = true;
+}
+}  // namespace
+
 vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag_rock *rock, const vag_bc *bc,
                       const vag_options *opt, vag_mem mem, void *hip_stream, vag_handle **out) {
     if (!out) return VAG_ERR_ARG;
@@ -779,13 +855,14 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         if (nn <= 0 || nc <= 0 || nf < 0) throw Error(VAG_ERR_ARG, "empty mesh");
         auto dir = host_copy(bc->node_dirichlet, (size_t)nn, mem, h->stream);
         h->general = mesh->hex8 == nullptr;
+        DBuf<int32_t> pat_rp, pat_cl;  // the system pattern (CSR), for the sliced-ELL columns
         if (!h->general) {
             auto hex8 = host_copy(mesh->hex8, 8 * (size_t)nc, mem, h->stream);
             if (nf && !frac->face_nodes) throw Error(VAG_ERR_ARG, "hex8 meshes give fracture faces by face_nodes");
             std::vector<int32_t> fnodes =
                 nf ? host_copy(frac->face_nodes, 4 * (size_t)nf, mem, h->stream) : std::vector<int32_t>();
             build_symbolic(nn, nc, nf, hex8.data(), fnodes.data(), dir.data(), h->opt.eliminate_frac_faces != 0,
-                           h->S);
+                           h->S, true);
             upload_vec(h, h->hex8, hex8);
             upload_vec(h, h->frac_nodes, fnodes);
             upload_vec(h, h->frac_slot, h->S.frac_slot);
@@ -793,6 +870,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
             upload_vec(h, h->node_cell, h->S.node_cell);
             upload_vec(h, h->node_frac_ptr, h->S.node_frac_ptr);
             upload_vec(h, h->node_frac, h->S.node_frac);
+            device_pattern(h, pat_rp, pat_cl);
         } else {
             if (!mesh->cell_face_ptr || !mesh->cell_faces || !mesh->face_node_ptr || !mesh->face_nodes ||
                 mesh->n_faces <= 0)
@@ -844,9 +922,13 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
 
         upload(h, h->xyz, mesh->node_xyz, 3 * (size_t)nn, mem);
         upload_vec(h, h->dirichlet, dir);
-        upload_vec(h, h->fmask, S.fmask);
-        upload_vec(h, h->cell_frac, S.cell_frac);
-        upload_vec(h, h->frac_cell, S.frac_cell);
+        if (h->general) {
+            upload_vec(h, h->fmask, S.fmask);
+            upload_vec(h, h->cell_frac, S.cell_frac);
+            upload_vec(h, h->frac_cell, S.frac_cell);
+            upload_vec(h, pat_rp, S.row_ptr);
+            upload_vec(h, pat_cl, S.col);
+        }
         upload_vec(h, h->node_unk, S.node_unk);
         upload_vec(h, h->frac_node, S.frac_node);
         upload_vec(h, h->sell_ptr, S.sell_ptr);
@@ -863,9 +945,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         upload_vec(h, h->grp_poff, S.grp_poff);
         {
             // sliced-ELL columns from the CSR pattern, on the device
-            DBuf<int32_t> rp, cl;
-            upload_vec(h, rp, S.row_ptr);
-            upload_vec(h, cl, S.col);
+            DBuf<int32_t> &rp = pat_rp, &cl = pat_cl;
             const int64_t nslice = (int64_t)S.sell_ptr.size() - 1;
             h->sell_col.alloc(std::max<int64_t>(S.sell_ptr.back(), 1), h->tr);
             h->row_len.alloc(std::max(S.nunk, 1), h->tr);
@@ -877,6 +957,8 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
             launch_sell_pack(h->stream, S.nunk, h->sell_ptr.p, h->sell_col.p, h->row_len.p, h->sell_col16.p,
                              h->sell_cbase.p);
             VAG_HIP(hipStreamSynchronize(h->stream));
+            rp.release();
+            cl.release();
         }
         h->Gb.alloc(std::max<int64_t>(S.grp_off.back(), 1), h->tr);
 
@@ -1173,7 +1255,10 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
             if (h->opt.precision == VAG_MIXED) h->amg.make_fp32(s, h->tr, nullptr);
         } else if (h->opt.precond == VAG_PC_BJILU0) {
             const int B = h->opt.ilu_block_rows > 0 ? h->opt.ilu_block_rows : kIluDefaultBlock;
-            if (!h->ilu.ready(B)) h->ilu.build(s, h->tr, S, B);
+            if (!h->ilu.ready(B)) {
+                host_pattern(h);
+                h->ilu.build(s, h->tr, S, B);
+            }
             if (!h->ilu_bad.p) h->ilu_bad.alloc(1, h->tr);
             VAG_HIP(hipMemsetAsync(h->ilu_bad.p, 0, sizeof(int), s));
             h->ilu.factor(s, h->A.p, h->ilu_bad.p);
@@ -1524,6 +1609,7 @@ vag_status vag_get_system(vag_handle *h, int64_t *row_ptr, int64_t *col, double 
     if (!h) return VAG_ERR_ARG;
     return guard(h, [&] {
         if (!h->solved) throw Error(VAG_ERR_STATE, "no pressure solve yet");
+        host_pattern(h);
         const Symbolic &S = h->S;
         const int32_t n = S.nunk;
         std::vector<double> sv(h->A.n), bv(std::max(n, 1));

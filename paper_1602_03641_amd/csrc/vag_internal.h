@@ -159,8 +159,15 @@ struct Symbolic {
     std::vector<uint8_t> frac_node;    // [nn] node of some fracture face
     std::vector<int32_t> node_cell_ptr, node_cell;  // node -> cell*8+slot, ascending
     std::vector<int32_t> node_frac_ptr, node_frac;  // node -> frac*4+i, ascending
-    std::vector<int32_t> row_ptr;                    // CSR pattern of the eliminated system (sorted rows)
+    // CSR pattern of the eliminated system (sorted rows).  col_on_host false:
+    // the device built the columns (straight into the sliced-ELL layout) and
+    // col is empty until a host consumer downloads them; row_ptr is there.
+    std::vector<int32_t> row_ptr;
     uvector<int32_t> col;
+    bool col_on_host = true;
+    // node row (natural numbering, before the renumbering) -> eliminated
+    // groups holding that node: the fill of its row
+    std::vector<int32_t> node_grp_ptr, node_grp;
     std::vector<int64_t> sell_ptr;                   // sliced-ELL slice pointers of that pattern
     std::vector<int32_t> unk_node, unk_face;         // row -> free node (rows < nfree), -> kept face
     std::vector<int32_t> sys_old, sys_new;           // system row renumbering: new -> natural, natural -> new
@@ -216,7 +223,11 @@ void build_symbolic_general(int64_t nn, int64_t nc, int64_t nface, const int64_t
                             GenSym &G);
 // Renumbering of the system rows (longest first inside windows) and the
 // sliced-ELL slice pointers of the CSR pattern in S (shared by both paths).
-void finish_symbolic_pattern(Symbolic &S, const std::vector<const int32_t *> *row_src = nullptr);
+void finish_symbolic_pattern(Symbolic &S, const std::vector<const int32_t *> *row_src = nullptr,
+                             bool columns = true);
+// the renumbering and layout from the row lengths the device found (natural
+// row order), without columns
+void finish_symbolic_lengths(Symbolic &S, const int32_t *len);
 
 // Rows are sorted by length inside windows of this many rows (slice padding).
 constexpr int kSortWindow = 512;
@@ -227,9 +238,12 @@ constexpr int kGroupMaxNodes = 64;
 
 // Builds the symbolic data; throws vag::Error on invalid input.
 // With eliminate, fracture-face groups within the limits above are
-// eliminated; otherwise every face stays an unknown.
+// eliminated; otherwise every face stays an unknown.  With rows_on_device,
+// it stops before the pattern (the caller builds the rows on the device and
+// then calls finish_symbolic_lengths); otherwise the host builds it.
 void build_symbolic(int64_t nn, int64_t nc, int64_t nf, const int32_t *hex8,
-                    const int32_t *frac_nodes, const uint8_t *dirichlet, bool eliminate, Symbolic &S);
+                    const int32_t *frac_nodes, const uint8_t *dirichlet, bool eliminate, Symbolic &S,
+                    bool rows_on_device = false);
 
 // ---------------------------------------------------------------------------
 // kernel launchers (defined in the .hip files)
@@ -304,6 +318,21 @@ struct AsmArgs {
 };
 // Node rows, kept-face rows, eliminated-face rows (into the group blocks).
 void launch_assemble(hipStream_t s, const AsmArgs &g, int32_t nkept, int32_t nelim);
+// The system pattern of a hexahedral mesh on the device: row bounds, then the
+// rows themselves (natural numbering and order, sorted, at off), then their
+// renumbering (see pattern.hip).
+struct PatArgs {
+    int32_t nn, nf, nunk;
+    const int32_t *hex8, *node_cell_ptr, *node_cell, *node_unk, *frac_unk, *cell_frac, *frac_cell;
+    const uint8_t *fmask;
+    const int32_t *node_grp_ptr, *node_grp, *grp_nptr, *grp_node;
+};
+void launch_pattern_bound(hipStream_t s, const PatArgs &g, int32_t *ub);
+void launch_pattern_rows(hipStream_t s, const PatArgs &g, const int64_t *off, int32_t *raw, int32_t *len);
+// col (row_ptr layout) = the rows of raw (natural order and numbering, sorted,
+// at off) renumbered by sys_new and sorted, row r from natural row sys_old[r]
+void launch_pattern_sort(hipStream_t s, int32_t n, const int32_t *row_ptr, const int32_t *sys_old,
+                         const int64_t *off, const int32_t *raw, const int32_t *sys_new, int32_t *col);
 // Sliced-ELL columns, row lengths and diagonal positions from the CSR pattern.
 void launch_sell_fill(hipStream_t s, int32_t n, int64_t nslice, const int32_t *row_ptr, const int32_t *col,
                       const int64_t *sell_ptr, int32_t *sell_col, int32_t *row_len, int32_t *diag_pos);
