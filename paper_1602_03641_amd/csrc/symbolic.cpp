@@ -212,15 +212,48 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
         if (frac_nodes[i] < 0 || frac_nodes[i] >= nn)
             throw Error(VAG_ERR_ARG, "fracture face node index out of range at face " + std::to_string(i / 4));
 
-    // node -> (cell, slot)
-    S.node_cell_ptr.assign(nn + 1, 0);
-    for (int64_t i = 0; i < 8 * (int64_t)nc; ++i) S.node_cell_ptr[hex8[i] + 1]++;
-    for (int32_t s = 0; s < nn; ++s) S.node_cell_ptr[s + 1] += S.node_cell_ptr[s];
-    S.node_cell.resize(S.node_cell_ptr[nn]);
-    {
+    // node -> (cell, slot), K * 8 + a in ascending order.  With the rows on
+    // the device, the device builds it too (launch_node_cell) and the host
+    // only lists the cells around the first node of each fracture face.
+    std::vector<int32_t> lead_id, lead_ptr, lead_cell;
+    if (!rows_on_device) {
+        S.node_cell_ptr.assign(nn + 1, 0);
+        for (int64_t i = 0; i < 8 * (int64_t)nc; ++i) S.node_cell_ptr[hex8[i] + 1]++;
+        for (int32_t s = 0; s < nn; ++s) S.node_cell_ptr[s + 1] += S.node_cell_ptr[s];
+        S.node_cell.resize(S.node_cell_ptr[nn]);
         std::vector<int32_t> fill(S.node_cell_ptr.begin(), S.node_cell_ptr.end() - 1);
-        for (int64_t i = 0; i < 8 * (int64_t)nc; ++i) S.node_cell[fill[hex8[i]]++] = (int32_t)i;  // K * 8 + a
+        for (int64_t i = 0; i < 8 * (int64_t)nc; ++i) S.node_cell[fill[hex8[i]]++] = (int32_t)i;
+    } else if (nf > 0) {
+        S.node_cell_ptr.clear();
+        S.node_cell.clear();
+        lead_id.assign(nn, -1);
+        int32_t nl = 0;
+        for (int32_t f = 0; f < nf; ++f)
+            if (lead_id[frac_nodes[4 * (int64_t)f]] < 0) lead_id[frac_nodes[4 * (int64_t)f]] = nl++;
+        std::vector<std::vector<int32_t>> part((size_t)chunk_count(nc));
+        parallel_chunks(nc, [&](int t, int64_t k0, int64_t k1) {
+            for (int64_t i = 8 * k0; i < 8 * k1; ++i)
+                if (lead_id[hex8[i]] >= 0) part[t].push_back((int32_t)i);
+        });
+        lead_ptr.assign((size_t)nl + 1, 0);
+        for (const auto &p : part)
+            for (int32_t i : p) lead_ptr[lead_id[hex8[i]] + 1]++;
+        for (int32_t l = 0; l < nl; ++l) lead_ptr[l + 1] += lead_ptr[l];
+        lead_cell.resize(lead_ptr[nl]);
+        std::vector<int32_t> fill(lead_ptr.begin(), lead_ptr.end() - 1);
+        for (const auto &p : part)
+            for (int32_t i : p) lead_cell[fill[lead_id[hex8[i]]]++] = i;
     }
+    // the cells (K * 8 + a, ascending) around node s, a first node of a fracture face
+    auto around = [&](int32_t s, const int32_t *&b, const int32_t *&e) {
+        if (rows_on_device) {
+            b = lead_cell.data() + lead_ptr[lead_id[s]];
+            e = lead_cell.data() + lead_ptr[lead_id[s] + 1];
+        } else {
+            b = S.node_cell.data() + S.node_cell_ptr[s];
+            e = S.node_cell.data() + S.node_cell_ptr[s + 1];
+        }
+    };
 
     // fracture faces: each matched against the faces of the cells around its
     // first node (cells in ascending order, then local faces in order)
@@ -245,8 +278,10 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
         const int32_t *fn = frac_nodes + 4 * (int64_t)f;
         const Key4 key = sorted_key(fn);
         int32_t prev = -1;
-        for (int32_t q = S.node_cell_ptr[fn[0]]; q < S.node_cell_ptr[fn[0] + 1]; ++q) {
-            const int32_t K = S.node_cell[q] >> 3;
+        const int32_t *qb, *qe;
+        around(fn[0], qb, qe);
+        for (const int32_t *q = qb; q < qe; ++q) {
+            const int32_t K = *q >> 3;
             if (K == prev) continue;  // a cell that names the node twice
             prev = K;
             const int32_t *cn = hex8 + 8 * (int64_t)K;
@@ -356,23 +391,38 @@ void build_symbolic(int64_t nn64, int64_t nc64, int64_t nf64, const int32_t *hex
                       cand_nptr[g + 1] - cand_nptr[g] <= kGroupMaxNodes;
         }
     }
-    // colour the eliminated groups: groups of one colour share no free node
+    // colour the eliminated groups: groups of one colour share no free node;
+    // greedy in group order, the least colour that no node of the group has
+    // yet (colours below 64 as a bit mask per node, higher ones listed)
     std::vector<int32_t> gcol(ncand, -1);
     {
-        std::vector<std::vector<int32_t>> node_colors(nfree);
+        std::vector<uint64_t> low(nfree, 0);
+        std::unordered_map<int32_t, std::vector<int32_t>> high;
         std::vector<int32_t> seen;
         for (int32_t g = 0; g < ncand; ++g) {
             if (!elim[g]) continue;
-            seen.clear();
-            for (int32_t q = cand_nptr[g]; q < cand_nptr[g + 1]; ++q)
-                for (int32_t c : node_colors[cand_node[q]]) seen.push_back(c);
-            std::sort(seen.begin(), seen.end());
-            int32_t c = 0;
-            for (int32_t x : seen)
-                if (x == c) ++c; else if (x > c) break;
+            uint64_t m = 0;
+            for (int32_t q = cand_nptr[g]; q < cand_nptr[g + 1]; ++q) m |= low[cand_node[q]];
+            int32_t c;
+            if (~m) {
+                c = __builtin_ctzll(~m);
+            } else {
+                seen.clear();
+                for (int32_t q = cand_nptr[g]; q < cand_nptr[g + 1]; ++q) {
+                    auto it = high.find(cand_node[q]);
+                    if (it != high.end()) seen.insert(seen.end(), it->second.begin(), it->second.end());
+                }
+                std::sort(seen.begin(), seen.end());
+                c = 64;
+                for (int32_t x : seen)
+                    if (x == c) ++c; else if (x > c) break;
+            }
             gcol[g] = c;
             S.ngcolor = std::max(S.ngcolor, c + 1);
-            for (int32_t q = cand_nptr[g]; q < cand_nptr[g + 1]; ++q) node_colors[cand_node[q]].push_back(c);
+            for (int32_t q = cand_nptr[g]; q < cand_nptr[g + 1]; ++q) {
+                if (c < 64) low[cand_node[q]] |= 1ull << c;
+                else high[cand_node[q]].push_back(c);
+            }
         }
     }
     // eliminated groups by colour

@@ -788,8 +788,10 @@ void device_pattern(vag_handle *h, DBuf<int32_t> &rp, DBuf<int32_t> &cl) {
         ub.alloc(n, h->tr);
         dlen.alloc(n, h->tr);
         off.alloc((size_t)n + 1, h->tr);
+        DBuf<int64_t> sums;
+        sums.alloc((size_t)n / 1024 + 2, h->tr);
         launch_pattern_bound(s, g, ub.p);
-        launch_slice_scan(s, n, ub.p, 1, off.p, nullptr, nullptr);
+        launch_scan64(s, n, ub.p, off.p, sums.p);
         int64_t total = 0;
         VAG_HIP(hipMemcpyAsync(&total, off.p + n, sizeof total, hipMemcpyDeviceToHost, s));
         VAG_HIP(hipStreamSynchronize(s));
@@ -857,17 +859,29 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         h->general = mesh->hex8 == nullptr;
         DBuf<int32_t> pat_rp, pat_cl;  // the system pattern (CSR), for the sliced-ELL columns
         if (!h->general) {
-            auto hex8 = host_copy(mesh->hex8, 8 * (size_t)nc, mem, h->stream);
+            // the caller's host array as it is; device arrays come over first
+            std::vector<int32_t> hex8_copy;
+            const int32_t *hex8 = mesh->hex8;
+            if (mem == VAG_MEM_DEVICE) {
+                hex8_copy = host_copy(mesh->hex8, 8 * (size_t)nc, mem, h->stream);
+                hex8 = hex8_copy.data();
+            }
             if (nf && !frac->face_nodes) throw Error(VAG_ERR_ARG, "hex8 meshes give fracture faces by face_nodes");
             std::vector<int32_t> fnodes =
                 nf ? host_copy(frac->face_nodes, 4 * (size_t)nf, mem, h->stream) : std::vector<int32_t>();
-            build_symbolic(nn, nc, nf, hex8.data(), fnodes.data(), dir.data(), h->opt.eliminate_frac_faces != 0,
-                           h->S, true);
-            upload_vec(h, h->hex8, hex8);
+            build_symbolic(nn, nc, nf, hex8, fnodes.data(), dir.data(), h->opt.eliminate_frac_faces != 0, h->S,
+                           true);
+            upload(h, h->hex8, mesh->hex8, 8 * (size_t)nc, mem);
             upload_vec(h, h->frac_nodes, fnodes);
             upload_vec(h, h->frac_slot, h->S.frac_slot);
-            upload_vec(h, h->node_cell_ptr, h->S.node_cell_ptr);
-            upload_vec(h, h->node_cell, h->S.node_cell);
+            {
+                DBuf<int32_t> work;
+                work.alloc((size_t)nn + 2 * ((size_t)nn / 1024 + 2), h->tr);
+                h->node_cell_ptr.alloc((size_t)nn + 1, h->tr);
+                h->node_cell.alloc(8 * (size_t)nc, h->tr);
+                launch_node_cell(h->stream, (int32_t)nn, nc, h->hex8.p, h->node_cell_ptr.p, h->node_cell.p, work.p);
+                VAG_HIP(hipStreamSynchronize(h->stream));  // before work goes
+            }
             upload_vec(h, h->node_frac_ptr, h->S.node_frac_ptr);
             upload_vec(h, h->node_frac, h->S.node_frac);
             device_pattern(h, pat_rp, pat_cl);
@@ -1031,7 +1045,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         VAG_HIP(hipMemsetAsync(h->bad.p, 0x7f, sizeof(int), h->stream));
         launch_grp_pos(h->stream, asm_args(h), S.ngroup, h->grp_poff.p, h->grp_pos.p);
         // slots of the cell-matrix columns in the node rows
-        h->node_pos.alloc(std::max<size_t>(S.node_cell.size() * 8, 1), h->tr);
+        h->node_pos.alloc(64 * (size_t)nc, h->tr);  // 8 slots per node_cell entry
         launch_node_pos(h->stream, asm_args(h), h->node_pos.p);
         int bad = 0;
         VAG_HIP(hipMemcpyAsync(&bad, h->bad.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));

@@ -327,7 +327,13 @@ struct PatArgs {
     const uint8_t *fmask;
     const int32_t *node_grp_ptr, *node_grp, *grp_nptr, *grp_node;
 };
+// node_cell_ptr (nn + 1) and node_cell (8 nc: K * 8 + a, ascending per node)
+// of a hexahedral mesh; work: nn + 2 (nn / 1024 + 2) ints
+void launch_node_cell(hipStream_t s, int32_t nn, int64_t nc, const int32_t *hex8, int32_t *ptr, int32_t *cells,
+                      int32_t *work);
 void launch_pattern_bound(hipStream_t s, const PatArgs &g, int32_t *ub);
+// out[0..n] = exclusive scan of in (out[n] the total), n > 0; sums: n / 1024 + 2
+void launch_scan64(hipStream_t s, int32_t n, const int32_t *in, int64_t *out, int64_t *sums);
 void launch_pattern_rows(hipStream_t s, const PatArgs &g, const int64_t *off, int32_t *raw, int32_t *len);
 // col (row_ptr layout) = the rows of raw (natural order and numbering, sorted,
 // at off) renumbered by sys_new and sorted, row r from natural row sys_old[r]
