@@ -244,22 +244,43 @@ __device__ inline void add_sys(const AsmArgs &g, int32_t r, int32_t c, int32_t n
     }
 }
 
-// Slots of the M_K columns in the node rows (positions found once per handle
-// by binary search; the per-solve assembly then adds at known slots).
+// Slots of the M_K columns in the node rows, found once per handle (the
+// per-solve assembly then adds at known slots).  A row of up to kPosRegs
+// columns is read into registers once and a column's slot is the count of
+// smaller columns there; longer rows take a binary search in the stored row.
+constexpr int kPosRegs = 32;
 __global__ __launch_bounds__(128) void node_pos_kernel(AsmArgs g, uint16_t *__restrict__ node_pos) {
     const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= g.nfree) return;
     const int32_t s = g.unk_node[r];
     const int64_t base = g.sell_ptr[r >> 6] + (r & 63);
+    const int32_t len = g.row_len[r];
+    const bool regs = len <= kPosRegs;
+    int32_t a[kPosRegs];
+#pragma unroll
+    for (int k = 0; k < kPosRegs; ++k) a[k] = regs && k < len ? g.sell_col[base + 64 * (int64_t)k] : INT32_MAX;
     for (int32_t q = g.node_cell_ptr[s]; q < g.node_cell_ptr[s + 1]; ++q) {
         const int32_t K = g.node_cell[q] >> 3;
         for (int c = 0; c < 8; ++c) {
             const int32_t u = g.node_unk[g.hex8[8 * (int64_t)K + c]];
             uint16_t k = 0xffff;
             if (u >= 0) {
-                const int64_t p = sell_find(g, r, u);
-                if (p < 0 || (p - base) / 64 >= 0xffff) atomicMin(g.bad, INT_MIN);
-                else k = (uint16_t)((p - base) / 64);
+                int64_t slot = -1;
+                if (regs) {
+                    int32_t below = 0;
+                    bool found = false;
+#pragma unroll
+                    for (int j = 0; j < kPosRegs; ++j) {
+                        below += a[j] < u;
+                        found |= a[j] == u;
+                    }
+                    if (found) slot = below;
+                } else {
+                    const int64_t p = sell_find(g, r, u);
+                    if (p >= 0) slot = (p - base) / 64;
+                }
+                if (slot < 0 || slot >= 0xffff) atomicMin(g.bad, INT_MIN);
+                else k = (uint16_t)slot;
             }
             node_pos[8 * (int64_t)q + c] = k;
         }

@@ -132,13 +132,18 @@ void finish_symbolic_pattern(Symbolic &S, const std::vector<const int32_t *> *ro
         };
         windows(0, nfree);
         windows(nfree, n);
-        S.sys_old.assign(order.begin(), order.end());  // new row -> old row
-        S.sys_new.assign(n, -1);                        // old row -> new row
-        for (int32_t r = 0; r < n; ++r) S.sys_new[order[r]] = r;
-        // row pointers in the new numbering
+        S.sys_old.swap(order);  // new row -> old row
+        S.sys_new.resize(n);    // old row -> new row
         std::vector<int32_t> rp(n + 1);
+        parallel_chunks(n, [&](int, int64_t r0, int64_t r1) {
+            for (int64_t r = r0; r < r1; ++r) {
+                S.sys_new[S.sys_old[r]] = (int32_t)r;
+                rp[r + 1] = len(S.sys_old[r]);
+            }
+        });
+        // row pointers in the new numbering
         rp[0] = 0;
-        for (int32_t r = 0; r < n; ++r) rp[r + 1] = rp[r] + len(order[r]);
+        for (int32_t r = 0; r < n; ++r) rp[r + 1] += rp[r];
         if (columns) {
             uvector<int32_t> cl = row_src ? sorted_rows(S, rp, [&](int32_t o) { return (*row_src)[o]; })
                                           : sorted_rows(S, rp, [&](int32_t o) { return S.col.data() + S.row_ptr[o]; });
@@ -149,8 +154,10 @@ void finish_symbolic_pattern(Symbolic &S, const std::vector<const int32_t *> *ro
             S.col_on_host = false;
         }
         S.row_ptr.swap(rp);
-        for (auto &u : S.node_unk)
-            if (u >= 0) u = S.sys_new[u];
+        parallel_chunks(nn, [&](int, int64_t s0, int64_t s1) {
+            for (int64_t v = s0; v < s1; ++v)
+                if (S.node_unk[v] >= 0) S.node_unk[v] = S.sys_new[S.node_unk[v]];
+        });
         for (auto &u : S.frac_unk)
             if (u < n) u = S.sys_new[u];
         for (int32_t G = 0; G < S.ngroup; ++G) {
@@ -165,20 +172,25 @@ void finish_symbolic_pattern(Symbolic &S, const std::vector<const int32_t *> *ro
         const int32_t n = S.nunk;
         const int64_t nslice = (n + kSliceRows - 1) / kSliceRows;
         S.sell_ptr.assign(nslice + 1, 0);
-        for (int64_t sl = 0; sl < nslice; ++sl) {
-            int32_t w = 0;
-            for (int32_t r = (int32_t)(sl * kSliceRows); r < std::min<int64_t>(n, (sl + 1) * kSliceRows); ++r)
-                w = std::max(w, S.row_ptr[r + 1] - S.row_ptr[r]);
-            S.sell_ptr[sl + 1] = S.sell_ptr[sl] + (int64_t)w * kSliceRows;
-        }
+        parallel_chunks(nslice, [&](int, int64_t l0, int64_t l1) {
+            for (int64_t sl = l0; sl < l1; ++sl) {
+                int32_t w = 0;
+                for (int32_t r = (int32_t)(sl * kSliceRows); r < std::min<int64_t>(n, (sl + 1) * kSliceRows); ++r)
+                    w = std::max(w, S.row_ptr[r + 1] - S.row_ptr[r]);
+                S.sell_ptr[sl + 1] = (int64_t)w * kSliceRows;
+            }
+        }, 1024);
+        for (int64_t sl = 0; sl < nslice; ++sl) S.sell_ptr[sl + 1] += S.sell_ptr[sl];
         if (S.sell_ptr[nslice] >= INT32_MAX)
             throw Error(VAG_ERR_UNSUPPORTED, "padded system has more than 2^31 entries");
     }
 
     // row -> node or kept face, face -> (group, local index)
     S.unk_node.assign(nfree, -1);
-    for (int32_t s = 0; s < nn; ++s)
-        if (S.node_unk[s] >= 0) S.unk_node[S.node_unk[s]] = s;
+    parallel_chunks(nn, [&](int, int64_t s0, int64_t s1) {
+        for (int64_t v = s0; v < s1; ++v)
+            if (S.node_unk[v] >= 0) S.unk_node[S.node_unk[v]] = (int32_t)v;
+    });
     S.unk_face.assign(S.nunk - nfree, -1);
     for (int32_t f = 0; f < nf; ++f)
         if (S.frac_unk[f] < S.nunk) S.unk_face[S.frac_unk[f] - nfree] = f;
