@@ -2,7 +2,9 @@
 // on meshes read from a file, for a build with the host address and
 // undefined-behaviour sanitizers: every input is run through the phase and
 // the pattern it builds is checked (rows sorted, columns in range, slices
-// covering the rows); inputs marked invalid must end in a vag::Error.
+// covering the rows), and the hexahedral phase run again in the mode that
+// leaves the rows to the device must reach the same numbering from the row
+// lengths; inputs marked invalid must end in a vag::Error.
 // File layout (little endian): int64 kind (0 hexahedra, 1 general), int64
 // expect_error, then the arrays of that kind (see read_* below).
 #include <cstdio>
@@ -66,6 +68,20 @@ int main(int argc, char **argv) {
                 Symbolic S;
                 build_symbolic(nn, nc, nf, hex8.data(), fn.data(), dir.data(), elim != 0, S);
                 rc = check_pattern(S);
+                // the same phase with the rows left to the device: given the row
+                // lengths (natural order), it must reach the same numbering
+                if (rc == 0) {
+                    Symbolic D;
+                    build_symbolic(nn, nc, nf, hex8.data(), fn.data(), dir.data(), elim != 0, D, true);
+                    std::vector<int32_t> len((size_t)D.nunk);
+                    for (int32_t o = 0; o < D.nunk; ++o)
+                        len[o] = S.row_ptr[S.sys_new[o] + 1] - S.row_ptr[S.sys_new[o]];
+                    finish_symbolic_lengths(D, len.data());
+                    if (D.sys_old != S.sys_old || D.row_ptr != S.row_ptr || D.sell_ptr != S.sell_ptr ||
+                        D.node_unk != S.node_unk || D.frac_unk != S.frac_unk || D.grp_node != S.grp_node ||
+                        D.frac_cell != S.frac_cell || D.cell_frac != S.cell_frac || D.col_on_host)
+                        rc = 18;
+                }
                 printf("hex eliminate=%d: %d unknowns, %lld nonzeros, %d groups, check %d\n", elim, S.nunk,
                        (long long)S.nnz, S.ngroup, rc);
             }
