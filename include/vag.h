@@ -474,8 +474,15 @@ size_t vag_estimate_footprint(int64_t n_nodes, int64_t n_cells, int64_t n_frac, 
  * one FIFO queue; the head job starts on the first free worker as soon as its
  * estimated footprint (vag_estimate_footprint) fits in what the running jobs
  * and the cached handles leave of hbm_budget.  Jobs on different workers run
- * concurrently, so their kernels overlap on the device; a job's own kernels
- * are the same, in the same order, as on a lone handle, so its results are
+ * concurrently, so their kernels overlap on the device.  The transport steps
+ * of jobs below 2^18 control volumes are batched per launch: per size class
+ * (below 2^16, 2^17, 2^18 control volumes) a host thread launches, tick after
+ * tick on a stream of its own, one kernel that takes one step of every job of
+ * the class in its transport phase (up to 8 jobs a launch); a job joins once
+ * its upwind operator is built and leaves after its last step, while its
+ * worker takes the next job (larger jobs' steps fill the device alone and
+ * their worker launches them).  Every row of a job gets the arithmetic, in
+ * the same order, of the job run alone on a lone handle, so its results are
  * bitwise those of the job run alone.
  *
  * A job with a nonzero mesh_key keeps its handle (matrices, AMG hierarchy and
@@ -519,6 +526,8 @@ typedef struct {
     int64_t submitted, queued, running, finished;
     size_t budget, bytes_in_use, peak_bytes_in_use, cached_bytes;
     int cached_handles;
+    int64_t step_launches;  /* batched transport launches so far */
+    int64_t job_steps;      /* transport steps of all jobs so far (>= step_launches) */
 } vag_server_stats;
 
 /* hbm_budget 0: 80 % of the free device memory at creation.  n_workers in

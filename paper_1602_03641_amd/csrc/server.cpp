@@ -4,16 +4,26 @@
 // takes the head job when its estimated device footprint fits in the budget
 // left by the running jobs and the cached handles (idle cached handles are
 // evicted, least recently used first, to make room).  Each job runs on a
-// handle of its own (vag_create .. vag_transport, outputs copied to the
-// caller's host buffers), so jobs on different workers overlap on the device
-// while each job's kernels, and therefore its results, are those of the job
-// run alone.
+// handle of its own (vag_create, the pressure solve and the transport's set-up
+// on the worker's stream, outputs copied to the caller's host buffers), so
+// jobs on different workers overlap on the device.  The transport steps of
+// the smaller jobs in their transport phase run batched: per lane of job
+// sizes, a batcher thread launches, tick after tick on a stream of its own,
+// one kernel that takes one step of every active job of the lane (up to
+// kBatchJobs per launch); a job joins at the next tick once its set-up is
+// done and leaves after its last step (a large job's steps fill the device
+// alone, and its worker launches them).  The worker hands the job over after the set-up and
+// takes the next one; a finisher thread waits for the job's last step,
+// copies its outputs and completes it.  Each row of
+// each job gets the arithmetic of the job run alone, so results are the
+// same alone and in the mix.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <list>
 #include <memory>
 #include <mutex>
@@ -25,7 +35,7 @@
 
 #include <hip/hip_runtime.h>
 
-#include "vag.h"
+#include "vag_internal.h"
 
 namespace {
 
@@ -45,6 +55,13 @@ struct Job {
     size_t est = 0;
     enum { QUEUED, RUNNING, DONE } state = QUEUED;
     vag_job_result res{};
+    // a job whose transport steps run batched: its handle, the bytes it is
+    // charged for, the solve's status, the event its set-up ends with
+    size_t charged = 0;
+    vag_handle *h = nullptr;
+    vag_status solve_status = VAG_OK;
+    hipEvent_t ready = nullptr;
+    int fin = 0;  // the finisher that completes it
 };
 
 struct Cached {
@@ -61,12 +78,152 @@ std::vector<T> copy_in(const T *p, size_t n) {
     return n ? std::vector<T>(p, p + n) : std::vector<T>();
 }
 
+// The transport steps of the served jobs, batched per launch.  A worker
+// hands a job over once its transport is set up (submit) and takes the next
+// job; the batcher calls done(job, failed) once the job's last step is
+// launched (the finisher then waits for it).
+class StepBatcher {
+public:
+    using Done = std::function<void(Job *, bool)>;
+    StepBatcher(int device, hipStream_t stream, Done done) : device_(device), stream_(stream), done_(std::move(done)) {
+        for (auto &e : tick_) {
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
+        }
+        th_ = std::thread([this] { loop(); });
+    }
+    ~StepBatcher() {
+        {
+            std::lock_guard<std::mutex> l(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        th_.join();
+        for (auto e : tick_)
+            if (e) (void)hipEventDestroy(e);
+    }
+    // j->h has its transport set up (vag_serving_transport_begin); its steps
+    // start after j->ready
+    void submit(Job *j, int64_t N) {
+        {
+            std::lock_guard<std::mutex> l(mu_);
+            pending_.push_back(Entry{j, N, 0});
+        }
+        cv_.notify_all();
+    }
+    void counts(int64_t *launches, int64_t *steps) {
+        std::lock_guard<std::mutex> l(mu_);
+        *launches = launches_;
+        *steps = steps_;
+    }
+
+private:
+    struct Entry {
+        Job *j;
+        int64_t N, k;
+    };
+    static constexpr int kDepth = 32;  // ticks in flight: the host runs ahead of the device, a new job joins within them
+
+    void loop() {
+        (void)hipSetDevice(device_);
+        int64_t ticks = 0;
+        std::vector<std::pair<Job *, bool>> finished;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> l(mu_);
+                cv_.wait(l, [&] { return stop_ || !pending_.empty() || !active_.empty(); });
+                if (stop_ && pending_.empty() && active_.empty()) return;
+                while (!pending_.empty()) {
+                    Entry e = pending_.front();
+                    pending_.pop_front();
+                    if (hipStreamWaitEvent(stream_, e.j->ready, 0) != hipSuccess ||
+                        hipEventRecord(vag_serving_event(e.j->h, 6), stream_) != hipSuccess)
+                        finished.emplace_back(e.j, true);
+                    else
+                        active_.push_back(e);
+                }
+            }
+            bool ok = true;
+            if (!active_.empty()) {
+                if (ticks >= kDepth && tick_[ticks % kDepth])
+                    ok = hipEventSynchronize(tick_[ticks % kDepth]) == hipSuccess;
+                try {
+                    for (size_t g = 0; ok && g < active_.size(); g += vag::kBatchJobs) {
+                        vag::TransportBatch B{};
+                        B.n = (int32_t)std::min<size_t>(vag::kBatchJobs, active_.size() - g);
+                        for (int32_t q = 0; q < B.n; ++q) {
+                            Entry &e = active_[g + q];
+                            vag_serving_transport_job(e.j->h, e.k, &B.job[q]);
+                        }
+                        vag::launch_transport_batch(stream_, B);
+                        std::lock_guard<std::mutex> l(mu_);
+                        ++launches_;
+                        steps_ += B.n;
+                    }
+                } catch (...) {
+                    ok = false;
+                }
+                if (ok && tick_[ticks % kDepth]) ok = hipEventRecord(tick_[ticks % kDepth], stream_) == hipSuccess;
+                ++ticks;
+                std::vector<Entry> still;
+                for (Entry &e : active_) {
+                    ++e.k;
+                    if (!ok)
+                        finished.emplace_back(e.j, true);
+                    else if (e.k == e.N)
+                        finished.emplace_back(e.j, hipEventRecord(vag_serving_event(e.j->h, 7), stream_) != hipSuccess);
+                    else
+                        still.push_back(e);
+                }
+                active_.swap(still);
+            }
+            for (auto &f : finished) done_(f.first, f.second);
+            finished.clear();
+        }
+    }
+
+    int device_;
+    hipStream_t stream_;
+    Done done_;
+    hipEvent_t tick_[kDepth] = {};
+    std::thread th_;
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::deque<Entry> pending_;
+    std::vector<Entry> active_;  // only the batcher thread touches it
+    int64_t launches_ = 0, steps_ = 0;
+    bool stop_ = false;
+};
+
 }  // namespace
 
 struct vag_server {
     int device = 0;
     size_t budget = 0;
     std::vector<hipStream_t> streams;
+    // transport lanes by job size (rows of the upwind operator): a launch
+    // takes one step of each job in its lane, so a step of a small job does
+    // not wait for the step of a large one
+    // Jobs of at least 2^18 rows step on their own: their launches fill the
+    // device, and in a shared launch each step would wait for the others.
+    static constexpr int kLanes = 3;
+    static constexpr int64_t kBatchRows = int64_t(1) << 18;
+    static int lane_of(int64_t rows) {  // rows below 2^16, 2^17, 2^18
+        int l = 0;
+        while (l + 1 < kLanes && rows >= (int64_t(1) << (16 + l))) ++l;
+        return l;
+    }
+    hipStream_t lane_stream[kLanes] = {};
+    std::unique_ptr<StepBatcher> lane[kLanes];
+    // finishers: each waits for a batched job's last step, copies its
+    // outputs (on its own stream, where the job's handle moved when it was
+    // handed over), then keeps or destroys the handle and completes the job
+    static constexpr int kFinishers = 4;
+    hipStream_t fin_stream[kFinishers] = {};
+    std::thread fin_thread[kFinishers];
+    std::deque<std::pair<Job *, bool>> fin_queue[kFinishers];
+    std::condition_variable cv_fin;
+    bool fin_stop = false;
+    int next_fin = 0;
     std::vector<std::thread> workers;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -94,8 +251,26 @@ struct vag_server {
         return true;
     }
 
-    vag_handle *run(Job *j, int w, vag_handle *h);
+    // a run ends with the handle to keep (or null), or the job handed over
+    struct Outcome {
+        vag_handle *keep = nullptr;
+        bool handed_over = false;
+    };
+    Outcome run(Job *j, int w, vag_handle *h);
+    vag_handle *finish_outputs(Job *j, vag_handle *h, hipStream_t s);
+    void complete(Job *j, vag_handle *keep);
     void loop(int w);
+    void fin_loop(int f);
+    // drains the finishers' queues, then ends their threads
+    void stop_finisher() {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            fin_stop = true;
+        }
+        cv_fin.notify_all();
+        for (auto &t : fin_thread)
+            if (t.joinable()) t.join();
+    }
 };
 
 void vag_server::loop(int w) {
@@ -135,6 +310,7 @@ void vag_server::loop(int w) {
                         peak = std::max(peak, in_use + cached_bytes);
                         ++running;
                         j->state = Job::RUNNING;
+                        j->charged = charged;
                         j->res.t_start = now();
                         j->res.worker = w;
                         j->res.reused = reuse != nullptr;
@@ -152,31 +328,62 @@ void vag_server::loop(int w) {
             }
         }
         for (vag_handle *e : evicted) vag_destroy(e);
-        evicted.clear();
-        vag_handle *keep = run(j, w, reuse);
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            in_use -= charged;
-            if (keep) {
-                const size_t bytes = vag_footprint_bytes(keep);
-                cache.push_front(Cached{j->key, j->nn, j->nc, j->nf, j->opt.eliminate_frac_faces != 0, keep, bytes});
-                cached_bytes += bytes;
-                make_room(0, evicted);  // the kept handle may have outgrown the estimate
-            }
-            --running;
-            ++finished;
-            j->state = Job::DONE;
-            j->res.t_end = now();
-        }
-        cv_done.notify_all();
-        cv_work.notify_all();
-        for (vag_handle *e : evicted) vag_destroy(e);
+        const Outcome o = run(j, w, reuse);
+        if (!o.handed_over) complete(j, o.keep);
     }
 }
 
+// Under no lock: the job's charge comes off, its handle goes to the cache
+// (or nothing), the job is done.
+void vag_server::complete(Job *j, vag_handle *keep) {
+    std::vector<vag_handle *> evicted;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        in_use -= j->charged;
+        if (keep) {
+            const size_t bytes = vag_footprint_bytes(keep);
+            cache.push_front(Cached{j->key, j->nn, j->nc, j->nf, j->opt.eliminate_frac_faces != 0, keep, bytes});
+            cached_bytes += bytes;
+            make_room(0, evicted);  // the kept handle may have outgrown the estimate
+        }
+        --running;
+        ++finished;
+        j->state = Job::DONE;
+        j->res.t_end = now();
+    }
+    cv_done.notify_all();
+    cv_work.notify_all();
+    for (vag_handle *e : evicted) vag_destroy(e);
+}
+
+// The outputs of a job whose work on h is done or queued on s; returns the
+// handle to keep, or null (destroyed).
+vag_handle *vag_server::finish_outputs(Job *j, vag_handle *h, hipStream_t s) {
+    vag_job_result &r = j->res;
+    const bool transport = j->n_steps > 0 || j->t_final > 0;
+    vag_status st = vag_get_pressure(h, j->out[0], j->out[1], j->out[2], VAG_MEM_HOST);
+    if (st == VAG_OK && transport) st = vag_get_concentration(h, j->out[3], j->out[4], j->out[5], VAG_MEM_HOST);
+    if (st == VAG_OK) st = hipStreamSynchronize(s) == hipSuccess ? VAG_OK : VAG_ERR_HIP;
+    if (st != VAG_OK) {
+        r.status = st;
+        std::snprintf(r.message, sizeof r.message, "%s", vag_last_error(h));
+        vag_destroy(h);
+        return nullptr;
+    }
+    r.ms_run = 1e3 * (now() - r.t_start);
+    r.status = j->solve_status;  // VAG_OK or VAG_WARN_NOT_CONVERGED
+    if (j->solve_status != VAG_OK) std::snprintf(r.message, sizeof r.message, "%s", vag_last_error(h));
+    r.footprint_bytes = vag_footprint_bytes(h);
+    if (j->key) return h;
+    vag_destroy(h);
+    return nullptr;
+}
+
 // Runs one job on worker w's stream, on h if given (a cached handle of the
-// same mesh) or on a new handle.  Returns the handle to cache, or null.
-vag_handle *vag_server::run(Job *j, int w, vag_handle *h) {
+// same mesh) or on a new handle: create (or update), the pressure solve and
+// the transport's set-up; then hands the transport steps to the job's lane
+// or, without transport, copies the outputs.
+vag_server::Outcome vag_server::run(Job *j, int w, vag_handle *h) {
     hipStream_t s = streams[w];
     vag_job_result &r = j->res;
     vag_mesh mesh{j->nn, j->nc, j->xyz.data(), j->hex8.data()};
@@ -198,7 +405,7 @@ vag_handle *vag_server::run(Job *j, int w, vag_handle *h) {
                             j->c_bar.empty() ? nullptr : j->c_bar.data(), VAG_MEM_HOST);
         if (failed(st)) {
             vag_destroy(h);
-            return nullptr;
+            return {};
         }
     } else {
         const double tc = now();
@@ -207,37 +414,80 @@ vag_handle *vag_server::run(Job *j, int w, vag_handle *h) {
         if (st != VAG_OK) {
             r.status = st;
             std::snprintf(r.message, sizeof r.message, "%s", vag_last_error(nullptr));
-            return nullptr;
+            return {};
         }
     }
     st = vag_solve_pressure(h, &r.solve);
     if (failed(st)) {
         vag_destroy(h);
-        return nullptr;
+        return {};
     }
-    const vag_status solve_status = st;
-    if (j->n_steps > 0 || j->t_final > 0) {
+    j->solve_status = st;
+    if ((j->n_steps > 0 || j->t_final > 0) && j->nc + j->nf + j->nn >= kBatchRows) {
         st = vag_transport(h, j->n_steps, j->t_final, nullptr, nullptr, nullptr, VAG_MEM_HOST, &r.transport);
         if (failed(st)) {
             vag_destroy(h);
-            return nullptr;
+            return {};
         }
+    } else if (j->n_steps > 0 || j->t_final > 0) {
+        int64_t N = 0;
+        st = vag_serving_transport_begin(h, j->n_steps, j->t_final, &N);
+        if (st == VAG_OK && hipEventCreateWithFlags(&j->ready, hipEventDisableTiming) != hipSuccess) st = VAG_ERR_HIP;
+        if (st == VAG_OK && hipEventRecord(j->ready, s) != hipSuccess) st = VAG_ERR_HIP;
+        // the handle moves to its finisher's stream (its work on s ends here)
+        if (st == VAG_OK) {
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                j->fin = next_fin;
+                next_fin = (next_fin + 1) % kFinishers;
+            }
+            st = vag_set_stream(h, fin_stream[j->fin]);
+        }
+        if (failed(st)) {
+            if (j->ready) (void)hipEventDestroy(j->ready);
+            j->ready = nullptr;
+            vag_destroy(h);
+            return {};
+        }
+        j->h = h;
+        lane[lane_of(j->nc + j->nf + j->nn)]->submit(j, N);
+        Outcome o;
+        o.handed_over = true;
+        return o;
     }
-    st = vag_get_pressure(h, j->out[0], j->out[1], j->out[2], VAG_MEM_HOST);
-    if (st == VAG_OK && (j->n_steps > 0 || j->t_final > 0))
-        st = vag_get_concentration(h, j->out[3], j->out[4], j->out[5], VAG_MEM_HOST);
-    if (st == VAG_OK) st = hipStreamSynchronize(s) == hipSuccess ? VAG_OK : VAG_ERR_HIP;
-    if (failed(st)) {
-        vag_destroy(h);
-        return nullptr;
+    Outcome o;
+    o.keep = finish_outputs(j, h, s);
+    return o;
+}
+
+void vag_server::fin_loop(int f) {
+    (void)hipSetDevice(device);
+    for (;;) {
+        std::pair<Job *, bool> item;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_fin.wait(lk, [&] { return fin_stop || !fin_queue[f].empty(); });
+            if (fin_queue[f].empty()) return;  // stop
+            item = fin_queue[f].front();
+            fin_queue[f].pop_front();
+        }
+        Job *j = item.first;
+        vag_handle *h = j->h, *keep = nullptr;
+        j->h = nullptr;
+        vag_status st = item.second ? VAG_ERR_HIP : vag_serving_transport_end(h, &j->res.transport);
+        if (st == VAG_OK) {
+            // the last step is done, so the lane's stream is past its wait on j->ready
+            (void)hipEventDestroy(j->ready);
+            j->ready = nullptr;
+            keep = finish_outputs(j, h, fin_stream[f]);
+        } else {  // j->ready stays: the lane's stream may still wait on it
+            j->res.status = st;
+            std::snprintf(j->res.message, sizeof j->res.message, "batched transport steps failed");
+            (void)hipDeviceSynchronize();  // steps launched before the failure may still read the handle
+            vag_destroy(h);
+        }
+        complete(j, keep);
     }
-    r.ms_run = 1e3 * (now() - r.t_start);
-    r.status = solve_status;  // VAG_OK or VAG_WARN_NOT_CONVERGED
-    if (solve_status != VAG_OK) std::snprintf(r.message, sizeof r.message, "%s", vag_last_error(h));
-    r.footprint_bytes = vag_footprint_bytes(h);
-    if (j->key) return h;
-    vag_destroy(h);
-    return nullptr;
 }
 
 extern "C" {
@@ -266,7 +516,31 @@ vag_status vag_server_create(size_t hbm_budget, int n_workers, vag_server **out)
         }
         s->streams.push_back(st);
     }
+    for (int l = 0; l < vag_server::kLanes; ++l)
+        if (hipStreamCreateWithFlags(&s->lane_stream[l], hipStreamNonBlocking) != hipSuccess) {
+            for (auto x : s->streams) (void)hipStreamDestroy(x);
+            for (int m = 0; m < l; ++m) (void)hipStreamDestroy(s->lane_stream[m]);
+            return VAG_ERR_HIP;
+        }
+    for (int f = 0; f < vag_server::kFinishers; ++f)
+        if (hipStreamCreateWithFlags(&s->fin_stream[f], hipStreamNonBlocking) != hipSuccess) {
+            for (auto x : s->streams) (void)hipStreamDestroy(x);
+            for (auto x : s->lane_stream) (void)hipStreamDestroy(x);
+            for (int g = 0; g < f; ++g) (void)hipStreamDestroy(s->fin_stream[g]);
+            return VAG_ERR_HIP;
+        }
     try {
+        vag_server *p = s.get();
+        auto to_finisher = [p](Job *j, bool failed) {
+            {
+                std::lock_guard<std::mutex> lk(p->mu);
+                p->fin_queue[j->fin].emplace_back(j, failed);
+            }
+            p->cv_fin.notify_all();
+        };
+        for (int f = 0; f < vag_server::kFinishers; ++f) s->fin_thread[f] = std::thread([p, f] { p->fin_loop(f); });
+        for (int l = 0; l < vag_server::kLanes; ++l)
+            s->lane[l].reset(new StepBatcher(s->device, s->lane_stream[l], to_finisher));
         for (int w = 0; w < n_workers; ++w) s->workers.emplace_back([p = s.get(), w] { p->loop(w); });
     } catch (...) {
         {
@@ -275,7 +549,11 @@ vag_status vag_server_create(size_t hbm_budget, int n_workers, vag_server **out)
         }
         s->cv_work.notify_all();
         for (auto &t : s->workers) t.join();
+        for (auto &b : s->lane) b.reset();
+        s->stop_finisher();
         for (auto x : s->streams) (void)hipStreamDestroy(x);
+        for (auto x : s->lane_stream) (void)hipStreamDestroy(x);
+        for (auto x : s->fin_stream) (void)hipStreamDestroy(x);
         return VAG_ERR_OOM;
     }
     *out = s.release();
@@ -388,6 +666,13 @@ vag_status vag_server_get_stats(vag_server *s, vag_server_stats *st) {
     st->peak_bytes_in_use = s->peak;
     st->cached_bytes = s->cached_bytes;
     st->cached_handles = (int)s->cache.size();
+    st->step_launches = st->job_steps = 0;
+    for (auto &b : s->lane) {
+        int64_t l = 0, k = 0;
+        b->counts(&l, &k);
+        st->step_launches += l;
+        st->job_steps += k;
+    }
     return VAG_OK;
 }
 
@@ -406,8 +691,12 @@ void vag_server_destroy(vag_server *s) {
     }
     s->cv_work.notify_all();
     for (auto &t : s->workers) t.join();
+    for (auto &b : s->lane) b.reset();  // their last jobs go to the finisher
+    s->stop_finisher();
     for (auto &c : s->cache) vag_destroy(c.h);
     for (auto x : s->streams) (void)hipStreamDestroy(x);
+    for (auto x : s->lane_stream) (void)hipStreamDestroy(x);
+    for (auto x : s->fin_stream) (void)hipStreamDestroy(x);
     delete s;
 }
 

@@ -582,17 +582,18 @@ __device__ __forceinline__ double upwind_row(const UpwindOp &T, const double *__
     return (a0 + a1) + (a2 + a3);
 }
 
-__global__ __launch_bounds__(256) void transport_step_kernel(UpwindOp T, const double *__restrict__ c_in,
-                                                             double *__restrict__ c_out, double theta, int backward) {
-    // block b runs on XCD b mod 8 (the hardware deals the blocks in turn);
-    // item q of XCD x is its run of A slices and its run of B slices merged
-    // in proportion: item q is an A slice iff floor((q+1) a / w) >
-    // floor(q a / w), and floor(q a / w) A slices come before it.  Every
-    // other step sweeps each XCD's run backwards, so that it starts on the
-    // slices the previous step read last, which the last-level cache still
-    // holds.
-    const int x = blockIdx.x & 7;
-    const int32_t q0 = 4 * (int32_t)(blockIdx.x >> 3) + (int32_t)(threadIdx.x >> 6);
+// The step for block b of a launch over T (b mod 8 names the XCD: the
+// hardware deals the blocks out in turn, so a batched launch starts each
+// operator's blocks at a multiple of 8).  Item q of XCD x is its run of A
+// slices and its run of B slices merged in proportion: item q is an A slice
+// iff floor((q+1) a / w) > floor(q a / w), and floor(q a / w) A slices come
+// before it.  Every other step sweeps each XCD's run backwards, so that it
+// starts on the slices the previous step read last, which the last-level
+// cache still holds.
+__device__ inline void transport_step_block(const UpwindOp &T, const double *__restrict__ c_in,
+                                            double *__restrict__ c_out, double theta, int backward, int32_t b) {
+    const int x = b & 7;
+    const int32_t q0 = 4 * (b >> 3) + (int32_t)(threadIdx.x >> 6);
     const int32_t a = T.xlo[x + 1] - T.xlo[x], w = a + T.ylo[x + 1] - T.ylo[x];
     const int lane = threadIdx.x & (kSliceRows - 1);
     if (q0 >= w) return;  // whole wavefronts
@@ -612,6 +613,21 @@ __global__ __launch_bounds__(256) void transport_step_kernel(UpwindOp T, const d
     const double acc = cb >= 0 ? upwind_row<true>(T, c_in, cnt, width, level0, last, lane, cb, d)
                                : upwind_row<false>(T, c_in, cnt, width, level0, last, lane, cb, d);
     if (row) c_out[i] = (theta == 1.0) ? acc : ci + theta * (acc - ci);
+}
+
+__global__ __launch_bounds__(256) void transport_step_kernel(UpwindOp T, const double *__restrict__ c_in,
+                                                             double *__restrict__ c_out, double theta, int backward) {
+    transport_step_block(T, c_in, c_out, theta, backward, (int32_t)blockIdx.x);
+}
+
+// One step of several operators in one launch: operator j takes blocks
+// [B.blk[j], B.blk[j + 1]), each block the same work as in its own launch.
+__global__ __launch_bounds__(256) void transport_batch_kernel(TransportBatch B) {
+    const int32_t b = (int32_t)blockIdx.x;
+    int j = 0;
+    while (j + 1 < B.n && b >= B.blk[j + 1]) ++j;
+    const TransportJob &J = B.job[j];
+    transport_step_block(J.T, J.c_in, J.c_out, J.theta, J.backward, b - B.blk[j]);
 }
 
 // Cost of the slices before slice s: the bytes the sweep moves for them
@@ -960,14 +976,26 @@ void launch_xcd_split(hipStream_t s, int32_t nslice, int32_t sa, const int64_t *
     hipLaunchKernelGGL(xcd_split_kernel, dim3(1), dim3(64), 0, s, nslice, sa, slice_ptr, xlo);
     VAG_HIP(hipGetLastError());
 }
-void launch_transport_step(hipStream_t s, const UpwindOp &T, const double *c_in, double *c_out, double theta,
-                           bool backward) {
+int32_t transport_step_blocks(const UpwindOp &T) {
     int32_t per_xcd = 0;  // blocks per XCD: the longest merged run, 4 slices per block
     for (int x = 0; x < 8; ++x)
         per_xcd = std::max(per_xcd, (T.xlo[x + 1] - T.xlo[x] + T.ylo[x + 1] - T.ylo[x] + 3) / 4);
-    if (per_xcd <= 0) return;
-    hipLaunchKernelGGL(transport_step_kernel, dim3(8 * (unsigned)per_xcd), dim3(256), 0, s, T, c_in, c_out, theta,
+    return 8 * per_xcd;
+}
+void launch_transport_step(hipStream_t s, const UpwindOp &T, const double *c_in, double *c_out, double theta,
+                           bool backward) {
+    const int32_t nb = transport_step_blocks(T);
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(transport_step_kernel, dim3((unsigned)nb), dim3(256), 0, s, T, c_in, c_out, theta,
                        backward ? 1 : 0);
+    VAG_HIP(hipGetLastError());
+}
+void launch_transport_batch(hipStream_t s, TransportBatch &B) {
+    if (B.n < 1 || B.n > kBatchJobs) throw Error(VAG_ERR_ARG, "transport batch size out of range");
+    B.blk[0] = 0;
+    for (int j = 0; j < B.n; ++j) B.blk[j + 1] = B.blk[j] + transport_step_blocks(B.job[j].T);
+    if (B.blk[B.n] <= 0) return;
+    hipLaunchKernelGGL(transport_batch_kernel, dim3((unsigned)B.blk[B.n]), dim3(256), 0, s, B);
     VAG_HIP(hipGetLastError());
 }
 void launch_transport_gather(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t *hex8,

@@ -6,6 +6,7 @@
 #include <cstring>
 
 #include <map>
+#include <memory>
 #include <mutex>
 #include <unordered_map>
 
@@ -132,6 +133,13 @@ void pinned_put(void *p, size_t bytes) {
     g_pinned_free.emplace(pinned_class(bytes), p);
 }
 
+// What a run of transport steps needs: step count, the last step's fraction
+// of dt, and the figures the info reports.
+struct TransportPlan {
+    int64_t N = 0, total = 0;
+    double dt = 0, last_dt = 0, theta_last = 1.0, dtb[3] = {};
+};
+
 }  // namespace vag
 
 struct vag_handle {
@@ -181,6 +189,7 @@ struct vag_handle {
     int cur = 0;
     bool solved = false, have_flux = false, have_c = false;
     bool have_op = false;  // the upwind operator of the last vag_transport exists
+    std::unique_ptr<vag::TransportPlan> plan;  // a served transport whose steps the server runs
 
     Amg amg;
     Ilu ilu;                 // block-Jacobi ILU(0)
@@ -1358,110 +1367,157 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
     return st;
 }
 
+namespace {
+// vag_transport up to its steps: CFL time step, the upwind operator, the
+// initial state (ev[5] .. ev[6] on the handle's stream)
+TransportPlan transport_prepare(vag_handle *h, int64_t n_steps, double t_final, const double *c0_cell,
+                                const double *c0_frac, const double *c0_node, vag_mem mem) {
+    if (!h->have_flux) throw Error(VAG_ERR_STATE, "vag_transport needs a pressure solve (or vag_set_fluxes) first");
+    if (n_steps < 0 || t_final < 0) throw Error(VAG_ERR_ARG, "negative step count or final time");
+    const Symbolic &S = h->S;
+    hipStream_t s = h->stream;
+    const int64_t nrow = (int64_t)S.nc + S.nf + S.nn;
+    const int32_t nslice = (int32_t)((nrow + kSliceRows - 1) / kSliceRows);
+    VAG_HIP(hipEventRecord(h->ev[5], s));
+    if (h->general) {
+        launch_gen_cfl(s, h->ginc(), h->Fall.p, h->well_out(), h->phi_cell.p, h->phi_frac.p, h->phi_node.p,
+                       h->opt.cfl, h->rparts.p, h->dt4.p);
+        launch_gen_upwind_count(s, h->ginc(), h->Fall.p, h->well_src(), h->slice_width.p, h->tmeta.p,
+                                h->slice_nnz.p);
+    } else {
+        launch_cfl(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
+                   h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
+                   h->F_cell_frac.p, h->F_frac.p, h->well_out(), h->phi_cell.p, h->phi_frac.p, h->phi_node.p,
+                   h->opt.cfl, h->rparts.p, h->dt4.p);
+        launch_upwind_count(s, S.nc, S.nf, S.nn, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
+                            h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
+                            h->F_cell_frac.p, h->F_frac.p, h->well_src(), h->slice_width.p, h->tmeta.p,
+                            h->slice_nnz.p);
+    }
+    launch_slice_scan(s, nslice, h->slice_nnz.p, 1, h->slice_ptr.p, h->slice_nnz.p, h->cnt.p);
+    // segment A: the slices of cells and fracture faces, B: of nodes
+    launch_xcd_split(s, nslice, (int32_t)((S.nc + (int64_t)S.nf + kSliceRows - 1) / kSliceRows), h->slice_ptr.p,
+                     h->xsplit.p);
+    int64_t total = 0;
+    VAG_HIP(hipMemcpyAsync(&total, h->slice_ptr.p + nslice, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    VAG_HIP(hipMemcpyAsync(h->h_cnt, h->cnt.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    VAG_HIP(hipMemcpyAsync(h->h_xsplit(), h->xsplit.p, 18 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    VAG_HIP(hipMemcpyAsync(h->h_scal, h->dt4.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    VAG_HIP(hipStreamSynchronize(s));
+    for (int x = 0; x < 18; ++x) h->xlo[x] = h->h_xsplit()[x];
+    const double dt = h->h_scal[3];
+    double dtb[3] = {h->h_scal[0], h->h_scal[1], h->h_scal[2]};
+    if (!(dt < INFINITY)) throw Error(VAG_ERR_ARG, "no control volume has an outflow: CFL bound is infinite");
+    if ((size_t)total > h->tcol.n) {
+        h->tcol.alloc((size_t)total + (size_t)total / 8, h->tr);
+        h->tcol16.alloc((size_t)total + (size_t)total / 8, h->tr);
+        h->tval.alloc((size_t)total + (size_t)total / 8, h->tr);
+    }
+    ensure(h->tbase, (size_t)std::max<int64_t>(nslice, 1), h->tr);
+    if (h->general)
+        launch_gen_upwind_fill(s, h->ginc(), h->Fall.p, h->well_src(), h->well_out(), h->phi_cell.p,
+                               h->phi_frac.p, h->phi_node.p, h->dt4.p, h->slice_ptr.p, h->tmeta.p, h->tcol.p,
+                               h->tval.p, h->tdiag.p);
+    else
+        launch_upwind_fill(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p,
+                           h->frac_nodes.p, h->dirichlet.p, h->node_cell_ptr.p, h->node_cell.p,
+                           h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p, h->F_cell_frac.p, h->F_frac.p,
+                           h->well_src(), h->well_out(), h->phi_cell.p, h->phi_frac.p, h->phi_node.p, h->dt4.p,
+                           h->slice_ptr.p, h->tmeta.p, h->tcol.p, h->tval.p, h->tdiag.p);
+    launch_upwind_pack(s, h->upwind(), h->tcol16.p, h->tbase.p);
+    h->have_op = true;
+    // initial state
+    if (c0_cell || c0_frac || c0_node) {
+        if (!c0_cell || !c0_node || (S.nf && !c0_frac))
+            throw Error(VAG_ERR_ARG, "give all of c0_cell, c0_frac, c0_node or none");
+        h->cur = 0;
+        VAG_HIP(hipMemcpyAsync(h->cbuf0.p, c0_cell, S.nc * sizeof(double), kind_in(mem), s));
+        if (S.nf)
+            VAG_HIP(hipMemcpyAsync(h->cbuf0.p + S.nc, c0_frac, S.nf * sizeof(double), kind_in(mem), s));
+        VAG_HIP(hipMemcpyAsync(h->cbuf0.p + S.nc + S.nf, c0_node, S.nn * sizeof(double), kind_in(mem), s));
+        if (mem == VAG_MEM_HOST) VAG_HIP(hipStreamSynchronize(s));
+    } else if (!h->have_c) {
+        h->cur = 0;
+        launch_fill(s, nrow, 0.0, h->cbuf0.p);
+    }
+    launch_set_dirichlet(s, S.nn, S.nc + S.nf, h->dirichlet.p, h->c_bar.p, h->c_cur());
+    launch_fill(s, 1, 1.0, h->cbuf0.p + nrow);  // the constant control volume
+    launch_fill(s, 1, 1.0, h->cbuf1.p + nrow);
+    h->have_c = true;
+    TransportPlan P;
+    P.N = n_steps;
+    P.dt = P.last_dt = dt;
+    P.total = total;
+    for (int i = 0; i < 3; ++i) P.dtb[i] = dtb[i];
+    if (t_final > 0) {
+        P.N = (int64_t)std::ceil(t_final / dt);
+        if (P.N < 1) P.N = 1;
+        P.last_dt = t_final - (double)(P.N - 1) * dt;
+        P.theta_last = P.last_dt / dt;
+    }
+    VAG_HIP(hipEventRecord(h->ev[6], s));
+    return P;
+}
+
+void transport_report(vag_handle *h, const TransportPlan &P, vag_transport_info *info) {
+    if (!info) return;
+    const Symbolic &S = h->S;
+    std::memset(info, 0, sizeof *info);
+    info->n_steps = P.N;
+    info->dt = P.dt;
+    info->last_dt = P.last_dt;
+    for (int i = 0; i < 3; ++i) info->dt_bounds[i] = P.dtb[i];
+    info->ms_setup = elapsed(h->ev[5], h->ev[6]);
+    info->ms_steps = elapsed(h->ev[6], h->ev[7]);
+    info->n_rows = (int64_t)S.nc + S.nf + S.nn;
+    info->t_nnz = h->h_cnt[0];
+    info->t_stored = P.total;
+}
+}  // namespace
+
 vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const double *c0_cell,
                          const double *c0_frac, const double *c0_node, vag_mem mem, vag_transport_info *info) {
     if (!h) return VAG_ERR_ARG;
     return guard(h, [&] {
-        if (!h->have_flux) throw Error(VAG_ERR_STATE, "vag_transport needs a pressure solve (or vag_set_fluxes) first");
-        if (n_steps < 0 || t_final < 0) throw Error(VAG_ERR_ARG, "negative step count or final time");
-        const Symbolic &S = h->S;
+        const TransportPlan P = transport_prepare(h, n_steps, t_final, c0_cell, c0_frac, c0_node, mem);
         hipStream_t s = h->stream;
-        const int64_t nrow = (int64_t)S.nc + S.nf + S.nn;
-        const int32_t nslice = (int32_t)((nrow + kSliceRows - 1) / kSliceRows);
-        VAG_HIP(hipEventRecord(h->ev[5], s));
-        if (h->general) {
-            launch_gen_cfl(s, h->ginc(), h->Fall.p, h->well_out(), h->phi_cell.p, h->phi_frac.p, h->phi_node.p,
-                           h->opt.cfl, h->rparts.p, h->dt4.p);
-            launch_gen_upwind_count(s, h->ginc(), h->Fall.p, h->well_src(), h->slice_width.p, h->tmeta.p,
-                                    h->slice_nnz.p);
-        } else {
-            launch_cfl(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
-                       h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
-                       h->F_cell_frac.p, h->F_frac.p, h->well_out(), h->phi_cell.p, h->phi_frac.p, h->phi_node.p,
-                       h->opt.cfl, h->rparts.p, h->dt4.p);
-            launch_upwind_count(s, S.nc, S.nf, S.nn, h->fmask.p, h->cell_frac.p, h->frac_cell.p, h->dirichlet.p,
-                                h->node_cell_ptr.p, h->node_cell.p, h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p,
-                                h->F_cell_frac.p, h->F_frac.p, h->well_src(), h->slice_width.p, h->tmeta.p,
-                                h->slice_nnz.p);
-        }
-        launch_slice_scan(s, nslice, h->slice_nnz.p, 1, h->slice_ptr.p, h->slice_nnz.p, h->cnt.p);
-        // segment A: the slices of cells and fracture faces, B: of nodes
-        launch_xcd_split(s, nslice, (int32_t)((S.nc + (int64_t)S.nf + kSliceRows - 1) / kSliceRows), h->slice_ptr.p,
-                         h->xsplit.p);
-        int64_t total = 0;
-        VAG_HIP(hipMemcpyAsync(&total, h->slice_ptr.p + nslice, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        VAG_HIP(hipMemcpyAsync(h->h_cnt, h->cnt.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-        VAG_HIP(hipMemcpyAsync(h->h_xsplit(), h->xsplit.p, 18 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        VAG_HIP(hipMemcpyAsync(h->h_scal, h->dt4.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-        VAG_HIP(hipStreamSynchronize(s));
-        for (int x = 0; x < 18; ++x) h->xlo[x] = h->h_xsplit()[x];
-        const double dt = h->h_scal[3];
-        double dtb[3] = {h->h_scal[0], h->h_scal[1], h->h_scal[2]};
-        if (!(dt < INFINITY)) throw Error(VAG_ERR_ARG, "no control volume has an outflow: CFL bound is infinite");
-        if ((size_t)total > h->tcol.n) {
-            h->tcol.alloc((size_t)total + (size_t)total / 8, h->tr);
-            h->tcol16.alloc((size_t)total + (size_t)total / 8, h->tr);
-            h->tval.alloc((size_t)total + (size_t)total / 8, h->tr);
-        }
-        ensure(h->tbase, (size_t)std::max<int64_t>(nslice, 1), h->tr);
-        if (h->general)
-            launch_gen_upwind_fill(s, h->ginc(), h->Fall.p, h->well_src(), h->well_out(), h->phi_cell.p,
-                                   h->phi_frac.p, h->phi_node.p, h->dt4.p, h->slice_ptr.p, h->tmeta.p, h->tcol.p,
-                                   h->tval.p, h->tdiag.p);
-        else
-            launch_upwind_fill(s, S.nc, S.nf, S.nn, h->hex8.p, h->fmask.p, h->cell_frac.p, h->frac_cell.p,
-                               h->frac_nodes.p, h->dirichlet.p, h->node_cell_ptr.p, h->node_cell.p,
-                               h->node_frac_ptr.p, h->node_frac.p, h->F_cell.p, h->F_cell_frac.p, h->F_frac.p,
-                               h->well_src(), h->well_out(), h->phi_cell.p, h->phi_frac.p, h->phi_node.p, h->dt4.p,
-                               h->slice_ptr.p, h->tmeta.p, h->tcol.p, h->tval.p, h->tdiag.p);
-        launch_upwind_pack(s, h->upwind(), h->tcol16.p, h->tbase.p);
-        h->have_op = true;
-        // initial state
-        if (c0_cell || c0_frac || c0_node) {
-            if (!c0_cell || !c0_node || (S.nf && !c0_frac))
-                throw Error(VAG_ERR_ARG, "give all of c0_cell, c0_frac, c0_node or none");
-            h->cur = 0;
-            VAG_HIP(hipMemcpyAsync(h->cbuf0.p, c0_cell, S.nc * sizeof(double), kind_in(mem), s));
-            if (S.nf)
-                VAG_HIP(hipMemcpyAsync(h->cbuf0.p + S.nc, c0_frac, S.nf * sizeof(double), kind_in(mem), s));
-            VAG_HIP(hipMemcpyAsync(h->cbuf0.p + S.nc + S.nf, c0_node, S.nn * sizeof(double), kind_in(mem), s));
-            if (mem == VAG_MEM_HOST) VAG_HIP(hipStreamSynchronize(s));
-        } else if (!h->have_c) {
-            h->cur = 0;
-            launch_fill(s, nrow, 0.0, h->cbuf0.p);
-        }
-        launch_set_dirichlet(s, S.nn, S.nc + S.nf, h->dirichlet.p, h->c_bar.p, h->c_cur());
-        launch_fill(s, 1, 1.0, h->cbuf0.p + nrow);  // the constant control volume
-        launch_fill(s, 1, 1.0, h->cbuf1.p + nrow);
-        h->have_c = true;
-        int64_t N = n_steps;
-        double theta_last = 1.0, last_dt = dt;
-        if (t_final > 0) {
-            N = (int64_t)std::ceil(t_final / dt);
-            if (N < 1) N = 1;
-            last_dt = t_final - (double)(N - 1) * dt;
-            theta_last = last_dt / dt;
-        }
-        VAG_HIP(hipEventRecord(h->ev[6], s));
-        for (int64_t k = 0; k < N; ++k) {
-            const double th = (k == N - 1) ? theta_last : 1.0;
+        for (int64_t k = 0; k < P.N; ++k) {
+            const double th = (k == P.N - 1) ? P.theta_last : 1.0;
             launch_transport_step(s, h->upwind(), h->c_cur(), h->c_next(), th, (k & 1) != 0);
             h->cur ^= 1;
         }
         VAG_HIP(hipEventRecord(h->ev[7], s));
         VAG_HIP(hipEventSynchronize(h->ev[7]));
-        if (info) {
-            std::memset(info, 0, sizeof *info);
-            info->n_steps = N;
-            info->dt = dt;
-            info->last_dt = last_dt;
-            for (int i = 0; i < 3; ++i) info->dt_bounds[i] = dtb[i];
-            info->ms_setup = elapsed(h->ev[5], h->ev[6]);
-            info->ms_steps = elapsed(h->ev[6], h->ev[7]);
-            info->n_rows = nrow;
-            info->t_nnz = h->h_cnt[0];
-            info->t_stored = total;
-        }
+        transport_report(h, P, info);
+    });
+}
+
+// Served jobs: the steps of a job's transport run in launches shared with
+// other jobs (launch_transport_batch), driven by the server.
+vag_status vag_serving_transport_begin(vag_handle *h, int64_t n_steps, double t_final, int64_t *N) {
+    if (!h || !N) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        h->plan = std::make_unique<TransportPlan>(transport_prepare(h, n_steps, t_final, nullptr, nullptr, nullptr,
+                                                                    VAG_MEM_HOST));
+        *N = h->plan->N;
+    });
+}
+void vag_serving_transport_job(vag_handle *h, int64_t k, TransportJob *J) {
+    const TransportPlan &P = *h->plan;
+    J->T = h->upwind();
+    J->c_in = h->c_cur();
+    J->c_out = h->c_next();
+    J->theta = (k == P.N - 1) ? P.theta_last : 1.0;
+    J->backward = (k & 1) != 0;
+    h->cur ^= 1;
+}
+hipEvent_t vag_serving_event(vag_handle *h, int i) { return h->ev[i]; }
+vag_status vag_serving_transport_end(vag_handle *h, vag_transport_info *info) {
+    if (!h || !h->plan) return VAG_ERR_ARG;
+    return guard(h, [&] {
+        VAG_HIP(hipEventSynchronize(h->ev[7]));
+        transport_report(h, *h->plan, info);
+        h->plan.reset();
     });
 }
 

@@ -501,6 +501,42 @@ void launch_xcd_split(hipStream_t s, int32_t nslice, int32_t sa, const int64_t *
 // backward: sweep each XCD's slices in reverse order (alternate steps)
 void launch_transport_step(hipStream_t s, const UpwindOp &T, const double *c_in, double *c_out, double theta,
                            bool backward);
+// blocks of one step's launch over T (a multiple of 8)
+int32_t transport_step_blocks(const UpwindOp &T);
+// One step of up to kBatchJobs operators in one launch (served jobs): each
+// operator's rows get exactly the arithmetic of launch_transport_step.
+constexpr int kBatchJobs = 8;
+struct TransportJob {
+    UpwindOp T;
+    const double *c_in;
+    double *c_out;
+    double theta;
+    int32_t backward;
+};
+struct TransportBatch {
+    int32_t n;
+    int32_t blk[kBatchJobs + 1];  // first block of each job (set by the launcher)
+    TransportJob job[kBatchJobs];
+};
+static_assert(sizeof(TransportBatch) <= 2048, "kernel argument block");
+void launch_transport_batch(hipStream_t s, TransportBatch &B);
+
+}  // namespace vag
+
+// The server's side of a served job's transport: begin prepares it (time
+// step, upwind operator, initial state) on the handle's stream and gives the
+// step count; job(k) describes step k for a batched launch and moves the
+// handle to the next state; the server records event 6 before the job's
+// first step and event 7 after its last, on the stream it launches on; end
+// waits for event 7 and reports.
+extern "C" {
+vag_status vag_serving_transport_begin(vag_handle *h, int64_t n_steps, double t_final, int64_t *N);
+void vag_serving_transport_job(vag_handle *h, int64_t k, vag::TransportJob *J);
+hipEvent_t vag_serving_event(vag_handle *h, int i);
+vag_status vag_serving_transport_end(vag_handle *h, vag_transport_info *info);
+}
+
+namespace vag {
 // Peaceman wells (wells.hip).  wsrc[f] = c_inj Q^+ (tracer injected into face
 // f per unit time), wout[f] = Q^- (volume produced); the upwind operator's
 // injection entries point at the constant control volume (index nc + nf + nn,

@@ -110,7 +110,8 @@ class vag_job_result(C.Structure):
 class vag_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("queued", C.c_int64), ("running", C.c_int64), ("finished", C.c_int64),
                 ("budget", C.c_size_t), ("bytes_in_use", C.c_size_t), ("peak_bytes_in_use", C.c_size_t),
-                ("cached_bytes", C.c_size_t), ("cached_handles", C.c_int)]
+                ("cached_bytes", C.c_size_t), ("cached_handles", C.c_int), ("step_launches", C.c_int64),
+                ("job_steps", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

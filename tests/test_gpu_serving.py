@@ -1,7 +1,9 @@
 """GPU tests of the serving loop (vag_server_*): every job's result is the same
-alone and in the mix (bitwise: a job runs the same kernels in the same order on
-its own handle whatever else is on the device), admission by footprint keeps
-the bytes in use within the budget, the footprint estimate bounds the real
+alone and in the mix (bitwise: a job's rows get the same arithmetic in the same
+order whatever else is on the device, its transport steps included, which run
+batched with other jobs' steps), the batched steps equal a lone handle's, jobs
+whose transports overlap share launches, admission by footprint keeps the
+bytes in use within the budget, the footprint estimate bounds the real
 footprint, cached handles are reused, cancel and out-of-memory rejection.
 """
 import numpy as np
@@ -65,6 +67,7 @@ def test_alone_equals_mix_bitwise(mode):
     alone, _ = _run(vag, jobs, mode, workers=1, together=False)
     mix, stats = _run(vag, jobs, mode, workers=4, together=True)
     assert stats["finished"] == len(jobs) and stats["bytes_in_use"] == 0
+    assert stats["job_steps"] == sum(p.n_steps for p in jobs) >= stats["step_launches"] > 0
     overlap = 0
     for a, m in zip(alone, mix):
         assert a["status"] == 0 and m["status"] == 0, (a["message"], m["message"])
@@ -76,6 +79,24 @@ def test_alone_equals_mix_bitwise(mode):
     overlap = sum(1 for i in range(1, len(iv)) if iv[i][0] < max(e for _, e in iv[:i]))
     assert overlap > 0
     print(f"{mode}: {overlap} of {len(mix)} jobs started while another was running")
+
+
+def test_transport_steps_share_launches():
+    """Eight jobs with long transports on eight workers: their steps run in
+    shared launches (fewer launches than steps), and every result equals the
+    job run alone, bitwise."""
+    vag = _vag()
+    jobs = [synth.random_problem((8, 7, 6), 200 + j, n_patches=3, n_steps=300) for j in range(8)]
+    alone, st1 = _run(vag, jobs, "fp64", workers=1, together=False)
+    assert st1["step_launches"] == st1["job_steps"] == 8 * 300  # one job at a time: one job per launch
+    mix, st8 = _run(vag, jobs, "fp64", workers=8, together=True)
+    assert st8["job_steps"] == 8 * 300
+    print(f"{st8['job_steps']} steps in {st8['step_launches']} launches")
+    assert st8["step_launches"] < st8["job_steps"]
+    for a, m in zip(alone, mix):
+        assert a["status"] == 0 and m["status"] == 0
+        for k in OUT:
+            np.testing.assert_array_equal(a[k], m[k], err_msg=k)
 
 
 def test_served_job_matches_handle_and_oracle():
