@@ -213,7 +213,9 @@ def serving_bench(vag, synth, n_jobs, workers, budget, seed=4):
     give the throughput of each mode (after an untimed pass of each);
     Poisson arrivals at 0.7 x the FP64 saturation rate give p50/p99 latency
     (scheduled arrival -> outputs on the host), the same arrival times for
-    both modes."""
+    both modes.  The transport steps of the jobs below 2^18 control volumes
+    run batched; batched_job_steps / batched_step_launches is how many jobs
+    a launch took on average."""
     import time as _t
     t0 = _t.perf_counter()
     jobs = [synth.config4_job(j) for j in range(n_jobs)]
@@ -251,7 +253,8 @@ def serving_bench(vag, synth, n_jobs, workers, budget, seed=4):
                                                            r["solve"]["ms_solve"] + r["solve"]["ms_fluxes"]
                                                            for r in res])), 2),
                     mean_iterations=round(float(np.mean([r["solve"]["iterations"] for r in res])), 1),
-                    peak_GB=round(st["peak_bytes_in_use"] / 1e9, 2), budget_GB=round(st["budget"] / 1e9, 2))
+                    peak_GB=round(st["peak_bytes_in_use"] / 1e9, 2), budget_GB=round(st["budget"] / 1e9, 2),
+                    batched_job_steps=st["job_steps"], batched_step_launches=st["step_launches"])
 
     log(f"serving: {n_jobs} jobs generated in {gen_s:.1f} s")
     zero = [0.0] * n_jobs
