@@ -114,6 +114,9 @@ void finish_symbolic_pattern(Symbolic &S, const std::vector<const int32_t *> *ro
         const int32_t n = S.nunk;
         std::vector<int32_t> order(n);
         auto len = [&](int32_t r) { return S.row_ptr[r + 1] - S.row_ptr[r]; };
+        // every row holds its own unknown, through a cell of its node or face
+        for (int32_t r = 0; r < nfree; ++r)
+            if (len(r) < 1) throw Error(VAG_ERR_MESH, "a free node of no cell (system row " + std::to_string(r) + ")");
         // a counting sort by decreasing length inside each window (stable)
         auto windows = [&](int32_t b0, int32_t b1) {
             const int64_t nw = ((int64_t)b1 - b0 + kSortWindow - 1) / kSortWindow;
@@ -600,8 +603,8 @@ void finish_symbolic_lengths(Symbolic &S, const int32_t *len) {
     S.row_ptr.assign((size_t)n + 1, 0);
     int64_t total = 0;
     for (int32_t r = 0; r < n; ++r) {
-        total += len[r];
-        if (len[r] < 1 || total >= INT32_MAX) throw Error(VAG_ERR_UNSUPPORTED, "system has more than 2^31 nonzeros");
+        total += std::max(len[r], 0);
+        if (total >= INT32_MAX) throw Error(VAG_ERR_UNSUPPORTED, "system has more than 2^31 nonzeros");
         S.row_ptr[r + 1] = (int32_t)total;
     }
     S.nnz = total;

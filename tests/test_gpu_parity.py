@@ -287,6 +287,20 @@ def test_inverted_cell_reported():
     assert e.value.status == vag.VAG_ERR_MESH and "cell 0" in str(e.value)
 
 
+def test_free_node_of_no_cell_rejected():
+    """A node that no cell names and no Dirichlet flag fixes has an empty
+    conservation equation: vag_create reports it as a mesh error."""
+    from paper_1602_03641_amd import vag
+    _torch()
+    p = synth.cartesian_problem(2)
+    p.xyz = np.vstack([p.xyz, [[2.0, 2.0, 2.0]]])
+    for k in ("dirichlet", "p_bar", "c_bar"):
+        setattr(p, k, np.append(getattr(p, k), 0))
+    with pytest.raises(vag.VagError) as e:
+        vag.Handle(p)
+    assert e.value.status == vag.VAG_ERR_MESH and "no cell" in str(e.value)
+
+
 def test_transport_before_solve():
     from paper_1602_03641_amd import vag
     _torch()
