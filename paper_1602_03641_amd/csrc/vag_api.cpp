@@ -8,6 +8,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <unordered_map>
 
 #include "amg.h"
@@ -741,6 +742,51 @@ void porous_volumes(vag_handle *h, hipStream_t s) {
 }
 }  // namespace
 
+namespace {
+// From host memory a copy holds the calling thread; so vag_create sends the
+// per-node and per-cell coefficients up from a thread (and stream) of their
+// own while it builds the system pattern, and waits for them at its end.
+struct InputUploads {
+    struct Copy {
+        void *dst;
+        const void *src;
+        size_t bytes;
+    };
+    std::vector<Copy> copies;
+    std::thread th;
+    bool failed = false;
+    template <class T>
+    void add(vag_handle *h, DBuf<T> &d, const T *src, size_t n) {
+        if (!n) return;
+        if (!src) throw Error(VAG_ERR_ARG, "null input array");
+        if (d.n < n) d.alloc(n, h->tr);
+        copies.push_back(Copy{d.p, src, n * sizeof(T)});
+    }
+    void start() {
+        int dev = 0;
+        VAG_HIP(hipGetDevice(&dev));
+        th = std::thread([this, dev] {
+            hipStream_t us = nullptr;
+            bool ok = hipSetDevice(dev) == hipSuccess && hipStreamCreateWithFlags(&us, hipStreamNonBlocking) == hipSuccess;
+            for (const Copy &c : copies)
+                ok = ok && hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyHostToDevice, us) == hipSuccess;
+            if (us) {
+                ok = hipStreamSynchronize(us) == hipSuccess && ok;
+                (void)hipStreamDestroy(us);
+            }
+            failed = !ok;
+        });
+    }
+    void finish() {
+        if (th.joinable()) th.join();
+        if (failed) throw Error(VAG_ERR_HIP, "uploading the coefficients failed");
+    }
+    ~InputUploads() {
+        if (th.joinable()) th.join();
+    }
+};
+}  // namespace
+
 extern "C" {
 
 const char *vag_version(void) { return "libvag 0.1 (gfx950)"; }
@@ -867,6 +913,21 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         auto dir = host_copy(bc->node_dirichlet, (size_t)nn, mem, h->stream);
         h->general = mesh->hex8 == nullptr;
         DBuf<int32_t> pat_rp, pat_cl;  // the system pattern (CSR), for the sliced-ELL columns
+        InputUploads inputs;           // once the host symbolic phase has accepted the mesh
+        auto start_inputs = [&] {
+            if (mem != VAG_MEM_HOST) return;
+            inputs.add(h, h->xyz, mesh->node_xyz, 3 * (size_t)nn);
+            inputs.add(h, h->perm, rock->perm, 6 * (size_t)nc);
+            inputs.add(h, h->poro, rock->porosity, (size_t)nc);
+            if (nf) {
+                inputs.add(h, h->fwidth, frac->width, (size_t)nf);
+                inputs.add(h, h->fperm, frac->perm, (size_t)nf);
+                inputs.add(h, h->fporo, frac->porosity, (size_t)nf);
+            }
+            inputs.add(h, h->p_bar, bc->p_bar, (size_t)nn);
+            if (bc->c_bar) inputs.add(h, h->c_bar, bc->c_bar, (size_t)nn);
+            inputs.start();
+        };
         if (!h->general) {
             // the caller's host array as it is; device arrays come over first
             std::vector<int32_t> hex8_copy;
@@ -880,6 +941,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
                 nf ? host_copy(frac->face_nodes, 4 * (size_t)nf, mem, h->stream) : std::vector<int32_t>();
             build_symbolic(nn, nc, nf, hex8, fnodes.data(), dir.data(), h->opt.eliminate_frac_faces != 0, h->S,
                            true);
+            start_inputs();
             upload(h, h->hex8, mesh->hex8, 8 * (size_t)nc, mem);
             upload_vec(h, h->frac_nodes, fnodes);
             upload_vec(h, h->frac_slot, h->S.frac_slot);
@@ -917,6 +979,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
                 nf ? host_copy(frac->face_ids, (size_t)nf, mem, h->stream) : std::vector<int32_t>();
             build_symbolic_general(nn, nc, nF, cfp.data(), cf.data(), fnp.data(), fnd.data(), nf, fid.data(),
                                    dir.data(), h->S, h->G);
+            start_inputs();
             const GenSym &G = h->G;
             upload_vec(h, h->g_cnode_ptr, G.cnode_ptr);
             upload_vec(h, h->g_cnode, G.cnode);
@@ -943,7 +1006,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         const Symbolic &S = h->S;
         h->mu = rock->mu;
 
-        upload(h, h->xyz, mesh->node_xyz, 3 * (size_t)nn, mem);
+        if (mem != VAG_MEM_HOST) upload(h, h->xyz, mesh->node_xyz, 3 * (size_t)nn, mem);
         upload_vec(h, h->dirichlet, dir);
         if (h->general) {
             upload_vec(h, h->fmask, S.fmask);
@@ -985,16 +1048,18 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         }
         h->Gb.alloc(std::max<int64_t>(S.grp_off.back(), 1), h->tr);
 
-        upload(h, h->perm, rock->perm, 6 * (size_t)nc, mem);
-        upload(h, h->poro, rock->porosity, (size_t)nc, mem);
-        if (nf) {
-            upload(h, h->fwidth, frac->width, (size_t)nf, mem);
-            upload(h, h->fperm, frac->perm, (size_t)nf, mem);
-            upload(h, h->fporo, frac->porosity, (size_t)nf, mem);
+        if (mem != VAG_MEM_HOST) {
+            upload(h, h->perm, rock->perm, 6 * (size_t)nc, mem);
+            upload(h, h->poro, rock->porosity, (size_t)nc, mem);
+            if (nf) {
+                upload(h, h->fwidth, frac->width, (size_t)nf, mem);
+                upload(h, h->fperm, frac->perm, (size_t)nf, mem);
+                upload(h, h->fporo, frac->porosity, (size_t)nf, mem);
+            }
+            upload(h, h->p_bar, bc->p_bar, (size_t)nn, mem);
+            if (bc->c_bar) upload(h, h->c_bar, bc->c_bar, (size_t)nn, mem);
         }
-        upload(h, h->p_bar, bc->p_bar, (size_t)nn, mem);
-        if (bc->c_bar) upload(h, h->c_bar, bc->c_bar, (size_t)nn, mem);
-        else {
+        if (!bc->c_bar) {
             h->c_bar.alloc(nn, h->tr);
             launch_fill(h->stream, nn, 0.0, h->c_bar.p);
         }
@@ -1048,6 +1113,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         h->h_pcg = static_cast<PcgState *>(pinned_get(sizeof(PcgState)));
         h->h_scal = static_cast<double *>(pinned_get(16 * sizeof(double)));
         for (auto &e : h->ev) VAG_HIP(hipEventCreate(&e));
+        inputs.finish();
         if (h->general) return;
         // system positions of the eliminated groups' node pairs
         h->grp_pos.alloc(std::max<int64_t>(S.grp_poff.back(), 1), h->tr);
