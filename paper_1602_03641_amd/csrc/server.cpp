@@ -4,18 +4,19 @@
 // takes the head job when its estimated device footprint fits in the budget
 // left by the running jobs and the cached handles (idle cached handles are
 // evicted, least recently used first, to make room).  Each job runs on a
-// handle of its own (vag_create, the pressure solve and the transport's set-up
-// on the worker's stream, outputs copied to the caller's host buffers), so
-// jobs on different workers overlap on the device.  The transport steps of
-// the smaller jobs in their transport phase run batched: per lane of job
-// sizes, a batcher thread launches, tick after tick on a stream of its own,
-// one kernel that takes one step of every active job of the lane (up to
-// kBatchJobs per launch); a job joins at the next tick once its set-up is
-// done and leaves after its last step (a large job's steps fill the device
-// alone, and its worker launches them).  The worker hands the job over after the set-up and
-// takes the next one; a finisher thread waits for the job's last step,
-// copies its outputs and completes it.  Each row of
-// each job gets the arithmetic of the job run alone, so results are the
+// handle of its own (vag_create, the pressure solve and the transport's
+// set-up on the worker's stream, outputs copied to the caller's host
+// buffers), so jobs on different workers overlap on the device.
+//
+// The transport steps of the jobs below kBatchRows control volumes run
+// batched: per lane of job sizes, a batcher thread launches, tick after tick
+// on a stream of its own, one kernel that takes one step of every active job
+// of the lane (up to kBatchJobs per launch).  A job joins at the next tick
+// once its set-up is done and leaves after its last step; its worker hands it
+// over after the set-up and takes the next job, and a finisher thread waits
+// for the last step, copies the outputs and completes the job.  A larger
+// job's steps fill the device alone, and its worker launches them.  Each row
+// of each job gets the arithmetic of the job run alone, so results are the
 // same alone and in the mix.
 #include <algorithm>
 #include <chrono>
@@ -55,13 +56,13 @@ struct Job {
     size_t est = 0;
     enum { QUEUED, RUNNING, DONE } state = QUEUED;
     vag_job_result res{};
-    // a job whose transport steps run batched: its handle, the bytes it is
-    // charged for, the solve's status, the event its set-up ends with
-    size_t charged = 0;
-    vag_handle *h = nullptr;
+    size_t charged = 0;  // the bytes it holds of the budget while it runs
     vag_status solve_status = VAG_OK;
+    // a job whose transport steps run batched: its handle, the event its
+    // set-up ends with, and the finisher that completes it
+    vag_handle *h = nullptr;
     hipEvent_t ready = nullptr;
-    int fin = 0;  // the finisher that completes it
+    int fin = 0;
 };
 
 struct Cached {
