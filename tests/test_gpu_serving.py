@@ -99,6 +99,30 @@ def test_transport_steps_share_launches():
             np.testing.assert_array_equal(a[k], m[k], err_msg=k)
 
 
+def test_served_final_time_matches_handle():
+    """Jobs run to a final time (the last step a fraction of dt) in the mix:
+    the batched steps, the partial last one included, equal a lone handle's
+    transport to that time, bitwise."""
+    vag = _vag()
+    jobs = [synth.random_problem((7, 6, 5), 300 + j, n_patches=3, n_steps=0) for j in range(4)]
+    srv = vag.Server(n_workers=4)
+    try:
+        ids = [srv.submit(p, t_final=0.037 * (j + 1), rtol=1e-12, max_iter=20000) for j, p in enumerate(jobs)]
+        res = [srv.wait(i) for i in ids]
+    finally:
+        srv.close()
+    for j, (p, r) in enumerate(zip(jobs, res)):
+        assert r["status"] in (0, 1), r["message"]
+        h = vag.Handle(p, rtol=1e-12, max_iter=20000)
+        h.solve_pressure()
+        t = h.transport(t_final=0.037 * (j + 1))
+        assert t["last_dt"] < t["dt"] and r["transport"]["n_steps"] == t["n_steps"]
+        d = vag.to_numpy(h.concentration())
+        for k in ("c_cell", "c_frac", "c_node"):
+            np.testing.assert_array_equal(r[k], d[k], err_msg=k)
+        h.close()
+
+
 def test_served_job_matches_handle_and_oracle():
     vag = _vag()
     p = synth.random_problem((9, 7, 6), 3, n_patches=5, n_steps=25)
