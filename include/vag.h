@@ -135,7 +135,8 @@ typedef struct {
 } vag_fractures;
 
 /* Matrix rock: symmetric positive definite Lambda_m per cell packed
- * [xx, yy, zz, xy, xz, yz], porosity phi_m per cell, constant viscosity mu. */
+ * [xx, yy, zz, xy, xz, yz] (checked at each vag_solve_pressure), porosity
+ * phi_m per cell, constant viscosity mu. */
 typedef struct {
     const double *perm;      /* [n_cells][6] */
     const double *porosity;  /* [n_cells] */
@@ -281,7 +282,11 @@ vag_status vag_set_options(vag_handle *h, const vag_options *opt);
  * the cell unknowns (eq eqschur), Dirichlet columns to the right-hand side,
  * preconditioned Krylov solve, cell recovery (eq eqschurcell), then the fluxes
  * F_{K,nu} and F_{sigma,s} kept on the device for transport.
- * Returns VAG_WARN_NOT_CONVERGED with the last iterate if rtol is not reached.
+ * Returns VAG_WARN_NOT_CONVERGED with the last iterate if rtol is not reached;
+ * VAG_ERR_ARG, before any solving, naming the first cell whose permeability
+ * tensor is not symmetric positive definite (leading minors positive, entries
+ * finite) or the first fracture face without positive width and permeability;
+ * VAG_ERR_MESH naming a cell with a non-positive sub-tetrahedron.
  */
 vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info);
 

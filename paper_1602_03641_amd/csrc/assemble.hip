@@ -244,6 +244,30 @@ __device__ inline void add_sys(const AsmArgs &g, int32_t r, int32_t c, int32_t n
     }
 }
 
+// The coefficients the scheme takes (§2: Lambda_m symmetric positive
+// definite; d_f and Lambda_f positive): a cell's packed tensor passes when
+// its leading principal minors are positive and every entry is finite, a
+// fracture face when its width and permeability are positive and finite.
+// bad[0] receives the least failing cell, bad[1] the least failing face.
+__global__ __launch_bounds__(256) void check_coef_kernel(int32_t nc, const double *__restrict__ perm, int32_t nf,
+                                                         const double *__restrict__ fwidth,
+                                                         const double *__restrict__ fperm, int *bad) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < nc) {
+        const double *L = perm + 6 * i;
+        const double xx = L[0], yy = L[1], zz = L[2], xy = L[3], xz = L[4], yz = L[5];
+        const double m2 = xx * yy - xy * xy;
+        const double m3 = xx * (yy * zz - yz * yz) - xy * (xy * zz - yz * xz) + xz * (xy * yz - yy * xz);
+        bool fin = true;
+        for (int k = 0; k < 6; ++k) fin &= isfinite(L[k]);
+        if (!(fin && xx > 0.0 && m2 > 0.0 && m3 > 0.0)) atomicMin(&bad[0], (int)i);
+    } else if (i < (int64_t)nc + nf) {
+        const int32_t f = (int32_t)(i - nc);
+        const double w = fwidth[f], k = fperm[f];
+        if (!(isfinite(w) && isfinite(k) && w > 0.0 && k > 0.0)) atomicMin(&bad[1], f);
+    }
+}
+
 // Slots of the M_K columns in the node rows, found once per handle (the
 // per-solve assembly then adds at known slots).  A row of up to kPosRegs
 // columns is read into registers once and a column's slot is the count of
@@ -653,6 +677,15 @@ void launch_frac_local(hipStream_t s, int32_t nf, const double *xyz, const int32
     if (nf <= 0) return;
     hipLaunchKernelGGL(vag_frac_kernel, dim3(nblk(nf, 256)), dim3(256), 0, s, nf, xyz, frac_nodes, width,
                        perm, 1.0 / mu, A5, area);
+    VAG_HIP(hipGetLastError());
+}
+
+void launch_check_coef(hipStream_t s, int32_t nc, const double *perm, int32_t nf, const double *fwidth,
+                       const double *fperm, int *bad) {
+    const int64_t n = (int64_t)nc + nf;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(check_coef_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nc, perm, nf, fwidth,
+                       fperm, bad);
     VAG_HIP(hipGetLastError());
 }
 

@@ -168,6 +168,7 @@ struct vag_handle {
     // assembly
     DBuf<double> aK, rK, AKK, vol, fside, A5, area, A, b, dinv;
     DBuf<int> bad;
+    DBuf<int> coef_bad;  // [2]: first cell / fracture face with invalid coefficients
     // Krylov
     DBuf<double> x, r, z, p, q, parts, rparts, scal;
     DBuf<PcgState> pcg;  // [0] the solve, [1] kernel timing (never done)
@@ -1078,6 +1079,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         h->b.alloc(n, h->tr);
         h->dinv.alloc(n, h->tr);
         h->bad.alloc(1, h->tr);
+        h->coef_bad.alloc(2, h->tr);
         for (auto *v : {&h->x, &h->r, &h->z, &h->p, &h->q}) v->alloc(n, h->tr);
         h->parts.alloc(6 * (size_t)kReduceBlocks, h->tr);
         h->rparts.alloc(4 * (size_t)kReduceBlocks, h->tr);
@@ -1305,8 +1307,21 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
         hipStream_t s = h->stream;
         const int32_t n = S.nunk;
         VAG_HIP(hipEventRecord(h->ev[0], s));
-        // 1. local matrices and fracture matrices
+        // 1. local matrices and fracture matrices (their coefficients checked on the way)
         VAG_HIP(hipMemsetAsync(h->bad.p, 0x7f, sizeof(int), s));
+        VAG_HIP(hipMemsetAsync(h->coef_bad.p, 0x7f, 2 * sizeof(int), s));
+        launch_check_coef(s, S.nc, h->perm.p, S.nf, h->fwidth.p, h->fperm.p, h->coef_bad.p);
+        {
+            int cb[2] = {0, 0};
+            VAG_HIP(hipMemcpyAsync(cb, h->coef_bad.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+            VAG_HIP(hipStreamSynchronize(s));
+            if (cb[0] != 0x7f7f7f7f)
+                throw Error(VAG_ERR_ARG,
+                            "cell " + std::to_string(cb[0]) + ": permeability tensor is not symmetric positive definite");
+            if (cb[1] != 0x7f7f7f7f)
+                throw Error(VAG_ERR_ARG,
+                            "fracture face " + std::to_string(cb[1]) + ": width and permeability must be positive");
+        }
         if (h->general) {
             // 2. the Schur blocks gathered into the system, Dirichlet columns to b
             const GenMesh g = h->gmesh();

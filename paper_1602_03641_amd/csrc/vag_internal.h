@@ -342,6 +342,11 @@ void launch_pattern_sort(hipStream_t s, int32_t n, const int32_t *row_ptr, const
 // Sliced-ELL columns, row lengths and diagonal positions from the CSR pattern.
 void launch_sell_fill(hipStream_t s, int32_t n, int64_t nslice, const int32_t *row_ptr, const int32_t *col,
                       const int64_t *sell_ptr, int32_t *sell_col, int32_t *row_len, int32_t *diag_pos);
+// bad[0] = the least cell whose tensor is not symmetric positive definite,
+// bad[1] = the least fracture face without positive width and permeability
+// (both left as they were where none fails)
+void launch_check_coef(hipStream_t s, int32_t nc, const double *perm, int32_t nf, const double *fwidth,
+                       const double *fperm, int *bad);
 // node_pos (see AsmArgs) for the rows of the free nodes, once per handle.
 void launch_node_pos(hipStream_t s, const AsmArgs &g, uint16_t *node_pos);
 // System positions of the node pairs of each eliminated group.

@@ -287,6 +287,36 @@ def test_inverted_cell_reported():
     assert e.value.status == vag.VAG_ERR_MESH and "cell 0" in str(e.value)
 
 
+@pytest.mark.parametrize("what", ["negative", "indefinite", "nan", "frac_perm", "frac_width"])
+def test_invalid_coefficients_rejected(what):
+    """A permeability tensor that is not symmetric positive definite (a
+    negative diagonal, positive diagonals with a leading 2x2 minor below zero,
+    a NaN), or a fracture face with zero permeability or negative width:
+    vag_solve_pressure names the first offending cell or face."""
+    from paper_1602_03641_amd import vag
+    _torch()
+    p = synth.random_problem((6, 5, 5), 36, n_patches=3, n_steps=0)
+    p.perm = p.perm.copy()
+    if what == "negative":
+        p.perm[7, 1] = -1.0
+    elif what == "indefinite":
+        p.perm[7, :] = [1.0, 1.0, 1.0, 2.0, 0.0, 0.0]   # xx yy - xy^2 = -3
+    elif what == "nan":
+        p.perm[7, 5] = np.nan
+    elif what == "frac_perm":
+        p.frac_perm = p.frac_perm.copy()
+        p.frac_perm[2] = 0.0
+    else:
+        p.frac_width = p.frac_width.copy()
+        p.frac_width[2] = -0.01
+    h = vag.Handle(p)
+    with pytest.raises(vag.VagError) as e:
+        h.solve_pressure()
+    assert e.value.status == vag.VAG_ERR_ARG
+    assert ("cell 7:" if what in ("negative", "indefinite", "nan") else "fracture face 2:") in str(e.value)
+    h.close()
+
+
 def test_free_node_of_no_cell_rejected():
     """A node that no cell names and no Dirichlet flag fixes has an empty
     conservation equation: vag_create reports it as a mesh error."""
