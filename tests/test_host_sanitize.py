@@ -5,7 +5,10 @@ group elimination; general cells) and the C oracle (a whole run: system,
 solve, residual, both volume rules, CFL, transport, wells) are built with
 -fsanitize=address,undefined for the host, and run on small meshes with
 fractures, intersections and wells, plus inputs the symbolic phase must
-reject.  A sanitizer report, a leak or a wrong result code fails the test.
+reject.  The host chunk pool the symbolic phases run on is driven by several
+submitting threads at once, nested calls and a throwing chunk under the thread
+sanitizer and under the address one.  A sanitizer report, a leak or a wrong
+result code fails the test.
 """
 import os
 import shutil
@@ -49,6 +52,19 @@ def tools(tmp_path_factory):
                   "-I" + os.path.join(ROOT, "oracle"), os.path.join(HERE, "oracle_check.c"),
                   os.path.join(ROOT, "oracle", "vag_oracle.c"), "-lm"])
     return tmp, sym, orc
+
+
+@pytest.mark.parametrize("san", [["-fsanitize=thread"], SAN])
+def test_chunk_pool(tmp_path, san):
+    if not shutil.which("g++"):
+        pytest.skip("no compiler")
+    exe = _build(str(tmp_path), "pool_check", ["g++", "-O1", "-g", "-std=c++17", *san, "-I" + CSRC,
+                                               os.path.join(HERE, "pool_check.cpp"), "-lpthread"])
+    env = dict(ENV, TSAN_OPTIONS="halt_on_error=1:exitcode=88")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    out = r.stdout + r.stderr
+    assert "ThreadSanitizer" not in out and "AddressSanitizer" not in out and "runtime error" not in out, out[-3000:]
+    assert r.returncode == 0 and "pool ok" in r.stdout, (r.returncode, out[-2000:])
 
 
 def _run(exe, path):
