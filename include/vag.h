@@ -469,6 +469,10 @@ vag_status vag_trim_memory(void);
  * admission by footprint.
  */
 size_t vag_estimate_footprint(int64_t n_nodes, int64_t n_cells, int64_t n_frac, const vag_options *opt);
+/* The same for a mesh in either form (host arrays): a hex8 mesh as above; a
+ * mesh given by its faces adds its local matrices (from each cell's face and
+ * node counts) and flux incidences.  0 for an inconsistent mesh. */
+size_t vag_estimate_footprint_mesh(const vag_mesh *mesh, int64_t n_frac, const vag_options *opt);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of independent Darcy + transport jobs.       */
@@ -477,7 +481,7 @@ size_t vag_estimate_footprint(int64_t n_nodes, int64_t n_cells, int64_t n_frac, 
  * A server owns n_workers host threads, each with its own HIP stream on the
  * device that is current when the server is created.  Submitted jobs wait in
  * one FIFO queue; the head job starts on the first free worker as soon as its
- * estimated footprint (vag_estimate_footprint) fits in what the running jobs
+ * estimated footprint (vag_estimate_footprint_mesh) fits in what the running jobs
  * and the cached handles leave of hbm_budget.  Jobs on different workers run
  * concurrently, so their kernels overlap on the device.  The transport steps
  * of jobs below 2^18 control volumes are batched per launch: per size class
@@ -540,8 +544,10 @@ typedef struct {
 vag_status vag_server_create(size_t hbm_budget, int n_workers, vag_server **out);
 
 /* Copies the job's input arrays (host memory) and queues it; returns at once.
+ * The mesh may take either form (hex8, or faces with fracture face_ids).
  * VAG_ERR_OOM when the job's estimate exceeds the whole budget, VAG_ERR_ARG
- * for missing inputs, VAG_ERR_UNSUPPORTED for a mesh without hex8. */
+ * for missing inputs or face lists whose offsets do not start at 0 and never
+ * decrease (the rest of the mesh is checked by vag_create when the job runs). */
 vag_status vag_server_submit(vag_server *s, const vag_job *job, uint64_t *job_id);
 
 /* Waits up to timeout_s seconds (< 0: no limit) for the job.  VAG_OK: *res is

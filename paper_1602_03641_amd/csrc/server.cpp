@@ -46,6 +46,11 @@ struct Job {
     int64_t nn = 0, nc = 0, nf = 0;
     std::vector<double> xyz, fwidth, fperm, fporo, perm, poro, p_bar, c_bar;
     std::vector<int32_t> hex8, fnodes;
+    // a mesh given by its faces (hex8 empty): cell -> faces, face -> nodes,
+    // fracture faces by face index
+    int64_t n_faces = 0;
+    std::vector<int64_t> cell_face_ptr, face_node_ptr;
+    std::vector<int32_t> cell_faces, face_nodes, face_ids;
     std::vector<uint8_t> dir;
     double mu = 1.0;
     vag_options opt{};
@@ -387,8 +392,17 @@ vag_handle *vag_server::finish_outputs(Job *j, vag_handle *h, hipStream_t s) {
 vag_server::Outcome vag_server::run(Job *j, int w, vag_handle *h) {
     hipStream_t s = streams[w];
     vag_job_result &r = j->res;
-    vag_mesh mesh{j->nn, j->nc, j->xyz.data(), j->hex8.data()};
+    vag_mesh mesh{j->nn, j->nc, j->xyz.data(), j->hex8.empty() ? nullptr : j->hex8.data()};
     vag_fractures fr{j->nf, j->fnodes.data(), j->fwidth.data(), j->fperm.data(), j->fporo.data()};
+    if (j->hex8.empty()) {
+        mesh.n_faces = j->n_faces;
+        mesh.cell_face_ptr = j->cell_face_ptr.data();
+        mesh.cell_faces = j->cell_faces.data();
+        mesh.face_node_ptr = j->face_node_ptr.data();
+        mesh.face_nodes = j->face_nodes.data();
+        fr.face_nodes = nullptr;
+        fr.face_ids = j->face_ids.data();
+    }
     vag_rock rock{j->perm.data(), j->poro.data(), j->mu};
     vag_bc bc{j->dir.data(), j->p_bar.data(), j->c_bar.empty() ? nullptr : j->c_bar.data()};
     r.footprint_estimate = j->est;
@@ -566,16 +580,33 @@ vag_status vag_server_submit(vag_server *s, const vag_job *job, uint64_t *job_id
     const vag_mesh *m = job->mesh;
     const int64_t nn = m->n_nodes, nc = m->n_cells, nf = job->frac ? job->frac->n_frac : 0;
     if (nn <= 0 || nc <= 0 || nf < 0 || job->n_steps < 0 || job->t_final < 0) return VAG_ERR_ARG;
-    if (!m->hex8) return VAG_ERR_UNSUPPORTED;  // jobs take hex8 meshes
     auto j = std::make_unique<Job>();
     try {
         j->nn = nn;
         j->nc = nc;
         j->nf = nf;
         j->xyz = copy_in(m->node_xyz, 3 * (size_t)nn);
-        j->hex8 = copy_in(m->hex8, 8 * (size_t)nc);
+        if (m->hex8) {
+            j->hex8 = copy_in(m->hex8, 8 * (size_t)nc);
+        } else {  // the general form: the two CSR lists (their sizes checked before the copies)
+            const int64_t nF = m->n_faces;
+            if (nF <= 0 || !m->cell_face_ptr || !m->face_node_ptr) return VAG_ERR_ARG;
+            j->n_faces = nF;
+            j->cell_face_ptr = copy_in(m->cell_face_ptr, (size_t)nc + 1);
+            j->face_node_ptr = copy_in(m->face_node_ptr, (size_t)nF + 1);
+            // non-decreasing offsets from 0, so that the lists' lengths are their last entries
+            for (int64_t K = 0; K < nc; ++K)
+                if (j->cell_face_ptr[K + 1] < j->cell_face_ptr[K]) return VAG_ERR_ARG;
+            for (int64_t f = 0; f < nF; ++f)
+                if (j->face_node_ptr[f + 1] < j->face_node_ptr[f]) return VAG_ERR_ARG;
+            const int64_t ncf = j->cell_face_ptr[nc], nfn = j->face_node_ptr[nF];
+            if (j->cell_face_ptr[0] != 0 || j->face_node_ptr[0] != 0) return VAG_ERR_ARG;
+            j->cell_faces = copy_in(m->cell_faces, (size_t)ncf);
+            j->face_nodes = copy_in(m->face_nodes, (size_t)nfn);
+            if (nf) j->face_ids = copy_in(job->frac->face_ids, (size_t)nf);
+        }
         if (nf) {
-            j->fnodes = copy_in(job->frac->face_nodes, 4 * (size_t)nf);
+            if (m->hex8) j->fnodes = copy_in(job->frac->face_nodes, 4 * (size_t)nf);
             j->fwidth = copy_in(job->frac->width, (size_t)nf);
             j->fperm = copy_in(job->frac->perm, (size_t)nf);
             j->fporo = copy_in(job->frac->porosity, (size_t)nf);
@@ -601,7 +632,17 @@ vag_status vag_server_submit(vag_server *s, const vag_job *job, uint64_t *job_id
     j->out[3] = job->c_cell;
     j->out[4] = job->c_frac;
     j->out[5] = job->c_node;
-    j->est = vag_estimate_footprint(nn, nc, nf, &j->opt);
+    {
+        vag_mesh em = *m;  // the copies, whose sizes were checked
+        if (!m->hex8) {
+            em.cell_face_ptr = j->cell_face_ptr.data();
+            em.cell_faces = j->cell_faces.data();
+            em.face_node_ptr = j->face_node_ptr.data();
+            em.face_nodes = j->face_nodes.data();
+        }
+        j->est = vag_estimate_footprint_mesh(&em, nf, &j->opt);
+        if (!j->est) return VAG_ERR_ARG;
+    }
     if (j->est > s->budget) return VAG_ERR_OOM;
     j->res.worker = -1;
     {

@@ -2044,6 +2044,41 @@ size_t vag_estimate_footprint(int64_t nn, int64_t nc, int64_t nf, const vag_opti
     return (size_t)(1.15 * b) + ((size_t)1 << 20);
 }
 
+size_t vag_estimate_footprint_mesh(const vag_mesh *mesh, int64_t n_frac, const vag_options *opt) {
+    if (!mesh || n_frac < 0) return 0;
+    const int64_t nn = mesh->n_nodes, nc = mesh->n_cells;
+    size_t b = vag_estimate_footprint(nn, nc, n_frac, opt);
+    if (mesh->hex8 || !b) return b;
+    // A general mesh adds, per cell of m = nv + f unknowns (nv nodes, f
+    // fracture faces), m^2 local values, their derivatives and their
+    // positions in the system (the gather lists of the assembly), and per
+    // cell node its flux and incidence entries.  nv is bounded by the cell's
+    // face-node count over 3 (a node of a polyhedron lies on three faces at
+    // least) and by 8; with f <= 6 and at most 2 n_frac fracture sides,
+    // sum m^2 <= sum nv^2 + (2 * 8 + 6) * 2 n_frac.
+    const int64_t nF = mesh->n_faces;
+    if (!mesh->cell_face_ptr || !mesh->cell_faces || !mesh->face_node_ptr || nF <= 0) return 0;
+    double m2 = 0.0, ncn = 0.0;
+    if (mesh->cell_face_ptr[0] != 0) return 0;
+    for (int64_t K = 0; K < nc; ++K) {
+        if (mesh->cell_face_ptr[K + 1] < mesh->cell_face_ptr[K]) return 0;
+        int64_t fn = 0;
+        for (int64_t q = mesh->cell_face_ptr[K]; q < mesh->cell_face_ptr[K + 1]; ++q) {
+            const int32_t f = mesh->cell_faces[q];
+            if (f < 0 || f >= nF) return 0;
+            const int64_t d = mesh->face_node_ptr[f + 1] - mesh->face_node_ptr[f];
+            if (d < 0) return 0;
+            fn += d;
+        }
+        const double nv = (double)std::min<int64_t>(8, (fn + 2) / 3);
+        m2 += nv * nv;
+        ncn += nv;
+    }
+    m2 += 44.0 * (double)n_frac;
+    b += (size_t)(1.15 * (24.0 * m2 + 48.0 * ncn + 32.0 * (double)nc + 16.0 * (double)nF));
+    return b;
+}
+
 const char *vag_last_error(const vag_handle *h) { return h ? h->err.c_str() : g_create_error.c_str(); }
 
 vag_status vag_trim_memory(void) {

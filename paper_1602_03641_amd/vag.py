@@ -151,6 +151,7 @@ _SIGS = {
     "vag_last_error": ([vp], C.c_char_p),
     "vag_destroy": ([vp], None),
     "vag_estimate_footprint": ([C.c_int64, C.c_int64, C.c_int64, C.POINTER(vag_options)], C.c_size_t),
+    "vag_estimate_footprint_mesh": ([C.POINTER(vag_mesh), C.c_int64, C.POINTER(vag_options)], C.c_size_t),
     "vag_server_create": ([C.c_size_t, C.c_int, C.POINTER(vp)], C.c_int),
     "vag_server_submit": ([vp, C.POINTER(vag_job), C.POINTER(C.c_uint64)], C.c_int),
     "vag_server_wait": ([vp, C.c_uint64, C.c_double, C.POINTER(vag_job_result)], C.c_int),
@@ -434,10 +435,35 @@ def to_numpy(d):
     return {k: v.detach().cpu().numpy() if hasattr(v, "detach") else v for k, v in d.items()}
 
 
+def _host_mesh(prob):
+    """The mesh and fracture structs of a problem in either form, over host
+    copies of its arrays (returned too: they must outlive the structs)."""
+    c = np.ascontiguousarray
+    p = lambda a: a.ctypes.data_as(C.c_void_p) if a.size else None  # noqa: E731
+    keep = dict(xyz=c(prob.xyz, np.float64), fw=c(prob.frac_width, np.float64), fk=c(prob.frac_perm, np.float64),
+                fp=c(prob.frac_poro, np.float64))
+    nn = int(prob.xyz.shape[0])
+    if getattr(prob, "face_node_ptr", None) is not None:
+        keep.update(cfp=c(prob.cell_face_ptr, np.int64), cf=c(prob.cell_faces, np.int32),
+                    fnp=c(prob.face_node_ptr, np.int64), fn=c(prob.face_nodes, np.int32),
+                    fid=c(prob.frac_face_ids, np.int32))
+        nc, nf = int(prob.n_cells), len(keep["fid"])
+        mesh = vag_mesh(nn, nc, p(keep["xyz"]), None, len(keep["fnp"]) - 1, p(keep["cfp"]), p(keep["cf"]),
+                        p(keep["fnp"]), p(keep["fn"]))
+        frac = vag_fractures(nf, None, p(keep["fw"]), p(keep["fk"]), p(keep["fp"]), p(keep["fid"]))
+    else:
+        keep.update(hex8=c(prob.hex8, np.int32), fnodes=c(np.asarray(prob.frac_nodes, np.int32).reshape(-1, 4)))
+        nc, nf = int(prob.hex8.shape[0]), int(keep["fnodes"].shape[0])
+        mesh = vag_mesh(nn, nc, p(keep["xyz"]), p(keep["hex8"]))
+        frac = vag_fractures(nf, p(keep["fnodes"]), p(keep["fw"]), p(keep["fk"]), p(keep["fp"]))
+    return keep, mesh, frac
+
+
 def estimate_footprint(prob, **opt_kw):
+    """vag_estimate_footprint_mesh of the problem's mesh (either form)."""
     o = default_options(**opt_kw)
-    return int(load().vag_estimate_footprint(int(prob.xyz.shape[0]), int(prob.hex8.shape[0]),
-                                             int(np.asarray(prob.frac_nodes).reshape(-1, 4).shape[0]), C.byref(o)))
+    keep, mesh, frac = _host_mesh(prob)
+    return int(load().vag_estimate_footprint_mesh(C.byref(mesh), int(frac.n_frac), C.byref(o)))
 
 
 class Server:
@@ -456,19 +482,14 @@ class Server:
         self._jobs = {}
 
     def submit(self, prob, n_steps=0, t_final=0.0, mesh_key=0, outputs=OUTPUTS, **opt_kw):
-        """Queues one job; returns its id.  The server copies the inputs."""
-        nn, nc = int(prob.xyz.shape[0]), int(prob.hex8.shape[0])
-        fn = np.ascontiguousarray(np.asarray(prob.frac_nodes, np.int32).reshape(-1, 4))
-        nf = fn.shape[0]
-        keep = dict(
-            xyz=np.ascontiguousarray(prob.xyz, np.float64), hex8=np.ascontiguousarray(prob.hex8, np.int32), fn=fn,
-            fw=np.ascontiguousarray(prob.frac_width, np.float64), fk=np.ascontiguousarray(prob.frac_perm, np.float64),
-            fp=np.ascontiguousarray(prob.frac_poro, np.float64), perm=np.ascontiguousarray(prob.perm, np.float64),
-            poro=np.ascontiguousarray(prob.poro, np.float64), dir=np.ascontiguousarray(prob.dirichlet, np.uint8),
-            pb=np.ascontiguousarray(prob.p_bar, np.float64), cb=np.ascontiguousarray(prob.c_bar, np.float64))
+        """Queues one job (a hex8 problem or one given by its faces); returns
+        its id.  The server copies the inputs."""
+        keep, mesh, frac = _host_mesh(prob)
+        nn, nc, nf = int(mesh.n_nodes), int(mesh.n_cells), int(frac.n_frac)
+        keep.update(perm=np.ascontiguousarray(prob.perm, np.float64), poro=np.ascontiguousarray(prob.poro, np.float64),
+                    dir=np.ascontiguousarray(prob.dirichlet, np.uint8), pb=np.ascontiguousarray(prob.p_bar, np.float64),
+                    cb=np.ascontiguousarray(prob.c_bar, np.float64))
         p = lambda a: a.ctypes.data_as(C.c_void_p) if a.size else None  # noqa: E731
-        mesh = vag_mesh(nn, nc, p(keep["xyz"]), p(keep["hex8"]))
-        frac = vag_fractures(nf, p(keep["fn"]), p(keep["fw"]), p(keep["fk"]), p(keep["fp"]))
         rock = vag_rock(p(keep["perm"]), p(keep["poro"]), float(prob.mu))
         bc = vag_bc(p(keep["dir"]), p(keep["pb"]), p(keep["cb"]))
         opt = default_options(**opt_kw)

@@ -221,3 +221,29 @@ def test_mesh_without_hex8_or_faces_rejected():
     st = lib.vag_create(C.byref(mesh), C.byref(fr), C.byref(rock), C.byref(bc), C.byref(o), vag.VAG_MEM_HOST,
                         None, C.byref(h))
     assert st == vag.VAG_ERR_ARG and "cell_face_ptr" in lib.vag_last_error(None).decode()
+
+
+def test_footprint_estimate_of_a_mesh():
+    """vag_estimate_footprint_mesh: a hex8 mesh gets the size-only estimate; a
+    mesh given by its faces adds its local matrices; inconsistent face lists
+    give 0."""
+    lib = vag.load()
+    o = vag.default_options()
+    p = synth.random_problem((6, 5, 4), 3, n_patches=2, n_steps=1)
+    nf = len(np.asarray(p.frac_nodes).reshape(-1, 4))
+    size_only = lib.vag_estimate_footprint(p.n_nodes, p.n_cells, nf, C.byref(o))
+    assert vag.estimate_footprint(p) == size_only > 0
+    q = synth.general_problem("hex", (6, 5, 4), 3, frac_plane=3)
+    e_hex = vag.estimate_footprint(q)
+    assert e_hex > lib.vag_estimate_footprint(q.n_nodes, q.n_cells, q.n_frac, C.byref(o))
+    t = synth.general_problem("tet", (6, 5, 4), 3, frac_plane=3)
+    assert vag.estimate_footprint(t) > e_hex  # six times the cells on the same nodes
+    import copy
+    r = copy.copy(q)
+    r.cell_face_ptr = q.cell_face_ptr.copy()
+    r.cell_face_ptr[2] = r.cell_face_ptr[1] - 1  # decreasing offsets
+    assert vag.estimate_footprint(r) == 0
+    r = copy.copy(q)
+    r.cell_faces = q.cell_faces.copy()
+    r.cell_faces[5] = len(q.face_node_ptr) - 1  # face index out of range
+    assert vag.estimate_footprint(r) == 0

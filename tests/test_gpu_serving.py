@@ -1,7 +1,8 @@
 """GPU tests of the serving loop (vag_server_*): every job's result is the same
 alone and in the mix (bitwise: a job's rows get the same arithmetic in the same
 order whatever else is on the device, its transport steps included, which run
-batched with other jobs' steps), the batched steps equal a lone handle's, jobs
+batched with other jobs' steps), on hex8 meshes and on meshes given by their
+faces, the batched steps equal a lone handle's, jobs
 whose transports overlap share launches, admission by footprint keeps the
 bytes in use within the budget, the footprint estimate bounds the real
 footprint, cached handles are reused, cancel and out-of-memory rejection.
@@ -174,6 +175,60 @@ def test_footprint_estimate_bounds_actual():
             assert r["footprint_bytes"] <= r["footprint_estimate"], (p.name, mode, r["footprint_bytes"])
             if r["footprint_bytes"] > 20e6:  # tightness, once the fixed part no longer dominates
                 assert r["footprint_estimate"] <= 3 * r["footprint_bytes"], (p.name, mode)
+
+
+def _general_jobs():
+    """Tetrahedra, prisms and hexahedra given by their faces, with fracture
+    planes, mixed with hex8 jobs."""
+    jobs = [synth.general_problem(kind, dims, 60 + k, frac_plane=dims[0] // 2, n_steps=12 + 5 * k)
+            for k, (kind, dims) in enumerate([("tet", (7, 6, 5)), ("prism", (9, 7, 6)), ("hex", (8, 7, 6)),
+                                              ("tet", (10, 8, 7)), ("prism", (6, 5, 4))])]
+    return jobs + _jobs(3)
+
+
+def test_general_jobs_alone_equal_mix_and_handle():
+    """Jobs on meshes given by their faces run in the mix with hex8 jobs: each
+    result equals the job run alone, bitwise, and a lone handle's."""
+    vag = _vag()
+    jobs = _general_jobs()
+    alone, _ = _run(vag, jobs, "fp64", workers=1, together=False)
+    mix, stats = _run(vag, jobs, "fp64", workers=4, together=True)
+    assert stats["finished"] == len(jobs) and stats["bytes_in_use"] == 0
+    assert stats["job_steps"] == sum(p.n_steps for p in jobs)
+    for a, m in zip(alone, mix):
+        assert a["status"] == 0 and m["status"] == 0, (a["message"], m["message"])
+        for k in OUT:
+            np.testing.assert_array_equal(a[k], m[k], err_msg=k)
+    for p, r in zip(jobs[:2], mix[:2]):
+        h = vag.Handle(p, **_opts("fp64"))
+        h.solve_pressure()
+        h.transport(n_steps=p.n_steps)
+        d = vag.to_numpy(h.pressure()) | vag.to_numpy(h.concentration())
+        h.close()
+        for k in OUT:
+            np.testing.assert_array_equal(r[k], d[k], err_msg=k)
+
+
+def test_general_footprint_estimate_bounds_actual():
+    """The mesh-based estimate bounds the footprint of jobs on tetrahedra,
+    prisms and hexahedra given by their faces, within 3x once the mesh is
+    large."""
+    vag = _vag()
+    for kind, dims in [("tet", (6, 5, 4)), ("prism", (9, 8, 6)), ("hex", (10, 9, 8)), ("tet", (28, 26, 24)),
+                       ("prism", (36, 32, 30)), ("hex", (44, 40, 36))]:
+        p = synth.general_problem(kind, dims, 7, frac_plane=dims[0] // 2)
+        for mode in ("fp64", "mixed"):
+            srv = vag.Server(n_workers=1)
+            try:
+                r = srv.wait(srv.submit(p, n_steps=3, **_opts(mode)))
+            finally:
+                srv.close()
+            assert r["status"] == 0, r["message"]
+            assert r["footprint_bytes"] <= r["footprint_estimate"], (kind, dims, mode, r["footprint_bytes"])
+            print(f"{kind}{dims} {mode}: {r['footprint_bytes'] / 1e6:.1f} MB, estimate "
+                  f"{r['footprint_estimate'] / 1e6:.1f} MB")
+            if r["footprint_bytes"] > 20e6:
+                assert r["footprint_estimate"] <= 3 * r["footprint_bytes"], (kind, dims, mode)
 
 
 def test_oom_rejected_at_submit():
