@@ -482,6 +482,9 @@ def main():
     ap.add_argument("--amg-kind", choices=["aggregation", "classical"], default="aggregation")
     ap.add_argument("--ilu-block-rows", type=int, default=0, help="block-Jacobi ILU(0) block size (0: default)")
     ap.add_argument("--amg-kcycle", type=int, default=-1, help="coarse levels with K-cycles (-1: library default)")
+    ap.add_argument("--log-jsonl", default=None,
+                    help="append one JSON record per solve, transport call and served job, and the result line, "
+                         "to this file")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the config-2 leg and the serving stream")
     ap.add_argument("--serving-jobs", type=int, default=int(os.environ.get("VAG_BENCH_SERVING_JOBS", "256")),
@@ -511,6 +514,8 @@ def main():
     import synth
     from paper_1602_03641_amd import vag
 
+    if args.log_jsonl:
+        vag.set_log(args.log_jsonl)
     n_def, prec_def, kry_def = DEFAULTS[args.workload]
     args.n = args.n or n_def
     args.precision = args.precision or (prec_def if args.precond == "amg" else "fp64")
@@ -586,6 +591,8 @@ def main():
         "config2": extra, "serving": serving,
     }
     print(json.dumps(out), flush=True)
+    if args.log_jsonl:
+        vag._log("bench", out)
 
 
 if __name__ == "__main__":

@@ -390,6 +390,7 @@ vag_handle *vag_server::finish_outputs(Job *j, vag_handle *h, hipStream_t s) {
 // the transport's set-up; then hands the transport steps to the job's lane
 // or, without transport, copies the outputs.
 vag_server::Outcome vag_server::run(Job *j, int w, vag_handle *h) {
+    vag::Phases ph("vag.job");
     hipStream_t s = streams[w];
     vag_job_result &r = j->res;
     vag_mesh mesh{j->nn, j->nc, j->xyz.data(), j->hex8.empty() ? nullptr : j->hex8.data()};

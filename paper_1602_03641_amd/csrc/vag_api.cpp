@@ -903,6 +903,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         return VAG_ERR_OOM;
     }
     vag_status st = guard(h, [&] {
+        Phases ph("vag.create");
         if (!mesh || !rock || !bc) throw Error(VAG_ERR_ARG, "mesh, rock and bc are required");
         if (!(rock->mu > 0)) throw Error(VAG_ERR_ARG, "viscosity must be positive");
         h->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -1306,6 +1307,7 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
         const Symbolic &S = h->S;
         hipStream_t s = h->stream;
         const int32_t n = S.nunk;
+        Phases ph("vag.assembly");
         VAG_HIP(hipEventRecord(h->ev[0], s));
         // 1. local matrices and fracture matrices (their coefficients checked on the way)
         VAG_HIP(hipMemsetAsync(h->bad.p, 0x7f, sizeof(int), s));
@@ -1353,6 +1355,7 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
                               h->grp_poff.p, h->grp_pos.p, h->frac_unk.p, h->Gb.p, h->A.p, h->b.p, h->bad.p);
         launch_diag_inv(s, n, h->diag_pos.p, h->A.p, h->dinv.p);
         VAG_HIP(hipEventRecord(h->ev[1], s));
+        ph.next("vag.preconditioner_setup");
         if (h->opt.precond == VAG_PC_AMG) {
             h->amg.setup(s, h->tr, h->Asell(), (int64_t)h->A.n, amg_options(h->opt));
             h->amg.stream_mode = h->opt.stream_loads;
@@ -1368,6 +1371,7 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
             h->ilu.factor(s, h->A.p, h->ilu_bad.p);
         }
         VAG_HIP(hipEventRecord(h->ev[2], s));
+        ph.next("vag.krylov");
         // 3. Krylov
         if (h->opt.precision == VAG_MIXED_IR)
             run_mixed(h);
@@ -1378,6 +1382,7 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
         else
             run_pcg(h);
         VAG_HIP(hipEventRecord(h->ev[3], s));
+        ph.next("vag.fluxes");
         const PcgState pst = *h->h_pcg;
         converged = pst.converged != 0;
         // 4. recovery and fluxes
@@ -1406,6 +1411,7 @@ vag_status vag_solve_pressure(vag_handle *h, vag_solve_info *info) {
             porous_volumes(h, s);
         }
         VAG_HIP(hipEventRecord(h->ev[4], s));
+        ph.next("vag.residual");
         // true residual ||b - A x|| / ||b||
         launch_residual_norm(s, h->Asell(), h->x.p, h->b.p, h->r.p, h->rparts.p, h->scal.p);
         VAG_HIP(hipMemcpyAsync(h->h_scal, h->scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1560,7 +1566,9 @@ vag_status vag_transport(vag_handle *h, int64_t n_steps, double t_final, const d
                          const double *c0_frac, const double *c0_node, vag_mem mem, vag_transport_info *info) {
     if (!h) return VAG_ERR_ARG;
     return guard(h, [&] {
+        Phases ph("vag.transport_setup");
         const TransportPlan P = transport_prepare(h, n_steps, t_final, c0_cell, c0_frac, c0_node, mem);
+        ph.next("vag.transport_steps");
         hipStream_t s = h->stream;
         for (int64_t k = 0; k < P.N; ++k) {
             const double th = (k == P.N - 1) ? P.theta_last : 1.0;

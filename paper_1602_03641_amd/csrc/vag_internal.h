@@ -11,6 +11,8 @@
 #include <utility>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "vag.h"
 
 namespace vag {
@@ -36,6 +38,28 @@ __device__ __forceinline__ T ld_matrix(const T *p) {
 // ---------------------------------------------------------------------------
 // errors: thrown inside the library, turned into a vag_status at the ABI
 // ---------------------------------------------------------------------------
+// Named ranges on the host timeline of a profiler's marker trace (rocprofv3
+// --marker-trace); a range is closed on every exit of its scope, exceptions
+// included.  Phases holds one open range at a time: next() closes the
+// current one and opens the next.
+class Phases {
+public:
+    explicit Phases(const char *name) { next(name); }
+    void next(const char *name) {
+        if (open_) roctxRangePop();
+        roctxRangePushA(name);
+        open_ = true;
+    }
+    ~Phases() {
+        if (open_) roctxRangePop();
+    }
+    Phases(const Phases &) = delete;
+    Phases &operator=(const Phases &) = delete;
+
+private:
+    bool open_ = false;
+};
+
 struct Error : std::runtime_error {
     vag_status status;
     Error(vag_status s, const std::string &m) : std::runtime_error(m), status(s) {}

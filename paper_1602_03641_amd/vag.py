@@ -11,12 +11,15 @@ fails loudly otherwise — there is no fallback path.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
+import time
 
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvag.so")
+_log_path = os.environ.get("VAG_LOG_JSONL") or None
 
 VAG_OK, VAG_WARN_NOT_CONVERGED = 0, 1
 VAG_ERR_ARG, VAG_ERR_MESH, VAG_ERR_UNSUPPORTED, VAG_ERR_OOM, VAG_ERR_HIP, VAG_ERR_STATE = -1, -2, -3, -4, -5, -6
@@ -189,6 +192,23 @@ def __getattr__(name):  # vag_* functions resolve to the C symbols
     raise AttributeError(name)
 
 
+def set_log(path):
+    """Appends one JSON record per line to `path` for every pressure solve,
+    transport call and served job (None turns the log off).  The environment
+    variable VAG_LOG_JSONL sets the path when the module is imported."""
+    global _log_path
+    _log_path = path
+
+
+def _log(kind, rec):
+    if not _log_path:
+        return
+    line = json.dumps({"kind": kind, "unix_time": time.time(), **rec},
+                      default=lambda o: list(o) if hasattr(o, "__len__") else str(o))
+    with open(_log_path, "a") as f:
+        f.write(line + "\n")
+
+
 class VagError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -286,11 +306,17 @@ class Handle:
             setattr(self.options, k, v)
         self._check(load().vag_set_options(self.h, C.byref(self.options)))
 
+    def _sizes(self):
+        o = self.options
+        return dict(n_cells=self.nc, n_nodes=self.nn, n_frac=self.nf, general=self.general,
+                    options=dict(precision=o.precision, krylov=o.krylov, precond=o.precond, rtol=o.rtol))
+
     def solve_pressure(self):
         info = vag_solve_info()
         st = self._check(load().vag_solve_pressure(self.h, C.byref(info)))
         d = info.as_dict()
         d["status"] = st
+        _log("solve", {**self._sizes(), **d})
         return d
 
     def transport(self, n_steps=0, t_final=0.0, c0=None):
@@ -303,7 +329,10 @@ class Handle:
             args = tuple(_dptr(x) for x in tt)
         self._check(load().vag_transport(self.h, int(n_steps), float(t_final), *args, VAG_MEM_DEVICE,
                                          C.byref(info)))
-        return info.as_dict()
+        d = info.as_dict()
+        d["dt_bounds"] = list(d["dt_bounds"])
+        _log("transport", {**self._sizes(), **d})
+        return d
 
     def transport_noalloc(self, n_steps=0, t_final=0.0, c0=None, info=True):
         """vag_transport_noalloc: the steps gathered from the fluxes, with the
@@ -515,6 +544,8 @@ class Server:
         if st != VAG_OK:
             raise VagError(st, f"vag_server_wait({job_id})")
         d = res.as_dict()
+        d["transport"]["dt_bounds"] = list(d["transport"]["dt_bounds"])
+        _log("job", {"job_id": job_id, **d})
         d.update(self._jobs.pop(job_id))
         return d
 

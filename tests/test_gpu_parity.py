@@ -1056,3 +1056,57 @@ def test_switching_solvers_on_one_handle():
         assert rel_l2(g["u_node"], ref["u_node"]) <= 1e-9, kw
     for k in ("u_node", "u_frac", "c_cell", "c_node"):
         np.testing.assert_array_equal(g[k], ref[k])
+
+
+# ---------------------------------------------------------------------------
+# Checkpoint and resume of the transport
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["hex8", "tet"])
+def test_transport_resume_bitwise(kind):
+    """The explicit scheme's state is the concentration vector (the time step
+    follows from the fluxes).  After a solve the state is 0; n steps, the
+    concentrations saved to host memory, then m more steps (continuing on the
+    handle, from the saved state on the same handle, and from it on a new
+    handle of the same problem after its own solve) equal n + m uninterrupted
+    steps, bitwise; a final-time run split at a step boundary agrees too."""
+    _torch()
+    from paper_1602_03641_amd import vag
+    if kind == "hex8":
+        p = synth.random_problem((9, 7, 6), 5, n_patches=4, n_steps=40)
+    else:
+        p = synth.general_problem("tet", (7, 6, 5), 5, frac_plane=3)
+    opt = dict(rtol=1e-12, max_iter=20000, precond=vag.VAG_PC_AMG)
+    keys = ("c_cell", "c_frac", "c_node")
+    h = vag.Handle(p, **opt)
+    h.solve_pressure()
+    t_full = h.transport(n_steps=40)
+    full = vag.to_numpy(h.concentration())
+    h.solve_pressure()  # the state starts again from 0
+    h.transport(n_steps=15)
+    ck = vag.to_numpy(h.concentration())
+    h.transport(n_steps=25)  # continues
+    cont = vag.to_numpy(h.concentration())
+    h.transport(n_steps=25, c0=ck)
+    again = vag.to_numpy(h.concentration())
+    h2 = vag.Handle(p, **opt)
+    h2.solve_pressure()
+    h2.transport(n_steps=25, c0=ck)
+    fresh = vag.to_numpy(h2.concentration())
+    assert np.abs(full["c_cell"] - ck["c_cell"]).max() > 1e-3  # the last 25 steps change the state
+    for r in (cont, again, fresh):
+        for k in keys:
+            np.testing.assert_array_equal(r[k], full[k], err_msg=k)
+    # final time 40 dt, and 15 dt followed by 25 dt
+    dt = t_full["dt"]
+    h.solve_pressure()
+    h.transport(t_final=40 * dt)
+    tf = vag.to_numpy(h.concentration())
+    h.solve_pressure()
+    h.transport(t_final=15 * dt)
+    h.transport(t_final=25 * dt)
+    tf2 = vag.to_numpy(h.concentration())
+    for k in keys:
+        np.testing.assert_allclose(tf2[k], tf[k], rtol=0, atol=1e-12, err_msg=k)
+        np.testing.assert_allclose(tf[k], full[k], rtol=0, atol=1e-12, err_msg=k)
+    h.close()
+    h2.close()

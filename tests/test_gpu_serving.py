@@ -299,3 +299,35 @@ def test_pool_reuse_and_trim():
             ref = d
         for key in OUT:
             np.testing.assert_array_equal(d[key], ref[key], err_msg=key)
+
+
+def test_jsonl_records(tmp_path):
+    """vag.set_log: one JSON record per solve, transport call and served job,
+    with the phases, iterations, residual and the job's times."""
+    import json
+    vag = _vag()
+    path = str(tmp_path / "log.jsonl")
+    vag.set_log(path)
+    try:
+        p = _jobs(1)[0]
+        h = vag.Handle(p, **_opts("fp64"))
+        h.solve_pressure()
+        h.transport(n_steps=3)
+        h.close()
+        srv = vag.Server(n_workers=1)
+        try:
+            jid = srv.submit(p, n_steps=3, **_opts("fp64"))
+            r = srv.wait(jid)
+        finally:
+            srv.close()
+    finally:
+        vag.set_log(None)
+    recs = [json.loads(line) for line in open(path)]
+    assert [x["kind"] for x in recs] == ["solve", "transport", "job"]
+    s, t, j = recs
+    assert s["n_cells"] == p.n_cells and s["iterations"] > 0 and s["rel_residual"] <= 1e-10
+    assert all(s[k] >= 0 for k in ("ms_assembly", "ms_setup", "ms_solve", "ms_fluxes"))
+    assert t["n_steps"] == 3 and len(t["dt_bounds"]) == 3
+    assert j["job_id"] == jid and j["status"] == r["status"] == 0
+    assert j["t_submit"] <= j["t_start"] <= j["t_end"] and j["solve"]["iterations"] == s["iterations"]
+    assert j["transport"]["n_steps"] == 3
