@@ -100,8 +100,11 @@ __global__ __launch_bounds__(kAT) void strength_kernel(Sell<double> A, const dou
     }
 }
 
-__global__ __launch_bounds__(kAT) void mis_init_kernel(int32_t n, uint32_t *__restrict__ T) {
-    GS(i, n) T[i] = (1u << 30) | perm30((uint32_t)i);
+__global__ __launch_bounds__(kAT) void mis_init_kernel(int32_t n, uint32_t *__restrict__ T, uint32_t *__restrict__ T1) {
+    GS(i, n) {
+        T[i] = (1u << 30) | perm30((uint32_t)i);
+        T1[i] = 1u << 30;  // rank 1: computed in the first round
+    }
 }
 
 // max of key[] over row i and its strong neighbours, four gathers in flight
@@ -129,12 +132,22 @@ __device__ inline bool any_count(const int *__restrict__ c) {
     return __ballot(v != 0) != 0;
 }
 
-// Tout[i] = max of T over {i} and its strong neighbours
+// Tout[i] = max of T over {i} and its strong neighbours, recomputed only
+// where the previous round's maximum had rank 1 (an undecided row among
+// them).  Rank 0: every row of the set was decided, and decided keys never
+// change, so the value is still exact.  Rank 2: a root among them, which stays
+// a root, so the maximum still has rank 2; the selection asks of a maximum
+// only whether it has rank 2 or, having rank 1, equals an undecided row's own
+// key, so its decisions are those of the full recomputation.  The later
+// rounds then touch only the rows next to the undecided ones.
 __global__ __launch_bounds__(kAT) void mis_max_kernel(int32_t n, const int64_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ scol, const uint32_t *__restrict__ Tin,
                                                       uint32_t *__restrict__ Tout, const int *__restrict__ active) {
     if (active && !any_count(active)) return;
-    GS(i, n) Tout[i] = strong_max(ptr, scol, (int32_t)i, Tin);
+    GS(i, n) {
+        if (rank_of(Tout[i]) != 1) continue;
+        Tout[i] = strong_max(ptr, scol, (int32_t)i, Tin);
+    }
 }
 
 // second hop, then the decision of undecided nodes
@@ -1385,7 +1398,7 @@ void amg_launch_diag(hipStream_t s, Sell<double> A, double *diag, double *dinv) 
 void amg_launch_mis(hipStream_t s, Sell<double> A, const double *diag, double theta, int rounds, int hops,
                     uint32_t *T, uint32_t *T1, int *undecided, int32_t *flag, int *hcnt, int32_t *scol) {
     ALAUNCH(strength_kernel, gridv(A.n), kAT, A, diag, theta, scol);
-    ALAUNCH(mis_init_kernel, gridv(A.n), kAT, A.n, T);
+    ALAUNCH(mis_init_kernel, gridv(A.n), kAT, A.n, T, T1);
     for (int r = 0; r < rounds; ++r) {
         int *cur = undecided + (int64_t)r * kCntSlots * kCntStride;
         const int *active = r ? cur - kCntSlots * kCntStride : nullptr;

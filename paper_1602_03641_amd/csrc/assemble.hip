@@ -285,8 +285,15 @@ __global__ __launch_bounds__(128) void node_pos_kernel(AsmArgs g, uint16_t *__re
     for (int k = 0; k < kPosRegs; ++k) a[k] = regs && k < len ? g.sell_col[base + 64 * (int64_t)k] : INT32_MAX;
     for (int32_t q = g.node_cell_ptr[s]; q < g.node_cell_ptr[s + 1]; ++q) {
         const int32_t K = g.node_cell[q] >> 3;
+        // the cell's 8 unknowns first (loads in flight together), its 8 slots
+        // stored at the end as one 16-byte write
+        int32_t uc[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) uc[c] = g.node_unk[g.hex8[8 * (int64_t)K + c]];
+        uint32_t pw[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
         for (int c = 0; c < 8; ++c) {
-            const int32_t u = g.node_unk[g.hex8[8 * (int64_t)K + c]];
+            const int32_t u = uc[c];
             uint16_t k = 0xffff;
             if (u >= 0) {
                 int64_t slot = -1;
@@ -306,8 +313,9 @@ __global__ __launch_bounds__(128) void node_pos_kernel(AsmArgs g, uint16_t *__re
                 if (slot < 0 || slot >= 0xffff) atomicMin(g.bad, INT_MIN);
                 else k = (uint16_t)slot;
             }
-            node_pos[8 * (int64_t)q + c] = k;
+            pw[c >> 1] |= (uint32_t)k << (16 * (c & 1));
         }
+        *reinterpret_cast<uint4 *>(node_pos + 8 * (int64_t)q) = make_uint4(pw[0], pw[1], pw[2], pw[3]);
     }
 }
 
@@ -349,11 +357,19 @@ __global__ __launch_bounds__(128) void asm_node_rows_kernel(AsmArgs g) {
         const int a = g.node_cell[q] & 7;
         const double inv = 1.0 / g.AKK[K];
         const double ra = g.rK[(int64_t)a * g.nc + K];
+        // the cell's loads first, all in flight together: an addition to a
+        // slot beyond kAccSlots stores to the row in global memory, which the
+        // compiler would not move a later load past
+        double v[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[c] = g.aK[(int64_t)sym8(a, c) * g.nc + K] - ra * g.rK[(int64_t)c * g.nc + K] * inv;
+        const uint4 pos = *reinterpret_cast<const uint4 *>(g.node_pos + 8 * (int64_t)q);  // 8 slots, 16 bytes
+        const uint32_t pw[4] = {pos.x, pos.y, pos.z, pos.w};
+#pragma unroll
         for (int c = 0; c < 8; ++c) {
-            const double v = g.aK[(int64_t)sym8(a, c) * g.nc + K] - ra * g.rK[(int64_t)c * g.nc + K] * inv;
-            const uint16_t k = g.node_pos[8 * (int64_t)q + c];
-            if (k != 0xffff) put(k, v);
-            else rhs -= v * g.p_bar[g.hex8[8 * (int64_t)K + c]];  // Dirichlet column
+            const uint16_t k = (uint16_t)(pw[c >> 1] >> (16 * (c & 1)));
+            if (k != 0xffff) put(k, v[c]);
+            else rhs -= v[c] * g.p_bar[g.hex8[8 * (int64_t)K + c]];  // Dirichlet column
         }
         const unsigned mask = g.fmask[K];
         for (int f = 0; f < 6; ++f) {
