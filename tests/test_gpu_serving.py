@@ -331,3 +331,37 @@ def test_jsonl_records(tmp_path):
     assert j["job_id"] == jid and j["status"] == r["status"] == 0
     assert j["t_submit"] <= j["t_start"] <= j["t_end"] and j["solve"]["iterations"] == s["iterations"]
     assert j["transport"]["n_steps"] == 3
+
+
+def test_general_job_errors():
+    """A mesh given by its faces with decreasing offsets is rejected at
+    submit; a job whose fracture face index is out of range fails in its own
+    result (the library's message), and the jobs around it finish as if alone."""
+    import copy
+    vag = _vag()
+    good = _general_jobs()[:2]
+    bad_ptr = copy.copy(good[0])
+    bad_ptr.cell_face_ptr = good[0].cell_face_ptr.copy()
+    bad_ptr.cell_face_ptr[3] = bad_ptr.cell_face_ptr[2] - 1
+    bad_fid = copy.copy(good[1])
+    bad_fid.frac_face_ids = good[1].frac_face_ids.copy()
+    bad_fid.frac_face_ids[0] = len(good[1].face_node_ptr) + 5
+    alone, _ = _run(vag, good, "fp64", workers=1, together=False)
+    srv = vag.Server(n_workers=2)
+    try:
+        with pytest.raises(vag.VagError) as e:
+            srv.submit(bad_ptr, n_steps=3)
+        assert e.value.status == vag.VAG_ERR_ARG
+        ids = [srv.submit(good[0], n_steps=good[0].n_steps, **_opts("fp64")),
+               srv.submit(bad_fid, n_steps=3, **_opts("fp64")),
+               srv.submit(good[1], n_steps=good[1].n_steps, **_opts("fp64"))]
+        res = [srv.wait(i) for i in ids]
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert res[1]["status"] == vag.VAG_ERR_ARG and "out of range" in res[1]["message"]
+    for a, m in zip(alone, (res[0], res[2])):
+        assert m["status"] == 0
+        for k in OUT:
+            np.testing.assert_array_equal(a[k], m[k], err_msg=k)
+    assert st["bytes_in_use"] == 0
