@@ -210,7 +210,14 @@ __device__ inline double node_out(int32_t s, const int32_t *ncp, const int32_t *
     return o;
 }
 
-__global__ __launch_bounds__(kT) void cfl_kernel(
+// The CFL kernels run 1024-thread blocks: the grid of a deterministic
+// reduction is capped at kReduceBlocks, and with 256 threads a block the
+// chip held two waves per SIMD, each walking ~100 control volumes through
+// dependent gathers.  A minimum is exact in any grouping, so dt does not
+// depend on the launch shape.
+constexpr int kCflT = 1024;
+
+__global__ __launch_bounds__(kCflT) void cfl_kernel(
     int32_t nc, int32_t nf, int32_t nn, const int32_t *__restrict__ hex8, const uint8_t *__restrict__ fmask,
     const int32_t *__restrict__ cell_frac, const int32_t *__restrict__ frac_cell,
     const uint8_t *__restrict__ dirichlet, const int32_t *__restrict__ ncp, const int32_t *__restrict__ ncl,
@@ -238,7 +245,7 @@ __global__ __launch_bounds__(kT) void cfl_kernel(
             }
         }
     }
-    block_partials<OpMin, 3, kT>(v, parts, gridDim.x);
+    block_partials<OpMin, 3, kCflT>(v, parts, gridDim.x);
 }
 
 __global__ __launch_bounds__(kT) void cfl_finish_kernel(const double *__restrict__ parts, int G, double cfl,
@@ -785,7 +792,7 @@ __device__ inline double inc_flux(const GenInc &I, const double *F, int64_t q) {
     return (e & 1) ? -f : f;
 }
 
-__global__ __launch_bounds__(kT) void gen_cfl_kernel(GenInc I, const double *__restrict__ F,
+__global__ __launch_bounds__(kCflT) void gen_cfl_kernel(GenInc I, const double *__restrict__ F,
                                                      const double *__restrict__ wout,
                                                      const double *__restrict__ phi_cell,
                                                      const double *__restrict__ phi_frac,
@@ -804,7 +811,7 @@ __global__ __launch_bounds__(kT) void gen_cfl_kernel(GenInc I, const double *__r
             v[kind] = fmin(v[kind], phi / o);
         }
     }
-    block_partials<OpMin, 3, kT>(v, parts, gridDim.x);
+    block_partials<OpMin, 3, kCflT>(v, parts, gridDim.x);
 }
 
 // entries of row i: one per inflow (negative outgoing flux), plus a well's
@@ -925,8 +932,8 @@ void launch_cfl(hipStream_t s, int32_t nc, int32_t nf, int32_t nn, const int32_t
                 const double *wout, const double *phi_cell, const double *phi_frac, const double *phi_node,
                 double cfl, double *parts, double *dt_out) {
     const int64_t total = (int64_t)nc + nf + nn;
-    const unsigned G = reduce_grid(total, kT);
-    hipLaunchKernelGGL(cfl_kernel, dim3(G), dim3(kT), 0, s, nc, nf, nn, hex8, fmask, cell_frac, frac_cell,
+    const unsigned G = reduce_grid(total, kCflT);
+    hipLaunchKernelGGL(cfl_kernel, dim3(G), dim3(kCflT), 0, s, nc, nf, nn, hex8, fmask, cell_frac, frac_cell,
                        dirichlet, node_cell_ptr, node_cell, node_frac_ptr, node_frac, F_cell, F_cell_frac, F_frac,
                        wout, phi_cell, phi_frac, phi_node, parts);
     hipLaunchKernelGGL(cfl_finish_kernel, dim3(1), dim3(kT), 0, s, parts, (int)G, cfl, dt_out);
@@ -1022,8 +1029,8 @@ void launch_set_dirichlet(hipStream_t s, int32_t nn, int32_t offset, const uint8
 void launch_gen_cfl(hipStream_t s, const GenInc &I, const double *F, const double *wout, const double *phi_cell,
                     const double *phi_frac, const double *phi_node, double cfl, double *parts, double *dt_out) {
     const int64_t total = (int64_t)I.nc + I.nf + I.nn;
-    const unsigned G = reduce_grid(total, kT);
-    hipLaunchKernelGGL(gen_cfl_kernel, dim3(G), dim3(kT), 0, s, I, F, wout, phi_cell, phi_frac, phi_node, parts);
+    const unsigned G = reduce_grid(total, kCflT);
+    hipLaunchKernelGGL(gen_cfl_kernel, dim3(G), dim3(kCflT), 0, s, I, F, wout, phi_cell, phi_frac, phi_node, parts);
     hipLaunchKernelGGL(cfl_finish_kernel, dim3(1), dim3(kT), 0, s, parts, (int)G, cfl, dt_out);
     VAG_HIP(hipGetLastError());
 }

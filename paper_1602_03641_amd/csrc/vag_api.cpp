@@ -183,7 +183,7 @@ struct vag_handle {
     DBuf<double> pmax;     // [nn] largest permeability around each node (alpha_rule 1)
     int32_t xlo[18] = {};  // host copy, passed to the sweep by value
     DBuf<double> tval, tdiag, cbuf0, cbuf1, dt4;
-    DBuf<unsigned long long> cnt;
+    DBuf<int64_t> tscan;  // per-block sums of the slice offsets' scan
     // pinned: [0] entry count of the upwind operator, from [2] the 18 ints of xsplit
     static constexpr int kCntWords = 16;
     unsigned long long *h_cnt = nullptr;
@@ -1111,7 +1111,7 @@ vag_status vag_create(const vag_mesh *mesh, const vag_fractures *frac, const vag
         h->cbuf0.alloc(nrow + 1, h->tr);
         h->cbuf1.alloc(nrow + 1, h->tr);
         h->dt4.alloc(4, h->tr);
-        h->cnt.alloc(1, h->tr);
+        h->tscan.alloc((size_t)nslice / 1024 + 2, h->tr);
         h->h_cnt = static_cast<unsigned long long *>(pinned_get(vag_handle::kCntWords * sizeof(unsigned long long)));
         h->h_pcg = static_cast<PcgState *>(pinned_get(sizeof(PcgState)));
         h->h_scal = static_cast<double *>(pinned_get(16 * sizeof(double)));
@@ -1481,17 +1481,17 @@ TransportPlan transport_prepare(vag_handle *h, int64_t n_steps, double t_final, 
                             h->F_cell_frac.p, h->F_frac.p, h->well_src(), h->slice_width.p, h->tmeta.p,
                             h->slice_nnz.p);
     }
-    launch_slice_scan(s, nslice, h->slice_nnz.p, 1, h->slice_ptr.p, h->slice_nnz.p, h->cnt.p);
+    launch_scan64(s, nslice, h->slice_nnz.p, h->slice_ptr.p, h->tscan.p);  // slice offsets; the total at nslice
     // segment A: the slices of cells and fracture faces, B: of nodes
     launch_xcd_split(s, nslice, (int32_t)((S.nc + (int64_t)S.nf + kSliceRows - 1) / kSliceRows), h->slice_ptr.p,
                      h->xsplit.p);
     int64_t total = 0;
     VAG_HIP(hipMemcpyAsync(&total, h->slice_ptr.p + nslice, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    VAG_HIP(hipMemcpyAsync(h->h_cnt, h->cnt.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     VAG_HIP(hipMemcpyAsync(h->h_xsplit(), h->xsplit.p, 18 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     VAG_HIP(hipMemcpyAsync(h->h_scal, h->dt4.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     VAG_HIP(hipStreamSynchronize(s));
     for (int x = 0; x < 18; ++x) h->xlo[x] = h->h_xsplit()[x];
+    h->h_cnt[0] = (unsigned long long)total;  // entries without padding
     const double dt = h->h_scal[3];
     double dtb[3] = {h->h_scal[0], h->h_scal[1], h->h_scal[2]};
     if (!(dt < INFINITY)) throw Error(VAG_ERR_ARG, "no control volume has an outflow: CFL bound is infinite");
