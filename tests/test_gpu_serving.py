@@ -365,3 +365,29 @@ def test_general_job_errors():
         for k in OUT:
             np.testing.assert_array_equal(a[k], m[k], err_msg=k)
     assert st["bytes_in_use"] == 0
+
+
+def test_general_cached_handle_reused():
+    """A job on a mesh given by its faces keeps its handle under a mesh key; a
+    second job on that mesh with new rock and boundary data reuses it and
+    equals the same job run on a fresh handle, bitwise."""
+    import copy
+    vag = _vag()
+    p = synth.general_problem("prism", (8, 7, 6), 41, frac_plane=4, n_steps=15)
+    q = copy.copy(p)
+    q.perm = p.perm * 2.5
+    q.frac_perm = p.frac_perm * 0.5
+    q.p_bar = p.p_bar * 1.5
+    srv = vag.Server(n_workers=2)
+    try:
+        r1 = srv.wait(srv.submit(p, n_steps=15, mesh_key=91, **_opts("fp64")))
+        r2 = srv.wait(srv.submit(q, n_steps=15, mesh_key=91, **_opts("fp64")))
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert r1["status"] == 0 and r2["status"] == 0, (r1["message"], r2["message"])
+    assert r1["reused"] == 0 and r2["reused"] == 1 and st["cached_handles"] == 1
+    fresh, _ = _run(vag, [q], "fp64", workers=1, together=False)
+    for k in OUT:
+        np.testing.assert_array_equal(r2[k], fresh[0][k], err_msg=k)
+    assert not np.array_equal(r1["u_node"], r2["u_node"])
