@@ -42,6 +42,9 @@ def _opts(mode):
     from paper_1602_03641_amd import vag
     if mode == "fp64":
         return dict(precond=vag.VAG_PC_AMG, precision=vag.VAG_FP64, rtol=1e-10, max_iter=5000)
+    if mode == "gmres_ir":  # FP64 refinement around flexible GMRES in FP32 (100 basis vectors)
+        return dict(precond=vag.VAG_PC_AMG, precision=vag.VAG_MIXED_IR, krylov=vag.VAG_GMRES, gmres_restart=100,
+                    inner_rtol=1e-2, rtol=1e-10, max_iter=5000)
     return dict(precond=vag.VAG_PC_AMG, precision=vag.VAG_MIXED, rtol=1e-10, max_iter=5000)
 
 
@@ -211,13 +214,14 @@ def test_general_jobs_alone_equal_mix_and_handle():
 
 def test_general_footprint_estimate_bounds_actual():
     """The mesh-based estimate bounds the footprint of jobs on tetrahedra,
-    prisms and hexahedra given by their faces, within 3x once the mesh is
+    prisms and hexahedra given by their faces (CG in FP64 and with the FP32
+    hierarchy, refinement around FP32 GMRES), within 3x once the mesh is
     large."""
     vag = _vag()
     for kind, dims in [("tet", (6, 5, 4)), ("prism", (9, 8, 6)), ("hex", (10, 9, 8)), ("tet", (28, 26, 24)),
                        ("prism", (36, 32, 30)), ("hex", (44, 40, 36))]:
         p = synth.general_problem(kind, dims, 7, frac_plane=dims[0] // 2)
-        for mode in ("fp64", "mixed"):
+        for mode in ("fp64", "mixed", "gmres_ir"):
             srv = vag.Server(n_workers=1)
             try:
                 r = srv.wait(srv.submit(p, n_steps=3, **_opts(mode)))
